@@ -1,0 +1,194 @@
+/*
+ * ell.h -- C ABI of an MI355X (gfx950) solver for the 3D anisotropic elliptic
+ * pressure-correction equation of Mueller & Scheichl, "Massively parallel
+ * solvers for elliptic PDEs in Numerical Weather- and Climate Prediction"
+ * (arXiv:1307.2036):
+ *
+ *     -omega^2 ( Lap_2d u + d/dz( lambda^2(z) du/dz ) ) + u = f        (Sec. 3)
+ *
+ * on nx x ny x nz cells that are doubly periodic in the horizontal, with
+ * homogeneous Neumann conditions at the bottom and top.  The discretisation
+ * is the cell-centred finite-volume 7-point stencil (Sec. 3.1); the solver is
+ * conjugate gradients (Appendix B, Alg. "Preconditioned Conjugate Gradient
+ * method") preconditioned by one tensor-product multigrid V-cycle (Sec. 4.3,
+ * Alg. "Multigrid V-cycle"; Sec. 4.3.1 and 6.2.1): vertical line relaxation
+ * (block red/black SOR over columns, each column solved by the Thomas
+ * algorithm of Appendix B), horizontal-only coarsening, sum restriction and
+ * bilinear prolongation, re-discretised coarse operators.
+ *
+ * Conventions shared by every entry point
+ *  - Vectors passed to ell_apply_A, ell_vcycle and ell_pcg_solve are DEVICE
+ *    pointers to nx*ny*nz doubles in plane-major layout,
+ *    idx = (k*ny + j)*nx + i.  The caller owns them.
+ *  - "Level" entry points (ell_level_*) work on the library's internal
+ *    colour-split layout of one multigrid level (see ell_to_split) and on the
+ *    grid's internal element type: double for ELL_FP64, float otherwise.
+ *  - The grid owns all of its hierarchy and workspace memory.  Calls on one
+ *    grid must not overlap: they share that workspace.  Calls are enqueued on
+ *    the given stream; ell_apply_A, ell_vcycle and the level entry points
+ *    return without synchronising, ell_pcg_solve returns when the solve is
+ *    complete because it fills host statistics.
+ *  - Return value: ELL_OK (0) on success, a negative ELL_ERR_* code on error
+ *    (outputs untouched or partially written; message in ell_last_error()),
+ *    ELL_NOT_CONVERGED (+1) from ell_pcg_solve when maxiter was reached with a
+ *    valid u.
+ */
+#ifndef ELL_H
+#define ELL_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ell_grid ell_grid;
+
+enum {
+    ELL_OK = 0,
+    ELL_NOT_CONVERGED = 1,
+    ELL_PENDING = 2,
+    ELL_ERR_INVALID = -1,   /* bad argument or descriptor                     */
+    ELL_ERR_OOM = -2,       /* device allocation failed                       */
+    ELL_ERR_HIP = -3,       /* a HIP runtime call failed                      */
+    ELL_ERR_NUMERIC = -4,   /* non-finite alpha, beta or residual norm        */
+    ELL_ERR_BUDGET = -5     /* request larger than a memory budget            */
+};
+
+/* Arithmetic of the V-cycle preconditioner.  The outer CG (dots, residual,
+ * solution update) is always FP64. */
+enum {
+    ELL_FP64 = 0,           /* FP64 everywhere                                */
+    ELL_FP32_PRECOND = 1,   /* FP32 V-cycle, FP64 coefficients rounded to FP32 */
+    ELL_FP32_BF16COEF = 2   /* FP32 V-cycle, stencil coefficients rounded to
+                               BF16, Thomas factors computed in FP32 from them */
+};
+
+/* Grid and multigrid description (Sec. 3, 3.1, 4.3, 6.2.1). */
+typedef struct {
+    int32_t nx, ny, nz;      /* cells; nx and ny must each be even or 1        */
+    double hx, hy;           /* horizontal spacings (> 0)                      */
+    double omega2;           /* omega^2 >= 0 (eq. omega2lambda2)               */
+    const double *dz;        /* HOST array of nz layer thicknesses (> 0); copied */
+    const double *lambda2;   /* HOST array of nz cell values of lambda^2 (> 0);
+                                copied.  Vertical face coefficients use the
+                                harmonic (series-resistance) rule.            */
+    int32_t n_levels;        /* multigrid levels incl. the finest; 0 = standard
+                                depth: halve nx, ny while both are even and each
+                                half is even or 1                              */
+    int32_t nu_pre, nu_post; /* red/black sweeps before / after the coarse
+                                correction (paper: 1 and 1)                    */
+    int32_t nu_coarse;       /* sweeps on the coarsest level (paper: 1, or 5
+                                for its four-level variant, Sec. 7.3.1)        */
+    double rho;              /* SOR relaxation factor, 0 < rho < 2 (1 = plain) */
+    int32_t prolong;         /* 0 = bilinear (paper), 1 = piecewise constant   */
+    int32_t precision;       /* ELL_FP64, ELL_FP32_PRECOND, ELL_FP32_BF16COEF  */
+} ell_grid_desc;
+
+typedef struct {
+    double rtol;             /* stop when ||r_K|| < rtol * ||r_0|| ...         */
+    double atol;             /* ... or ||r_K|| < atol (Appendix B, PCG)        */
+    int32_t maxiter;         /* > 0                                            */
+    int32_t flexible;        /* 1: beta = <z_K, r_K - r_{K-1}> / <z_{K-1}, r_{K-1}>
+                                (robust to a non-symmetric V-cycle);
+                                0: beta = <r_K,z_K>/<r_{K-1},z_{K-1}> as printed */
+    int32_t rel_to_rhs;      /* 1: the relative test uses ||b|| = ||V f||
+                                instead of ||r_0|| (warm starts)               */
+    int32_t poll_every;      /* iterations enqueued between host polls of the
+                                device-side convergence flag; 0 = default (4).
+                                Does not change the result.                   */
+} ell_solve_opts;
+
+typedef struct {
+    int32_t iters;           /* completed CG iterations K                      */
+    int32_t status;          /* ELL_OK, ELL_NOT_CONVERGED or ELL_ERR_NUMERIC   */
+    double r0_norm;          /* ||b - A u_0||                                  */
+    double r_norm;           /* ||r_K|| of the CG recurrence                   */
+    double true_r_norm;      /* ||b - A u_K|| recomputed in FP64 at the end    */
+    double b_norm;           /* ||b||, b = V f                                 */
+} ell_solve_stats;
+
+/* Build the level hierarchy: coefficient tables and Thomas factors for every
+ * level (Sec. 6.2.1: only O(nz) numbers per level, nothing per column) and
+ * all device work space.  Synchronous.  *out receives the new grid. */
+int ell_grid_create(const ell_grid_desc *desc, ell_grid **out);
+int ell_grid_destroy(ell_grid *g);
+
+/* Device bytes ell_grid_create would allocate for desc (0 if invalid). */
+size_t ell_grid_bytes(const ell_grid_desc *desc);
+
+/* Number of multigrid levels of the grid (>= 1), or a negative error. */
+int ell_grid_levels(const ell_grid *g);
+
+/* y = A x: the operator of eq. ModelEquation integrated over every cell
+ * (cell volume V = hx*hy*dz_k), so A is symmetric positive definite.
+ * x, y: device, plane-major, nx*ny*nz doubles, must not alias. */
+int ell_apply_A(ell_grid *g, const double *x, double *y, hipStream_t stream);
+
+/* z = M^{-1} r: one V-cycle (Alg. "Multigrid V-cycle") from a zero initial
+ * guess with right-hand side r.  Runs in the grid's precision; r and z are
+ * FP64 device vectors, plane-major, must not alias. */
+int ell_vcycle(ell_grid *g, const double *r, double *z, hipStream_t stream);
+
+/* Solve A u = V f by preconditioned CG (Appendix B) with one V-cycle as the
+ * preconditioner.  f: device, the per-volume right-hand side; u: device, the
+ * initial guess on entry and the solution on return.  opts may be NULL
+ * (rtol 1e-5, flexible, maxiter 500).  stats may be NULL. */
+int ell_pcg_solve(ell_grid *g, const double *f, double *u, const ell_solve_opts *opts,
+                  ell_solve_stats *stats, hipStream_t stream);
+
+/* ---- level entry points (the V-cycle's kernels one at a time) ------------
+ * Colour-split layout of level l (nx_l = nx >> l, ny_l = ny >> l): element
+ * (i, j, k) of colour c = (i+j) mod 2 lives at c*nz*H + k*H + m, where
+ * H = ceil(nx_l*ny_l/2) and m = j*(nx_l/2) + i/2 (m = j/2 when nx_l = 1).
+ * Element type: double for ELL_FP64 grids, float otherwise. */
+size_t ell_level_elems(const ell_grid *g, int level);  /* 2*nz*H; 0 if invalid */
+
+/* plane-major FP64 -> split / split -> plane-major FP64 conversion */
+int ell_to_split(ell_grid *g, int level, const double *src, void *dst, hipStream_t stream);
+int ell_from_split(ell_grid *g, int level, const void *src, double *dst, hipStream_t stream);
+
+/* One colour of block SOR (Sec. 4.2 eq. BlockRBSOR) on level l: every column
+ * of colour c gets its vertical tridiagonal system solved with the other
+ * colour's values on the right-hand side.  zero_init = 1 asserts u = 0 on
+ * entry (neighbour and old values are then not read). */
+int ell_level_smooth(ell_grid *g, int level, int colour, int zero_init, const void *b, void *u,
+                     hipStream_t stream);
+
+/* bc = R (b - A_l u): residual on level l summed over each 2x2 block of
+ * children into level l+1 (Alg. "Multigrid V-cycle", restriction step).
+ * black_zero = 1 asserts that the residual vanishes on colour-1 columns (true
+ * right after a colour-1 sweep with rho = 1); those columns are skipped. */
+int ell_level_resid_restrict(ell_grid *g, int level, const void *b, const void *u, void *bc,
+                             int black_zero, hipStream_t stream);
+
+/* u += P uc: interpolation from level l+1 to level l (bilinear 9/3/3/1 or
+ * piecewise constant, per the grid).  red_only = 1 updates colour-0 columns
+ * only (the colour-1 values are about to be overwritten by a rho = 1 sweep). */
+int ell_level_prolong_add(ell_grid *g, int level, const void *uc, void *u, int red_only,
+                          hipStream_t stream);
+
+/* y = A_l x on level l in the split layout. */
+int ell_level_apply(ell_grid *g, int level, const void *x, void *y, hipStream_t stream);
+
+/* ---- measurement -----------------------------------------------------------
+ * Kernel timing with HIP events recorded on the launch stream around each
+ * launch of one kernel family during subsequent calls (up to max_events
+ * launches).  Families: ELL_K_SMOOTH0 (finest-level line relaxation),
+ * ELL_K_APPLY (CG operator application), ELL_K_RESTRICT0, ELL_K_PROLONG0,
+ * ELL_K_UPDATE (CG vector update). */
+enum { ELL_K_SMOOTH0 = 0, ELL_K_APPLY = 1, ELL_K_RESTRICT0 = 2, ELL_K_PROLONG0 = 3,
+       ELL_K_UPDATE = 4, ELL_K_COUNT = 5 };
+int ell_profile_enable(ell_grid *g, int family, int max_events);
+/* Synchronises the recorded events; *count launches, *total_ms summed time. */
+int ell_profile_read(ell_grid *g, int family, int *count, double *total_ms);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *ell_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ELL_H */

@@ -1,0 +1,783 @@
+// Host side of the C ABI declared in include/ell.h: grid/level construction,
+// the V-cycle schedule and the preconditioned CG driver for one MI355X.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ell.h"
+#include "ell_kernels.hpp"
+
+using namespace ell;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ELL_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+#define CHK(expr)                \
+  do {                           \
+    int rc_ = (expr);            \
+    if (rc_ != ELL_OK) return rc_; \
+  } while (0)
+
+int check_launch(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ELL_ERR_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+  return ELL_OK;
+}
+
+inline int blocks8(long long threads) {
+  long long b = (threads + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  b = (b + 7) / 8 * 8;
+  return (int)b;
+}
+
+// Grid of a flat vector kernel over n2 element pairs: a fixed function of n2,
+// so reductions over it are reproducible.
+inline int flat_blocks(long long n2) {
+  long long b = (n2 + kBlock * 4 - 1) / (kBlock * 4);
+  if (b > 2048) b = 2048;
+  if (b < 8) b = 8;
+  return (int)((b + 7) / 8 * 8);
+}
+
+bool can_halve(int n) { return n % 2 == 0 && ((n / 2) % 2 == 0 || n / 2 == 1); }
+
+int standard_depth(int nx, int ny) {
+  int L = 1;
+  while (can_halve(nx) && can_halve(ny)) {
+    nx /= 2;
+    ny /= 2;
+    ++L;
+  }
+  return L;
+}
+
+// Round to the nearest bfloat16 (ties to even), returned as float.
+float round_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return x;
+  uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  u &= 0xffff0000u;
+  float r;
+  std::memcpy(&r, &u, 4);
+  return r;
+}
+
+struct Prof {
+  int cap = 0;
+  int n = 0;
+  std::vector<hipEvent_t> ev;
+};
+
+struct Level {
+  Geo geo;
+  double hx, hy;
+  void *tab = nullptr;  // device table, element type of the V-cycle
+  void *b = nullptr;    // levels >= 1: right-hand side (split)
+  void *u = nullptr;    // levels >= 1: correction (split)
+};
+
+}  // namespace
+
+struct ell_grid {
+  ell_grid_desc d;
+  std::vector<double> dz, lam;
+  int L = 0;
+  int prec = ELL_FP64;
+  size_t esz = 8;
+  std::vector<Level> lev;
+  long long n0 = 0;          // split elements of level 0 (2*cs)
+  double *us = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  void *b32 = nullptr, *z32 = nullptr;  // FP32 preconditioner: level-0 b and z
+  void *ybuf = nullptr;                 // rho != 1: forward-sweep values
+  double *vol0 = nullptr;               // level-0 cell volumes (FP64, nz)
+  const double *tab64_0 = nullptr;      // level-0 FP64 table of the CG operator
+  double *partial = nullptr;
+  long long partial_cap = 0;
+  PcgState *st = nullptr;
+  PcgState *st_host = nullptr;          // pinned
+  Prof prof[ELL_K_COUNT];
+  std::vector<void *> allocs;
+};
+
+namespace {
+
+int dalloc(ell_grid *g, void **p, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(ELL_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  g->allocs.push_back(*p);
+  HIPCHK(hipMemset(*p, 0, bytes));
+  return ELL_OK;
+}
+
+Geo make_geo(int nx, int ny, int nz) {
+  Geo G;
+  G.nx = nx;
+  G.ny = ny;
+  G.nz = nz;
+  long long ncols = (long long)nx * ny;
+  G.H = (int)((ncols + 1) / 2);
+  G.ncol0 = (int)((ncols + 1) / 2);
+  G.ncol1 = (int)(ncols / 2);
+  G.hx2 = nx > 1 ? nx / 2 : 0;
+  G.has_x = nx > 1;
+  G.has_y = ny > 1;
+  G.P = nz + 1;
+  G.cs = (long long)nz * G.H;
+  return G;
+}
+
+int validate(const ell_grid_desc *d, int *levels) {
+  if (!d) return fail(ELL_ERR_INVALID, "descriptor is NULL");
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(ELL_ERR_INVALID, "sizes must be >= 1");
+  if ((d->nx > 1 && d->nx % 2) || (d->ny > 1 && d->ny % 2))
+    return fail(ELL_ERR_INVALID, "nx and ny must each be even or 1 (red/black colouring)");
+  if ((long long)d->nx * d->ny > (1LL << 30) || (long long)d->nx * d->ny * d->nz > (1LL << 36))
+    return fail(ELL_ERR_INVALID, "grid too large");
+  if (!(d->hx > 0) || !(d->hy > 0) || !std::isfinite(d->hx) || !std::isfinite(d->hy))
+    return fail(ELL_ERR_INVALID, "hx and hy must be positive");
+  if (!(d->omega2 >= 0) || !std::isfinite(d->omega2)) return fail(ELL_ERR_INVALID, "omega2 must be >= 0");
+  if (!d->dz || !d->lambda2) return fail(ELL_ERR_INVALID, "dz and lambda2 are required");
+  for (int k = 0; k < d->nz; ++k) {
+    if (!(d->dz[k] > 0) || !std::isfinite(d->dz[k])) return fail(ELL_ERR_INVALID, "dz[%d] must be positive", k);
+    if (!(d->lambda2[k] > 0) || !std::isfinite(d->lambda2[k]))
+      return fail(ELL_ERR_INVALID, "lambda2[%d] must be positive", k);
+  }
+  if (d->nu_pre < 0 || d->nu_post < 0 || d->nu_coarse < 0 || d->nu_pre > 64 || d->nu_post > 64 ||
+      d->nu_coarse > 1024)
+    return fail(ELL_ERR_INVALID, "sweep counts out of range");
+  if (!(d->rho > 0 && d->rho < 2)) return fail(ELL_ERR_INVALID, "rho must lie in (0, 2)");
+  if (d->prolong != 0 && d->prolong != 1) return fail(ELL_ERR_INVALID, "prolong must be 0 or 1");
+  if (d->precision < ELL_FP64 || d->precision > ELL_FP32_BF16COEF)
+    return fail(ELL_ERR_INVALID, "unknown precision");
+  const int Ls = standard_depth(d->nx, d->ny);
+  int L = d->n_levels <= 0 ? Ls : d->n_levels;
+  if (L > Ls) return fail(ELL_ERR_INVALID, "n_levels %d exceeds the possible depth %d", d->n_levels, Ls);
+  *levels = L;
+  return ELL_OK;
+}
+
+// Coefficients of level l in FP64: V, Tx, Ty, Tz (nz+1), and the Thomas
+// factors 1/p_k and T_{k+1/2}/p_k of the column matrix
+//   diag s_k + T_{k-1/2} + T_{k+1/2}, off-diagonals -T_{k+-1/2},
+// with the pivot written p_k = T_{k+1/2} + e_k, e_0 = s_0,
+// e_k = s_k + T_{k-1/2} e_{k-1} / (T_{k-1/2} + e_{k-1}); s_k = V_k + 2Tx_k + 2Ty_k
+// is the part of the diagonal that the vertical couplings do not cancel.
+// Face coefficients: omega^2 * area / distance; vertical faces combine the two
+// half-cell resistances dz/(2 lambda^2) in series (Sec. 3.1).
+void level_table64(const ell_grid *g, int l, std::vector<double> &t) {
+  const int nz = g->d.nz, P = nz + 1;
+  const int nx = g->d.nx >> l, ny = g->d.ny >> l;
+  const double hx = g->d.hx * (double)(1 << l), hy = g->d.hy * (double)(1 << l);
+  const double w2 = g->d.omega2;
+  t.assign((size_t)TSLOTS * P, 0.0);
+  double *V = &t[TV * P], *Tx = &t[TX * P], *Ty = &t[TY * P], *Tz = &t[TZ * P];
+  double *ip = &t[TIP * P], *cf = &t[TCF * P];
+  for (int k = 0; k < nz; ++k) {
+    V[k] = hx * hy * g->dz[k];
+    Tx[k] = nx > 1 ? w2 * hy * g->dz[k] / hx : 0.0;
+    Ty[k] = ny > 1 ? w2 * hx * g->dz[k] / hy : 0.0;
+  }
+  Tz[0] = 0.0;
+  Tz[nz] = 0.0;
+  for (int k = 1; k < nz; ++k) {
+    const double res = g->dz[k - 1] / (2.0 * g->lam[k - 1]) + g->dz[k] / (2.0 * g->lam[k]);
+    Tz[k] = w2 * hx * hy / res;
+  }
+  double e = 0.0;
+  for (int k = 0; k < nz; ++k) {
+    const double s = (V[k] + 2.0 * Tx[k]) + 2.0 * Ty[k];
+    e = k == 0 ? s : s + Tz[k] * e / (Tz[k] + e);
+    const double p = Tz[k + 1] + e;
+    ip[k] = 1.0 / p;
+    cf[k] = Tz[k + 1] / p;
+  }
+}
+
+// FP32 tables: either the FP64 values rounded once, or (BF16 mode) the
+// stencil coefficients rounded to bfloat16 and the Thomas factors recomputed
+// in FP32 from those rounded coefficients.
+void level_table32(const ell_grid *g, int l, const std::vector<double> &t64, std::vector<float> &t) {
+  const int nz = g->d.nz, P = nz + 1;
+  t.assign((size_t)TSLOTS * P, 0.0f);
+  for (size_t i = 0; i < t64.size(); ++i) t[i] = (float)t64[i];
+  if (g->prec != ELL_FP32_BF16COEF) return;
+  for (int s = TV; s <= TZ; ++s)
+    for (int k = 0; k < P; ++k) t[s * P + k] = round_bf16(t[s * P + k]);
+  float *V = &t[TV * P], *Tx = &t[TX * P], *Ty = &t[TY * P], *Tz = &t[TZ * P];
+  float *ip = &t[TIP * P], *cf = &t[TCF * P];
+  float e = 0.0f;
+  for (int k = 0; k < nz; ++k) {
+    const float s = (V[k] + 2.0f * Tx[k]) + 2.0f * Ty[k];
+    e = k == 0 ? s : s + Tz[k] * e / (Tz[k] + e);
+    const float p = Tz[k + 1] + e;
+    ip[k] = 1.0f / p;
+    cf[k] = Tz[k + 1] / p;
+  }
+}
+
+size_t grid_bytes(const ell_grid_desc *d, int L) {
+  const size_t es = d->precision == ELL_FP64 ? 8 : 4;
+  const Geo g0 = make_geo(d->nx, d->ny, d->nz);
+  const size_t n0 = 2 * (size_t)g0.cs;
+  size_t bytes = 5 * n0 * 8;                           // u, r, z, p, q (FP64)
+  if (d->precision != ELL_FP64) bytes += 2 * n0 * 4;   // b32, z32
+  if (d->rho != 1.0) bytes += (size_t)g0.cs * es;      // ybuf
+  for (int l = 0; l < L; ++l) {
+    const Geo G = make_geo(d->nx >> l, d->ny >> l, d->nz);
+    bytes += (size_t)TSLOTS * G.P * es;
+    if (l > 0) bytes += 2 * 2 * (size_t)G.cs * es;
+  }
+  const long long nb = std::max<long long>(blocks8(2 * (long long)g0.H), flat_blocks(n0 / 2));
+  bytes += (size_t)nb * 2 * 8 + sizeof(PcgState) + (size_t)d->nz * 8;
+  return bytes;
+}
+
+// ------------------------------------------------------------------------
+// profiling helpers
+// ------------------------------------------------------------------------
+struct ProfScope {
+  Prof *p;
+  hipStream_t s;
+  bool on;
+  ProfScope(ell_grid *g, int fam, hipStream_t st, bool enabled = true) : p(&g->prof[fam]), s(st) {
+    on = enabled && p->cap > 0 && p->n < p->cap;
+    if (on) (void)hipEventRecord(p->ev[2 * p->n], s);
+  }
+  ~ProfScope() {
+    if (on) {
+      (void)hipEventRecord(p->ev[2 * p->n + 1], s);
+      p->n++;
+    }
+  }
+};
+
+// ------------------------------------------------------------------------
+// kernel launchers (element type R = double or float)
+// ------------------------------------------------------------------------
+template <typename R>
+int launch_smooth(ell_grid *g, int l, int c, bool zero, const R *b, R *u, const int *done, hipStream_t s) {
+  const Level &Lv = g->lev[l];
+  const Geo &G = Lv.geo;
+  const int ncol = c ? G.ncol1 : G.ncol0;
+  if (ncol == 0) return ELL_OK;
+  const int nb = blocks8(ncol);
+  const R *tab = (const R *)Lv.tab;
+  const bool rho1 = g->d.rho == 1.0;
+  R *yb = (R *)g->ybuf;
+  const R rho = (R)g->d.rho;
+  ProfScope ps(g, ELL_K_SMOOTH0, s, l == 0);
+  if (zero && rho1) k_smooth<R, true, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+  else if (zero) k_smooth<R, true, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+  else if (rho1) k_smooth<R, false, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+  else k_smooth<R, false, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+  return check_launch("k_smooth");
+}
+
+template <typename R>
+int launch_restrict(ell_grid *g, int l, const R *b, const R *u, R *bc, bool bz, const int *done,
+                    hipStream_t s) {
+  const Geo &F = g->lev[l].geo, &C = g->lev[l + 1].geo;
+  const int nb = blocks8(2LL * C.H);
+  const R *tab = (const R *)g->lev[l].tab;
+  ProfScope ps(g, ELL_K_RESTRICT0, s, l == 0);
+  if (bz) k_resid_restrict<R, true><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
+  else k_resid_restrict<R, false><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
+  return check_launch("k_resid_restrict");
+}
+
+template <typename R>
+int launch_prolong(ell_grid *g, int l, const R *uc, R *u, bool red_only, const int *done, hipStream_t s) {
+  const Geo &F = g->lev[l].geo, &C = g->lev[l + 1].geo;
+  const int nb = blocks8(red_only ? (long long)F.ncol0 : 2LL * F.H);
+  ProfScope ps(g, ELL_K_PROLONG0, s, l == 0);
+  if (g->d.prolong == 1) {
+    if (red_only) k_prolong<R, true, 1><<<nb, kBlock, 0, s>>>(F, C, uc, u, done);
+    else k_prolong<R, false, 1><<<nb, kBlock, 0, s>>>(F, C, uc, u, done);
+  } else {
+    if (red_only) k_prolong<R, true, 0><<<nb, kBlock, 0, s>>>(F, C, uc, u, done);
+    else k_prolong<R, false, 0><<<nb, kBlock, 0, s>>>(F, C, uc, u, done);
+  }
+  return check_launch("k_prolong");
+}
+
+template <typename R>
+int launch_fill(R *p, long long n, hipStream_t s) {
+  k_fill<R><<<flat_blocks(n / 2 + 1), kBlock, 0, s>>>(p, n, R(0));
+  return check_launch("k_fill");
+}
+
+// One V-cycle from u = 0 (Alg. "Multigrid V-cycle"), levels numbered from the
+// finest (0).  Pre-smoothing sweeps red then black, post-smoothing black then
+// red.  With rho = 1 two exact shortcuts apply: after a black sweep the black
+// residual is zero (only red children are restricted) and a black sweep
+// ignores the old black values (the correction is added to red columns only).
+template <typename R>
+int vcycle_impl(ell_grid *g, const R *b0, R *u0, const int *done, hipStream_t s) {
+  const int L = g->L;
+  const bool rho1 = g->d.rho == 1.0;
+  auto B = [&](int l) -> const R * { return l == 0 ? b0 : (const R *)g->lev[l].b; };
+  auto U = [&](int l) -> R * { return l == 0 ? u0 : (R *)g->lev[l].u; };
+  for (int l = 0; l < L - 1; ++l) {
+    if (g->d.nu_pre == 0) CHK(launch_fill<R>(U(l), 2 * g->lev[l].geo.cs, s));
+    for (int it = 0; it < g->d.nu_pre; ++it) {
+      CHK(launch_smooth<R>(g, l, 0, it == 0, B(l), U(l), done, s));
+      CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
+    }
+    CHK(launch_restrict<R>(g, l, B(l), U(l), (R *)g->lev[l + 1].b, rho1 && g->d.nu_pre > 0, done, s));
+  }
+  {
+    const int l = L - 1;
+    if (g->d.nu_coarse == 0) CHK(launch_fill<R>(U(l), 2 * g->lev[l].geo.cs, s));
+    for (int it = 0; it < g->d.nu_coarse; ++it) {
+      CHK(launch_smooth<R>(g, l, 0, it == 0, B(l), U(l), done, s));
+      CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
+    }
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    CHK(launch_prolong<R>(g, l, (const R *)g->lev[l + 1].u, U(l), rho1 && g->d.nu_post > 0, done, s));
+    for (int it = 0; it < g->d.nu_post; ++it) {
+      CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
+      CHK(launch_smooth<R>(g, l, 0, false, B(l), U(l), done, s));
+    }
+  }
+  return ELL_OK;
+}
+
+int launch_apply64(ell_grid *g, const double *x, double *y, bool dot, const int *done, hipStream_t s) {
+  const Geo &G = g->lev[0].geo;
+  const int nb = blocks8(2LL * G.H);
+  // the CG operator is always FP64 (FP32 grids keep a separate FP64 table)
+  const double *tab64 = g->tab64_0;
+  ProfScope ps(g, ELL_K_APPLY, s, dot);
+  if (dot) k_apply<double, true><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+  else k_apply<double, false><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+  return check_launch("k_apply");
+}
+
+int finalize(ell_grid *g, int nblk, int nq, int mode, hipStream_t s, double rtol = 0, double atol = 0,
+             int rel = 0) {
+  k_finalize<<<1, kBlock, 0, s>>>(g->partial, nblk, nq, g->st, mode, rtol, atol, rel);
+  return check_launch("k_finalize");
+}
+
+template <typename R>
+int precondition(ell_grid *g, const int *done, hipStream_t s);
+
+template <>
+int precondition<double>(ell_grid *g, const int *done, hipStream_t s) {
+  return vcycle_impl<double>(g, g->r, g->z, done, s);
+}
+
+template <>
+int precondition<float>(ell_grid *g, const int *done, hipStream_t s) {
+  const long long n2 = g->n0 / 2;
+  k_cast_f64_f32<<<flat_blocks(n2), kBlock, 0, s>>>((const double2 *)g->r, (float2 *)g->b32, n2, done);
+  CHK(check_launch("k_cast_f64_f32"));
+  return vcycle_impl<float>(g, (const float *)g->b32, (float *)g->z32, done, s);
+}
+
+template <typename R>
+int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, ell_solve_stats *out,
+             hipStream_t s) {
+  using Z = R;
+  const Geo &G = g->lev[0].geo;
+  const long long n2 = g->n0 / 2;
+  const int fb = flat_blocks(n2);
+  const int ab = blocks8(2LL * G.H);
+  const int *done = &g->st->done;
+  const typename Vec2<Z>::T *zv =
+      (const typename Vec2<Z>::T *)(g->prec == ELL_FP64 ? (void *)g->z : g->z32);
+
+  // r = V f - A u0 (split layout), ||b||, ||r0||
+  const int cb = blocks8(2LL * G.H);
+  k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, f, g->r, g->vol0);
+  CHK(check_launch("k_nat2split"));
+  k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, u, g->us, nullptr);
+  CHK(check_launch("k_nat2split"));
+  CHK(launch_apply64(g, g->us, g->q, false, nullptr, s));
+  k_resid_init<<<fb, kBlock, 0, s>>>((const double2 *)g->q, (double2 *)g->r, n2, g->partial);
+  CHK(check_launch("k_resid_init"));
+  k_finalize<<<1, kBlock, 0, s>>>(g->partial, fb, 2, g->st, F_INIT, o.rtol, o.atol, o.rel_to_rhs);
+  CHK(check_launch("k_finalize"));
+  // maxiter / flexible live in the state block
+  {
+    PcgState *h = g->st_host;
+    h->maxiter = o.maxiter;
+    h->flexible = o.flexible;
+    HIPCHK(hipMemcpyAsync(&g->st->maxiter, &h->maxiter, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  // z0 = M^{-1} r0, kappa = <r0, z0>
+  CHK(precondition<R>(g, done, s));
+  k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zv, (const double2 *)g->q, n2, g->st, g->partial);
+  CHK(check_launch("k_dots"));
+  CHK(finalize(g, fb, 2, F_KAPPA, s));
+
+  const int poll = o.poll_every > 0 ? o.poll_every : 4;
+  int enq = 0;
+  bool first = true;
+  while (enq < o.maxiter) {
+    const int batch = std::min(poll, o.maxiter - enq);
+    for (int it = 0; it < batch; ++it) {
+      k_dir<Z><<<fb, kBlock, 0, s>>>((double2 *)g->p, zv, n2, g->st, first ? 1 : 0);
+      CHK(check_launch("k_dir"));
+      first = false;
+      CHK(launch_apply64(g, g->p, g->q, true, done, s));
+      CHK(finalize(g, ab, 1, F_ALPHA, s));
+      {
+        ProfScope ps(g, ELL_K_UPDATE, s);
+        k_update<<<fb, kBlock, 0, s>>>((double2 *)g->us, (const double2 *)g->p, (double2 *)g->r,
+                                       (const double2 *)g->q, n2, g->st, g->partial);
+      }
+      CHK(check_launch("k_update"));
+      CHK(finalize(g, fb, 1, F_CONV, s));
+      CHK(precondition<R>(g, done, s));
+      k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zv, (const double2 *)g->q, n2, g->st,
+                                      g->partial);
+      CHK(check_launch("k_dots"));
+      CHK(finalize(g, fb, 2, F_BETA, s));
+    }
+    enq += batch;
+    HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (g->st_host->done) break;
+  }
+  // solution back to plane-major, true residual ||V f - A u||
+  k_split2nat<double, double><<<cb, kBlock, 0, s>>>(G, g->us, u);
+  CHK(check_launch("k_split2nat"));
+  k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, f, g->r, g->vol0);
+  CHK(check_launch("k_nat2split"));
+  CHK(launch_apply64(g, g->us, g->q, false, nullptr, s));
+  k_resid_init<<<fb, kBlock, 0, s>>>((const double2 *)g->q, (double2 *)g->r, n2, g->partial);
+  CHK(check_launch("k_resid_init"));
+  k_finalize<<<1, kBlock, 0, s>>>(g->partial, fb, 2, g->st, F_TRUE, 0, 0, 0);
+  CHK(check_launch("k_finalize"));
+  HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const PcgState &h = *g->st_host;
+  int status = h.status;
+  if (!h.done && status == 1) status = 1;
+  if (out) {
+    out->iters = h.iter;
+    out->status = status == -4 ? ELL_ERR_NUMERIC : (status == 0 ? ELL_OK : ELL_NOT_CONVERGED);
+    out->r0_norm = h.r0_norm;
+    out->r_norm = h.r_norm;
+    out->true_r_norm = h.true_r_norm;
+    out->b_norm = h.b_norm;
+  }
+  if (status == -4) return fail(ELL_ERR_NUMERIC, "non-finite value in the CG recurrence");
+  return status == 0 ? ELL_OK : ELL_NOT_CONVERGED;
+}
+
+int check_level(const ell_grid *g, int level, bool need_coarser) {
+  if (!g) return fail(ELL_ERR_INVALID, "grid is NULL");
+  if (level < 0 || level >= g->L) return fail(ELL_ERR_INVALID, "level %d out of range", level);
+  if (need_coarser && level + 1 >= g->L) return fail(ELL_ERR_INVALID, "level %d has no coarser level", level);
+  return ELL_OK;
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+const char *ell_last_error(void) { return g_err.c_str(); }
+
+size_t ell_grid_bytes(const ell_grid_desc *desc) {
+  int L = 0;
+  if (validate(desc, &L) != ELL_OK) return 0;
+  return grid_bytes(desc, L);
+}
+
+int ell_grid_create(const ell_grid_desc *desc, ell_grid **out) {
+  if (!out) return fail(ELL_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  int L = 0;
+  CHK(validate(desc, &L));
+  ell_grid *g = new ell_grid();
+  g->d = *desc;
+  g->dz.assign(desc->dz, desc->dz + desc->nz);
+  g->lam.assign(desc->lambda2, desc->lambda2 + desc->nz);
+  g->d.dz = g->dz.data();
+  g->d.lambda2 = g->lam.data();
+  g->L = L;
+  g->prec = desc->precision;
+  g->esz = g->prec == ELL_FP64 ? 8 : 4;
+  g->lev.resize(L);
+  auto bail = [&](int rc) {
+    ell_grid_destroy(g);
+    return rc;
+  };
+  int rc;
+  std::vector<double> t64;
+  std::vector<float> t32;
+  for (int l = 0; l < L; ++l) {
+    Level &Lv = g->lev[l];
+    Lv.geo = make_geo(desc->nx >> l, desc->ny >> l, desc->nz);
+    Lv.hx = desc->hx * (double)(1 << l);
+    Lv.hy = desc->hy * (double)(1 << l);
+    level_table64(g, l, t64);
+    const size_t tb = t64.size() * g->esz;
+    if ((rc = dalloc(g, &Lv.tab, tb)) != ELL_OK) return bail(rc);
+    if (g->prec == ELL_FP64) {
+      if (hipMemcpy(Lv.tab, t64.data(), tb, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(ELL_ERR_HIP, "table upload failed"));
+    } else {
+      level_table32(g, l, t64, t32);
+      if (hipMemcpy(Lv.tab, t32.data(), tb, hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(ELL_ERR_HIP, "table upload failed"));
+    }
+    if (l > 0) {
+      const size_t vb = 2 * (size_t)Lv.geo.cs * g->esz;
+      if ((rc = dalloc(g, &Lv.b, vb)) != ELL_OK) return bail(rc);
+      if ((rc = dalloc(g, &Lv.u, vb)) != ELL_OK) return bail(rc);
+    }
+  }
+  const Geo &G0 = g->lev[0].geo;
+  g->n0 = 2 * G0.cs;
+  const size_t vb = (size_t)g->n0 * 8;
+  void *tmp;
+  if ((rc = dalloc(g, &tmp, vb)) != ELL_OK) return bail(rc);
+  g->us = (double *)tmp;
+  if ((rc = dalloc(g, &tmp, vb)) != ELL_OK) return bail(rc);
+  g->r = (double *)tmp;
+  if ((rc = dalloc(g, &tmp, vb)) != ELL_OK) return bail(rc);
+  g->z = (double *)tmp;
+  if ((rc = dalloc(g, &tmp, vb)) != ELL_OK) return bail(rc);
+  g->p = (double *)tmp;
+  if ((rc = dalloc(g, &tmp, vb)) != ELL_OK) return bail(rc);
+  g->q = (double *)tmp;
+  if (g->prec != ELL_FP64) {
+    if ((rc = dalloc(g, &g->b32, (size_t)g->n0 * 4)) != ELL_OK) return bail(rc);
+    if ((rc = dalloc(g, &g->z32, (size_t)g->n0 * 4)) != ELL_OK) return bail(rc);
+  }
+  if (desc->rho != 1.0)
+    if ((rc = dalloc(g, &g->ybuf, (size_t)G0.cs * g->esz)) != ELL_OK) return bail(rc);
+  const long long nb = std::max<long long>(blocks8(2LL * G0.H), flat_blocks(g->n0 / 2));
+  g->partial_cap = nb * 2;
+  if ((rc = dalloc(g, &tmp, (size_t)g->partial_cap * 8)) != ELL_OK) return bail(rc);
+  g->partial = (double *)tmp;
+  if ((rc = dalloc(g, &tmp, sizeof(PcgState))) != ELL_OK) return bail(rc);
+  g->st = (PcgState *)tmp;
+  if (hipHostMalloc((void **)&g->st_host, sizeof(PcgState), hipHostMallocDefault) != hipSuccess) {
+    g->st_host = nullptr;
+    return bail(fail(ELL_ERR_OOM, "pinned state allocation failed"));
+  }
+  std::memset(g->st_host, 0, sizeof(PcgState));
+  {
+    std::vector<double> V(desc->nz);
+    for (int k = 0; k < desc->nz; ++k) V[k] = desc->hx * desc->hy * desc->dz[k];
+    if ((rc = dalloc(g, &tmp, V.size() * 8)) != ELL_OK) return bail(rc);
+    g->vol0 = (double *)tmp;
+    if (hipMemcpy(g->vol0, V.data(), V.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(ELL_ERR_HIP, "volume upload failed"));
+  }
+  if (g->prec != ELL_FP64) {
+    level_table64(g, 0, t64);
+    if ((rc = dalloc(g, &tmp, t64.size() * 8)) != ELL_OK) return bail(rc);
+    if (hipMemcpy(tmp, t64.data(), t64.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(ELL_ERR_HIP, "table upload failed"));
+    g->tab64_0 = (const double *)tmp;
+  } else {
+    g->tab64_0 = (const double *)g->lev[0].tab;
+  }
+  *out = g;
+  return ELL_OK;
+}
+
+int ell_grid_destroy(ell_grid *g) {
+  if (!g) return ELL_OK;
+  for (auto &p : g->prof)
+    for (auto &e : p.ev) (void)hipEventDestroy(e);
+  for (void *p : g->allocs) (void)hipFree(p);
+  if (g->st_host) (void)hipHostFree(g->st_host);
+  delete g;
+  return ELL_OK;
+}
+
+int ell_grid_levels(const ell_grid *g) {
+  if (!g) return fail(ELL_ERR_INVALID, "grid is NULL");
+  return g->L;
+}
+
+int ell_apply_A(ell_grid *g, const double *x, double *y, hipStream_t s) {
+  if (!g || !x || !y) return fail(ELL_ERR_INVALID, "NULL argument");
+  if (x == y) return fail(ELL_ERR_INVALID, "x and y must not alias");
+  const Geo &G = g->lev[0].geo;
+  const int cb = blocks8(2LL * G.H);
+  k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, x, g->p, nullptr);
+  CHK(check_launch("k_nat2split"));
+  CHK(launch_apply64(g, g->p, g->q, false, nullptr, s));
+  k_split2nat<double, double><<<cb, kBlock, 0, s>>>(G, g->q, y);
+  return check_launch("k_split2nat");
+}
+
+int ell_vcycle(ell_grid *g, const double *r, double *z, hipStream_t s) {
+  if (!g || !r || !z) return fail(ELL_ERR_INVALID, "NULL argument");
+  if (r == z) return fail(ELL_ERR_INVALID, "r and z must not alias");
+  const Geo &G = g->lev[0].geo;
+  const int cb = blocks8(2LL * G.H);
+  if (g->prec == ELL_FP64) {
+    k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, r, g->r, nullptr);
+    CHK(check_launch("k_nat2split"));
+    CHK(vcycle_impl<double>(g, g->r, g->z, nullptr, s));
+    k_split2nat<double, double><<<cb, kBlock, 0, s>>>(G, g->z, z);
+  } else {
+    k_nat2split<double, float><<<cb, kBlock, 0, s>>>(G, r, (float *)g->b32, nullptr);
+    CHK(check_launch("k_nat2split"));
+    CHK(vcycle_impl<float>(g, (const float *)g->b32, (float *)g->z32, nullptr, s));
+    k_split2nat<float, double><<<cb, kBlock, 0, s>>>(G, (const float *)g->z32, z);
+  }
+  return check_launch("k_split2nat");
+}
+
+int ell_pcg_solve(ell_grid *g, const double *f, double *u, const ell_solve_opts *opts,
+                  ell_solve_stats *stats, hipStream_t s) {
+  if (!g || !f || !u) return fail(ELL_ERR_INVALID, "NULL argument");
+  if ((const void *)f == (const void *)u) return fail(ELL_ERR_INVALID, "f and u must not alias");
+  ell_solve_opts o;
+  if (opts) o = *opts;
+  else {
+    o.rtol = 1e-5;
+    o.atol = 0.0;
+    o.maxiter = 500;
+    o.flexible = 1;
+    o.rel_to_rhs = 0;
+    o.poll_every = 4;
+  }
+  if (o.maxiter <= 0 || !(o.rtol >= 0) || !(o.atol >= 0))
+    return fail(ELL_ERR_INVALID, "maxiter must be > 0 and tolerances >= 0");
+  if (g->prec == ELL_FP64) return pcg_impl<double>(g, f, u, o, stats, s);
+  return pcg_impl<float>(g, f, u, o, stats, s);
+}
+
+size_t ell_level_elems(const ell_grid *g, int level) {
+  if (!g || level < 0 || level >= g->L) return 0;
+  return 2 * (size_t)g->lev[level].geo.cs;
+}
+
+int ell_to_split(ell_grid *g, int level, const double *src, void *dst, hipStream_t s) {
+  CHK(check_level(g, level, false));
+  if (!src || !dst) return fail(ELL_ERR_INVALID, "NULL argument");
+  const Geo &G = g->lev[level].geo;
+  const int cb = blocks8(2LL * G.H);
+  if (g->prec == ELL_FP64) k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, src, (double *)dst, nullptr);
+  else k_nat2split<double, float><<<cb, kBlock, 0, s>>>(G, src, (float *)dst, nullptr);
+  return check_launch("k_nat2split");
+}
+
+int ell_from_split(ell_grid *g, int level, const void *src, double *dst, hipStream_t s) {
+  CHK(check_level(g, level, false));
+  if (!src || !dst) return fail(ELL_ERR_INVALID, "NULL argument");
+  const Geo &G = g->lev[level].geo;
+  const int cb = blocks8(2LL * G.H);
+  if (g->prec == ELL_FP64) k_split2nat<double, double><<<cb, kBlock, 0, s>>>(G, (const double *)src, dst);
+  else k_split2nat<float, double><<<cb, kBlock, 0, s>>>(G, (const float *)src, dst);
+  return check_launch("k_split2nat");
+}
+
+int ell_level_smooth(ell_grid *g, int level, int colour, int zero_init, const void *b, void *u,
+                     hipStream_t s) {
+  CHK(check_level(g, level, false));
+  if (colour != 0 && colour != 1) return fail(ELL_ERR_INVALID, "colour must be 0 or 1");
+  if (!b || !u) return fail(ELL_ERR_INVALID, "NULL argument");
+  if (g->prec == ELL_FP64)
+    return launch_smooth<double>(g, level, colour, zero_init != 0, (const double *)b, (double *)u, nullptr, s);
+  return launch_smooth<float>(g, level, colour, zero_init != 0, (const float *)b, (float *)u, nullptr, s);
+}
+
+int ell_level_resid_restrict(ell_grid *g, int level, const void *b, const void *u, void *bc,
+                             int black_zero, hipStream_t s) {
+  CHK(check_level(g, level, true));
+  if (!b || !u || !bc) return fail(ELL_ERR_INVALID, "NULL argument");
+  if (g->prec == ELL_FP64)
+    return launch_restrict<double>(g, level, (const double *)b, (const double *)u, (double *)bc,
+                                   black_zero != 0, nullptr, s);
+  return launch_restrict<float>(g, level, (const float *)b, (const float *)u, (float *)bc, black_zero != 0,
+                                nullptr, s);
+}
+
+int ell_level_prolong_add(ell_grid *g, int level, const void *uc, void *u, int red_only, hipStream_t s) {
+  CHK(check_level(g, level, true));
+  if (!uc || !u) return fail(ELL_ERR_INVALID, "NULL argument");
+  if (g->prec == ELL_FP64)
+    return launch_prolong<double>(g, level, (const double *)uc, (double *)u, red_only != 0, nullptr, s);
+  return launch_prolong<float>(g, level, (const float *)uc, (float *)u, red_only != 0, nullptr, s);
+}
+
+int ell_level_apply(ell_grid *g, int level, const void *x, void *y, hipStream_t s) {
+  CHK(check_level(g, level, false));
+  if (!x || !y || x == y) return fail(ELL_ERR_INVALID, "bad vector arguments");
+  const Geo &G = g->lev[level].geo;
+  const int nb = blocks8(2LL * G.H);
+  if (g->prec == ELL_FP64)
+    k_apply<double, false><<<nb, kBlock, 0, s>>>(G, (const double *)g->lev[level].tab, (const double *)x,
+                                                 (double *)y, nullptr, nullptr);
+  else
+    k_apply<float, false><<<nb, kBlock, 0, s>>>(G, (const float *)g->lev[level].tab, (const float *)x,
+                                                (float *)y, nullptr, nullptr);
+  return check_launch("k_apply");
+}
+
+int ell_profile_enable(ell_grid *g, int family, int max_events) {
+  if (!g || family < 0 || family >= ELL_K_COUNT || max_events < 0)
+    return fail(ELL_ERR_INVALID, "bad profiling arguments");
+  Prof &p = g->prof[family];
+  for (auto &e : p.ev) (void)hipEventDestroy(e);
+  p.ev.assign(2 * (size_t)max_events, nullptr);
+  for (auto &e : p.ev) HIPCHK(hipEventCreate(&e));
+  p.cap = max_events;
+  p.n = 0;
+  return ELL_OK;
+}
+
+int ell_profile_read(ell_grid *g, int family, int *count, double *total_ms) {
+  if (!g || family < 0 || family >= ELL_K_COUNT || !count || !total_ms)
+    return fail(ELL_ERR_INVALID, "bad profiling arguments");
+  Prof &p = g->prof[family];
+  double tot = 0.0;
+  for (int i = 0; i < p.n; ++i) {
+    HIPCHK(hipEventSynchronize(p.ev[2 * i + 1]));
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, p.ev[2 * i], p.ev[2 * i + 1]));
+    tot += ms;
+  }
+  *count = p.n;
+  *total_ms = tot;
+  return ELL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,607 @@
+// Device kernels of the tensor-product multigrid / CG solver for gfx950.
+//
+// Every kernel is HBM-bandwidth bound (well under 1 flop per byte), so the
+// design is about data movement, not arithmetic: one lane owns one vertical
+// column and marches up (and down) the column; columns of one colour are
+// stored contiguously per level ("colour-split" layout, [colour][k][m]), so a
+// wavefront's 64 lanes touch 64 consecutive doubles at every level k and the
+// red/black sweeps read and write full cache lines.  The vertical
+// coefficients depend on k (and the level) only, so every coefficient is a
+// wave-uniform scalar load; nothing is stored per column (Sec. 6.2.1: the
+// matrix is never stored).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ell {
+
+constexpr int kBlock = 256;  // 4 wavefronts of 64 lanes
+
+// Table slots of one level, each nz+1 long (see host-side construction).
+enum : int { TV = 0, TX = 1, TY = 2, TZ = 3, TIP = 4, TCF = 5, TSLOTS = 6 };
+
+// Geometry of one level in the colour-split layout.
+struct Geo {
+  int nx, ny, nz;
+  int H;          // allocated columns per colour array = ceil(nx*ny/2)
+  int ncol0;      // red columns
+  int ncol1;      // black columns
+  int hx2;        // nx/2 (nx > 1)
+  int has_x;      // nx > 1: x faces exist
+  int has_y;      // ny > 1
+  int P;          // table stride = nz + 1
+  long long cs;   // elements per colour array = nz * H
+};
+
+struct PcgState {
+  double kappa_old, alpha, beta, r0_norm, b_norm, r_norm, thresh, true_r_norm;
+  int iter, done, status, maxiter, flexible, pad;
+};
+
+// Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b mod 8);
+// every grid here is a multiple of 8 blocks and this map gives each XCD a
+// contiguous range of logical blocks, so neighbouring rows of columns (which
+// share halo data) meet in the same L2.
+__device__ __forceinline__ int logical_block() {
+  const int g8 = gridDim.x >> 3;
+  return (blockIdx.x & 7) * g8 + (blockIdx.x >> 3);
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ void col_ij(const Geo &L, int c, int m, int &i, int &j) {
+  if (L.nx > 1) {
+    j = m / L.hx2;
+    i = 2 * (m - j * L.hx2) + ((j + c) & 1);
+  } else {
+    i = 0;
+    j = 2 * m + c;
+  }
+}
+
+__device__ __forceinline__ int col_m(const Geo &L, int i, int j) {
+  return L.nx > 1 ? j * L.hx2 + (i >> 1) : (j >> 1);
+}
+
+__device__ __forceinline__ bool is_done(const int *done) { return done != nullptr && *done != 0; }
+
+// Sum over the 256 threads of a block; the result is valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return r;
+}
+
+// -------------------------------------------------------------------------
+// One colour of block red/black SOR (Sec. 4.2 eq. BlockRBSOR): per column of
+// colour c, g_k = b_k + Tx_k (u_W + u_E) + Ty_k (u_S + u_N) with the other
+// colour's values, then the tridiagonal column solve (Thomas, Appendix B)
+// with per-level shared factors: y_k = (g_k + T_{k-1/2} y_{k-1}) / p_k
+// forward, w_k = y_k + (T_{k+1/2}/p_k) w_{k+1} backward.  The forward values y
+// are parked in the output column itself (rho = 1) and read back on the way
+// down, so no per-lane array is needed and occupancy stays high.
+// -------------------------------------------------------------------------
+template <typename R, bool ZERO, bool RHO1>
+__global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ tab, int c,
+                                                   const R *__restrict__ b, R *__restrict__ u,
+                                                   R *__restrict__ ybuf, R rho,
+                                                   const int *__restrict__ done) {
+  if (is_done(done)) return;
+  const int m = logical_block() * kBlock + threadIdx.x;
+  const int ncol = c ? L.ncol1 : L.ncol0;
+  if (m >= ncol) return;
+  int i, j;
+  col_ij(L, c, m, i, j);
+  int mW = 0, mE = 0, mS = 0, mN = 0;
+  if (L.has_x) {
+    mW = col_m(L, wrapi(i - 1, L.nx), j);
+    mE = col_m(L, wrapi(i + 1, L.nx), j);
+  }
+  if (L.has_y) {
+    mS = col_m(L, i, wrapi(j - 1, L.ny));
+    mN = col_m(L, i, wrapi(j + 1, L.ny));
+  }
+  const long long H = L.H;
+  const R *__restrict__ bo = b + (long long)c * L.cs + m;
+  const R *__restrict__ uo = u + (long long)(1 - c) * L.cs;
+  R *__restrict__ own = u + (long long)c * L.cs + m;
+  // forward values: in the output column itself (rho = 1) or in ybuf
+  R *ys = RHO1 ? own : ybuf + m;
+  const R *__restrict__ tx = tab + TX * L.P;
+  const R *__restrict__ ty = tab + TY * L.P;
+  const R *__restrict__ tz = tab + TZ * L.P;
+  const R *__restrict__ ip = tab + TIP * L.P;
+  const R *__restrict__ cf = tab + TCF * L.P;
+  const int nz = L.nz;
+
+  R yprev = R(0);
+#pragma unroll 4
+  for (int k = 0; k < nz; ++k) {
+    const long long o = (long long)k * H;
+    R g = bo[o];
+    if (!ZERO) {
+      if (L.has_x) g = g + tx[k] * (uo[o + mW] + uo[o + mE]);
+      if (L.has_y) g = g + ty[k] * (uo[o + mS] + uo[o + mN]);
+    }
+    const R y = (g + tz[k] * yprev) * ip[k];
+    ys[o] = y;
+    yprev = y;
+  }
+  R w = yprev;
+  if (!RHO1) {
+    const long long o = (long long)(nz - 1) * H;
+    const R old = ZERO ? R(0) : own[o];
+    own[o] = (R(1) - rho) * old + rho * w;
+  }
+#pragma unroll 4
+  for (int k = nz - 2; k >= 0; --k) {
+    const long long o = (long long)k * H;
+    w = (RHO1 ? own[o] : ys[o]) + cf[k] * w;
+    if (RHO1) {
+      own[o] = w;
+    } else {
+      const R old = ZERO ? R(0) : own[o];
+      own[o] = (R(1) - rho) * old + rho * w;
+    }
+  }
+}
+
+// Residual (b - A u) of one cell given its column neighbours at level k.
+template <typename R>
+__device__ __forceinline__ R cell_residual(R bk, R vk, R txk, R tyk, R tzlo, R tzhi, R uc, R um,
+                                           R up, R uW, R uE, R uS, R uN, int hasx, int hasy) {
+  R acc = vk * uc;
+  if (hasx) {
+    acc = acc + txk * (uc - uW);
+    acc = acc + txk * (uc - uE);
+  }
+  if (hasy) {
+    acc = acc + tyk * (uc - uS);
+    acc = acc + tyk * (uc - uN);
+  }
+  acc = acc + tzlo * (uc - um);
+  acc = acc + tzhi * (uc - up);
+  return bk - acc;
+}
+
+// -------------------------------------------------------------------------
+// Residual on the fine level summed over 2x2 children into the coarse
+// right-hand side (Alg. "Multigrid V-cycle": residual, then restriction).
+// One lane per coarse column.  BZ: children of colour 1 carry a zero residual
+// (they were just solved exactly), so only the two colour-0 children are
+// evaluated.
+// -------------------------------------------------------------------------
+template <typename R, bool BZ>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict(Geo F, Geo C, const R *__restrict__ tab,
+                                                           const R *__restrict__ b,
+                                                           const R *__restrict__ u,
+                                                           R *__restrict__ bc,
+                                                           const int *__restrict__ done) {
+  if (is_done(done)) return;
+  const int gid = logical_block() * kBlock + threadIdx.x;
+  if (gid >= 2 * C.H) return;
+  const int cc = gid >= C.H ? 1 : 0;
+  const int mc = gid - cc * C.H;
+  if (mc >= (cc ? C.ncol1 : C.ncol0)) return;
+  int I, J;
+  col_ij(C, cc, mc, I, J);
+
+  // children in the order (0,0), (1,0), (0,1), (1,1); colour of (a,b) is (a+b)&1
+  constexpr int NCH = BZ ? 2 : 4;
+  int ca[NCH], cm[NCH], nW[NCH], nE[NCH], nS[NCH], nN[NCH];
+#pragma unroll
+  for (int t = 0; t < NCH; ++t) {
+    int a, bb;
+    if (BZ) { a = t; bb = t; }                 // (0,0), (1,1)
+    else { a = t & 1; bb = t >> 1; }
+    const int i = 2 * I + a, j = 2 * J + bb;
+    ca[t] = (a + bb) & 1;
+    cm[t] = col_m(F, i, j);
+    nW[t] = F.has_x ? col_m(F, wrapi(i - 1, F.nx), j) : 0;
+    nE[t] = F.has_x ? col_m(F, wrapi(i + 1, F.nx), j) : 0;
+    nS[t] = F.has_y ? col_m(F, i, wrapi(j - 1, F.ny)) : 0;
+    nN[t] = F.has_y ? col_m(F, i, wrapi(j + 1, F.ny)) : 0;
+  }
+  const long long H = F.H;
+  const R *__restrict__ tv = tab + TV * F.P;
+  const R *__restrict__ tx = tab + TX * F.P;
+  const R *__restrict__ ty = tab + TY * F.P;
+  const R *__restrict__ tz = tab + TZ * F.P;
+  const int nz = F.nz;
+
+  R um[NCH], uc[NCH];
+#pragma unroll
+  for (int t = 0; t < NCH; ++t) {
+    uc[t] = u[ca[t] * F.cs + cm[t]];
+    um[t] = uc[t];
+  }
+  R *__restrict__ out = bc + (long long)cc * C.cs + mc;
+  for (int k = 0; k < nz; ++k) {
+    const long long o = (long long)k * H;
+    R acc = R(0);
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+      const R *__restrict__ uo = u + (long long)(1 - ca[t]) * F.cs + o;
+      const R *__restrict__ ow = u + (long long)ca[t] * F.cs;
+      const R up = (k + 1 < nz) ? ow[o + H + cm[t]] : uc[t];
+      const R uW = F.has_x ? uo[nW[t]] : R(0);
+      const R uE = F.has_x ? uo[nE[t]] : R(0);
+      const R uS = F.has_y ? uo[nS[t]] : R(0);
+      const R uN = F.has_y ? uo[nN[t]] : R(0);
+      const R bk = b[(long long)ca[t] * F.cs + o + cm[t]];
+      const R r = cell_residual<R>(bk, tv[k], tx[k], ty[k], tz[k], tz[k + 1], uc[t], um[t], up,
+                                   uW, uE, uS, uN, F.has_x, F.has_y);
+      acc = t == 0 ? r : acc + r;
+      um[t] = uc[t];
+      uc[t] = up;
+    }
+    out[(long long)k * C.H] = acc;
+  }
+}
+
+// -------------------------------------------------------------------------
+// u += P uc (Sec. 6.2.1 "linear interpolation"): the fine cell centre lies a
+// quarter coarse cell from its parent's centre, giving weights 9/16 (parent),
+// 3/16 (the nearer x and y neighbours) and 1/16 (the diagonal one).
+// MODE 1: piecewise constant.  RED_ONLY: colour-0 fine columns only.
+// -------------------------------------------------------------------------
+template <typename R, bool RED_ONLY, int MODE>
+__global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__restrict__ uc,
+                                                    R *__restrict__ u,
+                                                    const int *__restrict__ done) {
+  if (is_done(done)) return;
+  const int gid = logical_block() * kBlock + threadIdx.x;
+  int c, m;
+  if (RED_ONLY) {
+    c = 0;
+    m = gid;
+    if (m >= F.ncol0) return;
+  } else {
+    if (gid >= 2 * F.H) return;
+    c = gid >= F.H ? 1 : 0;
+    m = gid - c * F.H;
+    if (m >= (c ? F.ncol1 : F.ncol0)) return;
+  }
+  int i, j;
+  col_ij(F, c, m, i, j);
+  const int I = i >> 1, J = j >> 1;
+  const int I2 = wrapi(I + ((i & 1) ? 1 : -1), C.nx);
+  const int J2 = wrapi(J + ((j & 1) ? 1 : -1), C.ny);
+  const R *__restrict__ p11 = uc + (long long)((I + J) & 1) * C.cs + col_m(C, I, J);
+  const R *__restrict__ p21 = uc + (long long)((I2 + J) & 1) * C.cs + col_m(C, I2, J);
+  const R *__restrict__ p12 = uc + (long long)((I + J2) & 1) * C.cs + col_m(C, I, J2);
+  const R *__restrict__ p22 = uc + (long long)((I2 + J2) & 1) * C.cs + col_m(C, I2, J2);
+  R *__restrict__ own = u + (long long)c * F.cs + m;
+  const long long HC = C.H, HF = F.H;
+  const int nz = F.nz;
+#pragma unroll 4
+  for (int k = 0; k < nz; ++k) {
+    R e;
+    if (MODE == 1) {
+      e = p11[k * HC];
+    } else {
+      e = R(9.0 / 16.0) * p11[k * HC];
+      e = e + R(3.0 / 16.0) * p21[k * HC];
+      e = e + R(3.0 / 16.0) * p12[k * HC];
+      e = e + R(1.0 / 16.0) * p22[k * HC];
+    }
+    own[k * HF] = own[k * HF] + e;
+  }
+}
+
+// -------------------------------------------------------------------------
+// y = A x (eq. ModelEquation integrated over the cell, difference form), one
+// lane per column of either colour; DOT: also partial sums of <x, y>.
+// -------------------------------------------------------------------------
+template <typename R, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ tab,
+                                                  const R *__restrict__ x, R *__restrict__ y,
+                                                  double *__restrict__ partial,
+                                                  const int *__restrict__ done) {
+  __shared__ double sh[4];
+  if (is_done(done)) return;
+  const int gid = logical_block() * kBlock + threadIdx.x;
+  const int c = gid >= L.H ? 1 : 0;
+  const int m = gid - c * L.H;
+  const bool valid = gid < 2 * L.H && m < (c ? L.ncol1 : L.ncol0);
+  double dot = 0.0;
+  if (valid) {
+    int i, j;
+    col_ij(L, c, m, i, j);
+    int mW = 0, mE = 0, mS = 0, mN = 0;
+    if (L.has_x) {
+      mW = col_m(L, wrapi(i - 1, L.nx), j);
+      mE = col_m(L, wrapi(i + 1, L.nx), j);
+    }
+    if (L.has_y) {
+      mS = col_m(L, i, wrapi(j - 1, L.ny));
+      mN = col_m(L, i, wrapi(j + 1, L.ny));
+    }
+    const long long H = L.H;
+    const R *__restrict__ xo = x + (long long)(1 - c) * L.cs;
+    const R *__restrict__ xs = x + (long long)c * L.cs + m;
+    R *__restrict__ ys = y + (long long)c * L.cs + m;
+    const R *__restrict__ tv = tab + TV * L.P;
+    const R *__restrict__ tx = tab + TX * L.P;
+    const R *__restrict__ ty = tab + TY * L.P;
+    const R *__restrict__ tz = tab + TZ * L.P;
+    const int nz = L.nz;
+    R xc = xs[0];
+    R xm = xc;
+#pragma unroll 4
+    for (int k = 0; k < nz; ++k) {
+      const long long o = (long long)k * H;
+      const R xp = (k + 1 < nz) ? xs[o + H] : xc;
+      R acc = tv[k] * xc;
+      if (L.has_x) {
+        acc = acc + tx[k] * (xc - xo[o + mW]);
+        acc = acc + tx[k] * (xc - xo[o + mE]);
+      }
+      if (L.has_y) {
+        acc = acc + ty[k] * (xc - xo[o + mS]);
+        acc = acc + ty[k] * (xc - xo[o + mN]);
+      }
+      acc = acc + tz[k] * (xc - xm);
+      acc = acc + tz[k + 1] * (xc - xp);
+      ys[o] = acc;
+      if (DOT) dot += (double)xc * (double)acc;
+      xm = xc;
+      xc = xp;
+    }
+  }
+  if (DOT) {
+    const double s = block_sum(dot, sh);
+    if (threadIdx.x == 0) partial[logical_block()] = s;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_fill(R *__restrict__ p, long long n, R v) {
+  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = t; e < n; e += stride) p[e] = v;
+}
+
+// plane-major -> colour-split, optionally scaled by the cell volume V_k
+template <typename S, typename D>
+__global__ __launch_bounds__(kBlock) void k_nat2split(Geo L, const S *__restrict__ src,
+                                                      D *__restrict__ dst,
+                                                      const double *__restrict__ vol) {
+  const int gid = logical_block() * kBlock + threadIdx.x;
+  if (gid >= 2 * L.H) return;
+  const int c = gid >= L.H ? 1 : 0;
+  const int m = gid - c * L.H;
+  if (m >= (c ? L.ncol1 : L.ncol0)) return;
+  int i, j;
+  col_ij(L, c, m, i, j);
+  const long long plane = (long long)L.nx * L.ny;
+  for (int k = 0; k < L.nz; ++k) {
+    double v = (double)src[k * plane + (long long)j * L.nx + i];
+    if (vol) v = vol[k] * v;
+    dst[(long long)c * L.cs + (long long)k * L.H + m] = (D)v;
+  }
+}
+
+template <typename S, typename D>
+__global__ __launch_bounds__(kBlock) void k_split2nat(Geo L, const S *__restrict__ src,
+                                                      D *__restrict__ dst) {
+  const int gid = logical_block() * kBlock + threadIdx.x;
+  if (gid >= 2 * L.H) return;
+  const int c = gid >= L.H ? 1 : 0;
+  const int m = gid - c * L.H;
+  if (m >= (c ? L.ncol1 : L.ncol0)) return;
+  int i, j;
+  col_ij(L, c, m, i, j);
+  const long long plane = (long long)L.nx * L.ny;
+  for (int k = 0; k < L.nz; ++k)
+    dst[k * plane + (long long)j * L.nx + i] = (D)src[(long long)c * L.cs + (long long)k * L.H + m];
+}
+
+// FP64 residual -> FP32 right-hand side of the preconditioner
+__global__ __launch_bounds__(kBlock) void k_cast_f64_f32(const double2 *__restrict__ src,
+                                                         float2 *__restrict__ dst, long long n2,
+                                                         const int *__restrict__ done) {
+  if (is_done(done)) return;
+  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = t; e < n2; e += stride) {
+    const double2 v = src[e];
+    dst[e] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
+// -------------------------------------------------------------------------
+// CG vector kernels (FP64, flat over the split vectors; padding entries stay
+// zero).  Each block writes its partial sums; k_finalize reduces them in a
+// fixed order, so every result is independent of scheduling.
+// -------------------------------------------------------------------------
+
+// r <- r - q, partial sums of ||r_before||^2 (= ||b||^2) and ||r_after||^2
+__global__ __launch_bounds__(kBlock) void k_resid_init(const double2 *__restrict__ q,
+                                                       double2 *__restrict__ r, long long n2,
+                                                       double *__restrict__ partial) {
+  __shared__ double sh[4];
+  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kBlock;
+  double bb = 0.0, rr = 0.0;
+  for (long long e = t; e < n2; e += stride) {
+    double2 b = r[e];
+    const double2 a = q[e];
+    bb += b.x * b.x + b.y * b.y;
+    b.x = b.x - a.x;
+    b.y = b.y - a.y;
+    rr += b.x * b.x + b.y * b.y;
+    r[e] = b;
+  }
+  const double s0 = block_sum(bb, sh);
+  const double s1 = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * logical_block()] = s0;
+    partial[2 * logical_block() + 1] = s1;
+  }
+}
+
+// u <- u + alpha p, r <- r - alpha q, partial sums of ||r||^2
+__global__ __launch_bounds__(kBlock) void k_update(double2 *__restrict__ u,
+                                                   const double2 *__restrict__ p,
+                                                   double2 *__restrict__ r,
+                                                   const double2 *__restrict__ q, long long n2,
+                                                   const PcgState *__restrict__ st,
+                                                   double *__restrict__ partial) {
+  __shared__ double sh[4];
+  if (st->done) return;
+  const double alpha = st->alpha;
+  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kBlock;
+  double rr = 0.0;
+  for (long long e = t; e < n2; e += stride) {
+    const double2 pv = p[e], qv = q[e];
+    double2 uv = u[e], rv = r[e];
+    uv.x = uv.x + alpha * pv.x;
+    uv.y = uv.y + alpha * pv.y;
+    rv.x = rv.x - alpha * qv.x;
+    rv.y = rv.y - alpha * qv.y;
+    u[e] = uv;
+    r[e] = rv;
+    rr += rv.x * rv.x + rv.y * rv.y;
+  }
+  const double s = block_sum(rr, sh);
+  if (threadIdx.x == 0) partial[logical_block()] = s;
+}
+
+template <typename Z> struct Vec2;
+template <> struct Vec2<double> { using T = double2; };
+template <> struct Vec2<float> { using T = float2; };
+
+// partial sums of <r, z> and <z, q>
+template <typename Z>
+__global__ __launch_bounds__(kBlock) void k_dots(const double2 *__restrict__ r,
+                                                 const typename Vec2<Z>::T *__restrict__ z,
+                                                 const double2 *__restrict__ q, long long n2,
+                                                 const PcgState *__restrict__ st,
+                                                 double *__restrict__ partial) {
+  __shared__ double sh[4];
+  if (st->done) return;
+  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kBlock;
+  double rz = 0.0, zq = 0.0;
+  for (long long e = t; e < n2; e += stride) {
+    const double2 rv = r[e], qv = q[e];
+    const auto zv = z[e];
+    const double zx = (double)zv.x, zy = (double)zv.y;
+    rz += rv.x * zx + rv.y * zy;
+    zq += zx * qv.x + zy * qv.y;
+  }
+  const double s0 = block_sum(rz, sh);
+  const double s1 = block_sum(zq, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * logical_block()] = s0;
+    partial[2 * logical_block() + 1] = s1;
+  }
+}
+
+// p <- z + beta p (p <- z on the first iteration)
+template <typename Z>
+__global__ __launch_bounds__(kBlock) void k_dir(double2 *__restrict__ p,
+                                                const typename Vec2<Z>::T *__restrict__ z,
+                                                long long n2, const PcgState *__restrict__ st,
+                                                int first) {
+  if (st->done) return;
+  const double beta = st->beta;
+  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = t; e < n2; e += stride) {
+    const auto zv = z[e];
+    double2 pv;
+    if (first) {
+      pv.x = (double)zv.x;
+      pv.y = (double)zv.y;
+    } else {
+      pv = p[e];
+      pv.x = (double)zv.x + beta * pv.x;
+      pv.y = (double)zv.y + beta * pv.y;
+    }
+    p[e] = pv;
+  }
+}
+
+enum FinalizeMode : int { F_INIT = 0, F_KAPPA = 1, F_ALPHA = 2, F_CONV = 3, F_BETA = 4, F_TRUE = 5 };
+
+// One block: reduce nq interleaved partial sums over nblk blocks in a fixed
+// order and advance the CG scalars (Appendix B, Alg. PCG).
+__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partial, int nblk,
+                                                     int nq, PcgState *__restrict__ st, int mode,
+                                                     double rtol, double atol, int rel_to_rhs) {
+  __shared__ double sh[4];
+  __shared__ double tot[2];
+  if (mode != F_TRUE && mode != F_INIT && st->done) return;
+  for (int qi = 0; qi < nq; ++qi) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kBlock) v += partial[(long long)b * nq + qi];
+    const double s = block_sum(v, sh);
+    if (threadIdx.x == 0) tot[qi] = s;
+  }
+  if (threadIdx.x != 0) return;
+  switch (mode) {
+    case F_INIT: {
+      const double bn = sqrt(tot[0]), r0 = sqrt(tot[1]);
+      st->b_norm = bn;
+      st->r0_norm = r0;
+      st->r_norm = r0;
+      const double ref = rel_to_rhs ? bn : r0;
+      const double th = fmax(rtol * ref, atol);
+      st->thresh = th;
+      st->iter = 0;
+      st->alpha = st->beta = st->kappa_old = 0.0;
+      if (!isfinite(r0) || !isfinite(bn)) {
+        st->done = 1;
+        st->status = -4;
+      } else if (r0 == 0.0 || r0 < th) {
+        st->done = 1;
+        st->status = 0;
+      } else {
+        st->done = 0;
+        st->status = 1;
+      }
+      break;
+    }
+    case F_KAPPA:
+      st->kappa_old = tot[0];
+      if (!isfinite(tot[0])) { st->done = 1; st->status = -4; }
+      break;
+    case F_ALPHA: {
+      const double a = st->kappa_old / tot[0];
+      st->alpha = a;
+      if (!isfinite(a)) { st->done = 1; st->status = -4; }
+      break;
+    }
+    case F_CONV: {
+      const double rn = sqrt(tot[0]);
+      st->r_norm = rn;
+      st->iter += 1;
+      if (!isfinite(rn)) { st->done = 1; st->status = -4; }
+      else if (rn < st->thresh) { st->done = 1; st->status = 0; }
+      else if (st->iter >= st->maxiter) { st->done = 1; st->status = 1; }
+      break;
+    }
+    case F_BETA: {
+      const double kappa = tot[0];
+      const double beta = st->flexible ? -st->alpha * tot[1] / st->kappa_old : kappa / st->kappa_old;
+      st->beta = beta;
+      st->kappa_old = kappa;
+      if (!isfinite(beta)) { st->done = 1; st->status = -4; }
+      break;
+    }
+    case F_TRUE:  // partials of k_resid_init: [||b||^2, ||b - A u||^2]
+      st->true_r_norm = sqrt(tot[nq - 1]);
+      break;
+  }
+}
+
+}  // namespace ell

@@ -1,0 +1,264 @@
+"""Thin Python binding of the C ABI in include/ell.h.
+
+Argument marshalling only: every step of the solver runs in the HIP kernels
+of libell.so.  PyTorch provides device memory (tensors) and the stream; the
+library and PyTorch share one HIP runtime (torch is imported first, so the
+runtime it loaded also serves libell.so).
+
+If the library has not been built this module raises ImportError: there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libell.so")
+
+ELL_OK, ELL_NOT_CONVERGED, ELL_PENDING = 0, 1, 2
+ELL_ERR_INVALID, ELL_ERR_OOM, ELL_ERR_HIP, ELL_ERR_NUMERIC, ELL_ERR_BUDGET = -1, -2, -3, -4, -5
+ELL_FP64, ELL_FP32_PRECOND, ELL_FP32_BF16COEF = 0, 1, 2
+PRECISIONS = {"fp64": ELL_FP64, "fp32": ELL_FP32_PRECOND, "bf16coef": ELL_FP32_BF16COEF}
+ELL_K_SMOOTH0, ELL_K_APPLY, ELL_K_RESTRICT0, ELL_K_PROLONG0, ELL_K_UPDATE = 0, 1, 2, 3, 4
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("hx", ctypes.c_double), ("hy", ctypes.c_double), ("omega2", ctypes.c_double),
+                ("dz", _dp), ("lambda2", _dp), ("n_levels", ctypes.c_int32),
+                ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32),
+                ("nu_coarse", ctypes.c_int32), ("rho", ctypes.c_double),
+                ("prolong", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("maxiter", ctypes.c_int32),
+                ("flexible", ctypes.c_int32), ("rel_to_rhs", ctypes.c_int32),
+                ("poll_every", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("r0_norm", ctypes.c_double),
+                ("r_norm", ctypes.c_double), ("true_r_norm", ctypes.c_double),
+                ("b_norm", ctypes.c_double)]
+
+
+EXPORTS = ["ell_grid_create", "ell_grid_destroy", "ell_grid_bytes", "ell_grid_levels",
+           "ell_apply_A", "ell_vcycle", "ell_pcg_solve", "ell_level_elems", "ell_to_split",
+           "ell_from_split", "ell_level_smooth", "ell_level_resid_restrict",
+           "ell_level_prolong_add", "ell_level_apply", "ell_profile_enable", "ell_profile_read",
+           "ell_last_error"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libell.so (does not initialise the GPU)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1307_2036_amd/build.py "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(path)
+    vp, i32 = ctypes.c_void_p, ctypes.c_int
+    L.ell_grid_create.argtypes = [ctypes.POINTER(GridDesc), ctypes.POINTER(vp)]
+    L.ell_grid_destroy.argtypes = [vp]
+    L.ell_grid_bytes.argtypes = [ctypes.POINTER(GridDesc)]
+    L.ell_grid_bytes.restype = ctypes.c_size_t
+    L.ell_grid_levels.argtypes = [vp]
+    L.ell_apply_A.argtypes = [vp, vp, vp, vp]
+    L.ell_vcycle.argtypes = [vp, vp, vp, vp]
+    L.ell_pcg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
+    L.ell_level_elems.argtypes = [vp, i32]
+    L.ell_level_elems.restype = ctypes.c_size_t
+    L.ell_to_split.argtypes = [vp, i32, vp, vp, vp]
+    L.ell_from_split.argtypes = [vp, i32, vp, vp, vp]
+    L.ell_level_smooth.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+    L.ell_level_resid_restrict.argtypes = [vp, i32, vp, vp, vp, i32, vp]
+    L.ell_level_prolong_add.argtypes = [vp, i32, vp, vp, i32, vp]
+    L.ell_level_apply.argtypes = [vp, i32, vp, vp, vp]
+    L.ell_profile_enable.argtypes = [vp, i32, i32]
+    L.ell_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+    L.ell_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        if name not in ("ell_grid_bytes", "ell_level_elems", "ell_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+class EllError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ell error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int, allow=(ELL_OK,)) -> int:
+    if rc not in allow:
+        raise EllError(rc, load_library().ell_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype=torch.float64) -> ctypes.c_void_p:
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_desc(nx, ny, nz, hx, hy, omega2, dz, lambda2, n_levels=0, nu_pre=1, nu_post=1,
+              nu_coarse=1, rho=1.0, prolong=0, precision="fp64"):
+    dz = np.ascontiguousarray(np.asarray(dz, dtype=np.float64))
+    lam = np.ascontiguousarray(np.asarray(lambda2, dtype=np.float64))
+    if dz.shape != (nz,) or lam.shape != (nz,):
+        raise ValueError("dz and lambda2 must have nz entries")
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    d = GridDesc(nx, ny, nz, hx, hy, omega2, dz.ctypes.data_as(_dp), lam.ctypes.data_as(_dp),
+                 n_levels, nu_pre, nu_post, nu_coarse, rho, prolong, prec)
+    return d, (dz, lam)
+
+
+def grid_bytes(**kw) -> int:
+    d, keep = make_desc(**kw)
+    return int(load_library().ell_grid_bytes(ctypes.byref(d)))
+
+
+@dataclass
+class Stats:
+    iters: int
+    status: int
+    r0_norm: float
+    r_norm: float
+    true_r_norm: float
+    b_norm: float
+
+
+class Grid:
+    """Device-resident grid, multigrid hierarchy and solver workspace."""
+
+    def __init__(self, nx, ny, nz, hx, hy, omega2, dz, lambda2, n_levels=0, nu_pre=1, nu_post=1,
+                 nu_coarse=1, rho=1.0, prolong=0, precision="fp64"):
+        L = load_library()
+        d, keep = make_desc(nx, ny, nz, hx, hy, omega2, dz, lambda2, n_levels, nu_pre, nu_post,
+                            nu_coarse, rho, prolong, precision)
+        h = ctypes.c_void_p()
+        _check(L.ell_grid_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.precision = d.precision
+        self.levels = L.ell_grid_levels(h)
+        self.bytes = int(L.ell_grid_bytes(ctypes.byref(d)))
+
+    @classmethod
+    def from_problem(cls, p, precision="fp64", **over):
+        kw = dict(nx=p.nx, ny=p.ny, nz=p.nz, hx=p.hx, hy=p.hy, omega2=p.omega2, dz=p.dz,
+                  lambda2=p.lambda2, n_levels=p.n_levels, nu_pre=p.nu_pre, nu_post=p.nu_post,
+                  nu_coarse=p.nu_coarse, rho=p.rho, prolong=p.prolong, precision=precision)
+        kw.update(over)
+        return cls(**kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ell_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def elem_dtype(self):
+        return torch.float64 if self.precision == ELL_FP64 else torch.float32
+
+    # ---- whole-path entry points -------------------------------------------------
+    def apply_A(self, x: torch.Tensor, y: Optional[torch.Tensor] = None, stream=None):
+        y = torch.empty_like(x) if y is None else y
+        _check(load_library().ell_apply_A(self._h, _dev(x), _dev(y), _stream(stream)))
+        return y
+
+    def vcycle(self, r: torch.Tensor, z: Optional[torch.Tensor] = None, stream=None):
+        z = torch.empty_like(r) if z is None else z
+        _check(load_library().ell_vcycle(self._h, _dev(r), _dev(z), _stream(stream)))
+        return z
+
+    def pcg_solve(self, f: torch.Tensor, u: Optional[torch.Tensor] = None, rtol=1e-5, atol=0.0,
+                  maxiter=500, flexible=True, rel_to_rhs=False, poll_every=4, stream=None,
+                  check=True):
+        u = torch.zeros_like(f) if u is None else u
+        o = SolveOpts(rtol, atol, maxiter, int(flexible), int(rel_to_rhs), poll_every)
+        st = SolveStats()
+        rc = load_library().ell_pcg_solve(self._h, _dev(f), _dev(u), ctypes.byref(o),
+                                          ctypes.byref(st), _stream(stream))
+        if check:
+            _check(rc, allow=(ELL_OK, ELL_NOT_CONVERGED))
+        return u, Stats(st.iters, st.status, st.r0_norm, st.r_norm, st.true_r_norm, st.b_norm)
+
+    # ---- level entry points ----------------------------------------------------------
+    def level_elems(self, level: int) -> int:
+        return int(load_library().ell_level_elems(self._h, level))
+
+    def level_empty(self, level: int) -> torch.Tensor:
+        return torch.zeros(self.level_elems(level), dtype=self.elem_dtype, device="cuda")
+
+    def to_split(self, level: int, src: torch.Tensor, dst: Optional[torch.Tensor] = None, stream=None):
+        dst = self.level_empty(level) if dst is None else dst
+        _check(load_library().ell_to_split(self._h, level, _dev(src), _dev(dst, self.elem_dtype),
+                                           _stream(stream)))
+        return dst
+
+    def from_split(self, level: int, src: torch.Tensor, dst: torch.Tensor, stream=None):
+        _check(load_library().ell_from_split(self._h, level, _dev(src, self.elem_dtype), _dev(dst),
+                                             _stream(stream)))
+        return dst
+
+    def level_smooth(self, level, colour, b, u, zero_init=False, stream=None):
+        _check(load_library().ell_level_smooth(self._h, level, colour, int(zero_init),
+                                               _dev(b, self.elem_dtype), _dev(u, self.elem_dtype),
+                                               _stream(stream)))
+        return u
+
+    def level_resid_restrict(self, level, b, u, bc, black_zero=False, stream=None):
+        _check(load_library().ell_level_resid_restrict(
+            self._h, level, _dev(b, self.elem_dtype), _dev(u, self.elem_dtype),
+            _dev(bc, self.elem_dtype), int(black_zero), _stream(stream)))
+        return bc
+
+    def level_prolong_add(self, level, uc, u, red_only=False, stream=None):
+        _check(load_library().ell_level_prolong_add(self._h, level, _dev(uc, self.elem_dtype),
+                                                    _dev(u, self.elem_dtype), int(red_only),
+                                                    _stream(stream)))
+        return u
+
+    def level_apply(self, level, x, y, stream=None):
+        _check(load_library().ell_level_apply(self._h, level, _dev(x, self.elem_dtype),
+                                              _dev(y, self.elem_dtype), _stream(stream)))
+        return y
+
+    # ---- measurement -------------------------------------------------------------------
+    def profile_enable(self, family: int, max_events: int):
+        _check(load_library().ell_profile_enable(self._h, family, max_events))
+
+    def profile_read(self, family: int):
+        n = ctypes.c_int()
+        ms = ctypes.c_double()
+        _check(load_library().ell_profile_read(self._h, family, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value

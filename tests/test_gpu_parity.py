@@ -1,0 +1,293 @@
+"""GPU parity: every kernel of the hot path and the whole solve, called
+through the C ABI, against the FP64 oracle on the same seeded inputs.
+
+Tolerances (FP64): the kernels evaluate the same formulas as the oracle in a
+different association order and with fused multiply-adds, so a result may
+differ from the oracle's by a few units of rounding of the terms that form
+it.  Operator and residual values are compared against
+c * eps * (sum of |terms|), column solves against c * eps times the column's
+magnitude, whole solves in relative L2 (<= 1e-10, the same iteration count).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import small_grid
+from paper_1307_2036_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+EPS = 2.0 ** -52
+
+
+@pytest.fixture(scope="module")
+def ell():
+    from paper_1307_2036_amd import ell as E
+    E.load_library()
+    assert torch.cuda.is_available()
+    return E
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def gpu_grid(ell, g, precision="fp64"):
+    return ell.Grid(g.nx, g.ny, g.nz, g.hx, g.hy, g.omega2, g.dz, g.lambda2, g.n_levels, g.nu_pre,
+                    g.nu_post, g.nu_coarse, g.rho, g.prolong, precision)
+
+
+SHAPES = [(32, 32, 16), (64, 48, 37), (2, 2, 3), (1, 6, 4), (6, 1, 5), (1, 1, 5), (4, 2, 3),
+          (130, 8, 7)]
+
+
+def grid_for(orc, shape, seed=3, **mg):
+    nx, ny, nz = shape
+    return small_grid(orc, nx, ny, nz, seed=seed + nx + 7 * ny + 31 * nz, **mg)
+
+
+def level_grids(g, levels):
+    out = [g]
+    for _ in range(levels - 1):
+        out.append(out[-1].coarse())
+    return out
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_split_layout_roundtrip(ell, orc, shape):
+    g = grid_for(orc, shape)
+    G = gpu_grid(ell, g)
+    x = np.random.default_rng(0).standard_normal(g.shape)
+    xs = G.to_split(0, dev(x))
+    assert xs.numel() == G.level_elems(0)
+    y = G.from_split(0, xs, torch.zeros(g.shape, dtype=torch.float64, device="cuda"))
+    np.testing.assert_array_equal(host(y), x)
+    # the layout is the documented one: colour c, level k, column m
+    H = (g.nx * g.ny + 1) // 2
+    xs_h = host(xs).reshape(2, g.nz, H)
+    for j in range(g.ny):
+        for i in range(g.nx):
+            c = (i + j) % 2
+            m = j * (g.nx // 2) + i // 2 if g.nx > 1 else j // 2
+            np.testing.assert_array_equal(xs_h[c, :, m], x[:, j, i])
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_apply_matches_oracle(ell, orc, shape):
+    g = grid_for(orc, shape)
+    G = gpu_grid(ell, g)
+    x = np.random.default_rng(1).standard_normal(g.shape)
+    y = host(G.apply_A(dev(x)))
+    ref = orc.apply(g, x)
+    bound = 16 * EPS * orc.apply_abs(g, x)
+    assert np.all(np.abs(y - ref) <= bound)
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 16), (64, 48, 37), (2, 2, 3), (1, 6, 4), (6, 1, 5),
+                                   (1, 1, 5), (130, 8, 7)])
+@pytest.mark.parametrize("rho", [1.0, 0.8])
+def test_smoother_matches_oracle(ell, orc, shape, rho):
+    g = grid_for(orc, shape, rho=rho)
+    G = gpu_grid(ell, g)
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal(g.shape) * (g.hx * g.hy * g.dz)[:, None, None]
+    u0 = rng.standard_normal(g.shape) * 1e-3
+    bs = G.to_split(0, dev(b))
+    # red from zero, then black, then red again (all three code paths)
+    us = G.level_empty(0)
+    G.level_smooth(0, 0, bs, us, zero_init=True)
+    ref = orc.smooth_colour(g, 0, b, np.zeros(g.shape), rho)
+    for colour, zero in ((1, False), (0, False)):
+        G.level_smooth(0, colour, bs, us, zero_init=zero)
+        ref = orc.smooth_colour(g, colour, b, ref, rho)
+    got = host(G.from_split(0, us, torch.zeros(g.shape, dtype=torch.float64, device="cuda")))
+    scale = np.abs(ref).max(axis=0, keepdims=True)
+    assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300), np.abs(got - ref).max() / scale.max()
+    # from a non-zero start as well
+    us = G.to_split(0, dev(u0))
+    G.level_smooth(0, 1, bs, us)
+    ref = orc.smooth_colour(g, 1, b, u0, rho)
+    got = host(G.from_split(0, us, torch.zeros(g.shape, dtype=torch.float64, device="cuda")))
+    assert np.all(np.abs(got - ref) <= 1e-12 * np.abs(ref).max(axis=0, keepdims=True) + 1e-300)
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 16), (64, 48, 37), (4, 2, 3), (2, 2, 6), (256, 12, 9)])
+def test_residual_restriction_matches_oracle(ell, orc, shape):
+    g = grid_for(orc, shape, n_levels=2)
+    G = gpu_grid(ell, g)
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(g.shape)
+    u = rng.standard_normal(g.shape)
+    bc = G.level_empty(1)
+    G.level_resid_restrict(0, G.to_split(0, dev(b)), G.to_split(0, dev(u)), bc)
+    got = host(G.from_split(1, bc, torch.zeros((g.nz, g.ny // 2, g.nx // 2), dtype=torch.float64,
+                                               device="cuda")))
+    ref = orc.restrict(g, orc.residual(g, b, u))
+    scale = orc.restrict(g, orc.apply_abs(g, u) + np.abs(b))
+    assert np.all(np.abs(got - ref) <= 16 * EPS * scale)
+
+
+def test_black_zero_restriction_after_sweep(ell, orc):
+    """After red then black (rho = 1) the black residual is zero up to rounding,
+    and the restriction that skips the black children agrees with the full one."""
+    g = grid_for(orc, (64, 32, 24), n_levels=2)
+    G = gpu_grid(ell, g)
+    b = np.random.default_rng(5).standard_normal(g.shape) * (g.hx * g.hy * g.dz)[:, None, None]
+    bs = G.to_split(0, dev(b))
+    us = G.level_empty(0)
+    G.level_smooth(0, 0, bs, us, zero_init=True)
+    G.level_smooth(0, 1, bs, us)
+    u = host(G.from_split(0, us, torch.zeros(g.shape, dtype=torch.float64, device="cuda")))
+    bc = G.level_empty(1)
+    G.level_resid_restrict(0, bs, us, bc, black_zero=True)
+    got = host(G.from_split(1, bc, torch.zeros((g.nz, g.ny // 2, g.nx // 2), dtype=torch.float64,
+                                               device="cuda")))
+    ref = orc.restrict(g, orc.residual(g, b, u))
+    scale = orc.restrict(g, orc.apply_abs(g, u) + np.abs(b))
+    assert np.all(np.abs(got - ref) <= 64 * EPS * scale)
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 16), (64, 48, 37), (4, 2, 3), (2, 2, 6), (4, 4, 1)])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_prolongation_matches_oracle(ell, orc, shape, mode):
+    g = grid_for(orc, shape, n_levels=2, prolong=mode)
+    G = gpu_grid(ell, g)
+    rng = np.random.default_rng(6)
+    uc = rng.standard_normal((g.nz, g.ny // 2, g.nx // 2))
+    u = rng.standard_normal(g.shape)
+    us = G.to_split(0, dev(u))
+    G.level_prolong_add(0, G.to_split(1, dev(uc)), us)
+    got = host(G.from_split(0, us, torch.zeros(g.shape, dtype=torch.float64, device="cuda")))
+    ref = orc.prolong_add(g, uc, u, mode)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=8 * EPS * (np.abs(u).max() + np.abs(uc).max()))
+    # red-only leaves black columns as they were
+    us = G.to_split(0, dev(u))
+    G.level_prolong_add(0, G.to_split(1, dev(uc)), us, red_only=True)
+    got = host(G.from_split(0, us, torch.zeros(g.shape, dtype=torch.float64, device="cuda")))
+    red = np.array([[(i + j) % 2 == 0 for i in range(g.nx)] for j in range(g.ny)])
+    np.testing.assert_array_equal(got[:, ~red], u[:, ~red])
+    np.testing.assert_allclose(got[:, red], ref[:, red], rtol=0,
+                               atol=8 * EPS * (np.abs(u).max() + np.abs(uc).max()))
+
+
+def test_coarse_level_apply(ell, orc):
+    g = grid_for(orc, (32, 16, 9), n_levels=3)
+    G = gpu_grid(ell, g)
+    for lv, gl in enumerate(level_grids(g, 3)):
+        x = np.random.default_rng(lv).standard_normal(gl.shape)
+        y = G.level_empty(lv)
+        G.level_apply(lv, G.to_split(lv, dev(x)), y)
+        got = host(G.from_split(lv, y, torch.zeros(gl.shape, dtype=torch.float64, device="cuda")))
+        assert np.all(np.abs(got - orc.apply(gl, x)) <= 16 * EPS * orc.apply_abs(gl, x))
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("shape,mg", [
+    ((32, 32, 16), dict()),
+    ((64, 64, 32), dict(n_levels=4, nu_coarse=5)),
+    ((96, 96, 24), dict()),
+    ((32, 16, 12), dict(nu_pre=2, nu_post=1, nu_coarse=3)),
+    ((32, 32, 8), dict(rho=0.9)),
+    ((32, 32, 8), dict(prolong=1)),
+    ((32, 32, 8), dict(nu_pre=0, nu_post=2)),
+    ((16, 16, 8), dict(nu_post=0)),
+    ((1, 1, 12), dict()),
+])
+def test_vcycle_matches_oracle(ell, orc, shape, mg):
+    g = grid_for(orc, shape, **mg)
+    G = gpu_grid(ell, g)
+    assert G.levels == orc.num_levels(g)
+    r = np.random.default_rng(7).standard_normal(g.shape) * (g.hx * g.hy * g.dz)[:, None, None]
+    z = host(G.vcycle(dev(r)))
+    ref = orc.vcycle(g, r)
+    assert rel(z, ref) <= 1e-11
+
+
+def test_config0_solve_matches_oracle(ell, orc):
+    p = I.config0()
+    g = orc.Grid.from_problem(p)
+    u_ref, st_ref = orc.pcg(g, p.f, rtol=p.rtol)
+    G = ell.Grid.from_problem(p)
+    u, st = G.pcg_solve(dev(p.f), rtol=p.rtol)
+    assert st.status == 0 and st.iters == st_ref["iters"]
+    assert rel(host(u), u_ref) <= 1e-10
+    assert abs(st.r0_norm / st_ref["r0_norm"] - 1) < 1e-12
+    assert abs(st.r_norm / st_ref["r_norm"] - 1) < 1e-6
+
+
+@pytest.mark.parametrize("name,kw,opts", [
+    ("graded64_L4", dict(nx=64, nz=32, n_levels=4, nu_coarse=5), dict()),
+    ("graded96_std", dict(nx=96, nz=24), dict()),
+    ("graded64_classic_beta", dict(nx=64, nz=16), dict(flexible=False)),
+    ("graded128_tight", dict(nx=128, nz=64, n_levels=5, nu_coarse=5), dict(rtol=1e-10)),
+])
+def test_graded_solves_match_oracle(ell, orc, name, kw, opts):
+    nx = kw.pop("nx")
+    nz = kw.pop("nz")
+    p = I.graded_problem(name, nx, nz, 1e-2, 11, 12, **kw)
+    g = orc.Grid.from_problem(p)
+    rtol = opts.pop("rtol", 1e-5)
+    u_ref, st_ref = orc.pcg(g, p.f, rtol=rtol, **opts)
+    G = ell.Grid.from_problem(p)
+    u, st = G.pcg_solve(dev(p.f), rtol=rtol, **opts)
+    assert st.status == 0 and st.iters == st_ref["iters"], (st, st_ref)
+    assert rel(host(u), u_ref) <= 1e-10
+
+
+def test_solve_edge_cases(ell, orc):
+    p = I.graded_problem("edge", 32, 8, 1e-2, 1, 2)
+    G = ell.Grid.from_problem(p)
+    g = orc.Grid.from_problem(p)
+    # zero right-hand side: no iterations, u stays zero
+    u, st = G.pcg_solve(torch.zeros(p.f.shape, dtype=torch.float64, device="cuda"))
+    assert st.iters == 0 and st.status == 0 and not host(u).any()
+    # maxiter reached: NOT_CONVERGED with the same iterate as the oracle
+    u, st = G.pcg_solve(dev(p.f), rtol=1e-14, maxiter=2)
+    u_ref, st_ref = orc.pcg(g, p.f, rtol=1e-14, maxiter=2)
+    assert st.status == ell.ELL_NOT_CONVERGED and st.iters == 2 and st_ref["status"] == 1
+    assert rel(host(u), u_ref) <= 1e-10
+    # warm start relative to ||b||: a converged u needs no further iteration
+    u, st = G.pcg_solve(dev(p.f), rtol=1e-8, rel_to_rhs=True)
+    u2, st2 = G.pcg_solve(dev(p.f), u=u.clone(), rtol=1e-8, rel_to_rhs=True)
+    assert st2.iters == 0
+    # non-finite input is reported, not returned as a solution
+    f = p.f.copy()
+    f[3, 2, 1] = np.nan
+    with pytest.raises(ell.EllError) as ei:
+        G.pcg_solve(dev(f))
+    assert ei.value.code == ell.ELL_ERR_NUMERIC
+    # polling granularity does not change the result
+    ua, sa = G.pcg_solve(dev(p.f), poll_every=1)
+    ub, sb = G.pcg_solve(dev(p.f), poll_every=16)
+    assert sa.iters == sb.iters
+    np.testing.assert_array_equal(host(ua), host(ub))
+
+
+def test_single_column_solve(ell, orc):
+    g = small_grid(orc, 1, 1, 40, seed=2, graded=False)
+    G = gpu_grid(ell, g)
+    f = np.random.default_rng(9).standard_normal(g.shape)
+    u, st = G.pcg_solve(dev(f), rtol=1e-12)
+    u_ref, st_ref = orc.pcg(g, f, rtol=1e-12)
+    assert st.iters == st_ref["iters"] == 1
+    assert rel(host(u), u_ref) <= 1e-12
+
+
+def test_invalid_arguments(ell):
+    with pytest.raises(ell.EllError):
+        ell.Grid(33, 32, 4, 0.1, 0.1, 1e-2, np.ones(4), np.ones(4))
+    G = ell.Grid(8, 8, 4, 0.1, 0.1, 1e-2, np.ones(4), np.ones(4))
+    x = torch.zeros((4, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(ell.EllError):
+        G.apply_A(x, x)
+    with pytest.raises(ell.EllError):
+        G.level_smooth(5, 0, G.level_empty(0), G.level_empty(0))
