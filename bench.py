@@ -1,0 +1,146 @@
+"""Benchmark: FP64 multigrid-preconditioned CG on the 512 x 512 x 128 graded
+production-shaped problem (four-level hierarchy, five coarse sweeps).
+
+One step = one whole solve to a 1e-5 relative residual reduction from a zero
+initial guess, with f resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "solves/s & unknowns·iter/s to 1e-5 rel. residual; HBM GB/s; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16coef"])
+    ap.add_argument("--nx", type=int, default=512)
+    ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--nu-coarse", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=4,
+                    help="PCG iterations of the oracle in the CPU-baseline sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(p, gpu_iters: int, iters: int):
+    """The FP64 oracle, as it stands, on the host cores: a bounded sample of
+    the same solve (the first `iters` PCG iterations of the full-size problem),
+    scaled to solves/s with the GPU's iteration count."""
+    import numpy as np
+    from oracle import oracle as O
+    g = O.Grid.from_problem(p)
+    t0 = time.perf_counter()
+    u, st = O.pcg(g, p.f, rtol=0.0, atol=0.0, maxiter=iters)
+    dt = time.perf_counter() - t0
+    n = p.n
+    uips = n * st["iters"] / dt
+    return {"value": uips / (n * gpu_iters), "unit": "solves/s", "cores": O.num_threads(),
+            "kind": "oracle", "unknowns_iter_per_s": uips, "seconds": dt,
+            "sample": f"first {st['iters']} PCG iterations (incl. setup, initial residual and "
+                      f"V-cycle) of the same {p.nx}x{p.ny}x{p.nz} FP64 solve; solves/s = "
+                      f"unknowns*iter/s / (n * {gpu_iters} GPU iterations)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1307_2036_amd import ell, inputs, perfmodel
+
+    torch.cuda.set_device(0)
+    p = inputs.config1(n_levels=a.levels, nu_coarse=a.nu_coarse, nx=a.nx)
+    G = ell.Grid.from_problem(p, precision=a.precision)
+    f = torch.from_numpy(p.f).cuda()
+    u = torch.zeros_like(f)
+    n = p.n
+    e = 8 if a.precision == "fp64" else 4
+
+    def step():
+        u.zero_()
+        return G.pcg_solve(f, u, rtol=p.rtol, maxiter=500, poll_every=8)
+
+    for _ in range(a.warmup):
+        _, st = step()
+    torch.cuda.synchronize()
+    _, st = step()
+    iters = st.iters
+    G.profile_enable(ell.ELL_K_SMOOTH0, 4 * (iters + 2) * a.steps + 64)
+    G.profile_enable(ell.ELL_K_APPLY, (iters + 2) * a.steps + 16)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ts = time.perf_counter()
+        _, st = step()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    assert st.status == 0, st
+
+    cnt, ms = G.profile_read(ell.ELL_K_SMOOTH0)
+    cnt_a, ms_a = G.profile_read(ell.ELL_K_APPLY)
+    launch_bytes = perfmodel.smooth0_launch_bytes(n, e)
+    avg_ms = ms / cnt
+    achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
+    apply_gbs = 16 * n / (ms_a / cnt_a * 1e-3) / 1e9
+
+    solves = a.steps / elapsed
+    it_bytes = perfmodel.pcg_iteration_bytes(n, G.levels, e, nu_coarse=p.nu_coarse)
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": METRIC,
+        "value": solves,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if a.precision == "fp64" else "f64-outer/f32-vcycle",
+        "data": "synthetic (seeded N(0,1) f, graded dz, log-normal lambda^2 profile)",
+        "config": {"workload": f"gmg-pcg {p.nx}x{p.ny}x{p.nz} graded, omega2=1e-2, "
+                               f"{G.levels} levels, nu_coarse={p.nu_coarse}, rtol 1e-5, u0=0",
+                   "unknowns": n, "precision": a.precision, "parallelism": "single GPU"},
+        "iters": iters,
+        "unknowns_iter_per_s": n * iters * solves,
+        "hbm_gbs_algorithmic": it_bytes * iters * solves / 1e9,
+        "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "true_rel_residual": st.true_r_norm / st.b_norm,
+        "roofline": {"bound": "hbm", "kernel": "k_smooth (finest level, FP64)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": avg_ms * 1e3, "launches": cnt,
+                     "bytes_per_launch": launch_bytes},
+        "apply_kernel": {"achieved_gbs": apply_gbs, "avg_launch_us": ms_a / cnt_a * 1e3},
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, iters, a.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -298,10 +298,17 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const R *b, R *u, const 
   R *yb = (R *)g->ybuf;
   const R rho = (R)g->d.rho;
   ProfScope ps(g, ELL_K_SMOOTH0, s, l == 0);
-  if (zero && rho1) k_smooth<R, true, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
-  else if (zero) k_smooth<R, true, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
-  else if (rho1) k_smooth<R, false, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
-  else k_smooth<R, false, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+  if (l == 0) {
+    if (zero && rho1) k_smooth<R, true, true, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+    else if (zero) k_smooth<R, true, false, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+    else if (rho1) k_smooth<R, false, true, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+    else k_smooth<R, false, false, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+  } else {
+    if (zero && rho1) k_smooth<R, true, true, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+    else if (zero) k_smooth<R, true, false, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+    else if (rho1) k_smooth<R, false, true, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+    else k_smooth<R, false, false, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+  }
   return check_launch("k_smooth");
 }
 

@@ -87,7 +87,9 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 // are parked in the output column itself (rho = 1) and read back on the way
 // down, so no per-lane array is needed and occupancy stays high.
 // -------------------------------------------------------------------------
-template <typename R, bool ZERO, bool RHO1>
+// FINE marks launches on the finest level (a separate kernel symbol, so that
+// profiles attribute the dominant launches to it alone).
+template <typename R, bool ZERO, bool RHO1, bool FINE>
 __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ tab, int c,
                                                    const R *__restrict__ b, R *__restrict__ u,
                                                    R *__restrict__ ybuf, R rho,
