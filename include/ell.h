@@ -184,6 +184,11 @@ enum { ELL_K_SMOOTH0 = 0, ELL_K_APPLY = 1, ELL_K_RESTRICT0 = 2, ELL_K_PROLONG0 =
 int ell_profile_enable(ell_grid *g, int family, int max_events);
 /* Synchronises the recorded events; *count launches, *total_ms summed time. */
 int ell_profile_read(ell_grid *g, int family, int *count, double *total_ms);
+/* Per-launch times in milliseconds of the recorded launches, in launch order:
+ * writes min(count, cap) values to ms (host array) and returns the count, or a
+ * negative error.  Launches enqueued after the solve converged return at once
+ * and show up as near-zero times. */
+int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *ell_last_error(void);

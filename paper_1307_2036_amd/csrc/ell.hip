@@ -55,6 +55,9 @@ inline int blocks8(long long threads) {
   return (int)b;
 }
 
+// blocks of 64 columns x kSeg k-segments covering `cols` columns
+inline int seg_blocks(long long cols) { return blocks8((cols + kSegCols - 1) / kSegCols * kBlock); }
+
 // Grid of a flat vector kernel over n2 element pairs: a fixed function of n2,
 // so reductions over it are reproducible.
 inline int flat_blocks(long long n2) {
@@ -188,6 +191,27 @@ int validate(const ell_grid_desc *d, int *levels) {
   return ELL_OK;
 }
 
+// Products of the recurrence multipliers over each of the kSeg k-segments of
+// a column: pf[k] = prod_{i=start..k} Tz[i] ip[i] (forward),
+// qb[k] = prod_{i=k..end-1} cf[i] (backward), in the table's precision.
+template <typename T>
+void segment_products(int nz, const T *Tz, const T *ip, const T *cf, T *pf, T *qb) {
+  const int Ls = seg_len(nz);
+  for (int s0 = 0; s0 < nz; s0 += Ls) {
+    const int e = std::min(s0 + Ls, nz);
+    T acc = T(1);
+    for (int k = s0; k < e; ++k) {
+      acc = acc * (Tz[k] * ip[k]);
+      pf[k] = acc;
+    }
+    acc = T(1);
+    for (int k = e - 1; k >= s0; --k) {
+      acc = acc * cf[k];
+      qb[k] = acc;
+    }
+  }
+}
+
 // Coefficients of level l in FP64: V, Tx, Ty, Tz (nz+1), and the Thomas
 // factors 1/p_k and T_{k+1/2}/p_k of the column matrix
 //   diag s_k + T_{k-1/2} + T_{k+1/2}, off-diagonals -T_{k+-1/2},
@@ -223,6 +247,7 @@ void level_table64(const ell_grid *g, int l, std::vector<double> &t) {
     ip[k] = 1.0 / p;
     cf[k] = Tz[k + 1] / p;
   }
+  segment_products(nz, Tz, ip, cf, &t[TPF * P], &t[TQB * P]);
 }
 
 // FP32 tables: either the FP64 values rounded once, or (BF16 mode) the
@@ -232,7 +257,10 @@ void level_table32(const ell_grid *g, int l, const std::vector<double> &t64, std
   const int nz = g->d.nz, P = nz + 1;
   t.assign((size_t)TSLOTS * P, 0.0f);
   for (size_t i = 0; i < t64.size(); ++i) t[i] = (float)t64[i];
-  if (g->prec != ELL_FP32_BF16COEF) return;
+  if (g->prec != ELL_FP32_BF16COEF) {
+    segment_products(nz, &t[TZ * P], &t[TIP * P], &t[TCF * P], &t[TPF * P], &t[TQB * P]);
+    return;
+  }
   for (int s = TV; s <= TZ; ++s)
     for (int k = 0; k < P; ++k) t[s * P + k] = round_bf16(t[s * P + k]);
   float *V = &t[TV * P], *Tx = &t[TX * P], *Ty = &t[TY * P], *Tz = &t[TZ * P];
@@ -245,6 +273,7 @@ void level_table32(const ell_grid *g, int l, const std::vector<double> &t64, std
     ip[k] = 1.0f / p;
     cf[k] = Tz[k + 1] / p;
   }
+  segment_products(nz, Tz, ip, cf, &t[TPF * P], &t[TQB * P]);
 }
 
 size_t grid_bytes(const ell_grid_desc *d, int L) {
@@ -259,7 +288,7 @@ size_t grid_bytes(const ell_grid_desc *d, int L) {
     bytes += (size_t)TSLOTS * G.P * es;
     if (l > 0) bytes += 2 * 2 * (size_t)G.cs * es;
   }
-  const long long nb = std::max<long long>(blocks8(2 * (long long)g0.H), flat_blocks(n0 / 2));
+  const long long nb = std::max<long long>(seg_blocks(2 * (long long)g0.H), flat_blocks(n0 / 2));
   bytes += (size_t)nb * 2 * 8 + sizeof(PcgState) + (size_t)d->nz * 8;
   return bytes;
 }
@@ -286,6 +315,32 @@ struct ProfScope {
 // ------------------------------------------------------------------------
 // kernel launchers (element type R = double or float)
 // ------------------------------------------------------------------------
+template <typename R, bool FINE, bool HXY>
+void smooth_dispatch(int nb, hipStream_t s, const Geo &G, const R *tab, int c, bool zero, bool rho1,
+                     const R *bo, const R *uo, R *own, R *yb, R rho, const int *done) {
+  if (zero && rho1) k_smooth<R, true, true, FINE, HXY><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, yb, rho, done);
+  else if (zero) k_smooth<R, true, false, FINE, HXY><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, yb, rho, done);
+  else if (rho1) k_smooth<R, false, true, FINE, HXY><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, yb, rho, done);
+  else k_smooth<R, false, false, FINE, HXY><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, yb, rho, done);
+}
+
+template <typename R, bool FINE, int SEG>
+void seg_dispatch2(int nb, hipStream_t s, const Geo &G, const R *tab, int c, bool zero, bool rho1,
+                   const R *bo, const R *uo, R *own, R rho, const int *done) {
+  if (zero && rho1) k_smooth_seg<R, true, true, FINE, SEG><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+  else if (zero) k_smooth_seg<R, true, false, FINE, SEG><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+  else if (rho1) k_smooth_seg<R, false, true, FINE, SEG><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+  else k_smooth_seg<R, false, false, FINE, SEG><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+}
+
+template <typename R, bool FINE>
+void seg_dispatch(int nb, hipStream_t s, const Geo &G, const R *tab, int c, bool zero, bool rho1,
+                  const R *bo, const R *uo, R *own, R rho, const int *done, int Ls) {
+  if (Ls <= 16) seg_dispatch2<R, FINE, 16>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+  else if (Ls <= 32) seg_dispatch2<R, FINE, 32>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+  else seg_dispatch2<R, FINE, 64>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+}
+
 template <typename R>
 int launch_smooth(ell_grid *g, int l, int c, bool zero, const R *b, R *u, const int *done, hipStream_t s) {
   const Level &Lv = g->lev[l];
@@ -297,17 +352,24 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const R *b, R *u, const 
   const bool rho1 = g->d.rho == 1.0;
   R *yb = (R *)g->ybuf;
   const R rho = (R)g->d.rho;
+  const R *bo = b + (long long)c * G.cs;
+  const R *uo = u + (long long)(1 - c) * G.cs;
+  R *own = u + (long long)c * G.cs;
+  const bool hxy = G.has_x && G.has_y;
   ProfScope ps(g, ELL_K_SMOOTH0, s, l == 0);
+  const int Ls = seg_len(G.nz);
+  if (hxy && Ls <= 64) {
+    const int nbs = blocks8(((long long)ncol + kSegCols - 1) / kSegCols * kBlock);
+    if (l == 0) seg_dispatch<R, true>(nbs, s, G, tab, c, zero, rho1, bo, uo, own, rho, done, Ls);
+    else seg_dispatch<R, false>(nbs, s, G, tab, c, zero, rho1, bo, uo, own, rho, done, Ls);
+    return check_launch("k_smooth_seg");
+  }
   if (l == 0) {
-    if (zero && rho1) k_smooth<R, true, true, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
-    else if (zero) k_smooth<R, true, false, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
-    else if (rho1) k_smooth<R, false, true, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
-    else k_smooth<R, false, false, true><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+    if (hxy) smooth_dispatch<R, true, true>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
+    else smooth_dispatch<R, true, false>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
   } else {
-    if (zero && rho1) k_smooth<R, true, true, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
-    else if (zero) k_smooth<R, true, false, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
-    else if (rho1) k_smooth<R, false, true, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
-    else k_smooth<R, false, false, false><<<nb, kBlock, 0, s>>>(G, tab, c, b, u, yb, rho, done);
+    if (hxy) smooth_dispatch<R, false, true>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
+    else smooth_dispatch<R, false, false>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
   }
   return check_launch("k_smooth");
 }
@@ -319,7 +381,9 @@ int launch_restrict(ell_grid *g, int l, const R *b, const R *u, R *bc, bool bz, 
   const int nb = blocks8(2LL * C.H);
   const R *tab = (const R *)g->lev[l].tab;
   ProfScope ps(g, ELL_K_RESTRICT0, s, l == 0);
-  if (bz) k_resid_restrict<R, true><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
+  if (bz && F.has_x && F.has_y)
+    k_resid_restrict_bz<R><<<seg_blocks(2LL * C.H), kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
+  else if (bz) k_resid_restrict<R, true><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
   else k_resid_restrict<R, false><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
   return check_launch("k_resid_restrict");
 }
@@ -327,7 +391,7 @@ int launch_restrict(ell_grid *g, int l, const R *b, const R *u, R *bc, bool bz, 
 template <typename R>
 int launch_prolong(ell_grid *g, int l, const R *uc, R *u, bool red_only, const int *done, hipStream_t s) {
   const Geo &F = g->lev[l].geo, &C = g->lev[l + 1].geo;
-  const int nb = blocks8(red_only ? (long long)F.ncol0 : 2LL * F.H);
+  const int nb = seg_blocks(red_only ? (long long)F.ncol0 : 2LL * F.H);
   ProfScope ps(g, ELL_K_PROLONG0, s, l == 0);
   if (g->d.prolong == 1) {
     if (red_only) k_prolong<R, true, 1><<<nb, kBlock, 0, s>>>(F, C, uc, u, done);
@@ -384,12 +448,15 @@ int vcycle_impl(ell_grid *g, const R *b0, R *u0, const int *done, hipStream_t s)
 
 int launch_apply64(ell_grid *g, const double *x, double *y, bool dot, const int *done, hipStream_t s) {
   const Geo &G = g->lev[0].geo;
-  const int nb = blocks8(2LL * G.H);
+  const int nb = seg_blocks(2LL * G.H);
   // the CG operator is always FP64 (FP32 grids keep a separate FP64 table)
   const double *tab64 = g->tab64_0;
   ProfScope ps(g, ELL_K_APPLY, s, dot);
-  if (dot) k_apply<double, true><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
-  else k_apply<double, false><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+  const bool hxy = G.has_x && G.has_y;
+  if (dot && hxy) k_apply<double, true, true><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+  else if (dot) k_apply<double, true, false><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+  else if (hxy) k_apply<double, false, true><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+  else k_apply<double, false, false><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
   return check_launch("k_apply");
 }
 
@@ -422,7 +489,7 @@ int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, e
   const Geo &G = g->lev[0].geo;
   const long long n2 = g->n0 / 2;
   const int fb = flat_blocks(n2);
-  const int ab = blocks8(2LL * G.H);
+  const int ab = seg_blocks(2LL * G.H);  // blocks of the CG operator kernel
   const int *done = &g->st->done;
   const typename Vec2<Z>::T *zv =
       (const typename Vec2<Z>::T *)(g->prec == ELL_FP64 ? (void *)g->z : g->z32);
@@ -593,7 +660,7 @@ int ell_grid_create(const ell_grid_desc *desc, ell_grid **out) {
   }
   if (desc->rho != 1.0)
     if ((rc = dalloc(g, &g->ybuf, (size_t)G0.cs * g->esz)) != ELL_OK) return bail(rc);
-  const long long nb = std::max<long long>(blocks8(2LL * G0.H), flat_blocks(g->n0 / 2));
+  const long long nb = std::max<long long>(seg_blocks(2LL * G0.H), flat_blocks(g->n0 / 2));
   g->partial_cap = nb * 2;
   if ((rc = dalloc(g, &tmp, (size_t)g->partial_cap * 8)) != ELL_OK) return bail(rc);
   g->partial = (double *)tmp;
@@ -749,13 +816,13 @@ int ell_level_apply(ell_grid *g, int level, const void *x, void *y, hipStream_t 
   CHK(check_level(g, level, false));
   if (!x || !y || x == y) return fail(ELL_ERR_INVALID, "bad vector arguments");
   const Geo &G = g->lev[level].geo;
-  const int nb = blocks8(2LL * G.H);
+  const int nb = seg_blocks(2LL * G.H);
   if (g->prec == ELL_FP64)
-    k_apply<double, false><<<nb, kBlock, 0, s>>>(G, (const double *)g->lev[level].tab, (const double *)x,
-                                                 (double *)y, nullptr, nullptr);
+    k_apply<double, false, false><<<nb, kBlock, 0, s>>>(G, (const double *)g->lev[level].tab,
+                                                        (const double *)x, (double *)y, nullptr, nullptr);
   else
-    k_apply<float, false><<<nb, kBlock, 0, s>>>(G, (const float *)g->lev[level].tab, (const float *)x,
-                                                (float *)y, nullptr, nullptr);
+    k_apply<float, false, false><<<nb, kBlock, 0, s>>>(G, (const float *)g->lev[level].tab,
+                                                       (const float *)x, (float *)y, nullptr, nullptr);
   return check_launch("k_apply");
 }
 
@@ -785,6 +852,17 @@ int ell_profile_read(ell_grid *g, int family, int *count, double *total_ms) {
   *count = p.n;
   *total_ms = tot;
   return ELL_OK;
+}
+
+int ell_profile_times(ell_grid *g, int family, float *ms, int cap) {
+  if (!g || family < 0 || family >= ELL_K_COUNT || !ms || cap < 0)
+    return fail(ELL_ERR_INVALID, "bad profiling arguments");
+  Prof &p = g->prof[family];
+  for (int i = 0; i < p.n && i < cap; ++i) {
+    HIPCHK(hipEventSynchronize(p.ev[2 * i + 1]));
+    HIPCHK(hipEventElapsedTime(&ms[i], p.ev[2 * i], p.ev[2 * i + 1]));
+  }
+  return p.n;
 }
 
 }  // extern "C"

@@ -19,7 +19,16 @@ namespace ell {
 constexpr int kBlock = 256;  // 4 wavefronts of 64 lanes
 
 // Table slots of one level, each nz+1 long (see host-side construction).
-enum : int { TV = 0, TX = 1, TY = 2, TZ = 3, TIP = 4, TCF = 5, TSLOTS = 6 };
+// TPF/TQB: products of the forward / backward recurrence multipliers over
+// each k-segment (see k_smooth_seg).
+enum : int { TV = 0, TX = 1, TY = 2, TZ = 3, TIP = 4, TCF = 5, TPF = 6, TQB = 7, TSLOTS = 8 };
+
+// Segments a column is split into along k: one wavefront per segment, four
+// per 256-thread block, so a block covers 64 columns.
+constexpr int kSeg = 4;
+constexpr int kSegCols = 64;
+
+__host__ __device__ inline int seg_len(int nz) { return (nz + kSeg - 1) / kSeg; }
 
 // Geometry of one level in the colour-split layout.
 struct Geo {
@@ -78,6 +87,29 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
+// Neighbour columns (colour 1 - c) of column (i, j) in the split layout.
+struct Nbr {
+  int w, e, s, n;
+};
+
+__device__ __forceinline__ Nbr neighbours(const Geo &L, int i, int j) {
+  Nbr r{0, 0, 0, 0};
+  if (L.has_x) {
+    r.w = col_m(L, wrapi(i - 1, L.nx), j);
+    r.e = col_m(L, wrapi(i + 1, L.nx), j);
+  }
+  if (L.has_y) {
+    r.s = col_m(L, i, wrapi(j - 1, L.ny));
+    r.n = col_m(L, i, wrapi(j + 1, L.ny));
+  }
+  return r;
+}
+
+// Number of levels whose loads are issued together before they are used:
+// the column recurrences are sequential in k, so the memory-level
+// parallelism of a lane comes from fetching a chunk of levels at once.
+constexpr int kChunk = 8;
+
 // -------------------------------------------------------------------------
 // One colour of block red/black SOR (Sec. 4.2 eq. BlockRBSOR): per column of
 // colour c, g_k = b_k + Tx_k (u_W + u_E) + Ty_k (u_S + u_N) with the other
@@ -86,34 +118,33 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 // forward, w_k = y_k + (T_{k+1/2}/p_k) w_{k+1} backward.  The forward values y
 // are parked in the output column itself (rho = 1) and read back on the way
 // down, so no per-lane array is needed and occupancy stays high.
-// -------------------------------------------------------------------------
+//   bo: b of colour c; uo: u of colour 1-c; own: u of colour c (distinct
+//   arrays, so loads can run ahead of the stores).
 // FINE marks launches on the finest level (a separate kernel symbol, so that
-// profiles attribute the dominant launches to it alone).
-template <typename R, bool ZERO, bool RHO1, bool FINE>
+// profiles attribute the dominant launches to it alone).  HXY: both
+// horizontal directions have faces (every level but degenerate 1-wide ones).
+// -------------------------------------------------------------------------
+template <typename R, bool ZERO, bool RHO1, bool FINE, bool HXY>
 __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ tab, int c,
-                                                   const R *__restrict__ b, R *__restrict__ u,
-                                                   R *__restrict__ ybuf, R rho,
-                                                   const int *__restrict__ done) {
+                                                   const R *__restrict__ bo,
+                                                   const R *__restrict__ uo,
+                                                   R *__restrict__ own, R *__restrict__ ybuf,
+                                                   R rho, const int *__restrict__ done) {
   if (is_done(done)) return;
   const int m = logical_block() * kBlock + threadIdx.x;
   const int ncol = c ? L.ncol1 : L.ncol0;
   if (m >= ncol) return;
   int i, j;
   col_ij(L, c, m, i, j);
-  int mW = 0, mE = 0, mS = 0, mN = 0;
-  if (L.has_x) {
-    mW = col_m(L, wrapi(i - 1, L.nx), j);
-    mE = col_m(L, wrapi(i + 1, L.nx), j);
-  }
-  if (L.has_y) {
-    mS = col_m(L, i, wrapi(j - 1, L.ny));
-    mN = col_m(L, i, wrapi(j + 1, L.ny));
-  }
+  const Nbr nb = ZERO ? Nbr{0, 0, 0, 0} : neighbours(L, i, j);
+  const bool hx = HXY || L.has_x, hy = HXY || L.has_y;
   const long long H = L.H;
-  const R *__restrict__ bo = b + (long long)c * L.cs + m;
-  const R *__restrict__ uo = u + (long long)(1 - c) * L.cs;
-  R *__restrict__ own = u + (long long)c * L.cs + m;
-  // forward values: in the output column itself (rho = 1) or in ybuf
+  bo += m;
+  own += m;
+  const R *__restrict__ uw = uo + nb.w;
+  const R *__restrict__ ue = uo + nb.e;
+  const R *__restrict__ us = uo + nb.s;
+  const R *__restrict__ un = uo + nb.n;
   R *ys = RHO1 ? own : ybuf + m;
   const R *__restrict__ tx = tab + TX * L.P;
   const R *__restrict__ ty = tab + TY * L.P;
@@ -122,34 +153,188 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ 
   const R *__restrict__ cf = tab + TCF * L.P;
   const int nz = L.nz;
 
-  R yprev = R(0);
-#pragma unroll 4
-  for (int k = 0; k < nz; ++k) {
+  auto gval = [&](int k) -> R {
     const long long o = (long long)k * H;
-    R g = bo[o];
+    R v = bo[o];
     if (!ZERO) {
-      if (L.has_x) g = g + tx[k] * (uo[o + mW] + uo[o + mE]);
-      if (L.has_y) g = g + ty[k] * (uo[o + mS] + uo[o + mN]);
+      if (hx) v = v + tx[k] * (uw[o] + ue[o]);
+      if (hy) v = v + ty[k] * (us[o] + un[o]);
     }
-    const R y = (g + tz[k] * yprev) * ip[k];
-    ys[o] = y;
+    return v;
+  };
+
+  R yprev = R(0);
+  int k = 0;
+  for (; k + kChunk <= nz; k += kChunk) {
+    R g[kChunk];
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) g[t] = gval(k + t);
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) {
+      const R y = (g[t] + tz[k + t] * yprev) * ip[k + t];
+      ys[(long long)(k + t) * H] = y;
+      yprev = y;
+    }
+  }
+  for (; k < nz; ++k) {
+    const R y = (gval(k) + tz[k] * yprev) * ip[k];
+    ys[(long long)k * H] = y;
     yprev = y;
   }
+
   R w = yprev;
   if (!RHO1) {
     const long long o = (long long)(nz - 1) * H;
     const R old = ZERO ? R(0) : own[o];
     own[o] = (R(1) - rho) * old + rho * w;
   }
-#pragma unroll 4
-  for (int k = nz - 2; k >= 0; --k) {
+  k = nz - 2;
+  for (; k + 1 >= kChunk; k -= kChunk) {
+    R y[kChunk], old[kChunk];
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) {
+      y[t] = ys[(long long)(k - t) * H];
+      old[t] = (RHO1 || ZERO) ? R(0) : own[(long long)(k - t) * H];
+    }
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) {
+      w = y[t] + cf[k - t] * w;
+      own[(long long)(k - t) * H] = RHO1 ? w : (R(1) - rho) * old[t] + rho * w;
+    }
+  }
+  for (; k >= 0; --k) {
     const long long o = (long long)k * H;
-    w = (RHO1 ? own[o] : ys[o]) + cf[k] * w;
-    if (RHO1) {
-      own[o] = w;
-    } else {
-      const R old = ZERO ? R(0) : own[o];
-      own[o] = (R(1) - rho) * old + rho * w;
+    const R old = (RHO1 || ZERO) ? R(0) : own[o];
+    w = ys[o] + cf[k] * w;
+    own[o] = RHO1 ? w : (R(1) - rho) * old + rho * w;
+  }
+}
+
+// -------------------------------------------------------------------------
+// The same half-sweep with each column split into kSeg segments along k, one
+// wavefront per segment (k is uniform across a wavefront, so coefficients are
+// scalar loads and every access is 64 consecutive elements).  The Thomas
+// factors are shared by all columns, so the two triangular recurrences
+//   forward  y_k = a_k y_{k-1} + g_k/p_k,   a_k = T_{k-1/2}/p_k
+//   backward w_k = y_k + c_k w_{k+1},       c_k = T_{k+1/2}/p_k
+// are evaluated per segment from a zero start and joined afterwards:
+//   y_k = y_k(local) + Pf_k y_in,   Pf_k = prod_{i=start..k} a_i
+//   w_k = w_k(local) + Qb_k w_in,   Qb_k = prod_{i=k..end-1} c_i
+// with y_in / w_in the true values just below / above the segment, passed
+// from segment to segment through LDS.  Pf and Qb are per-level tables.  The
+// forward values stay in registers (SEG >= segment length).
+// -------------------------------------------------------------------------
+template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG>
+__global__ __launch_bounds__(kBlock) void k_smooth_seg(Geo L, const R *__restrict__ tab, int c,
+                                                       const R *__restrict__ bo,
+                                                       const R *__restrict__ uo,
+                                                       R *__restrict__ own, R rho,
+                                                       const int *__restrict__ done) {
+  __shared__ R xch[kSeg][kSegCols];
+  if (is_done(done)) return;
+  const int lane = threadIdx.x & 63;
+  const int sg = threadIdx.x >> 6;
+  const int ncol = c ? L.ncol1 : L.ncol0;
+  const int m = logical_block() * kSegCols + lane;
+  const bool valid = m < ncol;
+  const int mm = valid ? m : ncol - 1;  // in-bounds column for loads of idle lanes
+  const int nz = L.nz, Ls = seg_len(nz);
+  const int k0 = min(sg * Ls, nz), k1 = min(k0 + Ls, nz), len = k1 - k0;
+  int i, j;
+  col_ij(L, c, mm, i, j);
+  const Nbr nb = ZERO ? Nbr{0, 0, 0, 0} : neighbours(L, i, j);
+  const long long H = L.H;
+  const R *__restrict__ bb = bo + mm;
+  const R *__restrict__ uw = uo + nb.w;
+  const R *__restrict__ ue = uo + nb.e;
+  const R *__restrict__ us = uo + nb.s;
+  const R *__restrict__ un = uo + nb.n;
+  R *__restrict__ ow = own + mm;
+  const R *__restrict__ tx = tab + TX * L.P;
+  const R *__restrict__ ty = tab + TY * L.P;
+  const R *__restrict__ tz = tab + TZ * L.P;
+  const R *__restrict__ ip = tab + TIP * L.P;
+  const R *__restrict__ cf = tab + TCF * L.P;
+  const R *__restrict__ pf = tab + TPF * L.P;
+  const R *__restrict__ qb = tab + TQB * L.P;
+
+  R y[SEG];
+  R prev = R(0);
+#pragma unroll
+  for (int c0 = 0; c0 < SEG; c0 += 8) {
+    if (c0 < len) {
+      R g[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int k = min(k0 + c0 + t, k1 - 1);
+        const long long o = (long long)k * H;
+        R v = bb[o];
+        if (!ZERO) {
+          v = v + tx[k] * (uw[o] + ue[o]);
+          v = v + ty[k] * (us[o] + un[o]);
+        }
+        g[t] = v;
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (c0 + t < len) {
+          const int k = k0 + c0 + t;
+          prev = (g[t] + tz[k] * prev) * ip[k];
+          y[c0 + t] = prev;
+        }
+      }
+    }
+  }
+  // join the forward recurrence across segments
+  xch[sg][lane] = prev;
+  __syncthreads();
+  R yin = R(0);
+  for (int q = 0; q < sg; ++q) {
+    const int e = min(q * Ls + Ls, nz);
+    const int s0 = min(q * Ls, nz);
+    const R pend = e > s0 ? pf[e - 1] : R(1);
+    yin = xch[q][lane] + pend * yin;
+  }
+  __syncthreads();
+  // true y, then the local backward recurrence (in place)
+  R nxt = R(0);
+#pragma unroll
+  for (int t = SEG - 1; t >= 0; --t) {
+    if (t < len) {
+      const int k = k0 + t;
+      const R yt = y[t] + pf[k] * yin;
+      nxt = yt + cf[k] * nxt;
+      y[t] = nxt;
+    }
+  }
+  xch[sg][lane] = nxt;  // local w at the segment's first level
+  __syncthreads();
+  R win = R(0);
+  for (int q = kSeg - 1; q > sg; --q) {
+    const int s0 = min(q * Ls, nz);
+    const int e = min(s0 + Ls, nz);
+    const R qs = e > s0 ? qb[s0] : R(1);
+    win = xch[q][lane] + qs * win;
+  }
+  if (valid) {
+#pragma unroll
+    for (int c0 = 0; c0 < SEG; c0 += 8) {
+      if (c0 < len) {
+        R old[8];
+        if (!RHO1 && !ZERO) {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) old[t] = ow[(long long)min(k0 + c0 + t, k1 - 1) * H];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          if (c0 + t < len) {
+            const int k = k0 + c0 + t;
+            const R w = y[c0 + t] + qb[k] * win;
+            const R o = (RHO1 || ZERO) ? R(0) : old[t];
+            ow[(long long)k * H] = RHO1 ? w : (R(1) - rho) * o + rho * w;
+          }
+        }
+      }
     }
   }
 }
@@ -170,6 +355,95 @@ __device__ __forceinline__ R cell_residual(R bk, R vk, R txk, R tyk, R tzlo, R t
   acc = acc + tzlo * (uc - um);
   acc = acc + tzhi * (uc - up);
   return bk - acc;
+}
+
+// -------------------------------------------------------------------------
+// Residual + restriction right after a colour-1 sweep with rho = 1: the
+// colour-1 children have zero residual, so each coarse column needs only its
+// two colour-0 children (2I, 2J) and (2I+1, 2J+1).  Their eight horizontal
+// neighbours are six distinct colour-1 columns:
+//   A = (2I-1, 2J)  B = (2I+1, 2J)  C = (2I, 2J-1)  D = (2I, 2J+1)
+//   E = (2I+2, 2J+1)  F = (2I+1, 2J+2)
+// child (2I,2J): W=A E=B S=C N=D;  child (2I+1,2J+1): W=D E=E S=B N=F.
+// Requires both horizontal directions to have faces.
+// -------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict_bz(Geo F, Geo C,
+                                                              const R *__restrict__ tab,
+                                                              const R *__restrict__ b,
+                                                              const R *__restrict__ u,
+                                                              R *__restrict__ bc,
+                                                              const int *__restrict__ done) {
+  constexpr int U = 4;
+  if (is_done(done)) return;
+  const int gid = logical_block() * kSegCols + (threadIdx.x & 63);
+  if (gid >= 2 * C.H) return;
+  const int cc = gid >= C.H ? 1 : 0;
+  const int mc = gid - cc * C.H;
+  if (mc >= (cc ? C.ncol1 : C.ncol0)) return;
+  const int Ls = seg_len(F.nz);
+  const int k0 = min((int)(threadIdx.x >> 6) * Ls, F.nz), k1 = min(k0 + Ls, F.nz);
+  int I, J;
+  col_ij(C, cc, mc, I, J);
+  const int i0 = 2 * I, j0 = 2 * J;
+  const long long H = F.H;
+  const R *__restrict__ ured = u;            // colour 0
+  const R *__restrict__ ublk = u + F.cs;     // colour 1
+  const R *__restrict__ u0 = ured + col_m(F, i0, j0);
+  const R *__restrict__ u1 = ured + col_m(F, i0 + 1, j0 + 1);
+  const R *__restrict__ b0 = b + col_m(F, i0, j0);
+  const R *__restrict__ b1 = b + col_m(F, i0 + 1, j0 + 1);
+  const R *__restrict__ pA = ublk + col_m(F, wrapi(i0 - 1, F.nx), j0);
+  const R *__restrict__ pB = ublk + col_m(F, i0 + 1, j0);
+  const R *__restrict__ pC = ublk + col_m(F, i0, wrapi(j0 - 1, F.ny));
+  const R *__restrict__ pD = ublk + col_m(F, i0, j0 + 1);
+  const R *__restrict__ pE = ublk + col_m(F, wrapi(i0 + 2, F.nx), j0 + 1);
+  const R *__restrict__ pF = ublk + col_m(F, i0 + 1, wrapi(j0 + 2, F.ny));
+  const R *__restrict__ tv = tab + TV * F.P;
+  const R *__restrict__ tx = tab + TX * F.P;
+  const R *__restrict__ ty = tab + TY * F.P;
+  const R *__restrict__ tz = tab + TZ * F.P;
+  R *__restrict__ out = bc + (long long)cc * C.cs + mc;
+  const int nz = F.nz;
+  if (k1 <= k0) return;
+  R c0 = u0[(long long)k0 * H], c1 = u1[(long long)k0 * H];
+  R m0 = k0 > 0 ? u0[(long long)(k0 - 1) * H] : c0;
+  R m1 = k0 > 0 ? u1[(long long)(k0 - 1) * H] : c1;
+  auto step = [&](int k, R bb0, R bb1, R p0, R p1, R A, R B, R Cv, R D, R E, R Fv) {
+    const R r0 = cell_residual<R>(bb0, tv[k], tx[k], ty[k], tz[k], tz[k + 1], c0, m0, p0, A, B, Cv, D, 1, 1);
+    const R r1 = cell_residual<R>(bb1, tv[k], tx[k], ty[k], tz[k], tz[k + 1], c1, m1, p1, D, E, B, Fv, 1, 1);
+    out[(long long)k * C.H] = r0 + r1;
+    m0 = c0;
+    c0 = p0;
+    m1 = c1;
+    c1 = p1;
+  };
+  int k = k0;
+  for (; k + U <= k1; k += U) {
+    R bb0[U], bb1[U], p0[U], p1[U], A[U], B[U], Cv[U], D[U], E[U], Fv[U];
+#pragma unroll
+    for (int t = 0; t < U; ++t) {
+      const long long o = (long long)(k + t) * H;
+      const long long op = (long long)min(k + t + 1, nz - 1) * H;
+      bb0[t] = b0[o];
+      bb1[t] = b1[o];
+      p0[t] = u0[op];
+      p1[t] = u1[op];
+      A[t] = pA[o];
+      B[t] = pB[o];
+      Cv[t] = pC[o];
+      D[t] = pD[o];
+      E[t] = pE[o];
+      Fv[t] = pF[o];
+    }
+#pragma unroll
+    for (int t = 0; t < U; ++t) step(k + t, bb0[t], bb1[t], p0[t], p1[t], A[t], B[t], Cv[t], D[t], E[t], Fv[t]);
+  }
+  for (; k < k1; ++k) {
+    const long long o = (long long)k * H;
+    const long long op = (long long)min(k + 1, nz - 1) * H;
+    step(k, b0[o], b1[o], u0[op], u1[op], pA[o], pB[o], pC[o], pD[o], pE[o], pF[o]);
+  }
 }
 
 // -------------------------------------------------------------------------
@@ -258,7 +532,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__res
                                                     R *__restrict__ u,
                                                     const int *__restrict__ done) {
   if (is_done(done)) return;
-  const int gid = logical_block() * kBlock + threadIdx.x;
+  const int gid = logical_block() * kSegCols + (threadIdx.x & 63);
   int c, m;
   if (RED_ONLY) {
     c = 0;
@@ -270,6 +544,8 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__res
     m = gid - c * F.H;
     if (m >= (c ? F.ncol1 : F.ncol0)) return;
   }
+  const int Ls = seg_len(F.nz);
+  const int k0 = min((int)(threadIdx.x >> 6) * Ls, F.nz), k1 = min(k0 + Ls, F.nz);
   int i, j;
   col_ij(F, c, m, i, j);
   const int I = i >> 1, J = j >> 1;
@@ -281,19 +557,37 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__res
   const R *__restrict__ p22 = uc + (long long)((I2 + J2) & 1) * C.cs + col_m(C, I2, J2);
   R *__restrict__ own = u + (long long)c * F.cs + m;
   const long long HC = C.H, HF = F.H;
-  const int nz = F.nz;
-#pragma unroll 4
-  for (int k = 0; k < nz; ++k) {
-    R e;
-    if (MODE == 1) {
-      e = p11[k * HC];
-    } else {
-      e = R(9.0 / 16.0) * p11[k * HC];
-      e = e + R(3.0 / 16.0) * p21[k * HC];
-      e = e + R(3.0 / 16.0) * p12[k * HC];
-      e = e + R(1.0 / 16.0) * p22[k * HC];
+  auto interp = [&](R a, R b2, R c2, R d) -> R {
+    if (MODE == 1) return a;
+    R e = R(9.0 / 16.0) * a;
+    e = e + R(3.0 / 16.0) * b2;
+    e = e + R(3.0 / 16.0) * c2;
+    e = e + R(1.0 / 16.0) * d;
+    return e;
+  };
+  int k = k0;
+  for (; k + kChunk <= k1; k += kChunk) {
+    R o[kChunk], a[kChunk], b2[kChunk], c2[kChunk], d[kChunk];
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) {
+      const long long kc = (long long)(k + t) * HC;
+      o[t] = own[(long long)(k + t) * HF];
+      a[t] = p11[kc];
+      if (MODE != 1) {
+        b2[t] = p21[kc];
+        c2[t] = p12[kc];
+        d[t] = p22[kc];
+      } else {
+        b2[t] = c2[t] = d[t] = R(0);
+      }
     }
-    own[k * HF] = own[k * HF] + e;
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) own[(long long)(k + t) * HF] = o[t] + interp(a[t], b2[t], c2[t], d[t]);
+  }
+  for (; k < k1; ++k) {
+    const long long kc = (long long)k * HC;
+    const R e = MODE == 1 ? p11[kc] : interp(p11[kc], p21[kc], p12[kc], p22[kc]);
+    own[(long long)k * HF] = own[(long long)k * HF] + e;
   }
 }
 
@@ -301,32 +595,33 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__res
 // y = A x (eq. ModelEquation integrated over the cell, difference form), one
 // lane per column of either colour; DOT: also partial sums of <x, y>.
 // -------------------------------------------------------------------------
-template <typename R, bool DOT>
+template <typename R, bool DOT, bool HXY>
 __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ tab,
                                                   const R *__restrict__ x, R *__restrict__ y,
                                                   double *__restrict__ partial,
                                                   const int *__restrict__ done) {
   __shared__ double sh[4];
   if (is_done(done)) return;
-  const int gid = logical_block() * kBlock + threadIdx.x;
-  const int c = gid >= L.H ? 1 : 0;
-  const int m = gid - c * L.H;
-  const bool valid = gid < 2 * L.H && m < (c ? L.ncol1 : L.ncol0);
+  // 64 column slots (both colours) per block, one k-segment per wavefront
+  const int slot = logical_block() * kSegCols + (threadIdx.x & 63);
+  const int sg = threadIdx.x >> 6;
+  const int c = slot >= L.H ? 1 : 0;
+  const int m = slot - c * L.H;
+  const bool valid = slot < 2 * L.H && m < (c ? L.ncol1 : L.ncol0);
+  const int Ls = seg_len(L.nz);
+  const int k0 = min(sg * Ls, L.nz), k1 = min(k0 + Ls, L.nz);
   double dot = 0.0;
-  if (valid) {
+  if (valid && k1 > k0) {
     int i, j;
     col_ij(L, c, m, i, j);
-    int mW = 0, mE = 0, mS = 0, mN = 0;
-    if (L.has_x) {
-      mW = col_m(L, wrapi(i - 1, L.nx), j);
-      mE = col_m(L, wrapi(i + 1, L.nx), j);
-    }
-    if (L.has_y) {
-      mS = col_m(L, i, wrapi(j - 1, L.ny));
-      mN = col_m(L, i, wrapi(j + 1, L.ny));
-    }
+    const Nbr nb = neighbours(L, i, j);
+    const bool hx = HXY || L.has_x, hy = HXY || L.has_y;
     const long long H = L.H;
     const R *__restrict__ xo = x + (long long)(1 - c) * L.cs;
+    const R *__restrict__ xw = xo + nb.w;
+    const R *__restrict__ xe = xo + nb.e;
+    const R *__restrict__ xs_ = xo + nb.s;
+    const R *__restrict__ xn = xo + nb.n;
     const R *__restrict__ xs = x + (long long)c * L.cs + m;
     R *__restrict__ ys = y + (long long)c * L.cs + m;
     const R *__restrict__ tv = tab + TV * L.P;
@@ -334,27 +629,53 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ t
     const R *__restrict__ ty = tab + TY * L.P;
     const R *__restrict__ tz = tab + TZ * L.P;
     const int nz = L.nz;
-    R xc = xs[0];
-    R xm = xc;
-#pragma unroll 4
-    for (int k = 0; k < nz; ++k) {
-      const long long o = (long long)k * H;
-      const R xp = (k + 1 < nz) ? xs[o + H] : xc;
+    auto cell = [&](int k, R xc, R xm, R xp, R w, R e, R so, R no) -> R {
       R acc = tv[k] * xc;
-      if (L.has_x) {
-        acc = acc + tx[k] * (xc - xo[o + mW]);
-        acc = acc + tx[k] * (xc - xo[o + mE]);
+      if (hx) {
+        acc = acc + tx[k] * (xc - w);
+        acc = acc + tx[k] * (xc - e);
       }
-      if (L.has_y) {
-        acc = acc + ty[k] * (xc - xo[o + mS]);
-        acc = acc + ty[k] * (xc - xo[o + mN]);
+      if (hy) {
+        acc = acc + ty[k] * (xc - so);
+        acc = acc + ty[k] * (xc - no);
       }
       acc = acc + tz[k] * (xc - xm);
       acc = acc + tz[k + 1] * (xc - xp);
+      return acc;
+    };
+    R xc = xs[(long long)k0 * H];
+    R xm = k0 > 0 ? xs[(long long)(k0 - 1) * H] : xc;
+    int k = k0;
+    for (; k + kChunk <= k1; k += kChunk) {
+      R xp[kChunk], w[kChunk], e[kChunk], so[kChunk], no[kChunk];
+#pragma unroll
+      for (int t = 0; t < kChunk; ++t) {
+        const long long o = (long long)(k + t) * H;
+        const int kp = min(k + t + 1, nz - 1);
+        xp[t] = xs[(long long)kp * H];
+        w[t] = hx ? xw[o] : R(0);
+        e[t] = hx ? xe[o] : R(0);
+        so[t] = hy ? xs_[o] : R(0);
+        no[t] = hy ? xn[o] : R(0);
+      }
+#pragma unroll
+      for (int t = 0; t < kChunk; ++t) {
+        const R acc = cell(k + t, xc, xm, xp[t], w[t], e[t], so[t], no[t]);
+        ys[(long long)(k + t) * H] = acc;
+        if (DOT) dot += (double)xc * (double)acc;
+        xm = xc;
+        xc = xp[t];
+      }
+    }
+    for (; k < k1; ++k) {
+      const long long o = (long long)k * H;
+      const R xpv = xs[(long long)min(k + 1, nz - 1) * H];
+      const R acc = cell(k, xc, xm, xpv, hx ? xw[o] : R(0), hx ? xe[o] : R(0), hy ? xs_[o] : R(0),
+                         hy ? xn[o] : R(0));
       ys[o] = acc;
       if (DOT) dot += (double)xc * (double)acc;
       xm = xc;
-      xc = xp;
+      xc = xpv;
     }
   }
   if (DOT) {

@@ -55,7 +55,7 @@ EXPORTS = ["ell_grid_create", "ell_grid_destroy", "ell_grid_bytes", "ell_grid_le
            "ell_apply_A", "ell_vcycle", "ell_pcg_solve", "ell_level_elems", "ell_to_split",
            "ell_from_split", "ell_level_smooth", "ell_level_resid_restrict",
            "ell_level_prolong_add", "ell_level_apply", "ell_profile_enable", "ell_profile_read",
-           "ell_last_error"]
+           "ell_profile_times", "ell_last_error"]
 
 _lib = None
 
@@ -88,6 +88,7 @@ def load_library(path: str = LIB_PATH):
     L.ell_level_apply.argtypes = [vp, i32, vp, vp, vp]
     L.ell_profile_enable.argtypes = [vp, i32, i32]
     L.ell_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+    L.ell_profile_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_float), i32]
     L.ell_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("ell_grid_bytes", "ell_level_elems", "ell_last_error"):
@@ -262,3 +263,11 @@ class Grid:
         ms = ctypes.c_double()
         _check(load_library().ell_profile_read(self._h, family, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+    def profile_times(self, family: int) -> np.ndarray:
+        """Per-launch times (ms) of the recorded launches, in launch order."""
+        n, _ = self.profile_read(family)
+        buf = (ctypes.c_float * max(n, 1))()
+        got = load_library().ell_profile_times(self._h, family, buf, n)
+        _check(0 if got >= 0 else got)
+        return np.frombuffer(buf, dtype=np.float32, count=n).astype(np.float64)

@@ -15,6 +15,7 @@ import pytest
 import torch
 
 from helpers import small_grid
+from solve_parity import check_solve
 from paper_1307_2036_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -218,6 +219,7 @@ def test_config0_solve_matches_oracle(ell, orc):
     u_ref, st_ref = orc.pcg(g, p.f, rtol=p.rtol)
     G = ell.Grid.from_problem(p)
     u, st = G.pcg_solve(dev(p.f), rtol=p.rtol)
+    # uniform, moderately anisotropic grid: the stopping count is not rounding-sensitive
     assert st.status == 0 and st.iters == st_ref["iters"]
     assert rel(host(u), u_ref) <= 1e-10
     assert abs(st.r0_norm / st_ref["r0_norm"] - 1) < 1e-12
@@ -236,11 +238,10 @@ def test_graded_solves_match_oracle(ell, orc, name, kw, opts):
     p = I.graded_problem(name, nx, nz, 1e-2, 11, 12, **kw)
     g = orc.Grid.from_problem(p)
     rtol = opts.pop("rtol", 1e-5)
-    u_ref, st_ref = orc.pcg(g, p.f, rtol=rtol, **opts)
     G = ell.Grid.from_problem(p)
     u, st = G.pcg_solve(dev(p.f), rtol=rtol, **opts)
-    assert st.status == 0 and st.iters == st_ref["iters"], (st, st_ref)
-    assert rel(host(u), u_ref) <= 1e-10
+    assert st.status == 0
+    check_solve(orc, g, p.f, host(u), st, rtol, **opts)
 
 
 def test_solve_edge_cases(ell, orc):
