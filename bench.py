@@ -33,6 +33,8 @@ def parse():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--nu-coarse", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="also run one plain device copy of a 268 MB vector (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum seconds of oracle work in the CPU-baseline sample")
     return ap.parse_args()
@@ -79,6 +81,13 @@ def main():
         u.zero_()
         return G.pcg_solve(f, u, rtol=p.rtol, maxiter=500, poll_every=8)
 
+    if a.probe_copy:
+        # a plain copy of known size: 2^25 doubles read and written once
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(a.warmup):
         _, st = step()
     torch.cuda.synchronize()

@@ -141,10 +141,15 @@ int ell_pcg_solve(ell_grid *g, const double *f, double *u, const ell_solve_opts 
 
 /* ---- level entry points (the V-cycle's kernels one at a time) ------------
  * Colour-split layout of level l (nx_l = nx >> l, ny_l = ny >> l): element
- * (i, j, k) of colour c = (i+j) mod 2 lives at c*nz*H + k*H + m, where
- * H = ceil(nx_l*ny_l/2) and m = j*(nx_l/2) + i/2 (m = j/2 when nx_l = 1).
- * Element type: double for ELL_FP64 grids, float otherwise. */
-size_t ell_level_elems(const ell_grid *g, int level);  /* 2*nz*H; 0 if invalid */
+ * (i, j, k) of colour c = (i+j) mod 2 lives at c*C + k*S + m, where
+ * m = j*(nx_l/2) + i/2 (m = j/2 when nx_l = 1) runs over the H =
+ * ceil(nx_l*ny_l/2) columns of the colour, S >= H is the padded plane stride
+ * and C >= nz*S the colour stride (see ell_level_layout).  Padding entries
+ * are zero and never written.  Element type: double for ELL_FP64 grids,
+ * float otherwise. */
+size_t ell_level_elems(const ell_grid *g, int level);  /* 2*C; 0 if invalid */
+int ell_level_layout(const ell_grid *g, int level, int64_t *cols, int64_t *plane_stride,
+                     int64_t *colour_stride);
 
 /* plane-major FP64 -> split / split -> plane-major FP64 conversion */
 int ell_to_split(ell_grid *g, int level, const double *src, void *dst, hipStream_t stream);
@@ -189,6 +194,11 @@ int ell_profile_read(ell_grid *g, int family, int *count, double *total_ms);
  * negative error.  Launches enqueued after the solve converged return at once
  * and show up as near-zero times. */
 int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
+
+/* Layout tuning for grids created afterwards (process-wide): padding, in
+ * elements, added to the plane stride S and to the colour stride C. */
+enum { ELL_TUNE_PLANE_PAD = 0, ELL_TUNE_COLOUR_PAD = 1 };
+int ell_set_tuning(int key, int value);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char *ell_last_error(void);

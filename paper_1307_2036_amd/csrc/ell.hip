@@ -144,6 +144,13 @@ int dalloc(ell_grid *g, void **p, size_t bytes) {
   return ELL_OK;
 }
 
+// Layout tuning (process-wide; read when a grid is created).  Each k-plane of
+// a colour array is padded so that the planes a column walk touches in
+// parallel do not all start at the same offset modulo the HBM channel
+// interleave; the two colour arrays are offset from each other likewise.
+int g_plane_pad = 64;
+int g_colour_pad = 256;
+
 Geo make_geo(int nx, int ny, int nz) {
   Geo G;
   G.nx = nx;
@@ -157,7 +164,8 @@ Geo make_geo(int nx, int ny, int nz) {
   G.has_x = nx > 1;
   G.has_y = ny > 1;
   G.P = nz + 1;
-  G.cs = (long long)nz * G.H;
+  G.S = (int)(((long long)G.H + 63) / 64 * 64 + g_plane_pad);
+  G.cs = (long long)nz * G.S + g_colour_pad;
   return G;
 }
 
@@ -863,6 +871,26 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap) {
     HIPCHK(hipEventElapsedTime(&ms[i], p.ev[2 * i], p.ev[2 * i + 1]));
   }
   return p.n;
+}
+
+int ell_level_layout(const ell_grid *g, int level, int64_t *cols, int64_t *plane_stride,
+                     int64_t *colour_stride) {
+  CHK(check_level(g, level, false));
+  if (!cols || !plane_stride || !colour_stride) return fail(ELL_ERR_INVALID, "NULL argument");
+  const Geo &G = g->lev[level].geo;
+  *cols = G.H;
+  *plane_stride = G.S;
+  *colour_stride = G.cs;
+  return ELL_OK;
+}
+
+int ell_set_tuning(int key, int value) {
+  if (value < 0 || value > (1 << 20)) return fail(ELL_ERR_INVALID, "tuning value out of range");
+  switch (key) {
+    case ELL_TUNE_PLANE_PAD: g_plane_pad = value; return ELL_OK;
+    case ELL_TUNE_COLOUR_PAD: g_colour_pad = value; return ELL_OK;
+    default: return fail(ELL_ERR_INVALID, "unknown tuning key %d", key);
+  }
 }
 
 }  // extern "C"

@@ -40,7 +40,9 @@ struct Geo {
   int has_x;      // nx > 1: x faces exist
   int has_y;      // ny > 1
   int P;          // table stride = nz + 1
-  long long cs;   // elements per colour array = nz * H
+  int S;          // plane stride of a colour array (>= H, padded so that
+                  // successive k-planes do not start on the same HBM channel)
+  long long cs;   // colour stride (>= nz * S)
 };
 
 struct PcgState {
@@ -74,6 +76,11 @@ __device__ __forceinline__ int col_m(const Geo &L, int i, int j) {
 }
 
 __device__ __forceinline__ bool is_done(const int *done) { return done != nullptr && *done != 0; }
+
+// Index of the wavefront within the block, known to the compiler to be the
+// same for all lanes (so values derived from it live in scalar registers and
+// coefficient reads indexed by it stay scalar loads).
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Sum over the 256 threads of a block; the result is valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double *sh) {
@@ -138,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ 
   col_ij(L, c, m, i, j);
   const Nbr nb = ZERO ? Nbr{0, 0, 0, 0} : neighbours(L, i, j);
   const bool hx = HXY || L.has_x, hy = HXY || L.has_y;
-  const long long H = L.H;
+  const long long H = L.S;
   bo += m;
   own += m;
   const R *__restrict__ uw = uo + nb.w;
@@ -233,7 +240,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_seg(Geo L, const R *__restric
   __shared__ R xch[kSeg][kSegCols];
   if (is_done(done)) return;
   const int lane = threadIdx.x & 63;
-  const int sg = threadIdx.x >> 6;
+  const int sg = wave_id();
   const int ncol = c ? L.ncol1 : L.ncol0;
   const int m = logical_block() * kSegCols + lane;
   const bool valid = m < ncol;
@@ -243,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_seg(Geo L, const R *__restric
   int i, j;
   col_ij(L, c, mm, i, j);
   const Nbr nb = ZERO ? Nbr{0, 0, 0, 0} : neighbours(L, i, j);
-  const long long H = L.H;
+  const long long H = L.S;
   const R *__restrict__ bb = bo + mm;
   const R *__restrict__ uw = uo + nb.w;
   const R *__restrict__ ue = uo + nb.e;
@@ -378,15 +385,15 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_bz(Geo F, Geo C,
   if (is_done(done)) return;
   const int gid = logical_block() * kSegCols + (threadIdx.x & 63);
   if (gid >= 2 * C.H) return;
-  const int cc = gid >= C.H ? 1 : 0;
-  const int mc = gid - cc * C.H;
+  const int cc = gid & 1;  // lanes alternate coarse colours (adjacent coarse columns)
+  const int mc = gid >> 1;
   if (mc >= (cc ? C.ncol1 : C.ncol0)) return;
   const int Ls = seg_len(F.nz);
-  const int k0 = min((int)(threadIdx.x >> 6) * Ls, F.nz), k1 = min(k0 + Ls, F.nz);
+  const int k0 = min(wave_id() * Ls, F.nz), k1 = min(k0 + Ls, F.nz);
   int I, J;
   col_ij(C, cc, mc, I, J);
   const int i0 = 2 * I, j0 = 2 * J;
-  const long long H = F.H;
+  const long long H = F.S;
   const R *__restrict__ ured = u;            // colour 0
   const R *__restrict__ ublk = u + F.cs;     // colour 1
   const R *__restrict__ u0 = ured + col_m(F, i0, j0);
@@ -412,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_bz(Geo F, Geo C,
   auto step = [&](int k, R bb0, R bb1, R p0, R p1, R A, R B, R Cv, R D, R E, R Fv) {
     const R r0 = cell_residual<R>(bb0, tv[k], tx[k], ty[k], tz[k], tz[k + 1], c0, m0, p0, A, B, Cv, D, 1, 1);
     const R r1 = cell_residual<R>(bb1, tv[k], tx[k], ty[k], tz[k], tz[k + 1], c1, m1, p1, D, E, B, Fv, 1, 1);
-    out[(long long)k * C.H] = r0 + r1;
+    out[(long long)k * C.S] = r0 + r1;
     m0 = c0;
     c0 = p0;
     m1 = c1;
@@ -462,8 +469,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Geo F, Geo C, const R
   if (is_done(done)) return;
   const int gid = logical_block() * kBlock + threadIdx.x;
   if (gid >= 2 * C.H) return;
-  const int cc = gid >= C.H ? 1 : 0;
-  const int mc = gid - cc * C.H;
+  const int cc = gid & 1;
+  const int mc = gid >> 1;
   if (mc >= (cc ? C.ncol1 : C.ncol0)) return;
   int I, J;
   col_ij(C, cc, mc, I, J);
@@ -484,7 +491,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Geo F, Geo C, const R
     nS[t] = F.has_y ? col_m(F, i, wrapi(j - 1, F.ny)) : 0;
     nN[t] = F.has_y ? col_m(F, i, wrapi(j + 1, F.ny)) : 0;
   }
-  const long long H = F.H;
+  const long long H = F.S;
   const R *__restrict__ tv = tab + TV * F.P;
   const R *__restrict__ tx = tab + TX * F.P;
   const R *__restrict__ ty = tab + TY * F.P;
@@ -517,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Geo F, Geo C, const R
       um[t] = uc[t];
       uc[t] = up;
     }
-    out[(long long)k * C.H] = acc;
+    out[(long long)k * C.S] = acc;
   }
 }
 
@@ -540,12 +547,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__res
     if (m >= F.ncol0) return;
   } else {
     if (gid >= 2 * F.H) return;
-    c = gid >= F.H ? 1 : 0;
-    m = gid - c * F.H;
+    c = gid & 1;
+    m = gid >> 1;
     if (m >= (c ? F.ncol1 : F.ncol0)) return;
   }
   const int Ls = seg_len(F.nz);
-  const int k0 = min((int)(threadIdx.x >> 6) * Ls, F.nz), k1 = min(k0 + Ls, F.nz);
+  const int k0 = min(wave_id() * Ls, F.nz), k1 = min(k0 + Ls, F.nz);
   int i, j;
   col_ij(F, c, m, i, j);
   const int I = i >> 1, J = j >> 1;
@@ -556,7 +563,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__res
   const R *__restrict__ p12 = uc + (long long)((I + J2) & 1) * C.cs + col_m(C, I, J2);
   const R *__restrict__ p22 = uc + (long long)((I2 + J2) & 1) * C.cs + col_m(C, I2, J2);
   R *__restrict__ own = u + (long long)c * F.cs + m;
-  const long long HC = C.H, HF = F.H;
+  const long long HC = C.S, HF = F.S;
   auto interp = [&](R a, R b2, R c2, R d) -> R {
     if (MODE == 1) return a;
     R e = R(9.0 / 16.0) * a;
@@ -603,10 +610,12 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ t
   __shared__ double sh[4];
   if (is_done(done)) return;
   // 64 column slots (both colours) per block, one k-segment per wavefront
+  // lanes alternate colours: the red and black columns of one stretch of a
+  // row (each other's neighbours) are handled by the same wavefront
   const int slot = logical_block() * kSegCols + (threadIdx.x & 63);
-  const int sg = threadIdx.x >> 6;
-  const int c = slot >= L.H ? 1 : 0;
-  const int m = slot - c * L.H;
+  const int sg = wave_id();
+  const int c = slot & 1;
+  const int m = slot >> 1;
   const bool valid = slot < 2 * L.H && m < (c ? L.ncol1 : L.ncol0);
   const int Ls = seg_len(L.nz);
   const int k0 = min(sg * Ls, L.nz), k1 = min(k0 + Ls, L.nz);
@@ -616,7 +625,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ t
     col_ij(L, c, m, i, j);
     const Nbr nb = neighbours(L, i, j);
     const bool hx = HXY || L.has_x, hy = HXY || L.has_y;
-    const long long H = L.H;
+    const long long H = L.S;
     const R *__restrict__ xo = x + (long long)(1 - c) * L.cs;
     const R *__restrict__ xw = xo + nb.w;
     const R *__restrict__ xe = xo + nb.e;
@@ -707,7 +716,7 @@ __global__ __launch_bounds__(kBlock) void k_nat2split(Geo L, const S *__restrict
   for (int k = 0; k < L.nz; ++k) {
     double v = (double)src[k * plane + (long long)j * L.nx + i];
     if (vol) v = vol[k] * v;
-    dst[(long long)c * L.cs + (long long)k * L.H + m] = (D)v;
+    dst[(long long)c * L.cs + (long long)k * L.S + m] = (D)v;
   }
 }
 
@@ -723,7 +732,7 @@ __global__ __launch_bounds__(kBlock) void k_split2nat(Geo L, const S *__restrict
   col_ij(L, c, m, i, j);
   const long long plane = (long long)L.nx * L.ny;
   for (int k = 0; k < L.nz; ++k)
-    dst[k * plane + (long long)j * L.nx + i] = (D)src[(long long)c * L.cs + (long long)k * L.H + m];
+    dst[k * plane + (long long)j * L.nx + i] = (D)src[(long long)c * L.cs + (long long)k * L.S + m];
 }
 
 // FP64 residual -> FP32 right-hand side of the preconditioner

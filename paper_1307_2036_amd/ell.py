@@ -55,7 +55,7 @@ EXPORTS = ["ell_grid_create", "ell_grid_destroy", "ell_grid_bytes", "ell_grid_le
            "ell_apply_A", "ell_vcycle", "ell_pcg_solve", "ell_level_elems", "ell_to_split",
            "ell_from_split", "ell_level_smooth", "ell_level_resid_restrict",
            "ell_level_prolong_add", "ell_level_apply", "ell_profile_enable", "ell_profile_read",
-           "ell_profile_times", "ell_last_error"]
+           "ell_profile_times", "ell_level_layout", "ell_set_tuning", "ell_last_error"]
 
 _lib = None
 
@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH):
     L.ell_profile_enable.argtypes = [vp, i32, i32]
     L.ell_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
     L.ell_profile_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_float), i32]
+    L.ell_level_layout.argtypes = [vp, i32] + [ctypes.POINTER(ctypes.c_int64)] * 3
+    L.ell_set_tuning.argtypes = [i32, i32]
     L.ell_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         if name not in ("ell_grid_bytes", "ell_level_elems", "ell_last_error"):
@@ -130,6 +132,14 @@ def make_desc(nx, ny, nz, hx, hy, omega2, dz, lambda2, n_levels=0, nu_pre=1, nu_
     d = GridDesc(nx, ny, nz, hx, hy, omega2, dz.ctypes.data_as(_dp), lam.ctypes.data_as(_dp),
                  n_levels, nu_pre, nu_post, nu_coarse, rho, prolong, prec)
     return d, (dz, lam)
+
+
+ELL_TUNE_PLANE_PAD, ELL_TUNE_COLOUR_PAD = 0, 1
+
+
+def set_tuning(key: int, value: int) -> None:
+    """Layout padding for grids created afterwards (process-wide)."""
+    _check(load_library().ell_set_tuning(key, value))
 
 
 def grid_bytes(**kw) -> int:
@@ -216,6 +226,12 @@ class Grid:
     # ---- level entry points ----------------------------------------------------------
     def level_elems(self, level: int) -> int:
         return int(load_library().ell_level_elems(self._h, level))
+
+    def level_layout(self, level: int):
+        """(columns per colour H, plane stride S, colour stride C) of a level."""
+        v = [ctypes.c_int64() for _ in range(3)]
+        _check(load_library().ell_level_layout(self._h, level, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
 
     def level_empty(self, level: int) -> torch.Tensor:
         return torch.zeros(self.level_elems(level), dtype=self.elem_dtype, device="cuda")

@@ -70,13 +70,19 @@ def test_split_layout_roundtrip(ell, orc, shape):
     y = G.from_split(0, xs, torch.zeros(g.shape, dtype=torch.float64, device="cuda"))
     np.testing.assert_array_equal(host(y), x)
     # the layout is the documented one: colour c, level k, column m
-    H = (g.nx * g.ny + 1) // 2
-    xs_h = host(xs).reshape(2, g.nz, H)
+    H, S, C = G.level_layout(0)
+    assert H == (g.nx * g.ny + 1) // 2 and S >= H and C >= g.nz * S
+    flat = host(xs)
+    assert flat.size == 2 * C
+    seen = np.zeros(flat.size, dtype=bool)
     for j in range(g.ny):
         for i in range(g.nx):
             c = (i + j) % 2
             m = j * (g.nx // 2) + i // 2 if g.nx > 1 else j // 2
-            np.testing.assert_array_equal(xs_h[c, :, m], x[:, j, i])
+            idx = c * C + np.arange(g.nz) * S + m
+            np.testing.assert_array_equal(flat[idx], x[:, j, i])
+            seen[idx] = True
+    assert not flat[~seen].any()  # padding stays zero
 
 
 @pytest.mark.parametrize("shape", SHAPES)
