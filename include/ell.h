@@ -195,9 +195,10 @@ int ell_profile_read(ell_grid *g, int family, int *count, double *total_ms);
  * and show up as near-zero times. */
 int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
 
-/* Layout tuning for grids created afterwards (process-wide): padding, in
- * elements, added to the plane stride S and to the colour stride C. */
-enum { ELL_TUNE_PLANE_PAD = 0, ELL_TUNE_COLOUR_PAD = 1 };
+/* Tuning for grids created afterwards (process-wide): padding, in elements,
+ * added to the plane stride S and to the colour stride C; k-segments (1, 2
+ * or 4) of the CG operator kernels. */
+enum { ELL_TUNE_PLANE_PAD = 0, ELL_TUNE_COLOUR_PAD = 1, ELL_TUNE_STENCIL_SEG = 2 };
 int ell_set_tuning(int key, int value);
 
 /* Message of the last error on the calling thread ("" if none). */

@@ -58,6 +58,12 @@ inline int blocks8(long long threads) {
 // blocks of 64 columns x kSeg k-segments covering `cols` columns
 inline int seg_blocks(long long cols) { return blocks8((cols + kSegCols - 1) / kSegCols * kBlock); }
 
+// blocks of the CG operator kernels: (4 / nseg) chunks of 64 slots per block
+inline int stencil_blocks(long long slots, int nseg) {
+  const long long per = (long long)kSegCols * (4 / nseg);
+  return blocks8((slots + per - 1) / per * kBlock);
+}
+
 // Grid of a flat vector kernel over n2 element pairs: a fixed function of n2,
 // so reductions over it are reproducible.
 inline int flat_blocks(long long n2) {
@@ -117,10 +123,12 @@ struct ell_grid {
   std::vector<Level> lev;
   long long n0 = 0;          // split elements of level 0 (2*cs)
   double *us = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
+  double *p2 = nullptr;                 // second search-direction buffer (ping-pong)
   void *b32 = nullptr, *z32 = nullptr;  // FP32 preconditioner: level-0 b and z
   void *ybuf = nullptr;                 // rho != 1: forward-sweep values
   double *vol0 = nullptr;               // level-0 cell volumes (FP64, nz)
   const double *tab64_0 = nullptr;      // level-0 FP64 table of the CG operator
+  int stencil_seg = 1;                  // k-segments of the CG operator kernels
   double *partial = nullptr;
   long long partial_cap = 0;
   PcgState *st = nullptr;
@@ -150,8 +158,22 @@ int dalloc(ell_grid *g, void **p, size_t bytes) {
 // interleave; the two colour arrays are offset from each other likewise.
 int g_plane_pad = 64;
 int g_colour_pad = 256;
+int g_stencil_seg = 1;  // k-segments of the CG operator kernels (1, 2 or 4)
 
-Geo make_geo(int nx, int ny, int nz) {
+// Smoother segments per column: enough lanes to occupy the chip on small
+// levels, four (the register-resident optimum) on large ones; the finest
+// level always uses four.
+int smoother_segments(long long cols_per_colour, int nz, bool finest) {
+  int ns = 4;
+  if (!finest) {
+    if (cols_per_colour < 4096) ns = 16;
+    else if (cols_per_colour < 16384) ns = 8;
+  }
+  while (ns > 4 && seg_len(nz, ns) < 8) ns /= 2;  // keep at least 8 levels per lane
+  return ns;
+}
+
+Geo make_geo(int nx, int ny, int nz, bool finest = false) {
   Geo G;
   G.nx = nx;
   G.ny = ny;
@@ -166,6 +188,7 @@ Geo make_geo(int nx, int ny, int nz) {
   G.P = nz + 1;
   G.S = (int)(((long long)G.H + 63) / 64 * 64 + g_plane_pad);
   G.cs = (long long)nz * G.S + g_colour_pad;
+  G.nseg = smoother_segments(G.H, nz, finest);
   return G;
 }
 
@@ -199,12 +222,12 @@ int validate(const ell_grid_desc *d, int *levels) {
   return ELL_OK;
 }
 
-// Products of the recurrence multipliers over each of the kSeg k-segments of
+// Products of the recurrence multipliers over each of the nseg k-segments of
 // a column: pf[k] = prod_{i=start..k} Tz[i] ip[i] (forward),
 // qb[k] = prod_{i=k..end-1} cf[i] (backward), in the table's precision.
 template <typename T>
-void segment_products(int nz, const T *Tz, const T *ip, const T *cf, T *pf, T *qb) {
-  const int Ls = seg_len(nz);
+void segment_products(int nz, int nseg, const T *Tz, const T *ip, const T *cf, T *pf, T *qb) {
+  const int Ls = seg_len(nz, nseg);
   for (int s0 = 0; s0 < nz; s0 += Ls) {
     const int e = std::min(s0 + Ls, nz);
     T acc = T(1);
@@ -255,7 +278,7 @@ void level_table64(const ell_grid *g, int l, std::vector<double> &t) {
     ip[k] = 1.0 / p;
     cf[k] = Tz[k + 1] / p;
   }
-  segment_products(nz, Tz, ip, cf, &t[TPF * P], &t[TQB * P]);
+  segment_products(nz, g->lev[l].geo.nseg, Tz, ip, cf, &t[TPF * P], &t[TQB * P]);
 }
 
 // FP32 tables: either the FP64 values rounded once, or (BF16 mode) the
@@ -266,7 +289,8 @@ void level_table32(const ell_grid *g, int l, const std::vector<double> &t64, std
   t.assign((size_t)TSLOTS * P, 0.0f);
   for (size_t i = 0; i < t64.size(); ++i) t[i] = (float)t64[i];
   if (g->prec != ELL_FP32_BF16COEF) {
-    segment_products(nz, &t[TZ * P], &t[TIP * P], &t[TCF * P], &t[TPF * P], &t[TQB * P]);
+    segment_products(nz, g->lev[l].geo.nseg, &t[TZ * P], &t[TIP * P], &t[TCF * P], &t[TPF * P],
+                     &t[TQB * P]);
     return;
   }
   for (int s = TV; s <= TZ; ++s)
@@ -281,14 +305,14 @@ void level_table32(const ell_grid *g, int l, const std::vector<double> &t64, std
     ip[k] = 1.0f / p;
     cf[k] = Tz[k + 1] / p;
   }
-  segment_products(nz, Tz, ip, cf, &t[TPF * P], &t[TQB * P]);
+  segment_products(nz, g->lev[l].geo.nseg, Tz, ip, cf, &t[TPF * P], &t[TQB * P]);
 }
 
 size_t grid_bytes(const ell_grid_desc *d, int L) {
   const size_t es = d->precision == ELL_FP64 ? 8 : 4;
   const Geo g0 = make_geo(d->nx, d->ny, d->nz);
   const size_t n0 = 2 * (size_t)g0.cs;
-  size_t bytes = 5 * n0 * 8;                           // u, r, z, p, q (FP64)
+  size_t bytes = 6 * n0 * 8;                           // u, r, z, p (x2), q (FP64)
   if (d->precision != ELL_FP64) bytes += 2 * n0 * 4;   // b32, z32
   if (d->rho != 1.0) bytes += (size_t)g0.cs * es;      // ybuf
   for (int l = 0; l < L; ++l) {
@@ -332,21 +356,49 @@ void smooth_dispatch(int nb, hipStream_t s, const Geo &G, const R *tab, int c, b
   else k_smooth<R, false, false, FINE, HXY><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, yb, rho, done);
 }
 
-template <typename R, bool FINE, int SEG>
-void seg_dispatch2(int nb, hipStream_t s, const Geo &G, const R *tab, int c, bool zero, bool rho1,
+template <typename R, bool FINE, int SEG, int NSEG>
+void seg_dispatch3(int nb, hipStream_t s, const Geo &G, const R *tab, int c, bool zero, bool rho1,
                    const R *bo, const R *uo, R *own, R rho, const int *done) {
-  if (zero && rho1) k_smooth_seg<R, true, true, FINE, SEG><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
-  else if (zero) k_smooth_seg<R, true, false, FINE, SEG><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
-  else if (rho1) k_smooth_seg<R, false, true, FINE, SEG><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
-  else k_smooth_seg<R, false, false, FINE, SEG><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+  constexpr int T = NSEG * 64;
+  if (zero && rho1) k_smooth_seg<R, true, true, FINE, SEG, NSEG><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+  else if (zero) k_smooth_seg<R, true, false, FINE, SEG, NSEG><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+  else if (rho1) k_smooth_seg<R, false, true, FINE, SEG, NSEG><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+  else k_smooth_seg<R, false, false, FINE, SEG, NSEG><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
 }
 
-template <typename R, bool FINE>
-void seg_dispatch(int nb, hipStream_t s, const Geo &G, const R *tab, int c, bool zero, bool rho1,
-                  const R *bo, const R *uo, R *own, R rho, const int *done, int Ls) {
-  if (Ls <= 16) seg_dispatch2<R, FINE, 16>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-  else if (Ls <= 32) seg_dispatch2<R, FINE, 32>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-  else seg_dispatch2<R, FINE, 64>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+// returns false if no instantiation covers (nseg, segment length)
+template <typename R>
+bool seg_dispatch(bool fine, int nb, hipStream_t s, const Geo &G, const R *tab, int c, bool zero, bool rho1,
+                  const R *bo, const R *uo, R *own, R rho, const int *done) {
+  const int Ls = seg_len(G.nz, G.nseg);
+  if (fine) {
+    if (G.nseg != 4) return false;
+    if (Ls <= 16) seg_dispatch3<R, true, 16, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+    else if (Ls <= 32) seg_dispatch3<R, true, 32, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+    else if (Ls <= 64) seg_dispatch3<R, true, 64, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+    else return false;
+    return true;
+  }
+  switch (G.nseg) {
+    case 4:
+      if (Ls <= 16) seg_dispatch3<R, false, 16, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+      else if (Ls <= 32) seg_dispatch3<R, false, 32, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+      else if (Ls <= 64) seg_dispatch3<R, false, 64, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+      else return false;
+      return true;
+    case 8:
+      if (Ls <= 8) seg_dispatch3<R, false, 8, 8>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+      else if (Ls <= 16) seg_dispatch3<R, false, 16, 8>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+      else if (Ls <= 32) seg_dispatch3<R, false, 32, 8>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+      else return false;
+      return true;
+    case 16:
+      if (Ls <= 8) seg_dispatch3<R, false, 8, 16>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+      else if (Ls <= 16) seg_dispatch3<R, false, 16, 16>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+      else return false;
+      return true;
+  }
+  return false;
 }
 
 template <typename R>
@@ -365,12 +417,10 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const R *b, R *u, const 
   R *own = u + (long long)c * G.cs;
   const bool hxy = G.has_x && G.has_y;
   ProfScope ps(g, ELL_K_SMOOTH0, s, l == 0);
-  const int Ls = seg_len(G.nz);
-  if (hxy && Ls <= 64) {
+  if (hxy) {
     const int nbs = blocks8(((long long)ncol + kSegCols - 1) / kSegCols * kBlock);
-    if (l == 0) seg_dispatch<R, true>(nbs, s, G, tab, c, zero, rho1, bo, uo, own, rho, done, Ls);
-    else seg_dispatch<R, false>(nbs, s, G, tab, c, zero, rho1, bo, uo, own, rho, done, Ls);
-    return check_launch("k_smooth_seg");
+    if (seg_dispatch<R>(l == 0, nbs, s, G, tab, c, zero, rho1, bo, uo, own, rho, done))
+      return check_launch("k_smooth_seg");
   }
   if (l == 0) {
     if (hxy) smooth_dispatch<R, true, true>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
@@ -460,11 +510,22 @@ int launch_apply64(ell_grid *g, const double *x, double *y, bool dot, const int 
   // the CG operator is always FP64 (FP32 grids keep a separate FP64 table)
   const double *tab64 = g->tab64_0;
   ProfScope ps(g, ELL_K_APPLY, s, dot);
+  (void)nb;
   const bool hxy = G.has_x && G.has_y;
-  if (dot && hxy) k_apply<double, true, true><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
-  else if (dot) k_apply<double, true, false><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
-  else if (hxy) k_apply<double, false, true><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
-  else k_apply<double, false, false><<<nb, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+  const int ns = g->stencil_seg;
+  const int b = stencil_blocks(2LL * G.H, ns);
+  if (ns == 1) {
+    if (dot) k_apply<double, true, false, 1><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+    else k_apply<double, false, false, 1><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+  } else if (ns == 2) {
+    if (dot) k_apply<double, true, false, 2><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+    else k_apply<double, false, false, 2><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+  } else {
+    if (dot && hxy) k_apply<double, true, true, 4><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+    else if (dot) k_apply<double, true, false, 4><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+    else if (hxy) k_apply<double, false, true, 4><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+    else k_apply<double, false, false, 4><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
+  }
   return check_launch("k_apply");
 }
 
@@ -497,7 +558,7 @@ int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, e
   const Geo &G = g->lev[0].geo;
   const long long n2 = g->n0 / 2;
   const int fb = flat_blocks(n2);
-  const int ab = seg_blocks(2LL * G.H);  // blocks of the CG operator kernel
+  const int ab = stencil_blocks(2LL * G.H, g->stencil_seg);  // blocks of the CG operator kernel
   const int *done = &g->st->done;
   const typename Vec2<Z>::T *zv =
       (const typename Vec2<Z>::T *)(g->prec == ELL_FP64 ? (void *)g->z : g->z32);
@@ -527,22 +588,33 @@ int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, e
   CHK(finalize(g, fb, 2, F_KAPPA, s));
 
   const int poll = o.poll_every > 0 ? o.poll_every : 4;
+  double *pbuf[2] = {g->p, g->p2};
   int enq = 0;
-  bool first = true;
   while (enq < o.maxiter) {
     const int batch = std::min(poll, o.maxiter - enq);
     for (int it = 0; it < batch; ++it) {
-      k_dir<Z><<<fb, kBlock, 0, s>>>((double2 *)g->p, zv, n2, g->st, first ? 1 : 0);
-      CHK(check_launch("k_dir"));
-      first = false;
-      CHK(launch_apply64(g, g->p, g->q, true, done, s));
+      const int K = enq + it + 1;  // 1-based iteration number
+      {
+        ProfScope ps(g, ELL_K_APPLY, s);
+        const int first = K == 1 ? 1 : 0, defer = K > 1 ? 1 : 0;
+        const Z *zz = (const Z *)zv;
+        if (g->stencil_seg == 1)
+          k_apply_dir<Z, 1><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q,
+                                                  g->us, g->st, first, defer, g->partial);
+        else if (g->stencil_seg == 2)
+          k_apply_dir<Z, 2><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q,
+                                                  g->us, g->st, first, defer, g->partial);
+        else
+          k_apply_dir<Z, 4><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q,
+                                                  g->us, g->st, first, defer, g->partial);
+      }
+      CHK(check_launch("k_apply_dir"));
       CHK(finalize(g, ab, 1, F_ALPHA, s));
       {
         ProfScope ps(g, ELL_K_UPDATE, s);
-        k_update<<<fb, kBlock, 0, s>>>((double2 *)g->us, (const double2 *)g->p, (double2 *)g->r,
-                                       (const double2 *)g->q, n2, g->st, g->partial);
+        k_update_r<<<fb, kBlock, 0, s>>>((double2 *)g->r, (const double2 *)g->q, n2, g->st, g->partial);
       }
-      CHK(check_launch("k_update"));
+      CHK(check_launch("k_update_r"));
       CHK(finalize(g, fb, 1, F_CONV, s));
       CHK(precondition<R>(g, done, s));
       k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zv, (const double2 *)g->q, n2, g->st,
@@ -554,6 +626,14 @@ int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, e
     HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (g->st_host->done) break;
+  }
+  // the last step's solution update (deferred above)
+  {
+    const int K = g->st_host->iter;
+    if (K > 0 && g->st_host->status != -4) {
+      k_axpy_alpha<<<fb, kBlock, 0, s>>>((double2 *)g->us, (const double2 *)pbuf[K & 1], n2, g->st);
+      CHK(check_launch("k_axpy_alpha"));
+    }
   }
   // solution back to plane-major, true residual ||V f - A u||
   k_split2nat<double, double><<<cb, kBlock, 0, s>>>(G, g->us, u);
@@ -618,6 +698,7 @@ int ell_grid_create(const ell_grid_desc *desc, ell_grid **out) {
   g->L = L;
   g->prec = desc->precision;
   g->esz = g->prec == ELL_FP64 ? 8 : 4;
+  g->stencil_seg = g_stencil_seg;
   g->lev.resize(L);
   auto bail = [&](int rc) {
     ell_grid_destroy(g);
@@ -628,7 +709,7 @@ int ell_grid_create(const ell_grid_desc *desc, ell_grid **out) {
   std::vector<float> t32;
   for (int l = 0; l < L; ++l) {
     Level &Lv = g->lev[l];
-    Lv.geo = make_geo(desc->nx >> l, desc->ny >> l, desc->nz);
+    Lv.geo = make_geo(desc->nx >> l, desc->ny >> l, desc->nz, l == 0);
     Lv.hx = desc->hx * (double)(1 << l);
     Lv.hy = desc->hy * (double)(1 << l);
     level_table64(g, l, t64);
@@ -662,6 +743,8 @@ int ell_grid_create(const ell_grid_desc *desc, ell_grid **out) {
   g->p = (double *)tmp;
   if ((rc = dalloc(g, &tmp, vb)) != ELL_OK) return bail(rc);
   g->q = (double *)tmp;
+  if ((rc = dalloc(g, &tmp, vb)) != ELL_OK) return bail(rc);
+  g->p2 = (double *)tmp;
   if (g->prec != ELL_FP64) {
     if ((rc = dalloc(g, &g->b32, (size_t)g->n0 * 4)) != ELL_OK) return bail(rc);
     if ((rc = dalloc(g, &g->z32, (size_t)g->n0 * 4)) != ELL_OK) return bail(rc);
@@ -826,11 +909,11 @@ int ell_level_apply(ell_grid *g, int level, const void *x, void *y, hipStream_t 
   const Geo &G = g->lev[level].geo;
   const int nb = seg_blocks(2LL * G.H);
   if (g->prec == ELL_FP64)
-    k_apply<double, false, false><<<nb, kBlock, 0, s>>>(G, (const double *)g->lev[level].tab,
-                                                        (const double *)x, (double *)y, nullptr, nullptr);
+    k_apply<double, false, false, 4><<<nb, kBlock, 0, s>>>(G, (const double *)g->lev[level].tab,
+                                                           (const double *)x, (double *)y, nullptr, nullptr);
   else
-    k_apply<float, false, false><<<nb, kBlock, 0, s>>>(G, (const float *)g->lev[level].tab,
-                                                       (const float *)x, (float *)y, nullptr, nullptr);
+    k_apply<float, false, false, 4><<<nb, kBlock, 0, s>>>(G, (const float *)g->lev[level].tab,
+                                                          (const float *)x, (float *)y, nullptr, nullptr);
   return check_launch("k_apply");
 }
 
@@ -889,6 +972,10 @@ int ell_set_tuning(int key, int value) {
   switch (key) {
     case ELL_TUNE_PLANE_PAD: g_plane_pad = value; return ELL_OK;
     case ELL_TUNE_COLOUR_PAD: g_colour_pad = value; return ELL_OK;
+    case ELL_TUNE_STENCIL_SEG:
+      if (value != 1 && value != 2 && value != 4) return fail(ELL_ERR_INVALID, "segments must be 1, 2 or 4");
+      g_stencil_seg = value;
+      return ELL_OK;
     default: return fail(ELL_ERR_INVALID, "unknown tuning key %d", key);
   }
 }

@@ -23,12 +23,14 @@ constexpr int kBlock = 256;  // 4 wavefronts of 64 lanes
 // each k-segment (see k_smooth_seg).
 enum : int { TV = 0, TX = 1, TY = 2, TZ = 3, TIP = 4, TCF = 5, TPF = 6, TQB = 7, TSLOTS = 8 };
 
-// Segments a column is split into along k: one wavefront per segment, four
-// per 256-thread block, so a block covers 64 columns.
+// Segments a column is split into along k: one wavefront per segment, so a
+// block of kSeg wavefronts covers 64 columns.  The line smoother chooses its
+// own segment count per level (more segments on small, latency-bound levels).
 constexpr int kSeg = 4;
 constexpr int kSegCols = 64;
 
-__host__ __device__ inline int seg_len(int nz) { return (nz + kSeg - 1) / kSeg; }
+__host__ __device__ inline int seg_len(int nz, int nseg = kSeg) { return (nz + nseg - 1) / nseg; }
+
 
 // Geometry of one level in the colour-split layout.
 struct Geo {
@@ -42,6 +44,7 @@ struct Geo {
   int P;          // table stride = nz + 1
   int S;          // plane stride of a colour array (>= H, padded so that
                   // successive k-planes do not start on the same HBM channel)
+  int nseg;       // k-segments per column used by the line smoother
   long long cs;   // colour stride (>= nz * S)
 };
 
@@ -55,8 +58,12 @@ struct PcgState {
 // contiguous range of logical blocks, so neighbouring rows of columns (which
 // share halo data) meet in the same L2.
 __device__ __forceinline__ int logical_block() {
+#ifdef ELL_NO_XCD_REMAP
+  return blockIdx.x;
+#else
   const int g8 = gridDim.x >> 3;
   return (blockIdx.x & 7) * g8 + (blockIdx.x >> 3);
+#endif
 }
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
@@ -231,13 +238,13 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ 
 // from segment to segment through LDS.  Pf and Qb are per-level tables.  The
 // forward values stay in registers (SEG >= segment length).
 // -------------------------------------------------------------------------
-template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG>
-__global__ __launch_bounds__(kBlock) void k_smooth_seg(Geo L, const R *__restrict__ tab, int c,
-                                                       const R *__restrict__ bo,
-                                                       const R *__restrict__ uo,
-                                                       R *__restrict__ own, R rho,
-                                                       const int *__restrict__ done) {
-  __shared__ R xch[kSeg][kSegCols];
+template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_seg(Geo L, const R *__restrict__ tab, int c,
+                                                          const R *__restrict__ bo,
+                                                          const R *__restrict__ uo,
+                                                          R *__restrict__ own, R rho,
+                                                          const int *__restrict__ done) {
+  __shared__ R xch[NSEG][kSegCols];
   if (is_done(done)) return;
   const int lane = threadIdx.x & 63;
   const int sg = wave_id();
@@ -245,7 +252,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_seg(Geo L, const R *__restric
   const int m = logical_block() * kSegCols + lane;
   const bool valid = m < ncol;
   const int mm = valid ? m : ncol - 1;  // in-bounds column for loads of idle lanes
-  const int nz = L.nz, Ls = seg_len(nz);
+  const int nz = L.nz, Ls = seg_len(nz, NSEG);
   const int k0 = min(sg * Ls, nz), k1 = min(k0 + Ls, nz), len = k1 - k0;
   int i, j;
   col_ij(L, c, mm, i, j);
@@ -317,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_smooth_seg(Geo L, const R *__restric
   xch[sg][lane] = nxt;  // local w at the segment's first level
   __syncthreads();
   R win = R(0);
-  for (int q = kSeg - 1; q > sg; --q) {
+  for (int q = NSEG - 1; q > sg; --q) {
     const int s0 = min(q * Ls, nz);
     const int e = min(s0 + Ls, nz);
     const R qs = e > s0 ? qb[s0] : R(1);
@@ -602,7 +609,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__res
 // y = A x (eq. ModelEquation integrated over the cell, difference form), one
 // lane per column of either colour; DOT: also partial sums of <x, y>.
 // -------------------------------------------------------------------------
-template <typename R, bool DOT, bool HXY>
+template <typename R, bool DOT, bool HXY, int NSEG>
 __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ tab,
                                                   const R *__restrict__ x, R *__restrict__ y,
                                                   double *__restrict__ partial,
@@ -612,12 +619,14 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ t
   // 64 column slots (both colours) per block, one k-segment per wavefront
   // lanes alternate colours: the red and black columns of one stretch of a
   // row (each other's neighbours) are handled by the same wavefront
-  const int slot = logical_block() * kSegCols + (threadIdx.x & 63);
-  const int sg = wave_id();
+  constexpr int CH = 4 / NSEG;  // 64-slot chunks per block
+  const int w = wave_id();
+  const int sg = w / CH;
+  const int slot = (logical_block() * CH + (w % CH)) * kSegCols + (threadIdx.x & 63);
   const int c = slot & 1;
   const int m = slot >> 1;
   const bool valid = slot < 2 * L.H && m < (c ? L.ncol1 : L.ncol0);
-  const int Ls = seg_len(L.nz);
+  const int Ls = seg_len(L.nz, NSEG);
   const int k0 = min(sg * Ls, L.nz), k1 = min(k0 + Ls, L.nz);
   double dot = 0.0;
   if (valid && k1 > k0) {
@@ -690,6 +699,154 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ t
   if (DOT) {
     const double s = block_sum(dot, sh);
     if (threadIdx.x == 0) partial[logical_block()] = s;
+  }
+}
+
+// -------------------------------------------------------------------------
+// One CG step's vector work around the operator (Appendix B, Alg. PCG):
+//   p_new = z + beta p_old          (search direction; p_new = z when first)
+//   q     = A p_new, partial sums of <p_new, q>
+//   u    += alpha_prev p_old        (the previous step's solution update,
+//                                    deferred to ride on the p_old read)
+// p_old and p_new are different buffers, so neighbour values of p_new are
+// formed from z and p_old exactly as their owning lanes form them.
+// -------------------------------------------------------------------------
+template <typename Z, int NSEG>
+__global__ __launch_bounds__(kBlock) void k_apply_dir(Geo L, const double *__restrict__ tab,
+                                                      const Z *__restrict__ z,
+                                                      const double *__restrict__ pold,
+                                                      double *__restrict__ pnew,
+                                                      double *__restrict__ q,
+                                                      double *__restrict__ u,
+                                                      const PcgState *__restrict__ st, int first,
+                                                      int defer_u, double *__restrict__ partial) {
+  constexpr int U = 4;
+  constexpr int CH = 4 / NSEG;
+  __shared__ double sh[4];
+  if (st->done) return;
+  const double beta = first ? 0.0 : st->beta;
+  const double alpha = st->alpha;
+  const int w = wave_id();
+  const int sg = w / CH;
+  const int slot = (logical_block() * CH + (w % CH)) * kSegCols + (threadIdx.x & 63);
+  const int c = slot & 1;
+  const int m = slot >> 1;
+  const bool valid = slot < 2 * L.H && m < (c ? L.ncol1 : L.ncol0);
+  const int Ls = seg_len(L.nz, NSEG);
+  const int k0 = min(sg * Ls, L.nz), k1 = min(k0 + Ls, L.nz);
+  double dot = 0.0;
+  if (valid && k1 > k0) {
+    int i, j;
+    col_ij(L, c, m, i, j);
+    const Nbr nb = neighbours(L, i, j);
+    const bool hx = L.has_x, hy = L.has_y;
+    const long long H = L.S;
+    const long long oo = (long long)(1 - c) * L.cs, os = (long long)c * L.cs + m;
+    const double *__restrict__ tv = tab + TV * L.P;
+    const double *__restrict__ tx = tab + TX * L.P;
+    const double *__restrict__ ty = tab + TY * L.P;
+    const double *__restrict__ tz = tab + TZ * L.P;
+    const int nz = L.nz;
+    // direction value at (column offset, level): z + beta p_old
+    auto dir = [&](long long idx) -> double {
+      return first ? (double)z[idx] : (double)z[idx] + beta * pold[idx];
+    };
+    auto cell = [&](int k, double pc, double pm, double pp, double pw, double pe, double ps,
+                    double pn) -> double {
+      double acc = tv[k] * pc;
+      if (hx) {
+        acc = acc + tx[k] * (pc - pw);
+        acc = acc + tx[k] * (pc - pe);
+      }
+      if (hy) {
+        acc = acc + ty[k] * (pc - ps);
+        acc = acc + ty[k] * (pc - pn);
+      }
+      acc = acc + tz[k] * (pc - pm);
+      acc = acc + tz[k + 1] * (pc - pp);
+      return acc;
+    };
+    double pc = dir(os + (long long)k0 * H);
+    double pm = k0 > 0 ? dir(os + (long long)(k0 - 1) * H) : pc;
+    int k = k0;
+    for (; k + U <= k1; k += U) {
+      double pp[U], pw[U], pe[U], ps[U], pn[U], uu[U], po[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        const long long o = (long long)(k + t) * H;
+        pp[t] = dir(os + (long long)min(k + t + 1, nz - 1) * H);
+        pw[t] = hx ? dir(oo + nb.w + o) : 0.0;
+        pe[t] = hx ? dir(oo + nb.e + o) : 0.0;
+        ps[t] = hy ? dir(oo + nb.s + o) : 0.0;
+        pn[t] = hy ? dir(oo + nb.n + o) : 0.0;
+        uu[t] = defer_u ? u[os + o] : 0.0;
+        po[t] = defer_u ? pold[os + o] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        const long long o = (long long)(k + t) * H;
+        const double acc = cell(k + t, pc, pm, pp[t], pw[t], pe[t], ps[t], pn[t]);
+        q[os + o] = acc;
+        pnew[os + o] = pc;
+        if (defer_u) u[os + o] = uu[t] + alpha * po[t];
+        dot += pc * acc;
+        pm = pc;
+        pc = pp[t];
+      }
+    }
+    for (; k < k1; ++k) {
+      const long long o = (long long)k * H;
+      const double pp = dir(os + (long long)min(k + 1, nz - 1) * H);
+      const double acc = cell(k, pc, pm, pp, hx ? dir(oo + nb.w + o) : 0.0, hx ? dir(oo + nb.e + o) : 0.0,
+                              hy ? dir(oo + nb.s + o) : 0.0, hy ? dir(oo + nb.n + o) : 0.0);
+      q[os + o] = acc;
+      pnew[os + o] = pc;
+      if (defer_u) u[os + o] = u[os + o] + alpha * pold[os + o];
+      dot += pc * acc;
+      pm = pc;
+      pc = pp;
+    }
+  }
+  const double s = block_sum(dot, sh);
+  if (threadIdx.x == 0) partial[logical_block()] = s;
+}
+
+// r <- r - alpha q, partial sums of ||r||^2
+__global__ __launch_bounds__(kBlock) void k_update_r(double2 *__restrict__ r,
+                                                     const double2 *__restrict__ q, long long n2,
+                                                     const PcgState *__restrict__ st,
+                                                     double *__restrict__ partial) {
+  __shared__ double sh[4];
+  if (st->done) return;
+  const double alpha = st->alpha;
+  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kBlock;
+  double rr = 0.0;
+  for (long long e = t; e < n2; e += stride) {
+    const double2 qv = q[e];
+    double2 rv = r[e];
+    rv.x = rv.x - alpha * qv.x;
+    rv.y = rv.y - alpha * qv.y;
+    r[e] = rv;
+    rr += rv.x * rv.x + rv.y * rv.y;
+  }
+  const double s = block_sum(rr, sh);
+  if (threadIdx.x == 0) partial[logical_block()] = s;
+}
+
+// u <- u + alpha p (the last step's deferred solution update)
+__global__ __launch_bounds__(kBlock) void k_axpy_alpha(double2 *__restrict__ u,
+                                                       const double2 *__restrict__ p, long long n2,
+                                                       const PcgState *__restrict__ st) {
+  const double alpha = st->alpha;
+  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = t; e < n2; e += stride) {
+    const double2 pv = p[e];
+    double2 uv = u[e];
+    uv.x = uv.x + alpha * pv.x;
+    uv.y = uv.y + alpha * pv.y;
+    u[e] = uv;
   }
 }
 

@@ -19,7 +19,7 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libell.so")
+LIB_PATH = os.environ.get("ELL_LIBRARY", os.path.join(HERE, "libell.so"))
 
 ELL_OK, ELL_NOT_CONVERGED, ELL_PENDING = 0, 1, 2
 ELL_ERR_INVALID, ELL_ERR_OOM, ELL_ERR_HIP, ELL_ERR_NUMERIC, ELL_ERR_BUDGET = -1, -2, -3, -4, -5
@@ -134,7 +134,7 @@ def make_desc(nx, ny, nz, hx, hy, omega2, dz, lambda2, n_levels=0, nu_pre=1, nu_
     return d, (dz, lam)
 
 
-ELL_TUNE_PLANE_PAD, ELL_TUNE_COLOUR_PAD = 0, 1
+ELL_TUNE_PLANE_PAD, ELL_TUNE_COLOUR_PAD, ELL_TUNE_STENCIL_SEG = 0, 1, 2
 
 
 def set_tuning(key: int, value: int) -> None:
