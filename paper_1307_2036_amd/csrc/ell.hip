@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -356,94 +357,116 @@ void smooth_dispatch(int nb, hipStream_t s, const Geo &G, const R *tab, int c, b
   else k_smooth<R, false, false, FINE, HXY><<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, yb, rho, done);
 }
 
-template <typename R, bool FINE, int SEG, int NSEG>
+template <typename R, typename TB, bool FINE, int SEG, int NSEG>
 void seg_dispatch3(int nb, hipStream_t s, const Geo &G, const R *tab, int c, bool zero, bool rho1,
-                   const R *bo, const R *uo, R *own, R rho, const int *done) {
+                   const TB *bo, const R *uo, R *own, R rho, const int *done) {
   constexpr int T = NSEG * 64;
-  if (zero && rho1) k_smooth_seg<R, true, true, FINE, SEG, NSEG><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
-  else if (zero) k_smooth_seg<R, true, false, FINE, SEG, NSEG><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
-  else if (rho1) k_smooth_seg<R, false, true, FINE, SEG, NSEG><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
-  else k_smooth_seg<R, false, false, FINE, SEG, NSEG><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+  if (zero && rho1)
+    k_smooth_seg<R, true, true, FINE, SEG, NSEG, TB><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+  else if (zero)
+    k_smooth_seg<R, true, false, FINE, SEG, NSEG, TB><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+  else if (rho1)
+    k_smooth_seg<R, false, true, FINE, SEG, NSEG, TB><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
+  else
+    k_smooth_seg<R, false, false, FINE, SEG, NSEG, TB><<<nb, T, 0, s>>>(G, tab, c, bo, uo, own, rho, done);
 }
 
 // returns false if no instantiation covers (nseg, segment length)
-template <typename R>
+template <typename R, typename TB>
 bool seg_dispatch(bool fine, int nb, hipStream_t s, const Geo &G, const R *tab, int c, bool zero, bool rho1,
-                  const R *bo, const R *uo, R *own, R rho, const int *done) {
+                  const TB *bo, const R *uo, R *own, R rho, const int *done) {
   const int Ls = seg_len(G.nz, G.nseg);
   if (fine) {
     if (G.nseg != 4) return false;
-    if (Ls <= 16) seg_dispatch3<R, true, 16, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-    else if (Ls <= 32) seg_dispatch3<R, true, 32, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-    else if (Ls <= 64) seg_dispatch3<R, true, 64, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+    if (Ls <= 16) seg_dispatch3<R, TB, true, 16, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+    else if (Ls <= 32) seg_dispatch3<R, TB, true, 32, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+    else if (Ls <= 64) seg_dispatch3<R, TB, true, 64, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
     else return false;
     return true;
   }
-  switch (G.nseg) {
-    case 4:
-      if (Ls <= 16) seg_dispatch3<R, false, 16, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-      else if (Ls <= 32) seg_dispatch3<R, false, 32, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-      else if (Ls <= 64) seg_dispatch3<R, false, 64, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-      else return false;
-      return true;
-    case 8:
-      if (Ls <= 8) seg_dispatch3<R, false, 8, 8>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-      else if (Ls <= 16) seg_dispatch3<R, false, 16, 8>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-      else if (Ls <= 32) seg_dispatch3<R, false, 32, 8>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-      else return false;
-      return true;
-    case 16:
-      if (Ls <= 8) seg_dispatch3<R, false, 8, 16>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-      else if (Ls <= 16) seg_dispatch3<R, false, 16, 16>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
-      else return false;
-      return true;
+  if constexpr (!std::is_same<R, TB>::value) {
+    return false;  // mixed element types only on the finest level
+  } else {
+    switch (G.nseg) {
+      case 4:
+        if (Ls <= 16) seg_dispatch3<R, TB, false, 16, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+        else if (Ls <= 32) seg_dispatch3<R, TB, false, 32, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+        else if (Ls <= 64) seg_dispatch3<R, TB, false, 64, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+        else return false;
+        return true;
+      case 8:
+        if (Ls <= 8) seg_dispatch3<R, TB, false, 8, 8>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+        else if (Ls <= 16) seg_dispatch3<R, TB, false, 16, 8>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+        else if (Ls <= 32) seg_dispatch3<R, TB, false, 32, 8>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+        else return false;
+        return true;
+      case 16:
+        if (Ls <= 8) seg_dispatch3<R, TB, false, 8, 16>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+        else if (Ls <= 16) seg_dispatch3<R, TB, false, 16, 16>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+        else return false;
+        return true;
+    }
+    return false;
   }
-  return false;
 }
 
-template <typename R>
-int launch_smooth(ell_grid *g, int l, int c, bool zero, const R *b, R *u, const int *done, hipStream_t s) {
+// One colour of line relaxation on level l.  tab: coefficient table in the
+// arithmetic type R (nullptr: the level's own table).  TB != R is supported
+// on the finest level only.
+template <typename R, typename TB = R>
+int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const int *done, hipStream_t s,
+                  const R *tab = nullptr) {
   const Level &Lv = g->lev[l];
   const Geo &G = Lv.geo;
   const int ncol = c ? G.ncol1 : G.ncol0;
   if (ncol == 0) return ELL_OK;
   const int nb = blocks8(ncol);
-  const R *tab = (const R *)Lv.tab;
+  if (!tab) tab = (const R *)Lv.tab;
   const bool rho1 = g->d.rho == 1.0;
   R *yb = (R *)g->ybuf;
   const R rho = (R)g->d.rho;
-  const R *bo = b + (long long)c * G.cs;
+  const TB *bo = b + (long long)c * G.cs;
   const R *uo = u + (long long)(1 - c) * G.cs;
   R *own = u + (long long)c * G.cs;
   const bool hxy = G.has_x && G.has_y;
   ProfScope ps(g, ELL_K_SMOOTH0, s, l == 0);
   if (hxy) {
     const int nbs = blocks8(((long long)ncol + kSegCols - 1) / kSegCols * kBlock);
-    if (seg_dispatch<R>(l == 0, nbs, s, G, tab, c, zero, rho1, bo, uo, own, rho, done))
+    if (seg_dispatch<R, TB>(l == 0, nbs, s, G, tab, c, zero, rho1, bo, uo, own, rho, done))
       return check_launch("k_smooth_seg");
   }
-  if (l == 0) {
-    if (hxy) smooth_dispatch<R, true, true>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
-    else smooth_dispatch<R, true, false>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
+  if constexpr (!std::is_same<R, TB>::value) {
+    return fail(ELL_ERR_INVALID, "no line-relaxation kernel for this level shape");
   } else {
-    if (hxy) smooth_dispatch<R, false, true>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
-    else smooth_dispatch<R, false, false>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
+    if (l == 0) {
+      if (hxy) smooth_dispatch<R, true, true>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
+      else smooth_dispatch<R, true, false>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
+    } else {
+      if (hxy) smooth_dispatch<R, false, true>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
+      else smooth_dispatch<R, false, false>(nb, s, G, tab, c, zero, rho1, bo, uo, own, yb, rho, done);
+    }
+    return check_launch("k_smooth");
   }
-  return check_launch("k_smooth");
 }
 
-template <typename R>
-int launch_restrict(ell_grid *g, int l, const R *b, const R *u, R *bc, bool bz, const int *done,
+template <typename R, typename TB = R>
+int launch_restrict(ell_grid *g, int l, const TB *b, const R *u, R *bc, bool bz, const int *done,
                     hipStream_t s) {
   const Geo &F = g->lev[l].geo, &C = g->lev[l + 1].geo;
   const int nb = blocks8(2LL * C.H);
   const R *tab = (const R *)g->lev[l].tab;
   ProfScope ps(g, ELL_K_RESTRICT0, s, l == 0);
-  if (bz && F.has_x && F.has_y)
-    k_resid_restrict_bz<R><<<seg_blocks(2LL * C.H), kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
-  else if (bz) k_resid_restrict<R, true><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
-  else k_resid_restrict<R, false><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
-  return check_launch("k_resid_restrict");
+  if (bz && F.has_x && F.has_y) {
+    k_resid_restrict_bz<R, TB><<<seg_blocks(2LL * C.H), kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
+    return check_launch("k_resid_restrict_bz");
+  }
+  if constexpr (!std::is_same<R, TB>::value) {
+    return fail(ELL_ERR_INVALID, "mixed-type restriction needs the colour-1 shortcut");
+  } else {
+    if (bz) k_resid_restrict<R, true><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
+    else k_resid_restrict<R, false><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
+    return check_launch("k_resid_restrict");
+  }
 }
 
 template <typename R>
@@ -473,12 +496,12 @@ int launch_fill(R *p, long long n, hipStream_t s) {
 // residual is zero (only red children are restricted) and a black sweep
 // ignores the old black values (the correction is added to red columns only).
 template <typename R>
-int vcycle_impl(ell_grid *g, const R *b0, R *u0, const int *done, hipStream_t s) {
+int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, hipStream_t s) {
   const int L = g->L;
   const bool rho1 = g->d.rho == 1.0;
-  auto B = [&](int l) -> const R * { return l == 0 ? b0 : (const R *)g->lev[l].b; };
-  auto U = [&](int l) -> R * { return l == 0 ? u0 : (R *)g->lev[l].u; };
-  for (int l = 0; l < L - 1; ++l) {
+  auto B = [&](int l) -> const R * { return l == top ? btop : (const R *)g->lev[l].b; };
+  auto U = [&](int l) -> R * { return l == top ? utop : (R *)g->lev[l].u; };
+  for (int l = top; l < L - 1; ++l) {
     if (g->d.nu_pre == 0) CHK(launch_fill<R>(U(l), 2 * g->lev[l].geo.cs, s));
     for (int it = 0; it < g->d.nu_pre; ++it) {
       CHK(launch_smooth<R>(g, l, 0, it == 0, B(l), U(l), done, s));
@@ -494,12 +517,62 @@ int vcycle_impl(ell_grid *g, const R *b0, R *u0, const int *done, hipStream_t s)
       CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
     }
   }
-  for (int l = L - 2; l >= 0; --l) {
+  for (int l = L - 2; l >= top; --l) {
     CHK(launch_prolong<R>(g, l, (const R *)g->lev[l + 1].u, U(l), rho1 && g->d.nu_post > 0, done, s));
     for (int it = 0; it < g->d.nu_post; ++it) {
       CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
       CHK(launch_smooth<R>(g, l, 0, false, B(l), U(l), done, s));
     }
+  }
+  return ELL_OK;
+}
+
+// One V-cycle from u = 0 (Alg. "Multigrid V-cycle"), levels numbered from the
+// finest (0).  Pre-smoothing sweeps red then black, post-smoothing black then
+// red.  With rho = 1 two exact shortcuts apply: after a black sweep the black
+// residual is zero (only red children are restricted) and a black sweep
+// ignores the old black values (the correction is added to red columns only).
+template <typename R>
+int vcycle_impl(ell_grid *g, const R *b0, R *u0, const int *done, hipStream_t s) {
+  return vcycle_from<R>(g, 0, b0, u0, done, s);
+}
+
+// The mixed-precision V-cycle: FP32 everywhere except the finest level's
+// post-smoothing, which runs in FP64 and writes the FP64 output z.  On the
+// graded grids the bottom cells are coupled vertically ~1e10 times more
+// strongly than the solution's magnitude resolves in FP32, so an FP32 output
+// would carry rounding noise in exactly the stiff vertical modes (inflating
+// <p, A p> and the iteration count); the final FP64 column solves remove it,
+// while the coarse correction enters only through the weak horizontal
+// couplings.  The finest level's FP32 pre-smoothing and restriction read the
+// FP64 residual directly.
+bool hybrid_ok(const ell_grid *g) {
+  const Geo &G = g->lev[0].geo;
+  return g->L >= 2 && g->d.rho == 1.0 && g->d.nu_pre >= 1 && g->d.nu_post >= 1 && G.has_x && G.has_y &&
+         G.nseg == 4 && seg_len(G.nz, 4) <= 64;
+}
+
+int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipStream_t s) {
+  float *u32 = (float *)g->z32;
+  for (int it = 0; it < g->d.nu_pre; ++it) {
+    CHK((launch_smooth<float, double>(g, 0, 0, it == 0, r, u32, done, s)));
+    CHK((launch_smooth<float, double>(g, 0, 1, false, r, u32, done, s)));
+  }
+  CHK((launch_restrict<float, double>(g, 0, r, u32, (float *)g->lev[1].b, true, done, s)));
+  CHK(vcycle_from<float>(g, 1, (const float *)g->lev[1].b, (float *)g->lev[1].u, done, s));
+  {
+    const Geo &F = g->lev[0].geo, &C = g->lev[1].geo;
+    const int nb = seg_blocks(F.ncol0);
+    ProfScope ps(g, ELL_K_PROLONG0, s);
+    if (g->d.prolong == 1)
+      k_prolong_out<float, double, 1><<<nb, kBlock, 0, s>>>(F, C, (const float *)g->lev[1].u, u32, z, done);
+    else
+      k_prolong_out<float, double, 0><<<nb, kBlock, 0, s>>>(F, C, (const float *)g->lev[1].u, u32, z, done);
+    CHK(check_launch("k_prolong_out"));
+  }
+  for (int it = 0; it < g->d.nu_post; ++it) {
+    CHK(launch_smooth<double>(g, 0, 1, false, r, z, done, s, g->tab64_0));
+    CHK(launch_smooth<double>(g, 0, 0, false, r, z, done, s, g->tab64_0));
   }
   return ELL_OK;
 }
@@ -545,23 +618,25 @@ int precondition<double>(ell_grid *g, const int *done, hipStream_t s) {
 
 template <>
 int precondition<float>(ell_grid *g, const int *done, hipStream_t s) {
+  if (hybrid_ok(g)) return vcycle_hybrid(g, g->r, g->z, done, s);
   const long long n2 = g->n0 / 2;
   k_cast_f64_f32<<<flat_blocks(n2), kBlock, 0, s>>>((const double2 *)g->r, (float2 *)g->b32, n2, done);
   CHK(check_launch("k_cast_f64_f32"));
   return vcycle_impl<float>(g, (const float *)g->b32, (float *)g->z32, done, s);
 }
 
-template <typename R>
+// R: arithmetic of the V-cycle; Z: element type of its output z (FP64 for
+// the FP64 and the hybrid mixed-precision V-cycles, FP32 otherwise).
+template <typename R, typename Z>
 int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, ell_solve_stats *out,
              hipStream_t s) {
-  using Z = R;
   const Geo &G = g->lev[0].geo;
   const long long n2 = g->n0 / 2;
   const int fb = flat_blocks(n2);
   const int ab = stencil_blocks(2LL * G.H, g->stencil_seg);  // blocks of the CG operator kernel
   const int *done = &g->st->done;
   const typename Vec2<Z>::T *zv =
-      (const typename Vec2<Z>::T *)(g->prec == ELL_FP64 ? (void *)g->z : g->z32);
+      (const typename Vec2<Z>::T *)(std::is_same<Z, double>::value ? (void *)g->z : g->z32);
 
   // r = V f - A u0 (split layout), ||b||, ||r0||
   const int cb = blocks8(2LL * G.H);
@@ -820,6 +895,11 @@ int ell_vcycle(ell_grid *g, const double *r, double *z, hipStream_t s) {
     CHK(check_launch("k_nat2split"));
     CHK(vcycle_impl<double>(g, g->r, g->z, nullptr, s));
     k_split2nat<double, double><<<cb, kBlock, 0, s>>>(G, g->z, z);
+  } else if (hybrid_ok(g)) {
+    k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, r, g->r, nullptr);
+    CHK(check_launch("k_nat2split"));
+    CHK(vcycle_hybrid(g, g->r, g->z, nullptr, s));
+    k_split2nat<double, double><<<cb, kBlock, 0, s>>>(G, g->z, z);
   } else {
     k_nat2split<double, float><<<cb, kBlock, 0, s>>>(G, r, (float *)g->b32, nullptr);
     CHK(check_launch("k_nat2split"));
@@ -845,8 +925,9 @@ int ell_pcg_solve(ell_grid *g, const double *f, double *u, const ell_solve_opts 
   }
   if (o.maxiter <= 0 || !(o.rtol >= 0) || !(o.atol >= 0))
     return fail(ELL_ERR_INVALID, "maxiter must be > 0 and tolerances >= 0");
-  if (g->prec == ELL_FP64) return pcg_impl<double>(g, f, u, o, stats, s);
-  return pcg_impl<float>(g, f, u, o, stats, s);
+  if (g->prec == ELL_FP64) return pcg_impl<double, double>(g, f, u, o, stats, s);
+  if (hybrid_ok(g)) return pcg_impl<float, double>(g, f, u, o, stats, s);
+  return pcg_impl<float, float>(g, f, u, o, stats, s);
 }
 
 size_t ell_level_elems(const ell_grid *g, int level) {

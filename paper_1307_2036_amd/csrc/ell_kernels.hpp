@@ -238,9 +238,11 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ 
 // from segment to segment through LDS.  Pf and Qb are per-level tables.  The
 // forward values stay in registers (SEG >= segment length).
 // -------------------------------------------------------------------------
-template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG>
+// TB: element type of b (the FP32 preconditioner reads the FP64 CG residual
+// directly on the finest level).
+template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG, typename TB = R>
 __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg(Geo L, const R *__restrict__ tab, int c,
-                                                          const R *__restrict__ bo,
+                                                          const TB *__restrict__ bo,
                                                           const R *__restrict__ uo,
                                                           R *__restrict__ own, R rho,
                                                           const int *__restrict__ done) {
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg(Geo L, const R *__rest
   col_ij(L, c, mm, i, j);
   const Nbr nb = ZERO ? Nbr{0, 0, 0, 0} : neighbours(L, i, j);
   const long long H = L.S;
-  const R *__restrict__ bb = bo + mm;
+  const TB *__restrict__ bb = bo + mm;
   const R *__restrict__ uw = uo + nb.w;
   const R *__restrict__ ue = uo + nb.e;
   const R *__restrict__ us = uo + nb.s;
@@ -282,7 +284,7 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg(Geo L, const R *__rest
       for (int t = 0; t < 8; ++t) {
         const int k = min(k0 + c0 + t, k1 - 1);
         const long long o = (long long)k * H;
-        R v = bb[o];
+        R v = (R)bb[o];
         if (!ZERO) {
           v = v + tx[k] * (uw[o] + ue[o]);
           v = v + ty[k] * (us[o] + un[o]);
@@ -381,10 +383,10 @@ __device__ __forceinline__ R cell_residual(R bk, R vk, R txk, R tyk, R tzlo, R t
 // child (2I,2J): W=A E=B S=C N=D;  child (2I+1,2J+1): W=D E=E S=B N=F.
 // Requires both horizontal directions to have faces.
 // -------------------------------------------------------------------------
-template <typename R>
+template <typename R, typename TB = R>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict_bz(Geo F, Geo C,
                                                               const R *__restrict__ tab,
-                                                              const R *__restrict__ b,
+                                                              const TB *__restrict__ b,
                                                               const R *__restrict__ u,
                                                               R *__restrict__ bc,
                                                               const int *__restrict__ done) {
@@ -405,8 +407,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_bz(Geo F, Geo C,
   const R *__restrict__ ublk = u + F.cs;     // colour 1
   const R *__restrict__ u0 = ured + col_m(F, i0, j0);
   const R *__restrict__ u1 = ured + col_m(F, i0 + 1, j0 + 1);
-  const R *__restrict__ b0 = b + col_m(F, i0, j0);
-  const R *__restrict__ b1 = b + col_m(F, i0 + 1, j0 + 1);
+  const TB *__restrict__ b0 = b + col_m(F, i0, j0);
+  const TB *__restrict__ b1 = b + col_m(F, i0 + 1, j0 + 1);
   const R *__restrict__ pA = ublk + col_m(F, wrapi(i0 - 1, F.nx), j0);
   const R *__restrict__ pB = ublk + col_m(F, i0 + 1, j0);
   const R *__restrict__ pC = ublk + col_m(F, i0, wrapi(j0 - 1, F.ny));
@@ -439,8 +441,8 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_bz(Geo F, Geo C,
     for (int t = 0; t < U; ++t) {
       const long long o = (long long)(k + t) * H;
       const long long op = (long long)min(k + t + 1, nz - 1) * H;
-      bb0[t] = b0[o];
-      bb1[t] = b1[o];
+      bb0[t] = (R)b0[o];
+      bb1[t] = (R)b1[o];
       p0[t] = u0[op];
       p1[t] = u1[op];
       A[t] = pA[o];
@@ -456,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_bz(Geo F, Geo C,
   for (; k < k1; ++k) {
     const long long o = (long long)k * H;
     const long long op = (long long)min(k + 1, nz - 1) * H;
-    step(k, b0[o], b1[o], u0[op], u1[op], pA[o], pB[o], pC[o], pD[o], pE[o], pF[o]);
+    step(k, (R)b0[o], (R)b1[o], u0[op], u1[op], pA[o], pB[o], pC[o], pD[o], pE[o], pF[o]);
   }
 }
 
@@ -602,6 +604,47 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__res
     const long long kc = (long long)k * HC;
     const R e = MODE == 1 ? p11[kc] : interp(p11[kc], p21[kc], p12[kc], p22[kc]);
     own[(long long)k * HF] = own[(long long)k * HF] + e;
+  }
+}
+
+// Colour-0 prolongation from an FP32 hierarchy into the FP64 output of the
+// finest level: out = base + P uc on colour-0 columns (base: the FP32
+// pre-smoothed iterate).  Bilinear weights as in k_prolong.
+template <typename R, typename TO, int MODE>
+__global__ __launch_bounds__(kBlock) void k_prolong_out(Geo F, Geo C, const R *__restrict__ uc,
+                                                        const R *__restrict__ base,
+                                                        TO *__restrict__ out,
+                                                        const int *__restrict__ done) {
+  if (is_done(done)) return;
+  const int m = logical_block() * kSegCols + (threadIdx.x & 63);
+  if (m >= F.ncol0) return;
+  const int Ls = seg_len(F.nz);
+  const int k0 = min(wave_id() * Ls, F.nz), k1 = min(k0 + Ls, F.nz);
+  int i, j;
+  col_ij(F, 0, m, i, j);
+  const int I = i >> 1, J = j >> 1;
+  const int I2 = wrapi(I + ((i & 1) ? 1 : -1), C.nx);
+  const int J2 = wrapi(J + ((j & 1) ? 1 : -1), C.ny);
+  const R *__restrict__ p11 = uc + (long long)((I + J) & 1) * C.cs + col_m(C, I, J);
+  const R *__restrict__ p21 = uc + (long long)((I2 + J) & 1) * C.cs + col_m(C, I2, J);
+  const R *__restrict__ p12 = uc + (long long)((I + J2) & 1) * C.cs + col_m(C, I, J2);
+  const R *__restrict__ p22 = uc + (long long)((I2 + J2) & 1) * C.cs + col_m(C, I2, J2);
+  const R *__restrict__ bs = base + m;
+  TO *__restrict__ ow = out + m;
+  const long long HC = C.S, HF = F.S;
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) {
+    const long long kc = (long long)k * HC;
+    R e;
+    if (MODE == 1) {
+      e = p11[kc];
+    } else {
+      e = R(9.0 / 16.0) * p11[kc];
+      e = e + R(3.0 / 16.0) * p21[kc];
+      e = e + R(3.0 / 16.0) * p12[kc];
+      e = e + R(1.0 / 16.0) * p22[kc];
+    }
+    ow[(long long)k * HF] = (TO)bs[(long long)k * HF] + (TO)e;
   }
 }
 

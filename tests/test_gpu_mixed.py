@@ -1,0 +1,91 @@
+"""Mixed precision: FP32 V-cycle preconditioner (FP64 or BF16-rounded stencil
+coefficients) inside the FP64 flexible CG, against the FP64 oracle.
+
+Readings: the preconditioner's precision changes M^{-1}, not the problem, so
+(i) one FP32 V-cycle agrees with the FP64 one to FP32 accuracy (amplified by
+the column solves' conditioning), (ii) solved tightly (rtol 1e-12) both
+precisions reach the same discrete solution, required to 1e-8 relative L2,
+and (iii) at the production tolerance 1e-5 the mixed solve converges in at
+most two more iterations than FP64 and its error against the oracle's tight
+solution is of the same size as the FP64 solve's.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1307_2036_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+PROBLEMS = {
+    "config0": lambda: I.config0(),
+    "graded64_L4": lambda: I.graded_problem("g64", 64, 32, 1e-2, 21, 22, n_levels=4, nu_coarse=5),
+    "graded96_w1e-1": lambda: I.graded_problem("g96", 96, 24, 1e-1, 23, 24),
+}
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16coef", 3e-2)])
+def test_vcycle_precision(orc, name, precision, tol):
+    from paper_1307_2036_amd import ell
+    p = PROBLEMS[name]()
+    g = orc.Grid.from_problem(p)
+    G = ell.Grid.from_problem(p, precision=precision)
+    r = p.f * (p.hx * p.hy * p.dz)[:, None, None]
+    z = host(G.vcycle(dev(r)))
+    assert rel(z, orc.vcycle(g, r)) <= tol
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("precision", ["fp32", "bf16coef"])
+def test_tight_solve_reaches_fp64_solution(orc, name, precision):
+    from paper_1307_2036_amd import ell
+    p = PROBLEMS[name]()
+    g = orc.Grid.from_problem(p)
+    u_ref, st_ref = orc.pcg(g, p.f, rtol=1e-12, maxiter=300)
+    G = ell.Grid.from_problem(p, precision=precision)
+    u, st = G.pcg_solve(dev(p.f), rtol=1e-12, maxiter=300)
+    assert st.status == 0
+    assert rel(host(u), u_ref) <= 1e-8
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+@pytest.mark.parametrize("precision", ["fp32", "bf16coef"])
+def test_production_tolerance(orc, name, precision):
+    from paper_1307_2036_amd import ell
+    p = PROBLEMS[name]()
+    g = orc.Grid.from_problem(p)
+    u_tight, _ = orc.pcg(g, p.f, rtol=1e-12, maxiter=300)
+    u64, st64 = orc.pcg(g, p.f, rtol=p.rtol)
+    G = ell.Grid.from_problem(p, precision=precision)
+    u, st = G.pcg_solve(dev(p.f), rtol=p.rtol)
+    assert st.status == 0 and st.iters <= st64["iters"] + 2, (st.iters, st64["iters"])
+    e_mixed, e_64 = rel(host(u), u_tight), rel(u64, u_tight)
+    assert e_mixed <= 10 * e_64 + 1e-12, (e_mixed, e_64)
+
+
+def test_fullsize_mixed_solve(orc):
+    """512 x 512 x 128 production shape in FP32-preconditioned mode."""
+    from paper_1307_2036_amd import ell
+    p = I.config1()
+    g = orc.Grid.from_problem(p)
+    G = ell.Grid.from_problem(p, precision="fp32")
+    u, st = G.pcg_solve(dev(p.f), rtol=p.rtol)
+    u64, st64 = orc.pcg(g, p.f, rtol=p.rtol)
+    print("fp32 iters", st.iters, "fp64 iters", st64["iters"], "rel to fp64", rel(host(u), u64))
+    assert st.status == 0 and st.iters <= st64["iters"] + 2
+    assert rel(host(u), u64) <= 1e-4
