@@ -40,6 +40,21 @@ def parse():
     return ap.parse_args()
 
 
+def counter_traffic(precision: str):
+    """HBM bytes per finest-level smoother launch from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE summary, if it was taken on the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "smooth0_traffic.json")
+    src = os.path.join(ROOT, "paper_1307_2036_amd", "csrc", "ell_kernels.hpp")
+    if precision != "fp64" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("kernel_source_sha256_16") != cur:
+        return None
+    return rec["smooth0_traffic_bytes_per_launch"]
+
+
 def cpu_baseline(p, gpu_iters: int, min_seconds: float = 10.0):
     """The FP64 oracle, as it stands, on the host cores: whole solves of the
     same problem (1e-5 reduction from u0 = 0), repeated until at least
@@ -114,10 +129,12 @@ def main():
 
     t_s = live(G.profile_times(ell.ELL_K_SMOOTH0))
     t_a = live(G.profile_times(ell.ELL_K_APPLY))
-    launch_bytes = perfmodel.smooth0_launch_bytes(n, e)
+    launch_bytes = (perfmodel.smooth0_launch_bytes(n, 8) if a.precision == "fp64"
+                    else perfmodel.smooth0_launch_bytes_hybrid(n))
     avg_ms = float(t_s.mean())
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
-    apply_gbs = 16 * n / (float(t_a.mean()) * 1e-3) / 1e9
+    # the CG operator step reads z, p_old, u and writes p_new, q, u (48 B per unknown)
+    apply_gbs = 48 * n / (float(t_a.mean()) * 1e-3) / 1e9
     cnt = int(t_s.size)
 
     solves = a.steps / elapsed
@@ -145,12 +162,13 @@ def main():
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "true_rel_residual": st.true_r_norm / st.b_norm,
-        "roofline": {"bound": "hbm", "kernel": "k_smooth (finest level, FP64)",
+        "roofline": {"bound": "hbm", "kernel": f"k_smooth_seg (finest level, {'FP64' if a.precision == 'fp64' else 'FP32 pre / FP64 post'})",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(a.precision),
                      "avg_launch_us": avg_ms * 1e3, "launches": cnt,
                      "bytes_per_launch": launch_bytes},
-        "apply_kernel": {"achieved_gbs": apply_gbs, "avg_launch_us": float(t_a.mean()) * 1e3},
+        "cg_operator_kernel": {"kernel": "k_apply_dir", "achieved_gbs": apply_gbs,
+                               "avg_launch_us": float(t_a.mean()) * 1e3},
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, iters, a.cpu_seconds)

@@ -41,11 +41,34 @@ def vcycle_bytes(n0: int, levels: int, e: int, nu_pre=1, nu_post=1, nu_coarse=1)
     return total
 
 
-def pcg_iteration_bytes(n0: int, levels: int, e: int, **mg) -> float:
-    z = e
-    cg = 16 * n0 + 48 * n0 + (16 + z) * n0 + (16 + z) * n0
-    cast = (8 + 4) * n0 if e == 4 else 0.0
-    return cg + cast + vcycle_bytes(n0, levels, e, **mg)
+def cg_bytes(n0: int) -> float:
+    """CG vector work per iteration (FP64): fused direction + operator + deferred
+    solution update (z, p_old, u read; p_new, q, u written: 48 B), residual update
+    (r, q read; r written: 24 B), dots <r,z>, <z,q> (24 B)."""
+    return (48 + 24 + 24) * n0
+
+
+def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1) -> float:
+    """Mixed-precision V-cycle: FP32 everywhere except the finest level, whose
+    pre-smoothing and restriction read the FP64 residual and write FP32, and
+    whose colour-0 prolongation and post-smoothing write the FP64 output."""
+    fine = (6 + 8) * n0          # pre red (b64 read, u32 write), pre black (+ u32 red read)
+    fine += (4 + 4 + 1) * n0     # restriction: b64 red, u32 both colours, coarse write
+    fine += (2 + 1 + 4) * n0     # prolongation: u32 red, coarse, z64 red write
+    fine += 2 * 12 * n0          # FP64 post-smoothing, black then red
+    return fine + vcycle_bytes(n0 // 4, levels - 1, 4, nu_coarse=nu_coarse)
+
+
+def pcg_iteration_bytes(n0: int, levels: int, e: int, nu_coarse=1, **mg) -> float:
+    if e == 8:
+        return cg_bytes(n0) + vcycle_bytes(n0, levels, 8, nu_coarse=nu_coarse, **mg)
+    return cg_bytes(n0) + hybrid_vcycle_bytes(n0, levels, nu_coarse)
+
+
+def smooth0_launch_bytes_hybrid(n0: int) -> float:
+    """Average bytes of a finest-level half-sweep launch in the mixed-precision
+    V-cycle: FP32 pre-sweeps reading the FP64 residual, FP64 post-sweeps."""
+    return (6 + 8 + 12 + 12) * n0 / 4
 
 
 def smooth0_launch_bytes(n0: int, e: int, nu_pre=1, nu_post=1) -> float:
