@@ -201,6 +201,39 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
 enum { ELL_TUNE_PLANE_PAD = 0, ELL_TUNE_COLOUR_PAD = 1, ELL_TUNE_STENCIL_SEG = 2 };
 int ell_set_tuning(int key, int value);
 
+/* ---- batched solves and serving (beyond the paper) ---------------------------
+ * A batch engine advances many solves together: every stage of a CG iteration
+ * (operator step, residual update, each V-cycle half-sweep, restriction and
+ * prolongation, dots, scalar updates) is one launch covering all active grids,
+ * each grid with its own CG state on the device.  A worker thread admits
+ * submitted requests and retires finished ones between iterations, so requests
+ * that arrive while others run join at the next iteration (continuous
+ * batching).  Grids of a batch are created by the batch (uniform k-segment
+ * layout), count against its HBM budget and must all be FP64 or all use the
+ * FP32 preconditioner; they need rho = 1, nu >= 1, nx, ny > 1 on every level
+ * and nz <= 256.  Requests on one grid run one after another (warm starts:
+ * pass the previous solution as u). */
+typedef struct ell_batch ell_batch;
+
+/* hbm_budget_bytes: upper bound on the device bytes of the batch's grids. */
+int ell_batch_create(size_t hbm_budget_bytes, ell_batch **out);
+/* Create a grid owned by the batch; ELL_ERR_BUDGET if it does not fit. */
+int ell_batch_grid(ell_batch *b, const ell_grid_desc *desc, ell_grid **out);
+/* Destroy an idle grid of the batch and return its bytes to the budget. */
+int ell_batch_release(ell_batch *b, ell_grid *g);
+size_t ell_batch_bytes_in_use(const ell_batch *b);
+/* Enqueue n solves A u_i = V f_i (device vectors, plane-major, valid until
+ * the ticket completes); returns at once with a ticket. */
+int ell_batch_submit(ell_batch *b, int32_t n, ell_grid *const *grids, const double *const *f,
+                     double *const *u, const ell_solve_opts *opts, uint64_t *ticket_out);
+/* ELL_PENDING while any solve of the ticket runs; otherwise the combined
+ * status and n statistics (stats may be NULL). */
+int ell_batch_poll(ell_batch *b, uint64_t ticket, ell_solve_stats *stats);
+/* Block until the ticket completes, fill stats, release the ticket. */
+int ell_batch_wait(ell_batch *b, uint64_t ticket, ell_solve_stats *stats);
+/* Finish queued work, then free the batch and its grids. */
+int ell_batch_destroy(ell_batch *b);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char *ell_last_error(void);
 

@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libell.so")
 SOURCES = [os.path.join(CSRC, "ell.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, "ell_kernels.hpp"), os.path.join(INCLUDE, "ell.h")]
+DEPS = SOURCES + [os.path.join(CSRC, "ell_kernels.hpp"), os.path.join(CSRC, "ell_batch.inl"),
+                  os.path.join(INCLUDE, "ell.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -136,6 +136,9 @@ struct ell_grid {
   PcgState *st_host = nullptr;          // pinned
   Prof prof[ELL_K_COUNT];
   std::vector<void *> allocs;
+  bool batch_layout = false;  // every level uses 4 k-segments (grouped launches)
+  void *gdev = nullptr;       // device copy of the grid descriptor (batched kernels)
+  int busy = 0;               // a batch request is using the grid
 };
 
 namespace {
@@ -174,7 +177,7 @@ int smoother_segments(long long cols_per_colour, int nz, bool finest) {
   return ns;
 }
 
-Geo make_geo(int nx, int ny, int nz, bool finest = false) {
+Geo make_geo(int nx, int ny, int nz, bool finest = false, bool uniform_seg = false) {
   Geo G;
   G.nx = nx;
   G.ny = ny;
@@ -189,7 +192,7 @@ Geo make_geo(int nx, int ny, int nz, bool finest = false) {
   G.P = nz + 1;
   G.S = (int)(((long long)G.H + 63) / 64 * 64 + g_plane_pad);
   G.cs = (long long)nz * G.S + g_colour_pad;
-  G.nseg = smoother_segments(G.H, nz, finest);
+  G.nseg = uniform_seg ? 4 : smoother_segments(G.H, nz, finest);
   return G;
 }
 
@@ -627,18 +630,20 @@ int precondition<float>(ell_grid *g, const int *done, hipStream_t s) {
 
 // R: arithmetic of the V-cycle; Z: element type of its output z (FP64 for
 // the FP64 and the hybrid mixed-precision V-cycles, FP32 otherwise).
+template <typename Z>
+const typename Vec2<Z>::T *zvec(const ell_grid *g) {
+  return (const typename Vec2<Z>::T *)(std::is_same<Z, double>::value ? (void *)g->z : g->z32);
+}
+
+// Start of a solve (Appendix B, Alg. PCG, before the loop): r = V f - A u0
+// with ||b|| and ||r0|| (the device sets done if nothing is left to do),
+// z0 = M^{-1} r0, kappa = <r0, z0>.
 template <typename R, typename Z>
-int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, ell_solve_stats *out,
-             hipStream_t s) {
+int pcg_begin(ell_grid *g, const double *f, const double *u, const ell_solve_opts &o, hipStream_t s) {
   const Geo &G = g->lev[0].geo;
   const long long n2 = g->n0 / 2;
   const int fb = flat_blocks(n2);
-  const int ab = stencil_blocks(2LL * G.H, g->stencil_seg);  // blocks of the CG operator kernel
   const int *done = &g->st->done;
-  const typename Vec2<Z>::T *zv =
-      (const typename Vec2<Z>::T *)(std::is_same<Z, double>::value ? (void *)g->z : g->z32);
-
-  // r = V f - A u0 (split layout), ||b||, ||r0||
   const int cb = blocks8(2LL * G.H);
   k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, f, g->r, g->vol0);
   CHK(check_launch("k_nat2split"));
@@ -656,53 +661,59 @@ int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, e
     h->flexible = o.flexible;
     HIPCHK(hipMemcpyAsync(&g->st->maxiter, &h->maxiter, 2 * sizeof(int), hipMemcpyHostToDevice, s));
   }
-  // z0 = M^{-1} r0, kappa = <r0, z0>
   CHK(precondition<R>(g, done, s));
-  k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zv, (const double2 *)g->q, n2, g->st, g->partial);
+  k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zvec<Z>(g), (const double2 *)g->q, n2, g->st,
+                                  g->partial);
   CHK(check_launch("k_dots"));
-  CHK(finalize(g, fb, 2, F_KAPPA, s));
+  return finalize(g, fb, 2, F_KAPPA, s);
+}
 
-  const int poll = o.poll_every > 0 ? o.poll_every : 4;
+// Iteration K (1-based) of the loop; a no-op on the device once done is set.
+template <typename R, typename Z>
+int pcg_step(ell_grid *g, int K, hipStream_t s) {
+  const Geo &G = g->lev[0].geo;
+  const long long n2 = g->n0 / 2;
+  const int fb = flat_blocks(n2);
+  const int ab = stencil_blocks(2LL * G.H, g->stencil_seg);  // blocks of the CG operator kernel
+  const int *done = &g->st->done;
   double *pbuf[2] = {g->p, g->p2};
-  int enq = 0;
-  while (enq < o.maxiter) {
-    const int batch = std::min(poll, o.maxiter - enq);
-    for (int it = 0; it < batch; ++it) {
-      const int K = enq + it + 1;  // 1-based iteration number
-      {
-        ProfScope ps(g, ELL_K_APPLY, s);
-        const int first = K == 1 ? 1 : 0, defer = K > 1 ? 1 : 0;
-        const Z *zz = (const Z *)zv;
-        if (g->stencil_seg == 1)
-          k_apply_dir<Z, 1><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q,
-                                                  g->us, g->st, first, defer, g->partial);
-        else if (g->stencil_seg == 2)
-          k_apply_dir<Z, 2><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q,
-                                                  g->us, g->st, first, defer, g->partial);
-        else
-          k_apply_dir<Z, 4><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q,
-                                                  g->us, g->st, first, defer, g->partial);
-      }
-      CHK(check_launch("k_apply_dir"));
-      CHK(finalize(g, ab, 1, F_ALPHA, s));
-      {
-        ProfScope ps(g, ELL_K_UPDATE, s);
-        k_update_r<<<fb, kBlock, 0, s>>>((double2 *)g->r, (const double2 *)g->q, n2, g->st, g->partial);
-      }
-      CHK(check_launch("k_update_r"));
-      CHK(finalize(g, fb, 1, F_CONV, s));
-      CHK(precondition<R>(g, done, s));
-      k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zv, (const double2 *)g->q, n2, g->st,
-                                      g->partial);
-      CHK(check_launch("k_dots"));
-      CHK(finalize(g, fb, 2, F_BETA, s));
-    }
-    enq += batch;
-    HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    if (g->st_host->done) break;
+  {
+    ProfScope ps(g, ELL_K_APPLY, s);
+    const int first = K == 1 ? 1 : 0, defer = K > 1 ? 1 : 0;
+    const Z *zz = (const Z *)zvec<Z>(g);
+    if (g->stencil_seg == 1)
+      k_apply_dir<Z, 1><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us,
+                                              g->st, first, defer, g->partial);
+    else if (g->stencil_seg == 2)
+      k_apply_dir<Z, 2><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us,
+                                              g->st, first, defer, g->partial);
+    else
+      k_apply_dir<Z, 4><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us,
+                                              g->st, first, defer, g->partial);
   }
-  // the last step's solution update (deferred above)
+  CHK(check_launch("k_apply_dir"));
+  CHK(finalize(g, ab, 1, F_ALPHA, s));
+  {
+    ProfScope ps(g, ELL_K_UPDATE, s);
+    k_update_r<<<fb, kBlock, 0, s>>>((double2 *)g->r, (const double2 *)g->q, n2, g->st, g->partial);
+  }
+  CHK(check_launch("k_update_r"));
+  CHK(finalize(g, fb, 1, F_CONV, s));
+  CHK(precondition<R>(g, done, s));
+  k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zvec<Z>(g), (const double2 *)g->q, n2, g->st,
+                                  g->partial);
+  CHK(check_launch("k_dots"));
+  return finalize(g, fb, 2, F_BETA, s);
+}
+
+// End of a solve; g->st_host must hold the final state: the last step's
+// deferred solution update, u back to plane-major, the FP64 true residual.
+int pcg_finish(ell_grid *g, const double *f, double *u, ell_solve_stats *out, hipStream_t s) {
+  const Geo &G = g->lev[0].geo;
+  const long long n2 = g->n0 / 2;
+  const int fb = flat_blocks(n2);
+  const int cb = blocks8(2LL * G.H);
+  double *pbuf[2] = {g->p, g->p2};
   {
     const int K = g->st_host->iter;
     if (K > 0 && g->st_host->status != -4) {
@@ -710,7 +721,6 @@ int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, e
       CHK(check_launch("k_axpy_alpha"));
     }
   }
-  // solution back to plane-major, true residual ||V f - A u||
   k_split2nat<double, double><<<cb, kBlock, 0, s>>>(G, g->us, u);
   CHK(check_launch("k_split2nat"));
   k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, f, g->r, g->vol0);
@@ -723,8 +733,7 @@ int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, e
   HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const PcgState &h = *g->st_host;
-  int status = h.status;
-  if (!h.done && status == 1) status = 1;
+  const int status = h.status;
   if (out) {
     out->iters = h.iter;
     out->status = status == -4 ? ELL_ERR_NUMERIC : (status == 0 ? ELL_OK : ELL_NOT_CONVERGED);
@@ -735,6 +744,24 @@ int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, e
   }
   if (status == -4) return fail(ELL_ERR_NUMERIC, "non-finite value in the CG recurrence");
   return status == 0 ? ELL_OK : ELL_NOT_CONVERGED;
+}
+
+template <typename R, typename Z>
+int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, ell_solve_stats *out,
+             hipStream_t s) {
+  CHK((pcg_begin<R, Z>(g, f, u, o, s)));
+  const int poll = o.poll_every > 0 ? o.poll_every : 4;
+  int enq = 0;
+  HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  while (enq < o.maxiter && !g->st_host->done) {
+    const int batch = std::min(poll, o.maxiter - enq);
+    for (int it = 0; it < batch; ++it) CHK((pcg_step<R, Z>(g, enq + it + 1, s)));
+    enq += batch;
+    HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return pcg_finish(g, f, u, out, s);
 }
 
 int check_level(const ell_grid *g, int level, bool need_coarser) {
@@ -759,7 +786,11 @@ size_t ell_grid_bytes(const ell_grid_desc *desc) {
   return grid_bytes(desc, L);
 }
 
-int ell_grid_create(const ell_grid_desc *desc, ell_grid **out) {
+static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **out);
+
+int ell_grid_create(const ell_grid_desc *desc, ell_grid **out) { return grid_create(desc, false, out); }
+
+static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **out) {
   if (!out) return fail(ELL_ERR_INVALID, "out is NULL");
   *out = nullptr;
   int L = 0;
@@ -773,7 +804,8 @@ int ell_grid_create(const ell_grid_desc *desc, ell_grid **out) {
   g->L = L;
   g->prec = desc->precision;
   g->esz = g->prec == ELL_FP64 ? 8 : 4;
-  g->stencil_seg = g_stencil_seg;
+  g->stencil_seg = batch_layout ? 1 : g_stencil_seg;
+  g->batch_layout = batch_layout;
   g->lev.resize(L);
   auto bail = [&](int rc) {
     ell_grid_destroy(g);
@@ -784,7 +816,7 @@ int ell_grid_create(const ell_grid_desc *desc, ell_grid **out) {
   std::vector<float> t32;
   for (int l = 0; l < L; ++l) {
     Level &Lv = g->lev[l];
-    Lv.geo = make_geo(desc->nx >> l, desc->ny >> l, desc->nz, l == 0);
+    Lv.geo = make_geo(desc->nx >> l, desc->ny >> l, desc->nz, l == 0, batch_layout);
     Lv.hx = desc->hx * (double)(1 << l);
     Lv.hy = desc->hy * (double)(1 << l);
     level_table64(g, l, t64);
@@ -1062,3 +1094,5 @@ int ell_set_tuning(int key, int value) {
 }
 
 }  // extern "C"
+
+#include "ell_batch.inl"

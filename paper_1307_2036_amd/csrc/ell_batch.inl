@@ -1,0 +1,782 @@
+// Batch engine: many solves of uneven size advanced together.
+//
+// Every stage of a CG iteration (the fused operator step, the residual
+// update, each V-cycle half-sweep / restriction / prolongation, the dots and
+// the scalar updates) is one grouped launch covering every active grid: a
+// block looks up its grid in a stage table (binary search over block offsets)
+// and runs the same device body as the single-grid kernel on that grid's
+// arrays.  Grids of different depth share the launches of the levels they
+// have; each grid carries its own CG state on the device, so converged grids
+// drop out (their blocks return at once) while the others continue.  A host
+// worker thread admits new requests and retires finished ones between
+// iterations, so requests that arrive while others run join the next
+// iteration (continuous batching) and their work overlaps on the device.
+//
+// Included into ell.hip (it uses that file's launch helpers and grid type).
+
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+
+namespace {
+
+constexpr int kMaxLevels = 16;
+
+struct LevelDev {
+  Geo geo;
+  const void *tab;
+  void *b;
+  void *u;
+};
+
+// Everything the batched kernels need of one grid (device copy).
+struct GridDev {
+  LevelDev lev[kMaxLevels];
+  const double *tab64_0;
+  double *us, *r, *z, *p, *p2, *q;
+  float *u32;
+  double *partial;
+  PcgState *st;
+  long long n2;
+  int L, nb_apply, nb_flat, prolong;
+};
+
+struct StageEnt {
+  const GridDev *g;
+  int block0;
+  int pad;
+};
+
+enum Role : int { ROLE_COARSE = 0, ROLE_FINE64 = 1, ROLE_PRE32 = 2 };
+
+__device__ __forceinline__ int find_ent(const StageEnt *e, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (e[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// R: arithmetic type; TB: type of b.  ROLE selects the arrays of the stage.
+template <typename R, bool ZERO, bool FINE, int SEG, typename TB, int ROLE>
+__global__ __launch_bounds__(kBlock) void kb_smooth(const StageEnt *__restrict__ ents, int nent, int total,
+                                                    int l, int c) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = ents[e].g;
+  const LevelDev &Lv = gd->lev[l];
+  const Geo G = Lv.geo;
+  const R *tab;
+  const TB *b;
+  R *u;
+  if (ROLE == ROLE_FINE64) {
+    tab = (const R *)gd->tab64_0;
+    b = (const TB *)gd->r;
+    u = (R *)gd->z;
+  } else if (ROLE == ROLE_PRE32) {
+    tab = (const R *)Lv.tab;
+    b = (const TB *)gd->r;
+    u = (R *)gd->u32;
+  } else {
+    tab = (const R *)Lv.tab;
+    b = (const TB *)Lv.b;
+    u = (R *)Lv.u;
+  }
+  smooth_seg_body<R, ZERO, true, FINE, SEG, 4, TB>(G, tab, c, b + (long long)c * G.cs,
+                                                   u + (long long)(1 - c) * G.cs, u + (long long)c * G.cs,
+                                                   R(1), &gd->st->done, bg - ents[e].block0, 0);
+}
+
+template <typename R, typename TB, int ROLE>
+__global__ __launch_bounds__(kBlock) void kb_restrict(const StageEnt *__restrict__ ents, int nent, int total,
+                                                      int l) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = ents[e].g;
+  const LevelDev &F = gd->lev[l];
+  const LevelDev &C = gd->lev[l + 1];
+  const TB *b = ROLE == ROLE_COARSE ? (const TB *)F.b : (const TB *)gd->r;
+  const R *u = ROLE == ROLE_COARSE ? (const R *)F.u : (ROLE == ROLE_PRE32 ? (const R *)gd->u32 : (const R *)gd->z);
+  resid_restrict_bz_body<R, TB>(F.geo, C.geo, (const R *)F.tab, b, u, (R *)C.b, &gd->st->done,
+                                bg - ents[e].block0, 0);
+}
+
+template <typename R, int MODE, int ROLE>
+__global__ __launch_bounds__(kBlock) void kb_prolong(const StageEnt *__restrict__ ents, int nent, int total,
+                                                     int l) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = ents[e].g;
+  const LevelDev &F = gd->lev[l];
+  const LevelDev &C = gd->lev[l + 1];
+  R *u = ROLE == ROLE_FINE64 ? (R *)gd->z : (R *)F.u;
+  prolong_body<R, true, MODE>(F.geo, C.geo, (const R *)C.u, u, &gd->st->done, bg - ents[e].block0, 0);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void kb_prolong_out(const StageEnt *__restrict__ ents, int nent,
+                                                         int total) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = ents[e].g;
+  prolong_out_body<float, double, MODE>(gd->lev[0].geo, gd->lev[1].geo, (const float *)gd->lev[1].u, gd->u32,
+                                        gd->z, &gd->st->done, bg - ents[e].block0, 0);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_apply_dir(const StageEnt *__restrict__ ents, int nent, int total) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = ents[e].g;
+  const int K = gd->st->iter + 1;  // iteration about to run
+  double *pold = ((K - 1) & 1) ? gd->p2 : gd->p;
+  double *pnew = (K & 1) ? gd->p2 : gd->p;
+  apply_dir_body<double, 1>(gd->lev[0].geo, gd->tab64_0, gd->z, pold, pnew, gd->q, gd->us, gd->st,
+                            K == 1 ? 1 : 0, K > 1 ? 1 : 0, gd->partial, bg - ents[e].block0, 0);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_update_r(const StageEnt *__restrict__ ents, int nent, int total) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = ents[e].g;
+  update_r_body((double2 *)gd->r, (const double2 *)gd->q, gd->n2, gd->st, gd->partial, bg - ents[e].block0,
+                gd->nb_flat);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_dots(const StageEnt *__restrict__ ents, int nent, int total) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = ents[e].g;
+  dots_body<double>((const double2 *)gd->r, (const double2 *)gd->z, (const double2 *)gd->q, gd->n2, gd->st,
+                    gd->partial, bg - ents[e].block0, gd->nb_flat);
+}
+
+// one block per grid
+__global__ __launch_bounds__(kBlock) void kb_finalize(const StageEnt *__restrict__ ents, int mode) {
+  const GridDev *gd = ents[blockIdx.x].g;
+  const int nblk = mode == F_ALPHA ? gd->nb_apply : gd->nb_flat;
+  const int nq = mode == F_BETA ? 2 : 1;
+  finalize_body(gd->partial, nblk, nq, gd->st, mode, 0.0, 0.0, 0, 0, 1);
+}
+
+__global__ void kb_gather_states(const StageEnt *__restrict__ ents, int nent, PcgState *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nent) out[i] = *ents[i].g->st;
+}
+
+// ------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------
+int grid_dev_build(ell_grid *g) {
+  if (g->L > kMaxLevels) return fail(ELL_ERR_INVALID, "too many levels for the batch engine");
+  GridDev h;
+  std::memset(&h, 0, sizeof(h));
+  for (int l = 0; l < g->L; ++l) {
+    h.lev[l].geo = g->lev[l].geo;
+    h.lev[l].tab = g->lev[l].tab;
+    h.lev[l].b = g->lev[l].b;
+    h.lev[l].u = g->lev[l].u;
+  }
+  h.tab64_0 = g->tab64_0;
+  h.us = g->us;
+  h.r = g->r;
+  h.z = g->z;
+  h.p = g->p;
+  h.p2 = g->p2;
+  h.q = g->q;
+  h.u32 = (float *)g->z32;
+  h.partial = g->partial;
+  h.st = g->st;
+  h.n2 = g->n0 / 2;
+  h.L = g->L;
+  h.nb_apply = stencil_blocks(2LL * g->lev[0].geo.H, 1);
+  h.nb_flat = flat_blocks(h.n2);
+  h.prolong = g->d.prolong;
+  void *d = nullptr;
+  CHK(dalloc(g, &d, sizeof(GridDev)));
+  HIPCHK(hipMemcpy(d, &h, sizeof(GridDev), hipMemcpyHostToDevice));
+  g->gdev = d;
+  return ELL_OK;
+}
+
+bool batch_capable(const ell_grid *g, std::string *why) {
+  const auto &d = g->d;
+  if (d.rho != 1.0) { *why = "batched grids need rho = 1"; return false; }
+  if (d.nu_pre < 1 || d.nu_post < 1 || d.nu_coarse < 1) { *why = "batched grids need nu >= 1"; return false; }
+  // coarse levels may be one column wide: the segmented sweep then reads
+  // zero-initialised, never-written entries for the missing faces and
+  // multiplies them by zero coefficients
+  if (!g->lev[0].geo.has_x || !g->lev[0].geo.has_y) {
+    *why = "batched grids need nx, ny > 1 on the finest level";
+    return false;
+  }
+  if (seg_len(g->d.nz, 4) > 64) { *why = "batched grids need nz <= 256"; return false; }
+  if (g->prec != ELL_FP64 && !hybrid_ok(g)) { *why = "mixed precision batches need >= 2 levels"; return false; }
+  return true;
+}
+
+struct Request {
+  uint64_t ticket;
+  ell_grid *g;
+  const double *f;
+  double *u;
+  ell_solve_opts o;
+  ell_solve_stats st;
+  int rc = ELL_PENDING;
+};
+
+struct Ticket {
+  std::vector<Request *> reqs;
+  int remaining;
+};
+
+// One stage of a grouped iteration.
+struct Stage {
+  enum Kind { APPLY_DIR, UPDATE_R, DOTS, FINALIZE, SMOOTH, RESTRICT, PROLONG, PROLONG_OUT } kind;
+  int level, colour, zero, role, mode;  // mode: finalize mode
+  int seg;                              // SMOOTH: register segment length (16/32/64)
+  size_t off;                           // offset of the entry table in the device buffer
+  int nent, total;
+};
+
+}  // namespace
+
+struct ell_batch {
+  size_t budget = 0;
+  size_t used = 0;
+  hipStream_t stream = nullptr;
+  std::vector<ell_grid *> grids;  // owned
+  std::mutex mu;
+  std::condition_variable cv, cv_done;
+  std::deque<Request *> queue;
+  std::map<uint64_t, Ticket> tickets;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread worker;
+  int poll_every = 4;
+  // engine state (worker thread only)
+  std::vector<Request *> active;
+  std::vector<Stage> stages;
+  StageEnt *d_ents = nullptr;
+  StageEnt *h_ents = nullptr;  // pinned staging
+  size_t ents_cap = 0;
+  PcgState *d_states = nullptr;
+  PcgState *h_states = nullptr;  // pinned
+  int states_cap = 0;
+  bool dirty = true;
+  int prec = -1;
+  std::string last_error;
+  // statistics
+  long long steps = 0;
+};
+
+namespace {
+
+int batch_reserve(ell_batch *b, size_t ents, int states) {
+  if (ents > b->ents_cap) {
+    if (b->d_ents) (void)hipFree(b->d_ents);
+    if (b->h_ents) (void)hipHostFree(b->h_ents);
+    b->d_ents = nullptr;
+    b->h_ents = nullptr;
+    size_t cap = std::max<size_t>(ents, 2 * b->ents_cap);
+    HIPCHK(hipMalloc((void **)&b->d_ents, cap * sizeof(StageEnt)));
+    HIPCHK(hipHostMalloc((void **)&b->h_ents, cap * sizeof(StageEnt), hipHostMallocDefault));
+    b->ents_cap = cap;
+  }
+  if (states > b->states_cap) {
+    if (b->d_states) (void)hipFree(b->d_states);
+    if (b->h_states) (void)hipHostFree(b->h_states);
+    b->d_states = nullptr;
+    b->h_states = nullptr;
+    int cap = std::max(states, 2 * b->states_cap);
+    HIPCHK(hipMalloc((void **)&b->d_states, cap * sizeof(PcgState)));
+    HIPCHK(hipHostMalloc((void **)&b->h_states, cap * sizeof(PcgState), hipHostMallocDefault));
+    b->states_cap = cap;
+  }
+  return ELL_OK;
+}
+
+// Build the stage list and entry tables for the active grids.  The V-cycle of
+// every grid follows its own depth: at depth d the grids with more levels
+// pre-smooth and restrict, the grids whose coarsest level is d run their
+// coarse sweeps (the first of them shares the pre-smoothing launches).
+int batch_build(ell_batch *b) {
+  std::vector<StageEnt> ents;
+  b->stages.clear();
+  const auto &A = b->active;
+  const bool mixed = b->prec != ELL_FP64;
+  auto add = [&](Stage st, const std::vector<ell_grid *> &gs, auto blocks_of) {
+    if (gs.empty()) return;
+    st.off = ents.size();
+    int tot = 0;
+    for (ell_grid *g : gs) {
+      const int nb = blocks_of(g);
+      if (nb <= 0) continue;  // e.g. the empty colour of a 1x1 level
+      ents.push_back(StageEnt{(const GridDev *)g->gdev, tot, 0});
+      tot += nb;
+    }
+    st.nent = (int)(ents.size() - st.off);
+    if (st.nent == 0) return;
+    st.total = tot;
+    b->stages.push_back(st);
+  };
+  std::vector<ell_grid *> all;
+  for (Request *r : A) all.push_back(r->g);
+  auto one = [](ell_grid *) { return 1; };
+  auto flat = [](ell_grid *g) { return flat_blocks(g->n0 / 2); };
+  auto apply = [](ell_grid *g) { return stencil_blocks(2LL * g->lev[0].geo.H, 1); };
+  auto cols = [](int l, int c) {
+    return [l, c](ell_grid *g) {
+      const Geo &G = g->lev[l].geo;
+      return (int)(((c ? G.ncol1 : G.ncol0) + kSegCols - 1) / kSegCols);
+    };
+  };
+  auto coarse_cols = [](int l) {
+    return [l](ell_grid *g) { return (int)((2LL * g->lev[l + 1].geo.H + kSegCols - 1) / kSegCols); };
+  };
+  auto red_cols = [](int l) {
+    return [l](ell_grid *g) { return (int)((g->lev[l].geo.ncol0 + kSegCols - 1) / kSegCols); };
+  };
+  auto seg_of = [](const std::vector<ell_grid *> &gs, int l) {
+    int m = 16;
+    for (ell_grid *g : gs) m = std::max(m, seg_len(g->lev[l].geo.nz, 4));
+    return m <= 16 ? 16 : (m <= 32 ? 32 : 64);
+  };
+  Stage s0{};
+  // CG operator step, alpha, residual update, convergence
+  s0 = Stage{};
+  s0.kind = Stage::APPLY_DIR;
+  add(s0, all, apply);
+  s0 = Stage{};
+  s0.kind = Stage::FINALIZE;
+  s0.mode = F_ALPHA;
+  add(s0, all, one);
+  s0 = Stage{};
+  s0.kind = Stage::UPDATE_R;
+  add(s0, all, flat);
+  s0 = Stage{};
+  s0.kind = Stage::FINALIZE;
+  s0.mode = F_CONV;
+  add(s0, all, one);
+  // V-cycle, down
+  int Dmax = 0;
+  for (ell_grid *g : all) Dmax = std::max(Dmax, g->L);
+  const int nu_pre = all.empty() ? 1 : all[0]->d.nu_pre;
+  const int nu_post = all.empty() ? 1 : all[0]->d.nu_post;
+  for (int d = 0; d < Dmax; ++d) {
+    std::vector<ell_grid *> deep, bottom, here;
+    for (ell_grid *g : all) {
+      if (d < g->L - 1) deep.push_back(g);
+      else if (d == g->L - 1) bottom.push_back(g);
+    }
+    here = deep;
+    here.insert(here.end(), bottom.begin(), bottom.end());
+    if (here.empty()) continue;
+    const int role = d == 0 ? (mixed ? ROLE_PRE32 : ROLE_FINE64) : ROLE_COARSE;
+    int sweeps_shared = nu_pre;
+    for (int it = 0; it < sweeps_shared; ++it) {
+      // grids at their coarsest level take part in the first pair only if
+      // they have at least one coarse sweep (nu_coarse >= 1, checked)
+      const std::vector<ell_grid *> &gs = it == 0 ? here : deep;
+      for (int c = 0; c < 2; ++c) {
+        Stage st{};
+        st.kind = Stage::SMOOTH;
+        st.level = d;
+        st.colour = c;
+        st.zero = (it == 0 && c == 0) ? 1 : 0;
+        st.role = role;
+        st.seg = seg_of(gs, d);
+        add(st, gs, cols(d, c));
+      }
+    }
+    // remaining coarse sweeps of the grids whose coarsest level is d
+    int maxc = 0;
+    for (ell_grid *g : bottom) maxc = std::max(maxc, g->d.nu_coarse);
+    for (int it = 1; it < maxc; ++it) {
+      std::vector<ell_grid *> gs;
+      for (ell_grid *g : bottom)
+        if (g->d.nu_coarse > it) gs.push_back(g);
+      for (int c = 0; c < 2; ++c) {
+        Stage st{};
+        st.kind = Stage::SMOOTH;
+        st.level = d;
+        st.colour = c;
+        st.zero = 0;
+        st.role = d == 0 ? (mixed ? ROLE_PRE32 : ROLE_FINE64) : ROLE_COARSE;
+        st.seg = seg_of(gs, d);
+        add(st, gs, cols(d, c));
+      }
+    }
+    if (!deep.empty()) {
+      Stage st{};
+      st.kind = Stage::RESTRICT;
+      st.level = d;
+      st.role = role;
+      add(st, deep, coarse_cols(d));
+    }
+  }
+  // V-cycle, up
+  for (int d = Dmax - 2; d >= 0; --d) {
+    std::vector<ell_grid *> gs;
+    for (ell_grid *g : all)
+      if (d < g->L - 1) gs.push_back(g);
+    if (gs.empty()) continue;
+    Stage st{};
+    if (d == 0 && mixed) {
+      st.kind = Stage::PROLONG_OUT;
+      st.level = 0;
+    } else {
+      st.kind = Stage::PROLONG;
+      st.level = d;
+      st.role = d == 0 ? ROLE_FINE64 : ROLE_COARSE;
+    }
+    st.mode = gs[0]->d.prolong;
+    add(st, gs, red_cols(d));
+    for (int it = 0; it < nu_post; ++it) {
+      for (int c = 1; c >= 0; --c) {
+        Stage sm{};
+        sm.kind = Stage::SMOOTH;
+        sm.level = d;
+        sm.colour = c;
+        sm.zero = 0;
+        sm.role = d == 0 ? ROLE_FINE64 : ROLE_COARSE;
+        sm.seg = seg_of(gs, d);
+        add(sm, gs, cols(d, c));
+      }
+    }
+  }
+  s0 = Stage{};
+  s0.kind = Stage::DOTS;
+  add(s0, all, flat);
+  s0 = Stage{};
+  s0.kind = Stage::FINALIZE;
+  s0.mode = F_BETA;
+  add(s0, all, one);
+  // state gather table: one entry per active grid (reuses the FINALIZE layout)
+  CHK(batch_reserve(b, ents.size() + 1, (int)all.size() + 1));
+  if (!ents.empty()) {
+    std::memcpy(b->h_ents, ents.data(), ents.size() * sizeof(StageEnt));
+    HIPCHK(hipMemcpyAsync(b->d_ents, b->h_ents, ents.size() * sizeof(StageEnt), hipMemcpyHostToDevice,
+                          b->stream));
+  }
+  b->dirty = false;
+  return ELL_OK;
+}
+
+template <typename R, typename TB, bool FINE, int ROLE>
+void launch_kb_smooth(const Stage &st, const StageEnt *e, int nb, hipStream_t s) {
+  const int L = st.level, C = st.colour;
+  if (st.zero) {
+    if (st.seg == 16) kb_smooth<R, true, FINE, 16, TB, ROLE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, L, C);
+    else if (st.seg == 32) kb_smooth<R, true, FINE, 32, TB, ROLE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, L, C);
+    else kb_smooth<R, true, FINE, 64, TB, ROLE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, L, C);
+  } else {
+    if (st.seg == 16) kb_smooth<R, false, FINE, 16, TB, ROLE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, L, C);
+    else if (st.seg == 32) kb_smooth<R, false, FINE, 32, TB, ROLE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, L, C);
+    else kb_smooth<R, false, FINE, 64, TB, ROLE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, L, C);
+  }
+}
+
+// Enqueue one grouped CG iteration for every active grid.
+int batch_step(ell_batch *b) {
+  hipStream_t s = b->stream;
+  const bool mixed = b->prec != ELL_FP64;
+  for (const Stage &st : b->stages) {
+    const StageEnt *e = b->d_ents + st.off;
+    const int nb = blocks8((long long)st.total * kBlock);
+    switch (st.kind) {
+      case Stage::APPLY_DIR: kb_apply_dir<<<nb, kBlock, 0, s>>>(e, st.nent, st.total); break;
+      case Stage::UPDATE_R: kb_update_r<<<nb, kBlock, 0, s>>>(e, st.nent, st.total); break;
+      case Stage::DOTS: kb_dots<<<nb, kBlock, 0, s>>>(e, st.nent, st.total); break;
+      case Stage::FINALIZE: kb_finalize<<<st.nent, kBlock, 0, s>>>(e, st.mode); break;
+      case Stage::SMOOTH:
+        if (st.role == ROLE_FINE64) launch_kb_smooth<double, double, true, ROLE_FINE64>(st, e, nb, s);
+        else if (st.role == ROLE_PRE32) launch_kb_smooth<float, double, true, ROLE_PRE32>(st, e, nb, s);
+        else if (mixed) launch_kb_smooth<float, float, false, ROLE_COARSE>(st, e, nb, s);
+        else launch_kb_smooth<double, double, false, ROLE_COARSE>(st, e, nb, s);
+        break;
+      case Stage::RESTRICT:
+        if (st.role == ROLE_FINE64) kb_restrict<double, double, ROLE_FINE64><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+        else if (st.role == ROLE_PRE32) kb_restrict<float, double, ROLE_PRE32><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+        else if (mixed) kb_restrict<float, float, ROLE_COARSE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+        else kb_restrict<double, double, ROLE_COARSE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+        break;
+      case Stage::PROLONG:
+        if (st.role == ROLE_FINE64) {
+          if (st.mode == 1) kb_prolong<double, 1, ROLE_FINE64><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+          else kb_prolong<double, 0, ROLE_FINE64><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+        } else if (mixed) {
+          if (st.mode == 1) kb_prolong<float, 1, ROLE_COARSE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+          else kb_prolong<float, 0, ROLE_COARSE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+        } else {
+          if (st.mode == 1) kb_prolong<double, 1, ROLE_COARSE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+          else kb_prolong<double, 0, ROLE_COARSE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+        }
+        break;
+      case Stage::PROLONG_OUT:
+        if (st.mode == 1) kb_prolong_out<1><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
+        else kb_prolong_out<0><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
+        break;
+    }
+    CHK(check_launch("batched stage"));
+  }
+  b->steps++;
+  return ELL_OK;
+}
+
+int request_begin(Request *r, hipStream_t s) {
+  ell_grid *g = r->g;
+  if (g->prec == ELL_FP64) return pcg_begin<double, double>(g, r->f, r->u, r->o, s);
+  return pcg_begin<float, double>(g, r->f, r->u, r->o, s);
+}
+
+void finish_ticket(ell_batch *b, Request *r) {
+  std::lock_guard<std::mutex> lk(b->mu);
+  auto it = b->tickets.find(r->ticket);
+  if (it != b->tickets.end()) it->second.remaining--;
+  r->g->busy = 0;
+  b->cv_done.notify_all();
+}
+
+void worker_loop(ell_batch *b) {
+  hipStream_t s = b->stream;
+  for (;;) {
+    std::vector<Request *> admit;
+    {
+      std::unique_lock<std::mutex> lk(b->mu);
+      b->cv.wait(lk, [&] { return b->stop || !b->queue.empty() || !b->active.empty(); });
+      if (b->stop && b->queue.empty() && b->active.empty()) return;
+      // admit every queued request whose grid is idle (FIFO per grid)
+      for (auto it = b->queue.begin(); it != b->queue.end();) {
+        if (!(*it)->g->busy) {
+          (*it)->g->busy = 1;
+          admit.push_back(*it);
+          it = b->queue.erase(it);
+        } else {
+          ++it;
+        }
+      }
+    }
+    int rc = ELL_OK;
+    for (Request *r : admit) {
+      rc = request_begin(r, s);
+      if (rc != ELL_OK) {
+        r->rc = rc;
+        finish_ticket(b, r);
+        continue;
+      }
+      b->active.push_back(r);
+      b->dirty = true;
+    }
+    if (b->active.empty()) continue;
+    if (b->dirty && (rc = batch_build(b)) != ELL_OK) {
+      for (Request *r : b->active) {
+        r->rc = rc;
+        finish_ticket(b, r);
+      }
+      b->active.clear();
+      continue;
+    }
+    for (int k = 0; k < b->poll_every && rc == ELL_OK; ++k) rc = batch_step(b);
+    // gather the states of the active grids with one copy
+    const int n = (int)b->active.size();
+    if (rc == ELL_OK) {
+      const Stage *fin = nullptr;
+      for (const Stage &st : b->stages)
+        if (st.kind == Stage::FINALIZE) { fin = &st; break; }
+      kb_gather_states<<<(n + 63) / 64, 64, 0, s>>>(b->d_ents + fin->off, n, b->d_states);
+      rc = check_launch("kb_gather_states");
+      if (rc == ELL_OK && hipMemcpyAsync(b->h_states, b->d_states, n * sizeof(PcgState), hipMemcpyDeviceToHost,
+                                         s) != hipSuccess)
+        rc = fail(ELL_ERR_HIP, "state copy failed");
+      if (rc == ELL_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(ELL_ERR_HIP, "batch step failed");
+    }
+    std::vector<Request *> still;
+    for (int i = 0; i < n; ++i) {
+      Request *r = b->active[i];
+      if (rc != ELL_OK) {
+        r->rc = rc;
+        finish_ticket(b, r);
+        continue;
+      }
+      const PcgState &h = b->h_states[i];
+      if (h.done) {
+        *r->g->st_host = h;
+        r->rc = pcg_finish(r->g, r->f, r->u, &r->st, s);
+        finish_ticket(b, r);
+      } else {
+        still.push_back(r);
+      }
+    }
+    if (still.size() != b->active.size()) b->dirty = true;
+    b->active.swap(still);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int ell_batch_create(size_t hbm_budget_bytes, ell_batch **out) {
+  if (!out) return fail(ELL_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  ell_batch *b = new ell_batch();
+  b->budget = hbm_budget_bytes;
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete b;
+    return fail(ELL_ERR_HIP, "stream creation failed");
+  }
+  b->worker = std::thread(worker_loop, b);
+  *out = b;
+  return ELL_OK;
+}
+
+int ell_batch_grid(ell_batch *b, const ell_grid_desc *desc, ell_grid **out) {
+  if (!b || !desc || !out) return fail(ELL_ERR_INVALID, "NULL argument");
+  *out = nullptr;
+  int L = 0;
+  CHK(validate(desc, &L));
+  const size_t need = grid_bytes(desc, L) + sizeof(GridDev);
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    if (b->used + need > b->budget)
+      return fail(ELL_ERR_BUDGET, "grid needs %zu bytes, %zu of %zu in use", need, b->used, b->budget);
+    if (b->prec != -1 && (b->prec == ELL_FP64) != (desc->precision == ELL_FP64))
+      return fail(ELL_ERR_INVALID, "all grids of a batch use FP64 or all use the FP32 preconditioner");
+  }
+  ell_grid *g = nullptr;
+  CHK(grid_create(desc, true, &g));
+  std::string why;
+  if (!batch_capable(g, &why)) {
+    ell_grid_destroy(g);
+    return fail(ELL_ERR_INVALID, "%s", why.c_str());
+  }
+  int rc = grid_dev_build(g);
+  if (rc != ELL_OK) {
+    ell_grid_destroy(g);
+    return rc;
+  }
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->used += need;
+    b->grids.push_back(g);
+    if (b->prec == -1) b->prec = desc->precision == ELL_FP64 ? ELL_FP64 : ELL_FP32_PRECOND;
+  }
+  *out = g;
+  return ELL_OK;
+}
+
+int ell_batch_release(ell_batch *b, ell_grid *g) {
+  if (!b || !g) return fail(ELL_ERR_INVALID, "NULL argument");
+  std::lock_guard<std::mutex> lk(b->mu);
+  auto it = std::find(b->grids.begin(), b->grids.end(), g);
+  if (it == b->grids.end()) return fail(ELL_ERR_INVALID, "grid does not belong to this batch");
+  if (g->busy) return fail(ELL_ERR_INVALID, "grid is in use");
+  for (Request *r : b->queue)
+    if (r->g == g) return fail(ELL_ERR_INVALID, "grid has queued requests");
+  int L = g->L;
+  b->used -= grid_bytes(&g->d, L) + sizeof(GridDev);
+  b->grids.erase(it);
+  ell_grid_destroy(g);
+  return ELL_OK;
+}
+
+size_t ell_batch_bytes_in_use(const ell_batch *b) { return b ? b->used : 0; }
+
+int ell_batch_submit(ell_batch *b, int32_t n, ell_grid *const *grids, const double *const *f, double *const *u,
+                     const ell_solve_opts *opts, uint64_t *ticket_out) {
+  if (!b || n <= 0 || !grids || !f || !u || !ticket_out) return fail(ELL_ERR_INVALID, "bad arguments");
+  ell_solve_opts o;
+  if (opts) o = *opts;
+  else o = ell_solve_opts{1e-5, 0.0, 500, 1, 0, 4};
+  if (o.maxiter <= 0 || !(o.rtol >= 0) || !(o.atol >= 0)) return fail(ELL_ERR_INVALID, "bad solve options");
+  std::lock_guard<std::mutex> lk(b->mu);
+  for (int i = 0; i < n; ++i) {
+    if (std::find(b->grids.begin(), b->grids.end(), grids[i]) == b->grids.end())
+      return fail(ELL_ERR_INVALID, "grid %d was not created by ell_batch_grid on this batch", i);
+    if (!f[i] || !u[i]) return fail(ELL_ERR_INVALID, "NULL vector");
+  }
+  const uint64_t t = b->next_ticket++;
+  Ticket tk;
+  tk.remaining = n;
+  for (int i = 0; i < n; ++i) {
+    Request *r = new Request();
+    r->ticket = t;
+    r->g = grids[i];
+    r->f = f[i];
+    r->u = u[i];
+    r->o = o;
+    tk.reqs.push_back(r);
+    b->queue.push_back(r);
+  }
+  if (o.poll_every > 0) b->poll_every = o.poll_every;
+  b->tickets.emplace(t, std::move(tk));
+  *ticket_out = t;
+  b->cv.notify_all();
+  return ELL_OK;
+}
+
+static int ticket_result(ell_batch *b, Ticket &tk, ell_solve_stats *stats) {
+  int rc = ELL_OK;
+  for (size_t i = 0; i < tk.reqs.size(); ++i) {
+    Request *r = tk.reqs[i];
+    if (stats) stats[i] = r->st;
+    if (r->rc < 0 && (rc >= 0)) rc = r->rc;
+    else if (r->rc == ELL_NOT_CONVERGED && rc == ELL_OK) rc = ELL_NOT_CONVERGED;
+  }
+  return rc;
+}
+
+int ell_batch_poll(ell_batch *b, uint64_t ticket, ell_solve_stats *stats) {
+  if (!b) return fail(ELL_ERR_INVALID, "NULL batch");
+  std::lock_guard<std::mutex> lk(b->mu);
+  auto it = b->tickets.find(ticket);
+  if (it == b->tickets.end()) return fail(ELL_ERR_INVALID, "unknown ticket");
+  if (it->second.remaining > 0) return ELL_PENDING;
+  return ticket_result(b, it->second, stats);
+}
+
+int ell_batch_wait(ell_batch *b, uint64_t ticket, ell_solve_stats *stats) {
+  if (!b) return fail(ELL_ERR_INVALID, "NULL batch");
+  std::unique_lock<std::mutex> lk(b->mu);
+  auto it = b->tickets.find(ticket);
+  if (it == b->tickets.end()) return fail(ELL_ERR_INVALID, "unknown ticket");
+  b->cv_done.wait(lk, [&] { return it->second.remaining <= 0; });
+  const int rc = ticket_result(b, it->second, stats);
+  for (Request *r : it->second.reqs) delete r;
+  b->tickets.erase(it);
+  if (rc < 0) return fail(rc, "a solve of the batch failed");
+  return rc;
+}
+
+int ell_batch_destroy(ell_batch *b) {
+  if (!b) return ELL_OK;
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    b->stop = true;
+    b->cv.notify_all();
+  }
+  if (b->worker.joinable()) b->worker.join();
+  for (auto &kv : b->tickets)
+    for (Request *r : kv.second.reqs) delete r;
+  for (ell_grid *g : b->grids) ell_grid_destroy(g);
+  if (b->d_ents) (void)hipFree(b->d_ents);
+  if (b->h_ents) (void)hipHostFree(b->h_ents);
+  if (b->d_states) (void)hipFree(b->d_states);
+  if (b->h_states) (void)hipHostFree(b->h_states);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+  return ELL_OK;
+}
+
+}  // extern "C"

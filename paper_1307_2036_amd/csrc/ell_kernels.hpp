@@ -241,17 +241,17 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ 
 // TB: element type of b (the FP32 preconditioner reads the FP64 CG residual
 // directly on the finest level).
 template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG, typename TB = R>
-__global__ __launch_bounds__(NSEG * 64) void k_smooth_seg(Geo L, const R *__restrict__ tab, int c,
+__device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab, int c,
                                                           const TB *__restrict__ bo,
                                                           const R *__restrict__ uo,
                                                           R *__restrict__ own, R rho,
-                                                          const int *__restrict__ done) {
+                                                          const int *__restrict__ done, int lb, int nblocks) {
   __shared__ R xch[NSEG][kSegCols];
   if (is_done(done)) return;
   const int lane = threadIdx.x & 63;
   const int sg = wave_id();
   const int ncol = c ? L.ncol1 : L.ncol0;
-  const int m = logical_block() * kSegCols + lane;
+  const int m = lb * kSegCols + lane;
   const bool valid = m < ncol;
   const int mm = valid ? m : ncol - 1;  // in-bounds column for loads of idle lanes
   const int nz = L.nz, Ls = seg_len(nz, NSEG);
@@ -355,6 +355,15 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg(Geo L, const R *__rest
   }
 }
 
+template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG, typename TB = R>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_seg(Geo L, const R *__restrict__ tab, int c,
+                                                          const TB *__restrict__ bo,
+                                                          const R *__restrict__ uo,
+                                                          R *__restrict__ own, R rho,
+                                                          const int *__restrict__ done) {
+  smooth_seg_body<R, ZERO, RHO1, FINE, SEG, NSEG, TB>(L, tab, c, bo, uo, own, rho, done, logical_block(), gridDim.x);
+}
+
 // Residual (b - A u) of one cell given its column neighbours at level k.
 template <typename R>
 __device__ __forceinline__ R cell_residual(R bk, R vk, R txk, R tyk, R tzlo, R tzhi, R uc, R um,
@@ -384,15 +393,15 @@ __device__ __forceinline__ R cell_residual(R bk, R vk, R txk, R tyk, R tzlo, R t
 // Requires both horizontal directions to have faces.
 // -------------------------------------------------------------------------
 template <typename R, typename TB = R>
-__global__ __launch_bounds__(kBlock) void k_resid_restrict_bz(Geo F, Geo C,
+__device__ __forceinline__ void resid_restrict_bz_body(Geo F, Geo C,
                                                               const R *__restrict__ tab,
                                                               const TB *__restrict__ b,
                                                               const R *__restrict__ u,
                                                               R *__restrict__ bc,
-                                                              const int *__restrict__ done) {
+                                                              const int *__restrict__ done, int lb, int nblocks) {
   constexpr int U = 4;
   if (is_done(done)) return;
-  const int gid = logical_block() * kSegCols + (threadIdx.x & 63);
+  const int gid = lb * kSegCols + (threadIdx.x & 63);
   if (gid >= 2 * C.H) return;
   const int cc = gid & 1;  // lanes alternate coarse colours (adjacent coarse columns)
   const int mc = gid >> 1;
@@ -460,6 +469,16 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict_bz(Geo F, Geo C,
     const long long op = (long long)min(k + 1, nz - 1) * H;
     step(k, (R)b0[o], (R)b1[o], u0[op], u1[op], pA[o], pB[o], pC[o], pD[o], pE[o], pF[o]);
   }
+}
+
+template <typename R, typename TB = R>
+__global__ __launch_bounds__(kBlock) void k_resid_restrict_bz(Geo F, Geo C,
+                                                              const R *__restrict__ tab,
+                                                              const TB *__restrict__ b,
+                                                              const R *__restrict__ u,
+                                                              R *__restrict__ bc,
+                                                              const int *__restrict__ done) {
+  resid_restrict_bz_body<R, TB>(F, C, tab, b, u, bc, done, logical_block(), gridDim.x);
 }
 
 // -------------------------------------------------------------------------
@@ -544,11 +563,11 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Geo F, Geo C, const R
 // MODE 1: piecewise constant.  RED_ONLY: colour-0 fine columns only.
 // -------------------------------------------------------------------------
 template <typename R, bool RED_ONLY, int MODE>
-__global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__restrict__ uc,
+__device__ __forceinline__ void prolong_body(Geo F, Geo C, const R *__restrict__ uc,
                                                     R *__restrict__ u,
-                                                    const int *__restrict__ done) {
+                                                    const int *__restrict__ done, int lb, int nblocks) {
   if (is_done(done)) return;
-  const int gid = logical_block() * kSegCols + (threadIdx.x & 63);
+  const int gid = lb * kSegCols + (threadIdx.x & 63);
   int c, m;
   if (RED_ONLY) {
     c = 0;
@@ -607,16 +626,23 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__res
   }
 }
 
+template <typename R, bool RED_ONLY, int MODE>
+__global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__restrict__ uc,
+                                                    R *__restrict__ u,
+                                                    const int *__restrict__ done) {
+  prolong_body<R, RED_ONLY, MODE>(F, C, uc, u, done, logical_block(), gridDim.x);
+}
+
 // Colour-0 prolongation from an FP32 hierarchy into the FP64 output of the
 // finest level: out = base + P uc on colour-0 columns (base: the FP32
 // pre-smoothed iterate).  Bilinear weights as in k_prolong.
 template <typename R, typename TO, int MODE>
-__global__ __launch_bounds__(kBlock) void k_prolong_out(Geo F, Geo C, const R *__restrict__ uc,
+__device__ __forceinline__ void prolong_out_body(Geo F, Geo C, const R *__restrict__ uc,
                                                         const R *__restrict__ base,
                                                         TO *__restrict__ out,
-                                                        const int *__restrict__ done) {
+                                                        const int *__restrict__ done, int lb, int nblocks) {
   if (is_done(done)) return;
-  const int m = logical_block() * kSegCols + (threadIdx.x & 63);
+  const int m = lb * kSegCols + (threadIdx.x & 63);
   if (m >= F.ncol0) return;
   const int Ls = seg_len(F.nz);
   const int k0 = min(wave_id() * Ls, F.nz), k1 = min(k0 + Ls, F.nz);
@@ -646,6 +672,14 @@ __global__ __launch_bounds__(kBlock) void k_prolong_out(Geo F, Geo C, const R *_
     }
     ow[(long long)k * HF] = (TO)bs[(long long)k * HF] + (TO)e;
   }
+}
+
+template <typename R, typename TO, int MODE>
+__global__ __launch_bounds__(kBlock) void k_prolong_out(Geo F, Geo C, const R *__restrict__ uc,
+                                                        const R *__restrict__ base,
+                                                        TO *__restrict__ out,
+                                                        const int *__restrict__ done) {
+  prolong_out_body<R, TO, MODE>(F, C, uc, base, out, done, logical_block(), gridDim.x);
 }
 
 // -------------------------------------------------------------------------
@@ -755,14 +789,14 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ t
 // formed from z and p_old exactly as their owning lanes form them.
 // -------------------------------------------------------------------------
 template <typename Z, int NSEG>
-__global__ __launch_bounds__(kBlock) void k_apply_dir(Geo L, const double *__restrict__ tab,
+__device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__ tab,
                                                       const Z *__restrict__ z,
                                                       const double *__restrict__ pold,
                                                       double *__restrict__ pnew,
                                                       double *__restrict__ q,
                                                       double *__restrict__ u,
                                                       const PcgState *__restrict__ st, int first,
-                                                      int defer_u, double *__restrict__ partial) {
+                                                      int defer_u, double *__restrict__ partial, int lb, int nblocks) {
   constexpr int U = 4;
   constexpr int CH = 4 / NSEG;
   __shared__ double sh[4];
@@ -771,7 +805,7 @@ __global__ __launch_bounds__(kBlock) void k_apply_dir(Geo L, const double *__res
   const double alpha = st->alpha;
   const int w = wave_id();
   const int sg = w / CH;
-  const int slot = (logical_block() * CH + (w % CH)) * kSegCols + (threadIdx.x & 63);
+  const int slot = (lb * CH + (w % CH)) * kSegCols + (threadIdx.x & 63);
   const int c = slot & 1;
   const int m = slot >> 1;
   const bool valid = slot < 2 * L.H && m < (c ? L.ncol1 : L.ncol0);
@@ -851,19 +885,31 @@ __global__ __launch_bounds__(kBlock) void k_apply_dir(Geo L, const double *__res
     }
   }
   const double s = block_sum(dot, sh);
-  if (threadIdx.x == 0) partial[logical_block()] = s;
+  if (threadIdx.x == 0) partial[lb] = s;
+}
+
+template <typename Z, int NSEG>
+__global__ __launch_bounds__(kBlock) void k_apply_dir(Geo L, const double *__restrict__ tab,
+                                                      const Z *__restrict__ z,
+                                                      const double *__restrict__ pold,
+                                                      double *__restrict__ pnew,
+                                                      double *__restrict__ q,
+                                                      double *__restrict__ u,
+                                                      const PcgState *__restrict__ st, int first,
+                                                      int defer_u, double *__restrict__ partial) {
+  apply_dir_body<Z, NSEG>(L, tab, z, pold, pnew, q, u, st, first, defer_u, partial, logical_block(), gridDim.x);
 }
 
 // r <- r - alpha q, partial sums of ||r||^2
-__global__ __launch_bounds__(kBlock) void k_update_r(double2 *__restrict__ r,
+__device__ __forceinline__ void update_r_body(double2 *__restrict__ r,
                                                      const double2 *__restrict__ q, long long n2,
                                                      const PcgState *__restrict__ st,
-                                                     double *__restrict__ partial) {
+                                                     double *__restrict__ partial, int lb, int nblocks) {
   __shared__ double sh[4];
   if (st->done) return;
   const double alpha = st->alpha;
-  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
-  const long long stride = (long long)gridDim.x * kBlock;
+  const long long t = (long long)lb * kBlock + threadIdx.x;
+  const long long stride = (long long)nblocks * kBlock;
   double rr = 0.0;
   for (long long e = t; e < n2; e += stride) {
     const double2 qv = q[e];
@@ -874,7 +920,14 @@ __global__ __launch_bounds__(kBlock) void k_update_r(double2 *__restrict__ r,
     rr += rv.x * rv.x + rv.y * rv.y;
   }
   const double s = block_sum(rr, sh);
-  if (threadIdx.x == 0) partial[logical_block()] = s;
+  if (threadIdx.x == 0) partial[lb] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_r(double2 *__restrict__ r,
+                                                     const double2 *__restrict__ q, long long n2,
+                                                     const PcgState *__restrict__ st,
+                                                     double *__restrict__ partial) {
+  update_r_body(r, q, n2, st, partial, logical_block(), gridDim.x);
 }
 
 // u <- u + alpha p (the last step's deferred solution update)
@@ -1013,15 +1066,15 @@ template <> struct Vec2<float> { using T = float2; };
 
 // partial sums of <r, z> and <z, q>
 template <typename Z>
-__global__ __launch_bounds__(kBlock) void k_dots(const double2 *__restrict__ r,
+__device__ __forceinline__ void dots_body(const double2 *__restrict__ r,
                                                  const typename Vec2<Z>::T *__restrict__ z,
                                                  const double2 *__restrict__ q, long long n2,
                                                  const PcgState *__restrict__ st,
-                                                 double *__restrict__ partial) {
+                                                 double *__restrict__ partial, int lb, int nblocks) {
   __shared__ double sh[4];
   if (st->done) return;
-  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
-  const long long stride = (long long)gridDim.x * kBlock;
+  const long long t = (long long)lb * kBlock + threadIdx.x;
+  const long long stride = (long long)nblocks * kBlock;
   double rz = 0.0, zq = 0.0;
   for (long long e = t; e < n2; e += stride) {
     const double2 rv = r[e], qv = q[e];
@@ -1033,9 +1086,18 @@ __global__ __launch_bounds__(kBlock) void k_dots(const double2 *__restrict__ r,
   const double s0 = block_sum(rz, sh);
   const double s1 = block_sum(zq, sh);
   if (threadIdx.x == 0) {
-    partial[2 * logical_block()] = s0;
-    partial[2 * logical_block() + 1] = s1;
+    partial[2 * lb] = s0;
+    partial[2 * lb + 1] = s1;
   }
+}
+
+template <typename Z>
+__global__ __launch_bounds__(kBlock) void k_dots(const double2 *__restrict__ r,
+                                                 const typename Vec2<Z>::T *__restrict__ z,
+                                                 const double2 *__restrict__ q, long long n2,
+                                                 const PcgState *__restrict__ st,
+                                                 double *__restrict__ partial) {
+  dots_body<Z>(r, z, q, n2, st, partial, logical_block(), gridDim.x);
 }
 
 // p <- z + beta p (p <- z on the first iteration)
@@ -1067,9 +1129,9 @@ enum FinalizeMode : int { F_INIT = 0, F_KAPPA = 1, F_ALPHA = 2, F_CONV = 3, F_BE
 
 // One block: reduce nq interleaved partial sums over nblk blocks in a fixed
 // order and advance the CG scalars (Appendix B, Alg. PCG).
-__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partial, int nblk,
+__device__ __forceinline__ void finalize_body(const double *__restrict__ partial, int nblk,
                                                      int nq, PcgState *__restrict__ st, int mode,
-                                                     double rtol, double atol, int rel_to_rhs) {
+                                                     double rtol, double atol, int rel_to_rhs, int lb, int nblocks) {
   __shared__ double sh[4];
   __shared__ double tot[2];
   if (mode != F_TRUE && mode != F_INIT && st->done) return;
@@ -1134,6 +1196,12 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ 
       st->true_r_norm = sqrt(tot[nq - 1]);
       break;
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ partial, int nblk,
+                                                     int nq, PcgState *__restrict__ st, int mode,
+                                                     double rtol, double atol, int rel_to_rhs) {
+  finalize_body(partial, nblk, nq, st, mode, rtol, atol, rel_to_rhs, logical_block(), gridDim.x);
 }
 
 }  // namespace ell

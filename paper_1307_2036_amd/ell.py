@@ -55,7 +55,9 @@ EXPORTS = ["ell_grid_create", "ell_grid_destroy", "ell_grid_bytes", "ell_grid_le
            "ell_apply_A", "ell_vcycle", "ell_pcg_solve", "ell_level_elems", "ell_to_split",
            "ell_from_split", "ell_level_smooth", "ell_level_resid_restrict",
            "ell_level_prolong_add", "ell_level_apply", "ell_profile_enable", "ell_profile_read",
-           "ell_profile_times", "ell_level_layout", "ell_set_tuning", "ell_last_error"]
+           "ell_profile_times", "ell_level_layout", "ell_set_tuning", "ell_last_error",
+           "ell_batch_create", "ell_batch_grid", "ell_batch_release", "ell_batch_bytes_in_use",
+           "ell_batch_submit", "ell_batch_poll", "ell_batch_wait", "ell_batch_destroy"]
 
 _lib = None
 
@@ -92,8 +94,19 @@ def load_library(path: str = LIB_PATH):
     L.ell_level_layout.argtypes = [vp, i32] + [ctypes.POINTER(ctypes.c_int64)] * 3
     L.ell_set_tuning.argtypes = [i32, i32]
     L.ell_last_error.restype = ctypes.c_char_p
+    L.ell_batch_create.argtypes = [ctypes.c_size_t, ctypes.POINTER(vp)]
+    L.ell_batch_grid.argtypes = [vp, ctypes.POINTER(GridDesc), ctypes.POINTER(vp)]
+    L.ell_batch_release.argtypes = [vp, vp]
+    L.ell_batch_bytes_in_use.argtypes = [vp]
+    L.ell_batch_bytes_in_use.restype = ctypes.c_size_t
+    L.ell_batch_submit.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                   ctypes.POINTER(vp), ctypes.POINTER(SolveOpts),
+                                   ctypes.POINTER(ctypes.c_uint64)]
+    L.ell_batch_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(SolveStats)]
+    L.ell_batch_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(SolveStats)]
+    L.ell_batch_destroy.argtypes = [vp]
     for name in EXPORTS:
-        if name not in ("ell_grid_bytes", "ell_level_elems", "ell_last_error"):
+        if name not in ("ell_grid_bytes", "ell_level_elems", "ell_last_error", "ell_batch_bytes_in_use"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -287,3 +300,95 @@ class Grid:
         got = load_library().ell_profile_times(self._h, family, buf, n)
         _check(0 if got >= 0 else got)
         return np.frombuffer(buf, dtype=np.float32, count=n).astype(np.float64)
+
+
+class BatchGrid(Grid):
+    """A grid owned by a Batch (created with the batch's uniform layout)."""
+
+    def __init__(self, batch: "Batch", nx, ny, nz, hx, hy, omega2, dz, lambda2, n_levels=0, nu_pre=1,
+                 nu_post=1, nu_coarse=1, rho=1.0, prolong=0, precision="fp64"):
+        L = load_library()
+        d, keep = make_desc(nx, ny, nz, hx, hy, omega2, dz, lambda2, n_levels, nu_pre, nu_post,
+                            nu_coarse, rho, prolong, precision)
+        h = ctypes.c_void_p()
+        _check(L.ell_batch_grid(batch._h, ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self._batch = batch
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.precision = d.precision
+        self.levels = L.ell_grid_levels(h)
+        self.bytes = int(L.ell_grid_bytes(ctypes.byref(d)))
+
+    def close(self):
+        if getattr(self, "_h", None) and getattr(self._batch, "_h", None):
+            load_library().ell_batch_release(self._batch._h, self._h)
+        self._h = None
+
+
+class Batch:
+    """Grouped-launch batch engine with continuous admission (see ell.h)."""
+
+    def __init__(self, hbm_budget_bytes: int):
+        h = ctypes.c_void_p()
+        _check(load_library().ell_batch_create(int(hbm_budget_bytes), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def grid(self, p=None, precision="fp64", **kw) -> BatchGrid:
+        if p is not None:
+            args = dict(nx=p.nx, ny=p.ny, nz=p.nz, hx=p.hx, hy=p.hy, omega2=p.omega2, dz=p.dz,
+                        lambda2=p.lambda2, n_levels=p.n_levels, nu_pre=p.nu_pre,
+                        nu_post=p.nu_post, nu_coarse=p.nu_coarse, rho=p.rho, prolong=p.prolong)
+            args.update(kw)
+            kw = args
+        return BatchGrid(self, precision=precision, **kw)
+
+    def bytes_in_use(self) -> int:
+        return int(load_library().ell_batch_bytes_in_use(self._h))
+
+    def submit(self, grids, fs, us, rtol=1e-5, atol=0.0, maxiter=500, flexible=True,
+               rel_to_rhs=False, poll_every=4) -> int:
+        n = len(grids)
+        assert len(fs) == n and len(us) == n
+        G = (ctypes.c_void_p * n)(*[g._h for g in grids])
+        F = (ctypes.c_void_p * n)(*[_dev(f).value for f in fs])
+        U = (ctypes.c_void_p * n)(*[_dev(u).value for u in us])
+        o = SolveOpts(rtol, atol, maxiter, int(flexible), int(rel_to_rhs), poll_every)
+        t = ctypes.c_uint64()
+        # the engine reads the vectors on its own stream: make them ready first
+        torch.cuda.current_stream().synchronize()
+        _check(load_library().ell_batch_submit(self._h, n, G, F, U, ctypes.byref(o), ctypes.byref(t)))
+        self._keep[t.value] = (fs, us, n)
+        return t.value
+
+    def _stats(self, buf, n):
+        return [Stats(s.iters, s.status, s.r0_norm, s.r_norm, s.true_r_norm, s.b_norm) for s in buf[:n]]
+
+    def poll(self, ticket: int):
+        n = self._keep[ticket][2]
+        buf = (SolveStats * n)()
+        rc = load_library().ell_batch_poll(self._h, ticket, buf)
+        if rc == ELL_PENDING:
+            return None
+        _check(rc, allow=(ELL_OK, ELL_NOT_CONVERGED))
+        return self._stats(buf, n)
+
+    def wait(self, ticket: int, check=True):
+        n = self._keep[ticket][2]
+        buf = (SolveStats * n)()
+        rc = load_library().ell_batch_wait(self._h, ticket, buf)
+        self._keep.pop(ticket, None)
+        if check:
+            _check(rc, allow=(ELL_OK, ELL_NOT_CONVERGED))
+        return self._stats(buf, n)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ell_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,144 @@
+"""Batch engine: grouped launches over uneven grids with continuous
+admission.  Every result must equal the same solve alone (bitwise: each grid
+keeps its own deterministic reductions and the same kernels) and match the
+oracle like a single-grid solve."""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1307_2036_amd import inputs as I
+from solve_parity import check_solve
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def problems():
+    # uneven sizes and depths: 64 (7 levels), 96 (5), 128 (8), 32 (6)
+    return [I.graded_problem("b0", 64, 32, 1e-2, 31, 32),
+            I.graded_problem("b1", 96, 24, 3e-2, 33, 34),
+            I.graded_problem("b2", 128, 16, 1e-3, 35, 36),
+            I.graded_problem("b3", 32, 40, 1e-1, 37, 38),
+            I.graded_problem("b4", 64, 24, 5e-2, 39, 40, n_levels=4, nu_coarse=5)]
+
+
+@pytest.fixture(scope="module")
+def E():
+    from paper_1307_2036_amd import ell
+    return ell
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_alone_equals_in_mix_and_oracle(E, orc, precision):
+    ps = problems()
+    B = E.Batch(8 << 30)
+    grids = [B.grid(p, precision=precision) for p in ps]
+    fs = [dev(p.f) for p in ps]
+    # the mix: all five together
+    us = [torch.zeros_like(f) for f in fs]
+    st_mix = B.wait(B.submit(grids, fs, us))
+    mix = [host(u) for u in us]
+    # each alone
+    for i, (g, f) in enumerate(zip(grids, fs)):
+        u1 = torch.zeros_like(f)
+        st1 = B.wait(B.submit([g], [f], [u1]))
+        assert st1[0].iters == st_mix[i].iters
+        np.testing.assert_array_equal(host(u1), mix[i])
+    # against the oracle (FP64 path; the mixed path as in the mixed-precision tests)
+    for i, p in enumerate(ps):
+        assert st_mix[i].status == 0
+        g = orc.Grid.from_problem(p)
+        if precision == "fp64":
+            check_solve(orc, g, p.f, mix[i], st_mix[i], p.rtol)
+        else:
+            u64, s64 = orc.pcg(g, p.f, rtol=p.rtol)
+            assert st_mix[i].iters <= s64["iters"] + 2
+            assert np.linalg.norm(mix[i] - u64) <= 1e-4 * np.linalg.norm(u64)
+    B.close()
+
+
+def test_batch_matches_single_grid_path(E, orc):
+    """The batch (uniform 4-segment layout, grouped kernels) and the single-grid
+    path solve the same problem to the same iterates."""
+    p = problems()[1]
+    B = E.Batch(4 << 30)
+    g = B.grid(p)
+    f = dev(p.f)
+    u = torch.zeros_like(f)
+    st = B.wait(B.submit([g], [f], [u]))[0]
+    G = E.Grid.from_problem(p)
+    u2, st2 = G.pcg_solve(f, rtol=p.rtol)
+    assert st.iters == st2.iters
+    assert np.linalg.norm(host(u) - host(u2)) <= 1e-12 * np.linalg.norm(host(u2))
+    B.close()
+
+
+def test_continuous_admission_and_warm_start(E, orc):
+    """A ticket submitted while another runs joins the running iterations; two
+    requests on one grid run one after the other (the second warm-starts)."""
+    ps = problems()
+    B = E.Batch(8 << 30)
+    grids = [B.grid(p) for p in ps]
+    fs = [dev(p.f) for p in ps]
+    us = [torch.zeros_like(f) for f in fs]
+    t1 = B.submit(grids[:3], fs[:3], us[:3], rel_to_rhs=True)
+    u_late = torch.zeros_like(fs[3])
+    t2 = B.submit([grids[3]], [fs[3]], [u_late], rel_to_rhs=True)
+    # same grid again: queued behind t1's request on grid 0, warm start from its result
+    t3 = B.submit([grids[0]], [fs[0]], [us[0]], rel_to_rhs=True)
+    s1, s2, s3 = B.wait(t1), B.wait(t2), B.wait(t3)
+    assert all(s.status == 0 for s in s1 + s2 + s3)
+    assert s3[0].iters == 0  # already converged relative to ||b||
+    g = orc.Grid.from_problem(ps[3])
+    u_ref, st_ref = orc.pcg(g, ps[3].f, rtol=ps[3].rtol, rel_to_rhs=True)
+    assert np.linalg.norm(host(u_late) - u_ref) <= 1e-6 * np.linalg.norm(u_ref)
+    B.close()
+
+
+def test_budget_and_validation(E):
+    p = problems()[0]
+    need = E.grid_bytes(nx=p.nx, ny=p.ny, nz=p.nz, hx=p.hx, hy=p.hy, omega2=p.omega2, dz=p.dz,
+                        lambda2=p.lambda2)
+    B = E.Batch(int(1.5 * need))
+    g = B.grid(p)
+    with pytest.raises(E.EllError) as ei:
+        B.grid(p)
+    assert ei.value.code == E.ELL_ERR_BUDGET
+    used = B.bytes_in_use()
+    g.close()
+    assert B.bytes_in_use() < used
+    g2 = B.grid(p)  # fits again after the release
+    with pytest.raises(E.EllError):
+        B.grid(p, precision="fp32")  # mixed precision classes in one batch
+    B.close()
+    B2 = E.Batch(1 << 30)
+    with pytest.raises(E.EllError):
+        B2.grid(p, rho=0.9)
+    B2.close()
+
+
+def test_poll_pending_then_done(E):
+    p = problems()[2]
+    B = E.Batch(4 << 30)
+    g = B.grid(p)
+    f = dev(p.f)
+    u = torch.zeros_like(f)
+    t = B.submit([g], [f], [u])
+    deadline = time.time() + 60
+    res = None
+    while res is None and time.time() < deadline:
+        res = B.poll(t)
+        time.sleep(0.001)
+    assert res is not None and res[0].status == 0
+    B.wait(t)
+    B.close()
