@@ -33,6 +33,12 @@ def parse():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--nu-coarse", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="c1", choices=["c1", "batch", "serve"],
+                    help="c1: the 512^2x128 solve (default); batch: 64 uneven solves in the "
+                         "batch engine vs sequential FP64; serve: Poisson request stream")
+    ap.add_argument("--serve-seconds", type=float, default=8.0)
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="arrival rate as a fraction of the measured closed-loop capacity")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run one plain device copy of a 268 MB vector (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -79,6 +85,10 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
+    if a.workload == "batch":
+        return bench_batch(a)
+    if a.workload == "serve":
+        return bench_serve(a)
     import numpy as np
     import torch
 
@@ -173,6 +183,206 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, iters, a.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def _seq_fp64(problems, fs):
+    """Plain FP64 single-grid solves one after another (the baseline)."""
+    import torch
+    from paper_1307_2036_amd import ell
+    grids = [ell.Grid.from_problem(p) for p in problems]
+    us = [torch.zeros_like(f) for f in fs]
+    for g, f, u in zip(grids, fs, us):  # warm-up pass
+        u.zero_()
+        g.pcg_solve(f, u, rtol=1e-5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = []
+    for g, f, u in zip(grids, fs, us):
+        u.zero_()
+        _, st = g.pcg_solve(f, u, rtol=1e-5)
+        iters.append(st.iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for g in grids:
+        g.close()
+    return len(problems) / dt, iters
+
+
+def bench_batch(a):
+    """64 uneven solves (nx in {64..256}, nz in {64, 96, 128}, log-uniform omega^2)
+    advanced together by the batch engine with the FP32 preconditioner; one step
+    = all 64 solves from u0 = 0 to 1e-5."""
+    import numpy as np
+    import torch
+    from paper_1307_2036_amd import ell, inputs
+    torch.cuda.set_device(0)
+    ps = inputs.config3_instances(64)
+    fs = [torch.from_numpy(p.f).cuda() for p in ps]
+    n_total = sum(p.n for p in ps)
+    prec = "fp32" if a.precision == "fp64" else a.precision
+    B = ell.Batch(200 << 30)
+    grids = [B.grid(p, precision=prec) for p in ps]
+    us = [torch.zeros_like(f) for f in fs]
+
+    def step():
+        for u in us:
+            u.zero_()
+        return B.wait(B.submit(grids, fs, us, rtol=1e-5, poll_every=4))
+
+    for _ in range(max(a.warmup, 1)):
+        st = step()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ts = time.perf_counter()
+        st = step()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert all(s.status == 0 for s in st)
+    iters = [s.iters for s in st]
+    solves = len(ps) * a.steps / elapsed
+    seq, seq_iters = _seq_fp64(ps, fs)
+    out = {
+        "metric": METRIC, "value": solves, "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": elapsed / a.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64-outer/f32-vcycle",
+        "data": "synthetic (64 seeded uneven instances)",
+        "config": {"workload": "batch of 64 uneven gmg-pcg solves (nx in {64,96,128,192,256}, "
+                               "nz in {64,96,128}, log-uniform omega2), grouped launches",
+                   "unknowns_total": n_total, "precision": prec},
+        "unknowns_iter_per_s": float(np.sum([p.n * it for p, it in zip(ps, iters)]) * a.steps / elapsed),
+        "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
+        "batch_ms_p50": float(np.percentile(np.array(lat) * 1e3, 50)),
+        "fp64_sequential_solves_per_s": seq, "fp64_sequential_iters_mean": float(np.mean(seq_iters)),
+        "speedup_vs_fp64_sequential": solves / seq,
+    }
+    print(json.dumps(out), flush=True)
+    B.close()
+
+
+def bench_serve(a):
+    """Serving: Poisson arrivals of pressure solves on 24 resident streams
+    (17 x 256^2, 6 x 512^2, 1 x 1024^2, nz = 128; uniform stream choice gives
+    the 70/25/5 % mix), omega^2 in {1e-2, 5e-2}, fresh f ~ N(0,1) per request,
+    warm start from the stream's previous solution, 1e-5 relative to ||b||,
+    200 GB budget, FP32 preconditioner, continuous batching."""
+    import numpy as np
+    import torch
+    from paper_1307_2036_amd import ell, inputs
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng(inputs.seed_for(4))
+    sizes = [256] * 17 + [512] * 6 + [1024]
+    prec = "fp32" if a.precision == "fp64" else a.precision
+    B = ell.Batch(200 << 30)
+    streams = []
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(inputs.seed_for(4, stream=2))
+    for idx, nx in enumerate(sizes):
+        omega2 = float(rng.choice([1e-2, 5e-2]))
+        p = inputs.graded_problem(f"stream{idx}", nx, 128, omega2, inputs.seed_for(4, idx),
+                                  inputs.seed_for(4, idx, stream=1), with_f=False)
+        g = B.grid(p, precision=prec)
+        shape = (p.nz, p.ny, p.nx)
+        w = torch.from_numpy(p.dz).cuda().view(-1, 1, 1)
+        streams.append(dict(p=p, g=g, u=torch.zeros(shape, dtype=torch.float64, device="cuda"),
+                            f=torch.empty(shape, dtype=torch.float64, device="cuda"), w=w))
+
+    def new_rhs(s):
+        f = torch.randn(s["f"].shape, generator=gen, device="cuda", dtype=torch.float64)
+        f -= (f * s["w"]).sum() / (s["w"].sum() * f.shape[1] * f.shape[2])
+        s["f"].copy_(f)
+
+    def run(duration, rate):
+        """rate None: closed loop (every stream always has one request)."""
+        pending = {}
+        done_lat, done_iters = [], []
+        t_start = time.perf_counter()
+        next_arrival = t_start
+        queue_per_stream = [[] for _ in streams]  # arrivals waiting for their stream
+        busy = [False] * len(streams)
+        n_done = 0
+        while True:
+            now = time.perf_counter()
+            if now - t_start > duration:
+                break
+            if rate is None:
+                for i, s in enumerate(streams):
+                    if not busy[i]:
+                        queue_per_stream[i].append(now)
+            else:
+                while next_arrival <= now:
+                    i = int(rng.integers(len(streams)))
+                    queue_per_stream[i].append(next_arrival)
+                    next_arrival += rng.exponential(1.0 / rate)
+            for i, s in enumerate(streams):
+                if not busy[i] and queue_per_stream[i]:
+                    t_arr = queue_per_stream[i].pop(0)
+                    new_rhs(s)
+                    t = B.submit([s["g"]], [s["f"]], [s["u"]], rtol=1e-5, rel_to_rhs=True, poll_every=2)
+                    pending[t] = (i, t_arr)
+                    busy[i] = True
+            for t in list(pending):
+                r = B.poll(t)
+                if r is not None:
+                    i, t_arr = pending.pop(t)
+                    B.wait(t)
+                    done_lat.append(time.perf_counter() - t_arr)
+                    done_iters.append(r[0].iters)
+                    busy[i] = False
+                    n_done += 1
+            time.sleep(0.0002)
+        for t in list(pending):
+            B.wait(t)
+        elapsed = time.perf_counter() - t_start
+        return n_done / elapsed, np.array(done_lat) * 1e3, done_iters
+
+    run(2.0, None)  # warm-up: every stream solved at least once
+    capacity, _, _ = run(a.serve_seconds / 2, None)
+    rate = a.serve_load * capacity
+    thr, lat, iters = run(a.serve_seconds, rate)
+    # plain FP64 sequential baseline on the same GPU: for each size class, a few
+    # requests with the same semantics (fresh f, warm start, 1e-5 of ||b||)
+    # solved one after another with the single-grid FP64 path; mix-weighted
+    classes = {256: 17 / 24, 512: 6 / 24, 1024: 1 / 24}
+    t_class = {}
+    for nx, wgt in classes.items():
+        s0 = next(s for s in streams if s["p"].nx == nx)
+        G = ell.Grid.from_problem(s0["p"])
+        u = torch.zeros_like(s0["u"])
+        new_rhs(s0)
+        G.pcg_solve(s0["f"], u, rtol=1e-5, rel_to_rhs=True)
+        torch.cuda.synchronize()
+        reps, tt = 3, 0.0
+        for _ in range(reps):
+            new_rhs(s0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            G.pcg_solve(s0["f"], u, rtol=1e-5, rel_to_rhs=True)
+            tt += time.perf_counter() - t0
+        t_class[nx] = tt / reps
+        G.close()
+    seq = 1.0 / sum(w * t_class[nx] for nx, w in classes.items())
+    out = {
+        "metric": METRIC, "value": thr, "unit": "solves/s", "n_gpus": 1, "steps": len(lat),
+        "warmup": 0, "ms_per_step": 1e3 / thr if thr else None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64-outer/f32-vcycle",
+        "data": "synthetic (seeded Poisson arrivals, fresh N(0,1) f per request)",
+        "config": {"workload": "serving: 24 streams (17x256^2, 6x512^2, 1x1024^2, nz=128), "
+                               "Poisson arrivals, warm starts, continuous batching, 200 GB budget",
+                   "arrival_rate_per_s": rate, "load": a.serve_load, "precision": prec},
+        "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
+        "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
+        "closed_loop_capacity_solves_per_s": capacity,
+        "iters_mean": float(np.mean(iters)) if iters else None,
+        "hbm_resident_gb": B.bytes_in_use() / 1e9,
+        "fp64_sequential_solves_per_s": seq,
+        "fp64_sequential_ms_by_size": {str(k): v * 1e3 for k, v in t_class.items()},
+        "speedup_vs_fp64_sequential": thr / seq,
+    }
+    print(json.dumps(out), flush=True)
+    B.close()
 
 
 if __name__ == "__main__":
