@@ -74,6 +74,21 @@ inline int flat_blocks(long long n2) {
   return (int)((b + 7) / 8 * 8);
 }
 
+// Blocks of a vector kernel inside a grouped (batched) launch: a fixed chunk of
+// kBatchChunk double2 per thread, so that blocks of grids of every size cost
+// the same and the blocks of one launch spread evenly over the XCDs.
+constexpr int kBatchChunk = 16;
+inline int batch_flat_blocks(long long n2) {
+  const long long b = (n2 + (long long)kBlock * kBatchChunk - 1) / ((long long)kBlock * kBatchChunk);
+  return (int)std::max<long long>(b, 1);
+}
+
+// Blocks whose partial sums one grid's reduction buffer must hold.
+inline long long partial_blocks(long long n0, int H0) {
+  return std::max<long long>(std::max<long long>(seg_blocks(2LL * H0), flat_blocks(n0 / 2)),
+                             batch_flat_blocks(n0 / 2));
+}
+
 bool can_halve(int n) { return n % 2 == 0 && ((n / 2) % 2 == 0 || n / 2 == 1); }
 
 int standard_depth(int nx, int ny) {
@@ -324,7 +339,7 @@ size_t grid_bytes(const ell_grid_desc *d, int L) {
     bytes += (size_t)TSLOTS * G.P * es;
     if (l > 0) bytes += 2 * 2 * (size_t)G.cs * es;
   }
-  const long long nb = std::max<long long>(seg_blocks(2 * (long long)g0.H), flat_blocks(n0 / 2));
+  const long long nb = partial_blocks(n0, g0.H);
   bytes += (size_t)nb * 2 * 8 + sizeof(PcgState) + (size_t)d->nz * 8;
   return bytes;
 }
@@ -638,29 +653,40 @@ const typename Vec2<Z>::T *zvec(const ell_grid *g) {
 // Start of a solve (Appendix B, Alg. PCG, before the loop): r = V f - A u0
 // with ||b|| and ||r0|| (the device sets done if nothing is left to do),
 // z0 = M^{-1} r0, kappa = <r0, z0>.
+// Caller-facing statistics of a finished solve; the return code follows the
+// final status (0 converged, 1 iteration limit, -4 non-finite recurrence).
+int stats_from_state(const PcgState &h, ell_solve_stats *out) {
+  const int status = h.status;
+  if (out) {
+    out->iters = h.iter;
+    out->status = status == -4 ? ELL_ERR_NUMERIC : (status == 0 ? ELL_OK : ELL_NOT_CONVERGED);
+    out->r0_norm = h.r0_norm;
+    out->r_norm = h.r_norm;
+    out->true_r_norm = h.true_r_norm;
+    out->b_norm = h.b_norm;
+  }
+  if (status == -4) return fail(ELL_ERR_NUMERIC, "non-finite value in the CG recurrence");
+  return status == 0 ? ELL_OK : ELL_NOT_CONVERGED;
+}
+
 template <typename R, typename Z>
 int pcg_begin(ell_grid *g, const double *f, const double *u, const ell_solve_opts &o, hipStream_t s) {
   const Geo &G = g->lev[0].geo;
   const long long n2 = g->n0 / 2;
   const int fb = flat_blocks(n2);
   const int *done = &g->st->done;
-  const int cb = blocks8(2LL * G.H);
-  k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, f, g->r, g->vol0);
-  CHK(check_launch("k_nat2split"));
-  k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, u, g->us, nullptr);
-  CHK(check_launch("k_nat2split"));
-  CHK(launch_apply64(g, g->us, g->q, false, nullptr, s));
-  k_resid_init<<<fb, kBlock, 0, s>>>((const double2 *)g->q, (double2 *)g->r, n2, g->partial);
-  CHK(check_launch("k_resid_init"));
-  k_finalize<<<1, kBlock, 0, s>>>(g->partial, fb, 2, g->st, F_INIT, o.rtol, o.atol, o.rel_to_rhs);
-  CHK(check_launch("k_finalize"));
-  // maxiter / flexible live in the state block
+  // maxiter / flexible live in the state block (read by F_INIT and F_CONV)
   {
     PcgState *h = g->st_host;
     h->maxiter = o.maxiter;
     h->flexible = o.flexible;
     HIPCHK(hipMemcpyAsync(&g->st->maxiter, &h->maxiter, 2 * sizeof(int), hipMemcpyHostToDevice, s));
   }
+  const int bb = seg_blocks((long long)G.nx * G.ny);
+  k_begin<<<bb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, u, g->us, g->r, g->partial);
+  CHK(check_launch("k_begin"));
+  k_finalize<<<1, kBlock, 0, s>>>(g->partial, bb, 2, g->st, F_INIT, o.rtol, o.atol, o.rel_to_rhs);
+  CHK(check_launch("k_finalize"));
   CHK(precondition<R>(g, done, s));
   k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zvec<Z>(g), (const double2 *)g->q, n2, g->st,
                                   g->partial);
@@ -710,40 +736,17 @@ int pcg_step(ell_grid *g, int K, hipStream_t s) {
 // deferred solution update, u back to plane-major, the FP64 true residual.
 int pcg_finish(ell_grid *g, const double *f, double *u, ell_solve_stats *out, hipStream_t s) {
   const Geo &G = g->lev[0].geo;
-  const long long n2 = g->n0 / 2;
-  const int fb = flat_blocks(n2);
-  const int cb = blocks8(2LL * G.H);
-  double *pbuf[2] = {g->p, g->p2};
-  {
-    const int K = g->st_host->iter;
-    if (K > 0 && g->st_host->status != -4) {
-      k_axpy_alpha<<<fb, kBlock, 0, s>>>((double2 *)g->us, (const double2 *)pbuf[K & 1], n2, g->st);
-      CHK(check_launch("k_axpy_alpha"));
-    }
-  }
-  k_split2nat<double, double><<<cb, kBlock, 0, s>>>(G, g->us, u);
-  CHK(check_launch("k_split2nat"));
-  k_nat2split<double, double><<<cb, kBlock, 0, s>>>(G, f, g->r, g->vol0);
-  CHK(check_launch("k_nat2split"));
-  CHK(launch_apply64(g, g->us, g->q, false, nullptr, s));
-  k_resid_init<<<fb, kBlock, 0, s>>>((const double2 *)g->q, (double2 *)g->r, n2, g->partial);
-  CHK(check_launch("k_resid_init"));
+  const int K = g->st_host->iter;
+  const int with_p = (K > 0 && g->st_host->status != -4) ? 1 : 0;
+  const int fb = seg_blocks(2LL * G.H);
+  k_finish<<<fb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, g->us, (K & 1) ? g->p2 : g->p, g->st, with_p, u,
+                                 g->partial);
+  CHK(check_launch("k_finish"));
   k_finalize<<<1, kBlock, 0, s>>>(g->partial, fb, 2, g->st, F_TRUE, 0, 0, 0);
   CHK(check_launch("k_finalize"));
   HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  const PcgState &h = *g->st_host;
-  const int status = h.status;
-  if (out) {
-    out->iters = h.iter;
-    out->status = status == -4 ? ELL_ERR_NUMERIC : (status == 0 ? ELL_OK : ELL_NOT_CONVERGED);
-    out->r0_norm = h.r0_norm;
-    out->r_norm = h.r_norm;
-    out->true_r_norm = h.true_r_norm;
-    out->b_norm = h.b_norm;
-  }
-  if (status == -4) return fail(ELL_ERR_NUMERIC, "non-finite value in the CG recurrence");
-  return status == 0 ? ELL_OK : ELL_NOT_CONVERGED;
+  return stats_from_state(*g->st_host, out);
 }
 
 template <typename R, typename Z>
@@ -858,7 +861,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   }
   if (desc->rho != 1.0)
     if ((rc = dalloc(g, &g->ybuf, (size_t)G0.cs * g->esz)) != ELL_OK) return bail(rc);
-  const long long nb = std::max<long long>(seg_blocks(2LL * G0.H), flat_blocks(g->n0 / 2));
+  const long long nb = partial_blocks(g->n0, G0.H);
   g->partial_cap = nb * 2;
   if ((rc = dalloc(g, &tmp, (size_t)g->partial_cap * 8)) != ELL_OK) return bail(rc);
   g->partial = (double *)tmp;

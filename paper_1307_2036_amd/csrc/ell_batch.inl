@@ -35,21 +35,72 @@ struct LevelDev {
 struct GridDev {
   LevelDev lev[kMaxLevels];
   const double *tab64_0;
+  const double *vol0;  // finest-level cell volumes
   double *us, *r, *z, *p, *p2, *q;
   float *u32;
   double *partial;
   PcgState *st;
   long long n2;
   int L, nb_apply, nb_flat, prolong;
+  int nb_begin, nb_finish;  // blocks of the start / end kernels (partial sums each)
 };
 
 struct StageEnt {
   const GridDev *g;
   int block0;
-  int pad;
+  int aux;  // start / end tables: index of the request record
+};
+
+// What the start and end of one solve need beyond its grid: the caller's
+// vectors and the stopping rule.
+struct ReqDev {
+  const double *f;
+  double *u;
+  double rtol, atol;
+  int rel_to_rhs, maxiter, flexible, pad;
 };
 
 enum Role : int { ROLE_COARSE = 0, ROLE_FINE64 = 1, ROLE_PRE32 = 2 };
+
+// Pointers and sizes read from a grid descriptor are the same for the whole
+// block.  Re-deriving them through readfirstlane and the global address space
+// gives the bodies what a kernel argument gives them: values in scalar
+// registers, global (not flat) vector memory instructions, and scalar loads
+// for the per-level coefficient tables.
+template <typename T>
+__device__ __forceinline__ T *gp(T *p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  auto *g = (__attribute__((address_space(1))) T *)(((unsigned long long)hi << 32) | lo);
+  return (T *)g;
+}
+
+__device__ __forceinline__ int ui(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ long long ull(long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)((unsigned long long)v >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ Geo ugeo(const Geo &g) {
+  Geo r;
+  r.nx = ui(g.nx);
+  r.ny = ui(g.ny);
+  r.nz = ui(g.nz);
+  r.H = ui(g.H);
+  r.ncol0 = ui(g.ncol0);
+  r.ncol1 = ui(g.ncol1);
+  r.hx2 = ui(g.hx2);
+  r.has_x = ui(g.has_x);
+  r.has_y = ui(g.has_y);
+  r.P = ui(g.P);
+  r.S = ui(g.S);
+  r.nseg = ui(g.nseg);
+  r.cs = ull(g.cs);
+  return r;
+}
 
 __device__ __forceinline__ int find_ent(const StageEnt *e, int n, int b) {
   int lo = 0, hi = n - 1;
@@ -68,9 +119,9 @@ __global__ __launch_bounds__(kBlock) void kb_smooth(const StageEnt *__restrict__
   const int bg = logical_block();
   if (bg >= total) return;
   const int e = find_ent(ents, nent, bg);
-  const GridDev *gd = ents[e].g;
+  const GridDev *gd = gp(ents[e].g);
   const LevelDev &Lv = gd->lev[l];
-  const Geo G = Lv.geo;
+  const Geo G = ugeo(Lv.geo);
   const R *tab;
   const TB *b;
   R *u;
@@ -87,9 +138,12 @@ __global__ __launch_bounds__(kBlock) void kb_smooth(const StageEnt *__restrict__
     b = (const TB *)Lv.b;
     u = (R *)Lv.u;
   }
+  tab = gp(tab);
+  b = gp(b);
+  u = gp(u);
   smooth_seg_body<R, ZERO, true, FINE, SEG, 4, TB>(G, tab, c, b + (long long)c * G.cs,
                                                    u + (long long)(1 - c) * G.cs, u + (long long)c * G.cs,
-                                                   R(1), &gd->st->done, bg - ents[e].block0, 0);
+                                                   R(1), gp(&gd->st->done), ui(bg - ents[e].block0), 0);
 }
 
 template <typename R, typename TB, int ROLE>
@@ -98,13 +152,13 @@ __global__ __launch_bounds__(kBlock) void kb_restrict(const StageEnt *__restrict
   const int bg = logical_block();
   if (bg >= total) return;
   const int e = find_ent(ents, nent, bg);
-  const GridDev *gd = ents[e].g;
+  const GridDev *gd = gp(ents[e].g);
   const LevelDev &F = gd->lev[l];
   const LevelDev &C = gd->lev[l + 1];
   const TB *b = ROLE == ROLE_COARSE ? (const TB *)F.b : (const TB *)gd->r;
   const R *u = ROLE == ROLE_COARSE ? (const R *)F.u : (ROLE == ROLE_PRE32 ? (const R *)gd->u32 : (const R *)gd->z);
-  resid_restrict_bz_body<R, TB>(F.geo, C.geo, (const R *)F.tab, b, u, (R *)C.b, &gd->st->done,
-                                bg - ents[e].block0, 0);
+  resid_restrict_bz_body<R, TB>(ugeo(F.geo), ugeo(C.geo), gp((const R *)F.tab), gp(b), gp(u), gp((R *)C.b),
+                                gp(&gd->st->done), ui(bg - ents[e].block0), 0);
 }
 
 template <typename R, int MODE, int ROLE>
@@ -113,11 +167,12 @@ __global__ __launch_bounds__(kBlock) void kb_prolong(const StageEnt *__restrict_
   const int bg = logical_block();
   if (bg >= total) return;
   const int e = find_ent(ents, nent, bg);
-  const GridDev *gd = ents[e].g;
+  const GridDev *gd = gp(ents[e].g);
   const LevelDev &F = gd->lev[l];
   const LevelDev &C = gd->lev[l + 1];
   R *u = ROLE == ROLE_FINE64 ? (R *)gd->z : (R *)F.u;
-  prolong_body<R, true, MODE>(F.geo, C.geo, (const R *)C.u, u, &gd->st->done, bg - ents[e].block0, 0);
+  prolong_body<R, true, MODE>(ugeo(F.geo), ugeo(C.geo), gp((const R *)C.u), gp(u), gp(&gd->st->done),
+                              ui(bg - ents[e].block0), 0);
 }
 
 template <int MODE>
@@ -126,47 +181,91 @@ __global__ __launch_bounds__(kBlock) void kb_prolong_out(const StageEnt *__restr
   const int bg = logical_block();
   if (bg >= total) return;
   const int e = find_ent(ents, nent, bg);
-  const GridDev *gd = ents[e].g;
-  prolong_out_body<float, double, MODE>(gd->lev[0].geo, gd->lev[1].geo, (const float *)gd->lev[1].u, gd->u32,
-                                        gd->z, &gd->st->done, bg - ents[e].block0, 0);
+  const GridDev *gd = gp(ents[e].g);
+  prolong_out_body<float, double, MODE>(ugeo(gd->lev[0].geo), ugeo(gd->lev[1].geo), gp((const float *)gd->lev[1].u),
+                                        gp(gd->u32), gp(gd->z), gp(&gd->st->done), ui(bg - ents[e].block0), 0);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_apply_dir(const StageEnt *__restrict__ ents, int nent, int total) {
   const int bg = logical_block();
   if (bg >= total) return;
   const int e = find_ent(ents, nent, bg);
-  const GridDev *gd = ents[e].g;
-  const int K = gd->st->iter + 1;  // iteration about to run
-  double *pold = ((K - 1) & 1) ? gd->p2 : gd->p;
-  double *pnew = (K & 1) ? gd->p2 : gd->p;
-  apply_dir_body<double, 1>(gd->lev[0].geo, gd->tab64_0, gd->z, pold, pnew, gd->q, gd->us, gd->st,
-                            K == 1 ? 1 : 0, K > 1 ? 1 : 0, gd->partial, bg - ents[e].block0, 0);
+  const GridDev *gd = gp(ents[e].g);
+  const PcgState *st = gp(gd->st);
+  const int K = ui(st->iter) + 1;  // iteration about to run
+  double *pold = gp(((K - 1) & 1) ? gd->p2 : gd->p);
+  double *pnew = gp((K & 1) ? gd->p2 : gd->p);
+  apply_dir_body<double, 1>(ugeo(gd->lev[0].geo), gp(gd->tab64_0), gp(gd->z), pold, pnew, gp(gd->q), gp(gd->us),
+                            st, K == 1 ? 1 : 0, K > 1 ? 1 : 0, gp(gd->partial), ui(bg - ents[e].block0), 0);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_update_r(const StageEnt *__restrict__ ents, int nent, int total) {
   const int bg = logical_block();
   if (bg >= total) return;
   const int e = find_ent(ents, nent, bg);
-  const GridDev *gd = ents[e].g;
-  update_r_body((double2 *)gd->r, (const double2 *)gd->q, gd->n2, gd->st, gd->partial, bg - ents[e].block0,
-                gd->nb_flat);
+  const GridDev *gd = gp(ents[e].g);
+  update_r_body(gp((double2 *)gd->r), gp((const double2 *)gd->q), ull(gd->n2), gp(gd->st), gp(gd->partial),
+                ui(bg - ents[e].block0), ui(gd->nb_flat));
 }
 
 __global__ __launch_bounds__(kBlock) void kb_dots(const StageEnt *__restrict__ ents, int nent, int total) {
   const int bg = logical_block();
   if (bg >= total) return;
   const int e = find_ent(ents, nent, bg);
-  const GridDev *gd = ents[e].g;
-  dots_body<double>((const double2 *)gd->r, (const double2 *)gd->z, (const double2 *)gd->q, gd->n2, gd->st,
-                    gd->partial, bg - ents[e].block0, gd->nb_flat);
+  const GridDev *gd = gp(ents[e].g);
+  dots_body<double>(gp((const double2 *)gd->r), gp((const double2 *)gd->z), gp((const double2 *)gd->q),
+                    ull(gd->n2), gp(gd->st), gp(gd->partial), ui(bg - ents[e].block0), ui(gd->nb_flat));
+}
+
+// Start of the solves of a table: split-layout u and r = V f - A u0.
+__global__ __launch_bounds__(kBlock) void kb_begin(const StageEnt *__restrict__ ents, int nent, int total,
+                                                   const ReqDev *__restrict__ reqs) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = gp(ents[e].g);
+  const ReqDev *rq = gp(reqs + ents[e].aux);
+  begin_body(ugeo(gd->lev[0].geo), gp(gd->tab64_0), gp(gd->vol0), gp(rq->f), gp((const double *)rq->u),
+             gp(gd->us), gp(gd->r), gp(gd->partial), ui(bg - ents[e].block0));
+}
+
+// One block per grid: the stopping rule into the state, then the initial
+// norms and threshold (F_INIT).
+__global__ __launch_bounds__(kBlock) void kb_init(const StageEnt *__restrict__ ents,
+                                                  const ReqDev *__restrict__ reqs) {
+  const GridDev *gd = gp(ents[blockIdx.x].g);
+  const ReqDev *rq = gp(reqs + ents[blockIdx.x].aux);
+  PcgState *st = gp(gd->st);
+  if (threadIdx.x == 0) {
+    st->maxiter = rq->maxiter;
+    st->flexible = rq->flexible;
+  }
+  finalize_body(gp(gd->partial), ui(gd->nb_begin), 2, st, F_INIT, rq->rtol, rq->atol, rq->rel_to_rhs, 0, 1);
+}
+
+// End of the solves of a table: the deferred update of the last iteration,
+// u back in plane-major order and the partial sums of its true residual.
+__global__ __launch_bounds__(kBlock) void kb_finish(const StageEnt *__restrict__ ents, int nent, int total,
+                                                    const ReqDev *__restrict__ reqs) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = gp(ents[e].g);
+  const ReqDev *rq = gp(reqs + ents[e].aux);
+  const PcgState *st = gp(gd->st);
+  const int K = ui(st->iter);
+  const int with_p = (K > 0 && ui(st->status) != -4) ? 1 : 0;
+  const double alpha = with_p ? st->alpha : 0.0;
+  finish_body(ugeo(gd->lev[0].geo), gp(gd->tab64_0), gp(gd->vol0), gp(rq->f), gp(gd->us),
+              gp((K & 1) ? gd->p2 : gd->p), alpha, with_p, gp(rq->u), gp(gd->partial), ui(bg - ents[e].block0));
 }
 
 // one block per grid
 __global__ __launch_bounds__(kBlock) void kb_finalize(const StageEnt *__restrict__ ents, int mode) {
-  const GridDev *gd = ents[blockIdx.x].g;
-  const int nblk = mode == F_ALPHA ? gd->nb_apply : gd->nb_flat;
-  const int nq = mode == F_BETA ? 2 : 1;
-  finalize_body(gd->partial, nblk, nq, gd->st, mode, 0.0, 0.0, 0, 0, 1);
+  const GridDev *gd = gp(ents[blockIdx.x].g);
+  const int nblk = ui(mode == F_ALPHA ? gd->nb_apply : (mode == F_TRUE ? gd->nb_finish : gd->nb_flat));
+  const int nq = (mode == F_BETA || mode == F_TRUE) ? 2 : 1;
+  finalize_body(gp(gd->partial), nblk, nq, gp(gd->st), mode, 0.0, 0.0, 0, 0, 1);
 }
 
 __global__ void kb_gather_states(const StageEnt *__restrict__ ents, int nent, PcgState *__restrict__ out) {
@@ -177,6 +276,14 @@ __global__ void kb_gather_states(const StageEnt *__restrict__ ents, int nent, Pc
 // ------------------------------------------------------------------------
 // host side
 // ------------------------------------------------------------------------
+// Blocks of the start (64 plane-major columns each) and end (64 split slots
+// each) kernels of one grid inside a grouped launch.
+int begin_blocks(const ell_grid *g) {
+  const Geo &G = g->lev[0].geo;
+  return (int)(((long long)G.nx * G.ny + kSegCols - 1) / kSegCols);
+}
+int finish_blocks(const ell_grid *g) { return (int)((2LL * g->lev[0].geo.H + kSegCols - 1) / kSegCols); }
+
 int grid_dev_build(ell_grid *g) {
   if (g->L > kMaxLevels) return fail(ELL_ERR_INVALID, "too many levels for the batch engine");
   GridDev h;
@@ -188,6 +295,7 @@ int grid_dev_build(ell_grid *g) {
     h.lev[l].u = g->lev[l].u;
   }
   h.tab64_0 = g->tab64_0;
+  h.vol0 = g->vol0;
   h.us = g->us;
   h.r = g->r;
   h.z = g->z;
@@ -200,8 +308,10 @@ int grid_dev_build(ell_grid *g) {
   h.n2 = g->n0 / 2;
   h.L = g->L;
   h.nb_apply = stencil_blocks(2LL * g->lev[0].geo.H, 1);
-  h.nb_flat = flat_blocks(h.n2);
+  h.nb_flat = batch_flat_blocks(h.n2);
   h.prolong = g->d.prolong;
+  h.nb_begin = begin_blocks(g);
+  h.nb_finish = finish_blocks(g);
   void *d = nullptr;
   CHK(dalloc(g, &d, sizeof(GridDev)));
   HIPCHK(hipMemcpy(d, &h, sizeof(GridDev), hipMemcpyHostToDevice));
@@ -273,6 +383,9 @@ struct ell_batch {
   PcgState *d_states = nullptr;
   PcgState *h_states = nullptr;  // pinned
   int states_cap = 0;
+  void *d_tx = nullptr;  // start / end tables (request records + entries)
+  void *h_tx = nullptr;  // pinned staging
+  size_t tx_cap = 0;
   bool dirty = true;
   int prec = -1;
   std::string last_error;
@@ -306,6 +419,20 @@ int batch_reserve(ell_batch *b, size_t ents, int states) {
   return ELL_OK;
 }
 
+int tx_reserve(ell_batch *b, size_t bytes) {
+  if (bytes <= b->tx_cap) return ELL_OK;
+  if (b->d_tx) (void)hipFree(b->d_tx);
+  if (b->h_tx) (void)hipHostFree(b->h_tx);
+  const size_t cap = std::max<size_t>(bytes, 2 * b->tx_cap);
+  b->d_tx = nullptr;
+  b->h_tx = nullptr;
+  b->tx_cap = 0;
+  HIPCHK(hipMalloc(&b->d_tx, cap));
+  HIPCHK(hipHostMalloc(&b->h_tx, cap, hipHostMallocDefault));
+  b->tx_cap = cap;
+  return ELL_OK;
+}
+
 // Build the stage list and entry tables for the active grids.  The V-cycle of
 // every grid follows its own depth: at depth d the grids with more levels
 // pre-smooth and restrict, the grids whose coarsest level is d run their
@@ -333,7 +460,7 @@ int batch_build(ell_batch *b) {
   std::vector<ell_grid *> all;
   for (Request *r : A) all.push_back(r->g);
   auto one = [](ell_grid *) { return 1; };
-  auto flat = [](ell_grid *g) { return flat_blocks(g->n0 / 2); };
+  auto flat = [](ell_grid *g) { return batch_flat_blocks(g->n0 / 2); };
   auto apply = [](ell_grid *g) { return stencil_blocks(2LL * g->lev[0].geo.H, 1); };
   auto cols = [](int l, int c) {
     return [l, c](ell_grid *g) {
@@ -352,22 +479,12 @@ int batch_build(ell_batch *b) {
     for (ell_grid *g : gs) m = std::max(m, seg_len(g->lev[l].geo.nz, 4));
     return m <= 16 ? 16 : (m <= 32 ? 32 : 64);
   };
+  // One step is iteration K of every active grid, in the order
+  //   z = M r (V-cycle), <r,z> and <z,q>, beta (kappa at K = 1),
+  //   p = z + beta p, q = A p and <p,q>, alpha, r -= alpha q, convergence;
+  // the solution update of iteration K is deferred into step K + 1 (or the
+  // end of the solve).  A grid admitted just before the step starts at K = 1.
   Stage s0{};
-  // CG operator step, alpha, residual update, convergence
-  s0 = Stage{};
-  s0.kind = Stage::APPLY_DIR;
-  add(s0, all, apply);
-  s0 = Stage{};
-  s0.kind = Stage::FINALIZE;
-  s0.mode = F_ALPHA;
-  add(s0, all, one);
-  s0 = Stage{};
-  s0.kind = Stage::UPDATE_R;
-  add(s0, all, flat);
-  s0 = Stage{};
-  s0.kind = Stage::FINALIZE;
-  s0.mode = F_CONV;
-  add(s0, all, one);
   // V-cycle, down
   int Dmax = 0;
   for (ell_grid *g : all) Dmax = std::max(Dmax, g->L);
@@ -462,6 +579,21 @@ int batch_build(ell_batch *b) {
   s0.kind = Stage::FINALIZE;
   s0.mode = F_BETA;
   add(s0, all, one);
+  // CG operator step, alpha, residual update, convergence
+  s0 = Stage{};
+  s0.kind = Stage::APPLY_DIR;
+  add(s0, all, apply);
+  s0 = Stage{};
+  s0.kind = Stage::FINALIZE;
+  s0.mode = F_ALPHA;
+  add(s0, all, one);
+  s0 = Stage{};
+  s0.kind = Stage::UPDATE_R;
+  add(s0, all, flat);
+  s0 = Stage{};
+  s0.kind = Stage::FINALIZE;
+  s0.mode = F_CONV;
+  add(s0, all, one);
   // state gather table: one entry per active grid (reuses the FINALIZE layout)
   CHK(batch_reserve(b, ents.size() + 1, (int)all.size() + 1));
   if (!ents.empty()) {
@@ -534,10 +666,48 @@ int batch_step(ell_batch *b) {
   return ELL_OK;
 }
 
-int request_begin(Request *r, hipStream_t s) {
-  ell_grid *g = r->g;
-  if (g->prec == ELL_FP64) return pcg_begin<double, double>(g, r->f, r->u, r->o, s);
-  return pcg_begin<float, double>(g, r->f, r->u, r->o, s);
+// Start (start = true: split-layout u and r, initial norms) or end (u back
+// to the caller, true residual, final states into h_states in the order of
+// rs, stream synchronised) of the solves of rs, grouped: one table upload
+// and two launches for all of them.
+int batch_edge(ell_batch *b, const std::vector<Request *> &rs, bool start) {
+  hipStream_t s = b->stream;
+  const int n = (int)rs.size();
+  const size_t bytes = (size_t)n * sizeof(ReqDev) + 2 * (size_t)n * sizeof(StageEnt);
+  CHK(tx_reserve(b, bytes));
+  CHK(batch_reserve(b, 0, n + 1));
+  ReqDev *hr = (ReqDev *)b->h_tx;
+  StageEnt *he = (StageEnt *)(hr + n);
+  StageEnt *h1 = he + n;
+  int tot = 0;
+  for (int i = 0; i < n; ++i) {
+    const Request *r = rs[i];
+    hr[i] = ReqDev{r->f, r->u, r->o.rtol, r->o.atol, r->o.rel_to_rhs, r->o.maxiter, r->o.flexible, 0};
+    const GridDev *gd = (const GridDev *)r->g->gdev;
+    he[i] = StageEnt{gd, tot, i};
+    h1[i] = StageEnt{gd, i, i};
+    tot += start ? begin_blocks(r->g) : finish_blocks(r->g);
+  }
+  HIPCHK(hipMemcpyAsync(b->d_tx, b->h_tx, bytes, hipMemcpyHostToDevice, s));
+  const ReqDev *dr = (const ReqDev *)b->d_tx;
+  const StageEnt *de = (const StageEnt *)(dr + n);
+  const StageEnt *d1 = de + n;
+  const int nb = blocks8((long long)tot * kBlock);
+  if (start) {
+    kb_begin<<<nb, kBlock, 0, s>>>(de, n, tot, dr);
+    CHK(check_launch("kb_begin"));
+    kb_init<<<n, kBlock, 0, s>>>(d1, dr);
+    return check_launch("kb_init");
+  }
+  kb_finish<<<nb, kBlock, 0, s>>>(de, n, tot, dr);
+  CHK(check_launch("kb_finish"));
+  kb_finalize<<<n, kBlock, 0, s>>>(d1, F_TRUE);
+  CHK(check_launch("kb_finalize"));
+  kb_gather_states<<<(n + 63) / 64, 64, 0, s>>>(d1, n, b->d_states);
+  CHK(check_launch("kb_gather_states"));
+  HIPCHK(hipMemcpyAsync(b->h_states, b->d_states, n * sizeof(PcgState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return ELL_OK;
 }
 
 void finish_ticket(ell_batch *b, Request *r) {
@@ -548,6 +718,20 @@ void finish_ticket(ell_batch *b, Request *r) {
   b->cv_done.notify_all();
 }
 
+// Fail every request of rs with rc after draining the stream, so that no
+// queued kernel still reads or writes their vectors once they are released.
+void fail_all(ell_batch *b, std::vector<Request *> &rs, int rc) {
+  (void)hipStreamSynchronize(b->stream);
+  for (Request *r : rs) {
+    r->rc = rc;
+    finish_ticket(b, r);
+  }
+  rs.clear();
+}
+
+// One cycle: admit the queued requests whose grid is idle (their start runs
+// grouped), poll_every grouped steps of every active grid, read the states
+// back, end the finished solves (grouped) and hand back their tickets.
 void worker_loop(ell_batch *b) {
   hipStream_t s = b->stream;
   for (;;) {
@@ -568,23 +752,19 @@ void worker_loop(ell_batch *b) {
       }
     }
     int rc = ELL_OK;
-    for (Request *r : admit) {
-      rc = request_begin(r, s);
-      if (rc != ELL_OK) {
-        r->rc = rc;
-        finish_ticket(b, r);
+    if (!admit.empty()) {
+      if ((rc = batch_edge(b, admit, true)) != ELL_OK) {
+        fail_all(b, admit, rc);
+        fail_all(b, b->active, rc);
+        b->dirty = true;
         continue;
       }
-      b->active.push_back(r);
+      b->active.insert(b->active.end(), admit.begin(), admit.end());
       b->dirty = true;
     }
     if (b->active.empty()) continue;
     if (b->dirty && (rc = batch_build(b)) != ELL_OK) {
-      for (Request *r : b->active) {
-        r->rc = rc;
-        finish_ticket(b, r);
-      }
-      b->active.clear();
+      fail_all(b, b->active, rc);
       continue;
     }
     for (int k = 0; k < b->poll_every && rc == ELL_OK; ++k) rc = batch_step(b);
@@ -601,24 +781,31 @@ void worker_loop(ell_batch *b) {
         rc = fail(ELL_ERR_HIP, "state copy failed");
       if (rc == ELL_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(ELL_ERR_HIP, "batch step failed");
     }
-    std::vector<Request *> still;
+    if (rc != ELL_OK) {
+      fail_all(b, b->active, rc);
+      b->dirty = true;
+      continue;
+    }
+    std::vector<Request *> ended, still;
     for (int i = 0; i < n; ++i) {
       Request *r = b->active[i];
-      if (rc != ELL_OK) {
-        r->rc = rc;
-        finish_ticket(b, r);
-        continue;
-      }
-      const PcgState &h = b->h_states[i];
-      if (h.done) {
-        *r->g->st_host = h;
-        r->rc = pcg_finish(r->g, r->f, r->u, &r->st, s);
-        finish_ticket(b, r);
-      } else {
-        still.push_back(r);
-      }
+      (b->h_states[i].done ? ended : still).push_back(r);
     }
-    if (still.size() != b->active.size()) b->dirty = true;
+    if (!ended.empty()) {
+      rc = batch_edge(b, ended, false);
+      for (size_t i = 0; i < ended.size(); ++i) {
+        Request *r = ended[i];
+        if (rc == ELL_OK) {
+          *r->g->st_host = b->h_states[i];
+          r->rc = stats_from_state(b->h_states[i], &r->st);
+        } else {
+          r->rc = rc;
+        }
+      }
+      if (rc != ELL_OK) (void)hipStreamSynchronize(s);
+      for (Request *r : ended) finish_ticket(b, r);
+      b->dirty = true;
+    }
     b->active.swap(still);
   }
 }
@@ -774,6 +961,8 @@ int ell_batch_destroy(ell_batch *b) {
   if (b->h_ents) (void)hipHostFree(b->h_ents);
   if (b->d_states) (void)hipFree(b->d_states);
   if (b->h_states) (void)hipHostFree(b->h_states);
+  if (b->d_tx) (void)hipFree(b->d_tx);
+  if (b->h_tx) (void)hipHostFree(b->h_tx);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
   return ELL_OK;

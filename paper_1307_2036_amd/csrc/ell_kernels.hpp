@@ -1002,6 +1002,201 @@ __global__ __launch_bounds__(kBlock) void k_cast_f64_f32(const double2 *__restri
 }
 
 // -------------------------------------------------------------------------
+// Start and end of a solve, one pass each (Appendix B, Alg. PCG: initial
+// residual, final solution).  Both evaluate the operator exactly as the
+// split-layout operator kernel does (same terms in the same order), with
+// f and u in plane-major order [k][j][i] at the library boundary.
+// -------------------------------------------------------------------------
+
+// Operator row of one cell (eq. (FV) with the harmonic vertical faces):
+// V_k u_c + Tx_k (2 u_c - u_W - u_E) + Ty_k (2 u_c - u_S - u_N)
+//         + T_{k-1/2} (u_c - u_{k-1}) + T_{k+1/2} (u_c - u_{k+1}).
+__device__ __forceinline__ double op_row(const double *__restrict__ tab, int P, int k, bool hx, bool hy,
+                                         double uc, double um, double up, double uw, double ue,
+                                         double us, double un) {
+  double acc = tab[TV * P + k] * uc;
+  if (hx) {
+    acc = acc + tab[TX * P + k] * (uc - uw);
+    acc = acc + tab[TX * P + k] * (uc - ue);
+  }
+  if (hy) {
+    acc = acc + tab[TY * P + k] * (uc - us);
+    acc = acc + tab[TY * P + k] * (uc - un);
+  }
+  acc = acc + tab[TZ * P + k] * (uc - um);
+  acc = acc + tab[TZ * P + k + 1] * (uc - up);
+  return acc;
+}
+
+// us = u0 and r = V f - A u0 in the split layout, from plane-major f and u0;
+// partial[2 lb] = sum (V f)^2, partial[2 lb + 1] = sum r^2 over the block.
+// One block = 64 plane-major columns (lanes are consecutive i: every
+// plane-major access is coalesced, and each colour receives 32 consecutive
+// split entries per wavefront), one k-segment of four per wavefront.
+// Blocks past the last column write zero partial sums.
+__device__ __forceinline__ void begin_body(Geo L, const double *__restrict__ tab,
+                                           const double *__restrict__ vol,
+                                           const double *__restrict__ f,
+                                           const double *__restrict__ u0, double *__restrict__ us,
+                                           double *__restrict__ r, double *__restrict__ partial,
+                                           int lb) {
+  constexpr int NSEG = 4, U = 4;
+  __shared__ double sh[4];
+  const int sg = wave_id();
+  const long long plane = (long long)L.nx * L.ny;
+  const long long col = (long long)lb * kSegCols + (threadIdx.x & 63);
+  const int Ls = seg_len(L.nz, NSEG);
+  const int k0 = min(sg * Ls, L.nz), k1 = min(k0 + Ls, L.nz);
+  double bb = 0.0, rr = 0.0;
+  if (col < plane && k1 > k0) {
+    const int j = (int)(col / L.nx), i = (int)(col - (long long)j * L.nx);
+    const int c = (i + j) & 1;
+    const long long m = col_m(L, i, j);
+    const bool hx = L.has_x, hy = L.has_y;
+    const long long oc = col;
+    const long long ow = hx ? (long long)j * L.nx + wrapi(i - 1, L.nx) : oc;
+    const long long oe = hx ? (long long)j * L.nx + wrapi(i + 1, L.nx) : oc;
+    const long long osn = hy ? (long long)wrapi(j - 1, L.ny) * L.nx + i : oc;
+    const long long onn = hy ? (long long)wrapi(j + 1, L.ny) * L.nx + i : oc;
+    double *__restrict__ usc = us + (long long)c * L.cs + m;
+    double *__restrict__ rc = r + (long long)c * L.cs + m;
+    const long long S = L.S;
+    const int nz = L.nz, P = L.P;
+    double uc = u0[(long long)k0 * plane + oc];
+    double um = k0 > 0 ? u0[(long long)(k0 - 1) * plane + oc] : uc;
+    int k = k0;
+    for (; k < k1; k += U) {
+      double up[U], uw[U], ue[U], usv[U], un[U], fv[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        const int kk = min(k + t, k1 - 1);
+        const long long o = (long long)kk * plane;
+        up[t] = u0[(long long)min(kk + 1, nz - 1) * plane + oc];
+        uw[t] = hx ? u0[o + ow] : 0.0;
+        ue[t] = hx ? u0[o + oe] : 0.0;
+        usv[t] = hy ? u0[o + osn] : 0.0;
+        un[t] = hy ? u0[o + onn] : 0.0;
+        fv[t] = f[o + oc];
+      }
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        if (k + t < k1) {
+          const int kk = k + t;
+          const double acc = op_row(tab, P, kk, hx, hy, uc, um, up[t], uw[t], ue[t], usv[t], un[t]);
+          const double b = vol[kk] * fv[t];
+          const double res = b - acc;
+          usc[(long long)kk * S] = uc;
+          rc[(long long)kk * S] = res;
+          bb += b * b;
+          rr += res * res;
+          um = uc;
+          uc = up[t];
+        }
+      }
+    }
+  }
+  const double s0 = block_sum(bb, sh);
+  const double s1 = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * lb] = s0;
+    partial[2 * lb + 1] = s1;
+  }
+}
+
+// u = us + alpha p (the last iteration's deferred update; us alone when
+// with_p is 0) written plane-major, and the true residual of that u:
+// partial[2 lb] = sum (V f)^2, partial[2 lb + 1] = sum (V f - A u)^2.
+// One block = 64 split slots with alternating colours (a red and a black
+// column side by side are adjacent plane-major cells, so the plane-major
+// accesses are coalesced too), one k-segment of four per wavefront.
+__device__ __forceinline__ void finish_body(Geo L, const double *__restrict__ tab,
+                                            const double *__restrict__ vol,
+                                            const double *__restrict__ f,
+                                            const double *__restrict__ us,
+                                            const double *__restrict__ p, double alpha, int with_p,
+                                            double *__restrict__ u, double *__restrict__ partial,
+                                            int lb) {
+  constexpr int NSEG = 4, U = 4;
+  __shared__ double sh[4];
+  const int sg = wave_id();
+  const int slot = lb * kSegCols + (threadIdx.x & 63);
+  const int c = slot & 1;
+  const int m = slot >> 1;
+  const bool valid = slot < 2 * L.H && m < (c ? L.ncol1 : L.ncol0);
+  const int Ls = seg_len(L.nz, NSEG);
+  const int k0 = min(sg * Ls, L.nz), k1 = min(k0 + Ls, L.nz);
+  double bb = 0.0, rr = 0.0;
+  if (valid && k1 > k0) {
+    int i, j;
+    col_ij(L, c, m, i, j);
+    const Nbr nb = neighbours(L, i, j);
+    const bool hx = L.has_x, hy = L.has_y;
+    const long long S = L.S;
+    const long long plane = (long long)L.nx * L.ny;
+    const long long oc = (long long)j * L.nx + i;
+    const long long oo = (long long)(1 - c) * L.cs, os = (long long)c * L.cs + m;
+    const int nz = L.nz, P = L.P;
+    auto val = [&](long long idx) -> double { return with_p ? us[idx] + alpha * p[idx] : us[idx]; };
+    double uc = val(os + (long long)k0 * S);
+    double um = k0 > 0 ? val(os + (long long)(k0 - 1) * S) : uc;
+    int k = k0;
+    for (; k < k1; k += U) {
+      double up[U], uw[U], ue[U], usv[U], un[U], fv[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        const int kk = min(k + t, k1 - 1);
+        const long long o = (long long)kk * S;
+        up[t] = val(os + (long long)min(kk + 1, nz - 1) * S);
+        uw[t] = hx ? val(oo + nb.w + o) : 0.0;
+        ue[t] = hx ? val(oo + nb.e + o) : 0.0;
+        usv[t] = hy ? val(oo + nb.s + o) : 0.0;
+        un[t] = hy ? val(oo + nb.n + o) : 0.0;
+        fv[t] = f[(long long)kk * plane + oc];
+      }
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        if (k + t < k1) {
+          const int kk = k + t;
+          const double acc = op_row(tab, P, kk, hx, hy, uc, um, up[t], uw[t], ue[t], usv[t], un[t]);
+          const double b = vol[kk] * fv[t];
+          const double res = b - acc;
+          u[(long long)kk * plane + oc] = uc;
+          bb += b * b;
+          rr += res * res;
+          um = uc;
+          uc = up[t];
+        }
+      }
+    }
+  }
+  const double s0 = block_sum(bb, sh);
+  const double s1 = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * lb] = s0;
+    partial[2 * lb + 1] = s1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_begin(Geo L, const double *__restrict__ tab,
+                                                  const double *__restrict__ vol,
+                                                  const double *__restrict__ f,
+                                                  const double *__restrict__ u0,
+                                                  double *__restrict__ us, double *__restrict__ r,
+                                                  double *__restrict__ partial) {
+  begin_body(L, tab, vol, f, u0, us, r, partial, logical_block());
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish(Geo L, const double *__restrict__ tab,
+                                                   const double *__restrict__ vol,
+                                                   const double *__restrict__ f,
+                                                   const double *__restrict__ us,
+                                                   const double *__restrict__ p,
+                                                   const PcgState *__restrict__ st, int with_p,
+                                                   double *__restrict__ u, double *__restrict__ partial) {
+  finish_body(L, tab, vol, f, us, p, with_p ? st->alpha : 0.0, with_p, u, partial, logical_block());
+}
+
+// -------------------------------------------------------------------------
 // CG vector kernels (FP64, flat over the split vectors; padding entries stay
 // zero).  Each block writes its partial sums; k_finalize reduces them in a
 // fixed order, so every result is independent of scheduling.
@@ -1159,6 +1354,9 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
       } else if (r0 == 0.0 || r0 < th) {
         st->done = 1;
         st->status = 0;
+      } else if (st->maxiter <= 0) {
+        st->done = 1;
+        st->status = 1;
       } else {
         st->done = 0;
         st->status = 1;
@@ -1186,6 +1384,11 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
     }
     case F_BETA: {
       const double kappa = tot[0];
+      if (st->iter == 0) {  // first preconditioned residual: kappa_0 = <r_0, z_0>
+        st->kappa_old = kappa;
+        if (!isfinite(kappa)) { st->done = 1; st->status = -4; }
+        break;
+      }
       const double beta = st->flexible ? -st->alpha * tot[1] / st->kappa_old : kappa / st->kappa_old;
       st->beta = beta;
       st->kappa_old = kappa;
