@@ -83,10 +83,19 @@ inline int batch_flat_blocks(long long n2) {
   return (int)std::max<long long>(b, 1);
 }
 
+// k-segments of the tiled CG operator step: enough blocks to occupy the chip
+// on thin grids, few enough that the two extra levels a segment reads at its
+// ends stay a small fraction.
+inline int apply_segments(int nz) { return nz >= 64 ? 4 : (nz >= 32 ? 2 : 1); }
+inline long long tile_blocks(const Geo &G, int nseg) {
+  return G.has_x && G.has_y ? (long long)tile_count(G.hx2, G.ny) * nseg : 0;
+}
+
 // Blocks whose partial sums one grid's reduction buffer must hold.
-inline long long partial_blocks(long long n0, int H0) {
-  return std::max<long long>(std::max<long long>(seg_blocks(2LL * H0), flat_blocks(n0 / 2)),
-                             batch_flat_blocks(n0 / 2));
+inline long long partial_blocks(const Geo &G0, long long n0) {
+  long long b = std::max<long long>(seg_blocks(2LL * G0.H), flat_blocks(n0 / 2));
+  b = std::max<long long>(b, batch_flat_blocks(n0 / 2));
+  return std::max<long long>(b, blocks8(tile_blocks(G0, 4) * kBlock));
 }
 
 bool can_halve(int n) { return n % 2 == 0 && ((n / 2) % 2 == 0 || n / 2 == 1); }
@@ -145,6 +154,8 @@ struct ell_grid {
   double *vol0 = nullptr;               // level-0 cell volumes (FP64, nz)
   const double *tab64_0 = nullptr;      // level-0 FP64 table of the CG operator
   int stencil_seg = 1;                  // k-segments of the CG operator kernels
+  int apply_tile = 0;                   // the CG operator step uses the LDS-tiled kernel
+  int apply_nseg = 1;                   // its k-segments
   double *partial = nullptr;
   long long partial_cap = 0;
   PcgState *st = nullptr;
@@ -178,6 +189,7 @@ int dalloc(ell_grid *g, void **p, size_t bytes) {
 int g_plane_pad = 64;
 int g_colour_pad = 256;
 int g_stencil_seg = 1;  // k-segments of the CG operator kernels (1, 2 or 4)
+int g_apply_tile = 1;   // 1: LDS-tiled CG operator step where both horizontal directions exist
 
 // Smoother segments per column: enough lanes to occupy the chip on small
 // levels, four (the register-resident optimum) on large ones; the finest
@@ -339,7 +351,7 @@ size_t grid_bytes(const ell_grid_desc *d, int L) {
     bytes += (size_t)TSLOTS * G.P * es;
     if (l > 0) bytes += 2 * 2 * (size_t)G.cs * es;
   }
-  const long long nb = partial_blocks(n0, g0.H);
+  const long long nb = partial_blocks(g0, n0);
   bytes += (size_t)nb * 2 * 8 + sizeof(PcgState) + (size_t)d->nz * 8;
   return bytes;
 }
@@ -653,6 +665,12 @@ const typename Vec2<Z>::T *zvec(const ell_grid *g) {
 // Start of a solve (Appendix B, Alg. PCG, before the loop): r = V f - A u0
 // with ||b|| and ||r0|| (the device sets done if nothing is left to do),
 // z0 = M^{-1} r0, kappa = <r0, z0>.
+// Blocks of the CG operator step of a grid (single-grid launch).
+int apply_dir_blocks(const ell_grid *g) {
+  const Geo &G = g->lev[0].geo;
+  return g->apply_tile ? blocks8(tile_blocks(G, g->apply_nseg) * kBlock) : stencil_blocks(2LL * G.H, g->stencil_seg);
+}
+
 // Caller-facing statistics of a finished solve; the return code follows the
 // final status (0 converged, 1 iteration limit, -4 non-finite recurrence).
 int stats_from_state(const PcgState &h, ell_solve_stats *out) {
@@ -700,14 +718,17 @@ int pcg_step(ell_grid *g, int K, hipStream_t s) {
   const Geo &G = g->lev[0].geo;
   const long long n2 = g->n0 / 2;
   const int fb = flat_blocks(n2);
-  const int ab = stencil_blocks(2LL * G.H, g->stencil_seg);  // blocks of the CG operator kernel
+  const int ab = apply_dir_blocks(g);  // blocks of the CG operator kernel
   const int *done = &g->st->done;
   double *pbuf[2] = {g->p, g->p2};
   {
     ProfScope ps(g, ELL_K_APPLY, s);
     const int first = K == 1 ? 1 : 0, defer = K > 1 ? 1 : 0;
     const Z *zz = (const Z *)zvec<Z>(g);
-    if (g->stencil_seg == 1)
+    if (g->apply_tile)
+      k_apply_dir_tile<Z><<<ab, kBlock, 0, s>>>(G, g->apply_nseg, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1],
+                                                g->q, g->us, g->st, first, defer, g->partial);
+    else if (g->stencil_seg == 1)
       k_apply_dir<Z, 1><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us,
                                               g->st, first, defer, g->partial);
     else if (g->stencil_seg == 2)
@@ -808,6 +829,8 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->prec = desc->precision;
   g->esz = g->prec == ELL_FP64 ? 8 : 4;
   g->stencil_seg = batch_layout ? 1 : g_stencil_seg;
+  g->apply_tile = (g_apply_tile && desc->nx > 1 && desc->ny > 1) ? 1 : 0;
+  g->apply_nseg = apply_segments(desc->nz);
   g->batch_layout = batch_layout;
   g->lev.resize(L);
   auto bail = [&](int rc) {
@@ -861,7 +884,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   }
   if (desc->rho != 1.0)
     if ((rc = dalloc(g, &g->ybuf, (size_t)G0.cs * g->esz)) != ELL_OK) return bail(rc);
-  const long long nb = partial_blocks(g->n0, G0.H);
+  const long long nb = partial_blocks(G0, g->n0);
   g->partial_cap = nb * 2;
   if ((rc = dalloc(g, &tmp, (size_t)g->partial_cap * 8)) != ELL_OK) return bail(rc);
   g->partial = (double *)tmp;
@@ -1091,6 +1114,10 @@ int ell_set_tuning(int key, int value) {
     case ELL_TUNE_STENCIL_SEG:
       if (value != 1 && value != 2 && value != 4) return fail(ELL_ERR_INVALID, "segments must be 1, 2 or 4");
       g_stencil_seg = value;
+      return ELL_OK;
+    case ELL_TUNE_APPLY_TILE:
+      if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "apply tiling is 0 or 1");
+      g_apply_tile = value;
       return ELL_OK;
     default: return fail(ELL_ERR_INVALID, "unknown tuning key %d", key);
   }

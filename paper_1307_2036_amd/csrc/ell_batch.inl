@@ -43,6 +43,7 @@ struct GridDev {
   long long n2;
   int L, nb_apply, nb_flat, prolong;
   int nb_begin, nb_finish;  // blocks of the start / end kernels (partial sums each)
+  int apply_tile, apply_nseg;  // CG operator step: LDS-tiled kernel and its k-segments
 };
 
 struct StageEnt {
@@ -195,8 +196,14 @@ __global__ __launch_bounds__(kBlock) void kb_apply_dir(const StageEnt *__restric
   const int K = ui(st->iter) + 1;  // iteration about to run
   double *pold = gp(((K - 1) & 1) ? gd->p2 : gd->p);
   double *pnew = gp((K & 1) ? gd->p2 : gd->p);
-  apply_dir_body<double, 1>(ugeo(gd->lev[0].geo), gp(gd->tab64_0), gp(gd->z), pold, pnew, gp(gd->q), gp(gd->us),
-                            st, K == 1 ? 1 : 0, K > 1 ? 1 : 0, gp(gd->partial), ui(bg - ents[e].block0), 0);
+  if (ui(gd->apply_tile))
+    apply_dir_tile_body<double>(ugeo(gd->lev[0].geo), ui(gd->apply_nseg), gp(gd->tab64_0), gp(gd->z), pold, pnew,
+                                gp(gd->q), gp(gd->us), st, K == 1 ? 1 : 0, K > 1 ? 1 : 0, gp(gd->partial),
+                                ui(bg - ents[e].block0));
+  else
+    apply_dir_body<double, 1>(ugeo(gd->lev[0].geo), gp(gd->tab64_0), gp(gd->z), pold, pnew, gp(gd->q),
+                              gp(gd->us), st, K == 1 ? 1 : 0, K > 1 ? 1 : 0, gp(gd->partial),
+                              ui(bg - ents[e].block0), 0);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_update_r(const StageEnt *__restrict__ ents, int nent, int total) {
@@ -278,6 +285,12 @@ __global__ void kb_gather_states(const StageEnt *__restrict__ ents, int nent, Pc
 // ------------------------------------------------------------------------
 // Blocks of the start (64 plane-major columns each) and end (64 split slots
 // each) kernels of one grid inside a grouped launch.
+// Blocks of one grid in the grouped CG operator step.
+int batch_apply_blocks(const ell_grid *g) {
+  const Geo &G = g->lev[0].geo;
+  return g->apply_tile ? (int)tile_blocks(G, g->apply_nseg) : stencil_blocks(2LL * G.H, 1);
+}
+
 int begin_blocks(const ell_grid *g) {
   const Geo &G = g->lev[0].geo;
   return (int)(((long long)G.nx * G.ny + kSegCols - 1) / kSegCols);
@@ -307,7 +320,9 @@ int grid_dev_build(ell_grid *g) {
   h.st = g->st;
   h.n2 = g->n0 / 2;
   h.L = g->L;
-  h.nb_apply = stencil_blocks(2LL * g->lev[0].geo.H, 1);
+  h.apply_tile = g->apply_tile;
+  h.apply_nseg = g->apply_nseg;
+  h.nb_apply = batch_apply_blocks(g);
   h.nb_flat = batch_flat_blocks(h.n2);
   h.prolong = g->d.prolong;
   h.nb_begin = begin_blocks(g);
@@ -461,7 +476,7 @@ int batch_build(ell_batch *b) {
   for (Request *r : A) all.push_back(r->g);
   auto one = [](ell_grid *) { return 1; };
   auto flat = [](ell_grid *g) { return batch_flat_blocks(g->n0 / 2); };
-  auto apply = [](ell_grid *g) { return stencil_blocks(2LL * g->lev[0].geo.H, 1); };
+  auto apply = [](ell_grid *g) { return batch_apply_blocks(g); };
   auto cols = [](int l, int c) {
     return [l, c](ell_grid *g) {
       const Geo &G = g->lev[l].geo;

@@ -1002,6 +1002,180 @@ __global__ __launch_bounds__(kBlock) void k_cast_f64_f32(const double2 *__restri
 }
 
 // -------------------------------------------------------------------------
+// The same fused operator step on horizontal tiles staged in LDS.  A block
+// owns a tile of kTX x kTY columns per colour (64 x 16 plane-major columns)
+// over one k-segment and walks it level by level.  The direction values
+// p = z + beta p_old of a level, for the tile and its one-cell horizontal
+// halo, are formed once and put in LDS; the horizontal neighbours are read
+// from there and the vertical ones from registers, so each z and p_old value
+// is fetched by one block (halo values by two) instead of by up to five
+// wavefronts at different times.  LDS holds the tile per colour in the split
+// order (row-major, m-contiguous), so lanes of a wavefront touch consecutive
+// LDS words and consecutive memory.  Three LDS buffers rotate: one barrier
+// per level separates the writes of level k+1 from the reads of level k.
+// Requires nx and ny even (both horizontal directions present).  Blocks
+// (tiles x segments) past the end write zero partial sums.
+// -------------------------------------------------------------------------
+constexpr int kTX = 32;  // tile width per colour (m-columns)
+constexpr int kTY = 16;  // tile rows
+constexpr int kTW = kTX + 2, kTH = kTY + 2;
+
+__host__ __device__ inline int tile_count(int hx2, int ny) {
+  return ((hx2 + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
+}
+
+template <typename Z>
+__device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const double *__restrict__ tab,
+                                                    const Z *__restrict__ z,
+                                                    const double *__restrict__ pold,
+                                                    double *__restrict__ pnew, double *__restrict__ q,
+                                                    double *__restrict__ u,
+                                                    const PcgState *__restrict__ st, int first,
+                                                    int defer_u, double *__restrict__ partial, int lb) {
+  __shared__ double sp[3][2][kTH][kTW];
+  __shared__ double sh[4];
+  if (st->done) return;
+  const double beta = first ? 0.0 : st->beta;
+  const double alpha = st->alpha;
+  const int tiles_x = (L.hx2 + kTX - 1) / kTX;
+  const int per_seg = tile_count(L.hx2, L.ny);
+  const int sg = lb / per_seg, tt = lb - sg * per_seg;
+  const int ty = tt / tiles_x, tx = tt - ty * tiles_x;
+  const int Ls = seg_len(L.nz, nseg);
+  const int k0 = min(sg * Ls, L.nz), k1 = min(k0 + Ls, L.nz);
+  double dot = 0.0;
+  if (k1 > k0) {
+    const int t = threadIdx.x;
+    const int mx0 = tx * kTX, j0 = ty * kTY;
+    const int nxm = min(kTX, L.hx2 - mx0);  // valid m-columns of the tile
+    const int nyr = min(kTY, L.ny - j0);    // valid rows of the tile
+    const int x = t & 31, r0 = t >> 5;      // own cells: rows r0 and r0 + 8, both colours
+    const long long S = L.S, cs = L.cs;
+    long long off[4];
+    bool ok[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = e & 1, rr = r0 + 8 * (e >> 1);
+      ok[e] = x < nxm && rr < nyr;
+      off[e] = (long long)c * cs + (long long)(j0 + rr) * L.hx2 + mx0 + x;
+    }
+    // one halo cell per thread for threads 0..159: rows below / above the
+    // tile (both colours), then the cells left / right of each row
+    bool hok = false;
+    long long hoff = 0;
+    int hc = 0, hr = 0, hx = 0;
+    if (t < 128) {
+      const int side = t >> 6, c = (t >> 5) & 1, xx = t & 31;
+      const int j = side ? wrapi(j0 + nyr, L.ny) : wrapi(j0 - 1, L.ny);
+      hok = xx < nxm;
+      hoff = (long long)c * cs + (long long)j * L.hx2 + mx0 + xx;
+      hc = c;
+      hr = side ? nyr + 1 : 0;
+      hx = xx + 1;
+    } else if (t < 160) {
+      const int side = (t - 128) >> 4, rr = (t - 128) & 15;
+      const int j = j0 + rr;
+      const int i = side ? wrapi(2 * (mx0 + nxm), L.nx) : wrapi(2 * mx0 - 1, L.nx);
+      const int c = (i + j) & 1;
+      hok = rr < nyr;
+      hoff = (long long)c * cs + (long long)j * L.hx2 + (i >> 1);
+      hc = c;
+      hr = rr + 1;
+      hx = side ? nxm + 1 : 0;
+    }
+    auto dirv = [&](long long idx) -> double {
+      return first ? (double)z[idx] : (double)z[idx] + beta * pold[idx];
+    };
+    // level k: own direction values into pv (and LDS buffer b when b >= 0);
+    // with write set, also p_new and the deferred solution update
+    auto level = [&](int k, int b, bool write, double *pv) {
+      const long long o = (long long)k * S;
+      double zv[4], po[4], uu[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        zv[e] = ok[e] ? (double)z[off[e] + o] : 0.0;
+        po[e] = (ok[e] && !first) ? pold[off[e] + o] : 0.0;
+        uu[e] = (ok[e] && write && defer_u) ? u[off[e] + o] : 0.0;
+      }
+      double hv = 0.0;
+      if (b >= 0 && hok) hv = dirv(hoff + o);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double pvv = first ? zv[e] : zv[e] + beta * po[e];
+        pv[e] = pvv;
+        // only valid cells: in a partial tile the slots past the last valid
+        // row / m-column hold the halo
+        if (b >= 0 && ok[e]) sp[b][e & 1][r0 + 8 * (e >> 1) + 1][x + 1] = pvv;
+        if (ok[e] && write) {
+          pnew[off[e] + o] = pvv;
+          if (defer_u) u[off[e] + o] = uu[e] + alpha * po[e];
+        }
+      }
+      if (b >= 0 && hok) sp[b][hc][hr][hx] = hv;
+    };
+    const double *__restrict__ tv = tab + TV * L.P;
+    const double *__restrict__ txv = tab + TX * L.P;
+    const double *__restrict__ tyv = tab + TY * L.P;
+    const double *__restrict__ tz = tab + TZ * L.P;
+    double pm[4], pc[4], pn[4];
+    level(k0, k0 % 3, true, pc);
+    if (k0 > 0) level(k0 - 1, -1, false, pm);
+    else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) pm[e] = pc[e];
+    }
+    for (int k = k0; k < k1; ++k) {
+      if (k + 1 < k1) level(k + 1, (k + 1) % 3, true, pn);
+      else if (k + 1 < L.nz) level(k + 1, -1, false, pn);
+      else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) pn[e] = pc[e];
+      }
+      __syncthreads();
+      const int b = k % 3;
+      const long long o = (long long)k * S;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (ok[e]) {
+          const int c = e & 1, rr = r0 + 8 * (e >> 1);
+          const int par = (j0 + rr + c) & 1;  // 1: the cell sits at an odd i
+          const double(*oth)[kTW] = sp[b][1 - c];
+          const double pw = oth[rr + 1][x + par];
+          const double pe = oth[rr + 1][x + 1 + par];
+          const double ps = oth[rr][x + 1];
+          const double pnn = oth[rr + 2][x + 1];
+          const double pcv = pc[e];
+          double acc = tv[k] * pcv;
+          acc = acc + txv[k] * (pcv - pw);
+          acc = acc + txv[k] * (pcv - pe);
+          acc = acc + tyv[k] * (pcv - ps);
+          acc = acc + tyv[k] * (pcv - pnn);
+          acc = acc + tz[k] * (pcv - pm[e]);
+          acc = acc + tz[k + 1] * (pcv - pn[e]);
+          q[off[e] + o] = acc;
+          dot += pcv * acc;
+        }
+        pm[e] = pc[e];
+        pc[e] = pn[e];
+      }
+    }
+  }
+  const double s = block_sum(dot, sh);
+  if (threadIdx.x == 0) partial[lb] = s;
+}
+
+template <typename Z>
+__global__ __launch_bounds__(kBlock) void k_apply_dir_tile(Geo L, int nseg, const double *__restrict__ tab,
+                                                           const Z *__restrict__ z,
+                                                           const double *__restrict__ pold,
+                                                           double *__restrict__ pnew, double *__restrict__ q,
+                                                           double *__restrict__ u,
+                                                           const PcgState *__restrict__ st, int first,
+                                                           int defer_u, double *__restrict__ partial) {
+  apply_dir_tile_body<Z>(L, nseg, tab, z, pold, pnew, q, u, st, first, defer_u, partial, logical_block());
+}
+
+// -------------------------------------------------------------------------
 // Start and end of a solve, one pass each (Appendix B, Alg. PCG: initial
 // residual, final solution).  Both evaluate the operator exactly as the
 // split-layout operator kernel does (same terms in the same order), with

@@ -147,7 +147,7 @@ def make_desc(nx, ny, nz, hx, hy, omega2, dz, lambda2, n_levels=0, nu_pre=1, nu_
     return d, (dz, lam)
 
 
-ELL_TUNE_PLANE_PAD, ELL_TUNE_COLOUR_PAD, ELL_TUNE_STENCIL_SEG = 0, 1, 2
+ELL_TUNE_PLANE_PAD, ELL_TUNE_COLOUR_PAD, ELL_TUNE_STENCIL_SEG, ELL_TUNE_APPLY_TILE = 0, 1, 2, 3
 
 
 def set_tuning(key: int, value: int) -> None:

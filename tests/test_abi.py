@@ -68,3 +68,30 @@ def test_binding_fails_loudly_without_library(tmp_path):
             ell.load_library(str(tmp_path / "missing.so"))
     finally:
         ell._lib = saved
+
+
+def test_grid_create_without_gpu_fails_cleanly():
+    """Creating a grid (and a batch grid) on a host without a usable GPU returns
+    an error code with a message instead of crashing; run in a child process so
+    that a crash fails this test only."""
+    import subprocess
+    import sys
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present: creation succeeds there")
+    code = r"""
+import ctypes, sys
+import numpy as np
+sys.path.insert(0, %r)
+from paper_1307_2036_amd import ell
+L = ell.load_library()
+for kw in (dict(nx=32, ny=32, nz=16), dict(nx=1, ny=1, nz=5), dict(nx=2, ny=6, nz=70)):
+    nz = kw["nz"]
+    d, keep = ell.make_desc(hx=0.1, hy=0.1, omega2=1e-2, dz=np.full(nz, 0.1), lambda2=np.full(nz, 1.0), **kw)
+    h = ctypes.c_void_p()
+    rc = L.ell_grid_create(ctypes.byref(d), ctypes.byref(h))
+    assert rc < 0 and not h.value and L.ell_last_error(), rc
+print("clean")
+""" % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0 and "clean" in out.stdout, out.stderr[-2000:]

@@ -279,6 +279,38 @@ def test_solve_edge_cases(ell, orc):
     np.testing.assert_array_equal(host(ua), host(ub))
 
 
+# Shapes for the CG operator step: partial tiles in x and y (tiles are 64 x 16
+# plane-major columns), uneven k-segments (nz = 70: four segments of 18, 18,
+# 18, 16 levels), the smallest periodic grid (2 x 2) and a one-tile-wide one.
+# The iteration counts stop each solve while its residual is still far above
+# rounding (the 2 x 2 and 4 x 6 grids converge within a few iterations).
+TILE_SHAPES = [((130, 38, 7), 6), ((34, 10, 33), 6), ((2, 2, 3), 2), ((4, 6, 70), 3),
+               ((66, 18, 64), 6), ((64, 16, 5), 6)]
+
+
+@pytest.mark.parametrize("shape,K", TILE_SHAPES)
+def test_operator_step_tiles_fixed_iterations(ell, orc, shape, K):
+    """K CG iterations (none converges) match the oracle's K, on the LDS-tiled
+    operator step and on the column-walking one."""
+    g = small_grid(orc, *shape, seed=5 + sum(shape), graded=False)
+    f = np.random.default_rng(3).standard_normal(g.shape)
+    f -= f.mean()
+    u_ref, st_ref = orc.pcg(g, f, rtol=1e-30, maxiter=K)
+    got = {}
+    for tile in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_APPLY_TILE, tile)
+        try:
+            G = gpu_grid(ell, g)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_APPLY_TILE, 1)
+        u, st = G.pcg_solve(dev(f), rtol=1e-30, maxiter=K)
+        assert st.iters == st_ref["iters"] == K and st.status == ell.ELL_NOT_CONVERGED
+        got[tile] = host(u)
+        assert rel(got[tile], u_ref) <= 1e-12, (tile, rel(got[tile], u_ref))
+        assert abs(st.r_norm / st_ref["r_norm"] - 1) <= 1e-9
+    assert rel(got[1], got[0]) <= 1e-13
+
+
 def test_single_column_solve(ell, orc):
     g = small_grid(orc, 1, 1, 40, seed=2, graded=False)
     G = gpu_grid(ell, g)
