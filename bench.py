@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--workload", default="c1", choices=["c1", "batch", "serve"],
                     help="c1: the 512^2x128 solve (default); batch: 64 uneven solves in the "
                          "batch engine vs sequential FP64; serve: Poisson request stream")
+    ap.add_argument("--batch-graph", type=int, default=1, choices=[0, 1],
+                    help="batch/serve: replay each grouped step from a captured HIP graph (1) "
+                         "or launch its kernels directly (0)")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured closed-loop capacity")
@@ -220,6 +223,7 @@ def bench_batch(a):
     fs = [torch.from_numpy(p.f).cuda() for p in ps]
     n_total = sum(p.n for p in ps)
     prec = "fp32" if a.precision == "fp64" else a.precision
+    ell.set_tuning(ell.ELL_TUNE_BATCH_GRAPH, a.batch_graph)
     B = ell.Batch(200 << 30)
     grids = [B.grid(p, precision=prec) for p in ps]
     us = [torch.zeros_like(f) for f in fs]
@@ -251,7 +255,7 @@ def bench_batch(a):
         "data": "synthetic (64 seeded uneven instances)",
         "config": {"workload": "batch of 64 uneven gmg-pcg solves (nx in {64,96,128,192,256}, "
                                "nz in {64,96,128}, log-uniform omega2), grouped launches",
-                   "unknowns_total": n_total, "precision": prec},
+                   "unknowns_total": n_total, "precision": prec, "graph": a.batch_graph},
         "unknowns_iter_per_s": float(np.sum([p.n * it for p, it in zip(ps, iters)]) * a.steps / elapsed),
         "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
         "batch_ms_p50": float(np.percentile(np.array(lat) * 1e3, 50)),
@@ -275,6 +279,7 @@ def bench_serve(a):
     rng = np.random.default_rng(inputs.seed_for(4))
     sizes = [256] * 17 + [512] * 6 + [1024]
     prec = "fp32" if a.precision == "fp64" else a.precision
+    ell.set_tuning(ell.ELL_TUNE_BATCH_GRAPH, a.batch_graph)
     B = ell.Batch(200 << 30)
     streams = []
     gen = torch.Generator(device="cuda")
@@ -372,7 +377,8 @@ def bench_serve(a):
         "data": "synthetic (seeded Poisson arrivals, fresh N(0,1) f per request)",
         "config": {"workload": "serving: 24 streams (17x256^2, 6x512^2, 1x1024^2, nz=128), "
                                "Poisson arrivals, warm starts, continuous batching, 200 GB budget",
-                   "arrival_rate_per_s": rate, "load": a.serve_load, "precision": prec},
+                   "arrival_rate_per_s": rate, "load": a.serve_load, "precision": prec,
+                   "graph": a.batch_graph},
         "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
         "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
         "closed_loop_capacity_solves_per_s": capacity,

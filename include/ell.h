@@ -199,8 +199,16 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * added to the plane stride S and to the colour stride C; k-segments (1, 2
  * or 4) of the column-walking CG operator kernels; APPLY_TILE 1 (default) runs
  * the CG operator step of grids with nx, ny > 1 on LDS-staged horizontal
- * tiles, 0 on the column-walking kernel. */
-enum { ELL_TUNE_PLANE_PAD = 0, ELL_TUNE_COLOUR_PAD = 1, ELL_TUNE_STENCIL_SEG = 2, ELL_TUNE_APPLY_TILE = 3 };
+ * tiles, 0 on the column-walking kernel; BATCH_GRAPH 1 (default) makes batch
+ * engines created afterwards replay each grouped step from a captured HIP
+ * graph, 0 launches the kernels directly (same results, bitwise). */
+enum {
+  ELL_TUNE_PLANE_PAD = 0,
+  ELL_TUNE_COLOUR_PAD = 1,
+  ELL_TUNE_STENCIL_SEG = 2,
+  ELL_TUNE_APPLY_TILE = 3,
+  ELL_TUNE_BATCH_GRAPH = 4
+};
 int ell_set_tuning(int key, int value);
 
 /* ---- batched solves and serving (beyond the paper) ---------------------------

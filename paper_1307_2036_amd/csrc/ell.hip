@@ -190,6 +190,7 @@ int g_plane_pad = 64;
 int g_colour_pad = 256;
 int g_stencil_seg = 1;  // k-segments of the CG operator kernels (1, 2 or 4)
 int g_apply_tile = 1;   // 1: LDS-tiled CG operator step where both horizontal directions exist
+int g_batch_graph = 1;  // 1: batch engines replay each grouped step from a captured graph
 
 // Smoother segments per column: enough lanes to occupy the chip on small
 // levels, four (the register-resident optimum) on large ones; the finest
@@ -1118,6 +1119,10 @@ int ell_set_tuning(int key, int value) {
     case ELL_TUNE_APPLY_TILE:
       if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "apply tiling is 0 or 1");
       g_apply_tile = value;
+      return ELL_OK;
+    case ELL_TUNE_BATCH_GRAPH:
+      if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "batch graphs are 0 or 1");
+      g_batch_graph = value;
       return ELL_OK;
     default: return fail(ELL_ERR_INVALID, "unknown tuning key %d", key);
   }

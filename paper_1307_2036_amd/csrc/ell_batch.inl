@@ -401,6 +401,9 @@ struct ell_batch {
   void *d_tx = nullptr;  // start / end tables (request records + entries)
   void *h_tx = nullptr;  // pinned staging
   size_t tx_cap = 0;
+  // one grouped step captured as a graph (rebuilt with the stage tables)
+  bool use_graph = true;
+  hipGraphExec_t gexec = nullptr;
   bool dirty = true;
   int prec = -1;
   std::string last_error;
@@ -677,7 +680,6 @@ int batch_step(ell_batch *b) {
     }
     CHK(check_launch("batched stage"));
   }
-  b->steps++;
   return ELL_OK;
 }
 
@@ -722,6 +724,47 @@ int batch_edge(ell_batch *b, const std::vector<Request *> &rs, bool start) {
   CHK(check_launch("kb_gather_states"));
   HIPCHK(hipMemcpyAsync(b->h_states, b->d_states, n * sizeof(PcgState), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
+  return ELL_OK;
+}
+
+void drop_graph(ell_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+}
+
+// Enqueue n grouped steps.  With graphs on, the step's launches are captured
+// once per stage table (the tables, and with them every kernel argument, only
+// change in batch_build) and the instantiated graph is launched n times; the
+// step holds kernel launches only (no memset or copy nodes).  A capture that
+// fails switches the batch to direct launches.
+int batch_steps(ell_batch *b, int n) {
+  hipStream_t s = b->stream;
+  if (b->use_graph && !b->gexec) {
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      b->use_graph = false;
+    } else {
+      const int rc = batch_step(b);
+      const hipError_t e = hipStreamEndCapture(s, &graph);
+      if (rc != ELL_OK || e != hipSuccess || !graph ||
+          hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        b->gexec = nullptr;
+        b->use_graph = false;
+      }
+      if (graph) (void)hipGraphDestroy(graph);
+    }
+  }
+  for (int k = 0; k < n; ++k) {
+    if (b->gexec) {
+      HIPCHK(hipGraphLaunch(b->gexec, s));
+      b->steps++;
+    } else {
+      CHK(batch_step(b));
+      b->steps++;
+    }
+  }
   return ELL_OK;
 }
 
@@ -778,11 +821,14 @@ void worker_loop(ell_batch *b) {
       b->dirty = true;
     }
     if (b->active.empty()) continue;
-    if (b->dirty && (rc = batch_build(b)) != ELL_OK) {
-      fail_all(b, b->active, rc);
-      continue;
+    if (b->dirty) {
+      drop_graph(b);
+      if ((rc = batch_build(b)) != ELL_OK) {
+        fail_all(b, b->active, rc);
+        continue;
+      }
     }
-    for (int k = 0; k < b->poll_every && rc == ELL_OK; ++k) rc = batch_step(b);
+    rc = batch_steps(b, b->poll_every);
     // gather the states of the active grids with one copy
     const int n = (int)b->active.size();
     if (rc == ELL_OK) {
@@ -834,6 +880,7 @@ int ell_batch_create(size_t hbm_budget_bytes, ell_batch **out) {
   *out = nullptr;
   ell_batch *b = new ell_batch();
   b->budget = hbm_budget_bytes;
+  b->use_graph = g_batch_graph != 0;
   if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) {
     delete b;
     return fail(ELL_ERR_HIP, "stream creation failed");
@@ -976,6 +1023,7 @@ int ell_batch_destroy(ell_batch *b) {
   if (b->h_ents) (void)hipHostFree(b->h_ents);
   if (b->d_states) (void)hipFree(b->d_states);
   if (b->h_states) (void)hipHostFree(b->h_states);
+  drop_graph(b);
   if (b->d_tx) (void)hipFree(b->d_tx);
   if (b->h_tx) (void)hipHostFree(b->h_tx);
   if (b->stream) (void)hipStreamDestroy(b->stream);

@@ -142,3 +142,34 @@ def test_poll_pending_then_done(E):
     assert res is not None and res[0].status == 0
     B.wait(t)
     B.close()
+
+
+def test_graph_replays_equal_direct_launches(E):
+    """Grouped steps replayed from captured graphs give the same bits as direct
+    launches.  Each batch replays its graphs many times (two steps per poll,
+    a new capture whenever a grid converges and leaves), with other GPU work and
+    synchronisations between the solves; every result is compared."""
+    ps = problems()
+    res = {}
+    for graph in (0, 1):
+        E.set_tuning(E.ELL_TUNE_BATCH_GRAPH, graph)
+        try:
+            B = E.Batch(8 << 30)
+        finally:
+            E.set_tuning(E.ELL_TUNE_BATCH_GRAPH, 1)
+        grids = [B.grid(p, precision="fp32") for p in ps]
+        out = []
+        for rep in range(3):
+            fs = [dev(p.f * (1.0 + 0.5 * rep)) for p in ps]
+            us = [torch.zeros_like(f) for f in fs]
+            noise = torch.randn(1 << 20, device="cuda", dtype=torch.float64).sum()
+            st = B.wait(B.submit(grids, fs, us, poll_every=2))
+            torch.cuda.synchronize()
+            assert torch.isfinite(noise)
+            out.append(([host(u) for u in us], [s.iters for s in st]))
+        res[graph] = out
+        B.close()
+    for (u0, i0), (u1, i1) in zip(res[0], res[1]):
+        assert i0 == i1
+        for a, b in zip(u0, u1):
+            np.testing.assert_array_equal(a, b)
