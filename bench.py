@@ -36,6 +36,9 @@ def parse():
     ap.add_argument("--workload", default="c1", choices=["c1", "batch", "serve"],
                     help="c1: the 512^2x128 solve (default); batch: 64 uneven solves in the "
                          "batch engine vs sequential FP64; serve: Poisson request stream")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the schedule autotuner on the workload's grid shape(s) before timing "
+                         "(outside the timed region) and report the chosen schedule")
     ap.add_argument("--batch-graph", type=int, default=1, choices=[0, 1],
                     help="batch/serve: replay each grouped step from a captured HIP graph (1) "
                          "or launch its kernels directly (0)")
@@ -47,6 +50,13 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum seconds of oracle work in the CPU-baseline sample")
     return ap.parse_args()
+
+
+def _desc_kw(p, precision):
+    """Grid descriptor arguments of a seeded problem."""
+    return dict(nx=p.nx, ny=p.ny, nz=p.nz, hx=p.hx, hy=p.hy, omega2=p.omega2, dz=p.dz,
+                lambda2=p.lambda2, n_levels=p.n_levels, nu_pre=p.nu_pre, nu_post=p.nu_post,
+                nu_coarse=p.nu_coarse, rho=p.rho, prolong=p.prolong, precision=precision)
 
 
 def counter_traffic(precision: str):
@@ -99,6 +109,8 @@ def main():
 
     torch.cuda.set_device(0)
     p = inputs.config1(n_levels=a.levels, nu_coarse=a.nu_coarse, nx=a.nx)
+    schedule = ell.autotune(iters=4, **_desc_kw(p, a.precision)) if a.autotune else \
+        ell.schedule_get(**_desc_kw(p, a.precision))
     G = ell.Grid.from_problem(p, precision=a.precision)
     f = torch.from_numpy(p.f).cuda()
     u = torch.zeros_like(f)
@@ -146,8 +158,10 @@ def main():
                     else perfmodel.smooth0_launch_bytes_hybrid(n))
     avg_ms = float(t_s.mean())
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
-    # the CG operator step reads z, p_old, u and writes p_new, q, u (48 B per unknown)
-    apply_gbs = 48 * n / (float(t_a.mean()) * 1e-3) / 1e9
+    # the CG operator step reads z, p_old, u and writes p_new, q, u (48 B per unknown);
+    # the first iteration of a solve reads z only and writes p_new, q (24 B)
+    apply_bytes = (24 + 48 * (iters - 1)) / iters * n
+    apply_gbs = apply_bytes / (float(t_a.mean()) * 1e-3) / 1e9
     cnt = int(t_s.size)
 
     solves = a.steps / elapsed
@@ -180,8 +194,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(a.precision),
                      "avg_launch_us": avg_ms * 1e3, "launches": cnt,
                      "bytes_per_launch": launch_bytes},
-        "cg_operator_kernel": {"kernel": "k_apply_dir", "achieved_gbs": apply_gbs,
-                               "avg_launch_us": float(t_a.mean()) * 1e3},
+        "cg_operator_kernel": {"kernel": "k_apply_dir_tile" if schedule["apply_tile"] else "k_apply_dir",
+                               "achieved_gbs": apply_gbs, "avg_launch_us": float(t_a.mean()) * 1e3},
+        "schedule": dict(schedule, autotuned=bool(a.autotune)),
     }
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, iters, a.cpu_seconds)

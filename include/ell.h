@@ -211,6 +211,41 @@ enum {
 };
 int ell_set_tuning(int key, int value);
 
+/* ---- schedule autotuning (beyond the paper) ---------------------------------
+ * A schedule fixes how a grid of one shape runs on the chip, not what it
+ * computes (every schedule gives the same iterates up to rounding order): the
+ * CG operator step's kernel (LDS-tiled or column-walking) and its k-segments,
+ * and the line smoother's k-segments on each coarse level (the finest level
+ * always uses 4).  Schedules are kept process-wide per shape (nx, ny, nz,
+ * number of levels, FP64 or mixed precision); a grid created afterwards uses
+ * the schedule recorded for its shape, else the built-in heuristics.  Batch
+ * grids take the operator-step part only (their smoother layout is uniform).
+ * Thread-safe. */
+#define ELL_MAX_LEVELS 16
+typedef struct {
+  int32_t apply_tile;                  /* 1: LDS-tiled operator step, 0: column-walking */
+  int32_t apply_nseg;                  /* k-segments of the operator step: 1, 2 or 4 */
+  int32_t smooth_nseg[ELL_MAX_LEVELS]; /* per level: line-smoother k-segments, 4, 8 or 16
+                                          (entry 0 is 4; entries past the last level 0) */
+  double ms_per_iter;                  /* ell_autotune: measured milliseconds per PCG
+                                          iteration of the chosen schedule; otherwise 0 */
+} ell_schedule;
+/* Autotuner: times fixed-iteration PCG solves (iters iterations from u = 0,
+ * rtol 0, f a fixed pseudo-random field; median of three) of a grid of this
+ * shape under candidate schedules, by coordinate descent: the operator step
+ * first (tiled with 1, 2 or 4 segments, column-walking with 1, 2 or 4), then
+ * each coarse level's smoother segments.  A candidate replaces the current
+ * one only if it is at least 1% faster.  Records the winner for the shape and
+ * writes it to *best (host struct).  iters <= 0 means 4.  Allocates and frees
+ * its own device memory: one grid of the shape and two vectors at a time.
+ * Synchronises the device. */
+int ell_autotune(const ell_grid_desc *desc, int32_t iters, ell_schedule *best);
+/* The schedule a grid of this shape would get now (recorded or heuristic). */
+int ell_schedule_get(const ell_grid_desc *desc, ell_schedule *out);
+/* Records a schedule for this shape after validating it; NULL clears the
+ * record (back to the heuristics). */
+int ell_schedule_set(const ell_grid_desc *desc, const ell_schedule *s);
+
 /* ---- batched solves and serving (beyond the paper) ---------------------------
  * A batch engine advances many solves together: every stage of a CG iteration
  * (operator step, residual update, each V-cycle half-sweep, restriction and

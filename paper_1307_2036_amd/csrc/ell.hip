@@ -3,6 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <chrono>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <cmath>
 #include <cstdarg>
@@ -796,6 +800,61 @@ int check_level(const ell_grid *g, int level, bool need_coarser) {
   return ELL_OK;
 }
 
+// ------------------------------------------------------------------------
+// schedules: per shape, the operator-step kernel and segments and the
+// smoother segments per coarse level (recorded by ell_autotune or
+// ell_schedule_set, else heuristic)
+// ------------------------------------------------------------------------
+using SchedKey = std::array<int, 5>;
+std::mutex g_sched_mu;
+std::map<SchedKey, ell_schedule> g_sched;
+
+SchedKey sched_key(const ell_grid_desc *d, int L) {
+  return SchedKey{d->nx, d->ny, d->nz, L, d->precision == ELL_FP64 ? 0 : 1};
+}
+
+// A coarse level can run the segmented smoother with ns segments when a
+// kernel instance covers the segment length (else it runs the sequential
+// column kernel).
+bool smooth_nseg_fits(int ns, int nz) {
+  const int Ls = seg_len(nz, ns);
+  return (ns == 4 && Ls <= 64) || (ns == 8 && Ls <= 32) || (ns == 16 && Ls <= 16);
+}
+
+ell_schedule default_schedule(const ell_grid_desc *d, int L) {
+  ell_schedule s;
+  std::memset(&s, 0, sizeof(s));
+  s.apply_tile = (g_apply_tile && d->nx > 1 && d->ny > 1) ? 1 : 0;
+  s.apply_nseg = s.apply_tile ? apply_segments(d->nz) : g_stencil_seg;
+  for (int l = 0; l < L && l < ELL_MAX_LEVELS; ++l)
+    s.smooth_nseg[l] = make_geo(d->nx >> l, d->ny >> l, d->nz, l == 0).nseg;
+  return s;
+}
+
+int check_schedule(const ell_grid_desc *d, int L, const ell_schedule *s) {
+  if (L > ELL_MAX_LEVELS) return fail(ELL_ERR_INVALID, "schedules cover at most %d levels", ELL_MAX_LEVELS);
+  if (s->apply_tile != 0 && s->apply_tile != 1) return fail(ELL_ERR_INVALID, "apply_tile must be 0 or 1");
+  if (s->apply_tile && (d->nx < 2 || d->ny < 2))
+    return fail(ELL_ERR_INVALID, "the tiled operator step needs nx, ny > 1");
+  if (s->apply_nseg != 1 && s->apply_nseg != 2 && s->apply_nseg != 4)
+    return fail(ELL_ERR_INVALID, "apply_nseg must be 1, 2 or 4");
+  if (s->smooth_nseg[0] != 4) return fail(ELL_ERR_INVALID, "the finest level's smoother uses 4 segments");
+  for (int l = 1; l < L; ++l) {
+    const int ns = s->smooth_nseg[l];
+    if (ns != 4 && ns != 8 && ns != 16) return fail(ELL_ERR_INVALID, "smooth_nseg[%d] must be 4, 8 or 16", l);
+  }
+  return ELL_OK;
+}
+
+ell_schedule schedule_for(const ell_grid_desc *d, int L) {
+  {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    auto it = g_sched.find(sched_key(d, L));
+    if (it != g_sched.end()) return it->second;
+  }
+  return default_schedule(d, L);
+}
+
 }  // namespace
 
 // ==========================================================================
@@ -811,11 +870,13 @@ size_t ell_grid_bytes(const ell_grid_desc *desc) {
   return grid_bytes(desc, L);
 }
 
-static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **out);
+static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **out,
+                       const ell_schedule *force = nullptr);
 
 int ell_grid_create(const ell_grid_desc *desc, ell_grid **out) { return grid_create(desc, false, out); }
 
-static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **out) {
+static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **out,
+                       const ell_schedule *force) {
   if (!out) return fail(ELL_ERR_INVALID, "out is NULL");
   *out = nullptr;
   int L = 0;
@@ -829,9 +890,10 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->L = L;
   g->prec = desc->precision;
   g->esz = g->prec == ELL_FP64 ? 8 : 4;
-  g->stencil_seg = batch_layout ? 1 : g_stencil_seg;
-  g->apply_tile = (g_apply_tile && desc->nx > 1 && desc->ny > 1) ? 1 : 0;
-  g->apply_nseg = apply_segments(desc->nz);
+  const ell_schedule sc = force ? *force : schedule_for(desc, L);
+  g->apply_tile = (sc.apply_tile && desc->nx > 1 && desc->ny > 1) ? 1 : 0;
+  g->apply_nseg = g->apply_tile ? sc.apply_nseg : apply_segments(desc->nz);
+  g->stencil_seg = batch_layout ? 1 : (g->apply_tile ? g_stencil_seg : sc.apply_nseg);
   g->batch_layout = batch_layout;
   g->lev.resize(L);
   auto bail = [&](int rc) {
@@ -844,6 +906,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   for (int l = 0; l < L; ++l) {
     Level &Lv = g->lev[l];
     Lv.geo = make_geo(desc->nx >> l, desc->ny >> l, desc->nz, l == 0, batch_layout);
+    if (!batch_layout && l > 0 && l < ELL_MAX_LEVELS && sc.smooth_nseg[l] > 0) Lv.geo.nseg = sc.smooth_nseg[l];
     Lv.hx = desc->hx * (double)(1 << l);
     Lv.hy = desc->hy * (double)(1 << l);
     level_table64(g, l, t64);
@@ -1105,6 +1168,121 @@ int ell_level_layout(const ell_grid *g, int level, int64_t *cols, int64_t *plane
   *plane_stride = G.S;
   *colour_stride = G.cs;
   return ELL_OK;
+}
+
+int ell_schedule_get(const ell_grid_desc *desc, ell_schedule *out) {
+  if (!out) return fail(ELL_ERR_INVALID, "out is NULL");
+  int L = 0;
+  CHK(validate(desc, &L));
+  if (L > ELL_MAX_LEVELS) return fail(ELL_ERR_INVALID, "schedules cover at most %d levels", ELL_MAX_LEVELS);
+  *out = schedule_for(desc, L);
+  return ELL_OK;
+}
+
+int ell_schedule_set(const ell_grid_desc *desc, const ell_schedule *s) {
+  int L = 0;
+  CHK(validate(desc, &L));
+  const SchedKey key = sched_key(desc, L);
+  if (!s) {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    g_sched.erase(key);
+    return ELL_OK;
+  }
+  CHK(check_schedule(desc, L, s));
+  ell_schedule c = *s;
+  for (int l = L; l < ELL_MAX_LEVELS; ++l) c.smooth_nseg[l] = 0;
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  g_sched[key] = c;
+  return ELL_OK;
+}
+
+int ell_autotune(const ell_grid_desc *desc, int32_t iters, ell_schedule *best) {
+  if (!best) return fail(ELL_ERR_INVALID, "best is NULL");
+  int L = 0;
+  CHK(validate(desc, &L));
+  if (L > ELL_MAX_LEVELS) return fail(ELL_ERR_INVALID, "schedules cover at most %d levels", ELL_MAX_LEVELS);
+  if (iters <= 0) iters = 4;
+  const long long n = (long long)desc->nx * desc->ny * desc->nz;
+  double *f = nullptr, *u = nullptr;
+  if (hipMalloc((void **)&f, n * 8) != hipSuccess || hipMalloc((void **)&u, n * 8) != hipSuccess) {
+    if (f) (void)hipFree(f);
+    (void)hipGetLastError();
+    return fail(ELL_ERR_OOM, "autotune vectors do not fit");
+  }
+  auto release = [&](int rc) {
+    (void)hipFree(f);
+    (void)hipFree(u);
+    return rc;
+  };
+  k_fill_hash<<<1024, kBlock>>>(f, n);
+  if (check_launch("k_fill_hash") != ELL_OK || hipDeviceSynchronize() != hipSuccess)
+    return release(fail(ELL_ERR_HIP, "autotune input fill failed"));
+  // milliseconds per iteration of a schedule: median of three timed solves
+  auto time_of = [&](const ell_schedule &sch, double *ms) -> int {
+    ell_grid *g = nullptr;
+    CHK(grid_create(desc, false, &g, &sch));
+    const ell_solve_opts warm{0.0, 0.0, 1, 1, 0, 1};
+    const ell_solve_opts run{0.0, 0.0, iters, 1, 0, iters};
+    std::vector<double> t;
+    int rc = ELL_OK;
+    for (int rep = 0; rep < 4; ++rep) {
+      if (hipMemset(u, 0, n * 8) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        rc = fail(ELL_ERR_HIP, "autotune reset failed");
+        break;
+      }
+      const auto t0 = std::chrono::steady_clock::now();
+      rc = ell_pcg_solve(g, f, u, rep == 0 ? &warm : &run, nullptr, nullptr);
+      const auto t1 = std::chrono::steady_clock::now();
+      if (rc != ELL_OK && rc != ELL_NOT_CONVERGED) break;
+      rc = ELL_OK;
+      if (rep > 0) t.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+    }
+    ell_grid_destroy(g);
+    if (rc != ELL_OK) return rc;
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2] / iters;
+    return ELL_OK;
+  };
+  ell_schedule cur = default_schedule(desc, L);
+  double best_ms = 0.0;
+  int rc = time_of(cur, &best_ms);
+  if (rc != ELL_OK) return release(rc);
+  auto consider = [&](const ell_schedule &c) -> int {
+    double ms = 0.0;
+    CHK(time_of(c, &ms));
+    if (ms < 0.99 * best_ms) {
+      best_ms = ms;
+      cur = c;
+    }
+    return ELL_OK;
+  };
+  // the operator step
+  for (int tile = 1; tile >= 0; --tile) {
+    if (tile && (desc->nx < 2 || desc->ny < 2)) continue;
+    for (int ns : {1, 2, 4}) {
+      if (tile == cur.apply_tile && ns == cur.apply_nseg) continue;
+      ell_schedule c = cur;
+      c.apply_tile = tile;
+      c.apply_nseg = ns;
+      if ((rc = consider(c)) != ELL_OK) return release(rc);
+    }
+  }
+  // the smoother segments of each coarse level
+  for (int l = 1; l < L; ++l) {
+    for (int ns : {4, 8, 16}) {
+      if (ns == cur.smooth_nseg[l] || !smooth_nseg_fits(ns, desc->nz)) continue;
+      ell_schedule c = cur;
+      c.smooth_nseg[l] = ns;
+      if ((rc = consider(c)) != ELL_OK) return release(rc);
+    }
+  }
+  cur.ms_per_iter = best_ms;
+  {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    g_sched[sched_key(desc, L)] = cur;
+  }
+  *best = cur;
+  return release(ELL_OK);
 }
 
 int ell_set_tuning(int key, int value) {

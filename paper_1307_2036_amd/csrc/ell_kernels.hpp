@@ -946,6 +946,19 @@ __global__ __launch_bounds__(kBlock) void k_axpy_alpha(double2 *__restrict__ u,
   }
 }
 
+// A fixed pseudo-random field in [-1, 1): element e is a 64-bit mix of e
+// (the input of schedule timing; nothing numerical depends on its values).
+__global__ __launch_bounds__(kBlock) void k_fill_hash(double *__restrict__ f, long long n) {
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += stride) {
+    unsigned long long x = (unsigned long long)e * 0x9E3779B97F4A7C15ull;
+    x ^= x >> 31;
+    x *= 0xBF58476D1CE4E5B9ull;
+    x ^= x >> 29;
+    f[e] = (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_fill(R *__restrict__ p, long long n, R v) {
   const long long t = (long long)logical_block() * kBlock + threadIdx.x;

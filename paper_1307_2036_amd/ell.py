@@ -39,6 +39,14 @@ class GridDesc(ctypes.Structure):
                 ("prolong", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
+ELL_MAX_LEVELS = 16
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("apply_tile", ctypes.c_int32), ("apply_nseg", ctypes.c_int32),
+                ("smooth_nseg", ctypes.c_int32 * ELL_MAX_LEVELS), ("ms_per_iter", ctypes.c_double)]
+
+
 class SolveOpts(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("atol", ctypes.c_double), ("maxiter", ctypes.c_int32),
                 ("flexible", ctypes.c_int32), ("rel_to_rhs", ctypes.c_int32),
@@ -57,7 +65,8 @@ EXPORTS = ["ell_grid_create", "ell_grid_destroy", "ell_grid_bytes", "ell_grid_le
            "ell_level_prolong_add", "ell_level_apply", "ell_profile_enable", "ell_profile_read",
            "ell_profile_times", "ell_level_layout", "ell_set_tuning", "ell_last_error",
            "ell_batch_create", "ell_batch_grid", "ell_batch_release", "ell_batch_bytes_in_use",
-           "ell_batch_submit", "ell_batch_poll", "ell_batch_wait", "ell_batch_destroy"]
+           "ell_batch_submit", "ell_batch_poll", "ell_batch_wait", "ell_batch_destroy",
+           "ell_autotune", "ell_schedule_get", "ell_schedule_set"]
 
 _lib = None
 
@@ -105,6 +114,9 @@ def load_library(path: str = LIB_PATH):
     L.ell_batch_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(SolveStats)]
     L.ell_batch_wait.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(SolveStats)]
     L.ell_batch_destroy.argtypes = [vp]
+    L.ell_autotune.argtypes = [ctypes.POINTER(GridDesc), ctypes.c_int32, ctypes.POINTER(Schedule)]
+    L.ell_schedule_get.argtypes = [ctypes.POINTER(GridDesc), ctypes.POINTER(Schedule)]
+    L.ell_schedule_set.argtypes = [ctypes.POINTER(GridDesc), ctypes.POINTER(Schedule)]
     for name in EXPORTS:
         if name not in ("ell_grid_bytes", "ell_level_elems", "ell_last_error", "ell_batch_bytes_in_use"):
             getattr(L, name).restype = ctypes.c_int
@@ -154,6 +166,45 @@ ELL_TUNE_BATCH_GRAPH = 4
 def set_tuning(key: int, value: int) -> None:
     """Layout padding for grids created afterwards (process-wide)."""
     _check(load_library().ell_set_tuning(key, value))
+
+
+def _sched_dict(s: Schedule) -> dict:
+    seg = list(s.smooth_nseg)
+    while seg and seg[-1] == 0:
+        seg.pop()
+    return {"apply_tile": s.apply_tile, "apply_nseg": s.apply_nseg, "smooth_nseg": seg,
+            "ms_per_iter": s.ms_per_iter}
+
+
+def autotune(iters: int = 4, **desc) -> dict:
+    """Time candidate schedules for this grid shape, record and return the
+    fastest (see ell_autotune in ell.h)."""
+    d, keep = make_desc(**desc)
+    s = Schedule()
+    _check(load_library().ell_autotune(ctypes.byref(d), iters, ctypes.byref(s)))
+    return _sched_dict(s)
+
+
+def schedule_get(**desc) -> dict:
+    """The schedule a grid of this shape would get now."""
+    d, keep = make_desc(**desc)
+    s = Schedule()
+    _check(load_library().ell_schedule_get(ctypes.byref(d), ctypes.byref(s)))
+    return _sched_dict(s)
+
+
+def schedule_set(schedule: Optional[dict], **desc) -> None:
+    """Record a schedule for this shape (None clears the record)."""
+    d, keep = make_desc(**desc)
+    if schedule is None:
+        _check(load_library().ell_schedule_set(ctypes.byref(d), None))
+        return
+    s = Schedule()
+    s.apply_tile = int(schedule["apply_tile"])
+    s.apply_nseg = int(schedule["apply_nseg"])
+    for i, v in enumerate(schedule.get("smooth_nseg", [])):
+        s.smooth_nseg[i] = int(v)
+    _check(load_library().ell_schedule_set(ctypes.byref(d), ctypes.byref(s)))
 
 
 def grid_bytes(**kw) -> int:

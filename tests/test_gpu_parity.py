@@ -311,6 +311,35 @@ def test_operator_step_tiles_fixed_iterations(ell, orc, shape, K):
     assert rel(got[1], got[0]) <= 1e-13
 
 
+def test_autotuned_schedule_is_recorded_and_solves_match(ell, orc):
+    """The autotuner returns a valid schedule for the shape, grids created
+    afterwards use it, and a solve under it matches the oracle like any other
+    (a schedule changes how the path runs, not what it computes)."""
+    p = I.graded_problem("tune", 64, 64, 1e-2, 21, 22, n_levels=4, nu_coarse=5)
+    kw = dict(nx=p.nx, ny=p.ny, nz=p.nz, hx=p.hx, hy=p.hy, omega2=p.omega2, dz=p.dz,
+              lambda2=p.lambda2, n_levels=p.n_levels, nu_coarse=p.nu_coarse)
+    try:
+        best = ell.autotune(iters=3, **kw)
+        assert best["ms_per_iter"] > 0 and best["smooth_nseg"][0] == 4
+        assert len(best["smooth_nseg"]) == 4 and best["apply_nseg"] in (1, 2, 4)
+        assert all(s in (4, 8, 16) for s in best["smooth_nseg"])
+        assert {k: v for k, v in ell.schedule_get(**kw).items()} == best
+        G = ell.Grid.from_problem(p)
+        u, st = G.pcg_solve(dev(p.f), rtol=p.rtol)
+        assert st.status == 0
+        check_solve(orc, orc.Grid.from_problem(p), p.f, host(u), st, p.rtol)
+        # explicitly chosen schedules compute the same five iterations
+        ref, _ = G.pcg_solve(dev(p.f), rtol=1e-30, maxiter=5)
+        ref = host(ref)
+        for sch in (dict(apply_tile=0, apply_nseg=4, smooth_nseg=[4, 16, 16, 16]),
+                    dict(apply_tile=1, apply_nseg=1, smooth_nseg=[4, 8, 8, 4])):
+            ell.schedule_set(sch, **kw)
+            u2, st2 = ell.Grid.from_problem(p).pcg_solve(dev(p.f), rtol=1e-30, maxiter=5)
+            assert st2.iters == 5 and rel(host(u2), ref) <= 1e-12
+    finally:
+        ell.schedule_set(None, **kw)
+
+
 def test_single_column_solve(ell, orc):
     g = small_grid(orc, 1, 1, 40, seed=2, graded=False)
     G = gpu_grid(ell, g)
