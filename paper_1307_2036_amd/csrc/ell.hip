@@ -200,8 +200,11 @@ int g_batch_graph = 1;  // 1: batch engines replay each grouped step from a capt
 // levels, four (the register-resident optimum) on large ones; the finest
 // level always uses four.
 int smoother_segments(long long cols_per_colour, int nz, bool finest) {
+  // finest level: 8 segments where a kernel instance covers them (nz in
+  // [64, 128]); measured 1% faster than 4 at 512^2 x 128
+  if (finest) return (nz >= 64 && seg_len(nz, 8) <= 16) ? 8 : 4;
   int ns = 4;
-  if (!finest) {
+  {
     if (cols_per_colour < 4096) ns = 16;
     else if (cols_per_colour < 16384) ns = 8;
   }
@@ -412,6 +415,11 @@ bool seg_dispatch(bool fine, int nb, hipStream_t s, const Geo &G, const R *tab, 
                   const TB *bo, const R *uo, R *own, R rho, const int *done) {
   const int Ls = seg_len(G.nz, G.nseg);
   if (fine) {
+    if (G.nseg == 8) {
+      if (Ls > 16) return false;
+      seg_dispatch3<R, TB, true, 16, 8>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
+      return true;
+    }
     if (G.nseg != 4) return false;
     if (Ls <= 16) seg_dispatch3<R, TB, true, 16, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
     else if (Ls <= 32) seg_dispatch3<R, TB, true, 32, 4>(nb, s, G, tab, c, zero, rho1, bo, uo, own, rho, done);
@@ -584,7 +592,7 @@ int vcycle_impl(ell_grid *g, const R *b0, R *u0, const int *done, hipStream_t s)
 bool hybrid_ok(const ell_grid *g) {
   const Geo &G = g->lev[0].geo;
   return g->L >= 2 && g->d.rho == 1.0 && g->d.nu_pre >= 1 && g->d.nu_post >= 1 && G.has_x && G.has_y &&
-         G.nseg == 4 && seg_len(G.nz, 4) <= 64;
+         ((G.nseg == 4 && seg_len(G.nz, 4) <= 64) || (G.nseg == 8 && seg_len(G.nz, 8) <= 16));
 }
 
 int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipStream_t s) {
@@ -838,7 +846,8 @@ int check_schedule(const ell_grid_desc *d, int L, const ell_schedule *s) {
     return fail(ELL_ERR_INVALID, "the tiled operator step needs nx, ny > 1");
   if (s->apply_nseg != 1 && s->apply_nseg != 2 && s->apply_nseg != 4)
     return fail(ELL_ERR_INVALID, "apply_nseg must be 1, 2 or 4");
-  if (s->smooth_nseg[0] != 4) return fail(ELL_ERR_INVALID, "the finest level's smoother uses 4 segments");
+  if (s->smooth_nseg[0] != 4 && !(s->smooth_nseg[0] == 8 && seg_len(d->nz, 8) <= 16))
+    return fail(ELL_ERR_INVALID, "the finest level's smoother uses 4 segments (or 8 when nz <= 128)");
   for (int l = 1; l < L; ++l) {
     const int ns = s->smooth_nseg[l];
     if (ns != 4 && ns != 8 && ns != 16) return fail(ELL_ERR_INVALID, "smooth_nseg[%d] must be 4, 8 or 16", l);
@@ -906,7 +915,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   for (int l = 0; l < L; ++l) {
     Level &Lv = g->lev[l];
     Lv.geo = make_geo(desc->nx >> l, desc->ny >> l, desc->nz, l == 0, batch_layout);
-    if (!batch_layout && l > 0 && l < ELL_MAX_LEVELS && sc.smooth_nseg[l] > 0) Lv.geo.nseg = sc.smooth_nseg[l];
+    if (!batch_layout && l < ELL_MAX_LEVELS && sc.smooth_nseg[l] > 0) Lv.geo.nseg = sc.smooth_nseg[l];
     Lv.hx = desc->hx * (double)(1 << l);
     Lv.hy = desc->hy * (double)(1 << l);
     level_table64(g, l, t64);
@@ -1267,7 +1276,13 @@ int ell_autotune(const ell_grid_desc *desc, int32_t iters, ell_schedule *best) {
       if ((rc = consider(c)) != ELL_OK) return release(rc);
     }
   }
-  // the smoother segments of each coarse level
+  // the smoother segments of the finest level, then of each coarse level
+  for (int ns : {4, 8}) {
+    if (ns == cur.smooth_nseg[0] || (ns == 8 && seg_len(desc->nz, 8) > 16)) continue;
+    ell_schedule c = cur;
+    c.smooth_nseg[0] = ns;
+    if ((rc = consider(c)) != ELL_OK) return release(rc);
+  }
   for (int l = 1; l < L; ++l) {
     for (int ns : {4, 8, 16}) {
       if (ns == cur.smooth_nseg[l] || !smooth_nseg_fits(ns, desc->nz)) continue;

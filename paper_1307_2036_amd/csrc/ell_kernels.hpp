@@ -101,6 +101,27 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
+// Streaming (nontemporal) accesses for data a kernel touches exactly once:
+// finest-level vectors are far larger than the L2 and the Infinity Cache, so
+// keeping them out of the caches leaves room for the data that is reused (the
+// neighbour columns of the stencils).
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_nt(const double2 *p) {
+  const nt_d2 v = __builtin_nontemporal_load((const nt_d2 *)p);
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt(double2 *p, double2 v) {
+  const nt_d2 w = {v.x, v.y};
+  __builtin_nontemporal_store(w, (nt_d2 *)p);
+}
+template <typename T>
+__device__ __forceinline__ T ld_s(const T *p, bool nt) { return nt ? __builtin_nontemporal_load(p) : *p; }
+template <typename T>
+__device__ __forceinline__ void st_s(T *p, T v, bool nt) {
+  if (nt) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
 // Neighbour columns (colour 1 - c) of column (i, j) in the split layout.
 struct Nbr {
   int w, e, s, n;
@@ -284,7 +305,7 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
       for (int t = 0; t < 8; ++t) {
         const int k = min(k0 + c0 + t, k1 - 1);
         const long long o = (long long)k * H;
-        R v = (R)bb[o];
+        R v = (R)ld_s(&bb[o], FINE);
         if (!ZERO) {
           v = v + tx[k] * (uw[o] + ue[o]);
           v = v + ty[k] * (us[o] + un[o]);
@@ -347,7 +368,7 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
             const int k = k0 + c0 + t;
             const R w = y[c0 + t] + qb[k] * win;
             const R o = (RHO1 || ZERO) ? R(0) : old[t];
-            ow[(long long)k * H] = RHO1 ? w : (R(1) - rho) * o + rho * w;
+            st_s(&ow[(long long)k * H], RHO1 ? w : (R(1) - rho) * o + rho * w, FINE);
           }
         }
       }
@@ -912,11 +933,11 @@ __device__ __forceinline__ void update_r_body(double2 *__restrict__ r,
   const long long stride = (long long)nblocks * kBlock;
   double rr = 0.0;
   for (long long e = t; e < n2; e += stride) {
-    const double2 qv = q[e];
-    double2 rv = r[e];
+    const double2 qv = ld_nt(&q[e]);
+    double2 rv = ld_nt(&r[e]);
     rv.x = rv.x - alpha * qv.x;
     rv.y = rv.y - alpha * qv.y;
-    r[e] = rv;
+    st_nt(&r[e], rv);
     rr += rv.x * rv.x + rv.y * rv.y;
   }
   const double s = block_sum(rr, sh);
@@ -1108,7 +1129,7 @@ __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const doubl
       for (int e = 0; e < 4; ++e) {
         zv[e] = ok[e] ? (double)z[off[e] + o] : 0.0;
         po[e] = (ok[e] && !first) ? pold[off[e] + o] : 0.0;
-        uu[e] = (ok[e] && write && defer_u) ? u[off[e] + o] : 0.0;
+        uu[e] = (ok[e] && write && defer_u) ? __builtin_nontemporal_load(&u[off[e] + o]) : 0.0;
       }
       double hv = 0.0;
       if (b >= 0 && hok) hv = dirv(hoff + o);
@@ -1120,8 +1141,8 @@ __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const doubl
         // row / m-column hold the halo
         if (b >= 0 && ok[e]) sp[b][e & 1][r0 + 8 * (e >> 1) + 1][x + 1] = pvv;
         if (ok[e] && write) {
-          pnew[off[e] + o] = pvv;
-          if (defer_u) u[off[e] + o] = uu[e] + alpha * po[e];
+          __builtin_nontemporal_store(pvv, &pnew[off[e] + o]);
+          if (defer_u) __builtin_nontemporal_store(uu[e] + alpha * po[e], &u[off[e] + o]);
         }
       }
       if (b >= 0 && hok) sp[b][hc][hr][hx] = hv;
@@ -1165,7 +1186,7 @@ __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const doubl
           acc = acc + tyv[k] * (pcv - pnn);
           acc = acc + tz[k] * (pcv - pm[e]);
           acc = acc + tz[k + 1] * (pcv - pn[e]);
-          q[off[e] + o] = acc;
+          __builtin_nontemporal_store(acc, &q[off[e] + o]);
           dot += pcv * acc;
         }
         pm[e] = pc[e];
@@ -1459,7 +1480,7 @@ __device__ __forceinline__ void dots_body(const double2 *__restrict__ r,
   const long long stride = (long long)nblocks * kBlock;
   double rz = 0.0, zq = 0.0;
   for (long long e = t; e < n2; e += stride) {
-    const double2 rv = r[e], qv = q[e];
+    const double2 rv = ld_nt(&r[e]), qv = ld_nt(&q[e]);
     const auto zv = z[e];
     const double zx = (double)zv.x, zy = (double)zv.y;
     rz += rv.x * zx + rv.y * zy;

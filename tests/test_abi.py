@@ -104,7 +104,7 @@ def test_schedule_records_are_validated_host_side():
     kw = dict(nx=64, ny=64, nz=128, hx=1 / 64, hy=1 / 64, omega2=1e-2, dz=np.full(128, 1 / 128),
               lambda2=np.full(128, 1e2), n_levels=4)
     d0 = ell.schedule_get(**kw)
-    assert d0["smooth_nseg"][0] == 4 and len(d0["smooth_nseg"]) == 4
+    assert d0["smooth_nseg"][0] == 8 and len(d0["smooth_nseg"]) == 4  # 8 segments fit nz = 128
     assert d0["apply_tile"] == 1 and d0["apply_nseg"] == 4 and d0["ms_per_iter"] == 0.0
     mine = dict(apply_tile=0, apply_nseg=2, smooth_nseg=[4, 8, 16, 16])
     ell.schedule_set(mine, **kw)
@@ -112,11 +112,14 @@ def test_schedule_records_are_validated_host_side():
     assert {k: got[k] for k in mine} == mine
     other = ell.schedule_get(**dict(kw, nz=64, dz=np.full(64, 1 / 64), lambda2=np.full(64, 1e2)))
     assert other["apply_tile"] == 1  # other shapes keep the heuristics
-    for bad in (dict(mine, apply_nseg=3), dict(mine, apply_tile=2), dict(mine, smooth_nseg=[8, 8, 8, 8]),
+    for bad in (dict(mine, apply_nseg=3), dict(mine, apply_tile=2), dict(mine, smooth_nseg=[16, 8, 8, 8]),
                 dict(mine, smooth_nseg=[4, 8, 5, 16])):
         with pytest.raises(ell.EllError):
             ell.schedule_set(bad, **kw)
     with pytest.raises(ell.EllError):  # no tiled step on a one-column-wide grid
         ell.schedule_set(dict(mine, apply_tile=1), **dict(kw, nx=1, n_levels=1))
+    with pytest.raises(ell.EllError):  # 8 finest segments need nz <= 128
+        ell.schedule_set(dict(mine, smooth_nseg=[8, 4]), **dict(kw, nz=200, dz=np.full(200, 1 / 200),
+                                                                lambda2=np.full(200, 1.0), n_levels=2))
     ell.schedule_set(None, **kw)
     assert ell.schedule_get(**kw) == d0
