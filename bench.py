@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--nu-coarse", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c1", choices=["c1", "batch", "serve"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "batch", "serve"],
                     help="c1: the 512^2x128 solve (default); batch: 64 uneven solves in the "
                          "batch engine vs sequential FP64; serve: Poisson request stream")
     ap.add_argument("--autotune", action="store_true",
@@ -98,6 +98,8 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
         sys.exit(2)
+    if a.workload == "c2":
+        return bench_c2(a)
     if a.workload == "batch":
         return bench_batch(a)
     if a.workload == "serve":
@@ -279,6 +281,64 @@ def bench_batch(a):
     }
     print(json.dumps(out), flush=True)
     B.close()
+
+
+def bench_c2(a):
+    """Mixed precision at 1024x1024x128 (graded, standard depth), omega^2 swept
+    over {1e-3, 1e-2, 1e-1}: per omega^2 the mixed-precision solve (BF16-rounded
+    stencil coefficients, FP32 V-cycle, FP64 CG; or --precision fp32) and the
+    plain FP64 solve to 1e-5, timed, plus the error of a tight (1e-12) mixed
+    solve against the tight FP64 solve on the same GPU.  value = solves/s of the
+    mixed path over the sweep (one solve per omega^2 per step)."""
+    import numpy as np
+    import torch
+    from paper_1307_2036_amd import ell, inputs, perfmodel
+    torch.cuda.set_device(0)
+    prec = "bf16coef" if a.precision == "fp64" else a.precision
+    rows, t_mixed, t_64 = [], 0.0, 0.0
+    for omega2 in (1e-3, 1e-2, 1e-1):
+        p = inputs.config2(omega2)
+        f = torch.from_numpy(p.f).cuda()
+        p.f = None
+        u = torch.zeros_like(f)
+        per = {}
+        for name, pr in ((prec, prec), ("fp64", "fp64")):
+            G = ell.Grid.from_problem(p, precision=pr)
+            G.pcg_solve(f, u, rtol=p.rtol)  # warm-up
+            times = []
+            for _ in range(max(a.steps // 4, 2)):
+                u.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st = G.pcg_solve(f, u, rtol=p.rtol, poll_every=8)
+                times.append(time.perf_counter() - t0)
+            assert st.status == 0, st
+            ut = torch.zeros_like(f)
+            G.pcg_solve(f, ut, rtol=1e-12, maxiter=300)
+            per[name] = dict(iters=st.iters, s=float(np.median(times)), tight=ut, levels=G.levels)
+            G.close()
+        e = 8 if prec == "fp64" else 4
+        mixed_bytes = perfmodel.pcg_iteration_bytes(p.n, per[prec]["levels"], e) * per[prec]["iters"]
+        err = float(torch.linalg.vector_norm(per[prec]["tight"] - per["fp64"]["tight"]) /
+                    torch.linalg.vector_norm(per["fp64"]["tight"]))
+        rows.append({"omega2": omega2, "levels": per[prec]["levels"], "iters_mixed": per[prec]["iters"],
+                     "iters_fp64": per["fp64"]["iters"], "ms_mixed": per[prec]["s"] * 1e3,
+                     "ms_fp64": per["fp64"]["s"] * 1e3,
+                     "hbm_gbs_algorithmic_mixed": mixed_bytes / per[prec]["s"] / 1e9,
+                     "tight_rel_err_vs_fp64": err})
+        t_mixed += per[prec]["s"]
+        t_64 += per["fp64"]["s"]
+        del per, f, u
+        torch.cuda.empty_cache()
+    out = {
+        "metric": METRIC, "value": 3 / t_mixed, "unit": "solves/s", "n_gpus": 1, "steps": 3,
+        "warmup": 1, "ms_per_step": t_mixed * 1e3 / 3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64-outer/f32-vcycle", "data": "synthetic (seeded N(0,1) f)",
+        "config": {"workload": "gmg-pcg 1024x1024x128 graded, standard depth, omega2 in {1e-3,1e-2,1e-1}, "
+                               "rtol 1e-5, u0=0", "unknowns": 1024 * 1024 * 128, "precision": prec},
+        "fp64_solves_per_s": 3 / t_64, "speedup_vs_fp64": t_64 / t_mixed, "per_omega2": rows,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def bench_serve(a):

@@ -89,3 +89,29 @@ def test_fullsize_mixed_solve(orc):
     print("fp32 iters", st.iters, "fp64 iters", st64["iters"], "rel to fp64", rel(host(u), u64))
     assert st.status == 0 and st.iters <= st64["iters"] + 2
     assert rel(host(u), u64) <= 1e-4
+
+
+@pytest.mark.slow
+def test_config2_mixed_solves_against_oracle(orc):
+    """1024 x 1024 x 128, standard depth (11 levels), omega^2 = 1e-2, BF16-rounded
+    coefficients: at the production tolerance the mixed solve takes at most two
+    iterations more than the oracle and lies within 1e-4 of its solution; solved
+    tightly, mixed and FP64 GPU solves (the FP64 path being the one pinned to the
+    oracle at 1e-10) agree to 1e-8."""
+    from paper_1307_2036_amd import ell
+    p = I.config2(1e-2)
+    G = ell.Grid.from_problem(p, precision="bf16coef")
+    f = dev(p.f)
+    u, st = G.pcg_solve(f, rtol=p.rtol)
+    ut, stt = G.pcg_solve(f, rtol=1e-12, maxiter=300)
+    G.close()
+    G64 = ell.Grid.from_problem(p)
+    u64t, st64t = G64.pcg_solve(f, rtol=1e-12, maxiter=300)
+    G64.close()
+    assert st.status == 0 and stt.status == 0 and st64t.status == 0
+    assert float(torch.linalg.vector_norm(ut - u64t) / torch.linalg.vector_norm(u64t)) <= 1e-8
+    g = orc.Grid.from_problem(p)
+    u_o, st_o = orc.pcg(g, p.f, rtol=p.rtol)
+    print("mixed iters", st.iters, "oracle iters", st_o["iters"], "rel", rel(host(u), u_o))
+    assert st.iters <= st_o["iters"] + 2
+    assert rel(host(u), u_o) <= 1e-4
