@@ -421,7 +421,17 @@ static void vcycle_rec(hier_t *H, const orc_mg *mg, int l, const double *b, doub
     const level_t *Lv = &H->lev[l];
     memset(u, 0, sizeof(double) * level_n(Lv));
     if (l == H->L - 1) {
-        smooth(Lv, mg->nu_coarse, 0, mg->rho, b, u);
+        if (mg->nu_coarse > 0) {
+            smooth(Lv, mg->nu_coarse, 0, mg->rho, b, u);
+        } else {
+            /* no coarse sweeps: the level is smoothed like a finer one without a
+             * coarser correction, red-black then black-red sweeps; on a one-level
+             * hierarchy with one sweep each this is the block red/black SSOR
+             * line-relaxation preconditioner of the one-level CG solver
+             * (Sec. 6.1 and Sec. 7.2, Table 2) */
+            smooth(Lv, mg->nu_pre, 0, mg->rho, b, u);
+            smooth(Lv, mg->nu_post, 1, mg->rho, b, u);
+        }
         return;
     }
     smooth(Lv, mg->nu_pre, 0, mg->rho, b, u);                 /* pre-smoothing   */
