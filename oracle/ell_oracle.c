@@ -578,6 +578,61 @@ int orc_pcg(const orc_mg *mg, const orc_opts *opt, const double *f, double *u, o
     return 0;
 }
 
+/* Stand-alone multigrid (Sec. 4.3, the V-cycle iterated as a solver; Sec. 7.3):
+ * u_K = u_{K-1} + z_K, z_K one V-cycle from zero applied to r_{K-1} (the V-cycle
+ * is linear in (b, u), so this is the V-cycle started from the current
+ * iterate).  The residual is carried by the recurrence r_K = r_{K-1} - A z_K,
+ * equal to b - A u_K in exact arithmetic (recomputing b - A u has a rounding
+ * floor far above 1e-5 on strongly graded grids).  Stopping as in Alg. PCG. */
+int orc_mg_solve(const orc_mg *mg, const orc_opts *opt, const double *f, double *u, orc_stats *st)
+{
+    hier_t H;
+    if (hier_init(&H, mg) != 0) return -1;
+    const level_t *L0 = &H.lev[0];
+    const int nx = L0->nx, ny = L0->ny, nz = L0->nz;
+    size_t n = level_n(L0);
+    double *b = (double *)malloc(sizeof(double) * n);
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *z = (double *)malloc(sizeof(double) * n);
+    double *q = (double *)malloc(sizeof(double) * n);
+    for (int k = 0; k < nz; k++)
+        for (size_t c = (size_t)k * nx * ny; c < (size_t)(k + 1) * nx * ny; c++) b[c] = L0->V[k] * f[c];
+    memset(st, 0, sizeof(*st));
+    residual(L0, b, u, r);
+    double r0 = sqrt(dot(n, r, r));
+    double bn = sqrt(dot(n, b, b));
+    st->r0_norm = r0;
+    st->b_norm = bn;
+    st->r_norm = r0;
+    int status = 1;
+    int K = 0;
+    double ref = opt->rel_to_rhs ? bn : r0;
+    if (!isfinite(r0)) {
+        status = -4;
+    } else if (r0 == 0.0 || r0 < opt->atol || r0 < opt->rtol * ref) {
+        status = 0;
+    } else {
+        for (K = 1; K <= opt->maxiter; K++) {
+            vcycle_rec(&H, mg, 0, r, z);           /* z = M^{-1} r      */
+            apply_level(L0, z, q);                 /* q = A z           */
+            for (size_t c = 0; c < n; c++) u[c] += z[c];
+            for (size_t c = 0; c < n; c++) r[c] -= q[c];
+            double rn = sqrt(dot(n, r, r));
+            st->r_norm = rn;
+            if (!isfinite(rn)) { status = -4; break; }
+            if (rn < opt->rtol * ref || rn < opt->atol) { status = 0; break; }
+        }
+        if (K > opt->maxiter) K = opt->maxiter;
+    }
+    st->iters = K;
+    st->status = status;
+    residual(L0, b, u, q);
+    st->true_r_norm = sqrt(dot(n, q, q));
+    free(b); free(r); free(z); free(q);
+    hier_free(&H);
+    return 0;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -76,6 +76,8 @@ def lib():
         L.orc_vcycle.restype = ctypes.c_int
         L.orc_pcg.argtypes = [ctypes.POINTER(MG), ctypes.POINTER(Opts), _dp, _dp, ctypes.POINTER(Stats)]
         L.orc_pcg.restype = ctypes.c_int
+        L.orc_mg_solve.argtypes = [ctypes.POINTER(MG), ctypes.POINTER(Opts), _dp, _dp, ctypes.POINTER(Stats)]
+        L.orc_mg_solve.restype = ctypes.c_int
         L.orc_num_levels.argtypes = [ctypes.POINTER(MG)]
         L.orc_num_levels.restype = ctypes.c_int
         L.orc_standard_levels.argtypes = [ctypes.c_int, ctypes.c_int]
@@ -235,6 +237,21 @@ def pcg(g: Grid, f, u0=None, rtol: float = 1e-5, atol: float = 0.0, maxiter: int
     o = Opts(rtol, atol, maxiter, int(flexible), int(rel_to_rhs))
     st = Stats()
     rc = lib().orc_pcg(ctypes.byref(m), ctypes.byref(o), _ptr(f), _ptr(u), ctypes.byref(st))
+    if rc != 0:
+        raise ValueError("invalid multigrid hierarchy")
+    return u, dict(iters=st.iters, r0_norm=st.r0_norm, r_norm=st.r_norm,
+                   true_r_norm=st.true_r_norm, b_norm=st.b_norm, status=st.status)
+
+
+def mg_solve(g: Grid, f, u0=None, rtol: float = 1e-5, atol: float = 0.0, maxiter: int = 500,
+             rel_to_rhs: bool = False):
+    """Stand-alone multigrid for A u = V f (repeated V-cycles); returns (u, stats dict)."""
+    f = _c(f).reshape(g.shape)
+    u = np.zeros(g.shape) if u0 is None else _c(u0).reshape(g.shape).copy()
+    m = g.mg()
+    o = Opts(rtol, atol, maxiter, 1, int(rel_to_rhs))
+    st = Stats()
+    rc = lib().orc_mg_solve(ctypes.byref(m), ctypes.byref(o), _ptr(f), _ptr(u), ctypes.byref(st))
     if rc != 0:
         raise ValueError("invalid multigrid hierarchy")
     return u, dict(iters=st.iters, r0_norm=st.r0_norm, r_norm=st.r_norm,
