@@ -139,6 +139,17 @@ int ell_vcycle(ell_grid *g, const double *r, double *z, hipStream_t stream);
 int ell_pcg_solve(ell_grid *g, const double *f, double *u, const ell_solve_opts *opts,
                   ell_solve_stats *stats, hipStream_t stream);
 
+/* Stand-alone multigrid (Sec. 4.3, the V-cycle iterated as a solver, as the
+ * paper runs its geometric multigrid in Sec. 7.3): u_K = u_{K-1} + M r_{K-1},
+ * r_K = r_{K-1} - A M r_{K-1}, from the caller's u_0, stopped like
+ * ell_pcg_solve (same options, opts->flexible ignored; same statistics,
+ * return codes, ownership and synchronisation; true_r_norm is the FP64
+ * ||b - A u|| of the returned u).  The residual is carried by the recurrence:
+ * on strongly graded grids the recomputed b - A u has a rounding floor above
+ * practical tolerances. */
+int ell_mg_solve(ell_grid *g, const double *f, double *u, const ell_solve_opts *opts,
+                 ell_solve_stats *stats, hipStream_t stream);
+
 /* ---- level entry points (the V-cycle's kernels one at a time) ------------
  * Colour-split layout of level l (nx_l = nx >> l, ny_l = ny >> l): element
  * (i, j, k) of colour c = (i+j) mod 2 lives at c*C + k*S + m, where

@@ -554,10 +554,25 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
   }
   {
     const int l = L - 1;
-    if (g->d.nu_coarse == 0) CHK(launch_fill<R>(U(l), 2 * g->lev[l].geo.cs, s));
-    for (int it = 0; it < g->d.nu_coarse; ++it) {
-      CHK(launch_smooth<R>(g, l, 0, it == 0, B(l), U(l), done, s));
-      CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
+    if (g->d.nu_coarse > 0) {
+      for (int it = 0; it < g->d.nu_coarse; ++it) {
+        CHK(launch_smooth<R>(g, l, 0, it == 0, B(l), U(l), done, s));
+        CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
+      }
+    } else {
+      // no coarse sweeps: smoothed like a finer level without a coarser
+      // correction (red-black, then black-red); one level with one sweep each
+      // is the block red/black SSOR line-relaxation preconditioner of the
+      // one-level CG solver (Sec. 6.1, Sec. 7.2 Table 2)
+      if (g->d.nu_pre == 0) CHK(launch_fill<R>(U(l), 2 * g->lev[l].geo.cs, s));
+      for (int it = 0; it < g->d.nu_pre; ++it) {
+        CHK(launch_smooth<R>(g, l, 0, it == 0, B(l), U(l), done, s));
+        CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
+      }
+      for (int it = 0; it < g->d.nu_post; ++it) {
+        CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
+        CHK(launch_smooth<R>(g, l, 0, false, B(l), U(l), done, s));
+      }
     }
   }
   for (int l = L - 2; l >= top; --l) {
@@ -726,32 +741,39 @@ int pcg_begin(ell_grid *g, const double *f, const double *u, const ell_solve_opt
 }
 
 // Iteration K (1-based) of the loop; a no-op on the device once done is set.
+// The fused operator step of iteration K: p_new = z + beta p_old (z alone with
+// first set), q = A p_new with <p, q>, and with defer set the previous
+// iteration's u += alpha p_old.
+template <typename Z>
+int launch_apply_dir(ell_grid *g, int K, int first, int defer, hipStream_t s) {
+  const Geo &G = g->lev[0].geo;
+  const int ab = apply_dir_blocks(g);
+  double *pbuf[2] = {g->p, g->p2};
+  ProfScope ps(g, ELL_K_APPLY, s);
+  const Z *zz = (const Z *)zvec<Z>(g);
+  if (g->apply_tile)
+    k_apply_dir_tile<Z><<<ab, kBlock, 0, s>>>(G, g->apply_nseg, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1],
+                                              g->q, g->us, g->st, first, defer, g->partial);
+  else if (g->stencil_seg == 1)
+    k_apply_dir<Z, 1><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us, g->st,
+                                            first, defer, g->partial);
+  else if (g->stencil_seg == 2)
+    k_apply_dir<Z, 2><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us, g->st,
+                                            first, defer, g->partial);
+  else
+    k_apply_dir<Z, 4><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us, g->st,
+                                            first, defer, g->partial);
+  return check_launch("k_apply_dir");
+}
+
 template <typename R, typename Z>
 int pcg_step(ell_grid *g, int K, hipStream_t s) {
-  const Geo &G = g->lev[0].geo;
   const long long n2 = g->n0 / 2;
   const int fb = flat_blocks(n2);
   const int ab = apply_dir_blocks(g);  // blocks of the CG operator kernel
   const int *done = &g->st->done;
-  double *pbuf[2] = {g->p, g->p2};
-  {
-    ProfScope ps(g, ELL_K_APPLY, s);
-    const int first = K == 1 ? 1 : 0, defer = K > 1 ? 1 : 0;
-    const Z *zz = (const Z *)zvec<Z>(g);
-    if (g->apply_tile)
-      k_apply_dir_tile<Z><<<ab, kBlock, 0, s>>>(G, g->apply_nseg, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1],
-                                                g->q, g->us, g->st, first, defer, g->partial);
-    else if (g->stencil_seg == 1)
-      k_apply_dir<Z, 1><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us,
-                                              g->st, first, defer, g->partial);
-    else if (g->stencil_seg == 2)
-      k_apply_dir<Z, 2><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us,
-                                              g->st, first, defer, g->partial);
-    else
-      k_apply_dir<Z, 4><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us,
-                                              g->st, first, defer, g->partial);
-  }
-  CHK(check_launch("k_apply_dir"));
+  CHK(launch_apply_dir<Z>(g, K, K == 1 ? 1 : 0, K > 1 ? 1 : 0, s));
+
   CHK(finalize(g, ab, 1, F_ALPHA, s));
   {
     ProfScope ps(g, ELL_K_UPDATE, s);
@@ -764,6 +786,44 @@ int pcg_step(ell_grid *g, int K, hipStream_t s) {
                                   g->partial);
   CHK(check_launch("k_dots"));
   return finalize(g, fb, 2, F_BETA, s);
+}
+
+// Stand-alone multigrid (Sec. 4.3, the V-cycle iterated as a solver):
+// u_K = u_{K-1} + z_K with z_K = M r_{K-1}, r_K = r_{K-1} - A z_K.  It runs on
+// the CG kernels with alpha = 1 and beta = 0 (F_UNIT): the operator step forms
+// p = z, q = A z and applies the previous iterate's u += p_old, the residual
+// update takes r -= q; no dots, no scalar recurrences.
+template <typename R, typename Z>
+int mg_begin(ell_grid *g, const double *f, const double *u, const ell_solve_opts &o, hipStream_t s) {
+  const Geo &G = g->lev[0].geo;
+  {
+    PcgState *h = g->st_host;
+    h->maxiter = o.maxiter;
+    h->flexible = 0;
+    HIPCHK(hipMemcpyAsync(&g->st->maxiter, &h->maxiter, 2 * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  const int bb = seg_blocks((long long)G.nx * G.ny);
+  k_begin<<<bb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, u, g->us, g->r, g->partial);
+  CHK(check_launch("k_begin"));
+  k_finalize<<<1, kBlock, 0, s>>>(g->partial, bb, 2, g->st, F_INIT, o.rtol, o.atol, o.rel_to_rhs);
+  CHK(check_launch("k_finalize"));
+  k_finalize<<<1, kBlock, 0, s>>>(g->partial, 0, 0, g->st, F_UNIT, 0, 0, 0);
+  return check_launch("k_finalize");
+}
+
+template <typename R, typename Z>
+int mg_step(ell_grid *g, int K, hipStream_t s) {
+  const long long n2 = g->n0 / 2;
+  const int fb = flat_blocks(n2);
+  CHK(precondition<R>(g, &g->st->done, s));
+  // K = 1: p = z (nothing to defer); later: p = z + 0 p_old and u += 1 p_old
+  CHK(launch_apply_dir<Z>(g, K, K == 1 ? 1 : 0, K > 1 ? 1 : 0, s));
+  {
+    ProfScope ps(g, ELL_K_UPDATE, s);
+    k_update_r<<<fb, kBlock, 0, s>>>((double2 *)g->r, (const double2 *)g->q, n2, g->st, g->partial);
+  }
+  CHK(check_launch("k_update_r"));
+  return finalize(g, fb, 1, F_CONV, s);
 }
 
 // End of a solve; g->st_host must hold the final state: the last step's
@@ -794,6 +854,24 @@ int pcg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, e
   while (enq < o.maxiter && !g->st_host->done) {
     const int batch = std::min(poll, o.maxiter - enq);
     for (int it = 0; it < batch; ++it) CHK((pcg_step<R, Z>(g, enq + it + 1, s)));
+    enq += batch;
+    HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return pcg_finish(g, f, u, out, s);
+}
+
+template <typename R, typename Z>
+int mg_impl(ell_grid *g, const double *f, double *u, const ell_solve_opts &o, ell_solve_stats *out,
+            hipStream_t s) {
+  CHK((mg_begin<R, Z>(g, f, u, o, s)));
+  const int poll = o.poll_every > 0 ? o.poll_every : 4;
+  int enq = 0;
+  HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  while (enq < o.maxiter && !g->st_host->done) {
+    const int batch = std::min(poll, o.maxiter - enq);
+    for (int it = 0; it < batch; ++it) CHK((mg_step<R, Z>(g, enq + it + 1, s)));
     enq += batch;
     HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1059,6 +1137,19 @@ int ell_pcg_solve(ell_grid *g, const double *f, double *u, const ell_solve_opts 
   if (g->prec == ELL_FP64) return pcg_impl<double, double>(g, f, u, o, stats, s);
   if (hybrid_ok(g)) return pcg_impl<float, double>(g, f, u, o, stats, s);
   return pcg_impl<float, float>(g, f, u, o, stats, s);
+}
+
+int ell_mg_solve(ell_grid *g, const double *f, double *u, const ell_solve_opts *opts, ell_solve_stats *stats,
+                 hipStream_t s) {
+  if (!g || !f || !u) return fail(ELL_ERR_INVALID, "NULL argument");
+  if ((const void *)f == (const void *)u) return fail(ELL_ERR_INVALID, "f and u must not alias");
+  ell_solve_opts o{1e-5, 0.0, 500, 0, 0, 4};
+  if (opts) o = *opts;
+  if (o.maxiter <= 0 || !(o.rtol >= 0) || !(o.atol >= 0))
+    return fail(ELL_ERR_INVALID, "maxiter must be > 0 and tolerances >= 0");
+  if (g->prec == ELL_FP64) return mg_impl<double, double>(g, f, u, o, stats, s);
+  if (hybrid_ok(g)) return mg_impl<float, double>(g, f, u, o, stats, s);
+  return mg_impl<float, float>(g, f, u, o, stats, s);
 }
 
 size_t ell_level_elems(const ell_grid *g, int level) {

@@ -1528,7 +1528,7 @@ __global__ __launch_bounds__(kBlock) void k_dir(double2 *__restrict__ p,
   }
 }
 
-enum FinalizeMode : int { F_INIT = 0, F_KAPPA = 1, F_ALPHA = 2, F_CONV = 3, F_BETA = 4, F_TRUE = 5 };
+enum FinalizeMode : int { F_INIT = 0, F_KAPPA = 1, F_ALPHA = 2, F_CONV = 3, F_BETA = 4, F_TRUE = 5, F_UNIT = 6 };
 
 // One block: reduce nq interleaved partial sums over nblk blocks in a fixed
 // order and advance the CG scalars (Appendix B, Alg. PCG).
@@ -1603,6 +1603,10 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
       if (!isfinite(beta)) { st->done = 1; st->status = -4; }
       break;
     }
+    case F_UNIT:  // stand-alone multigrid: unit steps along z, no direction memory
+      st->alpha = 1.0;
+      st->beta = 0.0;
+      break;
     case F_TRUE:  // partials of k_resid_init: [||b||^2, ||b - A u||^2]
       st->true_r_norm = sqrt(tot[nq - 1]);
       break;

@@ -66,7 +66,7 @@ EXPORTS = ["ell_grid_create", "ell_grid_destroy", "ell_grid_bytes", "ell_grid_le
            "ell_profile_times", "ell_level_layout", "ell_set_tuning", "ell_last_error",
            "ell_batch_create", "ell_batch_grid", "ell_batch_release", "ell_batch_bytes_in_use",
            "ell_batch_submit", "ell_batch_poll", "ell_batch_wait", "ell_batch_destroy",
-           "ell_autotune", "ell_schedule_get", "ell_schedule_set"]
+           "ell_autotune", "ell_schedule_get", "ell_schedule_set", "ell_mg_solve"]
 
 _lib = None
 
@@ -89,6 +89,7 @@ def load_library(path: str = LIB_PATH):
     L.ell_apply_A.argtypes = [vp, vp, vp, vp]
     L.ell_vcycle.argtypes = [vp, vp, vp, vp]
     L.ell_pcg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
+    L.ell_mg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
     L.ell_level_elems.argtypes = [vp, i32]
     L.ell_level_elems.restype = ctypes.c_size_t
     L.ell_to_split.argtypes = [vp, i32, vp, vp, vp]
@@ -284,6 +285,18 @@ class Grid:
         st = SolveStats()
         rc = load_library().ell_pcg_solve(self._h, _dev(f), _dev(u), ctypes.byref(o),
                                           ctypes.byref(st), _stream(stream))
+        if check:
+            _check(rc, allow=(ELL_OK, ELL_NOT_CONVERGED))
+        return u, Stats(st.iters, st.status, st.r0_norm, st.r_norm, st.true_r_norm, st.b_norm)
+
+    def mg_solve(self, f: torch.Tensor, u: Optional[torch.Tensor] = None, rtol=1e-5, atol=0.0,
+                 maxiter=500, rel_to_rhs=False, poll_every=4, stream=None, check=True):
+        """Stand-alone multigrid: repeated V-cycles (see ell_mg_solve)."""
+        u = torch.zeros_like(f) if u is None else u
+        o = SolveOpts(rtol, atol, maxiter, 0, int(rel_to_rhs), poll_every)
+        st = SolveStats()
+        rc = load_library().ell_mg_solve(self._h, _dev(f), _dev(u), ctypes.byref(o), ctypes.byref(st),
+                                         _stream(stream))
         if check:
             _check(rc, allow=(ELL_OK, ELL_NOT_CONVERGED))
         return u, Stats(st.iters, st.status, st.r0_norm, st.r_norm, st.true_r_norm, st.b_norm)

@@ -30,6 +30,11 @@ def vcycle_bytes(n0: int, levels: int, e: int, nu_pre=1, nu_post=1, nu_coarse=1)
             if nu_coarse > 0:
                 total += smooth_bytes(n, e, True) + smooth_bytes(n, e, False)
                 total += (nu_coarse - 1) * 2 * smooth_bytes(n, e, False)
+            else:  # no coarse sweeps: pre and post sweeps without a coarser correction
+                if nu_pre > 0:
+                    total += smooth_bytes(n, e, True) + smooth_bytes(n, e, False)
+                    total += (nu_pre - 1) * 2 * smooth_bytes(n, e, False)
+                total += nu_post * 2 * smooth_bytes(n, e, False)
         else:
             if nu_pre > 0:
                 total += smooth_bytes(n, e, True) + smooth_bytes(n, e, False)

@@ -209,6 +209,9 @@ def rel(a, b):
     ((32, 32, 8), dict(nu_pre=0, nu_post=2)),
     ((16, 16, 8), dict(nu_post=0)),
     ((1, 1, 12), dict()),
+    ((32, 32, 8), dict(n_levels=1, nu_coarse=0)),         # block red/black SSOR (one level)
+    ((16, 12, 7), dict(n_levels=2, nu_coarse=0)),
+    ((20, 8, 6), dict(n_levels=1, nu_coarse=0, nu_pre=0, nu_post=2)),
 ])
 def test_vcycle_matches_oracle(ell, orc, shape, mg):
     g = grid_for(orc, shape, **mg)
@@ -339,6 +342,48 @@ def test_autotuned_schedule_is_recorded_and_solves_match(ell, orc):
             assert st2.iters == 5 and rel(host(u2), ref) <= 1e-12
     finally:
         ell.schedule_set(None, **kw)
+
+
+def test_one_level_line_relaxation_cg_matches_oracle(ell, orc):
+    """CG preconditioned by one block red/black SSOR sweep of vertical line
+    relaxation (the paper's one-level solver, Table 2): same iterates as the
+    oracle and the same iteration count as its classic-beta variant."""
+    p = I.graded_problem("onelevel", 64, 32, 1e-2, 41, 42, n_levels=1, nu_coarse=0)
+    g = orc.Grid.from_problem(p)
+    G = ell.Grid.from_problem(p)
+    assert G.levels == 1
+    u, st = G.pcg_solve(dev(p.f), rtol=p.rtol)
+    assert st.status == 0
+    check_solve(orc, g, p.f, host(u), st, p.rtol)
+    u2, st2 = G.pcg_solve(dev(p.f), rtol=p.rtol, flexible=False)
+    assert abs(st2.iters - st.iters) <= 1
+
+
+@pytest.mark.parametrize("name,kw", [
+    ("config0", None),
+    ("mg_graded64_L4", dict(nx=64, nz=32, n_levels=4, nu_coarse=5)),
+    ("mg_graded96", dict(nx=96, nz=24)),
+])
+def test_standalone_multigrid_matches_oracle(ell, orc, name, kw):
+    """Stand-alone multigrid (repeated V-cycles): four iterations equal the
+    oracle's four, and the converged solve stops with it."""
+    if kw is None:
+        p = I.config0()
+    else:
+        kw = dict(kw)
+        p = I.graded_problem(name, kw.pop("nx"), kw.pop("nz"), 1e-2, 51, 52, **kw)
+    g = orc.Grid.from_problem(p)
+    G = ell.Grid.from_problem(p)
+    u, st = G.mg_solve(dev(p.f), rtol=1e-30, maxiter=4)
+    u_ref, st_ref = orc.mg_solve(g, p.f, rtol=1e-30, maxiter=4)
+    assert st.iters == st_ref["iters"] == 4 and st.status == ell.ELL_NOT_CONVERGED
+    assert rel(host(u), u_ref) <= 1e-10
+    assert abs(st.r_norm / st_ref["r_norm"] - 1) <= 1e-6
+    u, st = G.mg_solve(dev(p.f), rtol=p.rtol)
+    u_ref, st_ref = orc.mg_solve(g, p.f, rtol=p.rtol)
+    assert st.status == 0 and abs(st.iters - st_ref["iters"]) <= 1, (st.iters, st_ref["iters"])
+    if st.iters == st_ref["iters"]:
+        assert rel(host(u), u_ref) <= 1e-10
 
 
 def test_single_column_solve(ell, orc):
