@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--nu-coarse", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "batch", "serve"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "batch", "serve", "robust"],
                     help="c1: the 512^2x128 solve (default); batch: 64 uneven solves in the "
                          "batch engine vs sequential FP64; serve: Poisson request stream")
     ap.add_argument("--autotune", action="store_true",
@@ -100,6 +100,8 @@ def main():
         sys.exit(2)
     if a.workload == "c2":
         return bench_c2(a)
+    if a.workload == "robust":
+        return bench_robust(a)
     if a.workload == "batch":
         return bench_batch(a)
     if a.workload == "serve":
@@ -337,6 +339,71 @@ def bench_c2(a):
         "config": {"workload": "gmg-pcg 1024x1024x128 graded, standard depth, omega2 in {1e-3,1e-2,1e-1}, "
                                "rtol 1e-5, u0=0", "unknowns": 1024 * 1024 * 128, "precision": prec},
         "fp64_solves_per_s": 3 / t_64, "speedup_vs_fp64": t_64 / t_mixed, "per_omega2": rows,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_robust(a):
+    """Robustness sweep of Sec. 7.3 (Table 7, 3.4e7 unknowns): the flat analogue
+    of the paper's 512^2 x 128 run (Table 1 parameters: C_horiz = 17.8,
+    lambda^2 = 0.0332, the paper's vertical grading with H = 1/100), omega^2
+    scaled by f in {1, 10, 100} and lambda^2 by {1e-2, 1e2}; stand-alone
+    multigrid with the standard depth (to one column), shallow (7 levels) and
+    very shallow (4 levels, 5 coarsest-level sweeps) hierarchies, the one-level
+    CG with block red/black SSOR line relaxation, and GMG-preconditioned CG
+    (standard depth), each from u0 = 0 to 1e-5 in FP64.  value = solves/s of the
+    standard stand-alone multigrid over the sweep."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1307_2036_amd import ell, inputs
+    torch.cuda.set_device(0)
+    nx, nz = 512, 128
+    h = math.pi / (2 * nx)
+    dz = inputs.dz_paper_grading(nz, 0.01)
+    f = torch.from_numpy(inputs.rhs_normal(nx, nx, dz, inputs.seed_for(1))).cuda()
+    solvers = [("standard_mg", dict(n_levels=0, nu_coarse=1), "mg"),
+               ("shallow_mg", dict(n_levels=7, nu_coarse=1), "mg"),
+               ("very_shallow_mg", dict(n_levels=4, nu_coarse=5), "mg"),
+               ("cg_line_relaxation", dict(n_levels=1, nu_coarse=0), "pcg"),
+               ("gmg_pcg", dict(n_levels=0, nu_coarse=1), "pcg")]
+    cases = [(1, 1), (1, 1e2), (1, 1e-2), (10, 1), (100, 1)]
+    rows, t_std = [], 0.0
+    for fw, fl in cases:
+        row = {"f_omega2": fw, "f_lambda2": fl}
+        for name, mg, kind in solvers:
+            G = ell.Grid(nx, nx, nz, h, h, 17.8 * h * h * fw, dz,
+                         np.full(nz, inputs.paper_lambda2(600.0) * fl), **mg)
+            solve = G.mg_solve if kind == "mg" else G.pcg_solve
+            u = torch.zeros_like(f)
+            solve(f, u, rtol=1e-5, maxiter=1000)  # warm-up
+            times = []
+            for _ in range(2):
+                u.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, st = solve(f, u, rtol=1e-5, maxiter=1000, poll_every=8)
+                times.append(time.perf_counter() - t0)
+            t = min(times)
+            row[name] = {"iters": st.iters, "status": st.status, "levels": G.levels, "ms": t * 1e3,
+                         "ms_per_iter": t * 1e3 / max(st.iters, 1)}
+            if name == "standard_mg":
+                t_std += t
+            G.close()
+        rows.append(row)
+        print(json.dumps({"progress": row}), file=sys.stderr, flush=True)
+    out = {
+        "metric": METRIC, "value": len(cases) / t_std, "unit": "solves/s", "n_gpus": 1,
+        "steps": len(cases), "warmup": 1, "ms_per_step": t_std * 1e3 / len(cases),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded N(0,1) f; the paper's Table 1 parameters on a flat periodic panel)",
+        "config": {"workload": "robustness sweep 512x512x128 (Table 7): omega2 x {1,10,100}, "
+                               "lambda2 x {1e-2,1e2}; standard/shallow/very shallow stand-alone GMG, "
+                               "CG with line relaxation, GMG-PCG", "unknowns": nx * nx * nz},
+        "paper_table7_iters": {"standard_mg": [6, 6, 6, 6, 8], "shallow_mg": [6, 6, 6, 6, 10],
+                               "very_shallow_mg": [6, 6, 6, 15, 100],
+                               "cg_line_relaxation": [43, 42, 42, 140, 300]},
+        "rows": rows,
     }
     print(json.dumps(out), flush=True)
 
