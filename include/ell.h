@@ -212,13 +212,17 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * the CG operator step of grids with nx, ny > 1 on LDS-staged horizontal
  * tiles, 0 on the column-walking kernel; BATCH_GRAPH 1 (default) makes batch
  * engines created afterwards replay each grouped step from a captured HIP
- * graph, 0 launches the kernels directly (same results, bitwise). */
+ * graph, 0 launches the kernels directly (same results, bitwise); SMOOTH_TILE
+ * 1 (default) runs the finest level's FP64 half-sweeps after the first
+ * (rho = 1, nx/2 and ny even) with the other colour staged in LDS tiles, 0
+ * with the column kernel (same values). */
 enum {
   ELL_TUNE_PLANE_PAD = 0,
   ELL_TUNE_COLOUR_PAD = 1,
   ELL_TUNE_STENCIL_SEG = 2,
   ELL_TUNE_APPLY_TILE = 3,
-  ELL_TUNE_BATCH_GRAPH = 4
+  ELL_TUNE_BATCH_GRAPH = 4,
+  ELL_TUNE_SMOOTH_TILE = 5
 };
 int ell_set_tuning(int key, int value);
 

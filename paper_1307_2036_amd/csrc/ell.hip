@@ -160,6 +160,7 @@ struct ell_grid {
   int stencil_seg = 1;                  // k-segments of the CG operator kernels
   int apply_tile = 0;                   // the CG operator step uses the LDS-tiled kernel
   int apply_nseg = 1;                   // its k-segments
+  int smooth_tile = 0;                  // finest-level FP64 half-sweeps use the LDS-tiled kernel
   double *partial = nullptr;
   long long partial_cap = 0;
   PcgState *st = nullptr;
@@ -195,6 +196,7 @@ int g_colour_pad = 256;
 int g_stencil_seg = 1;  // k-segments of the CG operator kernels (1, 2 or 4)
 int g_apply_tile = 1;   // 1: LDS-tiled CG operator step where both horizontal directions exist
 int g_batch_graph = 1;  // 1: batch engines replay each grouped step from a captured graph
+int g_smooth_tile = 1;  // 1: finest-level FP64 half-sweeps stage the other colour in LDS tiles
 
 // Smoother segments per column: enough lanes to occupy the chip on small
 // levels, four (the register-resident optimum) on large ones; the finest
@@ -473,6 +475,22 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
   R *own = u + (long long)c * G.cs;
   const bool hxy = G.has_x && G.has_y;
   ProfScope ps(g, ELL_K_SMOOTH0, s, l == 0);
+  if constexpr (std::is_same<R, double>::value && std::is_same<TB, double>::value) {
+    // finest level, after the first sweep, rho = 1: the LDS-tiled half-sweep
+    const int Ls = seg_len(G.nz, G.nseg);
+    if (l == 0 && !zero && rho1 && hxy && g->smooth_tile && G.hx2 % 2 == 0 && G.ny % 2 == 0 &&
+        ((G.nseg == 8 && Ls <= 16) || (G.nseg == 4 && Ls <= 32))) {
+      const int tiles = ((G.hx2 + kSTX - 1) / kSTX) * (G.ny / 2);
+      const int nbt = blocks8((long long)tiles * kBlock);
+      if (G.nseg == 8)
+        k_smooth_tile<16, 8><<<nbt, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+      else if (Ls <= 16)
+        k_smooth_tile<16, 4><<<nbt, 4 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+      else
+        k_smooth_tile<32, 4><<<nbt, 4 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+      return check_launch("k_smooth_tile");
+    }
+  }
   if (hxy) {
     const int nbs = blocks8(((long long)ncol + kSegCols - 1) / kSegCols * kBlock);
     if (seg_dispatch<R, TB>(l == 0, nbs, s, G, tab, c, zero, rho1, bo, uo, own, rho, done))
@@ -981,6 +999,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->apply_tile = (sc.apply_tile && desc->nx > 1 && desc->ny > 1) ? 1 : 0;
   g->apply_nseg = g->apply_tile ? sc.apply_nseg : apply_segments(desc->nz);
   g->stencil_seg = batch_layout ? 1 : (g->apply_tile ? g_stencil_seg : sc.apply_nseg);
+  g->smooth_tile = g_smooth_tile;
   g->batch_layout = batch_layout;
   g->lev.resize(L);
   auto bail = [&](int rc) {
@@ -1407,6 +1426,10 @@ int ell_set_tuning(int key, int value) {
     case ELL_TUNE_BATCH_GRAPH:
       if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "batch graphs are 0 or 1");
       g_batch_graph = value;
+      return ELL_OK;
+    case ELL_TUNE_SMOOTH_TILE:
+      if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "smoother tiling is 0 or 1");
+      g_smooth_tile = value;
       return ELL_OK;
     default: return fail(ELL_ERR_INVALID, "unknown tuning key %d", key);
   }

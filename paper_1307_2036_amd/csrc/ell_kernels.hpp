@@ -261,6 +261,71 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ 
 // -------------------------------------------------------------------------
 // TB: element type of b (the FP32 preconditioner reads the FP64 CG residual
 // directly on the finest level).
+// The rest of a segmented half-sweep once every segment has run its local
+// forward recurrence (y[] local, prev = its last value): join the forward
+// values across segments, run the local backward recurrence, join it, and
+// write the column (rho = 1: the new values; else the relaxation).  xch: the
+// block's exchange array [NSEG][kSegCols]; ow: the output column at level 0.
+template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG>
+__device__ __forceinline__ void seg_join_store(R (&y)[SEG], R prev, R (*xch)[kSegCols], int sg, int lane,
+                                               int k0, int k1, int len, int nz, int Ls,
+                                               const R *__restrict__ pf, const R *__restrict__ cf,
+                                               const R *__restrict__ qb, bool valid, R *__restrict__ ow,
+                                               long long H, R rho) {
+  // join the forward recurrence across segments
+  xch[sg][lane] = prev;
+  __syncthreads();
+  R yin = R(0);
+  for (int q = 0; q < sg; ++q) {
+    const int e = min(q * Ls + Ls, nz);
+    const int s0 = min(q * Ls, nz);
+    const R pend = e > s0 ? pf[e - 1] : R(1);
+    yin = xch[q][lane] + pend * yin;
+  }
+  __syncthreads();
+  // true y, then the local backward recurrence (in place)
+  R nxt = R(0);
+#pragma unroll
+  for (int t = SEG - 1; t >= 0; --t) {
+    if (t < len) {
+      const int k = k0 + t;
+      const R yt = y[t] + pf[k] * yin;
+      nxt = yt + cf[k] * nxt;
+      y[t] = nxt;
+    }
+  }
+  xch[sg][lane] = nxt;  // local w at the segment's first level
+  __syncthreads();
+  R win = R(0);
+  for (int q = NSEG - 1; q > sg; --q) {
+    const int s0 = min(q * Ls, nz);
+    const int e = min(s0 + Ls, nz);
+    const R qs = e > s0 ? qb[s0] : R(1);
+    win = xch[q][lane] + qs * win;
+  }
+  if (valid) {
+#pragma unroll
+    for (int c0 = 0; c0 < SEG; c0 += 8) {
+      if (c0 < len) {
+        R old[8];
+        if (!RHO1 && !ZERO) {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) old[t] = ow[(long long)min(k0 + c0 + t, k1 - 1) * H];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          if (c0 + t < len) {
+            const int k = k0 + c0 + t;
+            const R w = y[c0 + t] + qb[k] * win;
+            const R o = (RHO1 || ZERO) ? R(0) : old[t];
+            st_s(&ow[(long long)k * H], RHO1 ? w : (R(1) - rho) * o + rho * w, FINE);
+          }
+        }
+      }
+    }
+  }
+}
+
 template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG, typename TB = R>
 __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab, int c,
                                                           const TB *__restrict__ bo,
@@ -322,58 +387,113 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
       }
     }
   }
-  // join the forward recurrence across segments
-  xch[sg][lane] = prev;
-  __syncthreads();
-  R yin = R(0);
-  for (int q = 0; q < sg; ++q) {
-    const int e = min(q * Ls + Ls, nz);
-    const int s0 = min(q * Ls, nz);
-    const R pend = e > s0 ? pf[e - 1] : R(1);
-    yin = xch[q][lane] + pend * yin;
-  }
-  __syncthreads();
-  // true y, then the local backward recurrence (in place)
-  R nxt = R(0);
+  seg_join_store<R, ZERO, RHO1, FINE, SEG, NSEG>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf, qb, valid, ow,
+                                                 H, rho);
+}
+
+// -------------------------------------------------------------------------
+// The same half-sweep for the finest FP64 level with rho = 1 after the first
+// sweep, with the other colour staged in LDS.  Five 64-lane loads per level
+// (b and four neighbours) keep the texture units near saturation although the
+// neighbours hit in cache; here a block owns 64 columns of colour c arranged
+// as 32 m-columns by 2 rows, one k-segment per wavefront, and per level a
+// wavefront loads its b (8 bytes per lane), the other colour's 4 x 32
+// interior values of rows j0-1 .. j0+2 (16 bytes per lane) and the 8 wrapped
+// end values (8 lanes), stages them in its own LDS slot and reads the four
+// neighbours there.  Needs nx/2 even (16-byte aligned pairs) and ny even.
+// LDS slot layout per row: [1] left end, [2 + x] interior x, [2 + nxm] right
+// end (interior pairs start at even indices, so pair writes are aligned).
+// -------------------------------------------------------------------------
+constexpr int kSTX = 32;  // m-columns per tile
+
+template <int SEG, int NSEG>
+__device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict__ tab, int c,
+                                                 const double *__restrict__ bo,
+                                                 const double *__restrict__ uo,
+                                                 double *__restrict__ own,
+                                                 const int *__restrict__ done, int lb) {
+  __shared__ double xch[NSEG][kSegCols];
+  __shared__ __align__(16) double ot[NSEG][4][36];
+  const int tiles_x = (L.hx2 + kSTX - 1) / kSTX;
+  if (is_done(done) || lb >= tiles_x * (L.ny / 2)) return;  // whole blocks: no barrier is skipped
+  const int lane = threadIdx.x & 63;
+  const int sg = wave_id();
+  const int ty = lb / tiles_x, tx = lb - ty * tiles_x;
+  const int mx0 = tx * kSTX, j0 = ty * 2;
+  const int nxm = min(kSTX, L.hx2 - mx0);
+  const int x = lane & 31, r = lane >> 5;
+  const int j = j0 + r;
+  const bool valid = x < nxm;
+  const int xm = valid ? x : nxm - 1;
+  const long long mo = (long long)j * L.hx2 + mx0 + xm;  // own split column
+  const int par = (j + c) & 1;                            // 1: the own cell sits at an odd i
+  // staging: interior pair of this lane, end value of lanes 0..7
+  const int rr = lane >> 4, pp = lane & 15;
+  const bool pv = 2 * pp < nxm;
+  const long long po = (long long)wrapi(j0 - 1 + rr, L.ny) * L.hx2 + mx0 + (pv ? 2 * pp : 0);
+  const int er = (lane >> 1) & 3, side = lane & 1;
+  const long long eo = (long long)wrapi(j0 - 1 + er, L.ny) * L.hx2 +
+                       (side ? (mx0 + nxm) % L.hx2 : (mx0 - 1 + L.hx2) % L.hx2);
+  const int ei = side ? nxm + 2 : 1;
+  const long long H = L.S;
+  const int nz = L.nz, Ls = seg_len(nz, NSEG);
+  const int k0 = min(sg * Ls, nz), k1 = min(k0 + Ls, nz), len = k1 - k0;
+  const double *__restrict__ txv = tab + TX * L.P;
+  const double *__restrict__ tyv = tab + TY * L.P;
+  const double *__restrict__ tz = tab + TZ * L.P;
+  const double *__restrict__ ip = tab + TIP * L.P;
+  const double *__restrict__ cf = tab + TCF * L.P;
+  const double *__restrict__ pf = tab + TPF * L.P;
+  const double *__restrict__ qb = tab + TQB * L.P;
+  double(*slot)[36] = ot[sg];
+
+  double y[SEG];
+  double prev = 0.0;
 #pragma unroll
-  for (int t = SEG - 1; t >= 0; --t) {
-    if (t < len) {
-      const int k = k0 + t;
-      const R yt = y[t] + pf[k] * yin;
-      nxt = yt + cf[k] * nxt;
-      y[t] = nxt;
-    }
-  }
-  xch[sg][lane] = nxt;  // local w at the segment's first level
-  __syncthreads();
-  R win = R(0);
-  for (int q = NSEG - 1; q > sg; --q) {
-    const int s0 = min(q * Ls, nz);
-    const int e = min(s0 + Ls, nz);
-    const R qs = e > s0 ? qb[s0] : R(1);
-    win = xch[q][lane] + qs * win;
-  }
-  if (valid) {
+  for (int c0 = 0; c0 < SEG; c0 += 8) {
+    if (c0 < len) {
+      double bv[8], ev[8];
+      double2 tv[8];
 #pragma unroll
-    for (int c0 = 0; c0 < SEG; c0 += 8) {
-      if (c0 < len) {
-        R old[8];
-        if (!RHO1 && !ZERO) {
+      for (int t = 0; t < 8; ++t) {
+        const long long o = (long long)min(k0 + c0 + t, k1 - 1) * H;
+        bv[t] = __builtin_nontemporal_load(&bo[o + mo]);
+        tv[t] = *(const double2 *)&uo[o + po];
+        ev[t] = lane < 8 ? uo[o + eo] : 0.0;
+      }
 #pragma unroll
-          for (int t = 0; t < 8; ++t) old[t] = ow[(long long)min(k0 + c0 + t, k1 - 1) * H];
-        }
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-          if (c0 + t < len) {
-            const int k = k0 + c0 + t;
-            const R w = y[c0 + t] + qb[k] * win;
-            const R o = (RHO1 || ZERO) ? R(0) : old[t];
-            st_s(&ow[(long long)k * H], RHO1 ? w : (R(1) - rho) * o + rho * w, FINE);
-          }
+      for (int t = 0; t < 8; ++t) {
+        if (c0 + t < len) {
+          const int k = k0 + c0 + t;
+          // stage level k (LDS operations of a wavefront complete in order; the
+          // empty asm keeps the compiler from moving them across each other)
+          if (pv) *(double2 *)&slot[rr][2 + 2 * pp] = tv[t];
+          __asm__ volatile("" ::: "memory");
+          if (lane < 8) slot[er][ei] = ev[t];
+          __asm__ volatile("" ::: "memory");
+          const double w = slot[r + 1][x + 1 + par], e = slot[r + 1][x + 2 + par];
+          const double so = slot[r][x + 2], no = slot[r + 2][x + 2];
+          __asm__ volatile("" ::: "memory");
+          double g = bv[t];
+          g = g + txv[k] * (w + e);
+          g = g + tyv[k] * (so + no);
+          prev = (g + tz[k] * prev) * ip[k];
+          y[c0 + t] = prev;
         }
       }
     }
   }
+  seg_join_store<double, false, true, true, SEG, NSEG>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf, qb,
+                                                       valid, own + mo, H, 1.0);
+}
+
+template <int SEG, int NSEG>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_tile(Geo L, const double *__restrict__ tab, int c,
+                                                           const double *__restrict__ bo,
+                                                           const double *__restrict__ uo,
+                                                           double *__restrict__ own,
+                                                           const int *__restrict__ done) {
+  smooth_tile_body<SEG, NSEG>(L, tab, c, bo, uo, own, done, logical_block());
 }
 
 template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG, typename TB = R>

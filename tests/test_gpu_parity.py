@@ -96,9 +96,12 @@ def test_apply_matches_oracle(ell, orc, shape):
     assert np.all(np.abs(y - ref) <= bound)
 
 
-# (34, 10, 100) and (66, 18, 64): eight k-segments on the finest level (ragged: 13 x 7 + 9)
+# (34, 10, 100) and (66, 18, 64): eight k-segments on the finest level (ragged: 13 x 7 + 9);
+# (68, 10, 100), (4, 6, 70), (64, 48, 37): the LDS-tiled half-sweep (nx/2 and ny even), with a
+# partial tile (34 = 32 + 2 m-columns), eight and four ragged segments
 @pytest.mark.parametrize("shape", [(32, 32, 16), (64, 48, 37), (2, 2, 3), (1, 6, 4), (6, 1, 5),
-                                   (1, 1, 5), (130, 8, 7), (34, 10, 100), (66, 18, 64)])
+                                   (1, 1, 5), (130, 8, 7), (34, 10, 100), (66, 18, 64),
+                                   (68, 10, 100), (4, 6, 70)])
 @pytest.mark.parametrize("rho", [1.0, 0.8])
 def test_smoother_matches_oracle(ell, orc, shape, rho):
     g = grid_for(orc, shape, rho=rho)
@@ -123,6 +126,29 @@ def test_smoother_matches_oracle(ell, orc, shape, rho):
     ref = orc.smooth_colour(g, 1, b, u0, rho)
     got = host(G.from_split(0, us, torch.zeros(g.shape, dtype=torch.float64, device="cuda")))
     assert np.all(np.abs(got - ref) <= 1e-12 * np.abs(ref).max(axis=0, keepdims=True) + 1e-300)
+
+
+@pytest.mark.parametrize("shape", [(68, 10, 100), (64, 48, 37), (4, 6, 70), (128, 16, 128), (96, 4, 32)])
+def test_tiled_half_sweep_equals_column_kernel(ell, orc, shape):
+    """The LDS-tiled finest-level half-sweep computes every column from the same
+    terms in the same order as the column kernel: bitwise equal results."""
+    g = grid_for(orc, shape)
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal(g.shape) * (g.hx * g.hy * g.dz)[:, None, None]
+    out = []
+    for tile in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_SMOOTH_TILE, tile)
+        try:
+            G = gpu_grid(ell, g)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_SMOOTH_TILE, 1)
+        bs = G.to_split(0, dev(b))
+        us = G.level_empty(0)
+        G.level_smooth(0, 0, bs, us, zero_init=True)
+        for colour in (1, 0, 1, 0):
+            G.level_smooth(0, colour, bs, us)
+        out.append(host(us))
+    np.testing.assert_array_equal(out[0], out[1])
 
 
 @pytest.mark.parametrize("shape", [(32, 32, 16), (64, 48, 37), (4, 2, 3), (2, 2, 6), (256, 12, 9)])
