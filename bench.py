@@ -193,7 +193,9 @@ def main():
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "true_rel_residual": st.true_r_norm / st.b_norm,
-        "roofline": {"bound": "hbm", "kernel": f"k_smooth_seg (finest level, {'FP64' if a.precision == 'fp64' else 'FP32 pre / FP64 post'})",
+        "roofline": {"bound": "hbm", "kernel": "finest-level line relaxation, " + ("k_smooth_tile (+ k_smooth_seg first sweep), FP64"
+                                                                if a.precision == "fp64" else
+                                                                "FP32 pre / FP64 post sweeps"),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(a.precision),
                      "avg_launch_us": avg_ms * 1e3, "launches": cnt,
