@@ -1071,22 +1071,6 @@ __global__ __launch_bounds__(kBlock) void k_update_r(double2 *__restrict__ r,
   update_r_body(r, q, n2, st, partial, logical_block(), gridDim.x);
 }
 
-// u <- u + alpha p (the last step's deferred solution update)
-__global__ __launch_bounds__(kBlock) void k_axpy_alpha(double2 *__restrict__ u,
-                                                       const double2 *__restrict__ p, long long n2,
-                                                       const PcgState *__restrict__ st) {
-  const double alpha = st->alpha;
-  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
-  const long long stride = (long long)gridDim.x * kBlock;
-  for (long long e = t; e < n2; e += stride) {
-    const double2 pv = p[e];
-    double2 uv = u[e];
-    uv.x = uv.x + alpha * pv.x;
-    uv.y = uv.y + alpha * pv.y;
-    u[e] = uv;
-  }
-}
-
 // A fixed pseudo-random field in [-1, 1): element e is a 64-bit mix of e
 // (the input of schedule timing; nothing numerical depends on its values).
 __global__ __launch_bounds__(kBlock) void k_fill_hash(double *__restrict__ f, long long n) {
@@ -1530,59 +1514,6 @@ __global__ __launch_bounds__(kBlock) void k_finish(Geo L, const double *__restri
 // fixed order, so every result is independent of scheduling.
 // -------------------------------------------------------------------------
 
-// r <- r - q, partial sums of ||r_before||^2 (= ||b||^2) and ||r_after||^2
-__global__ __launch_bounds__(kBlock) void k_resid_init(const double2 *__restrict__ q,
-                                                       double2 *__restrict__ r, long long n2,
-                                                       double *__restrict__ partial) {
-  __shared__ double sh[4];
-  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
-  const long long stride = (long long)gridDim.x * kBlock;
-  double bb = 0.0, rr = 0.0;
-  for (long long e = t; e < n2; e += stride) {
-    double2 b = r[e];
-    const double2 a = q[e];
-    bb += b.x * b.x + b.y * b.y;
-    b.x = b.x - a.x;
-    b.y = b.y - a.y;
-    rr += b.x * b.x + b.y * b.y;
-    r[e] = b;
-  }
-  const double s0 = block_sum(bb, sh);
-  const double s1 = block_sum(rr, sh);
-  if (threadIdx.x == 0) {
-    partial[2 * logical_block()] = s0;
-    partial[2 * logical_block() + 1] = s1;
-  }
-}
-
-// u <- u + alpha p, r <- r - alpha q, partial sums of ||r||^2
-__global__ __launch_bounds__(kBlock) void k_update(double2 *__restrict__ u,
-                                                   const double2 *__restrict__ p,
-                                                   double2 *__restrict__ r,
-                                                   const double2 *__restrict__ q, long long n2,
-                                                   const PcgState *__restrict__ st,
-                                                   double *__restrict__ partial) {
-  __shared__ double sh[4];
-  if (st->done) return;
-  const double alpha = st->alpha;
-  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
-  const long long stride = (long long)gridDim.x * kBlock;
-  double rr = 0.0;
-  for (long long e = t; e < n2; e += stride) {
-    const double2 pv = p[e], qv = q[e];
-    double2 uv = u[e], rv = r[e];
-    uv.x = uv.x + alpha * pv.x;
-    uv.y = uv.y + alpha * pv.y;
-    rv.x = rv.x - alpha * qv.x;
-    rv.y = rv.y - alpha * qv.y;
-    u[e] = uv;
-    r[e] = rv;
-    rr += rv.x * rv.x + rv.y * rv.y;
-  }
-  const double s = block_sum(rr, sh);
-  if (threadIdx.x == 0) partial[logical_block()] = s;
-}
-
 template <typename Z> struct Vec2;
 template <> struct Vec2<double> { using T = double2; };
 template <> struct Vec2<float> { using T = float2; };
@@ -1621,31 +1552,6 @@ __global__ __launch_bounds__(kBlock) void k_dots(const double2 *__restrict__ r,
                                                  const PcgState *__restrict__ st,
                                                  double *__restrict__ partial) {
   dots_body<Z>(r, z, q, n2, st, partial, logical_block(), gridDim.x);
-}
-
-// p <- z + beta p (p <- z on the first iteration)
-template <typename Z>
-__global__ __launch_bounds__(kBlock) void k_dir(double2 *__restrict__ p,
-                                                const typename Vec2<Z>::T *__restrict__ z,
-                                                long long n2, const PcgState *__restrict__ st,
-                                                int first) {
-  if (st->done) return;
-  const double beta = st->beta;
-  const long long t = (long long)logical_block() * kBlock + threadIdx.x;
-  const long long stride = (long long)gridDim.x * kBlock;
-  for (long long e = t; e < n2; e += stride) {
-    const auto zv = z[e];
-    double2 pv;
-    if (first) {
-      pv.x = (double)zv.x;
-      pv.y = (double)zv.y;
-    } else {
-      pv = p[e];
-      pv.x = (double)zv.x + beta * pv.x;
-      pv.y = (double)zv.y + beta * pv.y;
-    }
-    p[e] = pv;
-  }
 }
 
 enum FinalizeMode : int { F_INIT = 0, F_KAPPA = 1, F_ALPHA = 2, F_CONV = 3, F_BETA = 4, F_TRUE = 5, F_UNIT = 6 };
@@ -1727,7 +1633,7 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
       st->alpha = 1.0;
       st->beta = 0.0;
       break;
-    case F_TRUE:  // partials of k_resid_init: [||b||^2, ||b - A u||^2]
+    case F_TRUE:  // partials of k_finish: [||V f||^2, ||V f - A u||^2]
       st->true_r_norm = sqrt(tot[nq - 1]);
       break;
   }
