@@ -510,6 +510,15 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
   }
 }
 
+// k-segments of the restriction and prolongation kernels: four on large
+// levels, more on small coarse levels, where the sequential walk over a
+// segment is the kernel's latency; at least 8 levels per segment.
+inline int transfer_segments(long long slots, int nz) {
+  int ns = slots >= 32768 ? 4 : (slots >= 8192 ? 8 : 16);
+  while (ns > 4 && seg_len(nz, ns) < 8) ns /= 2;
+  return ns;
+}
+
 template <typename R, typename TB = R>
 int launch_restrict(ell_grid *g, int l, const TB *b, const R *u, R *bc, bool bz, const int *done,
                     hipStream_t s) {
@@ -518,7 +527,11 @@ int launch_restrict(ell_grid *g, int l, const TB *b, const R *u, R *bc, bool bz,
   const R *tab = (const R *)g->lev[l].tab;
   ProfScope ps(g, ELL_K_RESTRICT0, s, l == 0);
   if (bz && F.has_x && F.has_y) {
-    k_resid_restrict_bz<R, TB><<<seg_blocks(2LL * C.H), kBlock, 0, s>>>(F, C, tab, b, u, bc, done);
+    const int nbz = seg_blocks(2LL * C.H);
+    const int ns = transfer_segments(2LL * C.H, F.nz);
+    if (ns == 16) k_resid_restrict_bz<R, TB, 16><<<nbz, 16 * 64, 0, s>>>(F, C, tab, b, u, bc, done);
+    else if (ns == 8) k_resid_restrict_bz<R, TB, 8><<<nbz, 8 * 64, 0, s>>>(F, C, tab, b, u, bc, done);
+    else k_resid_restrict_bz<R, TB, 4><<<nbz, 4 * 64, 0, s>>>(F, C, tab, b, u, bc, done);
     return check_launch("k_resid_restrict_bz");
   }
   if constexpr (!std::is_same<R, TB>::value) {
@@ -535,13 +548,20 @@ int launch_prolong(ell_grid *g, int l, const R *uc, R *u, bool red_only, const i
   const Geo &F = g->lev[l].geo, &C = g->lev[l + 1].geo;
   const int nb = seg_blocks(red_only ? (long long)F.ncol0 : 2LL * F.H);
   ProfScope ps(g, ELL_K_PROLONG0, s, l == 0);
-  if (g->d.prolong == 1) {
-    if (red_only) k_prolong<R, true, 1><<<nb, kBlock, 0, s>>>(F, C, uc, u, done);
-    else k_prolong<R, false, 1><<<nb, kBlock, 0, s>>>(F, C, uc, u, done);
-  } else {
-    if (red_only) k_prolong<R, true, 0><<<nb, kBlock, 0, s>>>(F, C, uc, u, done);
-    else k_prolong<R, false, 0><<<nb, kBlock, 0, s>>>(F, C, uc, u, done);
-  }
+  const int ns = transfer_segments(red_only ? (long long)F.ncol0 : 2LL * F.H, F.nz);
+  auto go = [&](auto nseg) {
+    constexpr int NS = decltype(nseg)::value;
+    if (g->d.prolong == 1) {
+      if (red_only) k_prolong<R, true, 1, NS><<<nb, NS * 64, 0, s>>>(F, C, uc, u, done);
+      else k_prolong<R, false, 1, NS><<<nb, NS * 64, 0, s>>>(F, C, uc, u, done);
+    } else {
+      if (red_only) k_prolong<R, true, 0, NS><<<nb, NS * 64, 0, s>>>(F, C, uc, u, done);
+      else k_prolong<R, false, 0, NS><<<nb, NS * 64, 0, s>>>(F, C, uc, u, done);
+    }
+  };
+  if (ns == 16) go(std::integral_constant<int, 16>());
+  else if (ns == 8) go(std::integral_constant<int, 8>());
+  else go(std::integral_constant<int, 4>());
   return check_launch("k_prolong");
 }
 

@@ -533,7 +533,7 @@ __device__ __forceinline__ R cell_residual(R bk, R vk, R txk, R tyk, R tzlo, R t
 // child (2I,2J): W=A E=B S=C N=D;  child (2I+1,2J+1): W=D E=E S=B N=F.
 // Requires both horizontal directions to have faces.
 // -------------------------------------------------------------------------
-template <typename R, typename TB = R>
+template <typename R, typename TB = R, int NSEG = kSeg>
 __device__ __forceinline__ void resid_restrict_bz_body(Geo F, Geo C,
                                                               const R *__restrict__ tab,
                                                               const TB *__restrict__ b,
@@ -547,7 +547,7 @@ __device__ __forceinline__ void resid_restrict_bz_body(Geo F, Geo C,
   const int cc = gid & 1;  // lanes alternate coarse colours (adjacent coarse columns)
   const int mc = gid >> 1;
   if (mc >= (cc ? C.ncol1 : C.ncol0)) return;
-  const int Ls = seg_len(F.nz);
+  const int Ls = seg_len(F.nz, NSEG);
   const int k0 = min(wave_id() * Ls, F.nz), k1 = min(k0 + Ls, F.nz);
   int I, J;
   col_ij(C, cc, mc, I, J);
@@ -612,14 +612,16 @@ __device__ __forceinline__ void resid_restrict_bz_body(Geo F, Geo C,
   }
 }
 
-template <typename R, typename TB = R>
-__global__ __launch_bounds__(kBlock) void k_resid_restrict_bz(Geo F, Geo C,
-                                                              const R *__restrict__ tab,
-                                                              const TB *__restrict__ b,
-                                                              const R *__restrict__ u,
-                                                              R *__restrict__ bc,
-                                                              const int *__restrict__ done) {
-  resid_restrict_bz_body<R, TB>(F, C, tab, b, u, bc, done, logical_block(), gridDim.x);
+// NSEG k-segments per column, one wavefront each (more on small coarse levels,
+// where the sequential walk over a segment is the kernel's latency).
+template <typename R, typename TB = R, int NSEG = kSeg>
+__global__ __launch_bounds__(NSEG * 64) void k_resid_restrict_bz(Geo F, Geo C,
+                                                                 const R *__restrict__ tab,
+                                                                 const TB *__restrict__ b,
+                                                                 const R *__restrict__ u,
+                                                                 R *__restrict__ bc,
+                                                                 const int *__restrict__ done) {
+  resid_restrict_bz_body<R, TB, NSEG>(F, C, tab, b, u, bc, done, logical_block(), gridDim.x);
 }
 
 // -------------------------------------------------------------------------
@@ -703,7 +705,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Geo F, Geo C, const R
 // 3/16 (the nearer x and y neighbours) and 1/16 (the diagonal one).
 // MODE 1: piecewise constant.  RED_ONLY: colour-0 fine columns only.
 // -------------------------------------------------------------------------
-template <typename R, bool RED_ONLY, int MODE>
+template <typename R, bool RED_ONLY, int MODE, int NSEG = kSeg>
 __device__ __forceinline__ void prolong_body(Geo F, Geo C, const R *__restrict__ uc,
                                                     R *__restrict__ u,
                                                     const int *__restrict__ done, int lb, int nblocks) {
@@ -720,7 +722,7 @@ __device__ __forceinline__ void prolong_body(Geo F, Geo C, const R *__restrict__
     m = gid >> 1;
     if (m >= (c ? F.ncol1 : F.ncol0)) return;
   }
-  const int Ls = seg_len(F.nz);
+  const int Ls = seg_len(F.nz, NSEG);
   const int k0 = min(wave_id() * Ls, F.nz), k1 = min(k0 + Ls, F.nz);
   int i, j;
   col_ij(F, c, m, i, j);
@@ -767,11 +769,11 @@ __device__ __forceinline__ void prolong_body(Geo F, Geo C, const R *__restrict__
   }
 }
 
-template <typename R, bool RED_ONLY, int MODE>
-__global__ __launch_bounds__(kBlock) void k_prolong(Geo F, Geo C, const R *__restrict__ uc,
-                                                    R *__restrict__ u,
-                                                    const int *__restrict__ done) {
-  prolong_body<R, RED_ONLY, MODE>(F, C, uc, u, done, logical_block(), gridDim.x);
+template <typename R, bool RED_ONLY, int MODE, int NSEG = kSeg>
+__global__ __launch_bounds__(NSEG * 64) void k_prolong(Geo F, Geo C, const R *__restrict__ uc,
+                                                       R *__restrict__ u,
+                                                       const int *__restrict__ done) {
+  prolong_body<R, RED_ONLY, MODE, NSEG>(F, C, uc, u, done, logical_block(), gridDim.x);
 }
 
 // Colour-0 prolongation from an FP32 hierarchy into the FP64 output of the

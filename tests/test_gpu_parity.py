@@ -167,10 +167,13 @@ def test_residual_restriction_matches_oracle(ell, orc, shape):
     assert np.all(np.abs(got - ref) <= 16 * EPS * scale)
 
 
-def test_black_zero_restriction_after_sweep(ell, orc):
+# (32, 32, 128), (64, 64, 100): small levels with deep columns run the
+# restriction with 16 and 8 (ragged) k-segments per coarse column
+@pytest.mark.parametrize("shape", [(64, 32, 24), (32, 32, 128), (64, 64, 100)])
+def test_black_zero_restriction_after_sweep(ell, orc, shape):
     """After red then black (rho = 1) the black residual is zero up to rounding,
     and the restriction that skips the black children agrees with the full one."""
-    g = grid_for(orc, (64, 32, 24), n_levels=2)
+    g = grid_for(orc, shape, n_levels=2)
     G = gpu_grid(ell, g)
     b = np.random.default_rng(5).standard_normal(g.shape) * (g.hx * g.hy * g.dz)[:, None, None]
     bs = G.to_split(0, dev(b))
@@ -187,7 +190,8 @@ def test_black_zero_restriction_after_sweep(ell, orc):
     assert np.all(np.abs(got - ref) <= 64 * EPS * scale)
 
 
-@pytest.mark.parametrize("shape", [(32, 32, 16), (64, 48, 37), (4, 2, 3), (2, 2, 6), (4, 4, 1)])
+@pytest.mark.parametrize("shape", [(32, 32, 16), (64, 48, 37), (4, 2, 3), (2, 2, 6), (4, 4, 1),
+                                   (32, 32, 128), (64, 64, 100)])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_prolongation_matches_oracle(ell, orc, shape, mode):
     g = grid_for(orc, shape, n_levels=2, prolong=mode)
