@@ -213,9 +213,10 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * tiles, 0 on the column-walking kernel; BATCH_GRAPH 1 (default) makes batch
  * engines created afterwards replay each grouped step from a captured HIP
  * graph, 0 launches the kernels directly (same results, bitwise); SMOOTH_TILE
- * 1 (default) runs the finest level's FP64 half-sweeps after the first
- * (rho = 1, nx/2 and ny even) with the other colour staged in LDS tiles, 0
- * with the column kernel (same values). */
+ * 1 (default) stages neighbour values in LDS tiles for the finest level's
+ * FP64 half-sweeps after the first (rho = 1, nx/2 and ny even) and for the
+ * bilinear colour-0 prolongation (ny even), 0 uses the column kernels (same
+ * values, bitwise). */
 enum {
   ELL_TUNE_PLANE_PAD = 0,
   ELL_TUNE_COLOUR_PAD = 1,

@@ -549,6 +549,14 @@ int launch_prolong(ell_grid *g, int l, const R *uc, R *u, bool red_only, const i
   const int nb = seg_blocks(red_only ? (long long)F.ncol0 : 2LL * F.H);
   ProfScope ps(g, ELL_K_PROLONG0, s, l == 0);
   const int ns = transfer_segments(red_only ? (long long)F.ncol0 : 2LL * F.H, F.nz);
+  if (red_only && g->d.prolong == 0 && g->smooth_tile && F.has_x && F.ny % 2 == 0) {
+    // bilinear onto colour 0 with the coarse rows staged in LDS
+    const int nbt = blocks8((long long)((F.hx2 + kSTX - 1) / kSTX) * (F.ny / 2) * kBlock);
+    if (ns == 16) k_prolong_tile<R, 16><<<nbt, 16 * 64, 0, s>>>(F, C, uc, u, done);
+    else if (ns == 8) k_prolong_tile<R, 8><<<nbt, 8 * 64, 0, s>>>(F, C, uc, u, done);
+    else k_prolong_tile<R, 4><<<nbt, 4 * 64, 0, s>>>(F, C, uc, u, done);
+    return check_launch("k_prolong_tile");
+  }
   auto go = [&](auto nseg) {
     constexpr int NS = decltype(nseg)::value;
     if (g->d.prolong == 1) {

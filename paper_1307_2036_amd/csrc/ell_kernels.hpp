@@ -769,6 +769,81 @@ __device__ __forceinline__ void prolong_body(Geo F, Geo C, const R *__restrict__
   }
 }
 
+// Colour-0 bilinear prolongation with the coarse values staged in LDS.  The
+// column kernel's four coarse loads per level go through the texture units
+// for every fine cell although each coarse value serves four fine cells; here
+// a wavefront owns 32 m-columns by 2 rows of fine red cells (rows j0, j0+1
+// share the coarse parent row J = j0/2) over one k-segment, and per level
+// loads its own values and the coarse rows J-1, J, J+1 at coarse columns
+// mx0-1 .. mx0+32 (102 values, two loads), then interpolates from LDS with
+// the column kernel's weights and order (bitwise equal results).  Needs ny
+// even and nx > 1; blocks past the last tile return at once.
+template <typename R, int NSEG>
+__device__ __forceinline__ void prolong_tile_body(Geo F, Geo C, const R *__restrict__ uc, R *__restrict__ u,
+                                                  const int *__restrict__ done, int lb) {
+  __shared__ R cs[NSEG][3][36];
+  const int tiles_x = (F.hx2 + kSTX - 1) / kSTX;
+  if (is_done(done) || lb >= tiles_x * (F.ny / 2)) return;
+  const int lane = threadIdx.x & 63;
+  const int sg = wave_id();
+  const int ty = lb / tiles_x, tx = lb - ty * tiles_x;
+  const int mx0 = tx * kSTX, j0 = ty * 2;
+  const int nxm = min(kSTX, F.hx2 - mx0);
+  const int x = lane & 31, r = lane >> 5;
+  const bool valid = x < nxm;
+  const long long mo = (long long)(j0 + r) * F.hx2 + mx0 + (valid ? x : nxm - 1);
+  const int J = j0 >> 1;
+  // staged coarse values: v = lane (first load) and 64 + lane (second); row v/34, column v%34
+  auto coarse_off = [&](int v, bool &need) -> long long {
+    const int row = v / 34, q = v - row * 34;
+    need = v < 102 && q <= nxm + 1;
+    const int I = wrapi(mx0 - 1 + (need ? q : 1), C.nx);
+    const int Jr = wrapi(J - 1 + (need ? row : 1), C.ny);
+    return (long long)((I + Jr) & 1) * C.cs + col_m(C, I, Jr);
+  };
+  bool need0, need1;
+  const long long co0 = coarse_off(lane, need0), co1 = coarse_off(64 + lane, need1);
+  const int r0 = lane / 34, q0 = lane - r0 * 34, r1 = (64 + lane) / 34, q1 = (64 + lane) - r1 * 34;
+  const long long HC = C.S, HF = F.S;
+  const int nz = F.nz, Ls = seg_len(nz, NSEG);
+  const int k0 = min(sg * Ls, nz), k1 = min(k0 + Ls, nz);
+  R(*slot)[36] = cs[sg];
+  // the four coarse neighbours of this lane's fine cell in the slot
+  const int ia = x + 1, ib = r ? x + 2 : x, rc = r ? 2 : 0;
+  R *__restrict__ own = u + mo;
+  for (int k = k0; k < k1; k += kChunk) {
+    R o[kChunk], v0[kChunk], v1[kChunk];
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) {
+      const int kk = min(k + t, k1 - 1);
+      o[t] = __builtin_nontemporal_load(&own[(long long)kk * HF]);
+      v0[t] = uc[(long long)kk * HC + co0];
+      v1[t] = need1 ? uc[(long long)kk * HC + co1] : R(0);
+    }
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) {
+      if (k + t < k1) {
+        if (need0) slot[r0][q0] = v0[t];
+        if (need1) slot[r1][q1] = v1[t];
+        __asm__ volatile("" ::: "memory");
+        const R a = slot[1][ia], b2 = slot[1][ib], c2 = slot[rc][ia], d = slot[rc][ib];
+        __asm__ volatile("" ::: "memory");
+        R e = R(9.0 / 16.0) * a;
+        e = e + R(3.0 / 16.0) * b2;
+        e = e + R(3.0 / 16.0) * c2;
+        e = e + R(1.0 / 16.0) * d;
+        if (valid) __builtin_nontemporal_store(o[t] + e, &own[(long long)(k + t) * HF]);
+      }
+    }
+  }
+}
+
+template <typename R, int NSEG>
+__global__ __launch_bounds__(NSEG * 64) void k_prolong_tile(Geo F, Geo C, const R *__restrict__ uc,
+                                                            R *__restrict__ u, const int *__restrict__ done) {
+  prolong_tile_body<R, NSEG>(F, C, uc, u, done, logical_block());
+}
+
 template <typename R, bool RED_ONLY, int MODE, int NSEG = kSeg>
 __global__ __launch_bounds__(NSEG * 64) void k_prolong(Geo F, Geo C, const R *__restrict__ uc,
                                                        R *__restrict__ u,

@@ -214,6 +214,27 @@ def test_prolongation_matches_oracle(ell, orc, shape, mode):
                                atol=8 * EPS * (np.abs(u).max() + np.abs(uc).max()))
 
 
+@pytest.mark.parametrize("shape", [(68, 12, 100), (4, 4, 70), (2, 2, 6), (132, 36, 7), (64, 64, 100)])
+def test_tiled_prolongation_equals_column_kernel(ell, orc, shape):
+    """The LDS-staged colour-0 bilinear prolongation combines the same four
+    coarse values with the same weights in the same order: bitwise equal."""
+    g = grid_for(orc, shape, n_levels=2)
+    rng = np.random.default_rng(12)
+    uc = rng.standard_normal((g.nz, g.ny // 2, g.nx // 2))
+    u = rng.standard_normal(g.shape)
+    out = []
+    for tile in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_SMOOTH_TILE, tile)
+        try:
+            G = gpu_grid(ell, g)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_SMOOTH_TILE, 1)
+        us = G.to_split(0, dev(u))
+        G.level_prolong_add(0, G.to_split(1, dev(uc)), us, red_only=True)
+        out.append(host(us))
+    np.testing.assert_array_equal(out[0], out[1])
+
+
 def test_coarse_level_apply(ell, orc):
     g = grid_for(orc, (32, 16, 9), n_levels=3)
     G = gpu_grid(ell, g)
