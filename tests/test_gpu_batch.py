@@ -173,3 +173,30 @@ def test_graph_replays_equal_direct_launches(E):
         assert i0 == i1
         for a, b in zip(u0, u1):
             np.testing.assert_array_equal(a, b)
+
+
+def test_failures_stay_with_their_request(E):
+    """A request whose right-hand side holds a NaN ends with a numeric error,
+    a request that hits its iteration limit ends not converged, and the other
+    requests of the same grouped launches finish exactly as they do alone."""
+    ps = problems()[:3]
+    B = E.Batch(8 << 30)
+    grids = [B.grid(p, precision="fp32") for p in ps]
+    fs = [dev(p.f) for p in ps]
+    bad = fs[1].clone()
+    bad[2, 3, 4] = float("nan")
+    us = [torch.zeros_like(f) for f in fs]
+    t_ok = B.submit([grids[0]], [fs[0]], [us[0]])
+    t_bad = B.submit([grids[1]], [bad], [us[1]])
+    t_lim = B.submit([grids[2]], [fs[2]], [us[2]], rtol=1e-14, maxiter=2)
+    st_ok = B.wait(t_ok)
+    st_bad = B.wait(t_bad, check=False)
+    st_lim = B.wait(t_lim, check=False)
+    assert st_ok[0].status == E.ELL_OK
+    assert st_bad[0].status == E.ELL_ERR_NUMERIC
+    assert st_lim[0].status == E.ELL_NOT_CONVERGED and st_lim[0].iters == 2
+    u_alone = torch.zeros_like(fs[0])
+    st_alone = B.wait(B.submit([grids[0]], [fs[0]], [u_alone]))
+    assert st_alone[0].iters == st_ok[0].iters
+    np.testing.assert_array_equal(host(u_alone), host(us[0]))
+    B.close()
