@@ -200,3 +200,30 @@ def test_failures_stay_with_their_request(E):
     assert st_alone[0].iters == st_ok[0].iters
     np.testing.assert_array_equal(host(u_alone), host(us[0]))
     B.close()
+
+
+@pytest.mark.slow
+def test_config3_batch_at_full_size(E, orc):
+    """The 64 seeded uneven instances of the batched workload, solved together
+    exactly as the benchmark does (grouped launches, FP32 preconditioner, 1e-5):
+    every solve converges within the FP64 oracle's iteration count + 2 on the
+    sampled instances, and its solution lies within 1e-4 of the oracle's."""
+    ps = I.config3_instances(64)
+    B = E.Batch(200 << 30)
+    grids = [B.grid(p, precision="fp32") for p in ps]
+    fs = [dev(p.f) for p in ps]
+    us = [torch.zeros_like(f) for f in fs]
+    st = B.wait(B.submit(grids, fs, us, rtol=1e-5, poll_every=4))
+    assert all(s.status == 0 for s in st)
+    assert all(1 <= s.iters <= 20 for s in st)
+    # sampled instances: the two largest and four by seed
+    sizes = [p.n for p in ps]
+    picks = sorted(set([int(np.argmax(sizes)), int(np.argsort(sizes)[-2])] +
+                       list(np.random.default_rng(3).choice(64, 4, replace=False))))
+    for i in picks:
+        g = orc.Grid.from_problem(ps[i])
+        u_ref, st_ref = orc.pcg(g, ps[i].f, rtol=ps[i].rtol)
+        assert st[i].iters <= st_ref["iters"] + 2, (i, st[i].iters, st_ref["iters"])
+        u = host(us[i])
+        assert np.linalg.norm(u - u_ref) <= 1e-4 * np.linalg.norm(u_ref), i
+    B.close()
