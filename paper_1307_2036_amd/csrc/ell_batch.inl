@@ -63,20 +63,6 @@ struct ReqDev {
 
 enum Role : int { ROLE_COARSE = 0, ROLE_FINE64 = 1, ROLE_PRE32 = 2 };
 
-// Pointers and sizes read from a grid descriptor are the same for the whole
-// block.  Re-deriving them through readfirstlane and the global address space
-// gives the bodies what a kernel argument gives them: values in scalar
-// registers, global (not flat) vector memory instructions, and scalar loads
-// for the per-level coefficient tables.
-template <typename T>
-__device__ __forceinline__ T *gp(T *p) {
-  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
-  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
-  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
-  auto *g = (__attribute__((address_space(1))) T *)(((unsigned long long)hi << 32) | lo);
-  return (T *)g;
-}
-
 __device__ __forceinline__ int ui(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ long long ull(long long v) {

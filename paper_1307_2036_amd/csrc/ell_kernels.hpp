@@ -101,6 +101,22 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
   return r;
 }
 
+// A pointer that is the same for the whole block, re-derived through
+// readfirstlane and the global address space: the value sits in scalar
+// registers and memory instructions through it are global (not flat) ones.
+// The batch kernels use it for pointers read from grid descriptors.  The
+// result carries no aliasing facts of the original, so the compiler keeps its
+// loads on the program-order side of a memory clobber: the tiled smoother
+// relies on that to issue a whole chunk's loads before its first level runs.
+template <typename T>
+__device__ __forceinline__ T *gp(T *p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  auto *g = (__attribute__((address_space(1))) T *)(((unsigned long long)hi << 32) | lo);
+  return (T *)g;
+}
+
 // Streaming (nontemporal) accesses for data a kernel touches exactly once:
 // finest-level vectors are far larger than the L2 and the Infinity Cache, so
 // keeping them out of the caches leaves room for the data that is reused (the
@@ -406,7 +422,7 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
 // -------------------------------------------------------------------------
 constexpr int kSTX = 32;  // m-columns per tile
 
-template <int SEG, int NSEG>
+template <int SEG, int NSEG, int CH = 8>
 __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict__ tab, int c,
                                                  const double *__restrict__ bo,
                                                  const double *__restrict__ uo,
@@ -446,40 +462,45 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   const double *__restrict__ pf = tab + TPF * L.P;
   const double *__restrict__ qb = tab + TQB * L.P;
   double(*slot)[36] = ot[sg];
+  const double *ug = gp(uo);
 
   double y[SEG];
   double prev = 0.0;
 #pragma unroll
-  for (int c0 = 0; c0 < SEG; c0 += 8) {
+  for (int c0 = 0; c0 < SEG; c0 += CH) {
     if (c0 < len) {
-      double bv[8], ev[8];
-      double2 tv[8];
+      double bv[CH], ev[CH];
+      nt_d2 tv[CH];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
+      for (int t = 0; t < CH; ++t) {
         const long long o = (long long)min(k0 + c0 + t, k1 - 1) * H;
         bv[t] = __builtin_nontemporal_load(&bo[o + mo]);
-        tv[t] = *(const double2 *)&uo[o + po];
-        ev[t] = lane < 8 ? uo[o + eo] : 0.0;
+        tv[t] = *(const nt_d2 *)&ug[o + po];
+        ev[t] = lane < 8 ? ug[o + eo] : 0.0;
       }
+      // Every level of the chunk runs without a branch (levels past the
+      // segment's end repeat its last level and are discarded), so no load is
+      // moved into a conditional block next to its first use.
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        if (c0 + t < len) {
-          const int k = k0 + c0 + t;
-          // stage level k (LDS operations of a wavefront complete in order; the
-          // empty asm keeps the compiler from moving them across each other)
-          if (pv) *(double2 *)&slot[rr][2 + 2 * pp] = tv[t];
-          __asm__ volatile("" ::: "memory");
-          if (lane < 8) slot[er][ei] = ev[t];
-          __asm__ volatile("" ::: "memory");
-          const double w = slot[r + 1][x + 1 + par], e = slot[r + 1][x + 2 + par];
-          const double so = slot[r][x + 2], no = slot[r + 2][x + 2];
-          __asm__ volatile("" ::: "memory");
-          double g = bv[t];
-          g = g + txv[k] * (w + e);
-          g = g + tyv[k] * (so + no);
-          prev = (g + tz[k] * prev) * ip[k];
-          y[c0 + t] = prev;
-        }
+      for (int t = 0; t < CH; ++t) {
+        const int k = min(k0 + c0 + t, k1 - 1);
+        // stage level k (LDS operations of a wavefront complete in order; the
+        // empty asm keeps the compiler from moving them across each other).
+        // Lanes past the tile's last pair write pads or the right end's place,
+        // which the end values written next overwrite.
+        *(nt_d2 *)&slot[rr][2 + 2 * pp] = tv[t];
+        __asm__ volatile("" ::: "memory");
+        if (lane < 8) slot[er][ei] = ev[t];
+        __asm__ volatile("" ::: "memory");
+        const double w = slot[r + 1][x + 1 + par], e = slot[r + 1][x + 2 + par];
+        const double so = slot[r][x + 2], no = slot[r + 2][x + 2];
+        __asm__ volatile("" ::: "memory");
+        double g = bv[t];
+        g = g + txv[k] * (w + e);
+        g = g + tyv[k] * (so + no);
+        const double nv = (g + tz[k] * prev) * ip[k];
+        prev = c0 + t < len ? nv : prev;
+        y[c0 + t] = prev;
       }
     }
   }
