@@ -74,16 +74,16 @@ def counter_traffic(precision: str):
     return rec["smooth0_traffic_bytes_per_launch"]
 
 
-def cpu_baseline(p, gpu_iters: int, min_seconds: float = 10.0):
+def cpu_baseline(p, gpu_iters: int, min_seconds: float = 10.0, flexible: bool = True):
     """The FP64 oracle, as it stands, on the host cores: whole solves of the
-    same problem (1e-5 reduction from u0 = 0), repeated until at least
-    min_seconds of CPU work have been timed."""
+    same problem (1e-5 reduction from u0 = 0, the same beta as the GPU solve),
+    repeated until at least min_seconds of CPU work have been timed."""
     from oracle import oracle as O
     g = O.Grid.from_problem(p)
     reps, dt, iters = 0, 0.0, 0
     while dt < min_seconds and reps < 20:
         t0 = time.perf_counter()
-        u, st = O.pcg(g, p.f, rtol=p.rtol)
+        u, st = O.pcg(g, p.f, rtol=p.rtol, flexible=flexible)
         dt += time.perf_counter() - t0
         reps += 1
         iters = st["iters"]
@@ -120,10 +120,14 @@ def main():
     u = torch.zeros_like(f)
     n = p.n
     e = 8 if a.precision == "fp64" else 4
+    # the plain FP64 solve uses the classic beta of Appendix B's PCG (the
+    # V-cycle is symmetric); the mixed-precision preconditioner needs the
+    # flexible one
+    flexible = a.precision != "fp64"
 
     def step():
         u.zero_()
-        return G.pcg_solve(f, u, rtol=p.rtol, maxiter=500, poll_every=8)
+        return G.pcg_solve(f, u, rtol=p.rtol, maxiter=500, poll_every=8, flexible=flexible)
 
     if a.probe_copy:
         # a plain copy of known size: 2^25 doubles read and written once
@@ -169,7 +173,7 @@ def main():
     cnt = int(t_s.size)
 
     solves = a.steps / elapsed
-    it_bytes = perfmodel.pcg_iteration_bytes(n, G.levels, e, nu_coarse=p.nu_coarse)
+    it_bytes = perfmodel.pcg_iteration_bytes(n, G.levels, e, nu_coarse=p.nu_coarse, flexible=flexible)
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC,
@@ -186,7 +190,8 @@ def main():
         "data": "synthetic (seeded N(0,1) f, graded dz, log-normal lambda^2 profile)",
         "config": {"workload": f"gmg-pcg {p.nx}x{p.ny}x{p.nz} graded, omega2=1e-2, "
                                f"{G.levels} levels, nu_coarse={p.nu_coarse}, rtol 1e-5, u0=0",
-                   "unknowns": n, "precision": a.precision, "parallelism": "single GPU"},
+                   "unknowns": n, "precision": a.precision, "parallelism": "single GPU",
+                   "beta": "flexible" if flexible else "classic"},
         "iters": iters,
         "unknowns_iter_per_s": n * iters * solves,
         "hbm_gbs_algorithmic": it_bytes * iters * solves / 1e9,
@@ -205,7 +210,7 @@ def main():
         "schedule": dict(schedule, autotuned=bool(a.autotune)),
     }
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, iters, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(p, iters, a.cpu_seconds, flexible)
     print(json.dumps(out), flush=True)
 
 
@@ -217,13 +222,13 @@ def _seq_fp64(problems, fs):
     us = [torch.zeros_like(f) for f in fs]
     for g, f, u in zip(grids, fs, us):  # warm-up pass
         u.zero_()
-        g.pcg_solve(f, u, rtol=1e-5)
+        g.pcg_solve(f, u, rtol=1e-5, flexible=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     iters = []
     for g, f, u in zip(grids, fs, us):
         u.zero_()
-        _, st = g.pcg_solve(f, u, rtol=1e-5)
+        _, st = g.pcg_solve(f, u, rtol=1e-5, flexible=False)
         iters.append(st.iters)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -308,13 +313,13 @@ def bench_c2(a):
         per = {}
         for name, pr in ((prec, prec), ("fp64", "fp64")):
             G = ell.Grid.from_problem(p, precision=pr)
-            G.pcg_solve(f, u, rtol=p.rtol)  # warm-up
+            G.pcg_solve(f, u, rtol=p.rtol, flexible=pr != "fp64")  # warm-up
             times = []
             for _ in range(max(a.steps // 4, 2)):
                 u.zero_()
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                _, st = G.pcg_solve(f, u, rtol=p.rtol, poll_every=8)
+                _, st = G.pcg_solve(f, u, rtol=p.rtol, poll_every=8, flexible=pr != "fp64")
                 times.append(time.perf_counter() - t0)
             assert st.status == 0, st
             ut = torch.zeros_like(f)
@@ -502,14 +507,14 @@ def bench_serve(a):
         G = ell.Grid.from_problem(s0["p"])
         u = torch.zeros_like(s0["u"])
         new_rhs(s0)
-        G.pcg_solve(s0["f"], u, rtol=1e-5, rel_to_rhs=True)
+        G.pcg_solve(s0["f"], u, rtol=1e-5, rel_to_rhs=True, flexible=False)
         torch.cuda.synchronize()
         reps, tt = 3, 0.0
         for _ in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             new_rhs(s0)
-            G.pcg_solve(s0["f"], u, rtol=1e-5, rel_to_rhs=True)
+            G.pcg_solve(s0["f"], u, rtol=1e-5, rel_to_rhs=True, flexible=False)
             tt += time.perf_counter() - t0
         t_class[nx] = tt / reps
         G.close()

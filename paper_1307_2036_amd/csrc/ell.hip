@@ -476,18 +476,32 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
   const bool hxy = G.has_x && G.has_y;
   ProfScope ps(g, ELL_K_SMOOTH0, s, l == 0);
   if constexpr (std::is_same<R, double>::value && std::is_same<TB, double>::value) {
-    // finest level, after the first sweep, rho = 1: the LDS-tiled half-sweep
+    // after the first sweep, rho = 1: the LDS-tiled half-sweep (streaming
+    // accesses on the finest level)
     const int Ls = seg_len(G.nz, G.nseg);
-    if (l == 0 && !zero && rho1 && hxy && g->smooth_tile && G.hx2 % 2 == 0 && G.ny % 2 == 0 &&
-        ((G.nseg == 8 && Ls <= 16) || (G.nseg == 4 && Ls <= 32))) {
+    if (!zero && rho1 && hxy && g->smooth_tile && G.hx2 % 2 == 0 && G.ny % 2 == 0 &&
+        ((G.nseg == 16 && Ls <= 8) || (G.nseg == 8 && Ls <= 16) || (G.nseg == 4 && Ls <= 32))) {
       const int tiles = ((G.hx2 + kSTX - 1) / kSTX) * (G.ny / 2);
       const int nbt = blocks8((long long)tiles * kBlock);
-      if (G.nseg == 8)
-        k_smooth_tile<16, 8><<<nbt, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
-      else if (Ls <= 16)
-        k_smooth_tile<16, 4><<<nbt, 4 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
-      else
-        k_smooth_tile<32, 4><<<nbt, 4 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+      if (l == 0) {
+        if (G.nseg == 16)
+          k_smooth_tile<8, 16, true><<<nbt, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+        else if (G.nseg == 8)
+          k_smooth_tile<16, 8, true><<<nbt, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+        else if (Ls <= 16)
+          k_smooth_tile<16, 4, true><<<nbt, 4 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+        else
+          k_smooth_tile<32, 4, true><<<nbt, 4 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+      } else {
+        if (G.nseg == 16)
+          k_smooth_tile<8, 16, false><<<nbt, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+        else if (G.nseg == 8)
+          k_smooth_tile<16, 8, false><<<nbt, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+        else if (Ls <= 16)
+          k_smooth_tile<16, 4, false><<<nbt, 4 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+        else
+          k_smooth_tile<32, 4, false><<<nbt, 4 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+      }
       return check_launch("k_smooth_tile");
     }
   }

@@ -130,12 +130,12 @@ __device__ __forceinline__ void st_nt(double2 *p, double2 v) {
   const nt_d2 w = {v.x, v.y};
   __builtin_nontemporal_store(w, (nt_d2 *)p);
 }
-template <typename T>
-__device__ __forceinline__ T ld_s(const T *p, bool nt) { return nt ? __builtin_nontemporal_load(p) : *p; }
-template <typename T>
-__device__ __forceinline__ void st_s(T *p, T v, bool nt) {
-  if (nt) __builtin_nontemporal_store(v, p);
-  else *p = v;
+// NT is a template argument: with a run-time flag the compiler merges the two
+// loads into one and drops the streaming hint.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_s(const T *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
 }
 
 // Neighbour columns (colour 1 - c) of column (i, j) in the split layout.
@@ -334,7 +334,9 @@ __device__ __forceinline__ void seg_join_store(R (&y)[SEG], R prev, R (*xch)[kSe
             const int k = k0 + c0 + t;
             const R w = y[c0 + t] + qb[k] * win;
             const R o = (RHO1 || ZERO) ? R(0) : old[t];
-            st_s(&ow[(long long)k * H], RHO1 ? w : (R(1) - rho) * o + rho * w, FINE);
+            // plain stores also on the finest level: streaming stores measured
+            // slower here
+            ow[(long long)k * H] = RHO1 ? w : (R(1) - rho) * o + rho * w;
           }
         }
       }
@@ -386,7 +388,7 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
       for (int t = 0; t < 8; ++t) {
         const int k = min(k0 + c0 + t, k1 - 1);
         const long long o = (long long)k * H;
-        R v = (R)ld_s(&bb[o], FINE);
+        R v = (R)ld_s<FINE>(&bb[o]);
         if (!ZERO) {
           v = v + tx[k] * (uw[o] + ue[o]);
           v = v + ty[k] * (us[o] + un[o]);
@@ -408,21 +410,22 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
 }
 
 // -------------------------------------------------------------------------
-// The same half-sweep for the finest FP64 level with rho = 1 after the first
-// sweep, with the other colour staged in LDS.  Five 64-lane loads per level
-// (b and four neighbours) keep the texture units near saturation although the
-// neighbours hit in cache; here a block owns 64 columns of colour c arranged
-// as 32 m-columns by 2 rows, one k-segment per wavefront, and per level a
-// wavefront loads its b (8 bytes per lane), the other colour's 4 x 32
-// interior values of rows j0-1 .. j0+2 (16 bytes per lane) and the 8 wrapped
-// end values (8 lanes), stages them in its own LDS slot and reads the four
-// neighbours there.  Needs nx/2 even (16-byte aligned pairs) and ny even.
-// LDS slot layout per row: [1] left end, [2 + x] interior x, [2 + nxm] right
-// end (interior pairs start at even indices, so pair writes are aligned).
+// The same FP64 half-sweep with rho = 1 after the first sweep, with the other
+// colour staged in LDS (FINE: the finest level, streaming accesses).  Five
+// 64-lane loads per level (b and four neighbours) keep the texture units near
+// saturation although the neighbours hit in cache; here a block owns 64
+// columns of colour c arranged as 32 m-columns by 2 rows, one k-segment per
+// wavefront, and per level a wavefront loads its b (8 bytes per lane), the
+// other colour's 4 x 32 interior values of rows j0-1 .. j0+2 (16 bytes per
+// lane) and the 8 wrapped end values (8 lanes), stages them in its own LDS
+// slot and reads the four neighbours there.  Needs nx/2 even (16-byte aligned
+// pairs) and ny even.  LDS slot layout per row: [1] left end, [2 + x]
+// interior x, [2 + nxm] right end (interior pairs start at even indices, so
+// pair writes are aligned).
 // -------------------------------------------------------------------------
 constexpr int kSTX = 32;  // m-columns per tile
 
-template <int SEG, int NSEG, int CH = 8>
+template <int SEG, int NSEG, bool FINE, int CH = 8>
 __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict__ tab, int c,
                                                  const double *__restrict__ bo,
                                                  const double *__restrict__ uo,
@@ -463,6 +466,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   const double *__restrict__ qb = tab + TQB * L.P;
   double(*slot)[36] = ot[sg];
   const double *ug = gp(uo);
+  const double *bg = gp(bo);
 
   double y[SEG];
   double prev = 0.0;
@@ -474,7 +478,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
         const long long o = (long long)min(k0 + c0 + t, k1 - 1) * H;
-        bv[t] = __builtin_nontemporal_load(&bo[o + mo]);
+        bv[t] = ld_s<FINE>(&bg[o + mo]);
         tv[t] = *(const nt_d2 *)&ug[o + po];
         ev[t] = lane < 8 ? ug[o + eo] : 0.0;
       }
@@ -504,17 +508,17 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
       }
     }
   }
-  seg_join_store<double, false, true, true, SEG, NSEG>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf, qb,
+  seg_join_store<double, false, true, FINE, SEG, NSEG>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf, qb,
                                                        valid, own + mo, H, 1.0);
 }
 
-template <int SEG, int NSEG>
+template <int SEG, int NSEG, bool FINE>
 __global__ __launch_bounds__(NSEG * 64) void k_smooth_tile(Geo L, const double *__restrict__ tab, int c,
                                                            const double *__restrict__ bo,
                                                            const double *__restrict__ uo,
                                                            double *__restrict__ own,
                                                            const int *__restrict__ done) {
-  smooth_tile_body<SEG, NSEG>(L, tab, c, bo, uo, own, done, logical_block());
+  smooth_tile_body<SEG, NSEG, FINE>(L, tab, c, bo, uo, own, done, logical_block());
 }
 
 template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG, typename TB = R>
@@ -853,7 +857,7 @@ __device__ __forceinline__ void prolong_tile_body(Geo F, Geo C, const R *__restr
         e = e + R(3.0 / 16.0) * b2;
         e = e + R(3.0 / 16.0) * c2;
         e = e + R(1.0 / 16.0) * d;
-        if (valid) __builtin_nontemporal_store(o[t] + e, &own[(long long)(k + t) * HF]);
+        if (valid) own[(long long)(k + t) * HF] = o[t] + e;
       }
     }
   }
@@ -1628,12 +1632,20 @@ __device__ __forceinline__ void dots_body(const double2 *__restrict__ r,
   const long long t = (long long)lb * kBlock + threadIdx.x;
   const long long stride = (long long)nblocks * kBlock;
   double rz = 0.0, zq = 0.0;
-  for (long long e = t; e < n2; e += stride) {
-    const double2 rv = ld_nt(&r[e]), qv = ld_nt(&q[e]);
-    const auto zv = z[e];
-    const double zx = (double)zv.x, zy = (double)zv.y;
-    rz += rv.x * zx + rv.y * zy;
-    zq += zx * qv.x + zy * qv.y;
+  if (st->flexible) {
+    for (long long e = t; e < n2; e += stride) {
+      const double2 rv = ld_nt(&r[e]), qv = ld_nt(&q[e]);
+      const auto zv = z[e];
+      const double zx = (double)zv.x, zy = (double)zv.y;
+      rz += rv.x * zx + rv.y * zy;
+      zq += zx * qv.x + zy * qv.y;
+    }
+  } else {  // the classic beta needs <r, z> only
+    for (long long e = t; e < n2; e += stride) {
+      const double2 rv = ld_nt(&r[e]);
+      const auto zv = z[e];
+      rz += rv.x * (double)zv.x + rv.y * (double)zv.y;
+    }
   }
   const double s0 = block_sum(rz, sh);
   const double s1 = block_sum(zq, sh);

@@ -11,7 +11,8 @@ Per-unknown figures for one level with n unknowns, element size e bytes
   prolongation + add (colour-0 columns only)   : u red r/w, coarse read      = 1.25 e
   CG operator + <p,q>                          : p read, q write              = 16 B
   CG update u, r                               : u, p, r, q read; u, r write  = 48 B
-  CG dots <r,z>, <z,q>                         : r, z, q read                 = 16 B + z size
+  CG dots <r,z>, <z,q> (flexible beta)         : r, z, q read                 = 16 B + z size
+  CG dot <r,z> (classic beta)                  : r, z read                    = 8 B + z size
   CG direction p = z + beta p                  : z, p read; p write           = 16 B + z size
 """
 from __future__ import annotations
@@ -46,11 +47,12 @@ def vcycle_bytes(n0: int, levels: int, e: int, nu_pre=1, nu_post=1, nu_coarse=1)
     return total
 
 
-def cg_bytes(n0: int) -> float:
+def cg_bytes(n0: int, flexible: bool = True) -> float:
     """CG vector work per iteration (FP64): fused direction + operator + deferred
     solution update (z, p_old, u read; p_new, q, u written: 48 B), residual update
-    (r, q read; r written: 24 B), dots <r,z>, <z,q> (24 B)."""
-    return (48 + 24 + 24) * n0
+    (r, q read; r written: 24 B), dots <r,z>, <z,q> (24 B; <r,z> alone, 16 B, with
+    the classic beta)."""
+    return (48 + 24 + (24 if flexible else 16)) * n0
 
 
 def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1) -> float:
@@ -64,10 +66,10 @@ def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1) -> float:
     return fine + vcycle_bytes(n0 // 4, levels - 1, 4, nu_coarse=nu_coarse)
 
 
-def pcg_iteration_bytes(n0: int, levels: int, e: int, nu_coarse=1, **mg) -> float:
+def pcg_iteration_bytes(n0: int, levels: int, e: int, nu_coarse=1, flexible=True, **mg) -> float:
     if e == 8:
-        return cg_bytes(n0) + vcycle_bytes(n0, levels, 8, nu_coarse=nu_coarse, **mg)
-    return cg_bytes(n0) + hybrid_vcycle_bytes(n0, levels, nu_coarse)
+        return cg_bytes(n0, flexible) + vcycle_bytes(n0, levels, 8, nu_coarse=nu_coarse, **mg)
+    return cg_bytes(n0, flexible) + hybrid_vcycle_bytes(n0, levels, nu_coarse)
 
 
 def smooth0_launch_bytes_hybrid(n0: int) -> float:

@@ -151,6 +151,35 @@ def test_tiled_half_sweep_equals_column_kernel(ell, orc, shape):
     np.testing.assert_array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("shape,levels", [((128, 64, 100), 4), ((136, 24, 37), 3), ((64, 64, 128), 4),
+                                          ((256, 32, 64), 3)])
+def test_tiled_half_sweep_on_coarse_levels_equals_column_kernel(ell, orc, shape, levels):
+    """Coarser levels use the tiled half-sweep too (plain accesses, 4, 8 or 16
+    k-segments by level size; a level with nx/2 odd falls back to the column
+    kernel): bitwise equal to the column kernel on every level."""
+    g = grid_for(orc, shape, n_levels=levels)
+    gl = level_grids(g, levels)
+    out = []
+    for tile in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_SMOOTH_TILE, tile)
+        try:
+            G = gpu_grid(ell, g)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_SMOOTH_TILE, 1)
+        res = []
+        for l in range(1, levels):
+            b = np.random.default_rng(9 + l).standard_normal(gl[l].shape)
+            bs = G.to_split(l, dev(b))
+            us = G.level_empty(l)
+            G.level_smooth(l, 0, bs, us, zero_init=True)
+            for colour in (1, 0, 1, 0):
+                G.level_smooth(l, colour, bs, us)
+            res.append(host(us))
+        out.append(res)
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_array_equal(a, b)
+
+
 @pytest.mark.parametrize("shape", [(32, 32, 16), (64, 48, 37), (4, 2, 3), (2, 2, 6), (256, 12, 9)])
 def test_residual_restriction_matches_oracle(ell, orc, shape):
     g = grid_for(orc, shape, n_levels=2)
