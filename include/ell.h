@@ -213,17 +213,23 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * tiles, 0 on the column-walking kernel; BATCH_GRAPH 1 (default) makes batch
  * engines created afterwards replay each grouped step from a captured HIP
  * graph, 0 launches the kernels directly (same results, bitwise); SMOOTH_TILE
- * 1 (default) stages neighbour values in LDS tiles for the finest level's
- * FP64 half-sweeps after the first (rho = 1, nx/2 and ny even) and for the
+ * 1 (default) stages neighbour values in LDS tiles for the FP64 half-sweeps
+ * after the first on every level (rho = 1, nx/2 and ny even) and for the
  * bilinear colour-0 prolongation (ny even), 0 uses the column kernels (same
- * values, bitwise). */
+ * values, bitwise); FUSED_DOT 1 (default) lets the finest level's last two
+ * post-smoothing half-sweeps of a CG preconditioner application (tiled, with
+ * at least two levels) also form the partial sums of <r, z> (and <z, q> for
+ * the flexible beta) that the next CG scalar needs, in place of a separate
+ * pass over r, z (and q); 0 always uses the separate pass (the same values up
+ * to the order of the summation). */
 enum {
   ELL_TUNE_PLANE_PAD = 0,
   ELL_TUNE_COLOUR_PAD = 1,
   ELL_TUNE_STENCIL_SEG = 2,
   ELL_TUNE_APPLY_TILE = 3,
   ELL_TUNE_BATCH_GRAPH = 4,
-  ELL_TUNE_SMOOTH_TILE = 5
+  ELL_TUNE_SMOOTH_TILE = 5,
+  ELL_TUNE_FUSED_DOT = 6
 };
 int ell_set_tuning(int key, int value);
 

@@ -99,6 +99,7 @@ inline long long tile_blocks(const Geo &G, int nseg) {
 inline long long partial_blocks(const Geo &G0, long long n0) {
   long long b = std::max<long long>(seg_blocks(2LL * G0.H), flat_blocks(n0 / 2));
   b = std::max<long long>(b, batch_flat_blocks(n0 / 2));
+  b = std::max<long long>(b, 2LL * ((G0.hx2 + kSTX - 1) / kSTX) * (G0.ny / 2));  // fused dots
   return std::max<long long>(b, blocks8(tile_blocks(G0, 4) * kBlock));
 }
 
@@ -160,7 +161,8 @@ struct ell_grid {
   int stencil_seg = 1;                  // k-segments of the CG operator kernels
   int apply_tile = 0;                   // the CG operator step uses the LDS-tiled kernel
   int apply_nseg = 1;                   // its k-segments
-  int smooth_tile = 0;                  // finest-level FP64 half-sweeps use the LDS-tiled kernel
+  int smooth_tile = 0;                  // FP64 half-sweeps use the LDS-tiled kernel
+  int fused_dot = 0;                    // the last post-smoothing half-sweeps form the CG dots
   double *partial = nullptr;
   long long partial_cap = 0;
   PcgState *st = nullptr;
@@ -196,7 +198,8 @@ int g_colour_pad = 256;
 int g_stencil_seg = 1;  // k-segments of the CG operator kernels (1, 2 or 4)
 int g_apply_tile = 1;   // 1: LDS-tiled CG operator step where both horizontal directions exist
 int g_batch_graph = 1;  // 1: batch engines replay each grouped step from a captured graph
-int g_smooth_tile = 1;  // 1: finest-level FP64 half-sweeps stage the other colour in LDS tiles
+int g_smooth_tile = 1;  // 1: FP64 half-sweeps stage the other colour in LDS tiles
+int g_fused_dot = 1;    // 1: the last post-smoothing half-sweeps form the CG dots
 
 // Smoother segments per column: enough lanes to occupy the chip on small
 // levels, four (the register-resident optimum) on large ones; the finest
@@ -455,6 +458,17 @@ bool seg_dispatch(bool fine, int nb, hipStream_t s, const Geo &G, const R *tab, 
   }
 }
 
+// The LDS-tiled half-sweep applies to level l (after a first sweep).
+bool tile_ok(const ell_grid *g, int l) {
+  const Geo &G = g->lev[l].geo;
+  const int Ls = seg_len(G.nz, G.nseg);
+  return g->d.rho == 1.0 && G.has_x && G.has_y && g->smooth_tile && G.hx2 % 2 == 0 && G.ny % 2 == 0 &&
+         ((G.nseg == 16 && Ls <= 8) || (G.nseg == 8 && Ls <= 16) || (G.nseg == 4 && Ls <= 32));
+}
+
+// Blocks (tiles of 32 x 2 columns of one colour) of a tiled half-sweep.
+inline int smooth_tiles(const Geo &G) { return ((G.hx2 + kSTX - 1) / kSTX) * (G.ny / 2); }
+
 // One colour of line relaxation on level l.  tab: coefficient table in the
 // arithmetic type R (nullptr: the level's own table).  TB != R is supported
 // on the finest level only.
@@ -479,10 +493,8 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
     // after the first sweep, rho = 1: the LDS-tiled half-sweep (streaming
     // accesses on the finest level)
     const int Ls = seg_len(G.nz, G.nseg);
-    if (!zero && rho1 && hxy && g->smooth_tile && G.hx2 % 2 == 0 && G.ny % 2 == 0 &&
-        ((G.nseg == 16 && Ls <= 8) || (G.nseg == 8 && Ls <= 16) || (G.nseg == 4 && Ls <= 32))) {
-      const int tiles = ((G.hx2 + kSTX - 1) / kSTX) * (G.ny / 2);
-      const int nbt = blocks8((long long)tiles * kBlock);
+    if (!zero && tile_ok(g, l)) {
+      const int nbt = blocks8((long long)smooth_tiles(G) * kBlock);
       if (l == 0) {
         if (G.nseg == 16)
           k_smooth_tile<8, 16, true><<<nbt, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
@@ -522,6 +534,36 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
     }
     return check_launch("k_smooth");
   }
+}
+
+template <int SEG, int NSEG>
+void tile_dot(int dot, int nbt, hipStream_t s, const Geo &G, const double *tab, int c, const double *bo,
+              const double *uo, double *own, const int *done, double *partial, int pbase, const double *qc) {
+  if (dot == 1)
+    k_smooth_tile_dot<SEG, NSEG, 1><<<nbt, NSEG * 64, 0, s>>>(G, tab, c, bo, uo, own, done, partial, pbase, qc);
+  else
+    k_smooth_tile_dot<SEG, NSEG, 2><<<nbt, NSEG * 64, 0, s>>>(G, tab, c, bo, uo, own, done, partial, pbase, qc);
+}
+
+// One of the finest level's last two post-smoothing half-sweeps of a CG
+// preconditioner application, with the fused partial sums (dot = 1: <r, z>;
+// 2: <r, z> and <z, q>) of its colour's columns into partial[pbase + tile].
+// The caller has checked tile_ok(g, 0).
+int launch_smooth_dot(ell_grid *g, int c, const double *b, double *u, const double *tab, int dot, int pbase,
+                      const int *done, hipStream_t s) {
+  const Geo &G = g->lev[0].geo;
+  const int Ls = seg_len(G.nz, G.nseg);
+  const double *bo = b + (long long)c * G.cs;
+  const double *uo = u + (long long)(1 - c) * G.cs;
+  double *own = u + (long long)c * G.cs;
+  const double *qc = g->q + (long long)c * G.cs;
+  const int nbt = blocks8((long long)smooth_tiles(G) * kBlock);
+  ProfScope ps(g, ELL_K_SMOOTH0, s);
+  if (G.nseg == 16) tile_dot<8, 16>(dot, nbt, s, G, tab, c, bo, uo, own, done, g->partial, pbase, qc);
+  else if (G.nseg == 8) tile_dot<16, 8>(dot, nbt, s, G, tab, c, bo, uo, own, done, g->partial, pbase, qc);
+  else if (Ls <= 16) tile_dot<16, 4>(dot, nbt, s, G, tab, c, bo, uo, own, done, g->partial, pbase, qc);
+  else tile_dot<32, 4>(dot, nbt, s, G, tab, c, bo, uo, own, done, g->partial, pbase, qc);
+  return check_launch("k_smooth_tile_dot");
 }
 
 // k-segments of the restriction and prolongation kernels: four on large
@@ -598,8 +640,10 @@ int launch_fill(R *p, long long n, hipStream_t s) {
 // red.  With rho = 1 two exact shortcuts apply: after a black sweep the black
 // residual is zero (only red children are restricted) and a black sweep
 // ignores the old black values (the correction is added to red columns only).
+// dot > 0 (top = 0, FP64, the finest level tiled): the last two post-smoothing
+// half-sweeps also form the CG dots (launch_smooth_dot).
 template <typename R>
-int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, hipStream_t s) {
+int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, hipStream_t s, int dot = 0) {
   const int L = g->L;
   const bool rho1 = g->d.rho == 1.0;
   auto B = [&](int l) -> const R * { return l == top ? btop : (const R *)g->lev[l].b; };
@@ -638,6 +682,14 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
   for (int l = L - 2; l >= top; --l) {
     CHK(launch_prolong<R>(g, l, (const R *)g->lev[l + 1].u, U(l), rho1 && g->d.nu_post > 0, done, s));
     for (int it = 0; it < g->d.nu_post; ++it) {
+      if constexpr (std::is_same<R, double>::value) {
+        if (dot && l == 0 && it == g->d.nu_post - 1) {
+          const int nt = smooth_tiles(g->lev[0].geo);
+          CHK(launch_smooth_dot(g, 1, B(l), U(l), (const double *)g->lev[0].tab, dot, 0, done, s));
+          CHK(launch_smooth_dot(g, 0, B(l), U(l), (const double *)g->lev[0].tab, dot, nt, done, s));
+          continue;
+        }
+      }
       CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
       CHK(launch_smooth<R>(g, l, 0, false, B(l), U(l), done, s));
     }
@@ -651,8 +703,8 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
 // residual is zero (only red children are restricted) and a black sweep
 // ignores the old black values (the correction is added to red columns only).
 template <typename R>
-int vcycle_impl(ell_grid *g, const R *b0, R *u0, const int *done, hipStream_t s) {
-  return vcycle_from<R>(g, 0, b0, u0, done, s);
+int vcycle_impl(ell_grid *g, const R *b0, R *u0, const int *done, hipStream_t s, int dot = 0) {
+  return vcycle_from<R>(g, 0, b0, u0, done, s, dot);
 }
 
 // The mixed-precision V-cycle: FP32 everywhere except the finest level's
@@ -670,7 +722,7 @@ bool hybrid_ok(const ell_grid *g) {
          ((G.nseg == 4 && seg_len(G.nz, 4) <= 64) || (G.nseg == 8 && seg_len(G.nz, 8) <= 16));
 }
 
-int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipStream_t s) {
+int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipStream_t s, int dot = 0) {
   float *u32 = (float *)g->z32;
   for (int it = 0; it < g->d.nu_pre; ++it) {
     CHK((launch_smooth<float, double>(g, 0, 0, it == 0, r, u32, done, s)));
@@ -689,10 +741,26 @@ int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipS
     CHK(check_launch("k_prolong_out"));
   }
   for (int it = 0; it < g->d.nu_post; ++it) {
+    if (dot && it == g->d.nu_post - 1) {
+      const int nt = smooth_tiles(g->lev[0].geo);
+      CHK(launch_smooth_dot(g, 1, r, z, g->tab64_0, dot, 0, done, s));
+      CHK(launch_smooth_dot(g, 0, r, z, g->tab64_0, dot, nt, done, s));
+      continue;
+    }
     CHK(launch_smooth<double>(g, 0, 1, false, r, z, done, s, g->tab64_0));
     CHK(launch_smooth<double>(g, 0, 0, false, r, z, done, s, g->tab64_0));
   }
   return ELL_OK;
+}
+
+// The CG dots are fused into the preconditioner application of this grid:
+// the finest level's post-smoothing is FP64 and tiled (the FP64 V-cycle, or
+// the mixed-precision one with its FP64 finest post-smoothing).
+template <typename R>
+bool fused_dot_path(const ell_grid *g) {
+  const bool base = g->fused_dot && g->L >= 2 && g->d.nu_post >= 1 && tile_ok(g, 0);
+  if constexpr (std::is_same<R, double>::value) return base;
+  else return base && hybrid_ok(g);
 }
 
 int launch_apply64(ell_grid *g, const double *x, double *y, bool dot, const int *done, hipStream_t s) {
@@ -726,17 +794,18 @@ int finalize(ell_grid *g, int nblk, int nq, int mode, hipStream_t s, double rtol
   return check_launch("k_finalize");
 }
 
+// z = M r; dot > 0 needs fused_dot_path<R>(g).
 template <typename R>
-int precondition(ell_grid *g, const int *done, hipStream_t s);
+int precondition(ell_grid *g, const int *done, hipStream_t s, int dot = 0);
 
 template <>
-int precondition<double>(ell_grid *g, const int *done, hipStream_t s) {
-  return vcycle_impl<double>(g, g->r, g->z, done, s);
+int precondition<double>(ell_grid *g, const int *done, hipStream_t s, int dot) {
+  return vcycle_impl<double>(g, g->r, g->z, done, s, dot);
 }
 
 template <>
-int precondition<float>(ell_grid *g, const int *done, hipStream_t s) {
-  if (hybrid_ok(g)) return vcycle_hybrid(g, g->r, g->z, done, s);
+int precondition<float>(ell_grid *g, const int *done, hipStream_t s, int dot) {
+  if (hybrid_ok(g)) return vcycle_hybrid(g, g->r, g->z, done, s, dot);
   const long long n2 = g->n0 / 2;
   k_cast_f64_f32<<<flat_blocks(n2), kBlock, 0, s>>>((const double2 *)g->r, (float2 *)g->b32, n2, done);
   CHK(check_launch("k_cast_f64_f32"));
@@ -793,6 +862,10 @@ int pcg_begin(ell_grid *g, const double *f, const double *u, const ell_solve_opt
   CHK(check_launch("k_begin"));
   k_finalize<<<1, kBlock, 0, s>>>(g->partial, bb, 2, g->st, F_INIT, o.rtol, o.atol, o.rel_to_rhs);
   CHK(check_launch("k_finalize"));
+  if (fused_dot_path<R>(g)) {  // kappa_0 = <r0, z0> from the last half-sweeps
+    CHK(precondition<R>(g, done, s, 1));
+    return finalize(g, 2 * smooth_tiles(G), 1, F_KAPPA, s);
+  }
   CHK(precondition<R>(g, done, s));
   k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zvec<Z>(g), (const double2 *)g->q, n2, g->st,
                                   g->partial);
@@ -841,6 +914,11 @@ int pcg_step(ell_grid *g, int K, hipStream_t s) {
   }
   CHK(check_launch("k_update_r"));
   CHK(finalize(g, fb, 1, F_CONV, s));
+  if (fused_dot_path<R>(g)) {  // <r, z> (and <z, q>) from the last half-sweeps
+    const int nq = g->st_host->flexible ? 2 : 1;
+    CHK(precondition<R>(g, done, s, nq));
+    return finalize(g, 2 * smooth_tiles(g->lev[0].geo), nq, F_BETA, s);
+  }
   CHK(precondition<R>(g, done, s));
   k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zvec<Z>(g), (const double2 *)g->q, n2, g->st,
                                   g->partial);
@@ -1042,6 +1120,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->apply_nseg = g->apply_tile ? sc.apply_nseg : apply_segments(desc->nz);
   g->stencil_seg = batch_layout ? 1 : (g->apply_tile ? g_stencil_seg : sc.apply_nseg);
   g->smooth_tile = g_smooth_tile;
+  g->fused_dot = g_fused_dot;
   g->batch_layout = batch_layout;
   g->lev.resize(L);
   auto bail = [&](int rc) {
@@ -1472,6 +1551,10 @@ int ell_set_tuning(int key, int value) {
     case ELL_TUNE_SMOOTH_TILE:
       if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "smoother tiling is 0 or 1");
       g_smooth_tile = value;
+      return ELL_OK;
+    case ELL_TUNE_FUSED_DOT:
+      if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "fused dots are 0 or 1");
+      g_fused_dot = value;
       return ELL_OK;
     default: return fail(ELL_ERR_INVALID, "unknown tuning key %d", key);
   }

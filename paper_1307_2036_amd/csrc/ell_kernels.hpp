@@ -282,12 +282,17 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ 
 // values across segments, run the local backward recurrence, join it, and
 // write the column (rho = 1: the new values; else the relaxation).  xch: the
 // block's exchange array [NSEG][kSegCols]; ow: the output column at level 0.
-template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG>
+// DOT (rho = 1 only) also accumulates the CG inner products of the written
+// values w: dsum[0] += b w with b from bl[t * 64 + lane] (level k0 + t), and
+// with DOT = 2 dsum[1] += q w with q read from the column qo.
+template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG, int DOT = 0>
 __device__ __forceinline__ void seg_join_store(R (&y)[SEG], R prev, R (*xch)[kSegCols], int sg, int lane,
                                                int k0, int k1, int len, int nz, int Ls,
                                                const R *__restrict__ pf, const R *__restrict__ cf,
                                                const R *__restrict__ qb, bool valid, R *__restrict__ ow,
-                                               long long H, R rho) {
+                                               long long H, R rho, const double *bl = nullptr,
+                                               const double *__restrict__ qo = nullptr,
+                                               double *dsum = nullptr) {
   // join the forward recurrence across segments
   xch[sg][lane] = prev;
   __syncthreads();
@@ -324,9 +329,14 @@ __device__ __forceinline__ void seg_join_store(R (&y)[SEG], R prev, R (*xch)[kSe
     for (int c0 = 0; c0 < SEG; c0 += 8) {
       if (c0 < len) {
         R old[8];
+        double qv[8];
         if (!RHO1 && !ZERO) {
 #pragma unroll
           for (int t = 0; t < 8; ++t) old[t] = ow[(long long)min(k0 + c0 + t, k1 - 1) * H];
+        }
+        if constexpr (DOT == 2) {
+#pragma unroll
+          for (int t = 0; t < 8; ++t) qv[t] = __builtin_nontemporal_load(&qo[(long long)min(k0 + c0 + t, k1 - 1) * H]);
         }
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -337,6 +347,8 @@ __device__ __forceinline__ void seg_join_store(R (&y)[SEG], R prev, R (*xch)[kSe
             // plain stores also on the finest level: streaming stores measured
             // slower here
             ow[(long long)k * H] = RHO1 ? w : (R(1) - rho) * o + rho * w;
+            if constexpr (DOT >= 1) dsum[0] += bl[(c0 + t) * 64 + lane] * (double)w;
+            if constexpr (DOT == 2) dsum[1] += qv[t] * (double)w;
           }
         }
       }
@@ -425,14 +437,24 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
 // -------------------------------------------------------------------------
 constexpr int kSTX = 32;  // m-columns per tile
 
-template <int SEG, int NSEG, bool FINE, int CH = 8>
+// DOT = 1 (the last two half-sweeps of a preconditioner application): also
+// the block's partial sum of <b, w> over its written columns, into
+// partial[pbase + lb]; DOT = 2: <b, w> and <q, w> (q: the colour's part of
+// the CG vector q) into partial[2 (pbase + lb)] and [2 (pbase + lb) + 1].  The
+// wavefront keeps its b values in LDS for that; a block's sum adds its
+// wavefronts' sums in segment order.
+template <int SEG, int NSEG, bool FINE, int DOT = 0, int CH = 8>
 __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict__ tab, int c,
                                                  const double *__restrict__ bo,
                                                  const double *__restrict__ uo,
                                                  double *__restrict__ own,
-                                                 const int *__restrict__ done, int lb) {
+                                                 const int *__restrict__ done, int lb,
+                                                 double *__restrict__ partial = nullptr, int pbase = 0,
+                                                 const double *__restrict__ qc = nullptr) {
   __shared__ double xch[NSEG][kSegCols];
   __shared__ __align__(16) double ot[NSEG][4][36];
+  __shared__ double bsh[DOT ? NSEG : 1][DOT ? SEG : 1][64];
+  __shared__ double red[DOT ? NSEG : 1][2];
   const int tiles_x = (L.hx2 + kSTX - 1) / kSTX;
   if (is_done(done) || lb >= tiles_x * (L.ny / 2)) return;  // whole blocks: no barrier is skipped
   const int lane = threadIdx.x & 63;
@@ -505,11 +527,29 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
         const double nv = (g + tz[k] * prev) * ip[k];
         prev = c0 + t < len ? nv : prev;
         y[c0 + t] = prev;
+        if constexpr (DOT > 0) bsh[sg][c0 + t][lane] = bv[t];
       }
     }
   }
-  seg_join_store<double, false, true, FINE, SEG, NSEG>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf, qb,
-                                                       valid, own + mo, H, 1.0);
+  double dsum[2] = {0.0, 0.0};
+  seg_join_store<double, false, true, FINE, SEG, NSEG, DOT>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf,
+                                                            qb, valid, own + mo, H, 1.0, &bsh[DOT ? sg : 0][0][0],
+                                                            DOT == 2 ? qc + mo : nullptr, dsum);
+  if constexpr (DOT > 0) {
+#pragma unroll
+    for (int q = 0; q < DOT; ++q) {
+      double v = dsum[q];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+      if (lane == 0) red[sg][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < DOT) {
+      double v = 0.0;
+      for (int w = 0; w < NSEG; ++w) v += red[w][threadIdx.x];
+      partial[(long long)(pbase + lb) * DOT + threadIdx.x] = v;
+    }
+  }
 }
 
 template <int SEG, int NSEG, bool FINE>
@@ -519,6 +559,18 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_tile(Geo L, const double *
                                                            double *__restrict__ own,
                                                            const int *__restrict__ done) {
   smooth_tile_body<SEG, NSEG, FINE>(L, tab, c, bo, uo, own, done, logical_block());
+}
+
+// The finest level's tiled half-sweep with the fused CG inner products.
+template <int SEG, int NSEG, int DOT>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_dot(Geo L, const double *__restrict__ tab, int c,
+                                                               const double *__restrict__ bo,
+                                                               const double *__restrict__ uo,
+                                                               double *__restrict__ own,
+                                                               const int *__restrict__ done,
+                                                               double *__restrict__ partial, int pbase,
+                                                               const double *__restrict__ qc) {
+  smooth_tile_body<SEG, NSEG, true, DOT>(L, tab, c, bo, uo, own, done, logical_block(), partial, pbase, qc);
 }
 
 template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG, typename TB = R>

@@ -163,6 +163,7 @@ def make_desc(nx, ny, nz, hx, hy, omega2, dz, lambda2, n_levels=0, nu_pre=1, nu_
 ELL_TUNE_PLANE_PAD, ELL_TUNE_COLOUR_PAD, ELL_TUNE_STENCIL_SEG, ELL_TUNE_APPLY_TILE = 0, 1, 2, 3
 ELL_TUNE_BATCH_GRAPH = 4
 ELL_TUNE_SMOOTH_TILE = 5
+ELL_TUNE_FUSED_DOT = 6
 
 
 def set_tuning(key: int, value: int) -> None:

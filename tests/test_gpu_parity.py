@@ -334,6 +334,41 @@ def test_graded_solves_match_oracle(ell, orc, name, kw, opts):
     check_solve(orc, g, p.f, host(u), st, rtol, **opts)
 
 
+# (64, 16, 32): whole tiles; (68, 12, 40): a partial tile (34 = 32 + 2 m-columns) and eight
+# k-segments on the finest level; (128, 32, 64) with the mixed-precision V-cycle
+@pytest.mark.parametrize("nx,ny,nz,levels,precision,flexible", [
+    (64, 16, 32, 3, "fp64", False), (64, 16, 32, 3, "fp64", True), (68, 12, 100, 2, "fp64", True),
+    (68, 12, 100, 2, "fp64", False), (128, 32, 64, 3, "fp32", True), (128, 32, 64, 3, "fp32", False)])
+def test_fused_dots_equal_separate_pass(ell, orc, nx, ny, nz, levels, precision, flexible):
+    """<r, z> (and <z, q>) formed by the last two post-smoothing half-sweeps give
+    the iterates of the separate dot pass, up to the summation order: the same
+    iteration count, solutions within 1e-10, both matching the oracle."""
+    h = 1.0 / nx
+    dz = I.dz_quadratic(nz, 1.0 / 50.0)
+    p = I.Problem("fused", nx, ny, nz, h, h, dz, I.lambda2_perturbed(h, dz, 0.3, 22), 1e-2,
+                  I.rhs_normal(nx, ny, dz, 21), n_levels=levels)
+    res = []
+    for fused in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_FUSED_DOT, fused)
+        try:
+            G = ell.Grid.from_problem(p, precision=precision)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_FUSED_DOT, 1)
+        u, st = G.pcg_solve(dev(p.f), rtol=1e-8, flexible=flexible)
+        assert st.status == 0
+        res.append((host(u), st))
+    (u1, s1), (u0, s0) = res
+    assert s1.iters == s0.iters
+    assert rel(u1, u0) <= 1e-10
+    g = orc.Grid.from_problem(p)
+    if precision == "fp64":
+        check_solve(orc, g, p.f, u1, s1, 1e-8, flexible=flexible)
+    else:
+        u_ref, st_ref = orc.pcg(g, p.f, rtol=1e-8, flexible=flexible)
+        assert s1.iters <= st_ref["iters"] + 2
+        assert rel(u1, u_ref) <= 1e-6
+
+
 def test_solve_edge_cases(ell, orc):
     p = I.graded_problem("edge", 32, 8, 1e-2, 1, 2)
     G = ell.Grid.from_problem(p)
