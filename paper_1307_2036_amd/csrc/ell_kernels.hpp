@@ -429,11 +429,11 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
 // columns of colour c arranged as 32 m-columns by 2 rows, one k-segment per
 // wavefront, and per level a wavefront loads its b (8 bytes per lane), the
 // other colour's 4 x 32 interior values of rows j0-1 .. j0+2 (16 bytes per
-// lane) and the 8 wrapped end values (8 lanes), stages them in its own LDS
-// slot and reads the four neighbours there.  Needs nx/2 even (16-byte aligned
-// pairs) and ny even.  LDS slot layout per row: [1] left end, [2 + x]
-// interior x, [2 + nxm] right end (interior pairs start at even indices, so
-// pair writes are aligned).
+// lane) and the two wrapped end values its own rows read (2 lanes), stages
+// them in its own LDS slot and reads the four neighbours there.  Needs nx/2
+// even (16-byte aligned pairs) and ny even.  LDS slot layout per row: [1]
+// left end, [2 + x] interior x, [2 + nxm] right end (interior pairs start at
+// even indices, so pair writes are aligned).
 // -------------------------------------------------------------------------
 constexpr int kSTX = 32;  // m-columns per tile
 
@@ -472,9 +472,10 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   const int rr = lane >> 4, pp = lane & 15;
   const bool pv = 2 * pp < nxm;
   const long long po = (long long)wrapi(j0 - 1 + rr, L.ny) * L.hx2 + mx0 + (pv ? 2 * pp : 0);
-  const int er = (lane >> 1) & 3, side = lane & 1;
-  const long long eo = (long long)wrapi(j0 - 1 + er, L.ny) * L.hx2 +
-                       (side ? (mx0 + nxm) % L.hx2 : (mx0 - 1 + L.hx2) % L.hx2);
+  // end values: lane 0 for own row j0 (slot row 1), lane 1 for j0 + 1 (slot
+  // row 2), each the one side its parity reads (left end: even, right: odd)
+  const int er = 1 + (lane & 1), side = (j0 + (lane & 1) + c) & 1;
+  const long long eo = (long long)(j0 - 1 + er) * L.hx2 + (side ? (mx0 + nxm) % L.hx2 : (mx0 - 1 + L.hx2) % L.hx2);
   const int ei = side ? nxm + 2 : 1;
   const long long H = L.S;
   const int nz = L.nz, Ls = seg_len(nz, NSEG);
@@ -502,7 +503,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
         const long long o = (long long)min(k0 + c0 + t, k1 - 1) * H;
         bv[t] = ld_s<FINE>(&bg[o + mo]);
         tv[t] = *(const nt_d2 *)&ug[o + po];
-        ev[t] = lane < 8 ? ug[o + eo] : 0.0;
+        ev[t] = lane < 2 ? ug[o + eo] : 0.0;
       }
       // Every level of the chunk runs without a branch (levels past the
       // segment's end repeat its last level and are discarded), so no load is
@@ -516,7 +517,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
         // which the end values written next overwrite.
         *(nt_d2 *)&slot[rr][2 + 2 * pp] = tv[t];
         __asm__ volatile("" ::: "memory");
-        if (lane < 8) slot[er][ei] = ev[t];
+        if (lane < 2) slot[er][ei] = ev[t];
         __asm__ volatile("" ::: "memory");
         const double w = slot[r + 1][x + 1 + par], e = slot[r + 1][x + 2 + par];
         const double so = slot[r][x + 2], no = slot[r + 2][x + 2];
