@@ -169,7 +169,7 @@ struct ell_grid {
   PcgState *st_host = nullptr;          // pinned
   Prof prof[ELL_K_COUNT];
   std::vector<void *> allocs;
-  bool batch_layout = false;  // every level uses 4 k-segments (grouped launches)
+  bool batch_layout = false;  // coarse levels use 4 k-segments (grouped launches)
   void *gdev = nullptr;       // device copy of the grid descriptor (batched kernels)
   int busy = 0;               // a batch request is using the grid
 };
@@ -232,7 +232,9 @@ Geo make_geo(int nx, int ny, int nz, bool finest = false, bool uniform_seg = fal
   G.P = nz + 1;
   G.S = (int)(((long long)G.H + 63) / 64 * 64 + g_plane_pad);
   G.cs = (long long)nz * G.S + g_colour_pad;
-  G.nseg = uniform_seg ? 4 : smoother_segments(G.H, nz, finest);
+  // batch grids: the finest level as a single grid, four segments elsewhere
+  // (the grouped launches of a coarse level share one block shape)
+  G.nseg = uniform_seg && !finest ? 4 : smoother_segments(G.H, nz, finest);
   return G;
 }
 

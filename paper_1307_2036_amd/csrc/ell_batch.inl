@@ -20,7 +20,7 @@
 #include <mutex>
 #include <thread>
 
-namespace {
+namespace ellb {  // named: the kernels keep external symbols (named in profiles)
 
 constexpr int kMaxLevels = 16;
 
@@ -44,6 +44,8 @@ struct GridDev {
   int L, nb_apply, nb_flat, prolong;
   int nb_begin, nb_finish;  // blocks of the start / end kernels (partial sums each)
   int apply_tile, apply_nseg;  // CG operator step: LDS-tiled kernel and its k-segments
+  int nb_tiles;                // finest level: tiles of a tiled half-sweep (0: column kernel)
+  int nb_dot;                  // partial sums of the fused CG dots (0: separate dot pass)
 };
 
 struct StageEnt {
@@ -100,9 +102,9 @@ __device__ __forceinline__ int find_ent(const StageEnt *e, int n, int b) {
 }
 
 // R: arithmetic type; TB: type of b.  ROLE selects the arrays of the stage.
-template <typename R, bool ZERO, bool FINE, int SEG, typename TB, int ROLE>
-__global__ __launch_bounds__(kBlock) void kb_smooth(const StageEnt *__restrict__ ents, int nent, int total,
-                                                    int l, int c) {
+template <typename R, bool ZERO, bool FINE, int SEG, typename TB, int ROLE, int NSEG = 4>
+__global__ __launch_bounds__(NSEG * 64) void kb_smooth(const StageEnt *__restrict__ ents, int nent, int total,
+                                                       int l, int c) {
   const int bg = logical_block();
   if (bg >= total) return;
   const int e = find_ent(ents, nent, bg);
@@ -125,12 +127,33 @@ __global__ __launch_bounds__(kBlock) void kb_smooth(const StageEnt *__restrict__
     b = (const TB *)Lv.b;
     u = (R *)Lv.u;
   }
-  tab = gp(tab);
+  tab = cp(tab);
   b = gp(b);
   u = gp(u);
-  smooth_seg_body<R, ZERO, true, FINE, SEG, 4, TB>(G, tab, c, b + (long long)c * G.cs,
+  smooth_seg_body<R, ZERO, true, FINE, SEG, NSEG, TB>(G, tab, c, b + (long long)c * G.cs,
                                                    u + (long long)(1 - c) * G.cs, u + (long long)c * G.cs,
                                                    R(1), gp(&gd->st->done), ui(bg - ents[e].block0), 0);
+}
+
+// The finest level's FP64 half-sweep of the grids that take the LDS-tiled
+// kernel (NSEG k-segments, one block per tile); with DOT (the last two
+// post-smoothing half-sweeps) also the partial sums <r, z> and <z, q> of the
+// fused CG dots (colour 1 into the first nb_tiles pairs, colour 0 after them).
+template <int SEG, int NSEG, bool DOT>
+__global__ __launch_bounds__(NSEG * 64) void kb_smooth_tile(const StageEnt *__restrict__ ents, int nent, int total,
+                                                            int c) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = gp(ents[e].g);
+  const Geo G = ugeo(gd->lev[0].geo);
+  const double *tab = cp(gd->tab64_0);
+  const double *b = gp(gd->r);
+  double *u = gp(gd->z);
+  const long long cs = G.cs;
+  smooth_tile_body<SEG, NSEG, true, DOT ? 2 : 0>(G, tab, c, b + c * cs, u + (1 - c) * cs, u + c * cs,
+                                              gp(&gd->st->done), ui(bg - ents[e].block0), gp(gd->partial),
+                                              c == 1 ? 0 : ui(gd->nb_tiles), gp(gd->q) + c * cs);
 }
 
 template <typename R, typename TB, int ROLE>
@@ -144,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void kb_restrict(const StageEnt *__restrict
   const LevelDev &C = gd->lev[l + 1];
   const TB *b = ROLE == ROLE_COARSE ? (const TB *)F.b : (const TB *)gd->r;
   const R *u = ROLE == ROLE_COARSE ? (const R *)F.u : (ROLE == ROLE_PRE32 ? (const R *)gd->u32 : (const R *)gd->z);
-  resid_restrict_bz_body<R, TB>(ugeo(F.geo), ugeo(C.geo), gp((const R *)F.tab), gp(b), gp(u), gp((R *)C.b),
+  resid_restrict_bz_body<R, TB>(ugeo(F.geo), ugeo(C.geo), cp((const R *)F.tab), gp(b), gp(u), gp((R *)C.b),
                                 gp(&gd->st->done), ui(bg - ents[e].block0), 0);
 }
 
@@ -183,11 +206,11 @@ __global__ __launch_bounds__(kBlock) void kb_apply_dir(const StageEnt *__restric
   double *pold = gp(((K - 1) & 1) ? gd->p2 : gd->p);
   double *pnew = gp((K & 1) ? gd->p2 : gd->p);
   if (ui(gd->apply_tile))
-    apply_dir_tile_body<double>(ugeo(gd->lev[0].geo), ui(gd->apply_nseg), gp(gd->tab64_0), gp(gd->z), pold, pnew,
+    apply_dir_tile_body<double>(ugeo(gd->lev[0].geo), ui(gd->apply_nseg), cp(gd->tab64_0), gp(gd->z), pold, pnew,
                                 gp(gd->q), gp(gd->us), st, K == 1 ? 1 : 0, K > 1 ? 1 : 0, gp(gd->partial),
                                 ui(bg - ents[e].block0));
   else
-    apply_dir_body<double, 1>(ugeo(gd->lev[0].geo), gp(gd->tab64_0), gp(gd->z), pold, pnew, gp(gd->q),
+    apply_dir_body<double, 1>(ugeo(gd->lev[0].geo), cp(gd->tab64_0), gp(gd->z), pold, pnew, gp(gd->q),
                               gp(gd->us), st, K == 1 ? 1 : 0, K > 1 ? 1 : 0, gp(gd->partial),
                               ui(bg - ents[e].block0), 0);
 }
@@ -218,7 +241,7 @@ __global__ __launch_bounds__(kBlock) void kb_begin(const StageEnt *__restrict__ 
   const int e = find_ent(ents, nent, bg);
   const GridDev *gd = gp(ents[e].g);
   const ReqDev *rq = gp(reqs + ents[e].aux);
-  begin_body(ugeo(gd->lev[0].geo), gp(gd->tab64_0), gp(gd->vol0), gp(rq->f), gp((const double *)rq->u),
+  begin_body(ugeo(gd->lev[0].geo), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f), gp((const double *)rq->u),
              gp(gd->us), gp(gd->r), gp(gd->partial), ui(bg - ents[e].block0));
 }
 
@@ -249,14 +272,16 @@ __global__ __launch_bounds__(kBlock) void kb_finish(const StageEnt *__restrict__
   const int K = ui(st->iter);
   const int with_p = (K > 0 && ui(st->status) != -4) ? 1 : 0;
   const double alpha = with_p ? st->alpha : 0.0;
-  finish_body(ugeo(gd->lev[0].geo), gp(gd->tab64_0), gp(gd->vol0), gp(rq->f), gp(gd->us),
+  finish_body(ugeo(gd->lev[0].geo), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f), gp(gd->us),
               gp((K & 1) ? gd->p2 : gd->p), alpha, with_p, gp(rq->u), gp(gd->partial), ui(bg - ents[e].block0));
 }
 
 // one block per grid
 __global__ __launch_bounds__(kBlock) void kb_finalize(const StageEnt *__restrict__ ents, int mode) {
   const GridDev *gd = gp(ents[blockIdx.x].g);
-  const int nblk = ui(mode == F_ALPHA ? gd->nb_apply : (mode == F_TRUE ? gd->nb_finish : gd->nb_flat));
+  const int nblk = ui(mode == F_ALPHA ? gd->nb_apply
+                                      : (mode == F_TRUE ? gd->nb_finish
+                                                        : (mode == F_BETA && gd->nb_dot ? gd->nb_dot : gd->nb_flat)));
   const int nq = (mode == F_BETA || mode == F_TRUE) ? 2 : 1;
   finalize_body(gp(gd->partial), nblk, nq, gp(gd->st), mode, 0.0, 0.0, 0, 0, 1);
 }
@@ -282,6 +307,15 @@ int begin_blocks(const ell_grid *g) {
   return (int)(((long long)G.nx * G.ny + kSegCols - 1) / kSegCols);
 }
 int finish_blocks(const ell_grid *g) { return (int)((2LL * g->lev[0].geo.H + kSegCols - 1) / kSegCols); }
+
+// The finest level's FP64 half-sweeps after the first take the tiled kernel
+// (four or eight k-segments there); with at least two levels
+// the last two post-smoothing half-sweeps also form the CG dots.
+bool batch_tile(const ell_grid *g) {
+  const int ns = g->lev[0].geo.nseg;
+  return tile_ok(g, 0) && ((ns == 4 && seg_len(g->d.nz, 4) <= 32) || (ns == 8 && seg_len(g->d.nz, 8) <= 16));
+}
+bool batch_fused_dot(const ell_grid *g) { return batch_tile(g) && g->fused_dot && g->L >= 2 && g->d.nu_post >= 1; }
 
 int grid_dev_build(ell_grid *g) {
   if (g->L > kMaxLevels) return fail(ELL_ERR_INVALID, "too many levels for the batch engine");
@@ -313,6 +347,8 @@ int grid_dev_build(ell_grid *g) {
   h.prolong = g->d.prolong;
   h.nb_begin = begin_blocks(g);
   h.nb_finish = finish_blocks(g);
+  h.nb_tiles = batch_tile(g) ? smooth_tiles(g->lev[0].geo) : 0;
+  h.nb_dot = batch_fused_dot(g) ? 2 * h.nb_tiles : 0;
   void *d = nullptr;
   CHK(dalloc(g, &d, sizeof(GridDev)));
   HIPCHK(hipMemcpy(d, &h, sizeof(GridDev), hipMemcpyHostToDevice));
@@ -353,14 +389,16 @@ struct Ticket {
 
 // One stage of a grouped iteration.
 struct Stage {
-  enum Kind { APPLY_DIR, UPDATE_R, DOTS, FINALIZE, SMOOTH, RESTRICT, PROLONG, PROLONG_OUT } kind;
-  int level, colour, zero, role, mode;  // mode: finalize mode
+  enum Kind { APPLY_DIR, UPDATE_R, DOTS, FINALIZE, SMOOTH, SMOOTH_TILE, RESTRICT, PROLONG, PROLONG_OUT } kind;
+  int level, colour, zero, role, mode;  // mode: finalize mode; SMOOTH_TILE: 1 with the fused dots
   int seg;                              // SMOOTH: register segment length (16/32/64)
+  int nseg;                             // SMOOTH, SMOOTH_TILE: k-segments (block of nseg wavefronts)
   size_t off;                           // offset of the entry table in the device buffer
   int nent, total;
 };
 
-}  // namespace
+}  // namespace ellb
+using namespace ellb;
 
 struct ell_batch {
   size_t budget = 0;
@@ -392,6 +430,7 @@ struct ell_batch {
   hipGraphExec_t gexec = nullptr;
   bool dirty = true;
   int prec = -1;
+  int nu_pre = -1, nu_post = -1;  // shared by every grid (one V-cycle schedule per step)
   std::string last_error;
   // statistics
   long long steps = 0;
@@ -483,6 +522,37 @@ int batch_build(ell_batch *b) {
     for (ell_grid *g : gs) m = std::max(m, seg_len(g->lev[l].geo.nz, 4));
     return m <= 16 ? 16 : (m <= 32 ? 32 : 64);
   };
+  // A half-sweep stage; the finest level's FP64 half-sweeps after the first
+  // go to the tiled kernel for the grids that take it (last_post: the last
+  // post-smoothing pair, with the fused CG dots where the grid has them).
+  // One stage per k-segment count: the finest level has four or eight.
+  auto add_smooth = [&](const Stage &st, const std::vector<ell_grid *> &gs, bool last_post) {
+    const int l = st.level;
+    const bool tiled = st.role == ROLE_FINE64 && l == 0 && !st.zero;
+    for (int ns : {4, 8}) {
+      std::vector<ell_grid *> col, tile, tile_dot;
+      for (ell_grid *g : gs) {
+        if (g->lev[l].geo.nseg != ns) continue;
+        if (!tiled || !batch_tile(g)) col.push_back(g);
+        else if (last_post && batch_fused_dot(g)) tile_dot.push_back(g);
+        else tile.push_back(g);
+      }
+      Stage cst = st;
+      cst.nseg = ns;
+      cst.seg = ns == 8 ? 16 : seg_of(col, l);
+      add(cst, col, cols(l, st.colour));
+      auto tiles = [](ell_grid *g) { return smooth_tiles(g->lev[0].geo); };
+      Stage t = st;
+      t.kind = Stage::SMOOTH_TILE;
+      t.nseg = ns;
+      t.mode = 0;
+      t.seg = ns == 8 ? 16 : seg_of(tile, 0);
+      add(t, tile, tiles);
+      t.mode = 1;
+      t.seg = ns == 8 ? 16 : seg_of(tile_dot, 0);
+      add(t, tile_dot, tiles);
+    }
+  };
   // One step is iteration K of every active grid, in the order
   //   z = M r (V-cycle), <r,z> and <z,q>, beta (kappa at K = 1),
   //   p = z + beta p, q = A p and <p,q>, alpha, r -= alpha q, convergence;
@@ -517,7 +587,7 @@ int batch_build(ell_batch *b) {
         st.zero = (it == 0 && c == 0) ? 1 : 0;
         st.role = role;
         st.seg = seg_of(gs, d);
-        add(st, gs, cols(d, c));
+        add_smooth(st, gs, false);
       }
     }
     // remaining coarse sweeps of the grids whose coarsest level is d
@@ -535,7 +605,7 @@ int batch_build(ell_batch *b) {
         st.zero = 0;
         st.role = d == 0 ? (mixed ? ROLE_PRE32 : ROLE_FINE64) : ROLE_COARSE;
         st.seg = seg_of(gs, d);
-        add(st, gs, cols(d, c));
+        add_smooth(st, gs, false);
       }
     }
     if (!deep.empty()) {
@@ -572,13 +642,16 @@ int batch_build(ell_batch *b) {
         sm.zero = 0;
         sm.role = d == 0 ? ROLE_FINE64 : ROLE_COARSE;
         sm.seg = seg_of(gs, d);
-        add(sm, gs, cols(d, c));
+        add_smooth(sm, gs, it == nu_post - 1);
       }
     }
   }
+  std::vector<ell_grid *> nodot;  // grids without the fused dots
+  for (ell_grid *g : all)
+    if (!batch_fused_dot(g)) nodot.push_back(g);
   s0 = Stage{};
   s0.kind = Stage::DOTS;
-  add(s0, all, flat);
+  add(s0, nodot, flat);
   s0 = Stage{};
   s0.kind = Stage::FINALIZE;
   s0.mode = F_BETA;
@@ -612,6 +685,11 @@ int batch_build(ell_batch *b) {
 template <typename R, typename TB, bool FINE, int ROLE>
 void launch_kb_smooth(const Stage &st, const StageEnt *e, int nb, hipStream_t s) {
   const int L = st.level, C = st.colour;
+  if (st.nseg == 8) {  // the finest level with eight segments (at most 16 levels each)
+    if (st.zero) kb_smooth<R, true, FINE, 16, TB, ROLE, 8><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total, L, C);
+    else kb_smooth<R, false, FINE, 16, TB, ROLE, 8><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total, L, C);
+    return;
+  }
   if (st.zero) {
     if (st.seg == 16) kb_smooth<R, true, FINE, 16, TB, ROLE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, L, C);
     else if (st.seg == 32) kb_smooth<R, true, FINE, 32, TB, ROLE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, L, C);
@@ -634,6 +712,18 @@ int batch_step(ell_batch *b) {
       case Stage::APPLY_DIR: kb_apply_dir<<<nb, kBlock, 0, s>>>(e, st.nent, st.total); break;
       case Stage::UPDATE_R: kb_update_r<<<nb, kBlock, 0, s>>>(e, st.nent, st.total); break;
       case Stage::DOTS: kb_dots<<<nb, kBlock, 0, s>>>(e, st.nent, st.total); break;
+      case Stage::SMOOTH_TILE:
+        if (st.nseg == 8) {
+          if (st.mode) kb_smooth_tile<16, 8, true><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total, st.colour);
+          else kb_smooth_tile<16, 8, false><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total, st.colour);
+        } else if (st.seg == 16) {
+          if (st.mode) kb_smooth_tile<16, 4, true><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.colour);
+          else kb_smooth_tile<16, 4, false><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.colour);
+        } else {
+          if (st.mode) kb_smooth_tile<32, 4, true><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.colour);
+          else kb_smooth_tile<32, 4, false><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.colour);
+        }
+        break;
       case Stage::FINALIZE: kb_finalize<<<st.nent, kBlock, 0, s>>>(e, st.mode); break;
       case Stage::SMOOTH:
         if (st.role == ROLE_FINE64) launch_kb_smooth<double, double, true, ROLE_FINE64>(st, e, nb, s);
@@ -888,6 +978,8 @@ int ell_batch_grid(ell_batch *b, const ell_grid_desc *desc, ell_grid **out) {
       return fail(ELL_ERR_BUDGET, "grid needs %zu bytes, %zu of %zu in use", need, b->used, b->budget);
     if (b->prec != -1 && (b->prec == ELL_FP64) != (desc->precision == ELL_FP64))
       return fail(ELL_ERR_INVALID, "all grids of a batch use FP64 or all use the FP32 preconditioner");
+    if (b->nu_pre != -1 && (b->nu_pre != desc->nu_pre || b->nu_post != desc->nu_post))
+      return fail(ELL_ERR_INVALID, "all grids of a batch use the same pre- and post-smoothing counts");
   }
   ell_grid *g = nullptr;
   CHK(grid_create(desc, true, &g));
@@ -906,6 +998,10 @@ int ell_batch_grid(ell_batch *b, const ell_grid_desc *desc, ell_grid **out) {
     b->used += need;
     b->grids.push_back(g);
     if (b->prec == -1) b->prec = desc->precision == ELL_FP64 ? ELL_FP64 : ELL_FP32_PRECOND;
+    if (b->nu_pre == -1) {
+      b->nu_pre = desc->nu_pre;
+      b->nu_post = desc->nu_post;
+    }
   }
   *out = g;
   return ELL_OK;

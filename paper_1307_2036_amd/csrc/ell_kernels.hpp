@@ -117,6 +117,19 @@ __device__ __forceinline__ T *gp(T *p) {
   return (T *)g;
 }
 
+// The same for data that no kernel writes while it runs (the coefficient
+// tables): through the constant address space, the loads of a uniform index
+// stay scalar loads even where stores through other re-derived pointers, or a
+// memory clobber, stand between the kernel's start and the load.
+template <typename T>
+__device__ __forceinline__ const T *cp(const T *p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  auto *c = (const __attribute__((address_space(4))) T *)(((unsigned long long)hi << 32) | lo);
+  return (const T *)c;
+}
+
 // Streaming (nontemporal) accesses for data a kernel touches exactly once:
 // finest-level vectors are far larger than the L2 and the Infinity Cache, so
 // keeping them out of the caches leaves room for the data that is reused (the

@@ -124,6 +124,10 @@ def test_budget_and_validation(E):
     B2 = E.Batch(1 << 30)
     with pytest.raises(E.EllError):
         B2.grid(p, rho=0.9)
+    g3 = B2.grid(p)
+    with pytest.raises(E.EllError):
+        B2.grid(p, nu_post=2)  # one smoothing schedule per batch
+    g3.close()
     B2.close()
 
 
@@ -227,3 +231,31 @@ def test_config3_batch_at_full_size(E, orc):
         u = host(us[i])
         assert np.linalg.norm(u - u_ref) <= 1e-4 * np.linalg.norm(u_ref), i
     B.close()
+
+
+@pytest.mark.parametrize("precision,flexible", [("fp32", True), ("fp64", False), ("fp64", True)])
+def test_fused_dots_and_tiles_in_batch(E, precision, flexible):
+    """The batch's tiled finest-level half-sweeps with the fused CG dots give the
+    iterates of the batch without them (column kernels, separate dot pass) up
+    to the summation order; (96, 24) has a partial tile and (32, 40) one tile
+    per row pair."""
+    ps = problems()
+    res = []
+    for on in (1, 0):
+        E.set_tuning(E.ELL_TUNE_FUSED_DOT, on)
+        E.set_tuning(E.ELL_TUNE_SMOOTH_TILE, on)
+        try:
+            B = E.Batch(8 << 30)
+            grids = [B.grid(p, precision=precision) for p in ps]
+        finally:
+            E.set_tuning(E.ELL_TUNE_FUSED_DOT, 1)
+            E.set_tuning(E.ELL_TUNE_SMOOTH_TILE, 1)
+        fs = [dev(p.f) for p in ps]
+        us = [torch.zeros_like(f) for f in fs]
+        st = B.wait(B.submit(grids, fs, us, rtol=1e-8, flexible=flexible))
+        res.append(([host(u) for u in us], [s.iters for s in st]))
+        B.close()
+    (u1, i1), (u0, i0) = res
+    assert i1 == i0
+    for a, b in zip(u1, u0):
+        assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b)
