@@ -162,8 +162,11 @@ def main():
 
     t_s = live(G.profile_times(ell.ELL_K_SMOOTH0))
     t_a = live(G.profile_times(ell.ELL_K_APPLY))
-    launch_bytes = (perfmodel.smooth0_launch_bytes(n, 8) if a.precision == "fp64"
-                    else perfmodel.smooth0_launch_bytes_hybrid(n))
+    feat = G.features
+    dot_q = feat["fused_dots"] and flexible
+    launch_bytes = (perfmodel.smooth0_launch_bytes(n, 8, fused_update=feat["fused_update"], dot_q=dot_q)
+                    if a.precision == "fp64" else
+                    perfmodel.smooth0_launch_bytes_hybrid(n, fused_update=feat["fused_update"], dot_q=dot_q))
     avg_ms = float(t_s.mean())
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
     # the CG operator step reads z, p_old, u and writes p_new, q, u (48 B per unknown);
@@ -173,7 +176,8 @@ def main():
     cnt = int(t_s.size)
 
     solves = a.steps / elapsed
-    it_bytes = perfmodel.pcg_iteration_bytes(n, G.levels, e, nu_coarse=p.nu_coarse, flexible=flexible)
+    it_bytes = perfmodel.pcg_iteration_bytes(n, G.levels, e, nu_coarse=p.nu_coarse, flexible=flexible,
+                                             fused_update=feat["fused_update"], fused_dots=feat["fused_dots"])
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC,
@@ -198,9 +202,10 @@ def main():
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "true_rel_residual": st.true_r_norm / st.b_norm,
-        "roofline": {"bound": "hbm", "kernel": "finest-level line relaxation, " + ("k_smooth_tile (+ k_smooth_seg first sweep), FP64"
-                                                                if a.precision == "fp64" else
-                                                                "FP32 pre / FP64 post sweeps"),
+        "roofline": {"bound": "hbm", "kernel": "finest-level line relaxation, " + (
+                         "k_smooth_seg first sweep, k_smooth_tile, k_smooth_tile_dot x2, FP64"
+                         if a.precision == "fp64" else "FP32 pre / FP64 post sweeps") +
+                     (" (residual update fused into the first pair)" if feat["fused_update"] else ""),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(a.precision),
                      "avg_launch_us": avg_ms * 1e3, "launches": cnt,

@@ -122,6 +122,16 @@ size_t ell_grid_bytes(const ell_grid_desc *desc);
 /* Number of multigrid levels of the grid (>= 1), or a negative error. */
 int ell_grid_levels(const ell_grid *g);
 
+/* Which fused forms the grid's CG solves (ell_pcg_solve) take, as a bit mask
+ * in *mask: ELL_FEAT_TILED_SMOOTH (the finest level's half-sweeps after the
+ * first stage neighbours in LDS tiles), ELL_FEAT_FUSED_DOTS (the CG inner
+ * products ride on the last two post-smoothing half-sweeps),
+ * ELL_FEAT_FUSED_UPDATE (the residual update r -= alpha q rides on the first
+ * pre-smoothing pair).  They change where bytes move, not what is computed;
+ * a benchmark's byte model reads them.  Returns ELL_OK or a negative error. */
+enum { ELL_FEAT_TILED_SMOOTH = 1, ELL_FEAT_FUSED_DOTS = 2, ELL_FEAT_FUSED_UPDATE = 4 };
+int ell_grid_features(const ell_grid *g, int32_t *mask);
+
 /* y = A x: the operator of eq. ModelEquation integrated over every cell
  * (cell volume V = hx*hy*dz_k), so A is symmetric positive definite.
  * x, y: device, plane-major, nx*ny*nz doubles, must not alias. */
@@ -221,7 +231,11 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * at least two levels) also form the partial sums of <r, z> (and <z, q> for
  * the flexible beta) that the next CG scalar needs, in place of a separate
  * pass over r, z (and q); 0 always uses the separate pass (the same values up
- * to the order of the summation). */
+ * to the order of the summation); FUSED_UPDATE 1 (default) lets the finest
+ * level's first pre-smoothing pair of a CG preconditioner application also
+ * carry the residual update r -= alpha q and the partial sums of ||r||^2 (the
+ * convergence test runs between that pair and the rest of the V-cycle), in
+ * place of a separate pass over r and q; 0 always uses the separate pass. */
 enum {
   ELL_TUNE_PLANE_PAD = 0,
   ELL_TUNE_COLOUR_PAD = 1,
@@ -229,7 +243,8 @@ enum {
   ELL_TUNE_APPLY_TILE = 3,
   ELL_TUNE_BATCH_GRAPH = 4,
   ELL_TUNE_SMOOTH_TILE = 5,
-  ELL_TUNE_FUSED_DOT = 6
+  ELL_TUNE_FUSED_DOT = 6,
+  ELL_TUNE_FUSED_UPDATE = 7
 };
 int ell_set_tuning(int key, int value);
 

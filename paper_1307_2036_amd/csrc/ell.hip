@@ -163,6 +163,7 @@ struct ell_grid {
   int apply_nseg = 1;                   // its k-segments
   int smooth_tile = 0;                  // FP64 half-sweeps use the LDS-tiled kernel
   int fused_dot = 0;                    // the last post-smoothing half-sweeps form the CG dots
+  int fused_update = 0;                 // the first pre-smoothing pair updates the CG residual
   double *partial = nullptr;
   long long partial_cap = 0;
   PcgState *st = nullptr;
@@ -200,6 +201,7 @@ int g_apply_tile = 1;   // 1: LDS-tiled CG operator step where both horizontal d
 int g_batch_graph = 1;  // 1: batch engines replay each grouped step from a captured graph
 int g_smooth_tile = 1;  // 1: FP64 half-sweeps stage the other colour in LDS tiles
 int g_fused_dot = 1;    // 1: the last post-smoothing half-sweeps form the CG dots
+int g_fused_update = 1; // 1: the first pre-smoothing pair updates the CG residual
 
 // Smoother segments per column: enough lanes to occupy the chip on small
 // levels, four (the register-resident optimum) on large ones; the finest
@@ -568,6 +570,61 @@ int launch_smooth_dot(ell_grid *g, int c, const double *b, double *u, const doub
   return check_launch("k_smooth_tile_dot");
 }
 
+// One half-sweep of the finest level's first pre-smoothing pair of a CG
+// preconditioner application with the residual update r -= alpha q fused in
+// (colour 0 from zero with the column kernel; colour 1 on the tile for FP64,
+// else the column kernel).  The partial sums of ||r||^2 go to partial[pbase +
+// block]; *slots receives the number of slots written.  The caller has
+// checked fused_update_path.
+template <typename R>
+int launch_smooth_upd(ell_grid *g, int c, double *r, R *u, const R *tab, int pbase, hipStream_t s, int *slots) {
+  const Geo &G = g->lev[0].geo;
+  const int Ls = seg_len(G.nz, G.nseg);
+  double *rc = r + (long long)c * G.cs;
+  const double *qc = g->q + (long long)c * G.cs;
+  const R *uo = u + (long long)(1 - c) * G.cs;
+  R *own = u + (long long)c * G.cs;
+  ProfScope ps(g, ELL_K_SMOOTH0, s);
+  if constexpr (std::is_same<R, double>::value) {
+    if (c == 1) {
+      const int nbt = blocks8((long long)smooth_tiles(G) * kBlock);
+      if (G.nseg == 8)
+        k_smooth_tile_upd<16, 8><<<nbt, 8 * 64, 0, s>>>(G, tab, c, rc, uo, own, qc, g->st, g->partial, pbase);
+      else if (Ls <= 16)
+        k_smooth_tile_upd<16, 4><<<nbt, 4 * 64, 0, s>>>(G, tab, c, rc, uo, own, qc, g->st, g->partial, pbase);
+      else
+        k_smooth_tile_upd<32, 4><<<nbt, 4 * 64, 0, s>>>(G, tab, c, rc, uo, own, qc, g->st, g->partial, pbase);
+      *slots = smooth_tiles(G);  // blocks past the last tile return at once
+      return check_launch("k_smooth_tile_upd");
+    }
+  }
+  const int ncol = c ? G.ncol1 : G.ncol0;
+  const int nbs = blocks8(((long long)ncol + kSegCols - 1) / kSegCols * kBlock);
+  if (G.nseg == 8) {
+    if (c == 0) k_smooth_seg_upd<R, true, 16, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, rc, uo, own, qc, g->st, g->partial, pbase);
+    else k_smooth_seg_upd<R, false, 16, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, rc, uo, own, qc, g->st, g->partial, pbase);
+  } else if (Ls <= 16) {
+    if (c == 0) k_smooth_seg_upd<R, true, 16, 4><<<nbs, 4 * 64, 0, s>>>(G, tab, c, rc, uo, own, qc, g->st, g->partial, pbase);
+    else k_smooth_seg_upd<R, false, 16, 4><<<nbs, 4 * 64, 0, s>>>(G, tab, c, rc, uo, own, qc, g->st, g->partial, pbase);
+  } else {
+    if (c == 0) k_smooth_seg_upd<R, true, 32, 4><<<nbs, 4 * 64, 0, s>>>(G, tab, c, rc, uo, own, qc, g->st, g->partial, pbase);
+    else k_smooth_seg_upd<R, false, 32, 4><<<nbs, 4 * 64, 0, s>>>(G, tab, c, rc, uo, own, qc, g->st, g->partial, pbase);
+  }
+  *slots = nbs;  // every block writes its slot
+  return check_launch("k_smooth_seg_upd");
+}
+
+// The first pre-smoothing pair with the fused residual update, then the
+// convergence test (F_CONV) that the rest of the V-cycle is predicated on.
+template <typename R>
+int pre_pair_upd(ell_grid *g, double *r, R *u, const R *tab, hipStream_t s) {
+  int s0 = 0, s1 = 0;
+  CHK(launch_smooth_upd<R>(g, 0, r, u, tab, 0, s, &s0));
+  CHK(launch_smooth_upd<R>(g, 1, r, u, tab, s0, s, &s1));
+  k_finalize<<<1, kBlock, 0, s>>>(g->partial, s0 + s1, 1, g->st, F_CONV, 0.0, 0.0, 0);
+  return check_launch("k_finalize");
+}
+
 // k-segments of the restriction and prolongation kernels: four on large
 // levels, more on small coarse levels, where the sequential walk over a
 // segment is the kernel's latency; at least 8 levels per segment.
@@ -645,7 +702,8 @@ int launch_fill(R *p, long long n, hipStream_t s) {
 // dot > 0 (top = 0, FP64, the finest level tiled): the last two post-smoothing
 // half-sweeps also form the CG dots (launch_smooth_dot).
 template <typename R>
-int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, hipStream_t s, int dot = 0) {
+int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, hipStream_t s, int dot = 0,
+                bool upd = false) {
   const int L = g->L;
   const bool rho1 = g->d.rho == 1.0;
   auto B = [&](int l) -> const R * { return l == top ? btop : (const R *)g->lev[l].b; };
@@ -653,6 +711,12 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
   for (int l = top; l < L - 1; ++l) {
     if (g->d.nu_pre == 0) CHK(launch_fill<R>(U(l), 2 * g->lev[l].geo.cs, s));
     for (int it = 0; it < g->d.nu_pre; ++it) {
+      if constexpr (std::is_same<R, double>::value) {
+        if (upd && l == 0 && it == 0) {  // b is the CG residual g->r
+          CHK(pre_pair_upd<double>(g, g->r, U(l), (const double *)g->lev[0].tab, s));
+          continue;
+        }
+      }
       CHK(launch_smooth<R>(g, l, 0, it == 0, B(l), U(l), done, s));
       CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
     }
@@ -705,8 +769,8 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
 // residual is zero (only red children are restricted) and a black sweep
 // ignores the old black values (the correction is added to red columns only).
 template <typename R>
-int vcycle_impl(ell_grid *g, const R *b0, R *u0, const int *done, hipStream_t s, int dot = 0) {
-  return vcycle_from<R>(g, 0, b0, u0, done, s, dot);
+int vcycle_impl(ell_grid *g, const R *b0, R *u0, const int *done, hipStream_t s, int dot = 0, bool upd = false) {
+  return vcycle_from<R>(g, 0, b0, u0, done, s, dot, upd);
 }
 
 // The mixed-precision V-cycle: FP32 everywhere except the finest level's
@@ -724,9 +788,14 @@ bool hybrid_ok(const ell_grid *g) {
          ((G.nseg == 4 && seg_len(G.nz, 4) <= 64) || (G.nseg == 8 && seg_len(G.nz, 8) <= 16));
 }
 
-int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipStream_t s, int dot = 0) {
+int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipStream_t s, int dot = 0,
+                  bool upd = false) {
   float *u32 = (float *)g->z32;
   for (int it = 0; it < g->d.nu_pre; ++it) {
+    if (upd && it == 0) {  // r is the CG residual g->r
+      CHK(pre_pair_upd<float>(g, g->r, u32, (const float *)g->lev[0].tab, s));
+      continue;
+    }
     CHK((launch_smooth<float, double>(g, 0, 0, it == 0, r, u32, done, s)));
     CHK((launch_smooth<float, double>(g, 0, 1, false, r, u32, done, s)));
   }
@@ -753,6 +822,23 @@ int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipS
     CHK(launch_smooth<double>(g, 0, 0, false, r, z, done, s, g->tab64_0));
   }
   return ELL_OK;
+}
+
+// The CG residual update is fused into the first pre-smoothing pair of this
+// grid's preconditioner application: at least two levels, rho = 1, four
+// k-segments of at most 32 levels or eight of at most 16 on the finest level;
+// FP64 with the tiled colour-1 sweep, or the mixed-precision V-cycle.
+template <typename R>
+bool fused_update_path(const ell_grid *g) {
+  const Geo &G = g->lev[0].geo;
+  const int Ls = seg_len(G.nz, G.nseg);
+  const bool segs = (G.nseg == 8 && Ls <= 16) || (G.nseg == 4 && Ls <= 32);
+  // at least two levels: the finest level's pre-smoothing, and with it the
+  // convergence test, then runs once per step
+  const bool base =
+      g->fused_update && g->L >= 2 && g->d.rho == 1.0 && g->d.nu_pre >= 1 && G.has_x && G.has_y && segs;
+  if constexpr (std::is_same<R, double>::value) return base && tile_ok(g, 0);
+  else return base && hybrid_ok(g);
 }
 
 // The CG dots are fused into the preconditioner application of this grid:
@@ -796,18 +882,18 @@ int finalize(ell_grid *g, int nblk, int nq, int mode, hipStream_t s, double rtol
   return check_launch("k_finalize");
 }
 
-// z = M r; dot > 0 needs fused_dot_path<R>(g).
+// z = M r; dot > 0 needs fused_dot_path<R>(g), upd fused_update_path<R>(g).
 template <typename R>
-int precondition(ell_grid *g, const int *done, hipStream_t s, int dot = 0);
+int precondition(ell_grid *g, const int *done, hipStream_t s, int dot = 0, bool upd = false);
 
 template <>
-int precondition<double>(ell_grid *g, const int *done, hipStream_t s, int dot) {
-  return vcycle_impl<double>(g, g->r, g->z, done, s, dot);
+int precondition<double>(ell_grid *g, const int *done, hipStream_t s, int dot, bool upd) {
+  return vcycle_impl<double>(g, g->r, g->z, done, s, dot, upd);
 }
 
 template <>
-int precondition<float>(ell_grid *g, const int *done, hipStream_t s, int dot) {
-  if (hybrid_ok(g)) return vcycle_hybrid(g, g->r, g->z, done, s, dot);
+int precondition<float>(ell_grid *g, const int *done, hipStream_t s, int dot, bool upd) {
+  if (hybrid_ok(g)) return vcycle_hybrid(g, g->r, g->z, done, s, dot, upd);
   const long long n2 = g->n0 / 2;
   k_cast_f64_f32<<<flat_blocks(n2), kBlock, 0, s>>>((const double2 *)g->r, (float2 *)g->b32, n2, done);
   CHK(check_launch("k_cast_f64_f32"));
@@ -910,18 +996,23 @@ int pcg_step(ell_grid *g, int K, hipStream_t s) {
   CHK(launch_apply_dir<Z>(g, K, K == 1 ? 1 : 0, K > 1 ? 1 : 0, s));
 
   CHK(finalize(g, ab, 1, F_ALPHA, s));
-  {
-    ProfScope ps(g, ELL_K_UPDATE, s);
-    k_update_r<<<fb, kBlock, 0, s>>>((double2 *)g->r, (const double2 *)g->q, n2, g->st, g->partial);
+  // r -= alpha q and the convergence test: fused into the first pre-smoothing
+  // pair of the V-cycle, or a pass of their own before it
+  const bool upd = fused_update_path<R>(g);
+  if (!upd) {
+    {
+      ProfScope ps(g, ELL_K_UPDATE, s);
+      k_update_r<<<fb, kBlock, 0, s>>>((double2 *)g->r, (const double2 *)g->q, n2, g->st, g->partial);
+    }
+    CHK(check_launch("k_update_r"));
+    CHK(finalize(g, fb, 1, F_CONV, s));
   }
-  CHK(check_launch("k_update_r"));
-  CHK(finalize(g, fb, 1, F_CONV, s));
   if (fused_dot_path<R>(g)) {  // <r, z> (and <z, q>) from the last half-sweeps
     const int nq = g->st_host->flexible ? 2 : 1;
-    CHK(precondition<R>(g, done, s, nq));
+    CHK(precondition<R>(g, done, s, nq, upd));
     return finalize(g, 2 * smooth_tiles(g->lev[0].geo), nq, F_BETA, s);
   }
-  CHK(precondition<R>(g, done, s));
+  CHK(precondition<R>(g, done, s, 0, upd));
   k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zvec<Z>(g), (const double2 *)g->q, n2, g->st,
                                   g->partial);
   CHK(check_launch("k_dots"));
@@ -1123,6 +1214,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->stencil_seg = batch_layout ? 1 : (g->apply_tile ? g_stencil_seg : sc.apply_nseg);
   g->smooth_tile = g_smooth_tile;
   g->fused_dot = g_fused_dot;
+  g->fused_update = g_fused_update;
   g->batch_layout = batch_layout;
   g->lev.resize(L);
   auto bail = [&](int rc) {
@@ -1222,6 +1314,22 @@ int ell_grid_destroy(ell_grid *g) {
 int ell_grid_levels(const ell_grid *g) {
   if (!g) return fail(ELL_ERR_INVALID, "grid is NULL");
   return g->L;
+}
+
+int ell_grid_features(const ell_grid *g, int32_t *mask) {
+  if (!g || !mask) return fail(ELL_ERR_INVALID, "NULL argument");
+  int m = 0;
+  if (g->prec == ELL_FP64) {
+    if (tile_ok(g, 0)) m |= ELL_FEAT_TILED_SMOOTH;
+    if (fused_dot_path<double>(g)) m |= ELL_FEAT_FUSED_DOTS;
+    if (fused_update_path<double>(g)) m |= ELL_FEAT_FUSED_UPDATE;
+  } else if (hybrid_ok(g)) {  // the FP64 post-smoothing of the mixed-precision V-cycle
+    if (tile_ok(g, 0)) m |= ELL_FEAT_TILED_SMOOTH;
+    if (fused_dot_path<float>(g)) m |= ELL_FEAT_FUSED_DOTS;
+    if (fused_update_path<float>(g)) m |= ELL_FEAT_FUSED_UPDATE;
+  }
+  *mask = m;
+  return ELL_OK;
 }
 
 int ell_apply_A(ell_grid *g, const double *x, double *y, hipStream_t s) {
@@ -1557,6 +1665,10 @@ int ell_set_tuning(int key, int value) {
     case ELL_TUNE_FUSED_DOT:
       if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "fused dots are 0 or 1");
       g_fused_dot = value;
+      return ELL_OK;
+    case ELL_TUNE_FUSED_UPDATE:
+      if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "the fused residual update is 0 or 1");
+      g_fused_update = value;
       return ELL_OK;
     default: return fail(ELL_ERR_INVALID, "unknown tuning key %d", key);
   }

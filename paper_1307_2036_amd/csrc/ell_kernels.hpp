@@ -369,13 +369,23 @@ __device__ __forceinline__ void seg_join_store(R (&y)[SEG], R prev, R (*xch)[kSe
   }
 }
 
-template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG, typename TB = R>
+// UPD (the first pre-smoothing pair of a CG preconditioner application, b
+// being the CG residual of this colour, TB = double): b is first advanced to
+// b - alpha q (alpha: the CG step length in st; qo: this colour's part of q)
+// and written back to rw, and the block's partial sum of its squares goes to
+// partial[pbase + lb] (the residual update and its norm, fused into the sweep).
+template <typename R, bool ZERO, bool RHO1, bool FINE, int SEG, int NSEG, typename TB = R, bool UPD = false>
 __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab, int c,
                                                           const TB *__restrict__ bo,
                                                           const R *__restrict__ uo,
                                                           R *__restrict__ own, R rho,
-                                                          const int *__restrict__ done, int lb, int nblocks) {
+                                                          const int *__restrict__ done, int lb, int nblocks,
+                                                          double *__restrict__ rw = nullptr,
+                                                          const double *__restrict__ qo = nullptr,
+                                                          const PcgState *__restrict__ st = nullptr,
+                                                          double *__restrict__ partial = nullptr, int pbase = 0) {
   __shared__ R xch[NSEG][kSegCols];
+  __shared__ double red[UPD ? NSEG : 1];
   if (is_done(done)) return;
   const int lane = threadIdx.x & 63;
   const int sg = wave_id();
@@ -405,6 +415,8 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
 
   R y[SEG];
   R prev = R(0);
+  double alpha = 0.0, rr = 0.0;
+  if constexpr (UPD) alpha = st->alpha;
 #pragma unroll
   for (int c0 = 0; c0 < SEG; c0 += 8) {
     if (c0 < len) {
@@ -413,7 +425,20 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
       for (int t = 0; t < 8; ++t) {
         const int k = min(k0 + c0 + t, k1 - 1);
         const long long o = (long long)k * H;
-        R v = (R)ld_s<FINE>(&bb[o]);
+        R v;
+        if constexpr (UPD) {
+          // the residual update of the CG step; only the lane that owns the
+          // column writes it (idle lanes, also those of blocks past the last
+          // column, read it and must not see their own write)
+          const double rv = __builtin_nontemporal_load(&bb[o]) - alpha * __builtin_nontemporal_load(&qo[mm + o]);
+          if (valid && c0 + t < len) {
+            __builtin_nontemporal_store(rv, &rw[mm + o]);
+            rr += rv * rv;
+          }
+          v = (R)rv;
+        } else {
+          v = (R)ld_s<FINE>(&bb[o]);
+        }
         if (!ZERO) {
           v = v + tx[k] * (uw[o] + ue[o]);
           v = v + ty[k] * (us[o] + un[o]);
@@ -432,6 +457,17 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
   }
   seg_join_store<R, ZERO, RHO1, FINE, SEG, NSEG>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf, qb, valid, ow,
                                                  H, rho);
+  if constexpr (UPD) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) rr += __shfl_down(rr, o, 64);
+    if (lane == 0) red[sg] = rr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double v = 0.0;
+      for (int w = 0; w < NSEG; ++w) v += red[w];
+      partial[pbase + lb] = v;
+    }
+  }
 }
 
 // -------------------------------------------------------------------------
@@ -456,18 +492,24 @@ constexpr int kSTX = 32;  // m-columns per tile
 // the CG vector q) into partial[2 (pbase + lb)] and [2 (pbase + lb) + 1].  The
 // wavefront keeps its b values in LDS for that; a block's sum adds its
 // wavefronts' sums in segment order.
-template <int SEG, int NSEG, bool FINE, int DOT = 0, int CH = 8>
+// UPD (the first pre-smoothing pair, as in smooth_seg_body): b is advanced to
+// b - alpha q and written back to rwc (this colour's CG residual), and the
+// block's partial sum of its squares goes to partial[pbase + lb].
+template <int SEG, int NSEG, bool FINE, int DOT = 0, bool UPD = false, int CH = 8>
 __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict__ tab, int c,
                                                  const double *__restrict__ bo,
                                                  const double *__restrict__ uo,
                                                  double *__restrict__ own,
                                                  const int *__restrict__ done, int lb,
                                                  double *__restrict__ partial = nullptr, int pbase = 0,
-                                                 const double *__restrict__ qc = nullptr) {
+                                                 const double *__restrict__ qc = nullptr,
+                                                 double *__restrict__ rwc = nullptr,
+                                                 const PcgState *__restrict__ st = nullptr) {
+  constexpr int NQ = DOT ? DOT : (UPD ? 1 : 0);  // partial sums per block
   __shared__ double xch[NSEG][kSegCols];
   __shared__ __align__(16) double ot[NSEG][4][36];
   __shared__ double bsh[DOT ? NSEG : 1][DOT ? SEG : 1][64];
-  __shared__ double red[DOT ? NSEG : 1][2];
+  __shared__ double red[NQ ? NSEG : 1][2];
   const int tiles_x = (L.hx2 + kSTX - 1) / kSTX;
   if (is_done(done) || lb >= tiles_x * (L.ny / 2)) return;  // whole blocks: no barrier is skipped
   const int lane = threadIdx.x & 63;
@@ -503,18 +545,22 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   double(*slot)[36] = ot[sg];
   const double *ug = gp(uo);
   const double *bg = gp(bo);
+  const double *qg = UPD ? gp(qc) : nullptr;
+  double alpha = 0.0, rsq = 0.0;
+  if constexpr (UPD) alpha = st->alpha;
 
   double y[SEG];
   double prev = 0.0;
 #pragma unroll
   for (int c0 = 0; c0 < SEG; c0 += CH) {
     if (c0 < len) {
-      double bv[CH], ev[CH];
+      double bv[CH], ev[CH], qv[UPD ? CH : 1];
       nt_d2 tv[CH];
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
         const long long o = (long long)min(k0 + c0 + t, k1 - 1) * H;
         bv[t] = ld_s<FINE>(&bg[o + mo]);
+        if constexpr (UPD) qv[t] = __builtin_nontemporal_load(&qg[o + mo]);
         tv[t] = *(const nt_d2 *)&ug[o + po];
         ev[t] = lane < 2 ? ug[o + eo] : 0.0;
       }
@@ -536,6 +582,15 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
         const double so = slot[r][x + 2], no = slot[r + 2][x + 2];
         __asm__ volatile("" ::: "memory");
         double g = bv[t];
+        if constexpr (UPD) {
+          // the residual update of the CG step; only the lane that owns the
+          // column writes it
+          g = bv[t] - alpha * qv[t];
+          if (valid && c0 + t < len) {
+            __builtin_nontemporal_store(g, &rwc[(long long)k * H + mo]);
+            rsq += g * g;
+          }
+        }
         g = g + txv[k] * (w + e);
         g = g + tyv[k] * (so + no);
         const double nv = (g + tz[k] * prev) * ip[k];
@@ -545,23 +600,23 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
       }
     }
   }
-  double dsum[2] = {0.0, 0.0};
+  double dsum[2] = {rsq, 0.0};
   seg_join_store<double, false, true, FINE, SEG, NSEG, DOT>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf,
                                                             qb, valid, own + mo, H, 1.0, &bsh[DOT ? sg : 0][0][0],
                                                             DOT == 2 ? qc + mo : nullptr, dsum);
-  if constexpr (DOT > 0) {
+  if constexpr (NQ > 0) {
 #pragma unroll
-    for (int q = 0; q < DOT; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       double v = dsum[q];
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
       if (lane == 0) red[sg][q] = v;
     }
     __syncthreads();
-    if (threadIdx.x < DOT) {
+    if (threadIdx.x < NQ) {
       double v = 0.0;
       for (int w = 0; w < NSEG; ++w) v += red[w][threadIdx.x];
-      partial[(long long)(pbase + lb) * DOT + threadIdx.x] = v;
+      partial[(long long)(pbase + lb) * NQ + threadIdx.x] = v;
     }
   }
 }
@@ -573,6 +628,20 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_tile(Geo L, const double *
                                                            double *__restrict__ own,
                                                            const int *__restrict__ done) {
   smooth_tile_body<SEG, NSEG, FINE>(L, tab, c, bo, uo, own, done, logical_block());
+}
+
+// The finest level's colour-1 half-sweep of the first pre-smoothing pair
+// with the CG residual update fused in.
+template <int SEG, int NSEG>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_upd(Geo L, const double *__restrict__ tab, int c,
+                                                               double *__restrict__ rc,
+                                                               const double *__restrict__ uo,
+                                                               double *__restrict__ own,
+                                                               const double *__restrict__ qc,
+                                                               const PcgState *__restrict__ st,
+                                                               double *__restrict__ partial, int pbase) {
+  smooth_tile_body<SEG, NSEG, true, 0, true>(L, tab, c, rc, uo, own, &st->done, logical_block(), partial, pbase, qc,
+                                             rc, st);
 }
 
 // The finest level's tiled half-sweep with the fused CG inner products.
@@ -594,6 +663,19 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg(Geo L, const R *__rest
                                                           R *__restrict__ own, R rho,
                                                           const int *__restrict__ done) {
   smooth_seg_body<R, ZERO, RHO1, FINE, SEG, NSEG, TB>(L, tab, c, bo, uo, own, rho, done, logical_block(), gridDim.x);
+}
+
+// The finest level's first pre-smoothing pair with the CG residual update
+// fused in (column kernel; rho = 1).
+template <typename R, bool ZERO, int SEG, int NSEG>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_seg_upd(Geo L, const R *__restrict__ tab, int c,
+                                                              double *__restrict__ rc, const R *__restrict__ uo,
+                                                              R *__restrict__ own, const double *__restrict__ qc,
+                                                              const PcgState *__restrict__ st,
+                                                              double *__restrict__ partial, int pbase) {
+  smooth_seg_body<R, ZERO, true, true, SEG, NSEG, double, true>(L, tab, c, rc, uo, own, R(1), &st->done,
+                                                                logical_block(), gridDim.x, rc, qc, st, partial,
+                                                                pbase);
 }
 
 // Residual (b - A u) of one cell given its column neighbours at level k.

@@ -59,7 +59,7 @@ class SolveStats(ctypes.Structure):
                 ("b_norm", ctypes.c_double)]
 
 
-EXPORTS = ["ell_grid_create", "ell_grid_destroy", "ell_grid_bytes", "ell_grid_levels",
+EXPORTS = ["ell_grid_create", "ell_grid_destroy", "ell_grid_bytes", "ell_grid_levels", "ell_grid_features",
            "ell_apply_A", "ell_vcycle", "ell_pcg_solve", "ell_level_elems", "ell_to_split",
            "ell_from_split", "ell_level_smooth", "ell_level_resid_restrict",
            "ell_level_prolong_add", "ell_level_apply", "ell_profile_enable", "ell_profile_read",
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     L.ell_grid_bytes.argtypes = [ctypes.POINTER(GridDesc)]
     L.ell_grid_bytes.restype = ctypes.c_size_t
     L.ell_grid_levels.argtypes = [vp]
+    L.ell_grid_features.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.ell_apply_A.argtypes = [vp, vp, vp, vp]
     L.ell_vcycle.argtypes = [vp, vp, vp, vp]
     L.ell_pcg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
@@ -164,6 +165,8 @@ ELL_TUNE_PLANE_PAD, ELL_TUNE_COLOUR_PAD, ELL_TUNE_STENCIL_SEG, ELL_TUNE_APPLY_TI
 ELL_TUNE_BATCH_GRAPH = 4
 ELL_TUNE_SMOOTH_TILE = 5
 ELL_TUNE_FUSED_DOT = 6
+ELL_TUNE_FUSED_UPDATE = 7
+ELL_FEAT_TILED_SMOOTH, ELL_FEAT_FUSED_DOTS, ELL_FEAT_FUSED_UPDATE = 1, 2, 4
 
 
 def set_tuning(key: int, value: int) -> None:
@@ -240,6 +243,11 @@ class Grid:
         self.precision = d.precision
         self.levels = L.ell_grid_levels(h)
         self.bytes = int(L.ell_grid_bytes(ctypes.byref(d)))
+        m = ctypes.c_int32(0)
+        _check(L.ell_grid_features(h, ctypes.byref(m)))
+        self.features = {"tiled_smooth": bool(m.value & ELL_FEAT_TILED_SMOOTH),
+                         "fused_dots": bool(m.value & ELL_FEAT_FUSED_DOTS),
+                         "fused_update": bool(m.value & ELL_FEAT_FUSED_UPDATE)}
 
     @classmethod
     def from_problem(cls, p, precision="fp64", **over):

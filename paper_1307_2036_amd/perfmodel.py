@@ -47,12 +47,19 @@ def vcycle_bytes(n0: int, levels: int, e: int, nu_pre=1, nu_post=1, nu_coarse=1)
     return total
 
 
-def cg_bytes(n0: int, flexible: bool = True) -> float:
-    """CG vector work per iteration (FP64): fused direction + operator + deferred
-    solution update (z, p_old, u read; p_new, q, u written: 48 B), residual update
-    (r, q read; r written: 24 B), dots <r,z>, <z,q> (24 B; <r,z> alone, 16 B, with
-    the classic beta)."""
-    return (48 + 24 + (24 if flexible else 16)) * n0
+def cg_bytes(n0: int, flexible: bool = True, fused_update: bool = False, fused_dots: bool = False) -> float:
+    """CG vector work per iteration (FP64) beyond the V-cycle's own bytes:
+    fused direction + operator + deferred solution update (z, p_old, u read;
+    p_new, q, u written: 48 B); residual update (r, q read, r written: 24 B; on
+    the first pre-smoothing pair, which reads r anyway: q read, r written,
+    16 B); dots <r,z>, <z,q> (24 B; <r,z> alone, 16 B, with the classic beta; on
+    the last post-smoothing pair: nothing, or the q read, 8 B, for <z,q>)."""
+    update = 16 if fused_update else 24
+    if fused_dots:
+        dots = 8 if flexible else 0
+    else:
+        dots = 24 if flexible else 16
+    return (48 + update + dots) * n0
 
 
 def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1) -> float:
@@ -66,21 +73,30 @@ def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1) -> float:
     return fine + vcycle_bytes(n0 // 4, levels - 1, 4, nu_coarse=nu_coarse)
 
 
-def pcg_iteration_bytes(n0: int, levels: int, e: int, nu_coarse=1, flexible=True, **mg) -> float:
+def pcg_iteration_bytes(n0: int, levels: int, e: int, nu_coarse=1, flexible=True, fused_update=False,
+                        fused_dots=False, **mg) -> float:
+    cg = cg_bytes(n0, flexible, fused_update, fused_dots)
     if e == 8:
-        return cg_bytes(n0, flexible) + vcycle_bytes(n0, levels, 8, nu_coarse=nu_coarse, **mg)
-    return cg_bytes(n0, flexible) + hybrid_vcycle_bytes(n0, levels, nu_coarse)
+        return cg + vcycle_bytes(n0, levels, 8, nu_coarse=nu_coarse, **mg)
+    return cg + hybrid_vcycle_bytes(n0, levels, nu_coarse)
 
 
-def smooth0_launch_bytes_hybrid(n0: int) -> float:
+def smooth0_launch_bytes_hybrid(n0: int, fused_update: bool = False, dot_q: bool = False) -> float:
     """Average bytes of a finest-level half-sweep launch in the mixed-precision
-    V-cycle: FP32 pre-sweeps reading the FP64 residual, FP64 post-sweeps."""
-    return (6 + 8 + 12 + 12) * n0 / 4
+    V-cycle: FP32 pre-sweeps reading the FP64 residual, FP64 post-sweeps; with
+    the fused residual update the pre-sweeps also read q and write r (16 B per
+    unknown of their colour), with the fused <z,q> the post-sweeps read q."""
+    return ((6 + 8 + 12 + 12) + (16 if fused_update else 0) + (8 if dot_q else 0)) * n0 / 4
 
 
-def smooth0_launch_bytes(n0: int, e: int, nu_pre=1, nu_post=1) -> float:
+def smooth0_launch_bytes(n0: int, e: int, nu_pre=1, nu_post=1, fused_update: bool = False,
+                         dot_q: bool = False) -> float:
     """Average algorithmic bytes of one finest-level half-sweep launch in a
-    V-cycle (the first pre-smoothing sweep starts from u = 0)."""
+    V-cycle (the first pre-smoothing sweep starts from u = 0).  The fused
+    residual update adds the q read and the r write to the first pre-smoothing
+    pair (8 + 8 B per unknown of each colour), the fused <z,q> the q read to the
+    last post-smoothing pair."""
     launches = 2 * nu_pre + 2 * nu_post
     total = smooth_bytes(n0, e, True) + (launches - 1) * smooth_bytes(n0, e, False)
+    total += (16 * n0 if fused_update else 0) + (8 * n0 if dot_q else 0)
     return total / launches

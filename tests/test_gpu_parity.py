@@ -369,6 +369,40 @@ def test_fused_dots_equal_separate_pass(ell, orc, nx, ny, nz, levels, precision,
         assert rel(u1, u_ref) <= 1e-6
 
 
+@pytest.mark.parametrize("nx,ny,nz,levels,precision,flexible", [
+    (64, 16, 32, 3, "fp64", False), (68, 12, 100, 2, "fp64", True), (64, 64, 48, 3, "fp64", False),
+    (128, 32, 64, 3, "fp32", True), (68, 12, 40, 2, "fp32", False)])
+def test_fused_update_equals_separate_pass(ell, orc, nx, ny, nz, levels, precision, flexible):
+    """r -= alpha q and ||r||^2 carried by the first pre-smoothing pair (the
+    convergence test between that pair and the rest of the V-cycle) give the
+    iterates of the separate residual pass: the same iteration count, solutions
+    within 1e-10, and the same final state at an iteration limit."""
+    h = 1.0 / nx
+    dz = I.dz_quadratic(nz, 1.0 / 50.0)
+    p = I.Problem("fused_update", nx, ny, nz, h, h, dz, I.lambda2_perturbed(h, dz, 0.3, 24), 1e-2,
+                  I.rhs_normal(nx, ny, dz, 23), n_levels=levels)
+    res = []
+    for fused in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_FUSED_UPDATE, fused)
+        try:
+            G = ell.Grid.from_problem(p, precision=precision)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_FUSED_UPDATE, 1)
+        assert G.features["fused_update"] == bool(fused)
+        u, st = G.pcg_solve(dev(p.f), rtol=1e-8, flexible=flexible)
+        assert st.status == 0
+        ul, stl = G.pcg_solve(dev(p.f), rtol=1e-14, maxiter=3, flexible=flexible)
+        assert stl.status == ell.ELL_NOT_CONVERGED and stl.iters == 3
+        res.append((host(u), st, host(ul), stl))
+    (u1, s1, l1, t1), (u0, s0, l0, t0) = res
+    assert s1.iters == s0.iters
+    assert rel(u1, u0) <= 1e-10 and rel(l1, l0) <= 1e-10
+    assert abs(t1.r_norm / t0.r_norm - 1) <= 1e-10
+    if precision == "fp64":
+        g = orc.Grid.from_problem(p)
+        check_solve(orc, g, p.f, u1, s1, 1e-8, flexible=flexible)
+
+
 def test_solve_edge_cases(ell, orc):
     p = I.graded_problem("edge", 32, 8, 1e-2, 1, 2)
     G = ell.Grid.from_problem(p)
