@@ -46,6 +46,7 @@ struct GridDev {
   int apply_tile, apply_nseg;  // CG operator step: LDS-tiled kernel and its k-segments
   int nb_tiles;                // finest level: tiles of a tiled half-sweep (0: column kernel)
   int nb_dot;                  // partial sums of the fused CG dots (0: separate dot pass)
+  int nb_upd0, nb_upd;         // fused residual update: colour-0 slots, all slots (0: separate pass)
 };
 
 struct StageEnt {
@@ -154,6 +155,62 @@ __global__ __launch_bounds__(NSEG * 64) void kb_smooth_tile(const StageEnt *__re
   smooth_tile_body<SEG, NSEG, true, DOT ? 2 : 0>(G, tab, c, b + c * cs, u + (1 - c) * cs, u + c * cs,
                                               gp(&gd->st->done), ui(bg - ents[e].block0), gp(gd->partial),
                                               c == 1 ? 0 : ui(gd->nb_tiles), gp(gd->q) + c * cs);
+}
+
+// The finest level's first pre-smoothing pair of the grids with the fused
+// residual update (column kernel; ROLE_PRE32: the FP32 sweep of the
+// mixed-precision V-cycle, ROLE_FINE64: FP64).  HEAD: at the start of a
+// grid's first step (nothing pending, no iteration yet), the plain pair;
+// otherwise (the end of every step, after alpha): the pair with r -= alpha q,
+// whose convergence test ends the step and whose V-cycle the next step
+// continues.  A block whose grid does not take this form of the pair returns
+// at once.
+template <typename R, bool ZERO, int SEG, int NSEG, int ROLE, bool HEAD>
+__global__ __launch_bounds__(NSEG * 64) void kb_smooth_upd(const StageEnt *__restrict__ ents, int nent, int total,
+                                                           int c) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = gp(ents[e].g);
+  const PcgState *st = gp(gd->st);
+  const int pending = ui(st->pending);
+  if (HEAD ? (pending != 0 || ui(st->iter) != 0) : pending == 0) return;
+  const Geo G = ugeo(gd->lev[0].geo);
+  const R *tab = cp(ROLE == ROLE_FINE64 ? (const R *)gd->tab64_0 : (const R *)gd->lev[0].tab);
+  double *r = gp(gd->r);
+  R *u = gp(ROLE == ROLE_FINE64 ? (R *)gd->z : (R *)gd->u32);
+  const long long cs = G.cs;
+  const int lb = ui(bg - ents[e].block0);
+  if (HEAD)
+    smooth_seg_body<R, ZERO, true, true, SEG, NSEG, double>(G, tab, c, r + c * cs, u + (1 - c) * cs, u + c * cs,
+                                                            R(1), &st->done, lb, 0);
+  else
+    smooth_seg_body<R, ZERO, true, true, SEG, NSEG, double, true>(
+        G, tab, c, r + c * cs, u + (1 - c) * cs, u + c * cs, R(1), &st->done, lb, 0, r + c * cs,
+        gp(gd->q) + c * cs, st, gp(gd->partial), c == 1 ? ui(gd->nb_upd0) : 0);
+}
+
+// Colour 1 of that pair on the tiled kernel (FP64 batches).
+template <int SEG, int NSEG, bool HEAD>
+__global__ __launch_bounds__(NSEG * 64) void kb_smooth_tile_upd(const StageEnt *__restrict__ ents, int nent,
+                                                                int total) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = gp(ents[e].g);
+  const PcgState *st = gp(gd->st);
+  const int pending = ui(st->pending);
+  if (HEAD ? (pending != 0 || ui(st->iter) != 0) : pending == 0) return;
+  const Geo G = ugeo(gd->lev[0].geo);
+  double *r = gp(gd->r);
+  double *u = gp(gd->z);
+  const long long cs = G.cs;
+  const int lb = ui(bg - ents[e].block0);
+  if (HEAD)
+    smooth_tile_body<SEG, NSEG, true>(G, cp(gd->tab64_0), 1, r + cs, u, u + cs, &st->done, lb);
+  else
+    smooth_tile_body<SEG, NSEG, true, 0, true>(G, cp(gd->tab64_0), 1, r + cs, u, u + cs, &st->done, lb,
+                                               gp(gd->partial), ui(gd->nb_upd0), gp(gd->q) + cs, r + cs, st);
 }
 
 template <typename R, typename TB, int ROLE>
@@ -281,7 +338,9 @@ __global__ __launch_bounds__(kBlock) void kb_finalize(const StageEnt *__restrict
   const GridDev *gd = gp(ents[blockIdx.x].g);
   const int nblk = ui(mode == F_ALPHA ? gd->nb_apply
                                       : (mode == F_TRUE ? gd->nb_finish
-                                                        : (mode == F_BETA && gd->nb_dot ? gd->nb_dot : gd->nb_flat)));
+                                                        : (mode == F_BETA && gd->nb_dot ? gd->nb_dot
+                                                                                        : (mode == F_CONV_PENDING ? gd->nb_upd
+                                                                                                                  : gd->nb_flat))));
   const int nq = (mode == F_BETA || mode == F_TRUE) ? 2 : 1;
   finalize_body(gp(gd->partial), nblk, nq, gp(gd->st), mode, 0.0, 0.0, 0, 0, 1);
 }
@@ -316,6 +375,19 @@ bool batch_tile(const ell_grid *g) {
   return tile_ok(g, 0) && ((ns == 4 && seg_len(g->d.nz, 4) <= 32) || (ns == 8 && seg_len(g->d.nz, 8) <= 16));
 }
 bool batch_fused_dot(const ell_grid *g) { return batch_tile(g) && g->fused_dot && g->L >= 2 && g->d.nu_post >= 1; }
+// The residual update rides on the finest level's first pre-smoothing pair
+// (four k-segments of at most 32 levels or eight of at most 16).
+bool batch_fused_update(const ell_grid *g) {
+  const Geo &G = g->lev[0].geo;
+  const int Ls = seg_len(G.nz, G.nseg);
+  return g->fused_update && g->L >= 2 && ((G.nseg == 8 && Ls <= 16) || (G.nseg == 4 && Ls <= 32));
+}
+// Blocks of the colour-c sweep of that pair for grid g (one slot each).
+int batch_upd_blocks(const ell_grid *g, int c) {
+  const Geo &G = g->lev[0].geo;
+  if (c == 1 && g->prec == ELL_FP64 && batch_tile(g)) return smooth_tiles(G);
+  return (int)(((c ? G.ncol1 : G.ncol0) + kSegCols - 1) / kSegCols);
+}
 
 int grid_dev_build(ell_grid *g) {
   if (g->L > kMaxLevels) return fail(ELL_ERR_INVALID, "too many levels for the batch engine");
@@ -349,6 +421,8 @@ int grid_dev_build(ell_grid *g) {
   h.nb_finish = finish_blocks(g);
   h.nb_tiles = batch_tile(g) ? smooth_tiles(g->lev[0].geo) : 0;
   h.nb_dot = batch_fused_dot(g) ? 2 * h.nb_tiles : 0;
+  h.nb_upd0 = batch_fused_update(g) ? batch_upd_blocks(g, 0) : 0;
+  h.nb_upd = batch_fused_update(g) ? h.nb_upd0 + batch_upd_blocks(g, 1) : 0;
   void *d = nullptr;
   CHK(dalloc(g, &d, sizeof(GridDev)));
   HIPCHK(hipMemcpy(d, &h, sizeof(GridDev), hipMemcpyHostToDevice));
@@ -389,7 +463,8 @@ struct Ticket {
 
 // One stage of a grouped iteration.
 struct Stage {
-  enum Kind { APPLY_DIR, UPDATE_R, DOTS, FINALIZE, SMOOTH, SMOOTH_TILE, RESTRICT, PROLONG, PROLONG_OUT } kind;
+  enum Kind { APPLY_DIR, UPDATE_R, DOTS, FINALIZE, SMOOTH, SMOOTH_TILE, SMOOTH_UPD, SMOOTH_TILE_UPD, RESTRICT,
+              PROLONG, PROLONG_OUT } kind;
   int level, colour, zero, role, mode;  // mode: finalize mode; SMOOTH_TILE: 1 with the fused dots
   int seg;                              // SMOOTH: register segment length (16/32/64)
   int nseg;                             // SMOOTH, SMOOTH_TILE: k-segments (block of nseg wavefronts)
@@ -525,6 +600,41 @@ int batch_build(ell_batch *b) {
   // A half-sweep stage; the finest level's FP64 half-sweeps after the first
   // go to the tiled kernel for the grids that take it (last_post: the last
   // post-smoothing pair, with the fused CG dots where the grid has them).
+  // The finest level's first pre-smoothing pair of the grids with the fused
+  // residual update (head: the plain pair of a grid's first step; tail: the
+  // pair with r -= alpha q at the end of every step, then the convergence
+  // test); one stage per colour, k-segment count and kernel.
+  auto add_upd_pair = [&](const std::vector<ell_grid *> &upd, bool head) {
+    const int role = mixed ? ROLE_PRE32 : ROLE_FINE64;
+    for (int c = 0; c < 2; ++c) {
+      for (int ns : {4, 8}) {
+        std::vector<ell_grid *> col, tile;
+        for (ell_grid *g : upd) {
+          if (g->lev[0].geo.nseg != ns) continue;
+          (c == 1 && !mixed && batch_tile(g) ? tile : col).push_back(g);
+        }
+        Stage st{};
+        st.level = 0;
+        st.colour = c;
+        st.zero = c == 0 ? 1 : 0;
+        st.role = role;
+        st.nseg = ns;
+        st.mode = head ? 1 : 0;
+        st.kind = Stage::SMOOTH_UPD;
+        st.seg = ns == 8 ? 16 : seg_of(col, 0);
+        add(st, col, [c](ell_grid *g) { return batch_upd_blocks(g, c); });
+        st.kind = Stage::SMOOTH_TILE_UPD;
+        st.seg = ns == 8 ? 16 : seg_of(tile, 0);
+        add(st, tile, [c](ell_grid *g) { return batch_upd_blocks(g, c); });
+      }
+    }
+    if (!head) {
+      Stage fc{};
+      fc.kind = Stage::FINALIZE;
+      fc.mode = F_CONV_PENDING;
+      add(fc, upd, one);
+    }
+  };
   // One stage per k-segment count: the finest level has four or eight.
   auto add_smooth = [&](const Stage &st, const std::vector<ell_grid *> &gs, bool last_post) {
     const int l = st.level;
@@ -558,6 +668,10 @@ int batch_build(ell_batch *b) {
   //   p = z + beta p, q = A p and <p,q>, alpha, r -= alpha q, convergence;
   // the solution update of iteration K is deferred into step K + 1 (or the
   // end of the solve).  A grid admitted just before the step starts at K = 1.
+  // For the grids with the fused residual update, r -= alpha q and the
+  // convergence test ride on the first pre-smoothing pair of the next
+  // V-cycle, run at the end of the step (the next step continues that
+  // V-cycle); a grid's first step runs that pair, plain, at its start.
   Stage s0{};
   // V-cycle, down
   int Dmax = 0;
@@ -578,7 +692,16 @@ int batch_build(ell_batch *b) {
     for (int it = 0; it < sweeps_shared; ++it) {
       // grids at their coarsest level take part in the first pair only if
       // they have at least one coarse sweep (nu_coarse >= 1, checked)
-      const std::vector<ell_grid *> &gs = it == 0 ? here : deep;
+      std::vector<ell_grid *> gs = it == 0 ? here : deep;
+      if (d == 0 && it == 0) {
+        // the grids with the fused residual update run this pair here only in
+        // their first step (the head form); later the end of the previous
+        // step ran it
+        std::vector<ell_grid *> upd, rest;
+        for (ell_grid *g : gs) (batch_fused_update(g) ? upd : rest).push_back(g);
+        add_upd_pair(upd, true);
+        gs = rest;
+      }
       for (int c = 0; c < 2; ++c) {
         Stage st{};
         st.kind = Stage::SMOOTH;
@@ -664,13 +787,16 @@ int batch_build(ell_batch *b) {
   s0.kind = Stage::FINALIZE;
   s0.mode = F_ALPHA;
   add(s0, all, one);
+  std::vector<ell_grid *> upd, noupd;  // grids with / without the fused residual update
+  for (ell_grid *g : all) (batch_fused_update(g) ? upd : noupd).push_back(g);
+  add_upd_pair(upd, false);
   s0 = Stage{};
   s0.kind = Stage::UPDATE_R;
-  add(s0, all, flat);
+  add(s0, noupd, flat);
   s0 = Stage{};
   s0.kind = Stage::FINALIZE;
   s0.mode = F_CONV;
-  add(s0, all, one);
+  add(s0, noupd, one);
   // state gather table: one entry per active grid (reuses the FINALIZE layout)
   CHK(batch_reserve(b, ents.size() + 1, (int)all.size() + 1));
   if (!ents.empty()) {
@@ -701,6 +827,28 @@ void launch_kb_smooth(const Stage &st, const StageEnt *e, int nb, hipStream_t s)
   }
 }
 
+template <typename R, int ROLE, bool HEAD>
+void launch_kb_smooth_upd(const Stage &st, const StageEnt *e, int nb, hipStream_t s) {
+  const int C = st.colour;
+  if (st.nseg == 8) {
+    if (st.zero) kb_smooth_upd<R, true, 16, 8, ROLE, HEAD><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total, C);
+    else kb_smooth_upd<R, false, 16, 8, ROLE, HEAD><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total, C);
+  } else if (st.seg == 16) {
+    if (st.zero) kb_smooth_upd<R, true, 16, 4, ROLE, HEAD><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, C);
+    else kb_smooth_upd<R, false, 16, 4, ROLE, HEAD><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, C);
+  } else {
+    if (st.zero) kb_smooth_upd<R, true, 32, 4, ROLE, HEAD><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, C);
+    else kb_smooth_upd<R, false, 32, 4, ROLE, HEAD><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, C);
+  }
+}
+
+template <bool HEAD>
+void launch_kb_tile_upd(const Stage &st, const StageEnt *e, int nb, hipStream_t s) {
+  if (st.nseg == 8) kb_smooth_tile_upd<16, 8, HEAD><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total);
+  else if (st.seg == 16) kb_smooth_tile_upd<16, 4, HEAD><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
+  else kb_smooth_tile_upd<32, 4, HEAD><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
+}
+
 // Enqueue one grouped CG iteration for every active grid.
 int batch_step(ell_batch *b) {
   hipStream_t s = b->stream;
@@ -712,6 +860,19 @@ int batch_step(ell_batch *b) {
       case Stage::APPLY_DIR: kb_apply_dir<<<nb, kBlock, 0, s>>>(e, st.nent, st.total); break;
       case Stage::UPDATE_R: kb_update_r<<<nb, kBlock, 0, s>>>(e, st.nent, st.total); break;
       case Stage::DOTS: kb_dots<<<nb, kBlock, 0, s>>>(e, st.nent, st.total); break;
+      case Stage::SMOOTH_UPD:
+        if (st.mode) {
+          if (st.role == ROLE_PRE32) launch_kb_smooth_upd<float, ROLE_PRE32, true>(st, e, nb, s);
+          else launch_kb_smooth_upd<double, ROLE_FINE64, true>(st, e, nb, s);
+        } else {
+          if (st.role == ROLE_PRE32) launch_kb_smooth_upd<float, ROLE_PRE32, false>(st, e, nb, s);
+          else launch_kb_smooth_upd<double, ROLE_FINE64, false>(st, e, nb, s);
+        }
+        break;
+      case Stage::SMOOTH_TILE_UPD:
+        if (st.mode) launch_kb_tile_upd<true>(st, e, nb, s);
+        else launch_kb_tile_upd<false>(st, e, nb, s);
+        break;
       case Stage::SMOOTH_TILE:
         if (st.nseg == 8) {
           if (st.mode) kb_smooth_tile<16, 8, true><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total, st.colour);

@@ -50,7 +50,8 @@ struct Geo {
 
 struct PcgState {
   double kappa_old, alpha, beta, r0_norm, b_norm, r_norm, thresh, true_r_norm;
-  int iter, done, status, maxiter, flexible, pad;
+  int iter, done, status, maxiter, flexible;
+  int pending;  // a step length alpha waits for its residual update (set by F_ALPHA)
 };
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b mod 8);
@@ -415,8 +416,14 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
 
   R y[SEG];
   R prev = R(0);
+  // go: an update is pending (always in a single grid's step; a batched
+  // grid's first step has none and sweeps with b = r as it is)
   double alpha = 0.0, rr = 0.0;
-  if constexpr (UPD) alpha = st->alpha;
+  bool go = false;
+  if constexpr (UPD) {
+    go = st->pending != 0;
+    alpha = st->alpha;
+  }
 #pragma unroll
   for (int c0 = 0; c0 < SEG; c0 += 8) {
     if (c0 < len) {
@@ -430,8 +437,10 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
           // the residual update of the CG step; only the lane that owns the
           // column writes it (idle lanes, also those of blocks past the last
           // column, read it and must not see their own write)
-          const double rv = __builtin_nontemporal_load(&bb[o]) - alpha * __builtin_nontemporal_load(&qo[mm + o]);
-          if (valid && c0 + t < len) {
+          const double b0 = __builtin_nontemporal_load(&bb[o]);
+          const double q0 = __builtin_nontemporal_load(&qo[mm + o]);
+          const double rv = go ? b0 - alpha * q0 : b0;  // a select: q may hold anything without go
+          if (go && valid && c0 + t < len) {
             __builtin_nontemporal_store(rv, &rw[mm + o]);
             rr += rv * rv;
           }
@@ -506,6 +515,13 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
                                                  double *__restrict__ rwc = nullptr,
                                                  const PcgState *__restrict__ st = nullptr) {
   constexpr int NQ = DOT ? DOT : (UPD ? 1 : 0);  // partial sums per block
+  if constexpr (UPD) {
+    // no update pending (a batched grid's first step): the plain sweep of b = r
+    if (st->pending == 0) {
+      smooth_tile_body<SEG, NSEG, FINE, 0, false, CH>(L, tab, c, bo, uo, own, done, lb);
+      return;
+    }
+  }
   __shared__ double xch[NSEG][kSegCols];
   __shared__ __align__(16) double ot[NSEG][4][36];
   __shared__ double bsh[DOT ? NSEG : 1][DOT ? SEG : 1][64];
@@ -1812,7 +1828,11 @@ __global__ __launch_bounds__(kBlock) void k_dots(const double2 *__restrict__ r,
   dots_body<Z>(r, z, q, n2, st, partial, logical_block(), gridDim.x);
 }
 
-enum FinalizeMode : int { F_INIT = 0, F_KAPPA = 1, F_ALPHA = 2, F_CONV = 3, F_BETA = 4, F_TRUE = 5, F_UNIT = 6 };
+// F_CONV_PENDING: F_CONV if a residual update is pending, else nothing (a
+// batched grid's first step has no update before its V-cycle).
+enum FinalizeMode : int {
+  F_INIT = 0, F_KAPPA = 1, F_ALPHA = 2, F_CONV = 3, F_BETA = 4, F_TRUE = 5, F_UNIT = 6, F_CONV_PENDING = 7
+};
 
 // One block: reduce nq interleaved partial sums over nblk blocks in a fixed
 // order and advance the CG scalars (Appendix B, Alg. PCG).
@@ -1822,6 +1842,10 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
   __shared__ double sh[4];
   __shared__ double tot[2];
   if (mode != F_TRUE && mode != F_INIT && st->done) return;
+  if (mode == F_CONV_PENDING) {
+    if (!st->pending) return;
+    mode = F_CONV;
+  }
   for (int qi = 0; qi < nq; ++qi) {
     double v = 0.0;
     for (int b = threadIdx.x; b < nblk; b += kBlock) v += partial[(long long)b * nq + qi];
@@ -1839,6 +1863,7 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
       const double th = fmax(rtol * ref, atol);
       st->thresh = th;
       st->iter = 0;
+      st->pending = 0;
       st->alpha = st->beta = st->kappa_old = 0.0;
       if (!isfinite(r0) || !isfinite(bn)) {
         st->done = 1;
@@ -1862,6 +1887,7 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
     case F_ALPHA: {
       const double a = st->kappa_old / tot[0];
       st->alpha = a;
+      st->pending = 1;
       if (!isfinite(a)) { st->done = 1; st->status = -4; }
       break;
     }
@@ -1869,6 +1895,7 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
       const double rn = sqrt(tot[0]);
       st->r_norm = rn;
       st->iter += 1;
+      st->pending = 0;
       if (!isfinite(rn)) { st->done = 1; st->status = -4; }
       else if (rn < st->thresh) { st->done = 1; st->status = 0; }
       else if (st->iter >= st->maxiter) { st->done = 1; st->status = 1; }

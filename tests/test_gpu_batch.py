@@ -235,21 +235,23 @@ def test_config3_batch_at_full_size(E, orc):
 
 @pytest.mark.parametrize("precision,flexible", [("fp32", True), ("fp64", False), ("fp64", True)])
 def test_fused_dots_and_tiles_in_batch(E, precision, flexible):
-    """The batch's tiled finest-level half-sweeps with the fused CG dots give the
-    iterates of the batch without them (column kernels, separate dot pass) up
-    to the summation order; (96, 24) has a partial tile and (32, 40) one tile
-    per row pair."""
+    """The batch's tiled finest-level half-sweeps with the fused CG dots and the
+    fused residual update give the iterates of the batch without them (column
+    kernels, separate passes) up to the summation order; (96, 24) has a partial
+    tile and (32, 40) one tile per row pair."""
     ps = problems()
     res = []
     for on in (1, 0):
         E.set_tuning(E.ELL_TUNE_FUSED_DOT, on)
         E.set_tuning(E.ELL_TUNE_SMOOTH_TILE, on)
+        E.set_tuning(E.ELL_TUNE_FUSED_UPDATE, on)
         try:
             B = E.Batch(8 << 30)
             grids = [B.grid(p, precision=precision) for p in ps]
         finally:
             E.set_tuning(E.ELL_TUNE_FUSED_DOT, 1)
             E.set_tuning(E.ELL_TUNE_SMOOTH_TILE, 1)
+            E.set_tuning(E.ELL_TUNE_FUSED_UPDATE, 1)
         fs = [dev(p.f) for p in ps]
         us = [torch.zeros_like(f) for f in fs]
         st = B.wait(B.submit(grids, fs, us, rtol=1e-8, flexible=flexible))
