@@ -805,7 +805,16 @@ int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipS
     const Geo &F = g->lev[0].geo, &C = g->lev[1].geo;
     const int nb = seg_blocks(F.ncol0);
     ProfScope ps(g, ELL_K_PROLONG0, s);
-    if (g->d.prolong == 1)
+    if (g->d.prolong == 0 && g->smooth_tile && F.has_x && F.ny % 2 == 0) {
+      // bilinear with the coarse rows staged in LDS (as launch_prolong)
+      const int ns = transfer_segments(F.ncol0, F.nz);
+      const int nbt = blocks8((long long)((F.hx2 + kSTX - 1) / kSTX) * (F.ny / 2) * kBlock);
+      const float *uc = (const float *)g->lev[1].u;
+      if (ns == 16) k_prolong_out_tile<float, double, 16><<<nbt, 16 * 64, 0, s>>>(F, C, uc, u32, z, done);
+      else if (ns == 8) k_prolong_out_tile<float, double, 8><<<nbt, 8 * 64, 0, s>>>(F, C, uc, u32, z, done);
+      else k_prolong_out_tile<float, double, 4><<<nbt, 4 * 64, 0, s>>>(F, C, uc, u32, z, done);
+      CHK(check_launch("k_prolong_out_tile"));
+    } else if (g->d.prolong == 1)
       k_prolong_out<float, double, 1><<<nb, kBlock, 0, s>>>(F, C, (const float *)g->lev[1].u, u32, z, done);
     else
       k_prolong_out<float, double, 0><<<nb, kBlock, 0, s>>>(F, C, (const float *)g->lev[1].u, u32, z, done);

@@ -253,6 +253,34 @@ __global__ __launch_bounds__(kBlock) void kb_prolong_out(const StageEnt *__restr
                                         gp(gd->u32), gp(gd->z), gp(&gd->st->done), ui(bg - ents[e].block0), 0);
 }
 
+// The colour-0 bilinear prolongation of the grids that take the LDS-tiled
+// kernel (one block per tile of level l), in place or, OUT, from the FP32
+// finest level into the FP64 output z (the mixed-precision V-cycle).
+template <typename R, int ROLE>
+__global__ __launch_bounds__(kBlock) void kb_prolong_tile(const StageEnt *__restrict__ ents, int nent, int total,
+                                                          int l) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = gp(ents[e].g);
+  const LevelDev &F = gd->lev[l];
+  const LevelDev &C = gd->lev[l + 1];
+  R *u = gp(ROLE == ROLE_FINE64 ? (R *)gd->z : (R *)F.u);
+  prolong_tile_body<R, kSeg>(ugeo(F.geo), ugeo(C.geo), gp((const R *)C.u), u, gp(&gd->st->done),
+                             ui(bg - ents[e].block0));
+}
+
+__global__ __launch_bounds__(kBlock) void kb_prolong_out_tile(const StageEnt *__restrict__ ents, int nent,
+                                                              int total) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = gp(ents[e].g);
+  prolong_tile_body<float, kSeg, double>(ugeo(gd->lev[0].geo), ugeo(gd->lev[1].geo),
+                                         gp((const float *)gd->lev[1].u), gp(gd->u32), gp(&gd->st->done),
+                                         ui(bg - ents[e].block0), gp(gd->z));
+}
+
 __global__ __launch_bounds__(kBlock) void kb_apply_dir(const StageEnt *__restrict__ ents, int nent, int total) {
   const int bg = logical_block();
   if (bg >= total) return;
@@ -464,7 +492,7 @@ struct Ticket {
 // One stage of a grouped iteration.
 struct Stage {
   enum Kind { APPLY_DIR, UPDATE_R, DOTS, FINALIZE, SMOOTH, SMOOTH_TILE, SMOOTH_UPD, SMOOTH_TILE_UPD, RESTRICT,
-              PROLONG, PROLONG_OUT } kind;
+              PROLONG, PROLONG_OUT, PROLONG_TILE, PROLONG_OUT_TILE } kind;
   int level, colour, zero, role, mode;  // mode: finalize mode; SMOOTH_TILE: 1 with the fused dots
   int seg;                              // SMOOTH: register segment length (16/32/64)
   int nseg;                             // SMOOTH, SMOOTH_TILE: k-segments (block of nseg wavefronts)
@@ -755,7 +783,18 @@ int batch_build(ell_batch *b) {
       st.role = d == 0 ? ROLE_FINE64 : ROLE_COARSE;
     }
     st.mode = gs[0]->d.prolong;
-    add(st, gs, red_cols(d));
+    {
+      // bilinear prolongations on the tiled kernel where the level takes it
+      std::vector<ell_grid *> col, tile;
+      for (ell_grid *g : gs) {
+        const Geo &F = g->lev[d].geo;
+        (g->d.prolong == 0 && g->smooth_tile && F.has_x && F.ny % 2 == 0 ? tile : col).push_back(g);
+      }
+      add(st, col, red_cols(d));
+      Stage t = st;
+      t.kind = st.kind == Stage::PROLONG_OUT ? Stage::PROLONG_OUT_TILE : Stage::PROLONG_TILE;
+      add(t, tile, [d](ell_grid *g) { return smooth_tiles(g->lev[d].geo); });
+    }
     for (int it = 0; it < nu_post; ++it) {
       for (int c = 1; c >= 0; --c) {
         Stage sm{};
@@ -910,6 +949,12 @@ int batch_step(ell_batch *b) {
           else kb_prolong<double, 0, ROLE_COARSE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
         }
         break;
+      case Stage::PROLONG_TILE:
+        if (st.role == ROLE_FINE64) kb_prolong_tile<double, ROLE_FINE64><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+        else if (mixed) kb_prolong_tile<float, ROLE_COARSE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+        else kb_prolong_tile<double, ROLE_COARSE><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.level);
+        break;
+      case Stage::PROLONG_OUT_TILE: kb_prolong_out_tile<<<nb, kBlock, 0, s>>>(e, st.nent, st.total); break;
       case Stage::PROLONG_OUT:
         if (st.mode == 1) kb_prolong_out<1><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
         else kb_prolong_out<0><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);

@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace ell {
 
 constexpr int kBlock = 256;  // 4 wavefronts of 64 lanes
@@ -967,9 +969,12 @@ __device__ __forceinline__ void prolong_body(Geo F, Geo C, const R *__restrict__
 // mx0-1 .. mx0+32 (102 values, two loads), then interpolates from LDS with
 // the column kernel's weights and order (bitwise equal results).  Needs ny
 // even and nx > 1; blocks past the last tile return at once.
-template <typename R, int NSEG>
+// TO != R (the mixed-precision V-cycle's last prolongation): the corrected
+// values go to out (of type TO) instead of back into u, as in prolong_out_body.
+template <typename R, int NSEG, typename TO = R>
 __device__ __forceinline__ void prolong_tile_body(Geo F, Geo C, const R *__restrict__ uc, R *__restrict__ u,
-                                                  const int *__restrict__ done, int lb) {
+                                                  const int *__restrict__ done, int lb,
+                                                  TO *__restrict__ out = nullptr) {
   __shared__ R cs[NSEG][3][36];
   const int tiles_x = (F.hx2 + kSTX - 1) / kSTX;
   if (is_done(done) || lb >= tiles_x * (F.ny / 2)) return;
@@ -1021,7 +1026,10 @@ __device__ __forceinline__ void prolong_tile_body(Geo F, Geo C, const R *__restr
         e = e + R(3.0 / 16.0) * b2;
         e = e + R(3.0 / 16.0) * c2;
         e = e + R(1.0 / 16.0) * d;
-        if (valid) own[(long long)(k + t) * HF] = o[t] + e;
+        if (valid) {
+          if constexpr (std::is_same<R, TO>::value) own[(long long)(k + t) * HF] = o[t] + e;
+          else out[mo + (long long)(k + t) * HF] = (TO)o[t] + (TO)e;
+        }
       }
     }
   }
@@ -1031,6 +1039,16 @@ template <typename R, int NSEG>
 __global__ __launch_bounds__(NSEG * 64) void k_prolong_tile(Geo F, Geo C, const R *__restrict__ uc,
                                                             R *__restrict__ u, const int *__restrict__ done) {
   prolong_tile_body<R, NSEG>(F, C, uc, u, done, logical_block());
+}
+
+// The mixed-precision V-cycle's last prolongation on the tile: out = base +
+// P e_c on colour 0 (FP32 base and correction, FP64 out), bitwise equal to
+// k_prolong_out.
+template <typename R, typename TO, int NSEG>
+__global__ __launch_bounds__(NSEG * 64) void k_prolong_out_tile(Geo F, Geo C, const R *__restrict__ uc,
+                                                                const R *__restrict__ base, TO *__restrict__ out,
+                                                                const int *__restrict__ done) {
+  prolong_tile_body<R, NSEG, TO>(F, C, uc, const_cast<R *>(base), done, logical_block(), out);
 }
 
 template <typename R, bool RED_ONLY, int MODE, int NSEG = kSeg>

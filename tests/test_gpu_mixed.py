@@ -50,6 +50,26 @@ def test_vcycle_precision(orc, name, precision, tol):
     assert rel(z, orc.vcycle(g, r)) <= tol
 
 
+@pytest.mark.parametrize("name", list(PROBLEMS) + ["partial_tile"])
+def test_tiled_kernels_in_mixed_vcycle_are_bitwise(name):
+    """The mixed-precision V-cycle with its LDS-tiled kernels (FP64 post-smoothing,
+    prolongations including the one into the FP64 output) equals the one with
+    the column kernels bitwise; (136, 24) has partial tiles on two levels."""
+    from paper_1307_2036_amd import ell
+    p = (I.graded_problem("pt", 136, 40, 1e-2, 25, 26, n_levels=3) if name == "partial_tile"
+         else PROBLEMS[name]())
+    r = dev(p.f * (p.hx * p.hy * p.dz)[:, None, None])
+    out = []
+    for tile in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_SMOOTH_TILE, tile)
+        try:
+            G = ell.Grid.from_problem(p, precision="fp32")
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_SMOOTH_TILE, 1)
+        out.append(host(G.vcycle(r)))
+    np.testing.assert_array_equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("name", list(PROBLEMS))
 @pytest.mark.parametrize("precision", ["fp32", "bf16coef"])
 def test_tight_solve_reaches_fp64_solution(orc, name, precision):
