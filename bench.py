@@ -164,7 +164,9 @@ def main():
     t_a = live(G.profile_times(ell.ELL_K_APPLY))
     feat = G.features
     dot_q = feat["fused_dots"] and flexible
-    launch_bytes = (perfmodel.smooth0_launch_bytes(n, 8, fused_update=feat["fused_update"], dot_q=dot_q)
+    fpro = feat["fused_prolong"] and not flexible
+    launch_bytes = (perfmodel.smooth0_launch_bytes(n, 8, fused_update=feat["fused_update"], dot_q=dot_q,
+                                                   fused_prolong=fpro)
                     if a.precision == "fp64" else
                     perfmodel.smooth0_launch_bytes_hybrid(n, fused_update=feat["fused_update"], dot_q=dot_q))
     avg_ms = float(t_s.mean())
@@ -177,7 +179,8 @@ def main():
 
     solves = a.steps / elapsed
     it_bytes = perfmodel.pcg_iteration_bytes(n, G.levels, e, nu_coarse=p.nu_coarse, flexible=flexible,
-                                             fused_update=feat["fused_update"], fused_dots=feat["fused_dots"])
+                                             fused_update=feat["fused_update"], fused_dots=feat["fused_dots"],
+                                             fused_prolong=fpro)
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC,
@@ -203,9 +206,11 @@ def main():
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "true_rel_residual": st.true_r_norm / st.b_norm,
         "roofline": {"bound": "hbm", "kernel": "finest-level line relaxation, " + (
-                         "k_smooth_seg first sweep, k_smooth_tile, k_smooth_tile_dot x2, FP64"
+                         ("k_smooth_seg_upd, k_smooth_tile_upd, k_smooth_tile_pro, k_smooth_tile_dot3, FP64"
+                          if fpro else "k_smooth_seg(_upd), k_smooth_tile(_upd), k_smooth_tile_dot x2, FP64")
                          if a.precision == "fp64" else "FP32 pre / FP64 post sweeps") +
-                     (" (residual update fused into the first pair)" if feat["fused_update"] else ""),
+                     (" (residual update fused into the first pair)" if feat["fused_update"] else "") +
+                     (" (finest prolongation fused into the first post sweep)" if fpro else ""),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(a.precision),
                      "avg_launch_us": avg_ms * 1e3, "launches": cnt,

@@ -127,9 +127,11 @@ int ell_grid_levels(const ell_grid *g);
  * first stage neighbours in LDS tiles), ELL_FEAT_FUSED_DOTS (the CG inner
  * products ride on the last two post-smoothing half-sweeps),
  * ELL_FEAT_FUSED_UPDATE (the residual update r -= alpha q rides on the first
- * pre-smoothing pair).  They change where bytes move, not what is computed;
+ * pre-smoothing pair), ELL_FEAT_FUSED_PROLONG (the finest prolongation rides
+ * on the first post-smoothing sweep, for solves with the printed beta).  They
+ * change where bytes move, not what is computed;
  * a benchmark's byte model reads them.  Returns ELL_OK or a negative error. */
-enum { ELL_FEAT_TILED_SMOOTH = 1, ELL_FEAT_FUSED_DOTS = 2, ELL_FEAT_FUSED_UPDATE = 4 };
+enum { ELL_FEAT_TILED_SMOOTH = 1, ELL_FEAT_FUSED_DOTS = 2, ELL_FEAT_FUSED_UPDATE = 4, ELL_FEAT_FUSED_PROLONG = 8 };
 int ell_grid_features(const ell_grid *g, int32_t *mask);
 
 /* y = A x: the operator of eq. ModelEquation integrated over every cell
@@ -235,7 +237,13 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * level's first pre-smoothing pair of a CG preconditioner application also
  * carry the residual update r -= alpha q and the partial sums of ||r||^2 (the
  * convergence test runs between that pair and the rest of the V-cycle), in
- * place of a separate pass over r and q; 0 always uses the separate pass. */
+ * place of a separate pass over r and q; 0 always uses the separate pass;
+ * FUSED_PROLONG 1 (default) lets the finest level's first post-smoothing sweep
+ * of an FP64 V-cycle (one post-smoothing sweep, bilinear prolongation, fused
+ * dots taking <r, z> alone, i.e. the printed beta) apply the coarse correction
+ * to the colour-0 values it reads instead of a prolongation pass (the
+ * colour-0 sweep that follows overwrites them), the colour-0 sweep then forming
+ * <r, z> of both colours; 0 always runs the prolongation pass. */
 enum {
   ELL_TUNE_PLANE_PAD = 0,
   ELL_TUNE_COLOUR_PAD = 1,
@@ -244,7 +252,8 @@ enum {
   ELL_TUNE_BATCH_GRAPH = 4,
   ELL_TUNE_SMOOTH_TILE = 5,
   ELL_TUNE_FUSED_DOT = 6,
-  ELL_TUNE_FUSED_UPDATE = 7
+  ELL_TUNE_FUSED_UPDATE = 7,
+  ELL_TUNE_FUSED_PROLONG = 8
 };
 int ell_set_tuning(int key, int value);
 

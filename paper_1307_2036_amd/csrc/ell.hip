@@ -164,6 +164,7 @@ struct ell_grid {
   int smooth_tile = 0;                  // FP64 half-sweeps use the LDS-tiled kernel
   int fused_dot = 0;                    // the last post-smoothing half-sweeps form the CG dots
   int fused_update = 0;                 // the first pre-smoothing pair updates the CG residual
+  int fused_prolong = 0;                // the first post-smoothing sweep applies the finest correction
   double *partial = nullptr;
   long long partial_cap = 0;
   PcgState *st = nullptr;
@@ -202,6 +203,7 @@ int g_batch_graph = 1;  // 1: batch engines replay each grouped step from a capt
 int g_smooth_tile = 1;  // 1: FP64 half-sweeps stage the other colour in LDS tiles
 int g_fused_dot = 1;    // 1: the last post-smoothing half-sweeps form the CG dots
 int g_fused_update = 1; // 1: the first pre-smoothing pair updates the CG residual
+int g_fused_prolong = 1;  // 1: the first post-smoothing sweep applies the finest correction
 
 // Smoother segments per column: enough lanes to occupy the chip on small
 // levels, four (the register-resident optimum) on large ones; the finest
@@ -614,6 +616,36 @@ int launch_smooth_upd(ell_grid *g, int c, double *r, R *u, const R *tab, int pba
   return check_launch("k_smooth_seg_upd");
 }
 
+// The finest level's post-smoothing (nu_post = 1) of an FP64 V-cycle whose
+// CG dots are fused and take <r, z> alone: the colour-1 sweep applies the
+// coarse correction to the colour-0 values it reads (no prolongation pass),
+// the colour-0 sweep forms <r, z> of both colours into the first tile-count
+// partial slots.  The caller has checked pro_path.
+template <int SEG, int NSEG>
+void pro_pair_k(ell_grid *g, const double *b, double *u, const int *done, hipStream_t s) {
+  const Geo &F = g->lev[0].geo, &C = g->lev[1].geo;
+  const double *tab = (const double *)g->lev[0].tab;
+  const int nbt = blocks8((long long)smooth_tiles(F) * kBlock);
+  const long long cs = F.cs;
+  {
+    ProfScope ps(g, ELL_K_SMOOTH0, s);
+    k_smooth_tile_pro<SEG, NSEG><<<nbt, NSEG * 64, 0, s>>>(F, C, tab, b + cs, u, u + cs,
+                                                           (const double *)g->lev[1].u, done);
+  }
+  ProfScope ps(g, ELL_K_SMOOTH0, s);
+  k_smooth_tile_dot3<SEG, NSEG><<<nbt, NSEG * 64, 0, s>>>(F, tab, b, u + cs, u, done, g->partial, b + cs);
+}
+
+int pro_pair(ell_grid *g, const double *b, double *u, const int *done, hipStream_t s) {
+  const Geo &F = g->lev[0].geo;
+  const int Ls = seg_len(F.nz, F.nseg);
+  if (F.nseg == 16) pro_pair_k<8, 16>(g, b, u, done, s);
+  else if (F.nseg == 8) pro_pair_k<16, 8>(g, b, u, done, s);
+  else if (Ls <= 16) pro_pair_k<16, 4>(g, b, u, done, s);
+  else pro_pair_k<32, 4>(g, b, u, done, s);
+  return check_launch("k_smooth_tile_pro / k_smooth_tile_dot3");
+}
+
 // The first pre-smoothing pair with the fused residual update, then the
 // convergence test (F_CONV) that the rest of the V-cycle is predicated on.
 template <typename R>
@@ -699,6 +731,8 @@ int launch_fill(R *p, long long n, hipStream_t s) {
 // red.  With rho = 1 two exact shortcuts apply: after a black sweep the black
 // residual is zero (only red children are restricted) and a black sweep
 // ignores the old black values (the correction is added to red columns only).
+bool pro_path(const ell_grid *g, int dot);
+
 // dot > 0 (top = 0, FP64, the finest level tiled): the last two post-smoothing
 // half-sweeps also form the CG dots (launch_smooth_dot).
 template <typename R>
@@ -746,6 +780,12 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
     }
   }
   for (int l = L - 2; l >= top; --l) {
+    if constexpr (std::is_same<R, double>::value) {
+      if (l == 0 && pro_path(g, dot)) {  // prolongation inside the post-smoothing pair
+        CHK(pro_pair(g, B(0), U(0), done, s));
+        continue;
+      }
+    }
     CHK(launch_prolong<R>(g, l, (const R *)g->lev[l + 1].u, U(l), rho1 && g->d.nu_post > 0, done, s));
     for (int it = 0; it < g->d.nu_post; ++it) {
       if constexpr (std::is_same<R, double>::value) {
@@ -860,6 +900,20 @@ bool fused_dot_path(const ell_grid *g) {
   else return base && hybrid_ok(g);
 }
 
+// The finest prolongation rides on the first post-smoothing sweep (pro_pair):
+// FP64 V-cycle with fused dots taking <r, z> alone (dot = 1), one
+// post-smoothing sweep, bilinear prolongation.
+bool pro_path(const ell_grid *g, int dot) {
+  return dot == 1 && g->fused_prolong && g->prec == ELL_FP64 && fused_dot_path<double>(g) &&
+         g->d.nu_post == 1 && g->d.prolong == 0;
+}
+
+// Partial slots of the fused dots.
+int dot_slots(const ell_grid *g, int dot) {
+  const int t = smooth_tiles(g->lev[0].geo);
+  return pro_path(g, dot) ? t : 2 * t;
+}
+
 int launch_apply64(ell_grid *g, const double *x, double *y, bool dot, const int *done, hipStream_t s) {
   const Geo &G = g->lev[0].geo;
   const int nb = seg_blocks(2LL * G.H);
@@ -961,7 +1015,7 @@ int pcg_begin(ell_grid *g, const double *f, const double *u, const ell_solve_opt
   CHK(check_launch("k_finalize"));
   if (fused_dot_path<R>(g)) {  // kappa_0 = <r0, z0> from the last half-sweeps
     CHK(precondition<R>(g, done, s, 1));
-    return finalize(g, 2 * smooth_tiles(G), 1, F_KAPPA, s);
+    return finalize(g, dot_slots(g, 1), 1, F_KAPPA, s);
   }
   CHK(precondition<R>(g, done, s));
   k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zvec<Z>(g), (const double2 *)g->q, n2, g->st,
@@ -1019,7 +1073,7 @@ int pcg_step(ell_grid *g, int K, hipStream_t s) {
   if (fused_dot_path<R>(g)) {  // <r, z> (and <z, q>) from the last half-sweeps
     const int nq = g->st_host->flexible ? 2 : 1;
     CHK(precondition<R>(g, done, s, nq, upd));
-    return finalize(g, 2 * smooth_tiles(g->lev[0].geo), nq, F_BETA, s);
+    return finalize(g, dot_slots(g, nq), nq, F_BETA, s);
   }
   CHK(precondition<R>(g, done, s, 0, upd));
   k_dots<Z><<<fb, kBlock, 0, s>>>((const double2 *)g->r, zvec<Z>(g), (const double2 *)g->q, n2, g->st,
@@ -1224,6 +1278,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->smooth_tile = g_smooth_tile;
   g->fused_dot = g_fused_dot;
   g->fused_update = g_fused_update;
+  g->fused_prolong = g_fused_prolong;
   g->batch_layout = batch_layout;
   g->lev.resize(L);
   auto bail = [&](int rc) {
@@ -1332,6 +1387,7 @@ int ell_grid_features(const ell_grid *g, int32_t *mask) {
     if (tile_ok(g, 0)) m |= ELL_FEAT_TILED_SMOOTH;
     if (fused_dot_path<double>(g)) m |= ELL_FEAT_FUSED_DOTS;
     if (fused_update_path<double>(g)) m |= ELL_FEAT_FUSED_UPDATE;
+    if (pro_path(g, 1)) m |= ELL_FEAT_FUSED_PROLONG;
   } else if (hybrid_ok(g)) {  // the FP64 post-smoothing of the mixed-precision V-cycle
     if (tile_ok(g, 0)) m |= ELL_FEAT_TILED_SMOOTH;
     if (fused_dot_path<float>(g)) m |= ELL_FEAT_FUSED_DOTS;
@@ -1678,6 +1734,10 @@ int ell_set_tuning(int key, int value) {
     case ELL_TUNE_FUSED_UPDATE:
       if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "the fused residual update is 0 or 1");
       g_fused_update = value;
+      return ELL_OK;
+    case ELL_TUNE_FUSED_PROLONG:
+      if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "the fused prolongation is 0 or 1");
+      g_fused_prolong = value;
       return ELL_OK;
     default: return fail(ELL_ERR_INVALID, "unknown tuning key %d", key);
   }

@@ -506,7 +506,19 @@ constexpr int kSTX = 32;  // m-columns per tile
 // UPD (the first pre-smoothing pair, as in smooth_seg_body): b is advanced to
 // b - alpha q and written back to rwc (this colour's CG residual), and the
 // block's partial sum of its squares goes to partial[pbase + lb].
-template <int SEG, int NSEG, bool FINE, int DOT = 0, bool UPD = false, int CH = 8>
+// PRO (colour 1, the first post-smoothing sweep, rho = 1): the colour-0
+// values it reads are the V-cycle's values before the coarse correction (uo)
+// and each staged one is corrected on the fly with the bilinear interpolation
+// of the coarser level's correction uc (coarse geometry C), in the order of
+// the column prolongation, so the correction is never written: the colour-0
+// sweep that follows overwrites colour 0 without reading it.  The 3 x 36
+// coarse values a wavefront's tile needs per level (rows J0-1 .. J0+1,
+// columns mx0-2 .. mx0+33) are staged in LDS with two loads.
+// DOT = 3 (colour 0, the last sweep, classic beta, after a PRO sweep): <b, w>
+// of the written columns plus <r1, z1> over the colour-1 cells of the tile's
+// rows, z1 from the staged values and r1 loaded (r1c: colour 1 of r), into
+// partial[pbase + lb].
+template <int SEG, int NSEG, bool FINE, int DOT = 0, bool UPD = false, bool PRO = false, int CH = 8>
 __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict__ tab, int c,
                                                  const double *__restrict__ bo,
                                                  const double *__restrict__ uo,
@@ -515,12 +527,16 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
                                                  double *__restrict__ partial = nullptr, int pbase = 0,
                                                  const double *__restrict__ qc = nullptr,
                                                  double *__restrict__ rwc = nullptr,
-                                                 const PcgState *__restrict__ st = nullptr) {
-  constexpr int NQ = DOT ? DOT : (UPD ? 1 : 0);  // partial sums per block
+                                                 const PcgState *__restrict__ st = nullptr,
+                                                 const Geo *Cg = nullptr,
+                                                 const double *__restrict__ uc = nullptr,
+                                                 const double *__restrict__ r1c = nullptr) {
+  constexpr int NQ = DOT ? (DOT == 3 ? 1 : DOT) : (UPD ? 1 : 0);  // partial sums per block
+  constexpr int SJ = DOT == 3 ? 1 : DOT;                         // seg_join_store's products
   if constexpr (UPD) {
     // no update pending (a batched grid's first step): the plain sweep of b = r
     if (st->pending == 0) {
-      smooth_tile_body<SEG, NSEG, FINE, 0, false, CH>(L, tab, c, bo, uo, own, done, lb);
+      smooth_tile_body<SEG, NSEG, FINE, 0, false, false, CH>(L, tab, c, bo, uo, own, done, lb);
       return;
     }
   }
@@ -528,6 +544,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   __shared__ __align__(16) double ot[NSEG][4][36];
   __shared__ double bsh[DOT ? NSEG : 1][DOT ? SEG : 1][64];
   __shared__ double red[NQ ? NSEG : 1][2];
+  __shared__ double csl[PRO ? NSEG : 1][PRO ? 128 : 1];
   const int tiles_x = (L.hx2 + kSTX - 1) / kSTX;
   if (is_done(done) || lb >= tiles_x * (L.ny / 2)) return;  // whole blocks: no barrier is skipped
   const int lane = threadIdx.x & 63;
@@ -566,21 +583,68 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   const double *qg = UPD ? gp(qc) : nullptr;
   double alpha = 0.0, rsq = 0.0;
   if constexpr (UPD) alpha = st->alpha;
+  // PRO: this lane's two coarse staging values (slot v = row * 36 + q for v <
+  // 108 and q <= nxm + 3, else an in-bounds dummy) and its corrections' rows
+  long long co0 = 0, co1 = 0, HC = 0;
+  const double *ucg = nullptr;
+  double *csf = nullptr;
+  int pa = 0, pb = 0, pd = 0, ea = 0, eb = 0, ed = 0;
+  if constexpr (PRO) {
+    const Geo C = *Cg;
+    const int J0 = j0 >> 1;
+    auto coff = [&](int v) -> long long {
+      const int row = v / 36, q = v - row * 36;
+      const bool need = v < 108 && q <= nxm + 3;
+      const int I = wrapi(mx0 - 2 + (need ? q : 0), C.nx);
+      const int J = wrapi(J0 - 1 + (need ? row : 0), C.ny);
+      return (long long)((I + J) & 1) * C.cs + col_m(C, I, J);
+    };
+    co0 = coff(lane);
+    co1 = coff(64 + lane);
+    HC = C.S;
+    ucg = gp(uc);
+    csf = csl[sg];
+    // staged row q -> coarse rows of its parent (pa) and y-neighbour (pb),
+    // x-neighbour direction pd (fine row odd: +1)
+    pa = (rr + 1) >> 1;
+    pb = (rr & 1) ? pa - 1 : pa + 1;
+    pd = (rr & 1) ? -1 : 1;
+    ea = (er + 1) >> 1;
+    eb = (er & 1) ? ea - 1 : ea + 1;
+    ed = (er & 1) ? -1 : 1;
+  }
+  // the bilinear correction of the staged colour-0 value at index idx of a
+  // staged row (coarse rows a, b, direction d), in the column kernel's order
+  auto corr = [&](int a, int b, int d, int idx) -> double {
+    double e = 9.0 / 16.0 * csf[a * 36 + idx];
+    e = e + 3.0 / 16.0 * csf[a * 36 + idx + d];
+    e = e + 3.0 / 16.0 * csf[b * 36 + idx];
+    e = e + 1.0 / 16.0 * csf[b * 36 + idx + d];
+    return e;
+  };
+  const double *r1g = DOT == 3 ? gp(r1c) : nullptr;
+  double d1 = 0.0;  // DOT 3: <r1, z1> of this lane's colour-1 cell
 
   double y[SEG];
   double prev = 0.0;
 #pragma unroll
   for (int c0 = 0; c0 < SEG; c0 += CH) {
     if (c0 < len) {
-      double bv[CH], ev[CH], qv[UPD ? CH : 1];
+      double bv[CH], ev[CH], qv[UPD ? CH : 1], cv0[PRO ? CH : 1], cv1[PRO ? CH : 1], r1v[DOT == 3 ? CH : 1];
       nt_d2 tv[CH];
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
-        const long long o = (long long)min(k0 + c0 + t, k1 - 1) * H;
+        const int kc = min(k0 + c0 + t, k1 - 1);
+        const long long o = (long long)kc * H;
         bv[t] = ld_s<FINE>(&bg[o + mo]);
         if constexpr (UPD) qv[t] = __builtin_nontemporal_load(&qg[o + mo]);
         tv[t] = *(const nt_d2 *)&ug[o + po];
         ev[t] = lane < 2 ? ug[o + eo] : 0.0;
+        if constexpr (PRO) {
+          cv0[t] = ucg[kc * HC + co0];
+          cv1[t] = ucg[kc * HC + co1];
+        }
+        if constexpr (DOT == 3) r1v[t] = __builtin_nontemporal_load(&r1g[o + mo]);
       }
       // Every level of the chunk runs without a branch (levels past the
       // segment's end repeat its last level and are discarded), so no load is
@@ -592,12 +656,27 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
         // empty asm keeps the compiler from moving them across each other).
         // Lanes past the tile's last pair write pads or the right end's place,
         // which the end values written next overwrite.
-        *(nt_d2 *)&slot[rr][2 + 2 * pp] = tv[t];
+        nt_d2 pr = tv[t];
+        double evk = ev[t];
+        if constexpr (PRO) {
+          csf[lane] = cv0[t];
+          csf[64 + lane] = cv1[t];
+          __asm__ volatile("" ::: "memory");
+          pr.x = pr.x + corr(pa, pb, pd, 2 + 2 * pp);
+          pr.y = pr.y + corr(pa, pb, pd, 3 + 2 * pp);
+          evk = evk + corr(ea, eb, ed, ei);
+          __asm__ volatile("" ::: "memory");
+        }
+        *(nt_d2 *)&slot[rr][2 + 2 * pp] = pr;
         __asm__ volatile("" ::: "memory");
-        if (lane < 2) slot[er][ei] = ev[t];
+        if (lane < 2) slot[er][ei] = evk;
         __asm__ volatile("" ::: "memory");
         const double w = slot[r + 1][x + 1 + par], e = slot[r + 1][x + 2 + par];
         const double so = slot[r][x + 2], no = slot[r + 2][x + 2];
+        if constexpr (DOT == 3) {
+          const double z1 = slot[r + 1][x + 2];  // the colour-1 cell (j, mx0 + x)
+          d1 += (valid && c0 + t < len) ? r1v[t] * z1 : 0.0;
+        }
         __asm__ volatile("" ::: "memory");
         double g = bv[t];
         if constexpr (UPD) {
@@ -618,10 +697,10 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
       }
     }
   }
-  double dsum[2] = {rsq, 0.0};
-  seg_join_store<double, false, true, FINE, SEG, NSEG, DOT>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf,
-                                                            qb, valid, own + mo, H, 1.0, &bsh[DOT ? sg : 0][0][0],
-                                                            DOT == 2 ? qc + mo : nullptr, dsum);
+  double dsum[2] = {UPD ? rsq : d1, 0.0};
+  seg_join_store<double, false, true, FINE, SEG, NSEG, SJ>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf,
+                                                           qb, valid, own + mo, H, 1.0, &bsh[DOT ? sg : 0][0][0],
+                                                           DOT == 2 ? qc + mo : nullptr, dsum);
   if constexpr (NQ > 0) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -660,6 +739,32 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_upd(Geo L, const doub
                                                                double *__restrict__ partial, int pbase) {
   smooth_tile_body<SEG, NSEG, true, 0, true>(L, tab, c, rc, uo, own, &st->done, logical_block(), partial, pbase, qc,
                                              rc, st);
+}
+
+// The finest level's first post-smoothing sweep (colour 1) with the coarse
+// correction of colour 0 applied on the fly (no separate prolongation).
+template <int SEG, int NSEG>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_pro(Geo L, Geo C, const double *__restrict__ tab,
+                                                               const double *__restrict__ bo,
+                                                               const double *__restrict__ uo,
+                                                               double *__restrict__ own,
+                                                               const double *__restrict__ uc,
+                                                               const int *__restrict__ done) {
+  smooth_tile_body<SEG, NSEG, true, 0, false, true, 4>(L, tab, 1, bo, uo, own, done, logical_block(), nullptr, 0,
+                                                       nullptr, nullptr, nullptr, &C, uc);
+}
+
+// The last sweep (colour 0) after it, with <r, z> of both colours.
+template <int SEG, int NSEG>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_dot3(Geo L, const double *__restrict__ tab,
+                                                                const double *__restrict__ bo,
+                                                                const double *__restrict__ uo,
+                                                                double *__restrict__ own,
+                                                                const int *__restrict__ done,
+                                                                double *__restrict__ partial,
+                                                                const double *__restrict__ r1c) {
+  smooth_tile_body<SEG, NSEG, true, 3, false, false, 4>(L, tab, 0, bo, uo, own, done, logical_block(), partial, 0,
+                                                        nullptr, nullptr, nullptr, nullptr, nullptr, r1c);
 }
 
 // The finest level's tiled half-sweep with the fused CG inner products.

@@ -166,7 +166,8 @@ ELL_TUNE_BATCH_GRAPH = 4
 ELL_TUNE_SMOOTH_TILE = 5
 ELL_TUNE_FUSED_DOT = 6
 ELL_TUNE_FUSED_UPDATE = 7
-ELL_FEAT_TILED_SMOOTH, ELL_FEAT_FUSED_DOTS, ELL_FEAT_FUSED_UPDATE = 1, 2, 4
+ELL_TUNE_FUSED_PROLONG = 8
+ELL_FEAT_TILED_SMOOTH, ELL_FEAT_FUSED_DOTS, ELL_FEAT_FUSED_UPDATE, ELL_FEAT_FUSED_PROLONG = 1, 2, 4, 8
 
 
 def set_tuning(key: int, value: int) -> None:
@@ -247,7 +248,8 @@ class Grid:
         _check(L.ell_grid_features(h, ctypes.byref(m)))
         self.features = {"tiled_smooth": bool(m.value & ELL_FEAT_TILED_SMOOTH),
                          "fused_dots": bool(m.value & ELL_FEAT_FUSED_DOTS),
-                         "fused_update": bool(m.value & ELL_FEAT_FUSED_UPDATE)}
+                         "fused_update": bool(m.value & ELL_FEAT_FUSED_UPDATE),
+                         "fused_prolong": bool(m.value & ELL_FEAT_FUSED_PROLONG)}
 
     @classmethod
     def from_problem(cls, p, precision="fp64", **over):

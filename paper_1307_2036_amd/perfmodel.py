@@ -74,10 +74,13 @@ def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1) -> float:
 
 
 def pcg_iteration_bytes(n0: int, levels: int, e: int, nu_coarse=1, flexible=True, fused_update=False,
-                        fused_dots=False, **mg) -> float:
+                        fused_dots=False, fused_prolong=False, **mg) -> float:
+    """fused_prolong: the finest prolongation (10 B/unknown) rides on the first
+    post-smoothing sweep, which reads the coarse correction (2 B/unknown), and
+    the last sweep reads colour 1 of r for <r, z> (4 B/unknown)."""
     cg = cg_bytes(n0, flexible, fused_update, fused_dots)
     if e == 8:
-        return cg + vcycle_bytes(n0, levels, 8, nu_coarse=nu_coarse, **mg)
+        return cg + vcycle_bytes(n0, levels, 8, nu_coarse=nu_coarse, **mg) - (4 * n0 if fused_prolong else 0)
     return cg + hybrid_vcycle_bytes(n0, levels, nu_coarse)
 
 
@@ -90,13 +93,15 @@ def smooth0_launch_bytes_hybrid(n0: int, fused_update: bool = False, dot_q: bool
 
 
 def smooth0_launch_bytes(n0: int, e: int, nu_pre=1, nu_post=1, fused_update: bool = False,
-                         dot_q: bool = False) -> float:
+                         dot_q: bool = False, fused_prolong: bool = False) -> float:
     """Average algorithmic bytes of one finest-level half-sweep launch in a
     V-cycle (the first pre-smoothing sweep starts from u = 0).  The fused
     residual update adds the q read and the r write to the first pre-smoothing
     pair (8 + 8 B per unknown of each colour), the fused <z,q> the q read to the
-    last post-smoothing pair."""
+    last post-smoothing pair, the fused prolongation the coarse correction
+    (2 B per fine unknown) to the first post-smoothing sweep and colour 1 of r
+    (4 B) to the last."""
     launches = 2 * nu_pre + 2 * nu_post
     total = smooth_bytes(n0, e, True) + (launches - 1) * smooth_bytes(n0, e, False)
-    total += (16 * n0 if fused_update else 0) + (8 * n0 if dot_q else 0)
+    total += (16 * n0 if fused_update else 0) + (8 * n0 if dot_q else 0) + (6 * n0 if fused_prolong else 0)
     return total / launches

@@ -403,6 +403,42 @@ def test_fused_update_equals_separate_pass(ell, orc, nx, ny, nz, levels, precisi
         check_solve(orc, g, p.f, u1, s1, 1e-8, flexible=flexible)
 
 
+@pytest.mark.parametrize("nx,ny,nz,levels", [(64, 16, 32, 3), (68, 12, 100, 2), (136, 8, 40, 2),
+                                           (64, 64, 48, 4)])
+def test_fused_prolongation_equals_prolongation_pass(ell, orc, nx, ny, nz, levels):
+    """With the printed beta, the finest coarse correction applied inside the
+    first post-smoothing sweep (and <r, z> of both colours formed by the last)
+    gives the iterates of the prolongation pass: the same iteration count,
+    solutions within 1e-10, the same state at an iteration limit, and the
+    oracle's solution.  (136, 8) has partial tiles, nz = 100 eight ragged
+    k-segments."""
+    h = 1.0 / nx
+    dz = I.dz_quadratic(nz, 1.0 / 50.0)
+    p = I.Problem("fused_prolong", nx, ny, nz, h, h, dz, I.lambda2_perturbed(h, dz, 0.3, 26), 1e-2,
+                  I.rhs_normal(nx, ny, dz, 25), n_levels=levels)
+    res = []
+    for fused in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_FUSED_PROLONG, fused)
+        try:
+            G = ell.Grid.from_problem(p)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_FUSED_PROLONG, 1)
+        assert G.features["fused_prolong"] == bool(fused)
+        u, st = G.pcg_solve(dev(p.f), rtol=1e-8, flexible=False)
+        assert st.status == 0
+        ul, stl = G.pcg_solve(dev(p.f), rtol=1e-14, maxiter=3, flexible=False)
+        assert stl.status == ell.ELL_NOT_CONVERGED and stl.iters == 3
+        res.append((host(u), st, host(ul), stl))
+    (u1, s1, l1, t1), (u0, s0, l0, t0) = res
+    assert s1.iters == s0.iters
+    assert rel(u1, u0) <= 1e-10 and rel(l1, l0) <= 1e-10
+    # the recurrence residual after 3 steps is 0.07 of ||r0|| on the slowest
+    # case: iterates equal to ~1e-11 move it by up to ~1e-9 of itself
+    assert abs(t1.r_norm / t0.r_norm - 1) <= 1e-8
+    g = orc.Grid.from_problem(p)
+    check_solve(orc, g, p.f, u1, s1, 1e-8, flexible=False)
+
+
 def test_solve_edge_cases(ell, orc):
     p = I.graded_problem("edge", 32, 8, 1e-2, 1, 2)
     G = ell.Grid.from_problem(p)
