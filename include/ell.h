@@ -128,10 +128,18 @@ int ell_grid_levels(const ell_grid *g);
  * products ride on the last two post-smoothing half-sweeps),
  * ELL_FEAT_FUSED_UPDATE (the residual update r -= alpha q rides on the first
  * pre-smoothing pair), ELL_FEAT_FUSED_PROLONG (the finest prolongation rides
- * on the first post-smoothing sweep, for solves with the printed beta).  They
- * change where bytes move, not what is computed;
+ * on the first post-smoothing sweep, for solves with the printed beta),
+ * ELL_FEAT_TILED_ENDS (a solve's start, r = V f - A u0, and end, the final
+ * update and true residual, run on LDS tiles).  They change where bytes move,
+ * not what is computed;
  * a benchmark's byte model reads them.  Returns ELL_OK or a negative error. */
-enum { ELL_FEAT_TILED_SMOOTH = 1, ELL_FEAT_FUSED_DOTS = 2, ELL_FEAT_FUSED_UPDATE = 4, ELL_FEAT_FUSED_PROLONG = 8 };
+enum {
+  ELL_FEAT_TILED_SMOOTH = 1,
+  ELL_FEAT_FUSED_DOTS = 2,
+  ELL_FEAT_FUSED_UPDATE = 4,
+  ELL_FEAT_FUSED_PROLONG = 8,
+  ELL_FEAT_TILED_ENDS = 16
+};
 int ell_grid_features(const ell_grid *g, int32_t *mask);
 
 /* y = A x: the operator of eq. ModelEquation integrated over every cell
@@ -243,7 +251,12 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * dots taking <r, z> alone, i.e. the printed beta) apply the coarse correction
  * to the colour-0 values it reads instead of a prolongation pass (the
  * colour-0 sweep that follows overwrites them), the colour-0 sweep then forming
- * <r, z> of both colours; 0 always runs the prolongation pass. */
+ * <r, z> of both colours; 0 always runs the prolongation pass; TILED_ENDS 1
+ * (default) runs the start of a solve (us = u0, r = V f - A u0) and its end (u
+ * = us + alpha p written plane-major, the true residual) on the LDS tiles of
+ * the operator step for grids created afterwards with nx, ny > 1, 0 on the
+ * column kernels (u and r the same bitwise, the norms up to summation
+ * order). */
 enum {
   ELL_TUNE_PLANE_PAD = 0,
   ELL_TUNE_COLOUR_PAD = 1,
@@ -253,7 +266,8 @@ enum {
   ELL_TUNE_SMOOTH_TILE = 5,
   ELL_TUNE_FUSED_DOT = 6,
   ELL_TUNE_FUSED_UPDATE = 7,
-  ELL_TUNE_FUSED_PROLONG = 8
+  ELL_TUNE_FUSED_PROLONG = 8,
+  ELL_TUNE_TILED_ENDS = 9
 };
 int ell_set_tuning(int key, int value);
 

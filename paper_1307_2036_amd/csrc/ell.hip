@@ -165,6 +165,7 @@ struct ell_grid {
   int fused_dot = 0;                    // the last post-smoothing half-sweeps form the CG dots
   int fused_update = 0;                 // the first pre-smoothing pair updates the CG residual
   int fused_prolong = 0;                // the first post-smoothing sweep applies the finest correction
+  int tiled_ends = 0;                   // a solve's start and end run on the operator step's LDS tiles
   double *partial = nullptr;
   long long partial_cap = 0;
   PcgState *st = nullptr;
@@ -204,6 +205,7 @@ int g_smooth_tile = 1;  // 1: FP64 half-sweeps stage the other colour in LDS til
 int g_fused_dot = 1;    // 1: the last post-smoothing half-sweeps form the CG dots
 int g_fused_update = 1; // 1: the first pre-smoothing pair updates the CG residual
 int g_fused_prolong = 1;  // 1: the first post-smoothing sweep applies the finest correction
+int g_tiled_ends = 1;     // 1: a solve's start and end on LDS tiles where both horizontal directions exist
 
 // Smoother segments per column: enough lanes to occupy the chip on small
 // levels, four (the register-resident optimum) on large ones; the finest
@@ -995,9 +997,28 @@ int stats_from_state(const PcgState &h, ell_solve_stats *out) {
   return status == 0 ? ELL_OK : ELL_NOT_CONVERGED;
 }
 
+// The k-segments and blocks of the tiled start / end of a solve (the operator
+// step's tiles and segments; at most 4 segments, so the partial-sum buffer
+// holds their two sums per block).
+int ends_nseg(const ell_grid *g) { return g->apply_tile ? g->apply_nseg : apply_segments(g->lev[0].geo.nz); }
+int ends_blocks(const ell_grid *g) { return blocks8(tile_blocks(g->lev[0].geo, ends_nseg(g)) * kBlock); }
+
+// us = u0 and r = V f - A u0 with the F_INIT partial sums; *nblk: the blocks
+// whose two sums the reduction takes.
+int launch_begin(ell_grid *g, const double *f, const double *u, int *nblk, hipStream_t s) {
+  const Geo &G = g->lev[0].geo;
+  if (g->tiled_ends) {
+    *nblk = ends_blocks(g);
+    k_begin_tile<<<*nblk, kBlock, 0, s>>>(G, ends_nseg(g), g->tab64_0, g->vol0, f, u, g->us, g->r, g->partial);
+    return check_launch("k_begin_tile");
+  }
+  *nblk = seg_blocks((long long)G.nx * G.ny);
+  k_begin<<<*nblk, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, u, g->us, g->r, g->partial);
+  return check_launch("k_begin");
+}
+
 template <typename R, typename Z>
 int pcg_begin(ell_grid *g, const double *f, const double *u, const ell_solve_opts &o, hipStream_t s) {
-  const Geo &G = g->lev[0].geo;
   const long long n2 = g->n0 / 2;
   const int fb = flat_blocks(n2);
   const int *done = &g->st->done;
@@ -1008,9 +1029,8 @@ int pcg_begin(ell_grid *g, const double *f, const double *u, const ell_solve_opt
     h->flexible = o.flexible;
     HIPCHK(hipMemcpyAsync(&g->st->maxiter, &h->maxiter, 2 * sizeof(int), hipMemcpyHostToDevice, s));
   }
-  const int bb = seg_blocks((long long)G.nx * G.ny);
-  k_begin<<<bb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, u, g->us, g->r, g->partial);
-  CHK(check_launch("k_begin"));
+  int bb = 0;
+  CHK(launch_begin(g, f, u, &bb, s));
   k_finalize<<<1, kBlock, 0, s>>>(g->partial, bb, 2, g->st, F_INIT, o.rtol, o.atol, o.rel_to_rhs);
   CHK(check_launch("k_finalize"));
   if (fused_dot_path<R>(g)) {  // kappa_0 = <r0, z0> from the last half-sweeps
@@ -1089,16 +1109,14 @@ int pcg_step(ell_grid *g, int K, hipStream_t s) {
 // update takes r -= q; no dots, no scalar recurrences.
 template <typename R, typename Z>
 int mg_begin(ell_grid *g, const double *f, const double *u, const ell_solve_opts &o, hipStream_t s) {
-  const Geo &G = g->lev[0].geo;
   {
     PcgState *h = g->st_host;
     h->maxiter = o.maxiter;
     h->flexible = 0;
     HIPCHK(hipMemcpyAsync(&g->st->maxiter, &h->maxiter, 2 * sizeof(int), hipMemcpyHostToDevice, s));
   }
-  const int bb = seg_blocks((long long)G.nx * G.ny);
-  k_begin<<<bb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, u, g->us, g->r, g->partial);
-  CHK(check_launch("k_begin"));
+  int bb = 0;
+  CHK(launch_begin(g, f, u, &bb, s));
   k_finalize<<<1, kBlock, 0, s>>>(g->partial, bb, 2, g->st, F_INIT, o.rtol, o.atol, o.rel_to_rhs);
   CHK(check_launch("k_finalize"));
   k_finalize<<<1, kBlock, 0, s>>>(g->partial, 0, 0, g->st, F_UNIT, 0, 0, 0);
@@ -1126,10 +1144,18 @@ int pcg_finish(ell_grid *g, const double *f, double *u, ell_solve_stats *out, hi
   const Geo &G = g->lev[0].geo;
   const int K = g->st_host->iter;
   const int with_p = (K > 0 && g->st_host->status != -4) ? 1 : 0;
-  const int fb = seg_blocks(2LL * G.H);
-  k_finish<<<fb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, g->us, (K & 1) ? g->p2 : g->p, g->st, with_p, u,
-                                 g->partial);
-  CHK(check_launch("k_finish"));
+  int fb = 0;
+  if (g->tiled_ends) {
+    fb = ends_blocks(g);
+    k_finish_tile<<<fb, kBlock, 0, s>>>(G, ends_nseg(g), g->tab64_0, g->vol0, f, g->us, (K & 1) ? g->p2 : g->p,
+                                        g->st, with_p, u, g->partial);
+    CHK(check_launch("k_finish_tile"));
+  } else {
+    fb = seg_blocks(2LL * G.H);
+    k_finish<<<fb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, g->us, (K & 1) ? g->p2 : g->p, g->st, with_p, u,
+                                   g->partial);
+    CHK(check_launch("k_finish"));
+  }
   k_finalize<<<1, kBlock, 0, s>>>(g->partial, fb, 2, g->st, F_TRUE, 0, 0, 0);
   CHK(check_launch("k_finalize"));
   HIPCHK(hipMemcpyAsync(g->st_host, g->st, sizeof(PcgState), hipMemcpyDeviceToHost, s));
@@ -1279,6 +1305,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->fused_dot = g_fused_dot;
   g->fused_update = g_fused_update;
   g->fused_prolong = g_fused_prolong;
+  g->tiled_ends = (g_tiled_ends && desc->nx > 1 && desc->ny > 1) ? 1 : 0;
   g->batch_layout = batch_layout;
   g->lev.resize(L);
   auto bail = [&](int rc) {
@@ -1388,10 +1415,12 @@ int ell_grid_features(const ell_grid *g, int32_t *mask) {
     if (fused_dot_path<double>(g)) m |= ELL_FEAT_FUSED_DOTS;
     if (fused_update_path<double>(g)) m |= ELL_FEAT_FUSED_UPDATE;
     if (pro_path(g, 1)) m |= ELL_FEAT_FUSED_PROLONG;
+    if (g->tiled_ends) m |= ELL_FEAT_TILED_ENDS;
   } else if (hybrid_ok(g)) {  // the FP64 post-smoothing of the mixed-precision V-cycle
     if (tile_ok(g, 0)) m |= ELL_FEAT_TILED_SMOOTH;
     if (fused_dot_path<float>(g)) m |= ELL_FEAT_FUSED_DOTS;
     if (fused_update_path<float>(g)) m |= ELL_FEAT_FUSED_UPDATE;
+    if (g->tiled_ends) m |= ELL_FEAT_TILED_ENDS;
   }
   *mask = m;
   return ELL_OK;
@@ -1738,6 +1767,10 @@ int ell_set_tuning(int key, int value) {
     case ELL_TUNE_FUSED_PROLONG:
       if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "the fused prolongation is 0 or 1");
       g_fused_prolong = value;
+      return ELL_OK;
+    case ELL_TUNE_TILED_ENDS:
+      if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "tiled solve ends are 0 or 1");
+      g_tiled_ends = value;
       return ELL_OK;
     default: return fail(ELL_ERR_INVALID, "unknown tuning key %d", key);
   }

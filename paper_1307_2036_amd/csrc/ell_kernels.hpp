@@ -1897,6 +1897,180 @@ __global__ __launch_bounds__(kBlock) void k_finish(Geo L, const double *__restri
   finish_body(L, tab, vol, f, us, p, with_p ? st->alpha : 0.0, with_p, u, partial, logical_block());
 }
 
+// The start and the end of a solve on the tiles of the CG operator step (a
+// block: 32 m-columns by 16 rows, both colours, one k-segment of nseg; the
+// horizontal neighbours of each level staged in a three-level LDS ring):
+//   BEGIN:  us = u0 and r = V f - A u0 in the split layout, u0 and f
+//           plane-major (src = u0, o1 = us, o2 = r);
+//   !BEGIN: u = us + alpha p (us alone without with_p) written plane-major,
+//           with the true residual V f - A u of that u (src = us, o1 = u).
+// partial[2 lb] = sum (V f)^2, partial[2 lb + 1] = sum res^2 over the block;
+// blocks past the last segment write zeros.  Each cell's A u is formed in
+// the order of op_row, so u and the residual equal the column kernels' (the
+// block sums differ in their order).
+template <bool BEGIN>
+__device__ __forceinline__ void ends_tile_body(Geo L, int nseg, const double *__restrict__ tab,
+                                               const double *__restrict__ vol,
+                                               const double *__restrict__ f,
+                                               const double *__restrict__ src,
+                                               const double *__restrict__ p, double alpha, int with_p,
+                                               double *__restrict__ o1, double *__restrict__ o2,
+                                               double *__restrict__ partial, int lb) {
+  __shared__ double sp[3][2][kTH][kTW];
+  __shared__ double sh[4];
+  const int tiles_x = (L.hx2 + kTX - 1) / kTX;
+  const int per_seg = tile_count(L.hx2, L.ny);
+  const int sg = lb / per_seg, tt = lb - sg * per_seg;
+  const int ty = tt / tiles_x, tx = tt - ty * tiles_x;
+  const int Ls = seg_len(L.nz, nseg);
+  const int k0 = min(sg * Ls, L.nz), k1 = min(k0 + Ls, L.nz);
+  double bb = 0.0, rs = 0.0;
+  if (k1 > k0) {
+    const int t = threadIdx.x;
+    const int mx0 = tx * kTX, j0 = ty * kTY;
+    const int nxm = min(kTX, L.hx2 - mx0);
+    const int nyr = min(kTY, L.ny - j0);
+    const int x = t & 31, r0 = t >> 5;  // own cells: rows r0 and r0 + 8, both colours
+    const long long S = L.S, cs = L.cs, plane = (long long)L.nx * L.ny;
+    long long off[4], pmo[4];  // split and plane-major offsets at level 0
+    bool ok[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int c = e & 1, rr = r0 + 8 * (e >> 1), j = j0 + rr;
+      ok[e] = x < nxm && rr < nyr;
+      off[e] = (long long)c * cs + (long long)j * L.hx2 + mx0 + x;
+      pmo[e] = (long long)j * L.nx + 2 * (mx0 + x) + ((j + c) & 1);
+    }
+    // one halo cell per thread for threads 0..159 (rows below / above the
+    // tile, both colours; then the cells left / right of each row), with its
+    // offset in the layout src is read in
+    bool hok = false;
+    long long hoff = 0;
+    int hc = 0, hr = 0, hx = 0;
+    if (t < 128) {
+      const int side = t >> 6, c = (t >> 5) & 1, xx = t & 31;
+      const int j = side ? wrapi(j0 + nyr, L.ny) : wrapi(j0 - 1, L.ny);
+      hok = xx < nxm;
+      hoff = BEGIN ? (long long)j * L.nx + 2 * (mx0 + xx) + ((j + c) & 1)
+                   : (long long)c * cs + (long long)j * L.hx2 + mx0 + xx;
+      hc = c;
+      hr = side ? nyr + 1 : 0;
+      hx = xx + 1;
+    } else if (t < 160) {
+      const int side = (t - 128) >> 4, rr = (t - 128) & 15;
+      const int j = j0 + rr;
+      const int i = side ? wrapi(2 * (mx0 + nxm), L.nx) : wrapi(2 * mx0 - 1, L.nx);
+      const int c = (i + j) & 1;
+      hok = rr < nyr;
+      hoff = BEGIN ? (long long)j * L.nx + i : (long long)c * cs + (long long)j * L.hx2 + (i >> 1);
+      hc = c;
+      hr = rr + 1;
+      hx = side ? nxm + 1 : 0;
+    }
+    const long long lstride = BEGIN ? plane : S;  // level stride of src
+    auto val = [&](long long idx) -> double {
+      if constexpr (BEGIN) return src[idx];
+      else return with_p ? src[idx] + alpha * p[idx] : src[idx];
+    };
+    // level k: own values into v (and LDS buffer b when b >= 0)
+    auto level = [&](int k, int b, double *v) {
+      const long long o = (long long)k * lstride;
+      double w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) w[e] = ok[e] ? val((BEGIN ? pmo[e] : off[e]) + o) : 0.0;
+      double hv = 0.0;
+      if (b >= 0 && hok) hv = val(hoff + o);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        v[e] = w[e];
+        if (b >= 0 && ok[e]) sp[b][e & 1][r0 + 8 * (e >> 1) + 1][x + 1] = w[e];
+      }
+      if (b >= 0 && hok) sp[b][hc][hr][hx] = hv;
+    };
+    const double *__restrict__ tv = tab + TV * L.P;
+    const double *__restrict__ txv = tab + TX * L.P;
+    const double *__restrict__ tyv = tab + TY * L.P;
+    const double *__restrict__ tz = tab + TZ * L.P;
+    double pm[4], pc[4], pn[4];
+    level(k0, k0 % 3, pc);
+    if (k0 > 0) level(k0 - 1, -1, pm);
+    else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) pm[e] = pc[e];
+    }
+    for (int k = k0; k < k1; ++k) {
+      if (k + 1 < k1) level(k + 1, (k + 1) % 3, pn);
+      else if (k + 1 < L.nz) level(k + 1, -1, pn);
+      else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) pn[e] = pc[e];
+      }
+      double fv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) fv[e] = ok[e] ? __builtin_nontemporal_load(&f[(long long)k * plane + pmo[e]]) : 0.0;
+      __syncthreads();
+      const int b = k % 3;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        if (ok[e]) {
+          const int c = e & 1, rr = r0 + 8 * (e >> 1);
+          const int par = (j0 + rr + c) & 1;  // 1: the cell sits at an odd i
+          const double(*oth)[kTW] = sp[b][1 - c];
+          const double pw = oth[rr + 1][x + par];
+          const double pe = oth[rr + 1][x + 1 + par];
+          const double ps = oth[rr][x + 1];
+          const double pnn = oth[rr + 2][x + 1];
+          const double pcv = pc[e];
+          double acc = tv[k] * pcv;
+          acc = acc + txv[k] * (pcv - pw);
+          acc = acc + txv[k] * (pcv - pe);
+          acc = acc + tyv[k] * (pcv - ps);
+          acc = acc + tyv[k] * (pcv - pnn);
+          acc = acc + tz[k] * (pcv - pm[e]);
+          acc = acc + tz[k + 1] * (pcv - pn[e]);
+          const double bv = vol[k] * fv[e];
+          const double res = bv - acc;
+          if constexpr (BEGIN) {
+            __builtin_nontemporal_store(pcv, &o1[off[e] + (long long)k * S]);
+            __builtin_nontemporal_store(res, &o2[off[e] + (long long)k * S]);
+          } else {
+            __builtin_nontemporal_store(pcv, &o1[pmo[e] + (long long)k * plane]);
+          }
+          bb += bv * bv;
+          rs += res * res;
+        }
+        pm[e] = pc[e];
+        pc[e] = pn[e];
+      }
+    }
+  }
+  const double s0 = block_sum(bb, sh);
+  const double s1 = block_sum(rs, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * lb] = s0;
+    partial[2 * lb + 1] = s1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_begin_tile(Geo L, int nseg, const double *__restrict__ tab,
+                                                       const double *__restrict__ vol,
+                                                       const double *__restrict__ f,
+                                                       const double *__restrict__ u0, double *__restrict__ us,
+                                                       double *__restrict__ r, double *__restrict__ partial) {
+  ends_tile_body<true>(L, nseg, tab, vol, f, u0, nullptr, 0.0, 0, us, r, partial, logical_block());
+}
+
+__global__ __launch_bounds__(kBlock) void k_finish_tile(Geo L, int nseg, const double *__restrict__ tab,
+                                                        const double *__restrict__ vol,
+                                                        const double *__restrict__ f,
+                                                        const double *__restrict__ us,
+                                                        const double *__restrict__ p,
+                                                        const PcgState *__restrict__ st, int with_p,
+                                                        double *__restrict__ u, double *__restrict__ partial) {
+  ends_tile_body<false>(L, nseg, tab, vol, f, us, p, with_p ? st->alpha : 0.0, with_p, u, nullptr, partial,
+                        logical_block());
+}
+
 // -------------------------------------------------------------------------
 // CG vector kernels (FP64, flat over the split vectors; padding entries stay
 // zero).  Each block writes its partial sums; k_finalize reduces them in a
@@ -1969,10 +2143,26 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
     if (!st->pending) return;
     mode = F_CONV;
   }
+  // nq <= 2.  Each thread adds the blocks threadIdx.x + i kBlock in order of
+  // i; eight of them are loaded before the first is added, so the latency of
+  // the loads (written by other XCDs) is paid once per eight.
+  double v[2] = {0.0, 0.0};
+  for (int b0 = threadIdx.x; b0 < nblk; b0 += 8 * kBlock) {
+    double a[8][2];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int b = b0 + t * kBlock;
+#pragma unroll
+      for (int qi = 0; qi < 2; ++qi) a[t][qi] = (b < nblk && qi < nq) ? partial[(long long)b * nq + qi] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+#pragma unroll
+      for (int qi = 0; qi < 2; ++qi) v[qi] = b0 + t * kBlock < nblk ? v[qi] + a[t][qi] : v[qi];
+    }
+  }
   for (int qi = 0; qi < nq; ++qi) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kBlock) v += partial[(long long)b * nq + qi];
-    const double s = block_sum(v, sh);
+    const double s = block_sum(v[qi], sh);
     if (threadIdx.x == 0) tot[qi] = s;
   }
   if (threadIdx.x != 0) return;

@@ -167,7 +167,9 @@ ELL_TUNE_SMOOTH_TILE = 5
 ELL_TUNE_FUSED_DOT = 6
 ELL_TUNE_FUSED_UPDATE = 7
 ELL_TUNE_FUSED_PROLONG = 8
+ELL_TUNE_TILED_ENDS = 9
 ELL_FEAT_TILED_SMOOTH, ELL_FEAT_FUSED_DOTS, ELL_FEAT_FUSED_UPDATE, ELL_FEAT_FUSED_PROLONG = 1, 2, 4, 8
+ELL_FEAT_TILED_ENDS = 16
 
 
 def set_tuning(key: int, value: int) -> None:
@@ -249,7 +251,8 @@ class Grid:
         self.features = {"tiled_smooth": bool(m.value & ELL_FEAT_TILED_SMOOTH),
                          "fused_dots": bool(m.value & ELL_FEAT_FUSED_DOTS),
                          "fused_update": bool(m.value & ELL_FEAT_FUSED_UPDATE),
-                         "fused_prolong": bool(m.value & ELL_FEAT_FUSED_PROLONG)}
+                         "fused_prolong": bool(m.value & ELL_FEAT_FUSED_PROLONG),
+                         "tiled_ends": bool(m.value & ELL_FEAT_TILED_ENDS)}
 
     @classmethod
     def from_problem(cls, p, precision="fp64", **over):

@@ -439,6 +439,68 @@ def test_fused_prolongation_equals_prolongation_pass(ell, orc, nx, ny, nz, level
     check_solve(orc, g, p.f, u1, s1, 1e-8, flexible=False)
 
 
+@pytest.mark.parametrize("nx,ny,nz,levels", [(64, 16, 32, 3), (68, 12, 100, 2), (136, 36, 40, 2),
+                                           (2, 8, 12, 2)])
+def test_tiled_solve_ends_equal_column_kernels(ell, orc, nx, ny, nz, levels):
+    """A solve's start (us = u0, r = V f - A u0 from a nonzero u0) and end (u =
+    us + alpha p written plane-major, the true residual) on the operator
+    step's LDS tiles give the column kernels' values: the same iterates
+    bitwise at a fixed iteration count (CG and stand-alone multigrid), the
+    norms up to summation order, and the oracle's norms of r0, V f and the
+    true residual.  (68, 12) and (136, 36) have partial tiles in both
+    directions, nz = 100 four 25-level segments, (2, 8) one-cell-wide tiles
+    whose left and right neighbours are one cell."""
+    h = 1.0 / nx
+    dz = I.dz_quadratic(nz, 1.0 / 50.0)
+    p = I.Problem("tiled_ends", nx, ny, nz, h, h, dz, I.lambda2_perturbed(h, dz, 0.3, 28), 1e-2,
+                  I.rhs_normal(nx, ny, dz, 27), n_levels=levels)
+    g = orc.Grid.from_problem(p)
+    V = orc.level_coeffs(g)[0]
+    b = V[:, None, None] * p.f
+    bn = float(np.linalg.norm(b))
+    # a random start scaled so that ||A u0|| = ||V f||
+    u0 = np.random.default_rng(29).standard_normal(p.f.shape)
+    u0 *= bn / np.linalg.norm(orc.apply(g, u0))
+    res = []
+    for tiled in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_TILED_ENDS, tiled)
+        try:
+            G = ell.Grid.from_problem(p)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_TILED_ENDS, 1)
+        assert G.features["tiled_ends"] == bool(tiled)
+        ul, stl = G.pcg_solve(dev(p.f), u=dev(u0), rtol=1e-14, maxiter=3)
+        assert stl.status == ell.ELL_NOT_CONVERGED and stl.iters == 3
+        um, stm = G.mg_solve(dev(p.f), u=dev(u0), rtol=1e-14, maxiter=2)
+        assert stm.iters == 2
+        u, st = G.pcg_solve(dev(p.f), u=dev(u0), rtol=1e-8)
+        assert st.status == 0
+        res.append((host(ul), stl, host(um), stm, host(u), st))
+    (l1, t1, m1, n1, u1, s1), (l0, t0, m0, n0, u0c, s0) = res
+    np.testing.assert_array_equal(l1, l0)
+    np.testing.assert_array_equal(m1, m0)
+    assert s1.iters == s0.iters
+    assert rel(u1, u0c) <= 1e-12
+    for sa, sb in ((t1, t0), (n1, n0), (s1, s0)):
+        for k in ("r0_norm", "b_norm", "true_r_norm"):
+            assert abs(getattr(sa, k) / getattr(sb, k) - 1) <= 1e-12, (k, getattr(sa, k), getattr(sb, k))
+    assert abs(t1.b_norm / bn - 1) <= 1e-13
+
+    def agree(gpu_norm, uu):
+        # two FP64 evaluations of ||V f - A u||, each cell's terms in any
+        # order (16 eps || |A| |u| + |V f| ||) and the sum of squares in any
+        # order (n eps of the norm)
+        eps = np.finfo(float).eps
+        rn = np.linalg.norm(orc.residual(g, b, uu))
+        tol = 16 * eps * np.linalg.norm(orc.apply_abs(g, np.abs(uu)) + np.abs(b)) + b.size * eps * rn
+        return abs(gpu_norm - rn) <= tol
+
+    assert agree(t1.r0_norm, u0)
+    for uu, stt in ((l1, t1), (m1, n1), (u1, s1)):
+        assert agree(stt.true_r_norm, uu)
+    check_solve(orc, g, p.f, u1, s1, 1e-8, u0=u0)
+
+
 def test_solve_edge_cases(ell, orc):
     p = I.graded_problem("edge", 32, 8, 1e-2, 1, 2)
     G = ell.Grid.from_problem(p)
