@@ -172,7 +172,7 @@ struct ell_grid {
   PcgState *st_host = nullptr;          // pinned
   Prof prof[ELL_K_COUNT];
   std::vector<void *> allocs;
-  bool batch_layout = false;  // coarse levels use 4 k-segments (grouped launches)
+  bool batch_layout = false;  // coarse levels use 4 or 8 k-segments (grouped launches)
   void *gdev = nullptr;       // device copy of the grid descriptor (batched kernels)
   int busy = 0;               // a batch request is using the grid
 };
@@ -223,6 +223,11 @@ int smoother_segments(long long cols_per_colour, int nz, bool finest) {
   return ns;
 }
 
+int batch_coarse_segments(long long cols_per_colour, int nz) {
+  const int L8 = seg_len(nz, 8);
+  return cols_per_colour < 16384 && L8 >= 8 && L8 <= 16 ? 8 : 4;
+}
+
 Geo make_geo(int nx, int ny, int nz, bool finest = false, bool uniform_seg = false) {
   Geo G;
   G.nx = nx;
@@ -238,9 +243,10 @@ Geo make_geo(int nx, int ny, int nz, bool finest = false, bool uniform_seg = fal
   G.P = nz + 1;
   G.S = (int)(((long long)G.H + 63) / 64 * 64 + g_plane_pad);
   G.cs = (long long)nz * G.S + g_colour_pad;
-  // batch grids: the finest level as a single grid, four segments elsewhere
-  // (the grouped launches of a coarse level share one block shape)
-  G.nseg = uniform_seg && !finest ? 4 : smoother_segments(G.H, nz, finest);
+  // batch grids: the finest level as a single grid; on coarse levels the
+  // grouped launches come in two block shapes, four segments, or eight on
+  // the small (latency-bound) levels where a segment holds 8..16 levels
+  G.nseg = uniform_seg && !finest ? batch_coarse_segments(G.H, nz) : smoother_segments(G.H, nz, finest);
   return G;
 }
 

@@ -43,6 +43,7 @@ struct GridDev {
   long long n2;
   int L, nb_apply, nb_flat, prolong;
   int nb_begin, nb_finish;  // blocks of the start / end kernels (partial sums each)
+  int ends_tile, ends_nseg;  // start / end on the operator step's LDS tiles, their k-segments
   int apply_tile, apply_nseg;  // CG operator step: LDS-tiled kernel and its k-segments
   int nb_tiles;                // finest level: tiles of a tiled half-sweep (0: column kernel)
   int nb_dot;                  // partial sums of the fused CG dots (0: separate dot pass)
@@ -326,8 +327,13 @@ __global__ __launch_bounds__(kBlock) void kb_begin(const StageEnt *__restrict__ 
   const int e = find_ent(ents, nent, bg);
   const GridDev *gd = gp(ents[e].g);
   const ReqDev *rq = gp(reqs + ents[e].aux);
-  begin_body(ugeo(gd->lev[0].geo), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f), gp((const double *)rq->u),
-             gp(gd->us), gp(gd->r), gp(gd->partial), ui(bg - ents[e].block0));
+  if (ui(gd->ends_tile))
+    ends_tile_body<true>(ugeo(gd->lev[0].geo), ui(gd->ends_nseg), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f),
+                         gp((const double *)rq->u), nullptr, 0.0, 0, gp(gd->us), gp(gd->r), gp(gd->partial),
+                         ui(bg - ents[e].block0));
+  else
+    begin_body(ugeo(gd->lev[0].geo), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f), gp((const double *)rq->u),
+               gp(gd->us), gp(gd->r), gp(gd->partial), ui(bg - ents[e].block0));
 }
 
 // One block per grid: the stopping rule into the state, then the initial
@@ -357,8 +363,13 @@ __global__ __launch_bounds__(kBlock) void kb_finish(const StageEnt *__restrict__
   const int K = ui(st->iter);
   const int with_p = (K > 0 && ui(st->status) != -4) ? 1 : 0;
   const double alpha = with_p ? st->alpha : 0.0;
-  finish_body(ugeo(gd->lev[0].geo), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f), gp(gd->us),
-              gp((K & 1) ? gd->p2 : gd->p), alpha, with_p, gp(rq->u), gp(gd->partial), ui(bg - ents[e].block0));
+  if (ui(gd->ends_tile))
+    ends_tile_body<false>(ugeo(gd->lev[0].geo), ui(gd->ends_nseg), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f),
+                          gp(gd->us), gp((K & 1) ? gd->p2 : gd->p), alpha, with_p, gp(rq->u), nullptr,
+                          gp(gd->partial), ui(bg - ents[e].block0));
+  else
+    finish_body(ugeo(gd->lev[0].geo), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f), gp(gd->us),
+                gp((K & 1) ? gd->p2 : gd->p), alpha, with_p, gp(rq->u), gp(gd->partial), ui(bg - ents[e].block0));
 }
 
 // one block per grid
@@ -381,19 +392,24 @@ __global__ void kb_gather_states(const StageEnt *__restrict__ ents, int nent, Pc
 // ------------------------------------------------------------------------
 // host side
 // ------------------------------------------------------------------------
-// Blocks of the start (64 plane-major columns each) and end (64 split slots
-// each) kernels of one grid inside a grouped launch.
 // Blocks of one grid in the grouped CG operator step.
 int batch_apply_blocks(const ell_grid *g) {
   const Geo &G = g->lev[0].geo;
   return g->apply_tile ? (int)tile_blocks(G, g->apply_nseg) : stencil_blocks(2LL * G.H, 1);
 }
 
+// Blocks of the start and end kernels of one grid inside a grouped launch:
+// the operator step's tiles times the k-segments, else 64 plane-major
+// columns (start) or 64 split slots (end) per block.
 int begin_blocks(const ell_grid *g) {
   const Geo &G = g->lev[0].geo;
+  if (g->tiled_ends) return (int)tile_blocks(G, ends_nseg(g));
   return (int)(((long long)G.nx * G.ny + kSegCols - 1) / kSegCols);
 }
-int finish_blocks(const ell_grid *g) { return (int)((2LL * g->lev[0].geo.H + kSegCols - 1) / kSegCols); }
+int finish_blocks(const ell_grid *g) {
+  if (g->tiled_ends) return (int)tile_blocks(g->lev[0].geo, ends_nseg(g));
+  return (int)((2LL * g->lev[0].geo.H + kSegCols - 1) / kSegCols);
+}
 
 // The finest level's FP64 half-sweeps after the first take the tiled kernel
 // (four or eight k-segments there); with at least two levels
@@ -447,6 +463,8 @@ int grid_dev_build(ell_grid *g) {
   h.prolong = g->d.prolong;
   h.nb_begin = begin_blocks(g);
   h.nb_finish = finish_blocks(g);
+  h.ends_tile = g->tiled_ends;
+  h.ends_nseg = ends_nseg(g);
   h.nb_tiles = batch_tile(g) ? smooth_tiles(g->lev[0].geo) : 0;
   h.nb_dot = batch_fused_dot(g) ? 2 * h.nb_tiles : 0;
   h.nb_upd0 = batch_fused_update(g) ? batch_upd_blocks(g, 0) : 0;

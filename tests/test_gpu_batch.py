@@ -68,8 +68,8 @@ def test_batch_alone_equals_in_mix_and_oracle(E, orc, precision):
 
 
 def test_batch_matches_single_grid_path(E, orc):
-    """The batch (uniform 4-segment layout, grouped kernels) and the single-grid
-    path solve the same problem to the same iterates."""
+    """The batch (4- or 8-segment coarse levels, grouped kernels) and the
+    single-grid path solve the same problem to the same iterates."""
     p = problems()[1]
     B = E.Batch(4 << 30)
     g = B.grid(p)
