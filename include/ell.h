@@ -313,8 +313,9 @@ int ell_schedule_set(const ell_grid_desc *desc, const ell_schedule *s);
  * each grid with its own CG state on the device.  A worker thread admits
  * submitted requests and retires finished ones between iterations, so requests
  * that arrive while others run join at the next iteration (continuous
- * batching).  Grids of a batch are created by the batch (uniform k-segment
- * layout), count against its HBM budget and must all be FP64 or all use the
+ * batching).  Grids of a batch are created by the batch (four or eight
+ * k-segments per coarse level, so a level's grouped launch takes at most two
+ * block shapes), count against its HBM budget and must all be FP64 or all use the
  * FP32 preconditioner; they need rho = 1, nu >= 1, nx, ny > 1 on every level
  * and nz <= 256.  Requests on one grid run one after another (warm starts:
  * pass the previous solution as u). */
