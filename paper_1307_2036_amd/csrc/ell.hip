@@ -153,7 +153,8 @@ struct ell_grid {
   std::vector<Level> lev;
   long long n0 = 0;          // split elements of level 0 (2*cs)
   double *us = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr;
-  double *p2 = nullptr;                 // second search-direction buffer (ping-pong)
+  double *p2 = nullptr;                 // second and third search-direction buffers (p_K
+  double *p3 = nullptr;                 //   lives in {p, p2, p3}[K mod 3])
   void *b32 = nullptr, *z32 = nullptr;  // FP32 preconditioner: level-0 b and z
   void *ybuf = nullptr;                 // rho != 1: forward-sweep values
   double *vol0 = nullptr;               // level-0 cell volumes (FP64, nz)
@@ -370,7 +371,7 @@ size_t grid_bytes(const ell_grid_desc *d, int L) {
   const size_t es = d->precision == ELL_FP64 ? 8 : 4;
   const Geo g0 = make_geo(d->nx, d->ny, d->nz);
   const size_t n0 = 2 * (size_t)g0.cs;
-  size_t bytes = 6 * n0 * 8;                           // u, r, z, p (x2), q (FP64)
+  size_t bytes = 7 * n0 * 8;                           // u, r, z, p (x3), q (FP64)
   if (d->precision != ELL_FP64) bytes += 2 * n0 * 4;   // b32, z32
   if (d->rho != 1.0) bytes += (size_t)g0.cs * es;      // ybuf
   for (int l = 0; l < L; ++l) {
@@ -1050,29 +1051,36 @@ int pcg_begin(ell_grid *g, const double *f, const double *u, const ell_solve_opt
   return finalize(g, fb, 2, F_KAPPA, s);
 }
 
+// The search direction of iteration K (deferred_updates in the kernels'
+// header gives the schedule that frees the buffers).
+inline double *dir_buf(ell_grid *g, int K) {
+  const int i = dir_slot(K);
+  return i == 0 ? g->p : (i == 1 ? g->p2 : g->p3);
+}
+
 // Iteration K (1-based) of the loop; a no-op on the device once done is set.
-// The fused operator step of iteration K: p_new = z + beta p_old (z alone with
-// first set), q = A p_new with <p, q>, and with defer set the previous
-// iteration's u += alpha p_old.
+// The fused operator step of iteration K: p_K = z + beta p_{K-1} (z alone with
+// first set), q = A p_K with <p, q>, and with defer = 2 the solution updates
+// of iterations K - 2 and K - 1 (deferred_updates).
 template <typename Z>
 int launch_apply_dir(ell_grid *g, int K, int first, int defer, hipStream_t s) {
   const Geo &G = g->lev[0].geo;
   const int ab = apply_dir_blocks(g);
-  double *pbuf[2] = {g->p, g->p2};
+  double *pold = dir_buf(g, K - 1), *pold2 = dir_buf(g, K - 2), *pnew = dir_buf(g, K);
   ProfScope ps(g, ELL_K_APPLY, s);
   const Z *zz = (const Z *)zvec<Z>(g);
   if (g->apply_tile)
-    k_apply_dir_tile<Z><<<ab, kBlock, 0, s>>>(G, g->apply_nseg, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1],
-                                              g->q, g->us, g->st, first, defer, g->partial);
+    k_apply_dir_tile<Z><<<ab, kBlock, 0, s>>>(G, g->apply_nseg, g->tab64_0, zz, pold, pold2, pnew, g->q, g->us,
+                                              g->st, first, defer, g->partial);
   else if (g->stencil_seg == 1)
-    k_apply_dir<Z, 1><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us, g->st,
-                                            first, defer, g->partial);
+    k_apply_dir<Z, 1><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pold, pold2, pnew, g->q, g->us, g->st, first, defer,
+                                            g->partial);
   else if (g->stencil_seg == 2)
-    k_apply_dir<Z, 2><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us, g->st,
-                                            first, defer, g->partial);
+    k_apply_dir<Z, 2><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pold, pold2, pnew, g->q, g->us, g->st, first, defer,
+                                            g->partial);
   else
-    k_apply_dir<Z, 4><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pbuf[(K - 1) & 1], pbuf[K & 1], g->q, g->us, g->st,
-                                            first, defer, g->partial);
+    k_apply_dir<Z, 4><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pold, pold2, pnew, g->q, g->us, g->st, first, defer,
+                                            g->partial);
   return check_launch("k_apply_dir");
 }
 
@@ -1082,7 +1090,7 @@ int pcg_step(ell_grid *g, int K, hipStream_t s) {
   const int fb = flat_blocks(n2);
   const int ab = apply_dir_blocks(g);  // blocks of the CG operator kernel
   const int *done = &g->st->done;
-  CHK(launch_apply_dir<Z>(g, K, K == 1 ? 1 : 0, K > 1 ? 1 : 0, s));
+  CHK(launch_apply_dir<Z>(g, K, K == 1 ? 1 : 0, deferred_updates(K), s));
 
   CHK(finalize(g, ab, 1, F_ALPHA, s));
   // r -= alpha q and the convergence test: fused into the first pre-smoothing
@@ -1111,8 +1119,9 @@ int pcg_step(ell_grid *g, int K, hipStream_t s) {
 // Stand-alone multigrid (Sec. 4.3, the V-cycle iterated as a solver):
 // u_K = u_{K-1} + z_K with z_K = M r_{K-1}, r_K = r_{K-1} - A z_K.  It runs on
 // the CG kernels with alpha = 1 and beta = 0 (F_UNIT): the operator step forms
-// p = z, q = A z and applies the previous iterate's u += p_old, the residual
-// update takes r -= q; no dots, no scalar recurrences.
+// p = z, q = A z and applies the deferred updates u += p of earlier iterates
+// (two at a time, as in CG), the residual update takes r -= q; no dots, no
+// scalar recurrences.
 template <typename R, typename Z>
 int mg_begin(ell_grid *g, const double *f, const double *u, const ell_solve_opts &o, hipStream_t s) {
   {
@@ -1134,8 +1143,8 @@ int mg_step(ell_grid *g, int K, hipStream_t s) {
   const long long n2 = g->n0 / 2;
   const int fb = flat_blocks(n2);
   CHK(precondition<R>(g, &g->st->done, s));
-  // K = 1: p = z (nothing to defer); later: p = z + 0 p_old and u += 1 p_old
-  CHK(launch_apply_dir<Z>(g, K, K == 1 ? 1 : 0, K > 1 ? 1 : 0, s));
+  // K = 1: p = z; later p = z + 0 p_old, with u += 1 p for the deferred updates
+  CHK(launch_apply_dir<Z>(g, K, K == 1 ? 1 : 0, deferred_updates(K), s));
   {
     ProfScope ps(g, ELL_K_UPDATE, s);
     k_update_r<<<fb, kBlock, 0, s>>>((double2 *)g->r, (const double2 *)g->q, n2, g->st, g->partial);
@@ -1149,17 +1158,17 @@ int mg_step(ell_grid *g, int K, hipStream_t s) {
 int pcg_finish(ell_grid *g, const double *f, double *u, ell_solve_stats *out, hipStream_t s) {
   const Geo &G = g->lev[0].geo;
   const int K = g->st_host->iter;
-  const int with_p = (K > 0 && g->st_host->status != -4) ? 1 : 0;
+  const int with_p = g->st_host->status != -4 ? pending_at_end(K) : 0;
   int fb = 0;
   if (g->tiled_ends) {
     fb = ends_blocks(g);
-    k_finish_tile<<<fb, kBlock, 0, s>>>(G, ends_nseg(g), g->tab64_0, g->vol0, f, g->us, (K & 1) ? g->p2 : g->p,
-                                        g->st, with_p, u, g->partial);
+    k_finish_tile<<<fb, kBlock, 0, s>>>(G, ends_nseg(g), g->tab64_0, g->vol0, f, g->us, dir_buf(g, K),
+                                        dir_buf(g, K - 1), g->st, with_p, u, g->partial);
     CHK(check_launch("k_finish_tile"));
   } else {
     fb = seg_blocks(2LL * G.H);
-    k_finish<<<fb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, g->us, (K & 1) ? g->p2 : g->p, g->st, with_p, u,
-                                   g->partial);
+    k_finish<<<fb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, g->us, dir_buf(g, K), dir_buf(g, K - 1), g->st,
+                                   with_p, u, g->partial);
     CHK(check_launch("k_finish"));
   }
   k_finalize<<<1, kBlock, 0, s>>>(g->partial, fb, 2, g->st, F_TRUE, 0, 0, 0);
@@ -1360,6 +1369,8 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->q = (double *)tmp;
   if ((rc = dalloc(g, &tmp, vb)) != ELL_OK) return bail(rc);
   g->p2 = (double *)tmp;
+  if ((rc = dalloc(g, &tmp, vb)) != ELL_OK) return bail(rc);
+  g->p3 = (double *)tmp;
   if (g->prec != ELL_FP64) {
     if ((rc = dalloc(g, &g->b32, (size_t)g->n0 * 4)) != ELL_OK) return bail(rc);
     if ((rc = dalloc(g, &g->z32, (size_t)g->n0 * 4)) != ELL_OK) return bail(rc);

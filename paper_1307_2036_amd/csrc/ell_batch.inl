@@ -36,7 +36,7 @@ struct GridDev {
   LevelDev lev[kMaxLevels];
   const double *tab64_0;
   const double *vol0;  // finest-level cell volumes
-  double *us, *r, *z, *p, *p2, *q;
+  double *us, *r, *z, *p, *p2, *p3, *q;  // p_K in {p, p2, p3}[dir_slot(K)]
   float *u32;
   double *partial;
   PcgState *st;
@@ -282,6 +282,12 @@ __global__ __launch_bounds__(kBlock) void kb_prolong_out_tile(const StageEnt *__
                                          ui(bg - ents[e].block0), gp(gd->z));
 }
 
+// The search direction of iteration K of a grid.
+__device__ __forceinline__ double *dir_dev(const GridDev *gd, int K) {
+  const int i = dir_slot(K);
+  return i == 0 ? gd->p : (i == 1 ? gd->p2 : gd->p3);
+}
+
 __global__ __launch_bounds__(kBlock) void kb_apply_dir(const StageEnt *__restrict__ ents, int nent, int total) {
   const int bg = logical_block();
   if (bg >= total) return;
@@ -289,15 +295,16 @@ __global__ __launch_bounds__(kBlock) void kb_apply_dir(const StageEnt *__restric
   const GridDev *gd = gp(ents[e].g);
   const PcgState *st = gp(gd->st);
   const int K = ui(st->iter) + 1;  // iteration about to run
-  double *pold = gp(((K - 1) & 1) ? gd->p2 : gd->p);
-  double *pnew = gp((K & 1) ? gd->p2 : gd->p);
+  double *pold = gp(dir_dev(gd, K - 1));
+  double *pold2 = gp(dir_dev(gd, K - 2));
+  double *pnew = gp(dir_dev(gd, K));
   if (ui(gd->apply_tile))
-    apply_dir_tile_body<double>(ugeo(gd->lev[0].geo), ui(gd->apply_nseg), cp(gd->tab64_0), gp(gd->z), pold, pnew,
-                                gp(gd->q), gp(gd->us), st, K == 1 ? 1 : 0, K > 1 ? 1 : 0, gp(gd->partial),
-                                ui(bg - ents[e].block0));
+    apply_dir_tile_body<double>(ugeo(gd->lev[0].geo), ui(gd->apply_nseg), cp(gd->tab64_0), gp(gd->z), pold, pold2,
+                                pnew, gp(gd->q), gp(gd->us), st, K == 1 ? 1 : 0, deferred_updates(K),
+                                gp(gd->partial), ui(bg - ents[e].block0));
   else
-    apply_dir_body<double, 1>(ugeo(gd->lev[0].geo), cp(gd->tab64_0), gp(gd->z), pold, pnew, gp(gd->q),
-                              gp(gd->us), st, K == 1 ? 1 : 0, K > 1 ? 1 : 0, gp(gd->partial),
+    apply_dir_body<double, 1>(ugeo(gd->lev[0].geo), cp(gd->tab64_0), gp(gd->z), pold, pold2, pnew, gp(gd->q),
+                              gp(gd->us), st, K == 1 ? 1 : 0, deferred_updates(K), gp(gd->partial),
                               ui(bg - ents[e].block0), 0);
 }
 
@@ -329,8 +336,8 @@ __global__ __launch_bounds__(kBlock) void kb_begin(const StageEnt *__restrict__ 
   const ReqDev *rq = gp(reqs + ents[e].aux);
   if (ui(gd->ends_tile))
     ends_tile_body<true>(ugeo(gd->lev[0].geo), ui(gd->ends_nseg), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f),
-                         gp((const double *)rq->u), nullptr, 0.0, 0, gp(gd->us), gp(gd->r), gp(gd->partial),
-                         ui(bg - ents[e].block0));
+                         gp((const double *)rq->u), nullptr, 0.0, nullptr, 0.0, 0, gp(gd->us), gp(gd->r),
+                         gp(gd->partial), ui(bg - ents[e].block0));
   else
     begin_body(ugeo(gd->lev[0].geo), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f), gp((const double *)rq->u),
                gp(gd->us), gp(gd->r), gp(gd->partial), ui(bg - ents[e].block0));
@@ -350,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void kb_init(const StageEnt *__restrict__ e
   finalize_body(gp(gd->partial), ui(gd->nb_begin), 2, st, F_INIT, rq->rtol, rq->atol, rq->rel_to_rhs, 0, 1);
 }
 
-// End of the solves of a table: the deferred update of the last iteration,
+// End of the solves of a table: the deferred updates of the last iterations,
 // u back in plane-major order and the partial sums of its true residual.
 __global__ __launch_bounds__(kBlock) void kb_finish(const StageEnt *__restrict__ ents, int nent, int total,
                                                     const ReqDev *__restrict__ reqs) {
@@ -361,15 +368,17 @@ __global__ __launch_bounds__(kBlock) void kb_finish(const StageEnt *__restrict__
   const ReqDev *rq = gp(reqs + ents[e].aux);
   const PcgState *st = gp(gd->st);
   const int K = ui(st->iter);
-  const int with_p = (K > 0 && ui(st->status) != -4) ? 1 : 0;
+  const int with_p = ui(st->status) != -4 ? pending_at_end(K) : 0;
   const double alpha = with_p ? st->alpha : 0.0;
+  const double alpha2 = with_p == 2 ? st->alpha_prev : 0.0;
+  double *pk = gp(dir_dev(gd, K)), *pk1 = gp(dir_dev(gd, K - 1));
   if (ui(gd->ends_tile))
     ends_tile_body<false>(ugeo(gd->lev[0].geo), ui(gd->ends_nseg), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f),
-                          gp(gd->us), gp((K & 1) ? gd->p2 : gd->p), alpha, with_p, gp(rq->u), nullptr,
-                          gp(gd->partial), ui(bg - ents[e].block0));
+                          gp(gd->us), pk, alpha, pk1, alpha2, with_p, gp(rq->u), nullptr, gp(gd->partial),
+                          ui(bg - ents[e].block0));
   else
-    finish_body(ugeo(gd->lev[0].geo), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f), gp(gd->us),
-                gp((K & 1) ? gd->p2 : gd->p), alpha, with_p, gp(rq->u), gp(gd->partial), ui(bg - ents[e].block0));
+    finish_body(ugeo(gd->lev[0].geo), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f), gp(gd->us), pk, alpha, pk1, alpha2,
+                with_p, gp(rq->u), gp(gd->partial), ui(bg - ents[e].block0));
 }
 
 // one block per grid
@@ -450,6 +459,7 @@ int grid_dev_build(ell_grid *g) {
   h.z = g->z;
   h.p = g->p;
   h.p2 = g->p2;
+  h.p3 = g->p3;
   h.q = g->q;
   h.u32 = (float *)g->z32;
   h.partial = g->partial;

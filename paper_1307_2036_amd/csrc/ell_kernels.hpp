@@ -51,10 +51,22 @@ struct Geo {
 };
 
 struct PcgState {
-  double kappa_old, alpha, beta, r0_norm, b_norm, r_norm, thresh, true_r_norm;
+  // alpha: the last step length; alpha_prev: the one before (the solution
+  // updates of two iterations are applied together)
+  double kappa_old, alpha, alpha_prev, beta, r0_norm, b_norm, r_norm, thresh, true_r_norm;
   int iter, done, status, maxiter, flexible;
   int pending;  // a step length alpha waits for its residual update (set by F_ALPHA)
 };
+
+// The deferred solution updates of CG: iteration K's update u += alpha_K p_K
+// waits for the operator step of a later iteration, which reads and writes u
+// for two updates at once.  The steps of odd K >= 3 apply those of K - 2 and
+// K - 1; the end of a solve after K iterations applies the rest (K even:
+// K - 1 and K; K odd: K).  p_K lives in buffer dir_slot(K) of three: the
+// step of K overwrites p_{K-3}, which was applied at step K - 1 or K - 2.
+__host__ __device__ inline int deferred_updates(int K) { return K >= 3 && (K & 1) ? 2 : 0; }
+__host__ __device__ inline int pending_at_end(int K) { return K <= 0 ? 0 : ((K & 1) ? 1 : 2); }
+__host__ __device__ inline int dir_slot(int K) { return ((K % 3) + 3) % 3; }
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b mod 8);
 // every grid here is a multiple of 8 blocks and this map gives each XCD a
@@ -1313,15 +1325,21 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ t
 // One CG step's vector work around the operator (Appendix B, Alg. PCG):
 //   p_new = z + beta p_old          (search direction; p_new = z when first)
 //   q     = A p_new, partial sums of <p_new, q>
-//   u    += alpha_prev p_old        (the previous step's solution update,
+//   defer_u = 1: u += alpha p_old   (the previous step's solution update,
 //                                    deferred to ride on the p_old read)
-// p_old and p_new are different buffers, so neighbour values of p_new are
-// formed from z and p_old exactly as their owning lanes form them.
+//   defer_u = 2: u = (u + alpha_prev p_old2) + alpha p_old
+//                                   (the updates of the two previous steps,
+//                                    in their order: every other step reads
+//                                    and writes u once for two updates)
+// alpha / alpha_prev: the step lengths of p_old / p_old2.  p_old2, p_old and
+// p_new are different buffers, so neighbour values of p_new are formed from
+// z and p_old exactly as their owning lanes form them.
 // -------------------------------------------------------------------------
 template <typename Z, int NSEG>
 __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__ tab,
                                                       const Z *__restrict__ z,
                                                       const double *__restrict__ pold,
+                                                      const double *__restrict__ pold2,
                                                       double *__restrict__ pnew,
                                                       double *__restrict__ q,
                                                       double *__restrict__ u,
@@ -1332,7 +1350,7 @@ __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__
   __shared__ double sh[4];
   if (st->done) return;
   const double beta = first ? 0.0 : st->beta;
-  const double alpha = st->alpha;
+  const double alpha = st->alpha, alpha2 = st->alpha_prev;
   const int w = wave_id();
   const int sg = w / CH;
   const int slot = (lb * CH + (w % CH)) * kSegCols + (threadIdx.x & 63);
@@ -1377,7 +1395,7 @@ __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__
     double pm = k0 > 0 ? dir(os + (long long)(k0 - 1) * H) : pc;
     int k = k0;
     for (; k + U <= k1; k += U) {
-      double pp[U], pw[U], pe[U], ps[U], pn[U], uu[U], po[U];
+      double pp[U], pw[U], pe[U], ps[U], pn[U], uu[U], po[U], p2[U];
 #pragma unroll
       for (int t = 0; t < U; ++t) {
         const long long o = (long long)(k + t) * H;
@@ -1388,6 +1406,7 @@ __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__
         pn[t] = hy ? dir(oo + nb.n + o) : 0.0;
         uu[t] = defer_u ? u[os + o] : 0.0;
         po[t] = defer_u ? pold[os + o] : 0.0;
+        p2[t] = defer_u == 2 ? pold2[os + o] : 0.0;
       }
 #pragma unroll
       for (int t = 0; t < U; ++t) {
@@ -1395,7 +1414,11 @@ __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__
         const double acc = cell(k + t, pc, pm, pp[t], pw[t], pe[t], ps[t], pn[t]);
         q[os + o] = acc;
         pnew[os + o] = pc;
-        if (defer_u) u[os + o] = uu[t] + alpha * po[t];
+        if (defer_u) {
+          double nu = uu[t];
+          if (defer_u == 2) nu = nu + alpha2 * p2[t];
+          u[os + o] = nu + alpha * po[t];
+        }
         dot += pc * acc;
         pm = pc;
         pc = pp[t];
@@ -1408,7 +1431,11 @@ __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__
                               hy ? dir(oo + nb.s + o) : 0.0, hy ? dir(oo + nb.n + o) : 0.0);
       q[os + o] = acc;
       pnew[os + o] = pc;
-      if (defer_u) u[os + o] = u[os + o] + alpha * pold[os + o];
+      if (defer_u) {
+        double nu = u[os + o];
+        if (defer_u == 2) nu = nu + alpha2 * pold2[os + o];
+        u[os + o] = nu + alpha * pold[os + o];
+      }
       dot += pc * acc;
       pm = pc;
       pc = pp;
@@ -1422,12 +1449,14 @@ template <typename Z, int NSEG>
 __global__ __launch_bounds__(kBlock) void k_apply_dir(Geo L, const double *__restrict__ tab,
                                                       const Z *__restrict__ z,
                                                       const double *__restrict__ pold,
+                                                      const double *__restrict__ pold2,
                                                       double *__restrict__ pnew,
                                                       double *__restrict__ q,
                                                       double *__restrict__ u,
                                                       const PcgState *__restrict__ st, int first,
                                                       int defer_u, double *__restrict__ partial) {
-  apply_dir_body<Z, NSEG>(L, tab, z, pold, pnew, q, u, st, first, defer_u, partial, logical_block(), gridDim.x);
+  apply_dir_body<Z, NSEG>(L, tab, z, pold, pold2, pnew, q, u, st, first, defer_u, partial, logical_block(),
+                          gridDim.x);
 }
 
 // r <- r - alpha q, partial sums of ||r||^2
@@ -1555,6 +1584,7 @@ template <typename Z>
 __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const double *__restrict__ tab,
                                                     const Z *__restrict__ z,
                                                     const double *__restrict__ pold,
+                                                    const double *__restrict__ pold2,
                                                     double *__restrict__ pnew, double *__restrict__ q,
                                                     double *__restrict__ u,
                                                     const PcgState *__restrict__ st, int first,
@@ -1563,7 +1593,7 @@ __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const doubl
   __shared__ double sh[4];
   if (st->done) return;
   const double beta = first ? 0.0 : st->beta;
-  const double alpha = st->alpha;
+  const double alpha = st->alpha, alpha2 = st->alpha_prev;
   const int tiles_x = (L.hx2 + kTX - 1) / kTX;
   const int per_seg = tile_count(L.hx2, L.ny);
   const int sg = lb / per_seg, tt = lb - sg * per_seg;
@@ -1617,12 +1647,13 @@ __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const doubl
     // with write set, also p_new and the deferred solution update
     auto level = [&](int k, int b, bool write, double *pv) {
       const long long o = (long long)k * S;
-      double zv[4], po[4], uu[4];
+      double zv[4], po[4], uu[4], p2[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         zv[e] = ok[e] ? (double)z[off[e] + o] : 0.0;
         po[e] = (ok[e] && !first) ? pold[off[e] + o] : 0.0;
         uu[e] = (ok[e] && write && defer_u) ? __builtin_nontemporal_load(&u[off[e] + o]) : 0.0;
+        p2[e] = (ok[e] && write && defer_u == 2) ? __builtin_nontemporal_load(&pold2[off[e] + o]) : 0.0;
       }
       double hv = 0.0;
       if (b >= 0 && hok) hv = dirv(hoff + o);
@@ -1635,7 +1666,13 @@ __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const doubl
         if (b >= 0 && ok[e]) sp[b][e & 1][r0 + 8 * (e >> 1) + 1][x + 1] = pvv;
         if (ok[e] && write) {
           __builtin_nontemporal_store(pvv, &pnew[off[e] + o]);
-          if (defer_u) __builtin_nontemporal_store(uu[e] + alpha * po[e], &u[off[e] + o]);
+          if (defer_u) {
+            // the older update first: the same two steps as one per iteration
+            double nu = uu[e];
+            if (defer_u == 2) nu = nu + alpha2 * p2[e];
+            nu = nu + alpha * po[e];
+            __builtin_nontemporal_store(nu, &u[off[e] + o]);
+          }
         }
       }
       if (b >= 0 && hok) sp[b][hc][hr][hx] = hv;
@@ -1695,11 +1732,12 @@ template <typename Z>
 __global__ __launch_bounds__(kBlock) void k_apply_dir_tile(Geo L, int nseg, const double *__restrict__ tab,
                                                            const Z *__restrict__ z,
                                                            const double *__restrict__ pold,
+                                                           const double *__restrict__ pold2,
                                                            double *__restrict__ pnew, double *__restrict__ q,
                                                            double *__restrict__ u,
                                                            const PcgState *__restrict__ st, int first,
                                                            int defer_u, double *__restrict__ partial) {
-  apply_dir_tile_body<Z>(L, nseg, tab, z, pold, pnew, q, u, st, first, defer_u, partial, logical_block());
+  apply_dir_tile_body<Z>(L, nseg, tab, z, pold, pold2, pnew, q, u, st, first, defer_u, partial, logical_block());
 }
 
 // -------------------------------------------------------------------------
@@ -1804,8 +1842,10 @@ __device__ __forceinline__ void begin_body(Geo L, const double *__restrict__ tab
   }
 }
 
-// u = us + alpha p (the last iteration's deferred update; us alone when
-// with_p is 0) written plane-major, and the true residual of that u:
+// u = us + alpha p (with_p = 1: the last iteration's deferred update), u =
+// (us + alpha2 p2) + alpha p (with_p = 2: the last two, p2 the older
+// direction), or us (with_p = 0), written plane-major, and the true residual
+// of that u:
 // partial[2 lb] = sum (V f)^2, partial[2 lb + 1] = sum (V f - A u)^2.
 // One block = 64 split slots with alternating colours (a red and a black
 // column side by side are adjacent plane-major cells, so the plane-major
@@ -1814,7 +1854,8 @@ __device__ __forceinline__ void finish_body(Geo L, const double *__restrict__ ta
                                             const double *__restrict__ vol,
                                             const double *__restrict__ f,
                                             const double *__restrict__ us,
-                                            const double *__restrict__ p, double alpha, int with_p,
+                                            const double *__restrict__ p, double alpha,
+                                            const double *__restrict__ p2, double alpha2, int with_p,
                                             double *__restrict__ u, double *__restrict__ partial,
                                             int lb) {
   constexpr int NSEG = 4, U = 4;
@@ -1837,7 +1878,12 @@ __device__ __forceinline__ void finish_body(Geo L, const double *__restrict__ ta
     const long long oc = (long long)j * L.nx + i;
     const long long oo = (long long)(1 - c) * L.cs, os = (long long)c * L.cs + m;
     const int nz = L.nz, P = L.P;
-    auto val = [&](long long idx) -> double { return with_p ? us[idx] + alpha * p[idx] : us[idx]; };
+    auto val = [&](long long idx) -> double {
+      if (!with_p) return us[idx];
+      double v = us[idx];
+      if (with_p == 2) v = v + alpha2 * p2[idx];
+      return v + alpha * p[idx];
+    };
     double uc = val(os + (long long)k0 * S);
     double um = k0 > 0 ? val(os + (long long)(k0 - 1) * S) : uc;
     int k = k0;
@@ -1892,9 +1938,11 @@ __global__ __launch_bounds__(kBlock) void k_finish(Geo L, const double *__restri
                                                    const double *__restrict__ f,
                                                    const double *__restrict__ us,
                                                    const double *__restrict__ p,
+                                                   const double *__restrict__ p2,
                                                    const PcgState *__restrict__ st, int with_p,
                                                    double *__restrict__ u, double *__restrict__ partial) {
-  finish_body(L, tab, vol, f, us, p, with_p ? st->alpha : 0.0, with_p, u, partial, logical_block());
+  finish_body(L, tab, vol, f, us, p, with_p ? st->alpha : 0.0, p2, with_p == 2 ? st->alpha_prev : 0.0, with_p, u,
+              partial, logical_block());
 }
 
 // The start and the end of a solve on the tiles of the CG operator step (a
@@ -1902,8 +1950,9 @@ __global__ __launch_bounds__(kBlock) void k_finish(Geo L, const double *__restri
 // horizontal neighbours of each level staged in a three-level LDS ring):
 //   BEGIN:  us = u0 and r = V f - A u0 in the split layout, u0 and f
 //           plane-major (src = u0, o1 = us, o2 = r);
-//   !BEGIN: u = us + alpha p (us alone without with_p) written plane-major,
-//           with the true residual V f - A u of that u (src = us, o1 = u).
+//   !BEGIN: u = us + alpha p, (us + alpha2 p2) + alpha p or us (with_p = 1,
+//           2, 0, as in finish_body) written plane-major, with the true
+//           residual V f - A u of that u (src = us, o1 = u).
 // partial[2 lb] = sum (V f)^2, partial[2 lb + 1] = sum res^2 over the block;
 // blocks past the last segment write zeros.  Each cell's A u is formed in
 // the order of op_row, so u and the residual equal the column kernels' (the
@@ -1913,7 +1962,8 @@ __device__ __forceinline__ void ends_tile_body(Geo L, int nseg, const double *__
                                                const double *__restrict__ vol,
                                                const double *__restrict__ f,
                                                const double *__restrict__ src,
-                                               const double *__restrict__ p, double alpha, int with_p,
+                                               const double *__restrict__ p, double alpha,
+                                               const double *__restrict__ p2, double alpha2, int with_p,
                                                double *__restrict__ o1, double *__restrict__ o2,
                                                double *__restrict__ partial, int lb) {
   __shared__ double sp[3][2][kTH][kTW];
@@ -1970,7 +2020,12 @@ __device__ __forceinline__ void ends_tile_body(Geo L, int nseg, const double *__
     const long long lstride = BEGIN ? plane : S;  // level stride of src
     auto val = [&](long long idx) -> double {
       if constexpr (BEGIN) return src[idx];
-      else return with_p ? src[idx] + alpha * p[idx] : src[idx];
+      else {
+        if (!with_p) return src[idx];
+        double v = src[idx];
+        if (with_p == 2) v = v + alpha2 * p2[idx];
+        return v + alpha * p[idx];
+      }
     };
     // level k: own values into v (and LDS buffer b when b >= 0)
     auto level = [&](int k, int b, double *v) {
@@ -2060,7 +2115,7 @@ __global__ __launch_bounds__(kBlock) void k_begin_tile(Geo L, int nseg, const do
                                                        const double *__restrict__ f,
                                                        const double *__restrict__ u0, double *__restrict__ us,
                                                        double *__restrict__ r, double *__restrict__ partial) {
-  ends_tile_body<true>(L, nseg, tab, vol, f, u0, nullptr, 0.0, 0, us, r, partial, logical_block());
+  ends_tile_body<true>(L, nseg, tab, vol, f, u0, nullptr, 0.0, nullptr, 0.0, 0, us, r, partial, logical_block());
 }
 
 __global__ __launch_bounds__(kBlock) void k_finish_tile(Geo L, int nseg, const double *__restrict__ tab,
@@ -2068,10 +2123,11 @@ __global__ __launch_bounds__(kBlock) void k_finish_tile(Geo L, int nseg, const d
                                                         const double *__restrict__ f,
                                                         const double *__restrict__ us,
                                                         const double *__restrict__ p,
+                                                        const double *__restrict__ p2,
                                                         const PcgState *__restrict__ st, int with_p,
                                                         double *__restrict__ u, double *__restrict__ partial) {
-  ends_tile_body<false>(L, nseg, tab, vol, f, us, p, with_p ? st->alpha : 0.0, with_p, u, nullptr, partial,
-                        logical_block());
+  ends_tile_body<false>(L, nseg, tab, vol, f, us, p, with_p ? st->alpha : 0.0, p2,
+                        with_p == 2 ? st->alpha_prev : 0.0, with_p, u, nullptr, partial, logical_block());
 }
 
 // -------------------------------------------------------------------------
@@ -2180,7 +2236,7 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
       st->thresh = th;
       st->iter = 0;
       st->pending = 0;
-      st->alpha = st->beta = st->kappa_old = 0.0;
+      st->alpha = st->alpha_prev = st->beta = st->kappa_old = 0.0;
       if (!isfinite(r0) || !isfinite(bn)) {
         st->done = 1;
         st->status = -4;
@@ -2202,6 +2258,7 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
       break;
     case F_ALPHA: {
       const double a = st->kappa_old / tot[0];
+      st->alpha_prev = st->alpha;
       st->alpha = a;
       st->pending = 1;
       if (!isfinite(a)) { st->done = 1; st->status = -4; }
@@ -2232,6 +2289,7 @@ __device__ __forceinline__ void finalize_body(const double *__restrict__ partial
     }
     case F_UNIT:  // stand-alone multigrid: unit steps along z, no direction memory
       st->alpha = 1.0;
+      st->alpha_prev = 1.0;
       st->beta = 0.0;
       break;
     case F_TRUE:  // partials of k_finish: [||V f||^2, ||V f - A u||^2]

@@ -49,8 +49,10 @@ def vcycle_bytes(n0: int, levels: int, e: int, nu_pre=1, nu_post=1, nu_coarse=1)
 
 def cg_bytes(n0: int, flexible: bool = True, fused_update: bool = False, fused_dots: bool = False) -> float:
     """CG vector work per iteration (FP64) beyond the V-cycle's own bytes:
-    fused direction + operator + deferred solution update (z, p_old, u read;
-    p_new, q, u written: 48 B); residual update (r, q read, r written: 24 B; on
+    fused direction + operator (z, p_old read; p_new, q written: 32 B) and the
+    deferred solution updates, two at a time on every other iteration (u,
+    p_old2 read, u written: 24 B per two iterations, 12 B on average: 44 B);
+    residual update (r, q read, r written: 24 B; on
     the first pre-smoothing pair, which reads r anyway: q read, r written,
     16 B); dots <r,z>, <z,q> (24 B; <r,z> alone, 16 B, with the classic beta; on
     the last post-smoothing pair: nothing, or the q read, 8 B, for <z,q>)."""
@@ -59,7 +61,7 @@ def cg_bytes(n0: int, flexible: bool = True, fused_update: bool = False, fused_d
         dots = 8 if flexible else 0
     else:
         dots = 24 if flexible else 16
-    return (48 + update + dots) * n0
+    return (44 + update + dots) * n0
 
 
 def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1) -> float:
