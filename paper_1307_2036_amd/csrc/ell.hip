@@ -1162,8 +1162,14 @@ int pcg_finish(ell_grid *g, const double *f, double *u, ell_solve_stats *out, hi
   int fb = 0;
   if (g->tiled_ends) {
     fb = ends_blocks(g);
-    k_finish_tile<<<fb, kBlock, 0, s>>>(G, ends_nseg(g), g->tab64_0, g->vol0, f, g->us, dir_buf(g, K),
-                                        dir_buf(g, K - 1), g->st, with_p, u, g->partial);
+    auto go = [&](auto wp) {
+      k_finish_tile<decltype(wp)::value><<<fb, kBlock, 0, s>>>(G, ends_nseg(g), g->tab64_0, g->vol0, f, g->us,
+                                                               dir_buf(g, K), dir_buf(g, K - 1), g->st, u,
+                                                               g->partial);
+    };
+    if (with_p == 2) go(std::integral_constant<int, 2>{});
+    else if (with_p == 1) go(std::integral_constant<int, 1>{});
+    else go(std::integral_constant<int, 0>{});
     CHK(check_launch("k_finish_tile"));
   } else {
     fb = seg_blocks(2LL * G.H);

@@ -334,10 +334,11 @@ __global__ __launch_bounds__(kBlock) void kb_begin(const StageEnt *__restrict__ 
   const int e = find_ent(ents, nent, bg);
   const GridDev *gd = gp(ents[e].g);
   const ReqDev *rq = gp(reqs + ents[e].aux);
+  __shared__ double smem[kEndsSmem];
   if (ui(gd->ends_tile))
     ends_tile_body<true>(ugeo(gd->lev[0].geo), ui(gd->ends_nseg), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f),
-                         gp((const double *)rq->u), nullptr, 0.0, nullptr, 0.0, 0, gp(gd->us), gp(gd->r),
-                         gp(gd->partial), ui(bg - ents[e].block0));
+                         gp((const double *)rq->u), nullptr, 0.0, nullptr, 0.0, gp(gd->us), gp(gd->r),
+                         gp(gd->partial), ui(bg - ents[e].block0), smem);
   else
     begin_body(ugeo(gd->lev[0].geo), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f), gp((const double *)rq->u),
                gp(gd->us), gp(gd->r), gp(gd->partial), ui(bg - ents[e].block0));
@@ -372,11 +373,18 @@ __global__ __launch_bounds__(kBlock) void kb_finish(const StageEnt *__restrict__
   const double alpha = with_p ? st->alpha : 0.0;
   const double alpha2 = with_p == 2 ? st->alpha_prev : 0.0;
   double *pk = gp(dir_dev(gd, K)), *pk1 = gp(dir_dev(gd, K - 1));
-  if (ui(gd->ends_tile))
-    ends_tile_body<false>(ugeo(gd->lev[0].geo), ui(gd->ends_nseg), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f),
-                          gp(gd->us), pk, alpha, pk1, alpha2, with_p, gp(rq->u), nullptr, gp(gd->partial),
-                          ui(bg - ents[e].block0));
-  else
+  __shared__ double smem[kEndsSmem];
+  if (ui(gd->ends_tile)) {
+    auto go = [&](auto wp) {
+      ends_tile_body<false, decltype(wp)::value>(ugeo(gd->lev[0].geo), ui(gd->ends_nseg), cp(gd->tab64_0),
+                                                 cp(gd->vol0), gp(rq->f), gp(gd->us), pk, alpha, pk1, alpha2,
+                                                 gp(rq->u), nullptr, gp(gd->partial), ui(bg - ents[e].block0),
+                                                 smem);
+    };
+    if (with_p == 2) go(std::integral_constant<int, 2>{});
+    else if (with_p == 1) go(std::integral_constant<int, 1>{});
+    else go(std::integral_constant<int, 0>{});
+  } else
     finish_body(ugeo(gd->lev[0].geo), cp(gd->tab64_0), cp(gd->vol0), gp(rq->f), gp(gd->us), pk, alpha, pk1, alpha2,
                 with_p, gp(rq->u), gp(gd->partial), ui(bg - ents[e].block0));
 }

@@ -1956,18 +1956,21 @@ __global__ __launch_bounds__(kBlock) void k_finish(Geo L, const double *__restri
 // partial[2 lb] = sum (V f)^2, partial[2 lb + 1] = sum res^2 over the block;
 // blocks past the last segment write zeros.  Each cell's A u is formed in
 // the order of op_row, so u and the residual equal the column kernels' (the
-// block sums differ in their order).
-template <bool BEGIN>
+// block sums differ in their order).  WP: with_p as a compile-time constant
+// (no branch per element).  smem: the block's LDS of kEndsSmem doubles, owned
+// by the kernel so that several instantiations in one kernel share it.
+constexpr int kEndsSmem = 3 * 2 * kTH * kTW + 4;
+template <bool BEGIN, int WP = 0>
 __device__ __forceinline__ void ends_tile_body(Geo L, int nseg, const double *__restrict__ tab,
                                                const double *__restrict__ vol,
                                                const double *__restrict__ f,
                                                const double *__restrict__ src,
                                                const double *__restrict__ p, double alpha,
-                                               const double *__restrict__ p2, double alpha2, int with_p,
+                                               const double *__restrict__ p2, double alpha2,
                                                double *__restrict__ o1, double *__restrict__ o2,
-                                               double *__restrict__ partial, int lb) {
-  __shared__ double sp[3][2][kTH][kTW];
-  __shared__ double sh[4];
+                                               double *__restrict__ partial, int lb, double *smem) {
+  double(*sp)[2][kTH][kTW] = reinterpret_cast<double(*)[2][kTH][kTW]>(smem);
+  double *sh = smem + 3 * 2 * kTH * kTW;
   const int tiles_x = (L.hx2 + kTX - 1) / kTX;
   const int per_seg = tile_count(L.hx2, L.ny);
   const int sg = lb / per_seg, tt = lb - sg * per_seg;
@@ -2019,11 +2022,11 @@ __device__ __forceinline__ void ends_tile_body(Geo L, int nseg, const double *__
     }
     const long long lstride = BEGIN ? plane : S;  // level stride of src
     auto val = [&](long long idx) -> double {
-      if constexpr (BEGIN) return src[idx];
-      else {
-        if (!with_p) return src[idx];
+      if constexpr (BEGIN || WP == 0) {
+        return src[idx];
+      } else {
         double v = src[idx];
-        if (with_p == 2) v = v + alpha2 * p2[idx];
+        if constexpr (WP == 2) v = v + alpha2 * p2[idx];
         return v + alpha * p[idx];
       }
     };
@@ -2115,19 +2118,22 @@ __global__ __launch_bounds__(kBlock) void k_begin_tile(Geo L, int nseg, const do
                                                        const double *__restrict__ f,
                                                        const double *__restrict__ u0, double *__restrict__ us,
                                                        double *__restrict__ r, double *__restrict__ partial) {
-  ends_tile_body<true>(L, nseg, tab, vol, f, u0, nullptr, 0.0, nullptr, 0.0, 0, us, r, partial, logical_block());
+  __shared__ double smem[kEndsSmem];
+  ends_tile_body<true>(L, nseg, tab, vol, f, u0, nullptr, 0.0, nullptr, 0.0, us, r, partial, logical_block(), smem);
 }
 
+template <int WP>
 __global__ __launch_bounds__(kBlock) void k_finish_tile(Geo L, int nseg, const double *__restrict__ tab,
                                                         const double *__restrict__ vol,
                                                         const double *__restrict__ f,
                                                         const double *__restrict__ us,
                                                         const double *__restrict__ p,
                                                         const double *__restrict__ p2,
-                                                        const PcgState *__restrict__ st, int with_p,
+                                                        const PcgState *__restrict__ st,
                                                         double *__restrict__ u, double *__restrict__ partial) {
-  ends_tile_body<false>(L, nseg, tab, vol, f, us, p, with_p ? st->alpha : 0.0, p2,
-                        with_p == 2 ? st->alpha_prev : 0.0, with_p, u, nullptr, partial, logical_block());
+  __shared__ double smem[kEndsSmem];
+  ends_tile_body<false, WP>(L, nseg, tab, vol, f, us, p, WP ? st->alpha : 0.0, p2, WP == 2 ? st->alpha_prev : 0.0, u,
+                            nullptr, partial, logical_block(), smem);
 }
 
 // -------------------------------------------------------------------------
