@@ -83,6 +83,25 @@ def test_batch_matches_single_grid_path(E, orc):
     B.close()
 
 
+def test_deferred_updates_in_batch(E, orc):
+    """Batched solves stopped after 1..6 iterations (the end of each applying
+    the one or two solution updates still pending) return the oracle's
+    iterate."""
+    ps = problems()[:2]
+    B = E.Batch(4 << 30)
+    grids = [B.grid(p) for p in ps]
+    gs = [orc.Grid.from_problem(p) for p in ps]
+    for k in range(1, 7):
+        fs = [dev(p.f) for p in ps]
+        us = [torch.zeros_like(f) for f in fs]
+        st = B.wait(B.submit(grids, fs, us, rtol=1e-15, maxiter=k))
+        for p, g, u, s in zip(ps, gs, us, st):
+            ur, sr = orc.pcg(g, p.f, rtol=1e-15, maxiter=k)
+            assert s.iters == k and sr["iters"] == k
+            assert np.linalg.norm(host(u) - ur) <= 1e-10 * np.linalg.norm(ur), k
+    B.close()
+
+
 def test_continuous_admission_and_warm_start(E, orc):
     """A ticket submitted while another runs joins the running iterations; two
     requests on one grid run one after the other (the second warm-starts)."""

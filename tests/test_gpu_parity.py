@@ -501,6 +501,28 @@ def test_tiled_solve_ends_equal_column_kernels(ell, orc, nx, ny, nz, levels):
     check_solve(orc, g, p.f, u1, s1, 1e-8, u0=u0)
 
 
+@pytest.mark.parametrize("flexible", [False, True])
+def test_deferred_updates_at_every_iteration_count(ell, orc, flexible):
+    """The solution updates ride on the operator steps two at a time (odd
+    steps from the third on) and the end of a solve applies what is pending
+    (one update after an odd iteration count, two after an even one, through
+    three rotating direction buffers): CG stopped after 1..6 iterations and
+    stand-alone multigrid after 1..5 return the oracle's iterate."""
+    p = I.graded_problem("defer", 64, 24, 1e-2, 41, 42)
+    G = ell.Grid.from_problem(p)
+    g = orc.Grid.from_problem(p)
+    for k in range(1, 7):
+        u, st = G.pcg_solve(dev(p.f), rtol=1e-15, maxiter=k, flexible=flexible)
+        ur, sr = orc.pcg(g, p.f, rtol=1e-15, maxiter=k, flexible=flexible)
+        assert st.iters == k and sr["iters"] == k
+        assert rel(host(u), ur) <= 1e-10, k
+    for k in range(1, 6):
+        u, st = G.mg_solve(dev(p.f), rtol=1e-15, maxiter=k)
+        ur, sr = orc.mg_solve(g, p.f, rtol=1e-15, maxiter=k)
+        assert st.iters == k and sr["iters"] == k
+        assert rel(host(u), ur) <= 1e-10, k
+
+
 def test_solve_edge_cases(ell, orc):
     p = I.graded_problem("edge", 32, 8, 1e-2, 1, 2)
     G = ell.Grid.from_problem(p)
