@@ -171,9 +171,10 @@ def main():
                     perfmodel.smooth0_launch_bytes_hybrid(n, fused_update=feat["fused_update"], dot_q=dot_q))
     avg_ms = float(t_s.mean())
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
-    # the CG operator step reads z, p_old, u and writes p_new, q, u (48 B per unknown);
-    # the first iteration of a solve reads z only and writes p_new, q (24 B)
-    apply_bytes = (24 + 48 * (iters - 1)) / iters * n
+    # the CG operator step reads z (and p_old after the first iteration) and writes
+    # p_new, q: 24 B per unknown at K = 1, 32 B after; the steps of odd K >= 3 also
+    # apply two deferred solution updates (u, p_old2 read, u written: 24 B more)
+    apply_bytes = sum(24 if K == 1 else (56 if K % 2 else 32) for K in range(1, iters + 1)) / iters * n
     apply_gbs = apply_bytes / (float(t_a.mean()) * 1e-3) / 1e9
     cnt = int(t_s.size)
 
