@@ -568,6 +568,7 @@ struct ell_batch {
   bool use_graph = true;
   hipGraphExec_t gexec = nullptr;
   bool dirty = true;
+  int table_cycles = 0;  // cycles the current stage table has run
   int prec = -1;
   int nu_pre = -1, nu_post = -1;  // shared by every grid (one V-cycle schedule per step)
   std::string last_error;
@@ -1053,11 +1054,15 @@ void drop_graph(ell_batch *b) {
 // Enqueue n grouped steps.  With graphs on, the step's launches are captured
 // once per stage table (the tables, and with them every kernel argument, only
 // change in batch_build) and the instantiated graph is launched n times; the
-// step holds kernel launches only (no memset or copy nodes).  A capture that
-// fails switches the batch to direct launches.
+// step holds kernel launches only (no memset or copy nodes).  A table that
+// runs a single step in its first cycle (a serving loop that polls every
+// step, its set of solves changing from cycle to cycle) launches directly:
+// the capture and instantiation would be host time the GPU waits for, spent
+// on one launch; it is captured when it runs again.  A capture that fails
+// switches the batch to direct launches.
 int batch_steps(ell_batch *b, int n) {
   hipStream_t s = b->stream;
-  if (b->use_graph && !b->gexec) {
+  if (b->use_graph && !b->gexec && (n > 1 || b->table_cycles > 0)) {
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       (void)hipGetLastError();
@@ -1083,6 +1088,7 @@ int batch_steps(ell_batch *b, int n) {
       b->steps++;
     }
   }
+  b->table_cycles++;
   return ELL_OK;
 }
 
@@ -1145,6 +1151,7 @@ void worker_loop(ell_batch *b) {
         fail_all(b, b->active, rc);
         continue;
       }
+      b->table_cycles = 0;
     }
     rc = batch_steps(b, b->poll_every);
     // gather the states of the active grids with one copy

@@ -170,8 +170,10 @@ def test_poll_pending_then_done(E):
 def test_graph_replays_equal_direct_launches(E):
     """Grouped steps replayed from captured graphs give the same bits as direct
     launches.  Each batch replays its graphs many times (two steps per poll,
-    a new capture whenever a grid converges and leaves), with other GPU work and
-    synchronisations between the solves; every result is compared."""
+    a new capture whenever a grid converges and leaves; the second batch polls
+    every step, so each new stage table first launches directly and is
+    captured when it runs again), with other GPU work and synchronisations
+    between the solves; every result is compared."""
     ps = problems()
     res = {}
     for graph in (0, 1):
@@ -186,7 +188,7 @@ def test_graph_replays_equal_direct_launches(E):
             fs = [dev(p.f * (1.0 + 0.5 * rep)) for p in ps]
             us = [torch.zeros_like(f) for f in fs]
             noise = torch.randn(1 << 20, device="cuda", dtype=torch.float64).sum()
-            st = B.wait(B.submit(grids, fs, us, poll_every=2))
+            st = B.wait(B.submit(grids, fs, us, poll_every=1 if rep == 1 else 2))
             torch.cuda.synchronize()
             assert torch.isfinite(noise)
             out.append(([host(u) for u in us], [s.iters for s in st]))
