@@ -289,6 +289,19 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ 
   }
 }
 
+// v of lane q (q wave-uniform) in every lane.
+template <typename R>
+__device__ __forceinline__ R lane_value(R v, int q) {
+  if constexpr (sizeof(R) == 8) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, q);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), q);
+    return __builtin_bit_cast(R, ((unsigned long long)hi << 32) | lo);
+  } else {
+    return __builtin_bit_cast(R, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), q));
+  }
+}
+
 // -------------------------------------------------------------------------
 // The same half-sweep with each column split into kSeg segments along k, one
 // wavefront per segment (k is uniform across a wavefront, so coefficients are
@@ -321,15 +334,38 @@ __device__ __forceinline__ void seg_join_store(R (&y)[SEG], R prev, R (*xch)[kSe
                                                long long H, R rho, const double *bl = nullptr,
                                                const double *__restrict__ qo = nullptr,
                                                double *dsum = nullptr) {
+  // Coarse levels (latency-bound): lane q < NSEG loads segment q's Pf at its
+  // last level and Qb at its first before the barrier, and the joins take
+  // them from that lane, so the joins' LDS reads issue together and only
+  // their multiply-adds are sequential (the same operations in the same
+  // order as the loops below).
+  R pfq = R(1), qbq = R(1);
+  if constexpr (!FINE) {
+    if (lane < NSEG) {
+      const int s0 = min(lane * Ls, nz), e = min(s0 + Ls, nz);
+      if (e > s0) {
+        pfq = pf[e - 1];
+        qbq = qb[s0];
+      }
+    }
+  }
   // join the forward recurrence across segments
   xch[sg][lane] = prev;
   __syncthreads();
   R yin = R(0);
-  for (int q = 0; q < sg; ++q) {
-    const int e = min(q * Ls + Ls, nz);
-    const int s0 = min(q * Ls, nz);
-    const R pend = e > s0 ? pf[e - 1] : R(1);
-    yin = xch[q][lane] + pend * yin;
+  if constexpr (!FINE) {
+#pragma unroll
+    for (int q = 0; q < NSEG - 1; ++q) {
+      const R cand = xch[q][lane] + lane_value(pfq, q) * yin;
+      yin = q < sg ? cand : yin;
+    }
+  } else {
+    for (int q = 0; q < sg; ++q) {
+      const int e = min(q * Ls + Ls, nz);
+      const int s0 = min(q * Ls, nz);
+      const R pend = e > s0 ? pf[e - 1] : R(1);
+      yin = xch[q][lane] + pend * yin;
+    }
   }
   __syncthreads();
   // true y, then the local backward recurrence (in place)
@@ -346,11 +382,19 @@ __device__ __forceinline__ void seg_join_store(R (&y)[SEG], R prev, R (*xch)[kSe
   xch[sg][lane] = nxt;  // local w at the segment's first level
   __syncthreads();
   R win = R(0);
-  for (int q = NSEG - 1; q > sg; --q) {
-    const int s0 = min(q * Ls, nz);
-    const int e = min(s0 + Ls, nz);
-    const R qs = e > s0 ? qb[s0] : R(1);
-    win = xch[q][lane] + qs * win;
+  if constexpr (!FINE) {
+#pragma unroll
+    for (int q = NSEG - 1; q > 0; --q) {
+      const R cand = xch[q][lane] + lane_value(qbq, q) * win;
+      win = q > sg ? cand : win;
+    }
+  } else {
+    for (int q = NSEG - 1; q > sg; --q) {
+      const int s0 = min(q * Ls, nz);
+      const int e = min(s0 + Ls, nz);
+      const R qs = e > s0 ? qb[s0] : R(1);
+      win = xch[q][lane] + qs * win;
+    }
   }
   if (valid) {
 #pragma unroll
