@@ -334,38 +334,26 @@ __device__ __forceinline__ void seg_join_store(R (&y)[SEG], R prev, R (*xch)[kSe
                                                long long H, R rho, const double *bl = nullptr,
                                                const double *__restrict__ qo = nullptr,
                                                double *dsum = nullptr) {
-  // Coarse levels (latency-bound): lane q < NSEG loads segment q's Pf at its
-  // last level and Qb at its first before the barrier, and the joins take
-  // them from that lane, so the joins' LDS reads issue together and only
-  // their multiply-adds are sequential (the same operations in the same
-  // order as the loops below).
+  // Lane q < NSEG loads segment q's Pf at its last level and Qb at its first
+  // (1 for an empty segment) before the barrier, and the joins take them
+  // from that lane: their LDS reads issue together and only the multiply-adds
+  // are sequential (segment q < sg joins forward, q > sg backward).
   R pfq = R(1), qbq = R(1);
-  if constexpr (!FINE) {
-    if (lane < NSEG) {
-      const int s0 = min(lane * Ls, nz), e = min(s0 + Ls, nz);
-      if (e > s0) {
-        pfq = pf[e - 1];
-        qbq = qb[s0];
-      }
+  if (lane < NSEG) {
+    const int s0 = min(lane * Ls, nz), e = min(s0 + Ls, nz);
+    if (e > s0) {
+      pfq = pf[e - 1];
+      qbq = qb[s0];
     }
   }
   // join the forward recurrence across segments
   xch[sg][lane] = prev;
   __syncthreads();
   R yin = R(0);
-  if constexpr (!FINE) {
 #pragma unroll
-    for (int q = 0; q < NSEG - 1; ++q) {
-      const R cand = xch[q][lane] + lane_value(pfq, q) * yin;
-      yin = q < sg ? cand : yin;
-    }
-  } else {
-    for (int q = 0; q < sg; ++q) {
-      const int e = min(q * Ls + Ls, nz);
-      const int s0 = min(q * Ls, nz);
-      const R pend = e > s0 ? pf[e - 1] : R(1);
-      yin = xch[q][lane] + pend * yin;
-    }
+  for (int q = 0; q < NSEG - 1; ++q) {
+    const R cand = xch[q][lane] + lane_value(pfq, q) * yin;
+    yin = q < sg ? cand : yin;
   }
   __syncthreads();
   // true y, then the local backward recurrence (in place)
@@ -382,19 +370,10 @@ __device__ __forceinline__ void seg_join_store(R (&y)[SEG], R prev, R (*xch)[kSe
   xch[sg][lane] = nxt;  // local w at the segment's first level
   __syncthreads();
   R win = R(0);
-  if constexpr (!FINE) {
 #pragma unroll
-    for (int q = NSEG - 1; q > 0; --q) {
-      const R cand = xch[q][lane] + lane_value(qbq, q) * win;
-      win = q > sg ? cand : win;
-    }
-  } else {
-    for (int q = NSEG - 1; q > sg; --q) {
-      const int s0 = min(q * Ls, nz);
-      const int e = min(s0 + Ls, nz);
-      const R qs = e > s0 ? qb[s0] : R(1);
-      win = xch[q][lane] + qs * win;
-    }
+  for (int q = NSEG - 1; q > 0; --q) {
+    const R cand = xch[q][lane] + lane_value(qbq, q) * win;
+    win = q > sg ? cand : win;
   }
   if (valid) {
 #pragma unroll
