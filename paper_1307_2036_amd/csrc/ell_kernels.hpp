@@ -461,42 +461,58 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
     go = st->pending != 0;
     alpha = st->alpha;
   }
+  if constexpr (ZERO && !UPD) {
+    // no neighbour terms: every level's b is loaded first (levels past the
+    // segment's end repeat its last one and are discarded), then the forward
+    // recurrence runs in place, so no load waits behind a level's arithmetic
 #pragma unroll
-  for (int c0 = 0; c0 < SEG; c0 += 8) {
-    if (c0 < len) {
-      R g[8];
+    for (int t = 0; t < SEG; ++t) y[t] = (R)ld_s<FINE>(&bb[(long long)min(k0 + t, k1 - 1) * H]);
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int k = min(k0 + c0 + t, k1 - 1);
-        const long long o = (long long)k * H;
-        R v;
-        if constexpr (UPD) {
-          // the residual update of the CG step; only the lane that owns the
-          // column writes it (idle lanes, also those of blocks past the last
-          // column, read it and must not see their own write)
-          const double b0 = __builtin_nontemporal_load(&bb[o]);
-          const double q0 = __builtin_nontemporal_load(&qo[mm + o]);
-          const double rv = go ? b0 - alpha * q0 : b0;  // a select: q may hold anything without go
-          if (go && valid && c0 + t < len) {
-            __builtin_nontemporal_store(rv, &rw[mm + o]);
-            rr += rv * rv;
-          }
-          v = (R)rv;
-        } else {
-          v = (R)ld_s<FINE>(&bb[o]);
-        }
-        if (!ZERO) {
-          v = v + tx[k] * (uw[o] + ue[o]);
-          v = v + ty[k] * (us[o] + un[o]);
-        }
-        g[t] = v;
+    for (int t = 0; t < SEG; ++t) {
+      if (t < len) {
+        const int k = k0 + t;
+        prev = (y[t] + tz[k] * prev) * ip[k];
+        y[t] = prev;
       }
+    }
+  } else {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        if (c0 + t < len) {
-          const int k = k0 + c0 + t;
-          prev = (g[t] + tz[k] * prev) * ip[k];
-          y[c0 + t] = prev;
+    for (int c0 = 0; c0 < SEG; c0 += 8) {
+      if (c0 < len) {
+        R g[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int k = min(k0 + c0 + t, k1 - 1);
+          const long long o = (long long)k * H;
+          R v;
+          if constexpr (UPD) {
+            // the residual update of the CG step; only the lane that owns the
+            // column writes it (idle lanes, also those of blocks past the last
+            // column, read it and must not see their own write)
+            const double b0 = __builtin_nontemporal_load(&bb[o]);
+            const double q0 = __builtin_nontemporal_load(&qo[mm + o]);
+            const double rv = go ? b0 - alpha * q0 : b0;  // a select: q may hold anything without go
+            if (go && valid && c0 + t < len) {
+              __builtin_nontemporal_store(rv, &rw[mm + o]);
+              rr += rv * rv;
+            }
+            v = (R)rv;
+          } else {
+            v = (R)ld_s<FINE>(&bb[o]);
+          }
+          if (!ZERO) {
+            v = v + tx[k] * (uw[o] + ue[o]);
+            v = v + ty[k] * (us[o] + un[o]);
+          }
+          g[t] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          if (c0 + t < len) {
+            const int k = k0 + c0 + t;
+            prev = (g[t] + tz[k] * prev) * ip[k];
+            y[c0 + t] = prev;
+          }
         }
       }
     }
