@@ -455,9 +455,11 @@ def bench_serve(a):
                             f=torch.empty(shape, dtype=torch.float64, device="cuda"), w=w))
 
     def new_rhs(s):
-        f = torch.randn(s["f"].shape, generator=gen, device="cuda", dtype=torch.float64)
-        f -= (f * s["w"]).sum() / (s["w"].sum() * f.shape[1] * f.shape[2])
-        s["f"].copy_(f)
+        # in place: the stream's previous request has finished when this runs
+        # (four passes over f: the draw, the per-level sums, the subtraction)
+        f = s["f"]
+        torch.randn(f.shape, generator=gen, device="cuda", dtype=torch.float64, out=f)
+        f -= (f.sum(dim=(1, 2)) * s["w"].view(-1)).sum() / (s["w"].sum() * f.shape[1] * f.shape[2])
 
     def run(duration, rate):
         """rate None: closed loop (every stream always has one request)."""
