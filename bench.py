@@ -4,13 +4,21 @@ production-shaped problem (four-level hierarchy, five coarse sweeps).
 One step = one whole solve to a 1e-5 relative residual reduction from a zero
 initial guess, with f resident in HBM.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Beside the timed solve the default run reports, as extra keys of the same
+line: the error of the timed path's solution against the FP64 oracle at the
+same iteration count; the same problem with five levels, at standard depth
+and with the mixed-precision preconditioner; the 1024 x 1024 x 128 omega^2
+sweep in mixed precision and FP64; the 64-instance uneven batch; the serving
+loop; and the oracle timed on the host (1 thread and all threads) for the
+32 x 32 x 16, 512 x 512 x 128, 1024 x 1024 x 128 and batched workloads.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--quick]
+  python bench.py --workload c2|batch|serve|robust    (one workload, its own line)
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -33,9 +41,12 @@ def parse():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--nu-coarse", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true",
+                    help="the timed 512^2x128 solve only (no other workloads, no oracle legs)")
     ap.add_argument("--workload", default="c1", choices=["c1", "c2", "batch", "serve", "robust"],
-                    help="c1: the 512^2x128 solve (default); batch: 64 uneven solves in the "
-                         "batch engine vs sequential FP64; serve: Poisson request stream")
+                    help="c1: the 512^2x128 solve (default); c2: the 1024^2x128 omega^2 sweep; "
+                         "batch: 64 uneven solves in the batch engine vs sequential FP64; "
+                         "serve: Poisson request stream; robust: the robustness sweep")
     ap.add_argument("--autotune", action="store_true",
                     help="run the schedule autotuner on the workload's grid shape(s) before timing "
                          "(outside the timed region) and report the chosen schedule")
@@ -47,8 +58,6 @@ def parse():
                     help="arrival rate as a fraction of the measured closed-loop capacity")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run one plain device copy of a 268 MB vector (counter calibration)")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="minimum seconds of oracle work in the CPU-baseline sample")
     return ap.parse_args()
 
 
@@ -57,6 +66,15 @@ def _desc_kw(p, precision):
     return dict(nx=p.nx, ny=p.ny, nz=p.nz, hx=p.hx, hy=p.hy, omega2=p.omega2, dz=p.dz,
                 lambda2=p.lambda2, n_levels=p.n_levels, nu_pre=p.nu_pre, nu_post=p.nu_post,
                 nu_coarse=p.nu_coarse, rho=p.rho, prolong=p.prolong, precision=precision)
+
+
+def _rel(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def progress(what):
+    print(json.dumps({"progress": what}), file=sys.stderr, flush=True)
 
 
 def counter_traffic(precision: str):
@@ -74,44 +92,156 @@ def counter_traffic(precision: str):
     return rec["smooth0_traffic_bytes_per_launch"]
 
 
-def cpu_baseline(p, gpu_iters: int, min_seconds: float = 10.0, flexible: bool = True):
-    """The FP64 oracle, as it stands, on the host cores: whole solves of the
-    same problem (1e-5 reduction from u0 = 0, the same beta as the GPU solve),
-    repeated until at least min_seconds of CPU work have been timed."""
+def timed_solves(G, f, u, steps, flexible, rtol=1e-5, poll_every=8):
+    """Median wall time of `steps` solves from u0 = 0 (after one warm-up)."""
+    import numpy as np
+    import torch
+    u.zero_()
+    G.pcg_solve(f, u, rtol=rtol, flexible=flexible, poll_every=poll_every)
+    times = []
+    for _ in range(steps):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = G.pcg_solve(f, u, rtol=rtol, flexible=flexible, poll_every=poll_every)
+        times.append(time.perf_counter() - t0)
+    assert st.status == 0, st
+    return float(np.median(times)), st
+
+
+# ---------------------------------------------------------------------------
+# host (oracle) timings
+# ---------------------------------------------------------------------------
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cpus() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def oracle_leg(p, gpu_u, gpu_iters, flexible):
+    """The FP64 oracle, as it stands, on the host cores, for the 512 x 512 x 128
+    problem: (1) the solve stopped at the GPU's iteration count, compared with
+    the GPU's solution (parity of the timed path); (2) the oracle's own solve to
+    1e-5 on all threads (the baseline value); (3) two iterations on one thread
+    (a bounded sample, extrapolated to the whole solve)."""
     from oracle import oracle as O
     g = O.Grid.from_problem(p)
-    reps, dt, iters = 0, 0.0, 0
-    while dt < min_seconds and reps < 20:
+    nth = O.num_threads()
+    t0 = time.perf_counter()
+    u_k, st_k = O.pcg(g, p.f, rtol=0.0, maxiter=gpu_iters, flexible=flexible)
+    t_k = time.perf_counter() - t0
+    parity = {"rel_l2_vs_oracle": _rel(gpu_u, u_k), "oracle_iters_compared": gpu_iters,
+              "oracle_parity_seconds": t_k}
+    t0 = time.perf_counter()
+    _, st = O.pcg(g, p.f, rtol=p.rtol, flexible=flexible)
+    t_c = time.perf_counter() - t0
+    iters = st["iters"]
+    O.set_num_threads(1)
+    try:
         t0 = time.perf_counter()
-        u, st = O.pcg(g, p.f, rtol=p.rtol, flexible=flexible)
-        dt += time.perf_counter() - t0
-        reps += 1
-        iters = st["iters"]
-    return {"value": reps / dt, "unit": "solves/s", "cores": O.num_threads(), "kind": "oracle",
-            "unknowns_iter_per_s": p.n * iters * reps / dt, "seconds": dt, "oracle_iters": iters,
-            "sample": f"{reps} whole FP64 solves of the same {p.nx}x{p.ny}x{p.nz} problem "
-                      f"(1e-5 reduction, {iters} iterations each, OpenMP over columns)"}
+        O.pcg(g, p.f, rtol=0.0, maxiter=2, flexible=flexible)
+        t_1 = time.perf_counter() - t0
+    finally:
+        O.set_num_threads(nth)
+    base = {"value": 1.0 / t_c, "unit": "solves/s", "cores": nth, "kind": "oracle",
+            "unknowns_iter_per_s": p.n * iters / t_c, "seconds": t_c, "oracle_iters": iters,
+            "sample": f"1 whole FP64 solve of the same {p.nx}x{p.ny}x{p.nz} problem (1e-5 reduction, "
+                      f"{iters} iterations, OpenMP over columns on {nth} threads)",
+            "cpu_model": cpu_model(), "host_cpus": host_cpus(),
+            "one_thread": {"value": 1.0 / (t_1 * iters / 2.0), "unit": "solves/s", "cores": 1,
+                           "unknowns_iter_per_s": p.n * 2 / t_1, "seconds": t_1,
+                           "sample": "2 PCG iterations (setup and first V-cycle included) on 1 thread, "
+                                     f"extrapolated to the {iters}-iteration solve"}}
+    return parity, base
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
-        sys.exit(2)
-    if a.workload == "c2":
-        return bench_c2(a)
-    if a.workload == "robust":
-        return bench_robust(a)
-    if a.workload == "batch":
-        return bench_batch(a)
-    if a.workload == "serve":
-        return bench_serve(a)
+def oracle_small(p, flexible=False):
+    """Whole oracle solves of a small problem, repeated for >= 0.5 s, on all
+    threads and on one."""
+    from oracle import oracle as O
+    g = O.Grid.from_problem(p)
+    nth = O.num_threads()
+    out = {}
+    for label, th in (("all_threads", nth), ("one_thread", 1)):
+        O.set_num_threads(th)
+        try:
+            reps, dt = 0, 0.0
+            while dt < 0.5:
+                t0 = time.perf_counter()
+                _, st = O.pcg(g, p.f, rtol=p.rtol, flexible=flexible)
+                dt += time.perf_counter() - t0
+                reps += 1
+        finally:
+            O.set_num_threads(nth)
+        out[label] = {"solves_per_s": reps / dt, "cores": th, "iters": st["iters"],
+                      "unknowns_iter_per_s": p.n * st["iters"] * reps / dt}
+    return out
+
+
+def cpu_configs(extra):
+    """The oracle on the host: the 32 x 32 x 16 solve on all threads and one;
+    the 1024 x 1024 x 128 solve at omega^2 = 1e-2 on all threads, stopped at the
+    GPU FP64 solve's iteration count and compared with it; the 64 batched
+    instances solved one after another on all threads (the batch's FP32
+    solutions compared with the oracle's at the production tolerance)."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1307_2036_amd import inputs
+    nth = O.num_threads()
+    out = {"c0_32x32x16": oracle_small(inputs.config0())}
+    progress("oracle c0")
+    if "c2" in extra:
+        _, omega2, k = extra["c2"]["_problem"]
+        p = inputs.config2(omega2)
+        g = O.Grid.from_problem(p)
+        t0 = time.perf_counter()
+        u, st = O.pcg(g, p.f, rtol=0.0, maxiter=k, flexible=False)
+        dt = time.perf_counter() - t0
+        out["c2_1024x1024x128_omega2_1e-2"] = {
+            "cores": nth, "iters": k, "seconds": dt, "unknowns_iter_per_s": p.n * k / dt,
+            "solves_per_s": 1.0 / dt, "gpu_fp64_rel_l2_vs_oracle": _rel(extra["c2"]["_gpu_u"], u),
+            "sample": "one FP64 solve stopped at the GPU FP64 solve's iteration count"}
+        del p, g, u
+        progress("oracle c2")
+    if "c3" in extra:
+        ps = inputs.config3_instances(64)
+        dt, its, errs = 0.0, [], []
+        for p, ug in zip(ps, extra["c3"]["_gpu_u"]):
+            g = O.Grid.from_problem(p)
+            t0 = time.perf_counter()
+            u, st = O.pcg(g, p.f, rtol=p.rtol, flexible=False)
+            dt += time.perf_counter() - t0
+            its.append(st["iters"])
+            errs.append(_rel(ug, u))
+        out["c3_batch64_sequential"] = {
+            "cores": nth, "seconds": dt, "solves_per_s": len(ps) / dt, "iters_mean": float(np.mean(its)),
+            "unknowns_iter_per_s": float(sum(p.n * k for p, k in zip(ps, its)) / dt),
+            "gpu_batch_fp32_max_rel_err_vs_oracle": float(np.max(errs)),
+            "sample": "all 64 instances solved one after another to 1e-5 (FP64, printed beta)"}
+        progress("oracle c3")
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the 512 x 512 x 128 solve (the headline)
+# ---------------------------------------------------------------------------
+def bench_c1(a):
     import numpy as np
     import torch
 
     from paper_1307_2036_amd import ell, inputs, perfmodel
 
-    torch.cuda.set_device(0)
     p = inputs.config1(n_levels=a.levels, nu_coarse=a.nu_coarse, nx=a.nx)
     schedule = ell.autotune(iters=4, **_desc_kw(p, a.precision)) if a.autotune else \
         ell.schedule_get(**_desc_kw(p, a.precision))
@@ -120,9 +250,11 @@ def main():
     u = torch.zeros_like(f)
     n = p.n
     e = 8 if a.precision == "fp64" else 4
-    # the plain FP64 solve uses the classic beta of Appendix B's PCG (the
-    # V-cycle is symmetric); the mixed-precision preconditioner needs the
-    # flexible one
+    # the plain FP64 solve uses the printed beta of Appendix B's PCG (with the
+    # bilinear prolongation the V-cycle is not symmetric, but on this problem
+    # the printed beta stops at the same count as the flexible one); the
+    # mixed-precision preconditioner varies from call to call and needs the
+    # flexible beta
     flexible = a.precision != "fp64"
 
     def step():
@@ -206,6 +338,7 @@ def main():
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "true_rel_residual": st.true_r_norm / st.b_norm,
+        "cg_rel_residual": st.r_norm / st.r0_norm,
         "roofline": {"bound": "hbm", "kernel": "finest-level line relaxation, " + (
                          ("k_smooth_seg_upd, k_smooth_tile_upd, k_smooth_tile_pro, k_smooth_tile_dot3, FP64"
                           if fpro else "k_smooth_seg(_upd), k_smooth_tile(_upd), k_smooth_tile_dot x2, FP64")
@@ -220,11 +353,126 @@ def main():
                                "achieved_gbs": apply_gbs, "avg_launch_us": float(t_a.mean()) * 1e3},
         "schedule": dict(schedule, autotuned=bool(a.autotune)),
     }
+    progress("c1 timed")
+    gpu_u = u.cpu().numpy()
+    G.close()
+    del f, u
+    torch.cuda.empty_cache()
+
+    extra = {}
+    if not a.quick:
+        extra["c1_variants"] = c1_variants(p)
+        progress("c1 variants")
+        extra["c2"] = c2_sweep(steps=3)
+        progress("c2")
+        extra["c3"] = batch_summary(a, steps=5)
+        progress("c3")
+        extra["c4"] = serve_summary(a, seconds=min(a.serve_seconds, 6.0))
+        progress("c4")
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, iters, a.cpu_seconds, flexible)
+        parity, base = oracle_leg(p, gpu_u, iters, flexible)
+        out.update(parity)
+        progress("oracle c1")
+        if not a.quick:
+            base["configs"] = cpu_configs(extra)
+        out["cpu_baseline"] = base
+    for k in ("c2", "c3"):
+        if k in extra:
+            extra[k].pop("_gpu_u", None)
+            extra[k].pop("_problem", None)
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 
+def c1_variants(p0):
+    """The 512 x 512 x 128 problem with five levels (four coarsenings), at
+    standard depth (to one column) and with the mixed-precision V-cycle."""
+    import torch
+    from paper_1307_2036_amd import ell, inputs
+    out = {}
+    f = torch.from_numpy(p0.f).cuda()
+    u = torch.zeros_like(f)
+    for name, kw, prec in (("L5_nu_coarse5", dict(n_levels=5, nu_coarse=5), "fp64"),
+                           ("standard_depth", dict(n_levels=0, nu_coarse=1), "fp64"),
+                           ("L4_bf16coef", dict(n_levels=4, nu_coarse=5), "bf16coef"),
+                           ("L4_fp32", dict(n_levels=4, nu_coarse=5), "fp32")):
+        p = inputs.config1(with_f=False, **kw)
+        G = ell.Grid.from_problem(p, precision=prec)
+        flexible = prec != "fp64"
+        t, st = timed_solves(G, f, u, 5, flexible)
+        out[name] = {"levels": G.levels, "precision": prec, "beta": "flexible" if flexible else "classic",
+                     "iters": st.iters, "solves_per_s": 1.0 / t, "ms": t * 1e3,
+                     "unknowns_iter_per_s": p0.n * st.iters / t}
+        G.close()
+    del f, u
+    torch.cuda.empty_cache()
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 1024 x 1024 x 128 omega^2 sweep
+# ---------------------------------------------------------------------------
+def c2_sweep(steps=3, precision="bf16coef"):
+    """Per omega^2 in {1e-3, 1e-2, 1e-1}: the mixed-precision solve (BF16-rounded
+    stencil coefficients, FP32 V-cycle, FP64 CG; standard depth) and the plain
+    FP64 solve to 1e-5, timed, plus the error of a tight (1e-12) mixed solve
+    against the tight FP64 solve.  The FP64 solution at omega^2 = 1e-2 is kept
+    for the oracle comparison."""
+    import torch
+    from paper_1307_2036_amd import ell, inputs, perfmodel
+    rows, t_mixed, t_64 = [], 0.0, 0.0
+    keep = None
+    for omega2 in (1e-3, 1e-2, 1e-1):
+        p = inputs.config2(omega2)
+        f = torch.from_numpy(p.f).cuda()
+        u = torch.zeros_like(f)
+        per = {}
+        for name, pr in ((precision, precision), ("fp64", "fp64")):
+            G = ell.Grid.from_problem(p, precision=pr)
+            t, st = timed_solves(G, f, u, steps, pr != "fp64")
+            if pr == "fp64" and omega2 == 1e-2:
+                keep = (u.cpu().numpy(), st.iters)
+            ut = torch.zeros_like(f)
+            G.pcg_solve(f, ut, rtol=1e-12, maxiter=300)
+            per[name] = dict(iters=st.iters, s=t, tight=ut, levels=G.levels)
+            G.close()
+        mixed_bytes = perfmodel.pcg_iteration_bytes(p.n, per[precision]["levels"], 4) * per[precision]["iters"]
+        err = float(torch.linalg.vector_norm(per[precision]["tight"] - per["fp64"]["tight"]) /
+                    torch.linalg.vector_norm(per["fp64"]["tight"]))
+        rows.append({"omega2": omega2, "levels": per[precision]["levels"],
+                     "iters_mixed": per[precision]["iters"], "iters_fp64": per["fp64"]["iters"],
+                     "ms_mixed": per[precision]["s"] * 1e3, "ms_fp64": per["fp64"]["s"] * 1e3,
+                     "hbm_gbs_algorithmic_mixed": mixed_bytes / per[precision]["s"] / 1e9,
+                     "tight_rel_err_vs_fp64": err})
+        t_mixed += per[precision]["s"]
+        t_64 += per["fp64"]["s"]
+        del per, f, u
+        torch.cuda.empty_cache()
+    return {"workload": "gmg-pcg 1024x1024x128 graded, standard depth, omega2 in {1e-3,1e-2,1e-1}, "
+                        "rtol 1e-5, u0=0", "precision": precision,
+            "mixed_solves_per_s": 3 / t_mixed, "fp64_solves_per_s": 3 / t_64,
+            "speedup_vs_fp64": t_64 / t_mixed, "per_omega2": rows,
+            "_gpu_u": keep[0], "_problem": ("config2", 1e-2, keep[1])}
+
+
+def bench_c2(a):
+    s = c2_sweep(steps=max(a.steps // 4, 2), precision="bf16coef" if a.precision == "fp64" else a.precision)
+    s.pop("_gpu_u")
+    s.pop("_problem")
+    out = {
+        "metric": METRIC, "value": s["mixed_solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": 3,
+        "warmup": 1, "ms_per_step": 1e3 / s["mixed_solves_per_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64-outer/f32-vcycle",
+        "data": "synthetic (seeded N(0,1) f)",
+        "config": {"workload": s["workload"], "unknowns": 1024 * 1024 * 128, "precision": s["precision"]},
+    }
+    out.update({k: v for k, v in s.items() if k not in ("workload", "precision")})
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# 64 uneven solves in the batch engine
+# ---------------------------------------------------------------------------
 def _seq_fp64(problems, fs):
     """Plain FP64 single-grid solves one after another (the baseline)."""
     import torch
@@ -248,14 +496,14 @@ def _seq_fp64(problems, fs):
     return len(problems) / dt, iters
 
 
-def bench_batch(a):
-    """64 uneven solves (nx in {64..256}, nz in {64, 96, 128}, log-uniform omega^2)
-    advanced together by the batch engine with the FP32 preconditioner; one step
-    = all 64 solves from u0 = 0 to 1e-5."""
+def batch_summary(a, steps):
+    """64 uneven solves (nx in {64..256}, nz in {64, 96, 128}, log-uniform
+    omega^2) advanced together by the batch engine with the FP32 preconditioner;
+    one step = all 64 solves from u0 = 0 to 1e-5.  The solutions of the last
+    step are kept for the comparison with the oracle."""
     import numpy as np
     import torch
     from paper_1307_2036_amd import ell, inputs
-    torch.cuda.set_device(0)
     ps = inputs.config3_instances(64)
     fs = [torch.from_numpy(p.f).cuda() for p in ps]
     n_total = sum(p.n for p in ps)
@@ -275,7 +523,7 @@ def bench_batch(a):
     torch.cuda.synchronize()
     lat = []
     t0 = time.perf_counter()
-    for _ in range(a.steps):
+    for _ in range(steps):
         ts = time.perf_counter()
         st = step()
         lat.append(time.perf_counter() - ts)
@@ -283,86 +531,142 @@ def bench_batch(a):
     elapsed = time.perf_counter() - t0
     assert all(s.status == 0 for s in st)
     iters = [s.iters for s in st]
-    solves = len(ps) * a.steps / elapsed
+    solves = len(ps) * steps / elapsed
+    gpu_u = [u.cpu().numpy() for u in us]
+    for g in grids:
+        g.close()
+    B.close()
     seq, seq_iters = _seq_fp64(ps, fs)
+    del fs, us
+    torch.cuda.empty_cache()
+    return {"workload": "batch of 64 uneven gmg-pcg solves (nx in {64,96,128,192,256}, nz in {64,96,128}, "
+                        "log-uniform omega2), grouped launches, FP32 preconditioner, FP64 CG, 1e-5",
+            "unknowns_total": n_total, "precision": prec, "graph": a.batch_graph, "steps": steps,
+            "solves_per_s": solves,
+            "unknowns_iter_per_s": float(np.sum([p.n * it for p, it in zip(ps, iters)]) * steps / elapsed),
+            "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
+            "batch_ms_p50": float(np.percentile(np.array(lat) * 1e3, 50)),
+            "fp64_sequential_solves_per_s": seq, "fp64_sequential_iters_mean": float(np.mean(seq_iters)),
+            "speedup_vs_fp64_sequential": solves / seq,
+            "_gpu_u": gpu_u, "_problem": ("config3", None, None)}
+
+
+def bench_batch(a):
+    s = batch_summary(a, a.steps)
+    s.pop("_gpu_u")
+    s.pop("_problem")
     out = {
-        "metric": METRIC, "value": solves, "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": elapsed / a.steps * 1e3, "higher_is_better": True,
+        "metric": METRIC, "value": s["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 64e3 / s["solves_per_s"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64-outer/f32-vcycle",
         "data": "synthetic (64 seeded uneven instances)",
-        "config": {"workload": "batch of 64 uneven gmg-pcg solves (nx in {64,96,128,192,256}, "
-                               "nz in {64,96,128}, log-uniform omega2), grouped launches",
-                   "unknowns_total": n_total, "precision": prec, "graph": a.batch_graph},
-        "unknowns_iter_per_s": float(np.sum([p.n * it for p, it in zip(ps, iters)]) * a.steps / elapsed),
-        "iters_mean": float(np.mean(iters)), "iters_max": int(np.max(iters)),
-        "batch_ms_p50": float(np.percentile(np.array(lat) * 1e3, 50)),
-        "fp64_sequential_solves_per_s": seq, "fp64_sequential_iters_mean": float(np.mean(seq_iters)),
-        "speedup_vs_fp64_sequential": solves / seq,
+        "config": {"workload": s["workload"], "unknowns_total": s["unknowns_total"],
+                   "precision": s["precision"], "graph": s["graph"]},
     }
+    out.update({k: v for k, v in s.items() if k not in ("workload", "unknowns_total", "precision", "graph")})
     print(json.dumps(out), flush=True)
-    B.close()
 
 
-def bench_c2(a):
-    """Mixed precision at 1024x1024x128 (graded, standard depth), omega^2 swept
-    over {1e-3, 1e-2, 1e-1}: per omega^2 the mixed-precision solve (BF16-rounded
-    stencil coefficients, FP32 V-cycle, FP64 CG; or --precision fp32) and the
-    plain FP64 solve to 1e-5, timed, plus the error of a tight (1e-12) mixed
-    solve against the tight FP64 solve on the same GPU.  value = solves/s of the
-    mixed path over the sweep (one solve per omega^2 per step)."""
+# ---------------------------------------------------------------------------
+# serving
+# ---------------------------------------------------------------------------
+SERVE_SIZES = [256] * 17 + [512] * 6 + [1024]
+
+
+def serve_summary(a, seconds):
+    """Serving: Poisson arrivals of pressure solves on 24 resident streams
+    (17 x 256^2, 6 x 512^2, 1 x 1024^2, nz = 128; uniform stream choice gives
+    the 70/25/5 % mix), omega^2 in {1e-2, 5e-2}, fresh f ~ N(0,1) per request,
+    warm start from the stream's previous solution, 1e-5 relative to ||b||,
+    200 GB budget, FP32 preconditioner, continuous batching
+    (paper_1307_2036_amd/serve.py).  The closed-loop capacity is measured
+    first, then arrivals at `load` times that rate."""
     import numpy as np
     import torch
-    from paper_1307_2036_amd import ell, inputs, perfmodel
-    torch.cuda.set_device(0)
-    prec = "bf16coef" if a.precision == "fp64" else a.precision
-    rows, t_mixed, t_64 = [], 0.0, 0.0
-    for omega2 in (1e-3, 1e-2, 1e-1):
-        p = inputs.config2(omega2)
-        f = torch.from_numpy(p.f).cuda()
-        p.f = None
-        u = torch.zeros_like(f)
-        per = {}
-        for name, pr in ((prec, prec), ("fp64", "fp64")):
-            G = ell.Grid.from_problem(p, precision=pr)
-            G.pcg_solve(f, u, rtol=p.rtol, flexible=pr != "fp64")  # warm-up
-            times = []
-            for _ in range(max(a.steps // 4, 2)):
-                u.zero_()
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                _, st = G.pcg_solve(f, u, rtol=p.rtol, poll_every=8, flexible=pr != "fp64")
-                times.append(time.perf_counter() - t0)
-            assert st.status == 0, st
-            ut = torch.zeros_like(f)
-            G.pcg_solve(f, ut, rtol=1e-12, maxiter=300)
-            per[name] = dict(iters=st.iters, s=float(np.median(times)), tight=ut, levels=G.levels)
-            G.close()
-        e = 8 if prec == "fp64" else 4
-        mixed_bytes = perfmodel.pcg_iteration_bytes(p.n, per[prec]["levels"], e) * per[prec]["iters"]
-        err = float(torch.linalg.vector_norm(per[prec]["tight"] - per["fp64"]["tight"]) /
-                    torch.linalg.vector_norm(per["fp64"]["tight"]))
-        rows.append({"omega2": omega2, "levels": per[prec]["levels"], "iters_mixed": per[prec]["iters"],
-                     "iters_fp64": per["fp64"]["iters"], "ms_mixed": per[prec]["s"] * 1e3,
-                     "ms_fp64": per["fp64"]["s"] * 1e3,
-                     "hbm_gbs_algorithmic_mixed": mixed_bytes / per[prec]["s"] / 1e9,
-                     "tight_rel_err_vs_fp64": err})
-        t_mixed += per[prec]["s"]
-        t_64 += per["fp64"]["s"]
-        del per, f, u
-        torch.cuda.empty_cache()
+    from paper_1307_2036_amd import ell, inputs
+    from paper_1307_2036_amd import serve as S
+    rng = np.random.default_rng(inputs.seed_for(4))
+    prec = "fp32" if a.precision == "fp64" else a.precision
+    ell.set_tuning(ell.ELL_TUNE_BATCH_GRAPH, a.batch_graph)
+    B = ell.Batch(200 << 30)
+    problems = []
+    for idx, nx in enumerate(SERVE_SIZES):
+        omega2 = float(rng.choice([1e-2, 5e-2]))
+        problems.append(inputs.graded_problem(f"stream{idx}", nx, 128, omega2, inputs.seed_for(4, idx),
+                                              inputs.seed_for(4, idx, stream=1), with_f=False))
+    eng = S.BatchEngine(B, problems, precision=prec, rtol=1e-5, seed=inputs.seed_for(4, stream=2))
+    loop = S.ServingLoop(len(problems), eng)
+    loop.run(2.0)  # warm-up: every stream solved at least once
+    done, el, _ = loop.run(seconds / 2)
+    cap = S.summary(done, el)
+    rate = a.serve_load * cap["solves_per_s"]
+    arr = S.PoissonArrivals(rate, len(problems), rng, t0=time.perf_counter())
+    done, el, backlog = loop.run(seconds, arr)
+    load = S.summary(done, el)
+    resident = B.bytes_in_use()
+    # plain FP64 sequential baseline on the same GPU: for each size class, the
+    # median of nine requests with the same semantics (fresh f drawn on the GPU
+    # as in the serving loop, warm start, 1e-5 of ||b||) solved one after
+    # another with the single-grid FP64 path; mix-weighted
+    classes = {256: 17 / 24, 512: 6 / 24, 1024: 1 / 24}
+    t_class = {}
+    for nx in classes:
+        i = SERVE_SIZES.index(nx)
+        s0 = eng.streams[i]
+        G = ell.Grid.from_problem(problems[i])
+        u = torch.zeros_like(s0["u"])
+        eng.new_rhs(s0)
+        G.pcg_solve(s0["f"], u, rtol=1e-5, rel_to_rhs=True, flexible=False)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(9):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eng.new_rhs(s0)
+            G.pcg_solve(s0["f"], u, rtol=1e-5, rel_to_rhs=True, flexible=False)
+            times.append(time.perf_counter() - t0)
+        t_class[nx] = float(np.median(times))
+        G.close()
+    seq = 1.0 / sum(w * t_class[nx] for nx, w in classes.items())
+    eng.close()
+    B.close()
+    torch.cuda.empty_cache()
+    return {"workload": "serving: 24 streams (17x256^2, 6x512^2, 1x1024^2, nz=128), Poisson arrivals, "
+                        "warm starts, continuous batching, 200 GB budget, FP32 preconditioner",
+            "precision": prec, "graph": a.batch_graph, "load": a.serve_load, "arrival_rate_per_s": rate,
+            "solves_per_s": load["solves_per_s"], "served": load["served"], "backlog_at_end": backlog,
+            "p50_ms": load["p50_ms"], "p99_ms": load["p99_ms"], "iters_mean": load["iters_mean"],
+            "failed": load["failed"] + cap["failed"],
+            "closed_loop_capacity_solves_per_s": cap["solves_per_s"],
+            "closed_loop_p50_ms": cap["p50_ms"], "closed_loop_p99_ms": cap["p99_ms"],
+            "hbm_resident_gb": resident / 1e9,
+            "fp64_sequential_solves_per_s": seq,
+            "fp64_sequential_ms_by_size": {str(k): v * 1e3 for k, v in t_class.items()},
+            "speedup_vs_fp64_sequential": load["solves_per_s"] / seq,
+            "capacity_speedup_vs_fp64_sequential": cap["solves_per_s"] / seq}
+
+
+def bench_serve(a):
+    s = serve_summary(a, a.serve_seconds)
+    thr = s["solves_per_s"]
     out = {
-        "metric": METRIC, "value": 3 / t_mixed, "unit": "solves/s", "n_gpus": 1, "steps": 3,
-        "warmup": 1, "ms_per_step": t_mixed * 1e3 / 3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64-outer/f32-vcycle", "data": "synthetic (seeded N(0,1) f)",
-        "config": {"workload": "gmg-pcg 1024x1024x128 graded, standard depth, omega2 in {1e-3,1e-2,1e-1}, "
-                               "rtol 1e-5, u0=0", "unknowns": 1024 * 1024 * 128, "precision": prec},
-        "fp64_solves_per_s": 3 / t_64, "speedup_vs_fp64": t_64 / t_mixed, "per_omega2": rows,
+        "metric": METRIC, "value": thr, "unit": "solves/s", "n_gpus": 1, "steps": s["served"],
+        "warmup": 0, "ms_per_step": 1e3 / thr if thr else None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64-outer/f32-vcycle",
+        "data": "synthetic (seeded Poisson arrivals, fresh N(0,1) f per request)",
+        "config": {"workload": s["workload"], "arrival_rate_per_s": s["arrival_rate_per_s"],
+                   "load": s["load"], "precision": s["precision"], "graph": s["graph"]},
     }
+    out.update({k: v for k, v in s.items() if k not in ("workload", "precision", "graph", "load",
+                                                         "arrival_rate_per_s")})
     print(json.dumps(out), flush=True)
 
 
+# ---------------------------------------------------------------------------
+# robustness sweep (stand-alone multigrid variants, Sec. 7.3)
+# ---------------------------------------------------------------------------
 def bench_robust(a):
-    """Robustness sweep of Sec. 7.3 (Table 7, 3.4e7 unknowns): the flat analogue
+    """Robustness sweep of Sec. 7.3 (Table 6, 3.4e7 unknowns): the flat analogue
     of the paper's 512^2 x 128 run (Table 1 parameters: C_horiz = 17.8,
     lambda^2 = 0.0332, the paper's vertical grading with H = 1/100), omega^2
     scaled by f in {1, 10, 100} and lambda^2 by {1e-2, 1e2}; stand-alone
@@ -375,7 +679,6 @@ def bench_robust(a):
     import numpy as np
     import torch
     from paper_1307_2036_amd import ell, inputs
-    torch.cuda.set_device(0)
     nx, nz = 512, 128
     h = math.pi / (2 * nx)
     dz = inputs.dz_paper_grading(nz, 0.01)
@@ -415,10 +718,10 @@ def bench_robust(a):
         "steps": len(cases), "warmup": 1, "ms_per_step": t_std * 1e3 / len(cases),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded N(0,1) f; the paper's Table 1 parameters on a flat periodic panel)",
-        "config": {"workload": "robustness sweep 512x512x128 (Table 7): omega2 x {1,10,100}, "
+        "config": {"workload": "robustness sweep 512x512x128 (Table 6): omega2 x {1,10,100}, "
                                "lambda2 x {1e-2,1e2}; standard/shallow/very shallow stand-alone GMG, "
                                "CG with line relaxation, GMG-PCG", "unknowns": nx * nx * nz},
-        "paper_table7_iters": {"standard_mg": [6, 6, 6, 6, 8], "shallow_mg": [6, 6, 6, 6, 10],
+        "paper_table6_iters": {"standard_mg": [6, 6, 6, 6, 8], "shallow_mg": [6, 6, 6, 6, 10],
                                "very_shallow_mg": [6, 6, 6, 15, 100],
                                "cg_line_relaxation": [43, 42, 42, 140, 300]},
         "rows": rows,
@@ -426,133 +729,22 @@ def bench_robust(a):
     print(json.dumps(out), flush=True)
 
 
-def bench_serve(a):
-    """Serving: Poisson arrivals of pressure solves on 24 resident streams
-    (17 x 256^2, 6 x 512^2, 1 x 1024^2, nz = 128; uniform stream choice gives
-    the 70/25/5 % mix), omega^2 in {1e-2, 5e-2}, fresh f ~ N(0,1) per request,
-    warm start from the stream's previous solution, 1e-5 relative to ||b||,
-    200 GB budget, FP32 preconditioner, continuous batching."""
-    import numpy as np
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
     import torch
-    from paper_1307_2036_amd import ell, inputs
     torch.cuda.set_device(0)
-    rng = np.random.default_rng(inputs.seed_for(4))
-    sizes = [256] * 17 + [512] * 6 + [1024]
-    prec = "fp32" if a.precision == "fp64" else a.precision
-    ell.set_tuning(ell.ELL_TUNE_BATCH_GRAPH, a.batch_graph)
-    B = ell.Batch(200 << 30)
-    streams = []
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(inputs.seed_for(4, stream=2))
-    for idx, nx in enumerate(sizes):
-        omega2 = float(rng.choice([1e-2, 5e-2]))
-        p = inputs.graded_problem(f"stream{idx}", nx, 128, omega2, inputs.seed_for(4, idx),
-                                  inputs.seed_for(4, idx, stream=1), with_f=False)
-        g = B.grid(p, precision=prec)
-        shape = (p.nz, p.ny, p.nx)
-        w = torch.from_numpy(p.dz).cuda().view(-1, 1, 1)
-        streams.append(dict(p=p, g=g, u=torch.zeros(shape, dtype=torch.float64, device="cuda"),
-                            f=torch.empty(shape, dtype=torch.float64, device="cuda"), w=w))
-
-    def new_rhs(s):
-        # in place: the stream's previous request has finished when this runs
-        # (four passes over f: the draw, the per-level sums, the subtraction)
-        f = s["f"]
-        torch.randn(f.shape, generator=gen, device="cuda", dtype=torch.float64, out=f)
-        f -= (f.sum(dim=(1, 2)) * s["w"].view(-1)).sum() / (s["w"].sum() * f.shape[1] * f.shape[2])
-
-    def run(duration, rate):
-        """rate None: closed loop (every stream always has one request)."""
-        pending = {}
-        done_lat, done_iters = [], []
-        t_start = time.perf_counter()
-        next_arrival = t_start
-        queue_per_stream = [[] for _ in streams]  # arrivals waiting for their stream
-        busy = [False] * len(streams)
-        n_done = 0
-        while True:
-            now = time.perf_counter()
-            if now - t_start > duration:
-                break
-            if rate is None:
-                for i, s in enumerate(streams):
-                    if not busy[i]:
-                        queue_per_stream[i].append(now)
-            else:
-                while next_arrival <= now:
-                    i = int(rng.integers(len(streams)))
-                    queue_per_stream[i].append(next_arrival)
-                    next_arrival += rng.exponential(1.0 / rate)
-            for i, s in enumerate(streams):
-                if not busy[i] and queue_per_stream[i]:
-                    t_arr = queue_per_stream[i].pop(0)
-                    new_rhs(s)
-                    t = B.submit([s["g"]], [s["f"]], [s["u"]], rtol=1e-5, rel_to_rhs=True, poll_every=1)
-                    pending[t] = (i, t_arr)
-                    busy[i] = True
-            for t in list(pending):
-                r = B.poll(t)
-                if r is not None:
-                    i, t_arr = pending.pop(t)
-                    B.wait(t)
-                    done_lat.append(time.perf_counter() - t_arr)
-                    done_iters.append(r[0].iters)
-                    busy[i] = False
-                    n_done += 1
-            time.sleep(0.0002)
-        for t in list(pending):
-            B.wait(t)
-        elapsed = time.perf_counter() - t_start
-        return n_done / elapsed, np.array(done_lat) * 1e3, done_iters
-
-    run(2.0, None)  # warm-up: every stream solved at least once
-    capacity, _, _ = run(a.serve_seconds / 2, None)
-    rate = a.serve_load * capacity
-    thr, lat, iters = run(a.serve_seconds, rate)
-    # plain FP64 sequential baseline on the same GPU: for each size class, a few
-    # requests with the same semantics (fresh f generated on the GPU as in the
-    # serving loop, warm start, 1e-5 of ||b||) solved one after another with the
-    # single-grid FP64 path; mix-weighted
-    classes = {256: 17 / 24, 512: 6 / 24, 1024: 1 / 24}
-    t_class = {}
-    for nx, wgt in classes.items():
-        s0 = next(s for s in streams if s["p"].nx == nx)
-        G = ell.Grid.from_problem(s0["p"])
-        u = torch.zeros_like(s0["u"])
-        new_rhs(s0)
-        G.pcg_solve(s0["f"], u, rtol=1e-5, rel_to_rhs=True, flexible=False)
-        torch.cuda.synchronize()
-        times = []
-        for _ in range(9):  # the median of nine warm-started requests per size
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            new_rhs(s0)
-            G.pcg_solve(s0["f"], u, rtol=1e-5, rel_to_rhs=True, flexible=False)
-            times.append(time.perf_counter() - t0)
-        t_class[nx] = float(np.median(times))
-        G.close()
-    seq = 1.0 / sum(w * t_class[nx] for nx, w in classes.items())
-    out = {
-        "metric": METRIC, "value": thr, "unit": "solves/s", "n_gpus": 1, "steps": len(lat),
-        "warmup": 0, "ms_per_step": 1e3 / thr if thr else None, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64-outer/f32-vcycle",
-        "data": "synthetic (seeded Poisson arrivals, fresh N(0,1) f per request)",
-        "config": {"workload": "serving: 24 streams (17x256^2, 6x512^2, 1x1024^2, nz=128), "
-                               "Poisson arrivals, warm starts, continuous batching, 200 GB budget",
-                   "arrival_rate_per_s": rate, "load": a.serve_load, "precision": prec,
-                   "graph": a.batch_graph},
-        "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,
-        "p99_ms": float(np.percentile(lat, 99)) if len(lat) else None,
-        "closed_loop_capacity_solves_per_s": capacity,
-        "iters_mean": float(np.mean(iters)) if iters else None,
-        "hbm_resident_gb": B.bytes_in_use() / 1e9,
-        "fp64_sequential_solves_per_s": seq,
-        "fp64_sequential_ms_by_size": {str(k): v * 1e3 for k, v in t_class.items()},
-        "speedup_vs_fp64_sequential": thr / seq,
-        "capacity_speedup_vs_fp64_sequential": capacity / seq,
-    }
-    print(json.dumps(out), flush=True)
-    B.close()
+    if a.workload == "c2":
+        return bench_c2(a)
+    if a.workload == "robust":
+        return bench_robust(a)
+    if a.workload == "batch":
+        return bench_batch(a)
+    if a.workload == "serve":
+        return bench_serve(a)
+    return bench_c1(a)
 
 
 if __name__ == "__main__":

@@ -275,8 +275,9 @@ int ell_set_tuning(int key, int value);
  * A schedule fixes how a grid of one shape runs on the chip, not what it
  * computes (every schedule gives the same iterates up to rounding order): the
  * CG operator step's kernel (LDS-tiled or column-walking) and its k-segments,
- * and the line smoother's k-segments on each coarse level (the finest level
- * always uses 4).  Schedules are kept process-wide per shape (nx, ny, nz,
+ * and the line smoother's k-segments on every level (4 or 8 on the finest
+ * level, 8 where a segment then holds at most 16 levels; 4, 8 or 16 on the
+ * coarse ones).  Schedules are kept process-wide per shape (nx, ny, nz,
  * number of levels, FP64 or mixed precision); a grid created afterwards uses
  * the schedule recorded for its shape, else the built-in heuristics.  Batch
  * grids take the operator-step part only (their smoother layout is uniform).
@@ -286,7 +287,7 @@ typedef struct {
   int32_t apply_tile;                  /* 1: LDS-tiled operator step, 0: column-walking */
   int32_t apply_nseg;                  /* k-segments of the operator step: 1, 2 or 4 */
   int32_t smooth_nseg[ELL_MAX_LEVELS]; /* per level: line-smoother k-segments, 4, 8 or 16
-                                          (entry 0 is 4; entries past the last level 0) */
+                                          (entry 0 is 4 or 8; entries past the last level 0) */
   double ms_per_iter;                  /* ell_autotune: measured milliseconds per PCG
                                           iteration of the chosen schedule; otherwise 0 */
 } ell_schedule;

@@ -173,7 +173,8 @@ ELL_FEAT_TILED_ENDS = 16
 
 
 def set_tuning(key: int, value: int) -> None:
-    """Layout padding for grids created afterwards (process-wide)."""
+    """Set one process-wide tuning key (ELL_TUNE_*: layout padding, kernel
+    choices and fused forms) for grids and batches created afterwards."""
     _check(load_library().ell_set_tuning(key, value))
 
 

@@ -23,7 +23,12 @@ def check_solve(orc, g, f, u_gpu, st_gpu, rtol, tol=1e-10, **opts):
     u_k, st_k = orc.pcg(g, f, rtol=0.0, maxiter=max(st_gpu.iters, 1), **opts)
     _, st_conv = orc.pcg(g, f, rtol=rtol, **opts)
     k_orc = st_conv["iters"]
-    err = rel(u_gpu, u_k) if st_gpu.iters > 0 else rel(u_gpu + 1.0, np.ones_like(u_gpu))
+    if st_gpu.iters > 0:
+        err = rel(u_gpu, u_k)
+    elif opts.get("u0") is not None:   # nothing to do: the initial guess comes back unchanged
+        err = float(np.abs(u_gpu - opts["u0"]).max())
+    else:
+        err = rel(u_gpu + 1.0, np.ones_like(u_gpu))
     info = dict(k_gpu=st_gpu.iters, k_orc=k_orc, rel_l2=err,
                 ratio_gpu=st_gpu.r_norm / st_gpu.r0_norm if st_gpu.r0_norm else 0.0,
                 ratio_orc=st_conv["r_norm"] / st_conv["r0_norm"] if st_conv["r0_norm"] else 0.0)

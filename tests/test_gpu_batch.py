@@ -67,6 +67,26 @@ def test_batch_alone_equals_in_mix_and_oracle(E, orc, precision):
     B.close()
 
 
+def test_batch_fp32_validation_mode(E, orc):
+    """The FP32 preconditioner in the batch, validation mode: every instance of
+    the uneven mix solved together to rtol 1e-12 lies within 1e-8 of the FP64
+    oracle's tight solution (the precision of the preconditioner changes the
+    iterates, not the discrete solution)."""
+    ps = problems()
+    B = E.Batch(8 << 30)
+    grids = [B.grid(p, precision="fp32") for p in ps]
+    fs = [dev(p.f) for p in ps]
+    us = [torch.zeros_like(f) for f in fs]
+    st = B.wait(B.submit(grids, fs, us, rtol=1e-12, maxiter=400))
+    for p, u, s in zip(ps, us, st):
+        assert s.status == 0, (p.name, s)
+        u_ref, s_ref = orc.pcg(orc.Grid.from_problem(p), p.f, rtol=1e-12, maxiter=400)
+        err = float(np.linalg.norm(host(u) - u_ref) / np.linalg.norm(u_ref))
+        print(p.name, "iters", s.iters, s_ref["iters"], "rel", err)
+        assert err <= 1e-8, (p.name, err)
+    B.close()
+
+
 def test_batch_matches_single_grid_path(E, orc):
     """The batch (4- or 8-segment coarse levels, grouped kernels) and the
     single-grid path solve the same problem to the same iterates."""
@@ -251,6 +271,29 @@ def test_config3_batch_at_full_size(E, orc):
         assert st[i].iters <= st_ref["iters"] + 2, (i, st[i].iters, st_ref["iters"])
         u = host(us[i])
         assert np.linalg.norm(u - u_ref) <= 1e-4 * np.linalg.norm(u_ref), i
+    B.close()
+
+
+@pytest.mark.slow
+def test_config3_batch_fp32_validation_mode(E, orc):
+    """The 64 instances of the batched workload together with the FP32
+    preconditioner to rtol 1e-12: the two largest and four sampled instances
+    lie within 1e-8 of the FP64 oracle's tight solutions."""
+    ps = I.config3_instances(64)
+    B = E.Batch(200 << 30)
+    grids = [B.grid(p, precision="fp32") for p in ps]
+    fs = [dev(p.f) for p in ps]
+    us = [torch.zeros_like(f) for f in fs]
+    st = B.wait(B.submit(grids, fs, us, rtol=1e-12, maxiter=400, poll_every=4))
+    assert all(s.status == 0 for s in st)
+    sizes = [p.n for p in ps]
+    picks = sorted(set([int(np.argmax(sizes)), int(np.argsort(sizes)[-2])] +
+                       list(np.random.default_rng(3).choice(64, 4, replace=False))))
+    for i in picks:
+        u_ref, s_ref = orc.pcg(orc.Grid.from_problem(ps[i]), ps[i].f, rtol=1e-12, maxiter=400)
+        err = float(np.linalg.norm(host(us[i]) - u_ref) / np.linalg.norm(u_ref))
+        print(ps[i].name, "iters", st[i].iters, s_ref["iters"], "rel", err)
+        assert err <= 1e-8, (i, err)
     B.close()
 
 

@@ -76,3 +76,40 @@ def test_fullsize_solve(orc, c1):
     assert st.status == 0
     info = check_solve(orc, g, p.f, host(u), st, p.rtol)
     print("solve parity", info)
+
+
+def test_fullsize_solve_printed_beta(orc, c1):
+    """The solve the benchmark times: the printed beta of Appendix B's PCG,
+    which takes the fused finest prolongation (k_smooth_tile_pro) and the
+    colour-0 sweep forming <r, z> of both colours (k_smooth_tile_dot3), against
+    the oracle with the same beta at the full 512 x 512 x 128 size."""
+    from solve_parity import check_solve
+    p, g, G = c1
+    assert G.features["fused_prolong"] and G.features["fused_dots"] and G.features["fused_update"]
+    f = dev(p.f)
+    u = torch.zeros_like(f)
+    _, st = G.pcg_solve(f, u, rtol=p.rtol, maxiter=500, poll_every=8, flexible=False)
+    assert st.status == 0
+    info = check_solve(orc, g, p.f, host(u), st, p.rtol, flexible=False)
+    print("printed-beta solve parity", info)
+
+
+@pytest.mark.parametrize("levels,nu_coarse", [(5, 5), (0, 1)])
+def test_fullsize_solve_other_depths(orc, levels, nu_coarse):
+    """The same problem with four coarsenings (five levels, five coarsest
+    sweeps; the other reading of the configuration's 'four coarsening
+    levels') and at standard depth (ten levels, down to one column), printed
+    beta, against the oracle."""
+    from paper_1307_2036_amd import ell
+    from solve_parity import check_solve
+    p = I.config1(n_levels=levels, nu_coarse=nu_coarse)
+    g = orc.Grid.from_problem(p)
+    G = ell.Grid.from_problem(p)
+    assert G.levels == (levels or 10) == orc.num_levels(g)
+    f = dev(p.f)
+    u = torch.zeros_like(f)
+    _, st = G.pcg_solve(f, u, rtol=p.rtol, poll_every=8, flexible=False)
+    assert st.status == 0
+    info = check_solve(orc, g, p.f, host(u), st, p.rtol, flexible=False)
+    print("levels", G.levels, "solve parity", info)
+    G.close()

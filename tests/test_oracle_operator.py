@@ -135,3 +135,25 @@ def test_standard_depth(orc):
     assert orc.standard_levels(4, 2) == 2        # 4x2 -> 2x1
     assert orc.standard_levels(6, 6) == 1
     assert orc.standard_levels(1, 1) == 1
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 4), (2, 4, 3), (4, 2, 4), (1, 4, 3), (4, 1, 3), (1, 1, 4), (2, 2, 2)])
+def test_apply_abs_is_abs_matrix_times_abs_vector(orc, shape):
+    """The error scale of the operator comparisons, sum over the terms of
+    (A x)_c of their absolute values, is |A| |x| of the dense matrix (every
+    coefficient is positive, so |V x_c| + sum T (|x_c| + |x_nbr|) equals the
+    absolute diagonal times |x_c| plus the absolute off-diagonals times the
+    neighbours).  The dense matrix comes from the operator, which the closed
+    forms above pin; periodic neighbours that coincide (size 2) and omitted
+    faces (size 1) are covered."""
+    nx, ny, nz = shape
+    g = small_grid(orc, nx, ny, nz, seed=5 * nx + 3 * ny + nz)
+    A = dense_from_apply(lambda x: orc.apply(g, x), g.shape)
+    rng = np.random.default_rng(17)
+    for _ in range(4):
+        x = rng.standard_normal(g.shape)
+        got = orc.apply_abs(g, x).ravel()
+        ref = np.abs(A) @ np.abs(x.ravel())
+        assert np.all(np.abs(got - ref) <= 1e-13 * ref), np.abs(got - ref).max()
+        # and it bounds the operator itself
+        assert np.all(np.abs(orc.apply(g, x)).ravel() <= got * (1 + 1e-14))
