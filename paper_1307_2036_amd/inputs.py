@@ -180,6 +180,21 @@ def graded_problem(name: str, nx: int, nz: int, omega2: float, seed_f: int,
                    nu_coarse=nu_coarse, seeds={"f": seed_f, "lambda": seed_lambda})
 
 
+def paper_graded_problem(name: str, nx: int, ny: int, nz: int, omega2: float, seed_f: int,
+                         seed_lambda: int, depth: float = 1.0, sigma: float = 0.3) -> Problem:
+    """nx x ny x nz with the paper's level placement (eq. VerticalGrading,
+    thicknesses growing linearly with height), h = 1/nx and 1/ny,
+    lambda^2 = (hx/dz)^2 * smooth log-normal perturbation, f ~ N(0,1).  Over
+    depth 1 the vertical couplings stay within ~1e15 of the cell volumes, so
+    FP64 resolves the residual of the solve (the quadratic grading over depth
+    1/50 does not at 192 or more levels)."""
+    dz = dz_paper_grading(nz, depth)
+    lam = lambda2_perturbed(1.0 / nx, dz, sigma, seed_lambda)
+    f = rhs_normal(nx, ny, dz, seed_f)
+    return Problem(name, nx, ny, nz, 1.0 / nx, 1.0 / ny, dz, lam, omega2, f,
+                   seeds={"f": seed_f, "lambda": seed_lambda})
+
+
 def config1(n_levels: int = 4, nu_coarse: int = 5, nx: int = 512, nz: int = 128,
             with_f: bool = True) -> Problem:
     """512x512x128 graded, omega^2 = 1e-2, four-level hierarchy, 5 coarse sweeps."""
