@@ -147,6 +147,22 @@ int ell_grid_features(const ell_grid *g, int32_t *mask);
  * x, y: device, plane-major, nx*ny*nz doubles, must not alias. */
 int ell_apply_A(ell_grid *g, const double *x, double *y, hipStream_t stream);
 
+/* y = A x without a grid object and without allocating device memory, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  desc describes the grid as for
+ * ell_grid_create (validated the same way; its multigrid and precision fields
+ * do not change the result); x, y: device, plane-major, nx*ny*nz doubles,
+ * must not alias; the values are those ell_apply_A gives for a grid created
+ * from desc.  The finest level's stencil coefficients (4 x (nz+1) doubles) go
+ * into a fixed library-owned device area of 32.8 KB per GPU, held until the
+ * process ends; nz > ELL_NOALLOC_MAX_NZ returns ELL_ERR_INVALID.  No hipMalloc,
+ * hipFree, host-to-device copy or other allocating call is made: the
+ * coefficients travel in kernel arguments.  All calls on one GPU share that
+ * area: calls on one stream are ordered, calls that overlap on one GPU
+ * (several streams or host threads) race.  Asynchronous like ell_apply_A. */
+#define ELL_NOALLOC_MAX_NZ 1024
+int ell_apply_A_noalloc(const ell_grid_desc *desc, const double *x, double *y, hipStream_t stream);
+
 /* z = M^{-1} r: one V-cycle (Alg. "Multigrid V-cycle") from a zero initial
  * guess with right-hand side r.  Runs in the grid's precision; r and z are
  * FP64 device vectors, plane-major, must not alias. */

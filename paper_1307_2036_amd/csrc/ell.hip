@@ -310,25 +310,34 @@ void segment_products(int nz, int nseg, const T *Tz, const T *ip, const T *cf, T
 // is the part of the diagonal that the vertical couplings do not cancel.
 // Face coefficients: omega^2 * area / distance; vertical faces combine the two
 // half-cell resistances dz/(2 lambda^2) in series (Sec. 3.1).
-void level_table64(const ell_grid *g, int l, std::vector<double> &t) {
-  const int nz = g->d.nz, P = nz + 1;
-  const int nx = g->d.nx >> l, ny = g->d.ny >> l;
-  const double hx = g->d.hx * (double)(1 << l), hy = g->d.hy * (double)(1 << l);
-  const double w2 = g->d.omega2;
-  t.assign((size_t)TSLOTS * P, 0.0);
+// The stencil part of level l's table (slots TV..TZ, each P = nz+1 long, at t)
+// from a descriptor; dz and lam: its nz thicknesses and lambda^2 values.
+void stencil_coeffs(const ell_grid_desc &d, const double *dz, const double *lam, int l, double *t) {
+  const int nz = d.nz, P = nz + 1;
+  const int nx = d.nx >> l, ny = d.ny >> l;
+  const double hx = d.hx * (double)(1 << l), hy = d.hy * (double)(1 << l);
+  const double w2 = d.omega2;
   double *V = &t[TV * P], *Tx = &t[TX * P], *Ty = &t[TY * P], *Tz = &t[TZ * P];
-  double *ip = &t[TIP * P], *cf = &t[TCF * P];
   for (int k = 0; k < nz; ++k) {
-    V[k] = hx * hy * g->dz[k];
-    Tx[k] = nx > 1 ? w2 * hy * g->dz[k] / hx : 0.0;
-    Ty[k] = ny > 1 ? w2 * hx * g->dz[k] / hy : 0.0;
+    V[k] = hx * hy * dz[k];
+    Tx[k] = nx > 1 ? w2 * hy * dz[k] / hx : 0.0;
+    Ty[k] = ny > 1 ? w2 * hx * dz[k] / hy : 0.0;
   }
+  V[nz] = Tx[nz] = Ty[nz] = 0.0;
   Tz[0] = 0.0;
   Tz[nz] = 0.0;
   for (int k = 1; k < nz; ++k) {
-    const double res = g->dz[k - 1] / (2.0 * g->lam[k - 1]) + g->dz[k] / (2.0 * g->lam[k]);
+    const double res = dz[k - 1] / (2.0 * lam[k - 1]) + dz[k] / (2.0 * lam[k]);
     Tz[k] = w2 * hx * hy / res;
   }
+}
+
+void level_table64(const ell_grid *g, int l, std::vector<double> &t) {
+  const int nz = g->d.nz, P = nz + 1;
+  t.assign((size_t)TSLOTS * P, 0.0);
+  stencil_coeffs(g->d, g->dz.data(), g->lam.data(), l, t.data());
+  const double *V = &t[TV * P], *Tx = &t[TX * P], *Ty = &t[TY * P], *Tz = &t[TZ * P];
+  double *ip = &t[TIP * P], *cf = &t[TCF * P];
   double e = 0.0;
   for (int k = 0; k < nz; ++k) {
     const double s = (V[k] + 2.0 * Tx[k]) + 2.0 * Ty[k];
@@ -1285,6 +1294,38 @@ ell_schedule schedule_for(const ell_grid_desc *d, int L) {
 
 }  // namespace
 
+// Device area of ell_apply_A_noalloc: the finest level's stencil coefficients
+// (slots TV..TZ, nz+1 values each, nz <= ELL_NOALLOC_MAX_NZ), 32.8 KB.  Every
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code never uses this name as an address (it is a host-side stand-in): it
+// takes the per-device address from noalloc_area().
+static __device__ __align__(256) double scratch[4 * (ELL_NOALLOC_MAX_NZ + 1)];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch, looked up once per device (with
+// that device current) and kept.
+int noalloc_area(double **out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(ELL_ERR_INVALID, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ELL_ERR_HIP, "no device address for the coefficient area");
+    g_noalloc_ptr[dev] = (double *)p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return ELL_OK;
+}
+
+}  // namespace
+
 // ==========================================================================
 // C ABI
 // ==========================================================================
@@ -1459,6 +1500,36 @@ int ell_apply_A(ell_grid *g, const double *x, double *y, hipStream_t s) {
   CHK(launch_apply64(g, g->p, g->q, false, nullptr, s));
   k_split2nat<double, double><<<cb, kBlock, 0, s>>>(G, g->q, y);
   return check_launch("k_split2nat");
+}
+
+int ell_apply_A_noalloc(const ell_grid_desc *desc, const double *x, double *y, hipStream_t s) {
+  int L = 0;
+  CHK(validate(desc, &L));
+  if (desc->nz > ELL_NOALLOC_MAX_NZ)
+    return fail(ELL_ERR_INVALID, "nz = %d exceeds ELL_NOALLOC_MAX_NZ = %d of the allocation-free apply",
+                desc->nz, ELL_NOALLOC_MAX_NZ);
+  if (!x || !y) return fail(ELL_ERR_INVALID, "NULL argument");
+  if (x == y) return fail(ELL_ERR_INVALID, "x and y must not alias");
+  double *area = nullptr;
+  CHK(noalloc_area(&area));
+  // the table is built on the host (the same values a grid's finest level
+  // holds) and travels in kernel arguments, a chunk per launch
+  double tab[4 * (ELL_NOALLOC_MAX_NZ + 1)];
+  stencil_coeffs(*desc, desc->dz, desc->lambda2, 0, tab);
+  const int n = 4 * (desc->nz + 1);
+  TabChunk c;
+  for (int off = 0; off < n; off += kTabChunk) {
+    c.off = off;
+    c.n = std::min(kTabChunk, n - off);
+    std::memcpy(c.v, tab + off, sizeof(double) * c.n);
+    k_put_table<<<1, kBlock, 0, s>>>(area, c);
+    CHK(check_launch("k_put_table"));
+  }
+  const long long plane = (long long)desc->nx * desc->ny;
+  const int nseg = apply_segments(desc->nz);
+  const dim3 grid((unsigned)((plane + kBlock - 1) / kBlock), (unsigned)nseg);
+  k_apply_nat<<<grid, kBlock, 0, s>>>(desc->nx, desc->ny, desc->nz, nseg, area, x, y);
+  return check_launch("k_apply_nat");
 }
 
 int ell_vcycle(ell_grid *g, const double *r, double *z, hipStream_t s) {

@@ -2349,4 +2349,88 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ 
   finalize_body(partial, nblk, nq, st, mode, rtol, atol, rel_to_rhs, logical_block(), gridDim.x);
 }
 
+// -------------------------------------------------------------------------
+// Grid-free operator application (no device allocation): a coefficient table
+// is written into a caller-provided device area from kernel arguments, a
+// chunk per launch (the arguments are copied at launch, so nothing on the host
+// has to outlive the call), and y = A x is evaluated straight in the
+// plane-major layout idx = (k*ny + j)*nx + i.
+// -------------------------------------------------------------------------
+constexpr int kTabChunk = 256;
+struct TabChunk {
+  int off, n;
+  double v[kTabChunk];
+};
+
+__global__ __launch_bounds__(kBlock) void k_put_table(double *__restrict__ dst, TabChunk c) {
+  for (int t = threadIdx.x; t < c.n; t += kBlock) dst[c.off + t] = c.v[t];
+}
+
+// One lane per column, blockIdx.y the k-segment (of nseg).  tab: V, Tx, Ty, Tz
+// in slots of nz+1 (the TV..TZ slots of a level table).  Each cell is the
+// same expression, in the same order, as in k_apply.
+__global__ __launch_bounds__(kBlock) void k_apply_nat(int nx, int ny, int nz, int nseg,
+                                                      const double *__restrict__ tab,
+                                                      const double *__restrict__ x,
+                                                      double *__restrict__ y) {
+  const long long plane = (long long)nx * ny;
+  const long long col = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (col >= plane) return;
+  const int Ls = seg_len(nz, nseg);
+  const int k0 = min((int)blockIdx.y * Ls, nz), k1 = min(k0 + Ls, nz);
+  if (k0 >= k1) return;
+  const int i = (int)(col % nx), j = (int)(col / nx);
+  const bool hx = nx > 1, hy = ny > 1;
+  const long long cw = (long long)j * nx + wrapi(i - 1, nx), ce = (long long)j * nx + wrapi(i + 1, nx);
+  const long long cs = (long long)wrapi(j - 1, ny) * nx + i, cn = (long long)wrapi(j + 1, ny) * nx + i;
+  const int P = nz + 1;
+  const double *__restrict__ tv = tab + TV * P;
+  const double *__restrict__ tx = tab + TX * P;
+  const double *__restrict__ ty = tab + TY * P;
+  const double *__restrict__ tz = tab + TZ * P;
+  auto cell = [&](int k, double xc, double xm, double xp, double w, double e, double so, double no) {
+    double acc = tv[k] * xc;
+    if (hx) {
+      acc = acc + tx[k] * (xc - w);
+      acc = acc + tx[k] * (xc - e);
+    }
+    if (hy) {
+      acc = acc + ty[k] * (xc - so);
+      acc = acc + ty[k] * (xc - no);
+    }
+    acc = acc + tz[k] * (xc - xm);
+    acc = acc + tz[k + 1] * (xc - xp);
+    return acc;
+  };
+  double xc = x[(long long)k0 * plane + col];
+  double xm = k0 > 0 ? x[(long long)(k0 - 1) * plane + col] : xc;
+  int k = k0;
+  for (; k + kChunk <= k1; k += kChunk) {
+    double xp[kChunk], w[kChunk], e[kChunk], so[kChunk], no[kChunk];
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) {
+      const long long o = (long long)(k + t) * plane;
+      xp[t] = x[(long long)min(k + t + 1, nz - 1) * plane + col];
+      w[t] = hx ? x[o + cw] : 0.0;
+      e[t] = hx ? x[o + ce] : 0.0;
+      so[t] = hy ? x[o + cs] : 0.0;
+      no[t] = hy ? x[o + cn] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) {
+      y[(long long)(k + t) * plane + col] = cell(k + t, xc, xm, xp[t], w[t], e[t], so[t], no[t]);
+      xm = xc;
+      xc = xp[t];
+    }
+  }
+  for (; k < k1; ++k) {
+    const long long o = (long long)k * plane;
+    const double xpv = x[(long long)min(k + 1, nz - 1) * plane + col];
+    y[o + col] = cell(k, xc, xm, xpv, hx ? x[o + cw] : 0.0, hx ? x[o + ce] : 0.0, hy ? x[o + cs] : 0.0,
+                      hy ? x[o + cn] : 0.0);
+    xm = xc;
+    xc = xpv;
+  }
+}
+
 }  // namespace ell

@@ -66,7 +66,9 @@ EXPORTS = ["ell_grid_create", "ell_grid_destroy", "ell_grid_bytes", "ell_grid_le
            "ell_profile_times", "ell_level_layout", "ell_set_tuning", "ell_last_error",
            "ell_batch_create", "ell_batch_grid", "ell_batch_release", "ell_batch_bytes_in_use",
            "ell_batch_submit", "ell_batch_poll", "ell_batch_wait", "ell_batch_destroy",
-           "ell_autotune", "ell_schedule_get", "ell_schedule_set", "ell_mg_solve"]
+           "ell_autotune", "ell_schedule_get", "ell_schedule_set", "ell_mg_solve",
+           "ell_apply_A_noalloc"]
+ELL_NOALLOC_MAX_NZ = 1024
 
 _lib = None
 
@@ -88,6 +90,7 @@ def load_library(path: str = LIB_PATH):
     L.ell_grid_levels.argtypes = [vp]
     L.ell_grid_features.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.ell_apply_A.argtypes = [vp, vp, vp, vp]
+    L.ell_apply_A_noalloc.argtypes = [ctypes.POINTER(GridDesc), vp, vp, vp]
     L.ell_vcycle.argtypes = [vp, vp, vp, vp]
     L.ell_pcg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
     L.ell_mg_solve.argtypes = [vp, vp, vp, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), vp]
@@ -215,6 +218,17 @@ def schedule_set(schedule: Optional[dict], **desc) -> None:
     for i, v in enumerate(schedule.get("smooth_nseg", [])):
         s.smooth_nseg[i] = int(v)
     _check(load_library().ell_schedule_set(ctypes.byref(d), ctypes.byref(s)))
+
+
+def apply_A_noalloc(x: torch.Tensor, y: Optional[torch.Tensor] = None, stream=None, **desc) -> torch.Tensor:
+    """y = A x for the grid described by ``desc`` (make_desc's arguments)
+    without a grid object and without device allocation in the library
+    (ell_apply_A_noalloc); x, y plane-major float64 CUDA tensors."""
+    d, keep = make_desc(**desc)
+    if y is None:
+        y = torch.empty_like(x)
+    _check(load_library().ell_apply_A_noalloc(ctypes.byref(d), _dev(x), _dev(y), _stream(stream)))
+    return y
 
 
 def grid_bytes(**kw) -> int:
