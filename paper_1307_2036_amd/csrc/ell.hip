@@ -210,7 +210,7 @@ int g_tiled_ends = 1;     // 1: a solve's start and end on LDS tiles where both 
 
 // Smoother segments per column: enough lanes to occupy the chip on small
 // levels, four (the register-resident optimum) on large ones; the finest
-// level always uses four.
+// level uses eight for 64 <= nz <= 128, else four.
 int smoother_segments(long long cols_per_colour, int nz, bool finest) {
   // finest level: 8 segments where a kernel instance covers them (nz in
   // [64, 128]); measured 1% faster than 4 at 512^2 x 128
