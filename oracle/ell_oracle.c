@@ -40,6 +40,15 @@
  *  - norms are Euclidean norms of the volume-integrated residual b - A u with
  *    b = V f.
  *
+ * Horizontally varying vertical coefficients (beyond the paper's lambda^2(r),
+ * the next step toward its panel geometry, Sec. 3 and 6.2.1): with a 3D cell
+ * field lambda^2(i,j,k) every column has its own vertical face coefficients,
+ * by the same harmonic rule; the coarse level's face of a column is the sum of
+ * its four children's faces (parallel faces, so the vertical fluxes of a
+ * horizontally constant correction are conserved; for a horizontally constant
+ * lambda^2 it is exactly the re-discretised face).  The column matrix of the
+ * line smoother then differs from column to column.
+ *
  * Dots are accumulated sequentially in natural index order.  Build with
  * -ffp-contract=off so that no fused multiply-add changes the rounding.
  */
@@ -60,6 +69,10 @@ typedef struct {
     double omega2;
     const double *dz;       /* nz cell thicknesses             */
     const double *lambda2;  /* nz cell-centre values of lambda^2 */
+    const double *tz3;      /* NULL: vertical faces from lambda2(z); else the
+                               per-column vertical face coefficients, (nz+1) x
+                               ny x nx, tz3[(k*ny + j)*nx + i] joining cells k-1
+                               and k of column (i, j) (faces 0 and nz are 0) */
 } orc_geom;
 
 typedef struct {
@@ -94,7 +107,14 @@ typedef struct {
     double *Tz;  /* nz+1 vertical faces; Tz[k] joins cells k-1 and k;      */
                  /* Tz[0] = Tz[nz] = 0 (homogeneous Neumann)               */
     double *s;   /* column "excess": V_k + (number of x faces) Tx_k + (y faces) Ty_k */
+    double *Tz3; /* NULL, or per-column vertical faces, layout as orc_geom.tz3 */
 } level_t;
+
+/* Vertical face coefficient joining cells k-1 and k of column (i, j). */
+static double tzf(const level_t *L, int i, int j, int k)
+{
+    return L->Tz3 ? L->Tz3[((size_t)k * L->ny + j) * L->nx + i] : L->Tz[k];
+}
 
 static int has_x(const level_t *L) { return L->nx > 1; }
 static int has_y(const level_t *L) { return L->ny > 1; }
@@ -136,11 +156,52 @@ static void level_init(level_t *L, int nx, int ny, int nz, double hx, double hy,
     L->Tz = (double *)malloc(sizeof(double) * (nz + 1));
     L->s = (double *)malloc(sizeof(double) * nz);
     orc_level_coeffs(nx, ny, nz, hx, hy, omega2, dz, lambda2, L->V, L->Tx, L->Ty, L->Tz, L->s);
+    L->Tz3 = NULL;
+}
+
+/* Per-column faces (copied), layout as orc_geom.tz3. */
+static void level_set_tz3(level_t *L, const double *tz3)
+{
+    size_t n = (size_t)(L->nz + 1) * L->ny * L->nx;
+    L->Tz3 = (double *)malloc(sizeof(double) * n);
+    memcpy(L->Tz3, tz3, sizeof(double) * n);
 }
 
 static void level_free(level_t *L)
 {
-    free(L->V); free(L->Tx); free(L->Ty); free(L->Tz); free(L->s);
+    free(L->V); free(L->Tx); free(L->Ty); free(L->Tz); free(L->s); free(L->Tz3);
+}
+
+/* Per-column vertical faces of a 3D cell field lambda^2 (layout nz x ny x nx,
+ * plane-major): the harmonic rule of orc_level_coeffs in every column. */
+void orc_tz3_from_lambda2(int nx, int ny, int nz, double hx, double hy, double omega2,
+                          const double *dz, const double *lambda2_3d, double *tz3)
+{
+    size_t plane = (size_t)nx * ny;
+    for (size_t c = 0; c < plane; c++) {
+        tz3[c] = 0.0;
+        tz3[(size_t)nz * plane + c] = 0.0;
+        for (int k = 1; k < nz; k++) {
+            double resistance = dz[k - 1] / (2.0 * lambda2_3d[(size_t)(k - 1) * plane + c])
+                              + dz[k] / (2.0 * lambda2_3d[(size_t)k * plane + c]);
+            tz3[(size_t)k * plane + c] = omega2 * hx * hy / resistance;
+        }
+    }
+}
+
+/* Coarse faces: each coarse column's face is the sum of its four children's,
+ * added in pairs ((0,0) + (1,0)) + ((0,1) + (1,1)); nx, ny: fine sizes. */
+void orc_tz3_coarsen(int nx, int ny, int nz, const double *tz3f, double *tz3c)
+{
+    int cx = nx / 2, cy = ny / 2;
+    for (int k = 0; k <= nz; k++)
+        for (int J = 0; J < cy; J++)
+            for (int I = 0; I < cx; I++) {
+                const double *f = tz3f + (size_t)k * nx * ny;
+                double a = f[(size_t)(2 * J) * nx + 2 * I] + f[(size_t)(2 * J) * nx + 2 * I + 1];
+                double b = f[(size_t)(2 * J + 1) * nx + 2 * I] + f[(size_t)(2 * J + 1) * nx + 2 * I + 1];
+                tz3c[((size_t)k * cy + J) * cx + I] = a + b;
+            }
 }
 
 static size_t IDX(const level_t *L, int i, int j, int k)
@@ -171,8 +232,8 @@ static void apply_level(const level_t *L, const double *x, double *y)
                     acc += L->Ty[k] * (xc - x[IDX(L, i, wrap(j - 1, ny), k)]);
                     acc += L->Ty[k] * (xc - x[IDX(L, i, wrap(j + 1, ny), k)]);
                 }
-                if (k > 0) acc += L->Tz[k] * (xc - x[IDX(L, i, j, k - 1)]);
-                if (k < nz - 1) acc += L->Tz[k + 1] * (xc - x[IDX(L, i, j, k + 1)]);
+                if (k > 0) acc += tzf(L, i, j, k) * (xc - x[IDX(L, i, j, k - 1)]);
+                if (k < nz - 1) acc += tzf(L, i, j, k + 1) * (xc - x[IDX(L, i, j, k + 1)]);
                 y[c] = acc;
             }
         }
@@ -199,8 +260,8 @@ static void apply_abs_level(const level_t *L, const double *x, double *y)
                     acc += L->Ty[k] * (fabs(xc) + fabs(x[IDX(L, i, wrap(j - 1, ny), k)]));
                     acc += L->Ty[k] * (fabs(xc) + fabs(x[IDX(L, i, wrap(j + 1, ny), k)]));
                 }
-                if (k > 0) acc += L->Tz[k] * (fabs(xc) + fabs(x[IDX(L, i, j, k - 1)]));
-                if (k < nz - 1) acc += L->Tz[k + 1] * (fabs(xc) + fabs(x[IDX(L, i, j, k + 1)]));
+                if (k > 0) acc += tzf(L, i, j, k) * (fabs(xc) + fabs(x[IDX(L, i, j, k - 1)]));
+                if (k < nz - 1) acc += tzf(L, i, j, k + 1) * (fabs(xc) + fabs(x[IDX(L, i, j, k + 1)]));
                 y[c] = acc;
             }
         }
@@ -269,6 +330,7 @@ static void smooth_colour(const level_t *L, int colour, double rho, const double
         double *g = (double *)malloc(sizeof(double) * nz);
         double *w = (double *)malloc(sizeof(double) * nz);
         double *work = (double *)malloc(sizeof(double) * 2 * nz);
+        double *tcol = (double *)malloc(sizeof(double) * (nz + 1));
 #pragma omp for schedule(static)
         for (int j = 0; j < ny; j++) {
             for (int i = 0; i < nx; i++) {
@@ -281,14 +343,19 @@ static void smooth_colour(const level_t *L, int colour, double rho, const double
                         acc += L->Ty[k] * (u[IDX(L, i, wrap(j - 1, ny), k)] + u[IDX(L, i, wrap(j + 1, ny), k)]);
                     g[k] = acc;
                 }
-                orc_column_solve(nz, L->s, L->Tz, g, w, work);
+                if (L->Tz3) {
+                    for (int k = 0; k <= nz; k++) tcol[k] = tzf(L, i, j, k);
+                    orc_column_solve(nz, L->s, tcol, g, w, work);
+                } else {
+                    orc_column_solve(nz, L->s, L->Tz, g, w, work);
+                }
                 for (int k = 0; k < nz; k++) {
                     size_t c = IDX(L, i, j, k);
                     u[c] = (1.0 - rho) * u[c] + rho * w[k];
                 }
             }
         }
-        free(g); free(w); free(work);
+        free(g); free(w); free(work); free(tcol);
     }
 }
 
@@ -378,6 +445,16 @@ static int hier_init(hier_t *H, const orc_mg *mg)
         int f = 1 << l;
         level_init(&H->lev[l], mg->g.nx / f, mg->g.ny / f, mg->g.nz, mg->g.hx * f, mg->g.hy * f,
                    mg->g.omega2, mg->g.dz, mg->g.lambda2);
+        if (mg->g.tz3) {
+            if (l == 0) {
+                level_set_tz3(&H->lev[0], mg->g.tz3);
+            } else {
+                const level_t *F = &H->lev[l - 1];
+                level_t *C = &H->lev[l];
+                C->Tz3 = (double *)malloc(sizeof(double) * (size_t)(C->nz + 1) * C->ny * C->nx);
+                orc_tz3_coarsen(F->nx, F->ny, F->nz, F->Tz3, C->Tz3);
+            }
+        }
         size_t n = (size_t)H->lev[l].nx * H->lev[l].ny * H->lev[l].nz;
         H->r[l] = (double *)malloc(sizeof(double) * n);
         if (l > 0) {
@@ -448,6 +525,7 @@ static void vcycle_rec(hier_t *H, const orc_mg *mg, int l, const double *b, doub
 static void geom_level(level_t *L, const orc_geom *g)
 {
     level_init(L, g->nx, g->ny, g->nz, g->hx, g->hy, g->omega2, g->dz, g->lambda2);
+    if (g->tz3) level_set_tz3(L, g->tz3);
 }
 
 void orc_apply(const orc_geom *g, const double *x, double *y)

@@ -12,6 +12,7 @@ import ctypes
 import os
 import subprocess
 from dataclasses import dataclass
+from typing import Optional
 
 import numpy as np
 
@@ -25,7 +26,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 class Geom(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("hx", ctypes.c_double), ("hy", ctypes.c_double),
-                ("omega2", ctypes.c_double), ("dz", _dp), ("lambda2", _dp)]
+                ("omega2", ctypes.c_double), ("dz", _dp), ("lambda2", _dp), ("tz3", _dp)]
 
 
 class MG(ctypes.Structure):
@@ -86,6 +87,9 @@ def lib():
                                        ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_thomas_plain.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
         L.orc_column_solve.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.orc_tz3_from_lambda2.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+        L.orc_tz3_coarsen.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, _dp]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -118,17 +122,26 @@ class Grid:
     nu_coarse: int = 1
     rho: float = 1.0
     prolong: int = 0
+    # None: vertical faces from lambda2(z); else the per-column vertical face
+    # coefficients, shape (nz+1, ny, nx) (see tz3_from_lambda2)
+    tz3: Optional[np.ndarray] = None
 
     def __post_init__(self):
         self.dz = _c(self.dz)
         self.lambda2 = _c(self.lambda2)
         assert self.dz.shape == (self.nz,) and self.lambda2.shape == (self.nz,)
+        if self.tz3 is not None:
+            self.tz3 = _c(self.tz3)
+            assert self.tz3.shape == (self.nz + 1, self.ny, self.nx)
 
     @classmethod
     def from_problem(cls, p, **over):
         kw = dict(nx=p.nx, ny=p.ny, nz=p.nz, hx=p.hx, hy=p.hy, omega2=p.omega2, dz=p.dz,
                   lambda2=p.lambda2, n_levels=p.n_levels, nu_pre=p.nu_pre, nu_post=p.nu_post,
                   nu_coarse=p.nu_coarse, rho=p.rho, prolong=p.prolong)
+        lam3 = getattr(p, "lambda2_3d", None)
+        if lam3 is not None:
+            kw["tz3"] = tz3_from_lambda2(p.nx, p.ny, p.nz, p.hx, p.hy, p.omega2, p.dz, lam3)
         kw.update(over)
         return cls(**kw)
 
@@ -138,7 +151,8 @@ class Grid:
 
     def geom(self) -> Geom:
         return Geom(self.nx, self.ny, self.nz, self.hx, self.hy, self.omega2,
-                    _ptr(self.dz), _ptr(self.lambda2))
+                    _ptr(self.dz), _ptr(self.lambda2),
+                    None if self.tz3 is None else _ptr(self.tz3))
 
     def mg(self) -> MG:
         return MG(self.geom(), self.n_levels, self.nu_pre, self.nu_post, self.nu_coarse,
@@ -147,7 +161,28 @@ class Grid:
     def coarse(self) -> "Grid":
         return Grid(self.nx // 2, self.ny // 2, self.nz, 2 * self.hx, 2 * self.hy, self.omega2,
                     self.dz, self.lambda2, 0, self.nu_pre, self.nu_post, self.nu_coarse,
-                    self.rho, self.prolong)
+                    self.rho, self.prolong,
+                    None if self.tz3 is None else tz3_coarsen(self.tz3))
+
+
+def tz3_from_lambda2(nx, ny, nz, hx, hy, omega2, dz, lambda2_3d) -> np.ndarray:
+    """Per-column vertical face coefficients, shape (nz+1, ny, nx), of a 3D
+    cell field lambda^2 of shape (nz, ny, nx)."""
+    dz = _c(dz)
+    lam = _c(lambda2_3d).reshape(nz, ny, nx)
+    out = np.empty((nz + 1, ny, nx))
+    lib().orc_tz3_from_lambda2(nx, ny, nz, hx, hy, omega2, _ptr(dz), _ptr(lam), _ptr(out))
+    return out
+
+
+def tz3_coarsen(tz3) -> np.ndarray:
+    """Faces of the next coarser level: each coarse face is the sum of its
+    four children's."""
+    tz3 = _c(tz3)
+    nz1, ny, nx = tz3.shape
+    out = np.empty((nz1, ny // 2, nx // 2))
+    lib().orc_tz3_coarsen(nx, ny, nz1 - 1, _ptr(tz3), _ptr(out))
+    return out
 
 
 def level_coeffs(g: Grid):

@@ -73,6 +73,38 @@ def lambda2_perturbed(h: float, dz: np.ndarray, sigma: float, seed: int,
     return (h / dz) ** 2 * np.exp(sigma * g)
 
 
+def lambda2_3d(nx: int, ny: int, lam_z: np.ndarray, sigma_h: float, seed: int,
+               n_modes: int = 3) -> np.ndarray:
+    """A 3D cell field lambda^2(i,j,k) = lambda^2_k * exp(sigma_h * g_k(x, y)),
+    shape (nz, ny, nx): the column profile lam_z modulated horizontally by a
+    smooth periodic random field whose pattern changes with height,
+    g = sum over 0 <= p, q <= n_modes, (p, q) != (0, 0), of
+    (xi_pq + eta_pq zeta_k) cos(2 pi (p x + q y) + phi_pq), x = (i+1/2)/nx,
+    y = (j+1/2)/ny, zeta_k = (k+1/2)/nz, xi, eta ~ N(0,1), phi ~ U[0, 2 pi),
+    rescaled to unit RMS.  It stands in for the horizontally varying metric
+    terms of the paper's cubed-sphere panel, which make every column's
+    vertical coefficients different (Sec. 3, Sec. 6.2.1)."""
+    lam_z = np.asarray(lam_z, dtype=np.float64)
+    nz = len(lam_z)
+    rng = np.random.default_rng(seed)
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    zeta = (np.arange(nz) + 0.5) / nz
+    g = np.zeros((nz, ny, nx))
+    for p in range(n_modes + 1):
+        for q in range(n_modes + 1):
+            if p == 0 and q == 0:
+                continue
+            xi, eta = rng.standard_normal(2)
+            phi = rng.uniform(0.0, 2.0 * math.pi)
+            wave = np.cos(2.0 * math.pi * (p * x[None, :] + q * y[:, None]) + phi)
+            g += (xi + eta * zeta)[:, None, None] * wave[None, :, :]
+    rms = math.sqrt(float(np.mean(g * g)))
+    if rms > 0:
+        g = g / rms
+    return np.ascontiguousarray(lam_z[:, None, None] * np.exp(sigma_h * g))
+
+
 # --------------------------------------------------------------------------
 # right-hand sides
 # --------------------------------------------------------------------------
@@ -148,6 +180,9 @@ class Problem:
     prolong: int = 0           # 0 bilinear, 1 piecewise constant
     rtol: float = 1e-5
     seeds: dict = field(default_factory=dict)
+    # None, or a 3D cell field lambda^2 of shape (nz, ny, nx) that replaces
+    # lambda2 (horizontally varying vertical coefficients)
+    lambda2_3d: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
@@ -193,6 +228,19 @@ def paper_graded_problem(name: str, nx: int, ny: int, nz: int, omega2: float, se
     f = rhs_normal(nx, ny, dz, seed_f)
     return Problem(name, nx, ny, nz, 1.0 / nx, 1.0 / ny, dz, lam, omega2, f,
                    seeds={"f": seed_f, "lambda": seed_lambda})
+
+
+def varying_problem(nx: int = 512, nz: int = 128, n_levels: int = 4, nu_coarse: int = 5,
+                    sigma_h: float = 0.5, with_f: bool = True) -> Problem:
+    """The 512 x 512 x 128 graded problem of config 1 with its lambda^2 profile
+    modulated horizontally (lambda2_3d, sigma_h = 0.5): every column has its own
+    vertical coefficients."""
+    p = graded_problem(f"varying_{nx}x{nx}x{nz}_L{n_levels}", nx, nz, 1e-2, seed_for(5),
+                       seed_for(5, stream=1), n_levels=n_levels, nu_coarse=nu_coarse,
+                       with_f=with_f)
+    p.lambda2_3d = lambda2_3d(nx, nx, p.lambda2, sigma_h, seed_for(5, stream=2))
+    p.seeds["lambda2_3d"] = seed_for(5, stream=2)
+    return p
 
 
 def config1(n_levels: int = 4, nu_coarse: int = 5, nx: int = 512, nz: int = 128,
