@@ -116,6 +116,23 @@ typedef struct {
 int ell_grid_create(const ell_grid_desc *desc, ell_grid **out);
 int ell_grid_destroy(ell_grid *g);
 
+/* A grid whose vertical coefficient lambda^2 varies horizontally too: the
+ * model equation of Sec. 3 with lambda^2(x, y, z), a step from the paper's
+ * lambda^2(r) toward its panel geometry, whose metric terms differ from column
+ * to column (Sec. 3, Sec. 6.2.1).  lambda2_3d: HOST array of nx*ny*nz cell
+ * values (> 0, finite), plane-major, copied; desc->lambda2 is not read (it may
+ * be NULL).  Every column gets its own vertical faces (the harmonic rule of
+ * ell_grid_desc.lambda2, column by column) and its own Thomas factors; a coarse
+ * column's face is the sum of its four children's (parallel faces; for a
+ * horizontally constant lambda^2 this is the re-discretised face exactly).
+ * desc->precision must be ELL_FP64.  The grid works with every grid entry point
+ * (ell_apply_A, ell_vcycle, ell_pcg_solve, ell_mg_solve, the level entry
+ * points) through the column-walking kernels and without the fused forms
+ * (ell_grid_features reports none); it holds three FP64 fields per level more
+ * than ell_grid_bytes reports.  The batch engine does not take such grids.
+ * Synchronous; ELL_ERR_INVALID for a bad descriptor or field. */
+int ell_grid_create_varying(const ell_grid_desc *desc, const double *lambda2_3d, ell_grid **out);
+
 /* Device bytes ell_grid_create would allocate for desc (0 if invalid). */
 size_t ell_grid_bytes(const ell_grid_desc *desc);
 

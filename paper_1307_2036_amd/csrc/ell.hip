@@ -140,6 +140,10 @@ struct Level {
   void *tab = nullptr;  // device table, element type of the V-cycle
   void *b = nullptr;    // levels >= 1: right-hand side (split)
   void *u = nullptr;    // levels >= 1: correction (split)
+  // grids with horizontally varying vertical coefficients (split layout, FP64):
+  // each column's faces T_{k-1/2} (zero at k = 0) and the factors 1/p_k and
+  // T_{k+1/2}/p_k of its column elimination
+  double *tz3 = nullptr, *ip3 = nullptr, *cf3 = nullptr;
 };
 
 }  // namespace
@@ -173,6 +177,7 @@ struct ell_grid {
   PcgState *st_host = nullptr;          // pinned
   Prof prof[ELL_K_COUNT];
   std::vector<void *> allocs;
+  bool varying = false;       // per-column vertical coefficients (Level::tz3, ip3, cf3)
   bool batch_layout = false;  // coarse levels use 4 or 8 k-segments (grouped launches)
   void *gdev = nullptr;       // device copy of the grid descriptor (batched kernels)
   int busy = 0;               // a batch request is using the grid
@@ -393,6 +398,82 @@ size_t grid_bytes(const ell_grid_desc *d, int L) {
   return bytes;
 }
 
+// Per-column vertical coefficients of every level (horizontally varying
+// lambda^2): level 0's faces by the harmonic rule of level_table64 in each
+// column, T_{k-1/2} = omega^2 hx hy / (dz_{k-1}/(2 lambda^2_{k-1}) +
+// dz_k/(2 lambda^2_k)); a coarse column's face is the sum of its four
+// children's, ((0,0) + (1,0)) + ((0,1) + (1,1)) (parallel faces).  Each
+// column's Thomas elimination in excess form with the level's shared excess
+// s_k = V_k + 2 Tx_k + 2 Ty_k gives 1/p_k and T_{k+1/2}/p_k.  Uploaded in the
+// split layout of the level.
+int build_varying(ell_grid *g, const double *lam3) {
+  const ell_grid_desc &d = g->d;
+  const int nz = d.nz;
+  std::vector<double> fz, fzc, t64, tz_s, ip_s, cf_s;
+  {
+    const size_t plane = (size_t)d.nx * d.ny;
+    fz.assign((size_t)(nz + 1) * plane, 0.0);
+    for (int k = 1; k < nz; ++k)
+      for (size_t c = 0; c < plane; ++c) {
+        const double res = g->dz[k - 1] / (2.0 * lam3[(size_t)(k - 1) * plane + c]) +
+                           g->dz[k] / (2.0 * lam3[(size_t)k * plane + c]);
+        fz[(size_t)k * plane + c] = d.omega2 * d.hx * d.hy / res;
+      }
+  }
+  for (int l = 0; l < g->L; ++l) {
+    Level &Lv = g->lev[l];
+    const Geo &G = Lv.geo;
+    const int nx = G.nx, ny = G.ny;
+    if (l > 0) {  // sum the children of the previous level's faces
+      const int fx = nx * 2, fy = ny * 2;
+      fzc.assign((size_t)(nz + 1) * nx * ny, 0.0);
+      for (int k = 0; k <= nz; ++k)
+        for (int J = 0; J < ny; ++J)
+          for (int I = 0; I < nx; ++I) {
+            const double *f = &fz[(size_t)k * fx * fy];
+            const double a = f[(size_t)(2 * J) * fx + 2 * I] + f[(size_t)(2 * J) * fx + 2 * I + 1];
+            const double b = f[(size_t)(2 * J + 1) * fx + 2 * I] + f[(size_t)(2 * J + 1) * fx + 2 * I + 1];
+            fzc[((size_t)k * ny + J) * nx + I] = a + b;
+          }
+      fz.swap(fzc);
+    }
+    const size_t plane = (size_t)nx * ny;
+    level_table64(g, l, t64);
+    const int P = nz + 1;
+    const size_t ne = 2 * (size_t)G.cs;
+    tz_s.assign(ne, 0.0);
+    ip_s.assign(ne, 0.0);
+    cf_s.assign(ne, 0.0);
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int c = (i + j) & 1;
+        const long long m = nx > 1 ? (long long)j * G.hx2 + (i >> 1) : (j >> 1);
+        const size_t col = (size_t)j * nx + i;
+        double e = 0.0;
+        for (int k = 0; k < nz; ++k) {
+          const double s = (t64[TV * P + k] + 2.0 * t64[TX * P + k]) + 2.0 * t64[TY * P + k];
+          const double tb = fz[(size_t)k * plane + col], ta = fz[(size_t)(k + 1) * plane + col];
+          e = k == 0 ? s : s + tb * e / (tb + e);
+          const double p = ta + e;
+          const size_t o = (size_t)c * G.cs + (size_t)k * G.S + m;
+          tz_s[o] = tb;
+          ip_s[o] = 1.0 / p;
+          cf_s[o] = ta / p;
+        }
+      }
+    void *tmp;
+    const std::vector<double> *src[3] = {&tz_s, &ip_s, &cf_s};
+    double **dst[3] = {&Lv.tz3, &Lv.ip3, &Lv.cf3};
+    for (int a = 0; a < 3; ++a) {
+      CHK(dalloc(g, &tmp, ne * 8));
+      *dst[a] = (double *)tmp;
+      if (hipMemcpy(tmp, src[a]->data(), ne * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(ELL_ERR_HIP, "coefficient upload failed");
+    }
+  }
+  return ELL_OK;
+}
+
 // ------------------------------------------------------------------------
 // profiling helpers
 // ------------------------------------------------------------------------
@@ -514,6 +595,23 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
   const bool hxy = G.has_x && G.has_y;
   ProfScope ps(g, ELL_K_SMOOTH0, s, l == 0);
   if constexpr (std::is_same<R, double>::value && std::is_same<TB, double>::value) {
+    if (g->varying) {  // every column its own factors: the column kernel
+      auto go = [&](auto z, auto r1, auto fn, auto h) {
+        k_smooth<double, decltype(z)::value, decltype(r1)::value, decltype(fn)::value, decltype(h)::value, true>
+            <<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, yb, rho, done, Lv.tz3, Lv.ip3, Lv.cf3);
+      };
+      using T_ = std::true_type;
+      using F_ = std::false_type;
+      auto go2 = [&](auto fn, auto h) {
+        if (zero && rho1) go(T_{}, T_{}, fn, h);
+        else if (zero) go(T_{}, F_{}, fn, h);
+        else if (rho1) go(F_{}, T_{}, fn, h);
+        else go(F_{}, F_{}, fn, h);
+      };
+      if (l == 0) { if (hxy) go2(T_{}, T_{}); else go2(T_{}, F_{}); }
+      else { if (hxy) go2(F_{}, T_{}); else go2(F_{}, F_{}); }
+      return check_launch("k_smooth");
+    }
     // after the first sweep, rho = 1: the LDS-tiled half-sweep (streaming
     // accesses on the finest level)
     const int Ls = seg_len(G.nz, G.nseg);
@@ -691,6 +789,14 @@ int launch_restrict(ell_grid *g, int l, const TB *b, const R *u, R *bc, bool bz,
   const int nb = blocks8(2LL * C.H);
   const R *tab = (const R *)g->lev[l].tab;
   ProfScope ps(g, ELL_K_RESTRICT0, s, l == 0);
+  if constexpr (std::is_same<R, double>::value && std::is_same<TB, double>::value) {
+    if (g->varying) {
+      const double *tz3 = g->lev[l].tz3;
+      if (bz) k_resid_restrict<double, true, true><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done, tz3);
+      else k_resid_restrict<double, false, true><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done, tz3);
+      return check_launch("k_resid_restrict");
+    }
+  }
   if (bz && F.has_x && F.has_y) {
     const int nbz = seg_blocks(2LL * C.H);
     const int ns = transfer_segments(2LL * C.H, F.nz);
@@ -942,6 +1048,18 @@ int launch_apply64(ell_grid *g, const double *x, double *y, bool dot, const int 
   const bool hxy = G.has_x && G.has_y;
   const int ns = g->stencil_seg;
   const int b = stencil_blocks(2LL * G.H, ns);
+  if (g->varying) {
+    const double *tz3 = g->lev[0].tz3;
+    auto go = [&](auto nsc) {
+      constexpr int NS = decltype(nsc)::value;
+      if (dot) k_apply<double, true, false, NS, true><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done, tz3);
+      else k_apply<double, false, false, NS, true><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done, tz3);
+    };
+    if (ns == 1) go(std::integral_constant<int, 1>{});
+    else if (ns == 2) go(std::integral_constant<int, 2>{});
+    else go(std::integral_constant<int, 4>{});
+    return check_launch("k_apply");
+  }
   if (ns == 1) {
     if (dot) k_apply<double, true, false, 1><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
     else k_apply<double, false, false, 1><<<b, kBlock, 0, s>>>(G, tab64, x, y, g->partial, done);
@@ -1029,7 +1147,10 @@ int launch_begin(ell_grid *g, const double *f, const double *u, int *nblk, hipSt
     return check_launch("k_begin_tile");
   }
   *nblk = seg_blocks((long long)G.nx * G.ny);
-  k_begin<<<*nblk, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, u, g->us, g->r, g->partial);
+  if (g->varying)
+    k_begin<true><<<*nblk, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, u, g->us, g->r, g->partial, g->lev[0].tz3);
+  else
+    k_begin<><<<*nblk, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, u, g->us, g->r, g->partial);
   return check_launch("k_begin");
 }
 
@@ -1078,7 +1199,18 @@ int launch_apply_dir(ell_grid *g, int K, int first, int defer, hipStream_t s) {
   double *pold = dir_buf(g, K - 1), *pold2 = dir_buf(g, K - 2), *pnew = dir_buf(g, K);
   ProfScope ps(g, ELL_K_APPLY, s);
   const Z *zz = (const Z *)zvec<Z>(g);
-  if (g->apply_tile)
+  if (g->varying) {
+    const double *tz3 = g->lev[0].tz3;
+    if (g->stencil_seg == 1)
+      k_apply_dir<Z, 1, true><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pold, pold2, pnew, g->q, g->us, g->st, first,
+                                                    defer, g->partial, tz3);
+    else if (g->stencil_seg == 2)
+      k_apply_dir<Z, 2, true><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pold, pold2, pnew, g->q, g->us, g->st, first,
+                                                    defer, g->partial, tz3);
+    else
+      k_apply_dir<Z, 4, true><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pold, pold2, pnew, g->q, g->us, g->st, first,
+                                                    defer, g->partial, tz3);
+  } else if (g->apply_tile)
     k_apply_dir_tile<Z><<<ab, kBlock, 0, s>>>(G, g->apply_nseg, g->tab64_0, zz, pold, pold2, pnew, g->q, g->us,
                                               g->st, first, defer, g->partial);
   else if (g->stencil_seg == 1)
@@ -1182,8 +1314,12 @@ int pcg_finish(ell_grid *g, const double *f, double *u, ell_solve_stats *out, hi
     CHK(check_launch("k_finish_tile"));
   } else {
     fb = seg_blocks(2LL * G.H);
-    k_finish<<<fb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, g->us, dir_buf(g, K), dir_buf(g, K - 1), g->st,
-                                   with_p, u, g->partial);
+    if (g->varying)
+      k_finish<true><<<fb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, g->us, dir_buf(g, K), dir_buf(g, K - 1),
+                                           g->st, with_p, u, g->partial, g->lev[0].tz3);
+    else
+      k_finish<><<<fb, kBlock, 0, s>>>(G, g->tab64_0, g->vol0, f, g->us, dir_buf(g, K), dir_buf(g, K - 1), g->st,
+                                       with_p, u, g->partial);
     CHK(check_launch("k_finish"));
   }
   k_finalize<<<1, kBlock, 0, s>>>(g->partial, fb, 2, g->st, F_TRUE, 0, 0, 0);
@@ -1340,12 +1476,31 @@ size_t ell_grid_bytes(const ell_grid_desc *desc) {
 }
 
 static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **out,
-                       const ell_schedule *force = nullptr);
+                       const ell_schedule *force = nullptr, const double *lam3 = nullptr);
 
 int ell_grid_create(const ell_grid_desc *desc, ell_grid **out) { return grid_create(desc, false, out); }
 
+int ell_grid_create_varying(const ell_grid_desc *desc, const double *lambda2_3d, ell_grid **out) {
+  if (!out) return fail(ELL_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!desc) return fail(ELL_ERR_INVALID, "descriptor is NULL");
+  if (!lambda2_3d) return fail(ELL_ERR_INVALID, "lambda2_3d is NULL");
+  if (desc->precision != ELL_FP64)
+    return fail(ELL_ERR_INVALID, "horizontally varying coefficients need precision ELL_FP64");
+  if (desc->nx < 1 || desc->ny < 1 || desc->nz < 1) return fail(ELL_ERR_INVALID, "sizes must be >= 1");
+  const size_t n = (size_t)desc->nx * desc->ny * desc->nz;
+  for (size_t e = 0; e < n; ++e)
+    if (!(lambda2_3d[e] > 0) || !std::isfinite(lambda2_3d[e]))
+      return fail(ELL_ERR_INVALID, "lambda2_3d[%zu] must be positive and finite", e);
+  // desc->lambda2 is not read: the z-only faces of the level tables are unused
+  std::vector<double> ones((size_t)desc->nz, 1.0);
+  ell_grid_desc d = *desc;
+  d.lambda2 = ones.data();
+  return grid_create(&d, false, out, nullptr, lambda2_3d);
+}
+
 static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **out,
-                       const ell_schedule *force) {
+                       const ell_schedule *force, const double *lam3) {
   if (!out) return fail(ELL_ERR_INVALID, "out is NULL");
   *out = nullptr;
   int L = 0;
@@ -1369,6 +1524,12 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->fused_prolong = g_fused_prolong;
   g->tiled_ends = (g_tiled_ends && desc->nx > 1 && desc->ny > 1) ? 1 : 0;
   g->batch_layout = batch_layout;
+  if (lam3) {  // per-column coefficients: the column-walking kernels, no fused forms
+    g->varying = true;
+    g->apply_tile = 0;
+    g->stencil_seg = apply_segments(desc->nz);
+    g->smooth_tile = g->fused_dot = g->fused_update = g->fused_prolong = g->tiled_ends = 0;
+  }
   g->lev.resize(L);
   auto bail = [&](int rc) {
     ell_grid_destroy(g);
@@ -1384,6 +1545,11 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
     Lv.hx = desc->hx * (double)(1 << l);
     Lv.hy = desc->hy * (double)(1 << l);
     level_table64(g, l, t64);
+    if (g->varying) {  // the shared vertical slots mean nothing here: make any use loud
+      const int P = desc->nz + 1;
+      for (int sl = TZ; sl < TSLOTS; ++sl)
+        for (int k = 0; k < P; ++k) t64[(size_t)sl * P + k] = std::nan("");
+    }
     const size_t tb = t64.size() * g->esz;
     if ((rc = dalloc(g, &Lv.tab, tb)) != ELL_OK) return bail(rc);
     if (g->prec == ELL_FP64) {
@@ -1452,6 +1618,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   } else {
     g->tab64_0 = (const double *)g->lev[0].tab;
   }
+  if (g->varying && (rc = build_varying(g, lam3)) != ELL_OK) return bail(rc);
   *out = g;
   return ELL_OK;
 }
@@ -1649,7 +1816,11 @@ int ell_level_apply(ell_grid *g, int level, const void *x, void *y, hipStream_t 
   if (!x || !y || x == y) return fail(ELL_ERR_INVALID, "bad vector arguments");
   const Geo &G = g->lev[level].geo;
   const int nb = seg_blocks(2LL * G.H);
-  if (g->prec == ELL_FP64)
+  if (g->varying)
+    k_apply<double, false, false, 4, true><<<nb, kBlock, 0, s>>>(G, (const double *)g->lev[level].tab,
+                                                                 (const double *)x, (double *)y, nullptr, nullptr,
+                                                                 g->lev[level].tz3);
+  else if (g->prec == ELL_FP64)
     k_apply<double, false, false, 4><<<nb, kBlock, 0, s>>>(G, (const double *)g->lev[level].tab,
                                                            (const double *)x, (double *)y, nullptr, nullptr);
   else

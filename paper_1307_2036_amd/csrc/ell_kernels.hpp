@@ -203,12 +203,19 @@ constexpr int kChunk = 8;
 // profiles attribute the dominant launches to it alone).  HXY: both
 // horizontal directions have faces (every level but degenerate 1-wide ones).
 // -------------------------------------------------------------------------
-template <typename R, bool ZERO, bool RHO1, bool FINE, bool HXY>
+// C3 (horizontally varying vertical coefficients): every column has its own
+// faces and Thomas factors, read from the level's split-layout fields tz3
+// (T_{k-1/2}, zero at k = 0), ip3 (1/p_k) and cf3 (T_{k+1/2}/p_k) instead of
+// the table's shared columns.
+template <typename R, bool ZERO, bool RHO1, bool FINE, bool HXY, bool C3 = false>
 __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ tab, int c,
                                                    const R *__restrict__ bo,
                                                    const R *__restrict__ uo,
                                                    R *__restrict__ own, R *__restrict__ ybuf,
-                                                   R rho, const int *__restrict__ done) {
+                                                   R rho, const int *__restrict__ done,
+                                                   const R *__restrict__ tz3 = nullptr,
+                                                   const R *__restrict__ ip3 = nullptr,
+                                                   const R *__restrict__ cf3 = nullptr) {
   if (is_done(done)) return;
   const int m = logical_block() * kBlock + threadIdx.x;
   const int ncol = c ? L.ncol1 : L.ncol0;
@@ -231,6 +238,11 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ 
   const R *__restrict__ ip = tab + TIP * L.P;
   const R *__restrict__ cf = tab + TCF * L.P;
   const int nz = L.nz;
+  // per-column fields of this column (C3)
+  const long long oc3 = (long long)c * L.cs + m;
+  auto tzb = [&](int k) -> R { if constexpr (C3) return tz3[oc3 + (long long)k * H]; else return tz[k]; };
+  auto ipk = [&](int k) -> R { if constexpr (C3) return ip3[oc3 + (long long)k * H]; else return ip[k]; };
+  auto cfk = [&](int k) -> R { if constexpr (C3) return cf3[oc3 + (long long)k * H]; else return cf[k]; };
 
   auto gval = [&](int k) -> R {
     const long long o = (long long)k * H;
@@ -245,18 +257,22 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ 
   R yprev = R(0);
   int k = 0;
   for (; k + kChunk <= nz; k += kChunk) {
-    R g[kChunk];
-#pragma unroll
-    for (int t = 0; t < kChunk; ++t) g[t] = gval(k + t);
+    R g[kChunk], a[kChunk], d[kChunk];
 #pragma unroll
     for (int t = 0; t < kChunk; ++t) {
-      const R y = (g[t] + tz[k + t] * yprev) * ip[k + t];
+      g[t] = gval(k + t);
+      a[t] = tzb(k + t);
+      d[t] = ipk(k + t);
+    }
+#pragma unroll
+    for (int t = 0; t < kChunk; ++t) {
+      const R y = (g[t] + a[t] * yprev) * d[t];
       ys[(long long)(k + t) * H] = y;
       yprev = y;
     }
   }
   for (; k < nz; ++k) {
-    const R y = (gval(k) + tz[k] * yprev) * ip[k];
+    const R y = (gval(k) + tzb(k) * yprev) * ipk(k);
     ys[(long long)k * H] = y;
     yprev = y;
   }
@@ -269,22 +285,23 @@ __global__ __launch_bounds__(kBlock) void k_smooth(Geo L, const R *__restrict__ 
   }
   k = nz - 2;
   for (; k + 1 >= kChunk; k -= kChunk) {
-    R y[kChunk], old[kChunk];
+    R y[kChunk], old[kChunk], e[kChunk];
 #pragma unroll
     for (int t = 0; t < kChunk; ++t) {
       y[t] = ys[(long long)(k - t) * H];
       old[t] = (RHO1 || ZERO) ? R(0) : own[(long long)(k - t) * H];
+      e[t] = cfk(k - t);
     }
 #pragma unroll
     for (int t = 0; t < kChunk; ++t) {
-      w = y[t] + cf[k - t] * w;
+      w = y[t] + e[t] * w;
       own[(long long)(k - t) * H] = RHO1 ? w : (R(1) - rho) * old[t] + rho * w;
     }
   }
   for (; k >= 0; --k) {
     const long long o = (long long)k * H;
     const R old = (RHO1 || ZERO) ? R(0) : own[o];
-    w = ys[o] + cf[k] * w;
+    w = ys[o] + cfk(k) * w;
     own[o] = RHO1 ? w : (R(1) - rho) * old + rho * w;
   }
 }
@@ -978,12 +995,15 @@ __global__ __launch_bounds__(NSEG * 64) void k_resid_restrict_bz(Geo F, Geo C,
 // (they were just solved exactly), so only the two colour-0 children are
 // evaluated.
 // -------------------------------------------------------------------------
-template <typename R, bool BZ>
+// C3: the vertical faces of each child column from the split-layout field
+// tz3 (T_{k-1/2}) instead of the table.
+template <typename R, bool BZ, bool C3 = false>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict(Geo F, Geo C, const R *__restrict__ tab,
                                                            const R *__restrict__ b,
                                                            const R *__restrict__ u,
                                                            R *__restrict__ bc,
-                                                           const int *__restrict__ done) {
+                                                           const int *__restrict__ done,
+                                                           const R *__restrict__ tz3 = nullptr) {
   if (is_done(done)) return;
   const int gid = logical_block() * kBlock + threadIdx.x;
   if (gid >= 2 * C.H) return;
@@ -1036,7 +1056,16 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Geo F, Geo C, const R
       const R uS = F.has_y ? uo[nS[t]] : R(0);
       const R uN = F.has_y ? uo[nN[t]] : R(0);
       const R bk = b[(long long)ca[t] * F.cs + o + cm[t]];
-      const R r = cell_residual<R>(bk, tv[k], tx[k], ty[k], tz[k], tz[k + 1], uc[t], um[t], up,
+      R tzlo, tzhi;
+      if constexpr (C3) {
+        const R *__restrict__ zc = tz3 + (long long)ca[t] * F.cs + cm[t];
+        tzlo = zc[o];
+        tzhi = k + 1 < nz ? zc[o + H] : R(0);
+      } else {
+        tzlo = tz[k];
+        tzhi = tz[k + 1];
+      }
+      const R r = cell_residual<R>(bk, tv[k], tx[k], ty[k], tzlo, tzhi, uc[t], um[t], up,
                                    uW, uE, uS, uN, F.has_x, F.has_y);
       acc = t == 0 ? r : acc + r;
       um[t] = uc[t];
@@ -1267,11 +1296,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong_out(Geo F, Geo C, const R *_
 // y = A x (eq. ModelEquation integrated over the cell, difference form), one
 // lane per column of either colour; DOT: also partial sums of <x, y>.
 // -------------------------------------------------------------------------
-template <typename R, bool DOT, bool HXY, int NSEG>
+template <typename R, bool DOT, bool HXY, int NSEG, bool C3 = false>
 __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ tab,
                                                   const R *__restrict__ x, R *__restrict__ y,
                                                   double *__restrict__ partial,
-                                                  const int *__restrict__ done) {
+                                                  const int *__restrict__ done,
+                                                  const R *__restrict__ tz3 = nullptr) {
   __shared__ double sh[4];
   if (is_done(done)) return;
   // 64 column slots (both colours) per block, one k-segment per wavefront
@@ -1305,6 +1335,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ t
     const R *__restrict__ ty = tab + TY * L.P;
     const R *__restrict__ tz = tab + TZ * L.P;
     const int nz = L.nz;
+    const R *__restrict__ zc = C3 ? tz3 + (long long)c * L.cs + m : nullptr;  // this column's faces
     auto cell = [&](int k, R xc, R xm, R xp, R w, R e, R so, R no) -> R {
       R acc = tv[k] * xc;
       if (hx) {
@@ -1315,8 +1346,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ t
         acc = acc + ty[k] * (xc - so);
         acc = acc + ty[k] * (xc - no);
       }
-      acc = acc + tz[k] * (xc - xm);
-      acc = acc + tz[k + 1] * (xc - xp);
+      if constexpr (C3) {
+        acc = acc + zc[(long long)k * H] * (xc - xm);
+        acc = acc + (k + 1 < nz ? zc[(long long)(k + 1) * H] : R(0)) * (xc - xp);
+      } else {
+        acc = acc + tz[k] * (xc - xm);
+        acc = acc + tz[k + 1] * (xc - xp);
+      }
       return acc;
     };
     R xc = xs[(long long)k0 * H];
@@ -1374,7 +1410,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo L, const R *__restrict__ t
 // p_new are different buffers, so neighbour values of p_new are formed from
 // z and p_old exactly as their owning lanes form them.
 // -------------------------------------------------------------------------
-template <typename Z, int NSEG>
+// C3: the vertical faces of each column from the split-layout field tz3
+// (T_{k-1/2}) instead of the table.
+template <typename Z, int NSEG, bool C3 = false>
 __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__ tab,
                                                       const Z *__restrict__ z,
                                                       const double *__restrict__ pold,
@@ -1383,7 +1421,8 @@ __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__
                                                       double *__restrict__ q,
                                                       double *__restrict__ u,
                                                       const PcgState *__restrict__ st, int first,
-                                                      int defer_u, double *__restrict__ partial, int lb, int nblocks) {
+                                                      int defer_u, double *__restrict__ partial, int lb, int nblocks,
+                                                      const double *__restrict__ tz3 = nullptr) {
   constexpr int U = 4;
   constexpr int CH = 4 / NSEG;
   __shared__ double sh[4];
@@ -1415,8 +1454,14 @@ __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__
     auto dir = [&](long long idx) -> double {
       return first ? (double)z[idx] : (double)z[idx] + beta * pold[idx];
     };
-    auto cell = [&](int k, double pc, double pm, double pp, double pw, double pe, double ps,
-                    double pn) -> double {
+    // faces below and above level k of this column
+    auto tlo = [&](int k) -> double { if constexpr (C3) return tz3[os + (long long)k * H]; else return tz[k]; };
+    auto thi = [&](int k) -> double {
+      if constexpr (C3) return k + 1 < nz ? tz3[os + (long long)(k + 1) * H] : 0.0;
+      else return tz[k + 1];
+    };
+    auto cell = [&](int k, double zlo, double zhi, double pc, double pm, double pp, double pw, double pe,
+                    double ps, double pn) -> double {
       double acc = tv[k] * pc;
       if (hx) {
         acc = acc + tx[k] * (pc - pw);
@@ -1426,18 +1471,20 @@ __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__
         acc = acc + ty[k] * (pc - ps);
         acc = acc + ty[k] * (pc - pn);
       }
-      acc = acc + tz[k] * (pc - pm);
-      acc = acc + tz[k + 1] * (pc - pp);
+      acc = acc + zlo * (pc - pm);
+      acc = acc + zhi * (pc - pp);
       return acc;
     };
     double pc = dir(os + (long long)k0 * H);
     double pm = k0 > 0 ? dir(os + (long long)(k0 - 1) * H) : pc;
     int k = k0;
     for (; k + U <= k1; k += U) {
-      double pp[U], pw[U], pe[U], ps[U], pn[U], uu[U], po[U], p2[U];
+      double pp[U], pw[U], pe[U], ps[U], pn[U], uu[U], po[U], p2[U], zl[U], zh[U];
 #pragma unroll
       for (int t = 0; t < U; ++t) {
         const long long o = (long long)(k + t) * H;
+        zl[t] = tlo(k + t);
+        zh[t] = thi(k + t);
         pp[t] = dir(os + (long long)min(k + t + 1, nz - 1) * H);
         pw[t] = hx ? dir(oo + nb.w + o) : 0.0;
         pe[t] = hx ? dir(oo + nb.e + o) : 0.0;
@@ -1450,7 +1497,7 @@ __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__
 #pragma unroll
       for (int t = 0; t < U; ++t) {
         const long long o = (long long)(k + t) * H;
-        const double acc = cell(k + t, pc, pm, pp[t], pw[t], pe[t], ps[t], pn[t]);
+        const double acc = cell(k + t, zl[t], zh[t], pc, pm, pp[t], pw[t], pe[t], ps[t], pn[t]);
         q[os + o] = acc;
         pnew[os + o] = pc;
         if (defer_u) {
@@ -1466,8 +1513,9 @@ __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__
     for (; k < k1; ++k) {
       const long long o = (long long)k * H;
       const double pp = dir(os + (long long)min(k + 1, nz - 1) * H);
-      const double acc = cell(k, pc, pm, pp, hx ? dir(oo + nb.w + o) : 0.0, hx ? dir(oo + nb.e + o) : 0.0,
-                              hy ? dir(oo + nb.s + o) : 0.0, hy ? dir(oo + nb.n + o) : 0.0);
+      const double acc = cell(k, tlo(k), thi(k), pc, pm, pp, hx ? dir(oo + nb.w + o) : 0.0,
+                              hx ? dir(oo + nb.e + o) : 0.0, hy ? dir(oo + nb.s + o) : 0.0,
+                              hy ? dir(oo + nb.n + o) : 0.0);
       q[os + o] = acc;
       pnew[os + o] = pc;
       if (defer_u) {
@@ -1484,7 +1532,7 @@ __device__ __forceinline__ void apply_dir_body(Geo L, const double *__restrict__
   if (threadIdx.x == 0) partial[lb] = s;
 }
 
-template <typename Z, int NSEG>
+template <typename Z, int NSEG, bool C3 = false>
 __global__ __launch_bounds__(kBlock) void k_apply_dir(Geo L, const double *__restrict__ tab,
                                                       const Z *__restrict__ z,
                                                       const double *__restrict__ pold,
@@ -1493,9 +1541,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_dir(Geo L, const double *__res
                                                       double *__restrict__ q,
                                                       double *__restrict__ u,
                                                       const PcgState *__restrict__ st, int first,
-                                                      int defer_u, double *__restrict__ partial) {
-  apply_dir_body<Z, NSEG>(L, tab, z, pold, pold2, pnew, q, u, st, first, defer_u, partial, logical_block(),
-                          gridDim.x);
+                                                      int defer_u, double *__restrict__ partial,
+                                                      const double *__restrict__ tz3 = nullptr) {
+  apply_dir_body<Z, NSEG, C3>(L, tab, z, pold, pold2, pnew, q, u, st, first, defer_u, partial, logical_block(),
+                              gridDim.x, tz3);
 }
 
 // r <- r - alpha q, partial sums of ||r||^2
@@ -1806,18 +1855,38 @@ __device__ __forceinline__ double op_row(const double *__restrict__ tab, int P, 
   return acc;
 }
 
+// The same row with the two vertical faces given (per-column coefficients).
+__device__ __forceinline__ double op_row_v(const double *__restrict__ tab, int P, int k, bool hx, bool hy,
+                                           double tzlo, double tzhi, double uc, double um, double up,
+                                           double uw, double ue, double us, double un) {
+  double acc = tab[TV * P + k] * uc;
+  if (hx) {
+    acc = acc + tab[TX * P + k] * (uc - uw);
+    acc = acc + tab[TX * P + k] * (uc - ue);
+  }
+  if (hy) {
+    acc = acc + tab[TY * P + k] * (uc - us);
+    acc = acc + tab[TY * P + k] * (uc - un);
+  }
+  acc = acc + tzlo * (uc - um);
+  acc = acc + tzhi * (uc - up);
+  return acc;
+}
+
 // us = u0 and r = V f - A u0 in the split layout, from plane-major f and u0;
 // partial[2 lb] = sum (V f)^2, partial[2 lb + 1] = sum r^2 over the block.
 // One block = 64 plane-major columns (lanes are consecutive i: every
 // plane-major access is coalesced, and each colour receives 32 consecutive
 // split entries per wavefront), one k-segment of four per wavefront.
 // Blocks past the last column write zero partial sums.
+// C3: the vertical faces of each column from the split-layout field tz3.
+template <bool C3 = false>
 __device__ __forceinline__ void begin_body(Geo L, const double *__restrict__ tab,
                                            const double *__restrict__ vol,
                                            const double *__restrict__ f,
                                            const double *__restrict__ u0, double *__restrict__ us,
                                            double *__restrict__ r, double *__restrict__ partial,
-                                           int lb) {
+                                           int lb, const double *__restrict__ tz3 = nullptr) {
   constexpr int NSEG = 4, U = 4;
   __shared__ double sh[4];
   const int sg = wave_id();
@@ -1860,7 +1929,14 @@ __device__ __forceinline__ void begin_body(Geo L, const double *__restrict__ tab
       for (int t = 0; t < U; ++t) {
         if (k + t < k1) {
           const int kk = k + t;
-          const double acc = op_row(tab, P, kk, hx, hy, uc, um, up[t], uw[t], ue[t], usv[t], un[t]);
+          double acc;
+          if constexpr (C3) {
+            const double *__restrict__ zc = tz3 + (long long)c * L.cs + m;
+            acc = op_row_v(tab, P, kk, hx, hy, zc[(long long)kk * S], kk + 1 < nz ? zc[(long long)(kk + 1) * S] : 0.0,
+                           uc, um, up[t], uw[t], ue[t], usv[t], un[t]);
+          } else {
+            acc = op_row(tab, P, kk, hx, hy, uc, um, up[t], uw[t], ue[t], usv[t], un[t]);
+          }
           const double b = vol[kk] * fv[t];
           const double res = b - acc;
           usc[(long long)kk * S] = uc;
@@ -1889,6 +1965,7 @@ __device__ __forceinline__ void begin_body(Geo L, const double *__restrict__ tab
 // One block = 64 split slots with alternating colours (a red and a black
 // column side by side are adjacent plane-major cells, so the plane-major
 // accesses are coalesced too), one k-segment of four per wavefront.
+template <bool C3 = false>
 __device__ __forceinline__ void finish_body(Geo L, const double *__restrict__ tab,
                                             const double *__restrict__ vol,
                                             const double *__restrict__ f,
@@ -1896,7 +1973,7 @@ __device__ __forceinline__ void finish_body(Geo L, const double *__restrict__ ta
                                             const double *__restrict__ p, double alpha,
                                             const double *__restrict__ p2, double alpha2, int with_p,
                                             double *__restrict__ u, double *__restrict__ partial,
-                                            int lb) {
+                                            int lb, const double *__restrict__ tz3 = nullptr) {
   constexpr int NSEG = 4, U = 4;
   __shared__ double sh[4];
   const int sg = wave_id();
@@ -1943,7 +2020,14 @@ __device__ __forceinline__ void finish_body(Geo L, const double *__restrict__ ta
       for (int t = 0; t < U; ++t) {
         if (k + t < k1) {
           const int kk = k + t;
-          const double acc = op_row(tab, P, kk, hx, hy, uc, um, up[t], uw[t], ue[t], usv[t], un[t]);
+          double acc;
+          if constexpr (C3) {
+            const double *__restrict__ zc = tz3 + os;
+            acc = op_row_v(tab, P, kk, hx, hy, zc[(long long)kk * S], kk + 1 < nz ? zc[(long long)(kk + 1) * S] : 0.0,
+                           uc, um, up[t], uw[t], ue[t], usv[t], un[t]);
+          } else {
+            acc = op_row(tab, P, kk, hx, hy, uc, um, up[t], uw[t], ue[t], usv[t], un[t]);
+          }
           const double b = vol[kk] * fv[t];
           const double res = b - acc;
           u[(long long)kk * plane + oc] = uc;
@@ -1963,15 +2047,18 @@ __device__ __forceinline__ void finish_body(Geo L, const double *__restrict__ ta
   }
 }
 
+template <bool C3 = false>
 __global__ __launch_bounds__(kBlock) void k_begin(Geo L, const double *__restrict__ tab,
                                                   const double *__restrict__ vol,
                                                   const double *__restrict__ f,
                                                   const double *__restrict__ u0,
                                                   double *__restrict__ us, double *__restrict__ r,
-                                                  double *__restrict__ partial) {
-  begin_body(L, tab, vol, f, u0, us, r, partial, logical_block());
+                                                  double *__restrict__ partial,
+                                                  const double *__restrict__ tz3 = nullptr) {
+  begin_body<C3>(L, tab, vol, f, u0, us, r, partial, logical_block(), tz3);
 }
 
+template <bool C3 = false>
 __global__ __launch_bounds__(kBlock) void k_finish(Geo L, const double *__restrict__ tab,
                                                    const double *__restrict__ vol,
                                                    const double *__restrict__ f,
@@ -1979,9 +2066,10 @@ __global__ __launch_bounds__(kBlock) void k_finish(Geo L, const double *__restri
                                                    const double *__restrict__ p,
                                                    const double *__restrict__ p2,
                                                    const PcgState *__restrict__ st, int with_p,
-                                                   double *__restrict__ u, double *__restrict__ partial) {
-  finish_body(L, tab, vol, f, us, p, with_p ? st->alpha : 0.0, p2, with_p == 2 ? st->alpha_prev : 0.0, with_p, u,
-              partial, logical_block());
+                                                   double *__restrict__ u, double *__restrict__ partial,
+                                                   const double *__restrict__ tz3 = nullptr) {
+  finish_body<C3>(L, tab, vol, f, us, p, with_p ? st->alpha : 0.0, p2, with_p == 2 ? st->alpha_prev : 0.0, with_p, u,
+                  partial, logical_block(), tz3);
 }
 
 // The start and the end of a solve on the tiles of the CG operator step (a

@@ -67,7 +67,7 @@ EXPORTS = ["ell_grid_create", "ell_grid_destroy", "ell_grid_bytes", "ell_grid_le
            "ell_batch_create", "ell_batch_grid", "ell_batch_release", "ell_batch_bytes_in_use",
            "ell_batch_submit", "ell_batch_poll", "ell_batch_wait", "ell_batch_destroy",
            "ell_autotune", "ell_schedule_get", "ell_schedule_set", "ell_mg_solve",
-           "ell_apply_A_noalloc"]
+           "ell_apply_A_noalloc", "ell_grid_create_varying"]
 ELL_NOALLOC_MAX_NZ = 1024
 
 _lib = None
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
     L = ctypes.CDLL(path)
     vp, i32 = ctypes.c_void_p, ctypes.c_int
     L.ell_grid_create.argtypes = [ctypes.POINTER(GridDesc), ctypes.POINTER(vp)]
+    L.ell_grid_create_varying.argtypes = [ctypes.POINTER(GridDesc), _dp, ctypes.POINTER(vp)]
     L.ell_grid_destroy.argtypes = [vp]
     L.ell_grid_bytes.argtypes = [ctypes.POINTER(GridDesc)]
     L.ell_grid_bytes.restype = ctypes.c_size_t
@@ -250,12 +251,21 @@ class Grid:
     """Device-resident grid, multigrid hierarchy and solver workspace."""
 
     def __init__(self, nx, ny, nz, hx, hy, omega2, dz, lambda2, n_levels=0, nu_pre=1, nu_post=1,
-                 nu_coarse=1, rho=1.0, prolong=0, precision="fp64"):
+                 nu_coarse=1, rho=1.0, prolong=0, precision="fp64", lambda2_3d=None):
+        """lambda2_3d: None, or a (nz, ny, nx) field of lambda^2 cell values that
+        replaces lambda2 (ell_grid_create_varying)."""
         L = load_library()
         d, keep = make_desc(nx, ny, nz, hx, hy, omega2, dz, lambda2, n_levels, nu_pre, nu_post,
                             nu_coarse, rho, prolong, precision)
         h = ctypes.c_void_p()
-        _check(L.ell_grid_create(ctypes.byref(d), ctypes.byref(h)))
+        if lambda2_3d is None:
+            _check(L.ell_grid_create(ctypes.byref(d), ctypes.byref(h)))
+        else:
+            lam3 = np.ascontiguousarray(np.asarray(lambda2_3d, dtype=np.float64))
+            if lam3.shape != (nz, ny, nx):
+                raise ValueError("lambda2_3d must have shape (nz, ny, nx)")
+            _check(L.ell_grid_create_varying(ctypes.byref(d), lam3.ctypes.data_as(_dp), ctypes.byref(h)))
+        self.varying = lambda2_3d is not None
         self._h = h
         self.nx, self.ny, self.nz = nx, ny, nz
         self.precision = d.precision
@@ -273,7 +283,8 @@ class Grid:
     def from_problem(cls, p, precision="fp64", **over):
         kw = dict(nx=p.nx, ny=p.ny, nz=p.nz, hx=p.hx, hy=p.hy, omega2=p.omega2, dz=p.dz,
                   lambda2=p.lambda2, n_levels=p.n_levels, nu_pre=p.nu_pre, nu_post=p.nu_post,
-                  nu_coarse=p.nu_coarse, rho=p.rho, prolong=p.prolong, precision=precision)
+                  nu_coarse=p.nu_coarse, rho=p.rho, prolong=p.prolong, precision=precision,
+                  lambda2_3d=getattr(p, "lambda2_3d", None))
         kw.update(over)
         return cls(**kw)
 

@@ -1,0 +1,172 @@
+"""GPU parity of horizontally varying vertical coefficients (a 3D lambda^2
+field: every column its own vertical faces and Thomas factors; coarse faces
+are the sums of the children's) against the oracle, through the C ABI.
+
+Operator (Sec. 3.1), both colours of line relaxation on every level (Sec. 4.2
+eq. BlockRBSOR, Appendix B Thomas algorithm per column), residual plus
+restriction, one V-cycle (Sec. 4.3), and whole solves (Appendix B, Alg. PCG;
+stand-alone multigrid) at equal iteration counts, also at 512 x 512 x 128."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import small_grid
+from solve_parity import check_solve
+from paper_1307_2036_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+EPS = 2.0 ** -52
+
+
+@pytest.fixture(scope="module")
+def ell():
+    from paper_1307_2036_amd import ell as E
+    E.load_library()
+    assert torch.cuda.is_available()
+    return E
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def zeros(shape):
+    return torch.zeros(shape, dtype=torch.float64, device="cuda")
+
+
+def pair(ell, orc, nx, ny, nz, seed=1, sigma=0.8, graded=True, **mg):
+    """Oracle grid with per-column faces and the GPU grid of the same field."""
+    g = small_grid(orc, nx, ny, nz, graded=graded, seed=seed, **mg)
+    lam3 = I.lambda2_3d(nx, ny, g.lambda2, sigma, seed + 100)
+    g.tz3 = orc.tz3_from_lambda2(nx, ny, nz, g.hx, g.hy, g.omega2, g.dz, lam3)
+    G = ell.Grid(g.nx, g.ny, g.nz, g.hx, g.hy, g.omega2, g.dz, g.lambda2, g.n_levels, g.nu_pre, g.nu_post,
+                 g.nu_coarse, g.rho, g.prolong, lambda2_3d=lam3)
+    return g, G, lam3
+
+
+SHAPES = [((64, 32, 24), 3), ((34, 10, 100), 1), ((68, 12, 100), 2), ((6, 1, 5), 1), ((1, 6, 4), 1),
+          ((16, 8, 300), 2), ((32, 32, 16), 0)]
+
+
+@pytest.mark.parametrize("shape,levels", SHAPES)
+def test_varying_operator_and_levels_match_oracle(ell, orc, shape, levels):
+    nx, ny, nz = shape
+    g, G, _ = pair(ell, orc, nx, ny, nz, seed=nx + nz, n_levels=levels)
+    assert G.varying and not any(G.features.values())
+    rng = np.random.default_rng(nz)
+    x = rng.standard_normal(g.shape)
+    y = host(G.apply_A(dev(x)))
+    assert np.all(np.abs(y - orc.apply(g, x)) <= 16 * EPS * orc.apply_abs(g, x))
+    gl = g
+    for lv in range(G.levels):
+        # operator of the level (coarse faces summed from the children's)
+        xl = rng.standard_normal(gl.shape)
+        yl = zeros(gl.shape)
+        ys = G.level_empty(lv)
+        G.level_apply(lv, G.to_split(lv, dev(xl)), ys)
+        yl = host(G.from_split(lv, ys, yl))
+        assert np.all(np.abs(yl - orc.apply(gl, xl)) <= 16 * EPS * orc.apply_abs(gl, xl)), lv
+        # red from zero, black, red again (rho = 1)
+        b = rng.standard_normal(gl.shape) * (gl.hx * gl.hy * gl.dz)[:, None, None]
+        bs = G.to_split(lv, dev(b))
+        us = G.level_empty(lv)
+        G.level_smooth(lv, 0, bs, us, zero_init=True)
+        G.level_smooth(lv, 1, bs, us)
+        G.level_smooth(lv, 0, bs, us)
+        ref = orc.smooth_colour(gl, 0, b, orc.smooth_colour(gl, 1, b, orc.smooth_colour(
+            gl, 0, b, np.zeros(gl.shape))))
+        got = host(G.from_split(lv, us, zeros(gl.shape)))
+        scale = np.abs(ref).max(axis=0, keepdims=True)
+        assert np.all(np.abs(got - ref) <= 1e-12 * scale + 1e-300), (lv, np.abs(got - ref).max())
+        if lv + 1 < G.levels:
+            # residual + restriction, general and after a colour-1 sweep
+            u = rng.standard_normal(gl.shape)
+            gc = gl.coarse()
+            for bz in (False, True):
+                uu = u
+                if bz:
+                    uu = orc.smooth_colour(gl, 1, b, u)
+                bc = G.level_empty(lv + 1)
+                G.level_resid_restrict(lv, bs, G.to_split(lv, dev(uu)), bc, black_zero=bz)
+                got = host(G.from_split(lv + 1, bc, zeros(gc.shape)))
+                ref = orc.restrict(gl, orc.residual(gl, b, uu))
+                bound = 64 * EPS * orc.restrict(gl, orc.apply_abs(gl, uu) + np.abs(b))
+                assert np.all(np.abs(got - ref) <= bound), (lv, bz)
+            gl = gc
+
+
+@pytest.mark.parametrize("shape,levels,rho", [((64, 32, 24), 3, 1.0), ((32, 16, 40), 0, 1.0),
+                                              ((16, 16, 12), 2, 0.8), ((1, 1, 33), 1, 1.0)])
+def test_varying_vcycle_matches_oracle(ell, orc, shape, levels, rho):
+    nx, ny, nz = shape
+    g, G, _ = pair(ell, orc, nx, ny, nz, seed=nx * ny + nz, n_levels=levels, rho=rho, nu_coarse=2)
+    r = np.random.default_rng(4).standard_normal(g.shape) * (g.hx * g.hy * g.dz)[:, None, None]
+    assert rel(host(G.vcycle(dev(r))), orc.vcycle(g, r)) <= 1e-11
+
+
+@pytest.mark.parametrize("shape,levels", [((64, 64, 32), 0), ((96, 32, 64), 3), ((32, 32, 130), 0)])
+def test_varying_solves_match_oracle(ell, orc, shape, levels):
+    nx, ny, nz = shape
+    p = I.paper_graded_problem(f"var{nx}", nx, ny, nz, 1e-2, 11 + nz, 12 + nz)
+    p.n_levels = levels
+    p.lambda2_3d = I.lambda2_3d(nx, ny, p.lambda2, 0.8, 13 + nz)
+    g = orc.Grid.from_problem(p)
+    assert g.tz3 is not None
+    G = ell.Grid.from_problem(p)
+    for flexible in (True, False):
+        u, st = G.pcg_solve(dev(p.f), rtol=p.rtol, flexible=flexible)
+        assert st.status == 0
+        print(shape, flexible, check_solve(orc, g, p.f, host(u), st, p.rtol, flexible=flexible))
+    u, st = G.mg_solve(dev(p.f), rtol=p.rtol)
+    assert st.status == 0
+    u_k, st_k = orc.mg_solve(g, p.f, rtol=0.0, maxiter=st.iters)
+    assert rel(host(u), u_k) <= 1e-10
+
+
+def test_horizontally_constant_field_equals_the_plain_grid(ell, orc):
+    p = I.paper_graded_problem("const3d", 64, 32, 40, 1e-2, 5, 6)
+    G0 = ell.Grid.from_problem(p)
+    G3 = ell.Grid.from_problem(p, lambda2_3d=np.broadcast_to(p.lambda2[:, None, None], (40, 32, 64)))
+    f = dev(p.f)
+    u0, s0 = G0.pcg_solve(f, rtol=0.0, maxiter=6)
+    u3, s3 = G3.pcg_solve(f, rtol=0.0, maxiter=6)
+    assert s0.iters == s3.iters == 6
+    assert rel(host(u3), host(u0)) <= 1e-12
+
+
+def test_varying_grid_rejects_bad_input(ell, orc):
+    p = I.paper_graded_problem("bad3d", 16, 16, 8, 1e-2, 5, 6)
+    lam3 = I.lambda2_3d(16, 16, p.lambda2, 0.5, 7)
+    with pytest.raises(ell.EllError) as e:
+        ell.Grid.from_problem(p, precision="fp32", lambda2_3d=lam3)
+    assert e.value.code == ell.ELL_ERR_INVALID
+    bad = lam3.copy()
+    bad[3, 2, 1] = 0.0
+    with pytest.raises(ell.EllError) as e:
+        ell.Grid.from_problem(p, lambda2_3d=bad)
+    assert e.value.code == ell.ELL_ERR_INVALID
+
+
+@pytest.mark.slow
+def test_varying_fullsize_solve(ell, orc):
+    """512 x 512 x 128, the graded profile of config 1 modulated horizontally,
+    four levels, five coarse sweeps: the iterates at the GPU's stopping count
+    against the oracle's (printed beta)."""
+    p = I.varying_problem()
+    g = orc.Grid.from_problem(p)
+    G = ell.Grid.from_problem(p)
+    u, st = G.pcg_solve(dev(p.f), rtol=p.rtol, flexible=False)
+    assert st.status == 0
+    u_k, st_k = orc.pcg(g, p.f, rtol=0.0, maxiter=st.iters, flexible=False)
+    err = rel(host(u), u_k)
+    print("varying 512^2x128: iters", st.iters, "rel_l2", err)
+    assert err <= 1e-10
