@@ -9,11 +9,12 @@ line: the error of the timed path's solution against the FP64 oracle at the
 same iteration count; the same problem with five levels, at standard depth
 and with the mixed-precision preconditioner; the 1024 x 1024 x 128 omega^2
 sweep in mixed precision and FP64; the 64-instance uneven batch; the serving
-loop; and the oracle timed on the host (1 thread and all threads) for the
-32 x 32 x 16, 512 x 512 x 128, 1024 x 1024 x 128 and batched workloads.
+loop; the same 512 x 512 x 128 problem with horizontally varying vertical
+coefficients; and the oracle timed on the host (1 thread and all threads) for
+the 32 x 32 x 16, 512 x 512 x 128, 1024 x 1024 x 128 and batched workloads.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--quick]
-  python bench.py --workload c2|batch|serve|robust    (one workload, its own line)
+  python bench.py --workload c2|batch|serve|robust|varying    (one workload, its own line)
 """
 from __future__ import annotations
 
@@ -43,10 +44,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true",
                     help="the timed 512^2x128 solve only (no other workloads, no oracle legs)")
-    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "batch", "serve", "robust"],
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "batch", "serve", "robust", "varying"],
                     help="c1: the 512^2x128 solve (default); c2: the 1024^2x128 omega^2 sweep; "
                          "batch: 64 uneven solves in the batch engine vs sequential FP64; "
-                         "serve: Poisson request stream; robust: the robustness sweep")
+                         "serve: Poisson request stream; robust: the robustness sweep; "
+                         "varying: 512^2x128 with horizontally varying vertical coefficients")
     ap.add_argument("--autotune", action="store_true",
                     help="run the schedule autotuner on the workload's grid shape(s) before timing "
                          "(outside the timed region) and report the chosen schedule")
@@ -369,6 +371,8 @@ def bench_c1(a):
         progress("c3")
         extra["c4"] = serve_summary(a, seconds=min(a.serve_seconds, 6.0))
         progress("c4")
+        extra["varying"] = varying_summary(a, steps=5)
+        progress("varying")
     if not a.no_cpu_baseline:
         parity, base = oracle_leg(p, gpu_u, iters, flexible)
         out.update(parity)
@@ -549,6 +553,74 @@ def batch_summary(a, steps):
             "fp64_sequential_solves_per_s": seq, "fp64_sequential_iters_mean": float(np.mean(seq_iters)),
             "speedup_vs_fp64_sequential": solves / seq,
             "_gpu_u": gpu_u, "_problem": ("config3", None, None)}
+
+
+# ---------------------------------------------------------------------------
+# horizontally varying vertical coefficients (a 3D lambda^2 field)
+# ---------------------------------------------------------------------------
+def varying_summary(a, steps):
+    """The 512 x 512 x 128 graded problem of config 1 with its lambda^2 profile
+    modulated horizontally (every column its own vertical coefficients), four
+    levels, five coarse sweeps, FP64, printed beta, from u0 = 0 to 1e-5, with
+    the average finest-level half-sweep against the HBM roofline."""
+    import numpy as np
+    import torch
+    from paper_1307_2036_amd import ell, inputs, perfmodel
+    p = inputs.varying_problem()
+    G = ell.Grid.from_problem(p)
+    f = torch.from_numpy(p.f).cuda()
+    u = torch.zeros_like(f)
+    for _ in range(max(a.warmup, 1)):
+        u.zero_()
+        _, st = G.pcg_solve(f, u, rtol=p.rtol, flexible=False, poll_every=8)
+    iters = st.iters
+    G.profile_enable(ell.ELL_K_SMOOTH0, 4 * (iters + 2) * steps + 64)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        u.zero_()
+        _, st = G.pcg_solve(f, u, rtol=p.rtol, flexible=False, poll_every=8)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert st.status == 0, st
+    ts_ = G.profile_times(ell.ELL_K_SMOOTH0)
+    ts_ = ts_[ts_ > 0.25 * float(np.median(ts_))]
+    avg_ms = float(ts_.mean())
+    launch_bytes = perfmodel.smooth0_launch_bytes_varying(p.n)
+    achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
+    it_bytes = perfmodel.pcg_iteration_bytes_varying(p.n, G.levels, p.nu_coarse, flexible=False)
+    solves = steps / elapsed
+    G.close()
+    del f, u
+    torch.cuda.empty_cache()
+    return {"workload": f"gmg-pcg {p.nx}x{p.ny}x{p.nz} graded, lambda^2 profile modulated horizontally "
+                        "(sigma 0.5), per-column vertical coefficients, 4 levels, nu_coarse=5, FP64, "
+                        "printed beta, rtol 1e-5, u0=0",
+            "unknowns": p.n, "iters": iters, "solves_per_s": solves, "ms": elapsed / steps * 1e3,
+            "p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
+            "unknowns_iter_per_s": p.n * iters * solves,
+            "hbm_gbs_algorithmic": it_bytes * iters * solves / 1e9,
+            "roofline": {"bound": "hbm", "kernel": "finest-level line relaxation, k_smooth (per-column "
+                                                   "coefficients), average over the four half-sweeps",
+                         "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "avg_launch_us": avg_ms * 1e3,
+                         "launches": int(ts_.size), "bytes_per_launch": launch_bytes}}
+
+
+def bench_varying(a):
+    s = varying_summary(a, a.steps)
+    out = {
+        "metric": METRIC, "value": s["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": s["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded N(0,1) f, graded dz, log-normal lambda^2 profile modulated horizontally)",
+        "config": {"workload": s["workload"], "unknowns": s["unknowns"], "precision": "fp64"},
+    }
+    out.update({k: v for k, v in s.items() if k not in ("workload", "unknowns")})
+    print(json.dumps(out), flush=True)
 
 
 def bench_batch(a):
@@ -744,6 +816,8 @@ def main():
         return bench_batch(a)
     if a.workload == "serve":
         return bench_serve(a)
+    if a.workload == "varying":
+        return bench_varying(a)
     return bench_c1(a)
 
 

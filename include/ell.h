@@ -127,9 +127,9 @@ int ell_grid_destroy(ell_grid *g);
  * horizontally constant lambda^2 this is the re-discretised face exactly).
  * desc->precision must be ELL_FP64.  The grid works with every grid entry point
  * (ell_apply_A, ell_vcycle, ell_pcg_solve, ell_mg_solve, the level entry
- * points) through the column-walking kernels and without the fused forms
- * (ell_grid_features reports none); it holds three FP64 fields per level more
- * than ell_grid_bytes reports.  The batch engine does not take such grids.
+ * points); its sweeps run k-segmented column kernels and none of the fused
+ * forms (ell_grid_features reports none); it holds three FP64 fields per
+ * level (faces, 1/p_k, T_{k+1/2}/p_k) more than ell_grid_bytes reports.  The batch engine does not take such grids.
  * Synchronous; ELL_ERR_INVALID for a bad descriptor or field. */
 int ell_grid_create_varying(const ell_grid_desc *desc, const double *lambda2_3d, ell_grid **out);
 

@@ -567,7 +567,8 @@ bool seg_dispatch(bool fine, int nb, hipStream_t s, const Geo &G, const R *tab, 
 bool tile_ok(const ell_grid *g, int l) {
   const Geo &G = g->lev[l].geo;
   const int Ls = seg_len(G.nz, G.nseg);
-  return g->d.rho == 1.0 && G.has_x && G.has_y && g->smooth_tile && G.hx2 % 2 == 0 && G.ny % 2 == 0 &&
+  return g->d.rho == 1.0 && G.has_x && G.has_y && g->smooth_tile && !g->varying && G.hx2 % 2 == 0 &&
+         G.ny % 2 == 0 &&
          ((G.nseg == 16 && Ls <= 8) || (G.nseg == 8 && Ls <= 16) || (G.nseg == 4 && Ls <= 32));
 }
 
@@ -595,6 +596,28 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
   const bool hxy = G.has_x && G.has_y;
   ProfScope ps(g, ELL_K_SMOOTH0, s, l == 0);
   if constexpr (std::is_same<R, double>::value && std::is_same<TB, double>::value) {
+    if (g->varying && rho1 && hxy && G.nz <= 256) {
+      // every column its own factors, k-segmented: sixteen segments on small
+      // (latency-bound) levels, eight on large ones
+      const int nbs = blocks8(((long long)ncol + kSegCols - 1) / kSegCols * kBlock);
+      const bool small = G.H < 16384 && seg_len(G.nz, 16) <= 16;
+      const int Ls = seg_len(G.nz, small ? 16 : 8);
+      auto go = [&](auto z, auto fn) {
+        constexpr bool Z = decltype(z)::value, FN = decltype(fn)::value;
+        const double *t3 = Lv.tz3, *i3 = Lv.ip3, *c3 = Lv.cf3;
+        if (small) {
+          if (Ls <= 8) k_smooth_seg3<Z, FN, 8, 16, 4><<<nbs, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
+          else k_smooth_seg3<Z, FN, 16, 16, 4><<<nbs, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
+        } else {
+          if (Ls <= 8) k_smooth_seg3<Z, FN, 8, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
+          else if (Ls <= 16) k_smooth_seg3<Z, FN, 16, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
+          else k_smooth_seg3<Z, FN, 32, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
+        }
+      };
+      if (zero) { if (l == 0) go(std::true_type{}, std::true_type{}); else go(std::true_type{}, std::false_type{}); }
+      else { if (l == 0) go(std::false_type{}, std::true_type{}); else go(std::false_type{}, std::false_type{}); }
+      return check_launch("k_smooth_seg3");
+    }
     if (g->varying) {  // every column its own factors: the column kernel
       auto go = [&](auto z, auto r1, auto fn, auto h) {
         k_smooth<double, decltype(z)::value, decltype(r1)::value, decltype(fn)::value, decltype(h)::value, true>
@@ -1199,7 +1222,10 @@ int launch_apply_dir(ell_grid *g, int K, int first, int defer, hipStream_t s) {
   double *pold = dir_buf(g, K - 1), *pold2 = dir_buf(g, K - 2), *pnew = dir_buf(g, K);
   ProfScope ps(g, ELL_K_APPLY, s);
   const Z *zz = (const Z *)zvec<Z>(g);
-  if (g->varying) {
+  if (g->varying && g->apply_tile) {
+    k_apply_dir_tile<Z, true><<<ab, kBlock, 0, s>>>(G, g->apply_nseg, g->tab64_0, zz, pold, pold2, pnew, g->q, g->us,
+                                                    g->st, first, defer, g->partial, g->lev[0].tz3);
+  } else if (g->varying) {
     const double *tz3 = g->lev[0].tz3;
     if (g->stencil_seg == 1)
       k_apply_dir<Z, 1, true><<<ab, kBlock, 0, s>>>(G, g->tab64_0, zz, pold, pold2, pnew, g->q, g->us, g->st, first,
@@ -1524,11 +1550,9 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->fused_prolong = g_fused_prolong;
   g->tiled_ends = (g_tiled_ends && desc->nx > 1 && desc->ny > 1) ? 1 : 0;
   g->batch_layout = batch_layout;
-  if (lam3) {  // per-column coefficients: the column-walking kernels, no fused forms
+  if (lam3) {  // per-column coefficients: no LDS-tiled sweeps (tile_ok), ends or fused forms
     g->varying = true;
-    g->apply_tile = 0;
-    g->stencil_seg = apply_segments(desc->nz);
-    g->smooth_tile = g->fused_dot = g->fused_update = g->fused_prolong = g->tiled_ends = 0;
+    g->fused_dot = g->fused_update = g->fused_prolong = g->tiled_ends = 0;
   }
   g->lev.resize(L);
   auto bail = [&](int rc) {

@@ -550,6 +550,137 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
 }
 
 // -------------------------------------------------------------------------
+// Line relaxation with horizontally varying vertical coefficients (FP64,
+// rho = 1, both horizontal directions), each column split into NSEG
+// k-segments, one wavefront per segment.  Every column has its own factors,
+// known per cell (tz3 = T_{k-1/2}, ip3 = 1/p_k, cf3 = T_{k+1/2}/p_k in the
+// level's split layout), so the two recurrences of a segment run from zero and
+// carry running products of their own multipliers, which the joins use where
+// smooth_seg_body takes the shared per-level tables:
+//   forward  y_k = (g_k + T_{k-1/2} y_{k-1}) / p_k,  pf_k = prod_{i=k0..k} T_{i-1/2}/p_i
+//   backward w_k = y_k + (T_{k+1/2}/p_k) w_{k+1},    qb_k = prod_{i=k..k1-1} T_{i+1/2}/p_i
+// y_k = y_k(local) + pf_k y_in, w_k = w_k(local) + qb_k w_in, with y_in / w_in
+// the true values below / above the segment passed through LDS (an empty
+// segment passes the identity).  Both arrays stay in registers (SEG >= the
+// segment length); CH levels are loaded together (fewer with sixteen
+// segments, whose 1024-lane blocks leave 128 registers per lane).  bo, uo,
+// own: b of colour c, u of the other colour, u of colour c.
+// -------------------------------------------------------------------------
+template <bool ZERO, bool FINE, int SEG, int NSEG, int CH>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const double *__restrict__ tab, int c,
+                                                           const double *__restrict__ bo,
+                                                           const double *__restrict__ uo,
+                                                           double *__restrict__ own,
+                                                           const int *__restrict__ done,
+                                                           const double *__restrict__ tz3,
+                                                           const double *__restrict__ ip3,
+                                                           const double *__restrict__ cf3) {
+  __shared__ double xv[NSEG][kSegCols], xq[NSEG][kSegCols];
+  if (is_done(done)) return;
+  const int lane = threadIdx.x & 63;
+  const int sg = wave_id();
+  const int ncol = c ? L.ncol1 : L.ncol0;
+  const int m = logical_block() * kSegCols + lane;
+  const bool valid = m < ncol;
+  const int mm = valid ? m : ncol - 1;  // in-bounds column for the loads of idle lanes
+  const int nz = L.nz, Ls = seg_len(nz, NSEG);
+  const int k0 = min(sg * Ls, nz), k1 = min(k0 + Ls, nz), len = k1 - k0;
+  int i, j;
+  col_ij(L, c, mm, i, j);
+  const Nbr nb = ZERO ? Nbr{0, 0, 0, 0} : neighbours(L, i, j);
+  const long long H = L.S;
+  const long long oc = (long long)c * L.cs + mm;
+  const double *__restrict__ bb = bo + mm;
+  const double *__restrict__ uw = uo + nb.w;
+  const double *__restrict__ ue = uo + nb.e;
+  const double *__restrict__ us = uo + nb.s;
+  const double *__restrict__ un = uo + nb.n;
+  double *__restrict__ ow = own + mm;
+  const double *__restrict__ zc = tz3 + oc;
+  const double *__restrict__ pc = ip3 + oc;
+  const double *__restrict__ fc = cf3 + oc;
+  const double *__restrict__ tx = tab + TX * L.P;
+  const double *__restrict__ ty = tab + TY * L.P;
+
+  static_assert(SEG % CH == 0, "chunks must tile the segment");
+  double y[SEG], pr[SEG];
+  double prev = 0.0, prod = 1.0;
+#pragma unroll
+  for (int c0 = 0; c0 < SEG; c0 += CH) {
+    if (c0 < len) {
+      double g[CH], a[CH], d[CH];
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        const int k = min(k0 + c0 + t, k1 - 1);
+        const long long o = (long long)k * H;
+        double v = ld_s<FINE>(&bb[o]);
+        if (!ZERO) {
+          v = v + tx[k] * (uw[o] + ue[o]);
+          v = v + ty[k] * (us[o] + un[o]);
+        }
+        g[t] = v;
+        a[t] = zc[o];
+        d[t] = pc[o];
+      }
+#pragma unroll
+      for (int t = 0; t < CH; ++t) {
+        if (c0 + t < len) {
+          prev = (g[t] + a[t] * prev) * d[t];
+          prod = prod * (a[t] * d[t]);
+          y[c0 + t] = prev;
+          pr[c0 + t] = prod;
+        }
+      }
+    }
+  }
+  // forward join: y_in of segment sg from the segments below it
+  xv[sg][lane] = prev;
+  xq[sg][lane] = prod;
+  __syncthreads();
+  double yin = 0.0;
+#pragma unroll
+  for (int q = 0; q < NSEG - 1; ++q) {
+    const double cand = xv[q][lane] + xq[q][lane] * yin;
+    yin = q < sg ? cand : yin;
+  }
+  __syncthreads();
+  // true y, then the local backward recurrence and its product (in place)
+  double nxt = 0.0, qprod = 1.0;
+#pragma unroll
+  for (int c0 = SEG - CH; c0 >= 0; c0 -= CH) {
+    if (c0 < len) {
+      double e[CH];
+#pragma unroll
+      for (int t = 0; t < CH; ++t) e[t] = fc[(long long)min(k0 + c0 + t, k1 - 1) * H];
+#pragma unroll
+      for (int t = CH - 1; t >= 0; --t) {
+        if (c0 + t < len) {
+          const double yt = y[c0 + t] + pr[c0 + t] * yin;
+          nxt = yt + e[t] * nxt;
+          qprod = qprod * e[t];
+          y[c0 + t] = nxt;
+          pr[c0 + t] = qprod;
+        }
+      }
+    }
+  }
+  xv[sg][lane] = nxt;
+  xq[sg][lane] = qprod;
+  __syncthreads();
+  double win = 0.0;
+#pragma unroll
+  for (int q = NSEG - 1; q > 0; --q) {
+    const double cand = xv[q][lane] + xq[q][lane] * win;
+    win = q > sg ? cand : win;
+  }
+  if (valid) {
+#pragma unroll
+    for (int t = 0; t < SEG; ++t)
+      if (t < len) ow[(long long)(k0 + t) * H] = y[t] + pr[t] * win;
+  }
+}
+
+// -------------------------------------------------------------------------
 // The same FP64 half-sweep with rho = 1 after the first sweep, with the other
 // colour staged in LDS (FINE: the finest level, streaming accesses).  Five
 // 64-lane loads per level (b and four neighbours) keep the texture units near
@@ -1668,7 +1799,9 @@ __host__ __device__ inline int tile_count(int hx2, int ny) {
   return ((hx2 + kTX - 1) / kTX) * ((ny + kTY - 1) / kTY);
 }
 
-template <typename Z>
+// C3: the vertical faces of each own cell from the split-layout field tz3
+// (T_{k-1/2}), loaded with the level they belong to.
+template <typename Z, bool C3 = false>
 __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const double *__restrict__ tab,
                                                     const Z *__restrict__ z,
                                                     const double *__restrict__ pold,
@@ -1676,7 +1809,8 @@ __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const doubl
                                                     double *__restrict__ pnew, double *__restrict__ q,
                                                     double *__restrict__ u,
                                                     const PcgState *__restrict__ st, int first,
-                                                    int defer_u, double *__restrict__ partial, int lb) {
+                                                    int defer_u, double *__restrict__ partial, int lb,
+                                                    const double *__restrict__ tz3 = nullptr) {
   __shared__ double sp[3][2][kTH][kTW];
   __shared__ double sh[4];
   if (st->done) return;
@@ -1769,19 +1903,35 @@ __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const doubl
     const double *__restrict__ txv = tab + TX * L.P;
     const double *__restrict__ tyv = tab + TY * L.P;
     const double *__restrict__ tz = tab + TZ * L.P;
+    // C3: faces below the own cells of level kk (the face above level kk - 1)
+    double fzc[4] = {0.0, 0.0, 0.0, 0.0}, fzn[4] = {0.0, 0.0, 0.0, 0.0};
+    auto faces = [&](int kk, double *fz) {
+      if constexpr (C3) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) fz[e] = ok[e] ? tz3[off[e] + (long long)kk * S] : 0.0;
+      }
+    };
     double pm[4], pc[4], pn[4];
     level(k0, k0 % 3, true, pc);
+    faces(k0, fzc);
     if (k0 > 0) level(k0 - 1, -1, false, pm);
     else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) pm[e] = pc[e];
     }
     for (int k = k0; k < k1; ++k) {
-      if (k + 1 < k1) level(k + 1, (k + 1) % 3, true, pn);
-      else if (k + 1 < L.nz) level(k + 1, -1, false, pn);
-      else {
+      if (k + 1 < k1) {
+        level(k + 1, (k + 1) % 3, true, pn);
+        faces(k + 1, fzn);
+      } else if (k + 1 < L.nz) {
+        level(k + 1, -1, false, pn);
+        faces(k + 1, fzn);
+      } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) pn[e] = pc[e];
+        for (int e = 0; e < 4; ++e) {
+          pn[e] = pc[e];
+          fzn[e] = 0.0;
+        }
       }
       __syncthreads();
       const int b = k % 3;
@@ -1802,13 +1952,19 @@ __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const doubl
           acc = acc + txv[k] * (pcv - pe);
           acc = acc + tyv[k] * (pcv - ps);
           acc = acc + tyv[k] * (pcv - pnn);
-          acc = acc + tz[k] * (pcv - pm[e]);
-          acc = acc + tz[k + 1] * (pcv - pn[e]);
+          if constexpr (C3) {
+            acc = acc + fzc[e] * (pcv - pm[e]);
+            acc = acc + fzn[e] * (pcv - pn[e]);
+          } else {
+            acc = acc + tz[k] * (pcv - pm[e]);
+            acc = acc + tz[k + 1] * (pcv - pn[e]);
+          }
           __builtin_nontemporal_store(acc, &q[off[e] + o]);
           dot += pcv * acc;
         }
         pm[e] = pc[e];
         pc[e] = pn[e];
+        fzc[e] = fzn[e];
       }
     }
   }
@@ -1816,7 +1972,7 @@ __device__ __forceinline__ void apply_dir_tile_body(Geo L, int nseg, const doubl
   if (threadIdx.x == 0) partial[lb] = s;
 }
 
-template <typename Z>
+template <typename Z, bool C3 = false>
 __global__ __launch_bounds__(kBlock) void k_apply_dir_tile(Geo L, int nseg, const double *__restrict__ tab,
                                                            const Z *__restrict__ z,
                                                            const double *__restrict__ pold,
@@ -1824,8 +1980,10 @@ __global__ __launch_bounds__(kBlock) void k_apply_dir_tile(Geo L, int nseg, cons
                                                            double *__restrict__ pnew, double *__restrict__ q,
                                                            double *__restrict__ u,
                                                            const PcgState *__restrict__ st, int first,
-                                                           int defer_u, double *__restrict__ partial) {
-  apply_dir_tile_body<Z>(L, nseg, tab, z, pold, pold2, pnew, q, u, st, first, defer_u, partial, logical_block());
+                                                           int defer_u, double *__restrict__ partial,
+                                                           const double *__restrict__ tz3 = nullptr) {
+  apply_dir_tile_body<Z, C3>(L, nseg, tab, z, pold, pold2, pnew, q, u, st, first, defer_u, partial, logical_block(),
+                             tz3);
 }
 
 // -------------------------------------------------------------------------

@@ -107,3 +107,36 @@ def smooth0_launch_bytes(n0: int, e: int, nu_pre=1, nu_post=1, fused_update: boo
     total = smooth_bytes(n0, e, True) + (launches - 1) * smooth_bytes(n0, e, False)
     total += (16 * n0 if fused_update else 0) + (8 * n0 if dot_q else 0) + (6 * n0 if fused_prolong else 0)
     return total / launches
+
+
+# ---------------------------------------------------------------------------
+# horizontally varying vertical coefficients (FP64, per-column fields): every
+# half-sweep also reads its colour's faces, 1/p and T/p (24 B per unknown of
+# the colour = 12 B per unknown of the level); the restriction reads the faces
+# of the colour-0 children (4 B); the CG operator step the faces (8 B)
+# ---------------------------------------------------------------------------
+def smooth_bytes_varying(n: int, zero: bool) -> float:
+    return smooth_bytes(n, 8, zero) + 12 * n
+
+
+def smooth0_launch_bytes_varying(n0: int, nu_pre=1, nu_post=1) -> float:
+    """Average algorithmic bytes of one finest-level half-sweep launch."""
+    launches = 2 * nu_pre + 2 * nu_post
+    total = smooth_bytes_varying(n0, True) + (launches - 1) * smooth_bytes_varying(n0, False)
+    return total / launches
+
+
+def pcg_iteration_bytes_varying(n0: int, levels: int, nu_coarse=1, flexible=True, nu_pre=1,
+                                nu_post=1) -> float:
+    """One PCG iteration on a varying grid (separate residual update and dots)."""
+    total = cg_bytes(n0, flexible) + 8 * n0 + vcycle_bytes(n0, levels, 8, nu_pre, nu_post, nu_coarse)
+    n = n0
+    for l in range(levels):
+        if l == levels - 1:
+            sweeps = 2 * (nu_coarse if nu_coarse > 0 else nu_pre + nu_post)
+        else:
+            sweeps = 2 * (nu_pre + nu_post)
+            total += 4 * n
+        total += sweeps * 12 * n
+        n //= 4
+    return total
