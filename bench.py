@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the measured closed-loop capacity")
+    ap.add_argument("--coarse-tail", type=int, default=0, choices=[0, 1],
+                    help="the coarsest level's sweeps in one cooperative launch (1) or one launch "
+                         "per half-sweep (0, faster on MI355X); the same values")
     ap.add_argument("--probe-copy", action="store_true",
                     help="also run one plain device copy of a 268 MB vector (counter calibration)")
     return ap.parse_args()
@@ -808,6 +811,8 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    from paper_1307_2036_amd import ell
+    ell.set_tuning(ell.ELL_TUNE_COARSE_TAIL, a.coarse_tail)
     if a.workload == "c2":
         return bench_c2(a)
     if a.workload == "robust":

@@ -147,15 +147,18 @@ int ell_grid_levels(const ell_grid *g);
  * pre-smoothing pair), ELL_FEAT_FUSED_PROLONG (the finest prolongation rides
  * on the first post-smoothing sweep, for solves with the printed beta),
  * ELL_FEAT_TILED_ENDS (a solve's start, r = V f - A u0, and end, the final
- * update and true residual, run on LDS tiles).  They change where bytes move,
- * not what is computed;
+ * update and true residual, run on LDS tiles), ELL_FEAT_COARSE_TAIL (the
+ * coarsest level's sweeps run in one cooperative launch; cleared if the
+ * runtime refused that launch, the sweeps then run one by one).  They change
+ * where bytes move and how many launches there are, not what is computed;
  * a benchmark's byte model reads them.  Returns ELL_OK or a negative error. */
 enum {
   ELL_FEAT_TILED_SMOOTH = 1,
   ELL_FEAT_FUSED_DOTS = 2,
   ELL_FEAT_FUSED_UPDATE = 4,
   ELL_FEAT_FUSED_PROLONG = 8,
-  ELL_FEAT_TILED_ENDS = 16
+  ELL_FEAT_TILED_ENDS = 16,
+  ELL_FEAT_COARSE_TAIL = 32
 };
 int ell_grid_features(const ell_grid *g, int32_t *mask);
 
@@ -289,7 +292,14 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * = us + alpha p written plane-major, the true residual) on the LDS tiles of
  * the operator step for grids created afterwards with nx, ny > 1, 0 on the
  * column kernels (u and r the same bitwise, the norms up to summation
- * order). */
+ * order); COARSE_TAIL 1 runs the coarsest level's nu_coarse sweep pairs of
+ * every V-cycle (Alg. "Multigrid V-cycle", coarsest-level solve) in one
+ * cooperative launch with grid-wide barriers between the half-sweeps, where
+ * that level's sweeps are the 8- or 16-segment kernels (rho = 1, both
+ * horizontal directions, segments of at most 16 levels); 0 (default) launches
+ * them one by one (the same values, bitwise; on MI355X a barrier across the
+ * eight XCDs costs more than a kernel boundary, so one launch per half-sweep
+ * is faster). */
 enum {
   ELL_TUNE_PLANE_PAD = 0,
   ELL_TUNE_COLOUR_PAD = 1,
@@ -300,7 +310,8 @@ enum {
   ELL_TUNE_FUSED_DOT = 6,
   ELL_TUNE_FUSED_UPDATE = 7,
   ELL_TUNE_FUSED_PROLONG = 8,
-  ELL_TUNE_TILED_ENDS = 9
+  ELL_TUNE_TILED_ENDS = 9,
+  ELL_TUNE_COARSE_TAIL = 10
 };
 int ell_set_tuning(int key, int value);
 

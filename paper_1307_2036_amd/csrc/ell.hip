@@ -171,6 +171,7 @@ struct ell_grid {
   int fused_update = 0;                 // the first pre-smoothing pair updates the CG residual
   int fused_prolong = 0;                // the first post-smoothing sweep applies the finest correction
   int tiled_ends = 0;                   // a solve's start and end run on the operator step's LDS tiles
+  int coarse_tail = 0;                  // the coarsest level's sweeps in one cooperative launch
   double *partial = nullptr;
   long long partial_cap = 0;
   PcgState *st = nullptr;
@@ -212,6 +213,8 @@ int g_fused_dot = 1;    // 1: the last post-smoothing half-sweeps form the CG do
 int g_fused_update = 1; // 1: the first pre-smoothing pair updates the CG residual
 int g_fused_prolong = 1;  // 1: the first post-smoothing sweep applies the finest correction
 int g_tiled_ends = 1;     // 1: a solve's start and end on LDS tiles where both horizontal directions exist
+int g_coarse_tail = 0;    // 1: the coarsest level's sweeps in one cooperative launch where it applies
+                          //    (off by default: measured slower than one launch per half-sweep)
 
 // Smoother segments per column: enough lanes to occupy the chip on small
 // levels, four (the register-resident optimum) on large ones; the finest
@@ -880,6 +883,68 @@ int launch_fill(R *p, long long n, hipStream_t s) {
 // ignores the old black values (the correction is added to red columns only).
 bool pro_path(const ell_grid *g, int dot);
 
+// The coarsest level's nu_coarse sweep pairs in one cooperative launch
+// (k_coarse_sweeps) where its kernels are the 8- or 16-segment ones: rho = 1,
+// both horizontal directions, FP64 with the tiled sweep after the first, FP32
+// with the segmented one (segments of at most 16 levels).  Returns false if it
+// does not apply or the launch was refused (the caller then launches the
+// sweeps one by one, and the grid stops trying).
+template <typename R>
+bool coarse_tail_applies(const ell_grid *g, int l) {
+  const Geo &G = g->lev[l].geo;
+  if (!g->coarse_tail || g->varying || l != g->L - 1 || g->d.nu_coarse < 1 || g->d.rho != 1.0) return false;
+  if (!(G.has_x && G.has_y) || (G.nseg != 16 && G.nseg != 8)) return false;
+  if (seg_len(G.nz, G.nseg) > 16) return false;
+  if constexpr (std::is_same<R, double>::value) return tile_ok(g, l);
+  else return true;
+}
+
+// The instantiation of k_coarse_sweeps a level takes: its segments, the
+// segmented sweep's depth (the smallest of 8 and 16 that holds a segment, as
+// seg_dispatch picks) and the tiled sweep's (8 with 16 segments, else 16, as
+// launch_smooth picks).
+template <typename R>
+const void *coarse_kernel(const Geo &G) {
+  const int Ls = seg_len(G.nz, G.nseg);
+  if (G.nseg == 16)
+    return Ls <= 8 ? reinterpret_cast<const void *>(&k_coarse_sweeps<R, 16, 8, 8>)
+                   : reinterpret_cast<const void *>(&k_coarse_sweeps<R, 16, 16, 8>);
+  return Ls <= 8 ? reinterpret_cast<const void *>(&k_coarse_sweeps<R, 8, 8, 16>)
+                 : reinterpret_cast<const void *>(&k_coarse_sweeps<R, 8, 16, 16>);
+}
+
+template <typename R>
+bool launch_coarse_tail(ell_grid *g, int l, const R *b, R *u, const int *done, hipStream_t s) {
+  if (!coarse_tail_applies<R>(g, l)) return false;
+  const Geo &G = g->lev[l].geo;
+  const int nb0 = (G.ncol0 + kSegCols - 1) / kSegCols;
+  const int ntiles = std::is_same<R, double>::value ? smooth_tiles(G) : 0;
+  const int nb = std::max(8, (std::max(nb0, ntiles) + 7) / 8 * 8);
+  const int threads = G.nseg * 64;
+  const void *kern = coarse_kernel<R>(G);
+  // every block must be resident at once: at most what the chip holds
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess ||
+      nb > cus * per_cu) {
+    (void)hipGetLastError();
+    g->coarse_tail = 0;
+    return false;
+  }
+  Geo Gv = G;
+  const R *tab = (const R *)g->lev[l].tab;
+  int sweeps = g->d.nu_coarse;
+  unsigned *bar = g->st->bar;
+  void *args[] = {&Gv, &tab, &b, &u, &sweeps, &done, &bar};
+  if (hipLaunchCooperativeKernel(kern, dim3(nb), dim3(threads), args, 0, s) != hipSuccess) {
+    (void)hipGetLastError();
+    g->coarse_tail = 0;
+    return false;
+  }
+  return true;
+}
+
 // dot > 0 (top = 0, FP64, the finest level tiled): the last two post-smoothing
 // half-sweeps also form the CG dots (launch_smooth_dot).
 template <typename R>
@@ -905,7 +970,9 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
   }
   {
     const int l = L - 1;
-    if (g->d.nu_coarse > 0) {
+    if (g->d.nu_coarse > 0 && launch_coarse_tail<R>(g, l, B(l), U(l), done, s)) {
+      // all coarsest-level sweeps in one launch
+    } else if (g->d.nu_coarse > 0) {
       for (int it = 0; it < g->d.nu_coarse; ++it) {
         CHK(launch_smooth<R>(g, l, 0, it == 0, B(l), U(l), done, s));
         CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
@@ -1150,6 +1217,7 @@ int stats_from_state(const PcgState &h, ell_solve_stats *out) {
     out->true_r_norm = h.true_r_norm;
     out->b_norm = h.b_norm;
   }
+  if (h.bar[2]) return fail(ELL_ERR_HIP, "a grid-wide barrier of the coarsest-level sweeps timed out");
   if (status == -4) return fail(ELL_ERR_NUMERIC, "non-finite value in the CG recurrence");
   return status == 0 ? ELL_OK : ELL_NOT_CONVERGED;
 }
@@ -1549,6 +1617,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->fused_update = g_fused_update;
   g->fused_prolong = g_fused_prolong;
   g->tiled_ends = (g_tiled_ends && desc->nx > 1 && desc->ny > 1) ? 1 : 0;
+  g->coarse_tail = g_coarse_tail && !batch_layout;
   g->batch_layout = batch_layout;
   if (lam3) {  // per-column coefficients: no LDS-tiled sweeps (tile_ok), ends or fused forms
     g->varying = true;
@@ -1620,6 +1689,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->partial = (double *)tmp;
   if ((rc = dalloc(g, &tmp, sizeof(PcgState))) != ELL_OK) return bail(rc);
   g->st = (PcgState *)tmp;
+  if (hipMemset(g->st, 0, sizeof(PcgState)) != hipSuccess) return bail(fail(ELL_ERR_HIP, "state clear failed"));
   if (hipHostMalloc((void **)&g->st_host, sizeof(PcgState), hipHostMallocDefault) != hipSuccess) {
     g->st_host = nullptr;
     return bail(fail(ELL_ERR_OOM, "pinned state allocation failed"));
@@ -1665,6 +1735,8 @@ int ell_grid_levels(const ell_grid *g) {
 int ell_grid_features(const ell_grid *g, int32_t *mask) {
   if (!g || !mask) return fail(ELL_ERR_INVALID, "NULL argument");
   int m = 0;
+  if (g->prec == ELL_FP64 ? coarse_tail_applies<double>(g, g->L - 1) : coarse_tail_applies<float>(g, g->L - 1))
+    m |= ELL_FEAT_COARSE_TAIL;
   if (g->prec == ELL_FP64) {
     if (tile_ok(g, 0)) m |= ELL_FEAT_TILED_SMOOTH;
     if (fused_dot_path<double>(g)) m |= ELL_FEAT_FUSED_DOTS;
@@ -2060,6 +2132,10 @@ int ell_set_tuning(int key, int value) {
     case ELL_TUNE_TILED_ENDS:
       if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "tiled solve ends are 0 or 1");
       g_tiled_ends = value;
+      return ELL_OK;
+    case ELL_TUNE_COARSE_TAIL:
+      if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "the coarse tail is 0 or 1");
+      g_coarse_tail = value;
       return ELL_OK;
     default: return fail(ELL_ERR_INVALID, "unknown tuning key %d", key);
   }

@@ -56,6 +56,9 @@ struct PcgState {
   double kappa_old, alpha, alpha_prev, beta, r0_norm, b_norm, r_norm, thresh, true_r_norm;
   int iter, done, status, maxiter, flexible;
   int pending;  // a step length alpha waits for its residual update (set by F_ALPHA)
+  // grid_barrier of the cooperative coarsest-level sweeps: arrivals,
+  // generation, a timeout flag (zeroed when the grid is created)
+  unsigned bar[4];
 };
 
 // The deferred solution updates of CG: iteration K's update u += alpha_K p_K
@@ -2593,6 +2596,94 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ 
                                                      int nq, PcgState *__restrict__ st, int mode,
                                                      double rtol, double atol, int rel_to_rhs) {
   finalize_body(partial, nblk, nq, st, mode, rtol, atol, rel_to_rhs, logical_block(), gridDim.x);
+}
+
+// -------------------------------------------------------------------------
+// The coarsest level's sweeps in one cooperative launch (every block
+// resident): nu_coarse red/black pairs from u = 0, the half-sweeps separated
+// by a grid-wide barrier.  Each half-sweep is the device body the per-sweep
+// kernels run, with the same template arguments (the first one the zero-start
+// segmented sweep, the others the LDS-tiled one in FP64 or the segmented one
+// in FP32), so the values are those of the separate launches; the block index
+// of each body comes from the same XCD-contiguous map.
+//
+// grid_barrier: sense-reversing over bar[0] (arrivals) and bar[1]
+// (generation), zeroed once when the grid is created; the last block to
+// arrive resets the count and advances the generation.  Agent-scope fences
+// release a block's writes before it arrives and acquire the others' after it
+// leaves (the XCDs' L2 caches are not coherent with each other).  The wait is
+// bounded: a block that polls kBarrierSpins times without the generation
+// moving gives up, raises bar[2] and leaves, so the kernel always ends.
+// -------------------------------------------------------------------------
+constexpr long kBarrierSpins = 1L << 24;
+
+// One release fence before a block arrives and one acquire fence after it
+// leaves; the arrival and the polling are relaxed (an acquiring poll would
+// invalidate the L2 on every read).  The last block to arrive acquires the
+// others' writes before it releases the new generation.
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nblocks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long spins = 0;
+      while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kBarrierSpins) {
+          __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+  }
+  __syncthreads();
+}
+
+// NSEG: the level's k-segments (8 or 16); SEG: the segmented sweep's register
+// depth, TSEG the tiled one's (as the per-sweep dispatch picks them).
+template <typename R, int NSEG, int SEG, int TSEG>
+__global__ __launch_bounds__(NSEG * 64) void k_coarse_sweeps(Geo L, const R *__restrict__ tab,
+                                                             const R *__restrict__ b, R *__restrict__ u,
+                                                             int sweeps, const int *__restrict__ done,
+                                                             unsigned *__restrict__ bar) {
+  if (is_done(done)) return;  // the flag does not change during the launch: every block leaves
+  const int g8 = gridDim.x >> 3;
+  const int lb0 = (blockIdx.x & 7) * g8 + (blockIdx.x >> 3);
+  const long long cs = L.cs;
+  const int nb0 = (L.ncol0 + kSegCols - 1) / kSegCols, nb1 = (L.ncol1 + kSegCols - 1) / kSegCols;
+  const int ntiles = ((L.hx2 + kSTX - 1) / kSTX) * (L.ny / 2);
+  for (int it = 0; it < sweeps; ++it) {
+    for (int c = 0; c < 2; ++c) {
+      const R *bo = b + (long long)c * cs;
+      const R *uo = u + (long long)(1 - c) * cs;
+      R *own = u + (long long)c * cs;
+      if (it == 0 && c == 0) {
+        for (int lb = lb0; lb < nb0; lb += gridDim.x) {
+          smooth_seg_body<R, true, true, false, SEG, NSEG, R>(L, tab, 0, bo, uo, own, R(1), done, lb, nb0);
+          __syncthreads();
+        }
+      } else if constexpr (std::is_same<R, double>::value) {
+        for (int lb = lb0; lb < ntiles; lb += gridDim.x) {
+          smooth_tile_body<TSEG, NSEG, false>(L, tab, c, bo, uo, own, done, lb);
+          __syncthreads();
+        }
+      } else {
+        const int nb = c ? nb1 : nb0;
+        for (int lb = lb0; lb < nb; lb += gridDim.x) {
+          smooth_seg_body<R, false, true, false, SEG, NSEG, R>(L, tab, c, bo, uo, own, R(1), done, lb, nb);
+          __syncthreads();
+        }
+      }
+      if (it + 1 < sweeps || c == 0) grid_barrier(bar, gridDim.x);
+    }
+  }
 }
 
 // -------------------------------------------------------------------------

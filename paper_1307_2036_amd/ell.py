@@ -172,8 +172,10 @@ ELL_TUNE_FUSED_DOT = 6
 ELL_TUNE_FUSED_UPDATE = 7
 ELL_TUNE_FUSED_PROLONG = 8
 ELL_TUNE_TILED_ENDS = 9
+ELL_TUNE_COARSE_TAIL = 10
 ELL_FEAT_TILED_SMOOTH, ELL_FEAT_FUSED_DOTS, ELL_FEAT_FUSED_UPDATE, ELL_FEAT_FUSED_PROLONG = 1, 2, 4, 8
 ELL_FEAT_TILED_ENDS = 16
+ELL_FEAT_COARSE_TAIL = 32
 
 
 def set_tuning(key: int, value: int) -> None:
@@ -277,7 +279,14 @@ class Grid:
                          "fused_dots": bool(m.value & ELL_FEAT_FUSED_DOTS),
                          "fused_update": bool(m.value & ELL_FEAT_FUSED_UPDATE),
                          "fused_prolong": bool(m.value & ELL_FEAT_FUSED_PROLONG),
-                         "tiled_ends": bool(m.value & ELL_FEAT_TILED_ENDS)}
+                         "tiled_ends": bool(m.value & ELL_FEAT_TILED_ENDS),
+                         "coarse_tail": bool(m.value & ELL_FEAT_COARSE_TAIL)}
+
+    def feature_mask(self) -> int:
+        """The current ell_grid_features mask (ELL_FEAT_*)."""
+        m = ctypes.c_int32(0)
+        _check(load_library().ell_grid_features(self._h, ctypes.byref(m)))
+        return m.value
 
     @classmethod
     def from_problem(cls, p, precision="fp64", **over):
