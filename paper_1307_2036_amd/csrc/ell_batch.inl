@@ -93,14 +93,22 @@ __device__ __forceinline__ Geo ugeo(const Geo &g) {
   return r;
 }
 
+// The entry whose block range holds block b (b wave-uniform, every lane
+// active): the entries are sorted by their first block, so the number of
+// entries that start at or before b is the index plus one.  Each lane tests
+// one entry, 64 at a time (one vector load and a ballot per 64 entries, where
+// a binary search waited for log2(n) dependent loads).
 __device__ __forceinline__ int find_ent(const StageEnt *e, int n, int b) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (e[mid].block0 <= b) lo = mid;
-    else hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int cnt = 0;
+  for (int base = 0; base < n; base += 64) {
+    const int i = base + lane;
+    const bool p = i < n && e[i].block0 <= b;
+    const unsigned long long m = __ballot(p);
+    cnt += __popcll(m);
+    if (m != ~0ull) break;  // the first entry past b lies in this chunk
   }
-  return lo;
+  return ui(cnt - 1);
 }
 
 // R: arithmetic type; TB: type of b.  ROLE selects the arrays of the stage.
