@@ -374,7 +374,13 @@ def bench_c1(a):
         progress("c3")
         extra["c4"] = serve_summary(a, seconds=min(a.serve_seconds, 6.0))
         progress("c4")
-        extra["varying"] = varying_summary(a, steps=5)
+        from paper_1307_2036_amd import inputs as _inputs
+        pv = _inputs.varying_problem()
+        extra["varying"] = varying_summary(a, steps=5, p=pv)
+        extra["varying_fp32"] = varying_summary(a, steps=5, precision="fp32", p=pv)
+        extra["varying_fp32"]["speedup_vs_fp64"] = (extra["varying_fp32"]["solves_per_s"] /
+                                                    extra["varying"]["solves_per_s"])
+        del pv
         progress("varying")
     if not a.no_cpu_baseline:
         parity, base = oracle_leg(p, gpu_u, iters, flexible)
@@ -561,21 +567,23 @@ def batch_summary(a, steps):
 # ---------------------------------------------------------------------------
 # horizontally varying vertical coefficients (a 3D lambda^2 field)
 # ---------------------------------------------------------------------------
-def varying_summary(a, steps):
+def varying_summary(a, steps, precision="fp64", p=None):
     """The 512 x 512 x 128 graded problem of config 1 with its lambda^2 profile
     modulated horizontally (every column its own vertical coefficients), four
-    levels, five coarse sweeps, FP64, printed beta, from u0 = 0 to 1e-5, with
-    the average finest-level half-sweep against the HBM roofline."""
+    levels, five coarse sweeps, from u0 = 0 to 1e-5: FP64 with the printed beta,
+    or the mixed-precision V-cycle (FP32 per-column fields) in flexible CG; the
+    average finest-level half-sweep against the HBM roofline."""
     import numpy as np
     import torch
     from paper_1307_2036_amd import ell, inputs, perfmodel
-    p = inputs.varying_problem()
-    G = ell.Grid.from_problem(p)
+    p = inputs.varying_problem() if p is None else p
+    G = ell.Grid.from_problem(p, precision=precision)
+    flexible = precision != "fp64"
     f = torch.from_numpy(p.f).cuda()
     u = torch.zeros_like(f)
     for _ in range(max(a.warmup, 1)):
         u.zero_()
-        _, st = G.pcg_solve(f, u, rtol=p.rtol, flexible=False, poll_every=8)
+        _, st = G.pcg_solve(f, u, rtol=p.rtol, flexible=flexible, poll_every=8)
     iters = st.iters
     G.profile_enable(ell.ELL_K_SMOOTH0, 4 * (iters + 2) * steps + 64)
     torch.cuda.synchronize()
@@ -584,7 +592,7 @@ def varying_summary(a, steps):
     for _ in range(steps):
         ts = time.perf_counter()
         u.zero_()
-        _, st = G.pcg_solve(f, u, rtol=p.rtol, flexible=False, poll_every=8)
+        _, st = G.pcg_solve(f, u, rtol=p.rtol, flexible=flexible, poll_every=8)
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -592,21 +600,29 @@ def varying_summary(a, steps):
     ts_ = G.profile_times(ell.ELL_K_SMOOTH0)
     ts_ = ts_[ts_ > 0.25 * float(np.median(ts_))]
     avg_ms = float(ts_.mean())
-    launch_bytes = perfmodel.smooth0_launch_bytes_varying(p.n)
+    if precision == "fp64":
+        launch_bytes = perfmodel.smooth0_launch_bytes_varying(p.n)
+        it_bytes = perfmodel.pcg_iteration_bytes_varying(p.n, G.levels, p.nu_coarse, flexible=False)
+    else:
+        launch_bytes = perfmodel.smooth0_launch_bytes_varying_hybrid(p.n)
+        it_bytes = perfmodel.pcg_iteration_bytes_varying_hybrid(p.n, G.levels, p.nu_coarse)
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
-    it_bytes = perfmodel.pcg_iteration_bytes_varying(p.n, G.levels, p.nu_coarse, flexible=False)
     solves = steps / elapsed
     G.close()
     del f, u
     torch.cuda.empty_cache()
+    what = ("FP64, printed beta" if precision == "fp64" else
+            "FP32 V-cycle with FP32 per-column fields, FP64 finest post-smoothing with FP64 fields, "
+            "flexible FP64 CG")
     return {"workload": f"gmg-pcg {p.nx}x{p.ny}x{p.nz} graded, lambda^2 profile modulated horizontally "
-                        "(sigma 0.5), per-column vertical coefficients, 4 levels, nu_coarse=5, FP64, "
-                        "printed beta, rtol 1e-5, u0=0",
+                        f"(sigma 0.5), per-column vertical coefficients, 4 levels, nu_coarse=5, {what}, "
+                        "rtol 1e-5, u0=0",
+            "precision": precision,
             "unknowns": p.n, "iters": iters, "solves_per_s": solves, "ms": elapsed / steps * 1e3,
             "p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
             "unknowns_iter_per_s": p.n * iters * solves,
             "hbm_gbs_algorithmic": it_bytes * iters * solves / 1e9,
-            "roofline": {"bound": "hbm", "kernel": "finest-level line relaxation, k_smooth (per-column "
+            "roofline": {"bound": "hbm", "kernel": "finest-level line relaxation, k_smooth_seg3 (per-column "
                                                    "coefficients), average over the four half-sweeps",
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "avg_launch_us": avg_ms * 1e3,
@@ -614,15 +630,15 @@ def varying_summary(a, steps):
 
 
 def bench_varying(a):
-    s = varying_summary(a, a.steps)
+    s = varying_summary(a, a.steps, precision=a.precision)
     out = {
         "metric": METRIC, "value": s["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": s["ms"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64",
+        "vs_baseline": None, "dtype": "f64" if a.precision == "fp64" else "f64-outer/f32-vcycle",
         "data": "synthetic (seeded N(0,1) f, graded dz, log-normal lambda^2 profile modulated horizontally)",
-        "config": {"workload": s["workload"], "unknowns": s["unknowns"], "precision": "fp64"},
+        "config": {"workload": s["workload"], "unknowns": s["unknowns"], "precision": a.precision},
     }
-    out.update({k: v for k, v in s.items() if k not in ("workload", "unknowns")})
+    out.update({k: v for k, v in s.items() if k not in ("workload", "unknowns", "precision")})
     print(json.dumps(out), flush=True)
 
 

@@ -125,12 +125,16 @@ int ell_grid_destroy(ell_grid *g);
  * ell_grid_desc.lambda2, column by column) and its own Thomas factors; a coarse
  * column's face is the sum of its four children's (parallel faces; for a
  * horizontally constant lambda^2 this is the re-discretised face exactly).
- * desc->precision must be ELL_FP64.  The grid works with every grid entry point
- * (ell_apply_A, ell_vcycle, ell_pcg_solve, ell_mg_solve, the level entry
- * points); its sweeps run k-segmented column kernels and none of the fused
- * forms (ell_grid_features reports none); it holds three FP64 fields per
- * level (faces, 1/p_k, T_{k+1/2}/p_k) more than ell_grid_bytes reports.  The batch engine does not take such grids.
- * Synchronous; ELL_ERR_INVALID for a bad descriptor or field. */
+ * desc->precision is ELL_FP64 or ELL_FP32_PRECOND (ELL_BF16COEF returns
+ * ELL_ERR_INVALID).  The grid works with every grid entry point (ell_apply_A,
+ * ell_vcycle, ell_pcg_solve, ell_mg_solve, the level entry points); its sweeps
+ * run k-segmented column kernels and none of the fused forms
+ * (ell_grid_features reports none).  It holds three FP64 fields per level
+ * (faces, 1/p_k, T_{k+1/2}/p_k) more than ell_grid_bytes reports, and with
+ * ELL_FP32_PRECOND their FP32 copies too, which every V-cycle sweep reads
+ * (the FP64 finest post-smoothing included); the operator step and the
+ * solve's ends read the FP64 faces.  The batch engine does not take such
+ * grids.  Synchronous; ELL_ERR_INVALID for a bad descriptor or field. */
 int ell_grid_create_varying(const ell_grid_desc *desc, const double *lambda2_3d, ell_grid **out);
 
 /* Device bytes ell_grid_create would allocate for desc (0 if invalid). */

@@ -144,6 +144,7 @@ struct Level {
   // each column's faces T_{k-1/2} (zero at k = 0) and the factors 1/p_k and
   // T_{k+1/2}/p_k of its column elimination
   double *tz3 = nullptr, *ip3 = nullptr, *cf3 = nullptr;
+  float *tz3f = nullptr, *ip3f = nullptr, *cf3f = nullptr;  // FP32 copies (mixed-precision grids)
 };
 
 }  // namespace
@@ -467,11 +468,20 @@ int build_varying(ell_grid *g, const double *lam3) {
     void *tmp;
     const std::vector<double> *src[3] = {&tz_s, &ip_s, &cf_s};
     double **dst[3] = {&Lv.tz3, &Lv.ip3, &Lv.cf3};
+    float **dstf[3] = {&Lv.tz3f, &Lv.ip3f, &Lv.cf3f};
+    std::vector<float> f32;
     for (int a = 0; a < 3; ++a) {
       CHK(dalloc(g, &tmp, ne * 8));
       *dst[a] = (double *)tmp;
       if (hipMemcpy(tmp, src[a]->data(), ne * 8, hipMemcpyHostToDevice) != hipSuccess)
         return fail(ELL_ERR_HIP, "coefficient upload failed");
+      if (g->prec != ELL_FP64) {  // the FP64 values rounded once, as level_table32 rounds the tables
+        f32.assign(src[a]->begin(), src[a]->end());
+        CHK(dalloc(g, &tmp, ne * 4));
+        *dstf[a] = (float *)tmp;
+        if (hipMemcpy(tmp, f32.data(), ne * 4, hipMemcpyHostToDevice) != hipSuccess)
+          return fail(ELL_ERR_HIP, "coefficient upload failed");
+      }
     }
   }
   return ELL_OK;
@@ -598,33 +608,68 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
   R *own = u + (long long)c * G.cs;
   const bool hxy = G.has_x && G.has_y;
   ProfScope ps(g, ELL_K_SMOOTH0, s, l == 0);
-  if constexpr (std::is_same<R, double>::value && std::is_same<TB, double>::value) {
-    if (g->varying && rho1 && hxy && G.nz <= 256) {
-      // every column its own factors, k-segmented: sixteen segments on small
-      // (latency-bound) levels, eight on large ones
+  if (g->varying) {
+    // every column its own factors, in the arithmetic type: the FP32 sweeps
+    // of the mixed-precision V-cycles read the FP32 copies, the FP64 finest
+    // post-smoothing the FP64 fields.  Rounding T_{k+1/2}/p_k to FP32 loses the
+    // excess of a strongly coupled column (T/p = 1 - O(1e-7) or closer), so
+    // FP32 factors there would undo what that sweep is for.
+    if (rho1 && hxy && G.nz <= 256) {
+      // k-segmented: sixteen segments on small (latency-bound) levels, eight
+      // on large ones
       const int nbs = blocks8(((long long)ncol + kSegCols - 1) / kSegCols * kBlock);
       const bool small = G.H < 16384 && seg_len(G.nz, 16) <= 16;
       const int Ls = seg_len(G.nz, small ? 16 : 8);
-      auto go = [&](auto z, auto fn) {
+      auto go = [&](auto z, auto fn, const auto *t3, const auto *i3, const auto *c3) {
         constexpr bool Z = decltype(z)::value, FN = decltype(fn)::value;
-        const double *t3 = Lv.tz3, *i3 = Lv.ip3, *c3 = Lv.cf3;
+        using F = std::remove_cv_t<std::remove_pointer_t<decltype(t3)>>;
         if (small) {
-          if (Ls <= 8) k_smooth_seg3<Z, FN, 8, 16, 4><<<nbs, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
-          else k_smooth_seg3<Z, FN, 16, 16, 4><<<nbs, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
+          if (Ls <= 8)
+            k_smooth_seg3<R, TB, F, Z, FN, 8, 16, 4><<<nbs, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
+          else
+            k_smooth_seg3<R, TB, F, Z, FN, 16, 16, 4><<<nbs, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
         } else {
-          if (Ls <= 8) k_smooth_seg3<Z, FN, 8, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
-          else if (Ls <= 16) k_smooth_seg3<Z, FN, 16, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
-          else k_smooth_seg3<Z, FN, 32, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
+          if (Ls <= 8)
+            k_smooth_seg3<R, TB, F, Z, FN, 8, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
+          else if (Ls <= 16)
+            k_smooth_seg3<R, TB, F, Z, FN, 16, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
+          else
+            k_smooth_seg3<R, TB, F, Z, FN, 32, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
         }
       };
-      if (zero) { if (l == 0) go(std::true_type{}, std::true_type{}); else go(std::true_type{}, std::false_type{}); }
-      else { if (l == 0) go(std::false_type{}, std::true_type{}); else go(std::false_type{}, std::false_type{}); }
+      auto go_f = [&](auto z, auto fn) {
+        if constexpr (std::is_same<R, double>::value)
+          go(z, fn, Lv.tz3, Lv.ip3, Lv.cf3);
+        else
+          go(z, fn, (const float *)Lv.tz3f, (const float *)Lv.ip3f, (const float *)Lv.cf3f);
+      };
+      using T_ = std::true_type;
+      using F_ = std::false_type;
+      if constexpr (std::is_same<R, TB>::value) {
+        if (zero) { if (l == 0) go_f(T_{}, T_{}); else go_f(T_{}, F_{}); }
+        else { if (l == 0) go_f(F_{}, T_{}); else go_f(F_{}, F_{}); }
+      } else {  // mixed element types only on the finest level
+        if (l != 0) return fail(ELL_ERR_INVALID, "mixed element types only on the finest level");
+        if (zero) go_f(T_{}, T_{});
+        else go_f(F_{}, T_{});
+      }
       return check_launch("k_smooth_seg3");
     }
-    if (g->varying) {  // every column its own factors: the column kernel
+    if constexpr (std::is_same<R, TB>::value) {
+      // the column kernel, with fields in the arithmetic type
+      const R *t3, *i3, *c3;
+      if constexpr (std::is_same<R, double>::value) {
+        t3 = Lv.tz3;
+        i3 = Lv.ip3;
+        c3 = Lv.cf3;
+      } else {
+        t3 = Lv.tz3f;
+        i3 = Lv.ip3f;
+        c3 = Lv.cf3f;
+      }
       auto go = [&](auto z, auto r1, auto fn, auto h) {
-        k_smooth<double, decltype(z)::value, decltype(r1)::value, decltype(fn)::value, decltype(h)::value, true>
-            <<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, yb, rho, done, Lv.tz3, Lv.ip3, Lv.cf3);
+        k_smooth<R, decltype(z)::value, decltype(r1)::value, decltype(fn)::value, decltype(h)::value, true>
+            <<<nb, kBlock, 0, s>>>(G, tab, c, bo, uo, own, yb, rho, done, t3, i3, c3);
       };
       using T_ = std::true_type;
       using F_ = std::false_type;
@@ -637,7 +682,11 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
       if (l == 0) { if (hxy) go2(T_{}, T_{}); else go2(T_{}, F_{}); }
       else { if (hxy) go2(F_{}, T_{}); else go2(F_{}, F_{}); }
       return check_launch("k_smooth");
+    } else {
+      return fail(ELL_ERR_INVALID, "no line-relaxation kernel for this level shape");
     }
+  }
+  if constexpr (std::is_same<R, double>::value && std::is_same<TB, double>::value) {
     // after the first sweep, rho = 1: the LDS-tiled half-sweep (streaming
     // accesses on the finest level)
     const int Ls = seg_len(G.nz, G.nseg);
@@ -815,13 +864,13 @@ int launch_restrict(ell_grid *g, int l, const TB *b, const R *u, R *bc, bool bz,
   const int nb = blocks8(2LL * C.H);
   const R *tab = (const R *)g->lev[l].tab;
   ProfScope ps(g, ELL_K_RESTRICT0, s, l == 0);
-  if constexpr (std::is_same<R, double>::value && std::is_same<TB, double>::value) {
-    if (g->varying) {
-      const double *tz3 = g->lev[l].tz3;
-      if (bz) k_resid_restrict<double, true, true><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done, tz3);
-      else k_resid_restrict<double, false, true><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done, tz3);
-      return check_launch("k_resid_restrict");
-    }
+  if (g->varying) {  // per-column faces, in the arithmetic type
+    const R *tz3;
+    if constexpr (std::is_same<R, double>::value) tz3 = g->lev[l].tz3;
+    else tz3 = g->lev[l].tz3f;
+    if (bz) k_resid_restrict<R, true, true, TB><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done, tz3);
+    else k_resid_restrict<R, false, true, TB><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done, tz3);
+    return check_launch("k_resid_restrict");
   }
   if (bz && F.has_x && F.has_y) {
     const int nbz = seg_blocks(2LL * C.H);
@@ -1579,8 +1628,8 @@ int ell_grid_create_varying(const ell_grid_desc *desc, const double *lambda2_3d,
   *out = nullptr;
   if (!desc) return fail(ELL_ERR_INVALID, "descriptor is NULL");
   if (!lambda2_3d) return fail(ELL_ERR_INVALID, "lambda2_3d is NULL");
-  if (desc->precision != ELL_FP64)
-    return fail(ELL_ERR_INVALID, "horizontally varying coefficients need precision ELL_FP64");
+  if (desc->precision != ELL_FP64 && desc->precision != ELL_FP32_PRECOND)
+    return fail(ELL_ERR_INVALID, "horizontally varying coefficients take ELL_FP64 or ELL_FP32_PRECOND");
   if (desc->nx < 1 || desc->ny < 1 || desc->nz < 1) return fail(ELL_ERR_INVALID, "sizes must be >= 1");
   const size_t n = (size_t)desc->nx * desc->ny * desc->nz;
   for (size_t e = 0; e < n; ++e)
@@ -1705,6 +1754,11 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   }
   if (g->prec != ELL_FP64) {
     level_table64(g, 0, t64);
+    if (g->varying) {
+      const int P = desc->nz + 1;
+      for (int sl = TZ; sl < TSLOTS; ++sl)
+        for (int k = 0; k < P; ++k) t64[(size_t)sl * P + k] = std::nan("");
+    }
     if ((rc = dalloc(g, &tmp, t64.size() * 8)) != ELL_OK) return bail(rc);
     if (hipMemcpy(tmp, t64.data(), t64.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
       return bail(fail(ELL_ERR_HIP, "table upload failed"));
@@ -1912,10 +1966,14 @@ int ell_level_apply(ell_grid *g, int level, const void *x, void *y, hipStream_t 
   if (!x || !y || x == y) return fail(ELL_ERR_INVALID, "bad vector arguments");
   const Geo &G = g->lev[level].geo;
   const int nb = seg_blocks(2LL * G.H);
-  if (g->varying)
+  if (g->varying && g->prec == ELL_FP64)
     k_apply<double, false, false, 4, true><<<nb, kBlock, 0, s>>>(G, (const double *)g->lev[level].tab,
                                                                  (const double *)x, (double *)y, nullptr, nullptr,
                                                                  g->lev[level].tz3);
+  else if (g->varying)
+    k_apply<float, false, false, 4, true><<<nb, kBlock, 0, s>>>(G, (const float *)g->lev[level].tab,
+                                                                (const float *)x, (float *)y, nullptr, nullptr,
+                                                                g->lev[level].tz3f);
   else if (g->prec == ELL_FP64)
     k_apply<double, false, false, 4><<<nb, kBlock, 0, s>>>(G, (const double *)g->lev[level].tab,
                                                            (const double *)x, (double *)y, nullptr, nullptr);

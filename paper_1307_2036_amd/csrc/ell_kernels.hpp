@@ -569,16 +569,20 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
 // segments, whose 1024-lane blocks leave 128 registers per lane).  bo, uo,
 // own: b of colour c, u of the other colour, u of colour c.
 // -------------------------------------------------------------------------
-template <bool ZERO, bool FINE, int SEG, int NSEG, int CH>
-__global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const double *__restrict__ tab, int c,
-                                                           const double *__restrict__ bo,
-                                                           const double *__restrict__ uo,
-                                                           double *__restrict__ own,
+// R: arithmetic and element type of u and tab; TB: element type of b (the
+// FP32 preconditioner's finest level reads the FP64 CG residual); F: element
+// type of the per-column fields (FP32 copies for the mixed-precision V-cycles,
+// also under its FP64 finest post-smoothing).
+template <typename R, typename TB, typename F, bool ZERO, bool FINE, int SEG, int NSEG, int CH>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const R *__restrict__ tab, int c,
+                                                           const TB *__restrict__ bo,
+                                                           const R *__restrict__ uo,
+                                                           R *__restrict__ own,
                                                            const int *__restrict__ done,
-                                                           const double *__restrict__ tz3,
-                                                           const double *__restrict__ ip3,
-                                                           const double *__restrict__ cf3) {
-  __shared__ double xv[NSEG][kSegCols], xq[NSEG][kSegCols];
+                                                           const F *__restrict__ tz3,
+                                                           const F *__restrict__ ip3,
+                                                           const F *__restrict__ cf3) {
+  __shared__ R xv[NSEG][kSegCols], xq[NSEG][kSegCols];
   if (is_done(done)) return;
   const int lane = threadIdx.x & 63;
   const int sg = wave_id();
@@ -593,37 +597,37 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const double *
   const Nbr nb = ZERO ? Nbr{0, 0, 0, 0} : neighbours(L, i, j);
   const long long H = L.S;
   const long long oc = (long long)c * L.cs + mm;
-  const double *__restrict__ bb = bo + mm;
-  const double *__restrict__ uw = uo + nb.w;
-  const double *__restrict__ ue = uo + nb.e;
-  const double *__restrict__ us = uo + nb.s;
-  const double *__restrict__ un = uo + nb.n;
-  double *__restrict__ ow = own + mm;
-  const double *__restrict__ zc = tz3 + oc;
-  const double *__restrict__ pc = ip3 + oc;
-  const double *__restrict__ fc = cf3 + oc;
-  const double *__restrict__ tx = tab + TX * L.P;
-  const double *__restrict__ ty = tab + TY * L.P;
+  const TB *__restrict__ bb = bo + mm;
+  const R *__restrict__ uw = uo + nb.w;
+  const R *__restrict__ ue = uo + nb.e;
+  const R *__restrict__ us = uo + nb.s;
+  const R *__restrict__ un = uo + nb.n;
+  R *__restrict__ ow = own + mm;
+  const F *__restrict__ zc = tz3 + oc;
+  const F *__restrict__ pc = ip3 + oc;
+  const F *__restrict__ fc = cf3 + oc;
+  const R *__restrict__ tx = tab + TX * L.P;
+  const R *__restrict__ ty = tab + TY * L.P;
 
   static_assert(SEG % CH == 0, "chunks must tile the segment");
-  double y[SEG], pr[SEG];
-  double prev = 0.0, prod = 1.0;
+  R y[SEG], pr[SEG];
+  R prev = R(0), prod = R(1);
 #pragma unroll
   for (int c0 = 0; c0 < SEG; c0 += CH) {
     if (c0 < len) {
-      double g[CH], a[CH], d[CH];
+      R g[CH], a[CH], d[CH];
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
         const int k = min(k0 + c0 + t, k1 - 1);
         const long long o = (long long)k * H;
-        double v = ld_s<FINE>(&bb[o]);
+        R v = (R)ld_s<FINE>(&bb[o]);
         if (!ZERO) {
           v = v + tx[k] * (uw[o] + ue[o]);
           v = v + ty[k] * (us[o] + un[o]);
         }
         g[t] = v;
-        a[t] = zc[o];
-        d[t] = pc[o];
+        a[t] = (R)zc[o];
+        d[t] = (R)pc[o];
       }
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
@@ -640,25 +644,25 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const double *
   xv[sg][lane] = prev;
   xq[sg][lane] = prod;
   __syncthreads();
-  double yin = 0.0;
+  R yin = R(0);
 #pragma unroll
   for (int q = 0; q < NSEG - 1; ++q) {
-    const double cand = xv[q][lane] + xq[q][lane] * yin;
+    const R cand = xv[q][lane] + xq[q][lane] * yin;
     yin = q < sg ? cand : yin;
   }
   __syncthreads();
   // true y, then the local backward recurrence and its product (in place)
-  double nxt = 0.0, qprod = 1.0;
+  R nxt = R(0), qprod = R(1);
 #pragma unroll
   for (int c0 = SEG - CH; c0 >= 0; c0 -= CH) {
     if (c0 < len) {
-      double e[CH];
+      R e[CH];
 #pragma unroll
-      for (int t = 0; t < CH; ++t) e[t] = fc[(long long)min(k0 + c0 + t, k1 - 1) * H];
+      for (int t = 0; t < CH; ++t) e[t] = (R)fc[(long long)min(k0 + c0 + t, k1 - 1) * H];
 #pragma unroll
       for (int t = CH - 1; t >= 0; --t) {
         if (c0 + t < len) {
-          const double yt = y[c0 + t] + pr[c0 + t] * yin;
+          const R yt = y[c0 + t] + pr[c0 + t] * yin;
           nxt = yt + e[t] * nxt;
           qprod = qprod * e[t];
           y[c0 + t] = nxt;
@@ -670,10 +674,10 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const double *
   xv[sg][lane] = nxt;
   xq[sg][lane] = qprod;
   __syncthreads();
-  double win = 0.0;
+  R win = R(0);
 #pragma unroll
   for (int q = NSEG - 1; q > 0; --q) {
-    const double cand = xv[q][lane] + xq[q][lane] * win;
+    const R cand = xv[q][lane] + xq[q][lane] * win;
     win = q > sg ? cand : win;
   }
   if (valid) {
@@ -1131,9 +1135,11 @@ __global__ __launch_bounds__(NSEG * 64) void k_resid_restrict_bz(Geo F, Geo C,
 // -------------------------------------------------------------------------
 // C3: the vertical faces of each child column from the split-layout field
 // tz3 (T_{k-1/2}) instead of the table.
-template <typename R, bool BZ, bool C3 = false>
+// TB: element type of b (the mixed-precision V-cycle's finest level reads the
+// FP64 CG residual).
+template <typename R, bool BZ, bool C3 = false, typename TB = R>
 __global__ __launch_bounds__(kBlock) void k_resid_restrict(Geo F, Geo C, const R *__restrict__ tab,
-                                                           const R *__restrict__ b,
+                                                           const TB *__restrict__ b,
                                                            const R *__restrict__ u,
                                                            R *__restrict__ bc,
                                                            const int *__restrict__ done,
@@ -1189,7 +1195,7 @@ __global__ __launch_bounds__(kBlock) void k_resid_restrict(Geo F, Geo C, const R
       const R uE = F.has_x ? uo[nE[t]] : R(0);
       const R uS = F.has_y ? uo[nS[t]] : R(0);
       const R uN = F.has_y ? uo[nN[t]] : R(0);
-      const R bk = b[(long long)ca[t] * F.cs + o + cm[t]];
+      const R bk = (R)b[(long long)ca[t] * F.cs + o + cm[t]];
       R tzlo, tzhi;
       if constexpr (C3) {
         const R *__restrict__ zc = tz3 + (long long)ca[t] * F.cs + cm[t];

@@ -140,3 +140,32 @@ def pcg_iteration_bytes_varying(n0: int, levels: int, nu_coarse=1, flexible=True
         total += sweeps * 12 * n
         n //= 4
     return total
+
+
+def smooth0_launch_bytes_varying_hybrid(n0: int) -> float:
+    """Average algorithmic bytes of a finest-level half-sweep launch of the
+    mixed-precision V-cycle on a varying grid, per unknown of the level: the
+    FP32 pre-sweeps read the FP64 residual (4 B), write FP32 u (2 B), the second
+    reads the other colour (2 B), and each reads its colour's FP32 faces, 1/p
+    and T/p (6 B); the FP64 post-sweeps read r (4 B) and the other colour of z
+    (4 B), write z (4 B) and read the FP64 fields (12 B):
+    (12 + 14 + 24 + 24) / 4 = 18.5 B."""
+    return (12 + 14 + 24 + 24) * n0 / 4
+
+
+def pcg_iteration_bytes_varying_hybrid(n0: int, levels: int, nu_coarse=1, nu_pre=1, nu_post=1) -> float:
+    """One flexible PCG iteration on a varying grid with the mixed-precision
+    V-cycle (separate residual update and dots): the FP64 CG work with the
+    operator step's faces, the hybrid V-cycle, and the fields of every
+    half-sweep (6 B per unknown of the level in FP32, 12 B for the FP64 finest
+    post-sweeps) and restriction (2 B)."""
+    total = cg_bytes(n0, True) + 8 * n0 + hybrid_vcycle_bytes(n0, levels, nu_coarse)
+    n = n0
+    for l in range(levels):
+        if l == levels - 1:
+            sweeps = 2 * (nu_coarse if nu_coarse > 0 else nu_pre + nu_post)
+            total += sweeps * 6 * n
+        else:
+            total += 2 * n + 2 * nu_pre * 6 * n + 2 * nu_post * (12 if l == 0 else 6) * n
+        n //= 4
+    return total

@@ -147,7 +147,7 @@ def test_varying_grid_rejects_bad_input(ell, orc):
     p = I.paper_graded_problem("bad3d", 16, 16, 8, 1e-2, 5, 6)
     lam3 = I.lambda2_3d(16, 16, p.lambda2, 0.5, 7)
     with pytest.raises(ell.EllError) as e:
-        ell.Grid.from_problem(p, precision="fp32", lambda2_3d=lam3)
+        ell.Grid.from_problem(p, precision="bf16coef", lambda2_3d=lam3)
     assert e.value.code == ell.ELL_ERR_INVALID
     bad = lam3.copy()
     bad[3, 2, 1] = 0.0
@@ -170,3 +170,61 @@ def test_varying_fullsize_solve(ell, orc):
     err = rel(host(u), u_k)
     print("varying 512^2x128: iters", st.iters, "rel_l2", err)
     assert err <= 1e-10
+
+
+VARYING_MIXED = [((64, 64, 32), 0), ((96, 32, 64), 3), ((32, 32, 130), 0), ((64, 32, 200), 2)]
+
+
+def varying_problem_small(nx, ny, nz, levels):
+    p = I.paper_graded_problem(f"varm{nx}", nx, ny, nz, 1e-2, 31 + nz, 32 + nz)
+    p.n_levels = levels
+    p.lambda2_3d = I.lambda2_3d(nx, ny, p.lambda2, 0.8, 33 + nz)
+    return p
+
+
+@pytest.mark.parametrize("shape,levels", VARYING_MIXED)
+def test_varying_mixed_vcycle_and_tight_solve(ell, orc, shape, levels):
+    """FP32 V-cycle with FP32 per-column fields (the FP64 finest post-smoothing
+    also reads them): one V-cycle agrees with the oracle's FP64 one to FP32
+    accuracy; solved to rtol 1e-12 the mixed solve reaches the oracle's tight
+    solution to 1e-8; at 1e-5 it needs at most two iterations more than FP64."""
+    nx, ny, nz = shape
+    p = varying_problem_small(nx, ny, nz, levels)
+    g = orc.Grid.from_problem(p)
+    G = ell.Grid.from_problem(p, precision="fp32")
+    assert G.varying
+    r = p.f * (p.hx * p.hy * p.dz)[:, None, None]
+    assert rel(host(G.vcycle(dev(r))), orc.vcycle(g, r)) <= 1e-5
+    u_ref, _ = orc.pcg(g, p.f, rtol=1e-12, maxiter=400)
+    u, st = G.pcg_solve(dev(p.f), rtol=1e-12, maxiter=400)
+    assert st.status == 0, st
+    err = rel(host(u), u_ref)
+    print(shape, "tight iters", st.iters, "rel", err)
+    assert err <= 1e-8
+    G64 = ell.Grid.from_problem(p)
+    _, s64 = G64.pcg_solve(dev(p.f), rtol=p.rtol)
+    _, s32 = G.pcg_solve(dev(p.f), rtol=p.rtol)
+    assert s32.status == 0 and s32.iters <= s64.iters + 2, (s32.iters, s64.iters)
+
+
+def test_varying_mixed_levels_match_oracle(ell, orc):
+    """FP32 levels of a varying grid: both colours of line relaxation and the
+    restriction on every level against the oracle, to FP32 accuracy scaled by
+    each column's largest value."""
+    p = varying_problem_small(64, 32, 48, 3)
+    g = orc.Grid.from_problem(p)
+    G = ell.Grid.from_problem(p, precision="fp32")
+    rng = np.random.default_rng(3)
+    gl = g
+    for lv in range(G.levels):
+        b = rng.standard_normal(gl.shape) * (gl.hx * gl.hy * gl.dz)[:, None, None]
+        bs = G.to_split(lv, dev(b))
+        us = G.level_empty(lv)
+        G.level_smooth(lv, 0, bs, us, zero_init=True)
+        G.level_smooth(lv, 1, bs, us)
+        ref = orc.smooth_colour(gl, 1, b, orc.smooth_colour(gl, 0, b, np.zeros(gl.shape)))
+        got = host(G.from_split(lv, us, zeros(gl.shape)))
+        scale = np.abs(ref).max(axis=0, keepdims=True)
+        assert np.all(np.abs(got - ref) <= 1e-4 * scale), (lv, (np.abs(got - ref) / scale).max())
+        if lv + 1 < G.levels:
+            gl = gl.coarse()
