@@ -258,6 +258,11 @@ int ell_level_apply(ell_grid *g, int level, const void *x, void *y, hipStream_t 
 enum { ELL_K_SMOOTH0 = 0, ELL_K_APPLY = 1, ELL_K_RESTRICT0 = 2, ELL_K_PROLONG0 = 3,
        ELL_K_UPDATE = 4, ELL_K_COUNT = 5 };
 int ell_profile_enable(ell_grid *g, int family, int max_events);
+/* Pause (paused != 0) or resume the recording of a family enabled above; the
+ * events already recorded are kept.  Each recorded launch costs two event
+ * records on the stream (a few microseconds of idle GPU each), so a caller
+ * that times a long run can record a sample of its launches. */
+int ell_profile_pause(ell_grid *g, int family, int paused);
 /* Synchronises the recorded events; *count launches, *total_ms summed time. */
 int ell_profile_read(ell_grid *g, int family, int *count, double *total_ms);
 /* Per-launch times in milliseconds of the recorded launches, in launch order:

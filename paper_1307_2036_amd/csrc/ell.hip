@@ -131,6 +131,7 @@ float round_bf16(float x) {
 struct Prof {
   int cap = 0;
   int n = 0;
+  bool paused = false;  // launches made while paused record nothing
   std::vector<hipEvent_t> ev;
 };
 
@@ -495,7 +496,7 @@ struct ProfScope {
   hipStream_t s;
   bool on;
   ProfScope(ell_grid *g, int fam, hipStream_t st, bool enabled = true) : p(&g->prof[fam]), s(st) {
-    on = enabled && p->cap > 0 && p->n < p->cap;
+    on = enabled && !p->paused && p->cap > 0 && p->n < p->cap;
     if (on) (void)hipEventRecord(p->ev[2 * p->n], s);
   }
   ~ProfScope() {
@@ -1992,6 +1993,13 @@ int ell_profile_enable(ell_grid *g, int family, int max_events) {
   for (auto &e : p.ev) HIPCHK(hipEventCreate(&e));
   p.cap = max_events;
   p.n = 0;
+  p.paused = false;
+  return ELL_OK;
+}
+
+int ell_profile_pause(ell_grid *g, int family, int paused) {
+  if (!g || family < 0 || family >= ELL_K_COUNT) return fail(ELL_ERR_INVALID, "bad profiling arguments");
+  g->prof[family].paused = paused != 0;
   return ELL_OK;
 }
 

@@ -62,7 +62,7 @@ class SolveStats(ctypes.Structure):
 EXPORTS = ["ell_grid_create", "ell_grid_destroy", "ell_grid_bytes", "ell_grid_levels", "ell_grid_features",
            "ell_apply_A", "ell_vcycle", "ell_pcg_solve", "ell_level_elems", "ell_to_split",
            "ell_from_split", "ell_level_smooth", "ell_level_resid_restrict",
-           "ell_level_prolong_add", "ell_level_apply", "ell_profile_enable", "ell_profile_read",
+           "ell_level_prolong_add", "ell_level_apply", "ell_profile_enable", "ell_profile_pause", "ell_profile_read",
            "ell_profile_times", "ell_level_layout", "ell_set_tuning", "ell_last_error",
            "ell_batch_create", "ell_batch_grid", "ell_batch_release", "ell_batch_bytes_in_use",
            "ell_batch_submit", "ell_batch_poll", "ell_batch_wait", "ell_batch_destroy",
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH):
     L.ell_level_prolong_add.argtypes = [vp, i32, vp, vp, i32, vp]
     L.ell_level_apply.argtypes = [vp, i32, vp, vp, vp]
     L.ell_profile_enable.argtypes = [vp, i32, i32]
+    L.ell_profile_pause.argtypes = [vp, i32, i32]
     L.ell_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
     L.ell_profile_times.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_float), i32]
     L.ell_level_layout.argtypes = [vp, i32] + [ctypes.POINTER(ctypes.c_int64)] * 3
@@ -401,6 +402,9 @@ class Grid:
     # ---- measurement -------------------------------------------------------------------
     def profile_enable(self, family: int, max_events: int):
         _check(load_library().ell_profile_enable(self._h, family, max_events))
+
+    def profile_pause(self, family: int, paused: bool = True):
+        _check(load_library().ell_profile_pause(self._h, family, int(bool(paused))))
 
     def profile_read(self, family: int):
         n = ctypes.c_int()
