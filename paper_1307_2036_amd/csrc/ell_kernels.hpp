@@ -702,6 +702,7 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const R *__res
 // even indices, so pair writes are aligned).
 // -------------------------------------------------------------------------
 constexpr int kSTX = 32;  // m-columns per tile
+constexpr int kCRow = 48;  // LDS row stride of the staged coarse values (40 used)
 
 // DOT = 1 (the last two half-sweeps of a preconditioner application): also
 // the block's partial sum of <b, w> over its written columns, into
@@ -719,7 +720,8 @@ constexpr int kSTX = 32;  // m-columns per tile
 // the column prolongation, so the correction is never written: the colour-0
 // sweep that follows overwrites colour 0 without reading it.  The 3 x 36
 // coarse values a wavefront's tile needs per level (rows J0-1 .. J0+1,
-// columns mx0-2 .. mx0+33) are staged in LDS with two loads.
+// columns mx0-2 .. mx0+33) are staged in LDS with two loads, even and odd
+// columns apart.
 // DOT = 3 (colour 0, the last sweep, classic beta, after a PRO sweep): <b, w>
 // of the written columns plus <r1, z1> over the colour-1 cells of the tile's
 // rows, z1 from the staged values and r1 loaded (r1c: colour 1 of r), into
@@ -750,7 +752,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   __shared__ __align__(16) double ot[NSEG][4][36];
   __shared__ double bsh[DOT ? NSEG : 1][DOT ? SEG : 1][64];
   __shared__ double red[NQ ? NSEG : 1][2];
-  __shared__ double csl[PRO ? NSEG : 1][PRO ? 128 : 1];
+  __shared__ double csl[PRO ? NSEG : 1][PRO ? 3 * kCRow : 1];
   const int tiles_x = (L.hx2 + kSTX - 1) / kSTX;
   if (is_done(done) || lb >= tiles_x * (L.ny / 2)) return;  // whole blocks: no barrier is skipped
   const int lane = threadIdx.x & 63;
@@ -789,9 +791,15 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   const double *qg = UPD ? gp(qc) : nullptr;
   double alpha = 0.0, rsq = 0.0;
   if constexpr (UPD) alpha = st->alpha;
-  // PRO: this lane's two coarse staging values (slot v = row * 36 + q for v <
-  // 108 and q <= nxm + 3, else an in-bounds dummy) and its corrections' rows
+  // PRO: this lane's two coarse staging values and their LDS slots, and its
+  // corrections' rows.  Staging value v < 120 is coarse row J0 - 1 + v / 40,
+  // column I = mx0 - 4 + 2 t + par (rem = v % 40 = 20 par + t), at slot
+  // row * kCRow + rem: the even columns of a row, then the odd ones, so the
+  // neighbours a lane reads lie 8 bytes apart across lanes (interleaved they
+  // were 16 bytes apart, a two-way LDS bank conflict on every read); values
+  // no staged fine cell reads, and v >= 120, load an in-bounds dummy.
   long long co0 = 0, co1 = 0, HC = 0;
+  int cs0 = 0, cs1 = 0;
   const double *ucg = nullptr;
   double *csf = nullptr;
   int pa = 0, pb = 0, pd = 0, ea = 0, eb = 0, ed = 0;
@@ -799,14 +807,18 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
     const Geo C = *Cg;
     const int J0 = j0 >> 1;
     auto coff = [&](int v) -> long long {
-      const int row = v / 36, q = v - row * 36;
-      const bool need = v < 108 && q <= nxm + 3;
+      const int row = v / 40, rem = v - row * 40, par = rem / 20, t = rem - par * 20;
+      const int q = 2 * t + par - 2;  // I - (mx0 - 2)
+      const bool need = v < 120 && q >= 0 && q <= nxm + 3;
       const int I = wrapi(mx0 - 2 + (need ? q : 0), C.nx);
       const int J = wrapi(J0 - 1 + (need ? row : 0), C.ny);
       return (long long)((I + J) & 1) * C.cs + col_m(C, I, J);
     };
+    auto cslot = [](int v) -> int { return v < 120 ? (v / 40) * kCRow + v % 40 : 2 * kCRow + 40 + (v - 120); };
     co0 = coff(lane);
     co1 = coff(64 + lane);
+    cs0 = cslot(lane);
+    cs1 = cslot(64 + lane);
     HC = C.S;
     ucg = gp(uc);
     csf = csl[sg];
@@ -820,12 +832,15 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
     ed = (er & 1) ? -1 : 1;
   }
   // the bilinear correction of the staged colour-0 value at index idx of a
-  // staged row (coarse rows a, b, direction d), in the column kernel's order
+  // staged row (coarse rows a, b, direction d; coarse column I = mx0 - 2 + q
+  // sits at slot row * kCRow + 20 ((q + 2) & 1) + ((q + 2) >> 1)), in the
+  // column kernel's order
+  auto cv = [&](int row, int q) -> double { return csf[row * kCRow + 20 * ((q + 2) & 1) + ((q + 2) >> 1)]; };
   auto corr = [&](int a, int b, int d, int idx) -> double {
-    double e = 9.0 / 16.0 * csf[a * 36 + idx];
-    e = e + 3.0 / 16.0 * csf[a * 36 + idx + d];
-    e = e + 3.0 / 16.0 * csf[b * 36 + idx];
-    e = e + 1.0 / 16.0 * csf[b * 36 + idx + d];
+    double e = 9.0 / 16.0 * cv(a, idx);
+    e = e + 3.0 / 16.0 * cv(a, idx + d);
+    e = e + 3.0 / 16.0 * cv(b, idx);
+    e = e + 1.0 / 16.0 * cv(b, idx + d);
     return e;
   };
   const double *r1g = DOT == 3 ? gp(r1c) : nullptr;
@@ -865,8 +880,8 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
         nt_d2 pr = tv[t];
         double evk = ev[t];
         if constexpr (PRO) {
-          csf[lane] = cv0[t];
-          csf[64 + lane] = cv1[t];
+          csf[cs0] = cv0[t];
+          csf[cs1] = cv1[t];
           __asm__ volatile("" ::: "memory");
           pr.x = pr.x + corr(pa, pb, pd, 2 + 2 * pp);
           pr.y = pr.y + corr(pa, pb, pd, 3 + 2 * pp);
