@@ -321,7 +321,7 @@ def bench_c1(a):
     solves = a.steps / elapsed
     it_bytes = perfmodel.pcg_iteration_bytes(n, G.levels, e, nu_coarse=p.nu_coarse, flexible=flexible,
                                              fused_update=feat["fused_update"], fused_dots=feat["fused_dots"],
-                                             fused_prolong=fpro)
+                                             fused_prolong=fpro, coarse_prolong=feat["coarse_prolong"])
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC,

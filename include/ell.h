@@ -153,7 +153,10 @@ int ell_grid_levels(const ell_grid *g);
  * ELL_FEAT_TILED_ENDS (a solve's start, r = V f - A u0, and end, the final
  * update and true residual, run on LDS tiles), ELL_FEAT_COARSE_TAIL (the
  * coarsest level's sweeps run in one cooperative launch; cleared if the
- * runtime refused that launch, the sweeps then run one by one).  They change
+ * runtime refused that launch, the sweeps then run one by one),
+ * ELL_FEAT_COARSE_PROLONG (on at least one coarse level the bilinear
+ * prolongation rides on the first post-smoothing sweep, as the finest one
+ * does: FP64, rho = 1, LDS-tiled sweeps; any beta).  They change
  * where bytes move and how many launches there are, not what is computed;
  * a benchmark's byte model reads them.  Returns ELL_OK or a negative error. */
 enum {
@@ -162,7 +165,8 @@ enum {
   ELL_FEAT_FUSED_UPDATE = 4,
   ELL_FEAT_FUSED_PROLONG = 8,
   ELL_FEAT_TILED_ENDS = 16,
-  ELL_FEAT_COARSE_TAIL = 32
+  ELL_FEAT_COARSE_TAIL = 32,
+  ELL_FEAT_COARSE_PROLONG = 64
 };
 int ell_grid_features(const ell_grid *g, int32_t *mask);
 
@@ -296,7 +300,9 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * dots taking <r, z> alone, i.e. the printed beta) apply the coarse correction
  * to the colour-0 values it reads instead of a prolongation pass (the
  * colour-0 sweep that follows overwrites them), the colour-0 sweep then forming
- * <r, z> of both colours; 0 always runs the prolongation pass; TILED_ENDS 1
+ * <r, z> of both colours, and does the same on every coarse FP64 level with
+ * LDS-tiled sweeps and rho = 1 (any beta; same values, bitwise); 0 always
+ * runs the prolongation pass; TILED_ENDS 1
  * (default) runs the start of a solve (us = u0, r = V f - A u0) and its end (u
  * = us + alpha p written plane-major, the true residual) on the LDS tiles of
  * the operator step for grids created afterwards with nx, ny > 1, 0 on the

@@ -828,6 +828,32 @@ void pro_pair_k(ell_grid *g, const double *b, double *u, const int *done, hipStr
   k_smooth_tile_dot3<SEG, NSEG><<<nbt, NSEG * 64, 0, s>>>(F, tab, b, u + cs, u, done, g->partial, b + cs);
 }
 
+// A coarse level's prolongation rides on its first post-smoothing sweep the
+// same way: FP64 level with a coarser one below it and the LDS-tiled sweep,
+// rho = 1 (the colour-0 sweep that follows overwrites colour 0 without
+// reading it, the colour-1 sweep overwrites colour 1), bilinear prolongation.
+bool coarse_pro_ok(const ell_grid *g, int l) {
+  return l >= 1 && l <= g->L - 2 && g->prec == ELL_FP64 && g->fused_prolong && g->d.nu_post >= 1 &&
+         g->d.prolong == 0 && tile_ok(g, l);
+}
+
+int coarse_pro_sweep(ell_grid *g, int l, const double *b, double *u, const int *done, hipStream_t s) {
+  const Geo &F = g->lev[l].geo, &C = g->lev[l + 1].geo;
+  const double *tab = (const double *)g->lev[l].tab, *uc = (const double *)g->lev[l + 1].u;
+  const int nbt = blocks8((long long)smooth_tiles(F) * kBlock);
+  const int Ls = seg_len(F.nz, F.nseg);
+  const long long cs = F.cs;
+  if (F.nseg == 16)
+    k_smooth_tile_pro<8, 16, false><<<nbt, 16 * 64, 0, s>>>(F, C, tab, b + cs, u, u + cs, uc, done);
+  else if (F.nseg == 8)
+    k_smooth_tile_pro<16, 8, false><<<nbt, 8 * 64, 0, s>>>(F, C, tab, b + cs, u, u + cs, uc, done);
+  else if (Ls <= 16)
+    k_smooth_tile_pro<16, 4, false><<<nbt, 4 * 64, 0, s>>>(F, C, tab, b + cs, u, u + cs, uc, done);
+  else
+    k_smooth_tile_pro<32, 4, false><<<nbt, 4 * 64, 0, s>>>(F, C, tab, b + cs, u, u + cs, uc, done);
+  return check_launch("k_smooth_tile_pro");
+}
+
 int pro_pair(ell_grid *g, const double *b, double *u, const int *done, hipStream_t s) {
   const Geo &F = g->lev[0].geo;
   const int Ls = seg_len(F.nz, F.nseg);
@@ -1047,6 +1073,15 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
     if constexpr (std::is_same<R, double>::value) {
       if (l == 0 && pro_path(g, dot)) {  // prolongation inside the post-smoothing pair
         CHK(pro_pair(g, B(0), U(0), done, s));
+        continue;
+      }
+      if (coarse_pro_ok(g, l)) {  // prolongation inside the first post-smoothing sweep
+        CHK(coarse_pro_sweep(g, l, B(l), U(l), done, s));
+        CHK(launch_smooth<R>(g, l, 0, false, B(l), U(l), done, s));
+        for (int it = 1; it < g->d.nu_post; ++it) {
+          CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
+          CHK(launch_smooth<R>(g, l, 0, false, B(l), U(l), done, s));
+        }
         continue;
       }
     }
@@ -1798,6 +1833,8 @@ int ell_grid_features(const ell_grid *g, int32_t *mask) {
     if (fused_update_path<double>(g)) m |= ELL_FEAT_FUSED_UPDATE;
     if (pro_path(g, 1)) m |= ELL_FEAT_FUSED_PROLONG;
     if (g->tiled_ends) m |= ELL_FEAT_TILED_ENDS;
+    for (int l = 1; l <= g->L - 2; ++l)
+      if (coarse_pro_ok(g, l)) m |= ELL_FEAT_COARSE_PROLONG;
   } else if (hybrid_ok(g)) {  // the FP64 post-smoothing of the mixed-precision V-cycle
     if (tile_ok(g, 0)) m |= ELL_FEAT_TILED_SMOOTH;
     if (fused_dot_path<float>(g)) m |= ELL_FEAT_FUSED_DOTS;

@@ -962,16 +962,17 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_upd(Geo L, const doub
                                              rc, st);
 }
 
-// The finest level's first post-smoothing sweep (colour 1) with the coarse
-// correction of colour 0 applied on the fly (no separate prolongation).
-template <int SEG, int NSEG>
+// A level's first post-smoothing sweep (colour 1) with the coarse correction
+// of colour 0 applied on the fly (no separate prolongation); FINE: the finest
+// level (streaming accesses).
+template <int SEG, int NSEG, bool FINE = true>
 __global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_pro(Geo L, Geo C, const double *__restrict__ tab,
                                                                const double *__restrict__ bo,
                                                                const double *__restrict__ uo,
                                                                double *__restrict__ own,
                                                                const double *__restrict__ uc,
                                                                const int *__restrict__ done) {
-  smooth_tile_body<SEG, NSEG, true, 0, false, true, 4>(L, tab, 1, bo, uo, own, done, logical_block(), nullptr, 0,
+  smooth_tile_body<SEG, NSEG, FINE, 0, false, true, 4>(L, tab, 1, bo, uo, own, done, logical_block(), nullptr, 0,
                                                        nullptr, nullptr, nullptr, &C, uc);
 }
 

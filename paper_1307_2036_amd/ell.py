@@ -177,6 +177,7 @@ ELL_TUNE_COARSE_TAIL = 10
 ELL_FEAT_TILED_SMOOTH, ELL_FEAT_FUSED_DOTS, ELL_FEAT_FUSED_UPDATE, ELL_FEAT_FUSED_PROLONG = 1, 2, 4, 8
 ELL_FEAT_TILED_ENDS = 16
 ELL_FEAT_COARSE_TAIL = 32
+ELL_FEAT_COARSE_PROLONG = 64
 
 
 def set_tuning(key: int, value: int) -> None:
@@ -280,6 +281,7 @@ class Grid:
                          "fused_dots": bool(m.value & ELL_FEAT_FUSED_DOTS),
                          "fused_update": bool(m.value & ELL_FEAT_FUSED_UPDATE),
                          "fused_prolong": bool(m.value & ELL_FEAT_FUSED_PROLONG),
+                         "coarse_prolong": bool(m.value & ELL_FEAT_COARSE_PROLONG),
                          "tiled_ends": bool(m.value & ELL_FEAT_TILED_ENDS),
                          "coarse_tail": bool(m.value & ELL_FEAT_COARSE_TAIL)}
 

@@ -22,8 +22,11 @@ def smooth_bytes(n: int, e: int, zero: bool) -> float:
     return n * (e if zero else 1.5 * e)
 
 
-def vcycle_bytes(n0: int, levels: int, e: int, nu_pre=1, nu_post=1, nu_coarse=1) -> float:
-    """Bytes of one V-cycle with rho = 1 (the shortcuts of the schedule)."""
+def vcycle_bytes(n0: int, levels: int, e: int, nu_pre=1, nu_post=1, nu_coarse=1, coarse_prolong=False) -> float:
+    """Bytes of one V-cycle with rho = 1 (the shortcuts of the schedule).
+    coarse_prolong: on levels 1 .. levels - 2 the prolongation rides on the
+    first post-smoothing sweep, which reads the coarse correction (0.25 e per
+    unknown of the level) instead of the 1.25 e of the pass."""
     total = 0.0
     n = n0
     for l in range(levels):
@@ -41,7 +44,7 @@ def vcycle_bytes(n0: int, levels: int, e: int, nu_pre=1, nu_post=1, nu_coarse=1)
                 total += smooth_bytes(n, e, True) + smooth_bytes(n, e, False)
                 total += (nu_pre - 1) * 2 * smooth_bytes(n, e, False)
             total += 1.75 * e * n                      # residual + restriction
-            total += 1.25 * e * n                      # prolongation (red only)
+            total += (0.25 if coarse_prolong and l >= 1 else 1.25) * e * n  # prolongation (red only)
             total += nu_post * 2 * smooth_bytes(n, e, False)
         n //= 4
     return total
@@ -76,13 +79,15 @@ def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1) -> float:
 
 
 def pcg_iteration_bytes(n0: int, levels: int, e: int, nu_coarse=1, flexible=True, fused_update=False,
-                        fused_dots=False, fused_prolong=False, **mg) -> float:
+                        fused_dots=False, fused_prolong=False, coarse_prolong=False, **mg) -> float:
     """fused_prolong: the finest prolongation (10 B/unknown) rides on the first
     post-smoothing sweep, which reads the coarse correction (2 B/unknown), and
-    the last sweep reads colour 1 of r for <r, z> (4 B/unknown)."""
+    the last sweep reads colour 1 of r for <r, z> (4 B/unknown); coarse_prolong:
+    the same on the coarse levels (vcycle_bytes)."""
     cg = cg_bytes(n0, flexible, fused_update, fused_dots)
     if e == 8:
-        return cg + vcycle_bytes(n0, levels, 8, nu_coarse=nu_coarse, **mg) - (4 * n0 if fused_prolong else 0)
+        return (cg + vcycle_bytes(n0, levels, 8, nu_coarse=nu_coarse, coarse_prolong=coarse_prolong, **mg) -
+                (4 * n0 if fused_prolong else 0))
     return cg + hybrid_vcycle_bytes(n0, levels, nu_coarse)
 
 
