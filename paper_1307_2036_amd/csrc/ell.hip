@@ -895,6 +895,14 @@ int launch_restrict(ell_grid *g, int l, const TB *b, const R *u, R *bc, bool bz,
     const R *tz3;
     if constexpr (std::is_same<R, double>::value) tz3 = g->lev[l].tz3;
     else tz3 = g->lev[l].tz3f;
+    if (bz && F.has_x && F.has_y) {  // k-segmented, colour-0 children only
+      const int nbz = seg_blocks(2LL * C.H);
+      const int ns = transfer_segments(2LL * C.H, F.nz);
+      if (ns == 16) k_resid_restrict_bz<R, TB, 16, true><<<nbz, 16 * 64, 0, s>>>(F, C, tab, b, u, bc, done, tz3);
+      else if (ns == 8) k_resid_restrict_bz<R, TB, 8, true><<<nbz, 8 * 64, 0, s>>>(F, C, tab, b, u, bc, done, tz3);
+      else k_resid_restrict_bz<R, TB, 4, true><<<nbz, 4 * 64, 0, s>>>(F, C, tab, b, u, bc, done, tz3);
+      return check_launch("k_resid_restrict_bz");
+    }
     if (bz) k_resid_restrict<R, true, true, TB><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done, tz3);
     else k_resid_restrict<R, false, true, TB><<<nb, kBlock, 0, s>>>(F, C, tab, b, u, bc, done, tz3);
     return check_launch("k_resid_restrict");

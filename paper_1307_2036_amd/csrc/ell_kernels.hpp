@@ -1049,15 +1049,18 @@ __device__ __forceinline__ R cell_residual(R bk, R vk, R txk, R tyk, R tzlo, R t
 //   A = (2I-1, 2J)  B = (2I+1, 2J)  C = (2I, 2J-1)  D = (2I, 2J+1)
 //   E = (2I+2, 2J+1)  F = (2I+1, 2J+2)
 // child (2I,2J): W=A E=B S=C N=D;  child (2I+1,2J+1): W=D E=E S=B N=F.
-// Requires both horizontal directions to have faces.
+// Requires both horizontal directions to have faces.  C3: the two children's
+// vertical faces from the split-layout field tz3 (T_{k-1/2} at plane k; the
+// top face is zero) instead of the table.
 // -------------------------------------------------------------------------
-template <typename R, typename TB = R, int NSEG = kSeg>
+template <typename R, typename TB = R, int NSEG = kSeg, bool C3 = false>
 __device__ __forceinline__ void resid_restrict_bz_body(Geo F, Geo C,
                                                               const R *__restrict__ tab,
                                                               const TB *__restrict__ b,
                                                               const R *__restrict__ u,
                                                               R *__restrict__ bc,
-                                                              const int *__restrict__ done, int lb, int nblocks) {
+                                                              const int *__restrict__ done, int lb, int nblocks,
+                                                              const R *__restrict__ tz3 = nullptr) {
   constexpr int U = 4;
   if (is_done(done)) return;
   const int gid = lb * kSegCols + (threadIdx.x & 63);
@@ -1090,12 +1093,29 @@ __device__ __forceinline__ void resid_restrict_bz_body(Geo F, Geo C,
   R *__restrict__ out = bc + (long long)cc * C.cs + mc;
   const int nz = F.nz;
   if (k1 <= k0) return;
+  // C3: the children's faces (both colour 0)
+  const R *__restrict__ z0 = C3 ? tz3 + col_m(F, i0, j0) : nullptr;
+  const R *__restrict__ z1 = C3 ? tz3 + col_m(F, i0 + 1, j0 + 1) : nullptr;
   R c0 = u0[(long long)k0 * H], c1 = u1[(long long)k0 * H];
   R m0 = k0 > 0 ? u0[(long long)(k0 - 1) * H] : c0;
   R m1 = k0 > 0 ? u1[(long long)(k0 - 1) * H] : c1;
-  auto step = [&](int k, R bb0, R bb1, R p0, R p1, R A, R B, R Cv, R D, R E, R Fv) {
-    const R r0 = cell_residual<R>(bb0, tv[k], tx[k], ty[k], tz[k], tz[k + 1], c0, m0, p0, A, B, Cv, D, 1, 1);
-    const R r1 = cell_residual<R>(bb1, tv[k], tx[k], ty[k], tz[k], tz[k + 1], c1, m1, p1, D, E, B, Fv, 1, 1);
+  R f0 = R(0), f1 = R(0);  // C3: the faces below level k
+  if constexpr (C3) {
+    f0 = z0[(long long)k0 * H];
+    f1 = z1[(long long)k0 * H];
+  }
+  auto step = [&](int k, R bb0, R bb1, R p0, R p1, R A, R B, R Cv, R D, R E, R Fv, R g0, R g1) {
+    R lo0 = tz[k], hi0 = tz[k + 1], lo1 = tz[k], hi1 = tz[k + 1];
+    if constexpr (C3) {
+      lo0 = f0;
+      lo1 = f1;
+      hi0 = k + 1 < nz ? g0 : R(0);
+      hi1 = k + 1 < nz ? g1 : R(0);
+      f0 = g0;
+      f1 = g1;
+    }
+    const R r0 = cell_residual<R>(bb0, tv[k], tx[k], ty[k], lo0, hi0, c0, m0, p0, A, B, Cv, D, 1, 1);
+    const R r1 = cell_residual<R>(bb1, tv[k], tx[k], ty[k], lo1, hi1, c1, m1, p1, D, E, B, Fv, 1, 1);
     out[(long long)k * C.S] = r0 + r1;
     m0 = c0;
     c0 = p0;
@@ -1104,7 +1124,7 @@ __device__ __forceinline__ void resid_restrict_bz_body(Geo F, Geo C,
   };
   int k = k0;
   for (; k + U <= k1; k += U) {
-    R bb0[U], bb1[U], p0[U], p1[U], A[U], B[U], Cv[U], D[U], E[U], Fv[U];
+    R bb0[U], bb1[U], p0[U], p1[U], A[U], B[U], Cv[U], D[U], E[U], Fv[U], g0[U], g1[U];
 #pragma unroll
     for (int t = 0; t < U; ++t) {
       const long long o = (long long)(k + t) * H;
@@ -1119,27 +1139,36 @@ __device__ __forceinline__ void resid_restrict_bz_body(Geo F, Geo C,
       D[t] = pD[o];
       E[t] = pE[o];
       Fv[t] = pF[o];
+      if constexpr (C3) {  // the faces above level k + t (level k + t + 1's, clamped)
+        g0[t] = z0[op];
+        g1[t] = z1[op];
+      } else {
+        g0[t] = g1[t] = R(0);
+      }
     }
 #pragma unroll
-    for (int t = 0; t < U; ++t) step(k + t, bb0[t], bb1[t], p0[t], p1[t], A[t], B[t], Cv[t], D[t], E[t], Fv[t]);
+    for (int t = 0; t < U; ++t)
+      step(k + t, bb0[t], bb1[t], p0[t], p1[t], A[t], B[t], Cv[t], D[t], E[t], Fv[t], g0[t], g1[t]);
   }
   for (; k < k1; ++k) {
     const long long o = (long long)k * H;
     const long long op = (long long)min(k + 1, nz - 1) * H;
-    step(k, (R)b0[o], (R)b1[o], u0[op], u1[op], pA[o], pB[o], pC[o], pD[o], pE[o], pF[o]);
+    step(k, (R)b0[o], (R)b1[o], u0[op], u1[op], pA[o], pB[o], pC[o], pD[o], pE[o], pF[o], C3 ? z0[op] : R(0),
+         C3 ? z1[op] : R(0));
   }
 }
 
 // NSEG k-segments per column, one wavefront each (more on small coarse levels,
 // where the sequential walk over a segment is the kernel's latency).
-template <typename R, typename TB = R, int NSEG = kSeg>
+template <typename R, typename TB = R, int NSEG = kSeg, bool C3 = false>
 __global__ __launch_bounds__(NSEG * 64) void k_resid_restrict_bz(Geo F, Geo C,
                                                                  const R *__restrict__ tab,
                                                                  const TB *__restrict__ b,
                                                                  const R *__restrict__ u,
                                                                  R *__restrict__ bc,
-                                                                 const int *__restrict__ done) {
-  resid_restrict_bz_body<R, TB, NSEG>(F, C, tab, b, u, bc, done, logical_block(), gridDim.x);
+                                                                 const int *__restrict__ done,
+                                                                 const R *__restrict__ tz3 = nullptr) {
+  resid_restrict_bz_body<R, TB, NSEG, C3>(F, C, tab, b, u, bc, done, logical_block(), gridDim.x, tz3);
 }
 
 // -------------------------------------------------------------------------

@@ -403,6 +403,33 @@ def test_fused_update_equals_separate_pass(ell, orc, nx, ny, nz, levels, precisi
         check_solve(orc, g, p.f, u1, s1, 1e-8, flexible=flexible)
 
 
+@pytest.mark.parametrize("shape,mg", [((64, 64, 48), dict(n_levels=4, nu_coarse=5)),
+                                      ((136, 16, 40), dict(n_levels=3)),
+                                      ((128, 32, 100), dict(n_levels=4, nu_coarse=2, nu_post=2)),
+                                      ((64, 8, 24), dict(n_levels=3))])
+def test_coarse_prolongation_in_sweep_is_bitwise(ell, orc, shape, mg):
+    """On the coarse levels the bilinear correction applied inside the first
+    post-smoothing sweep adds the same four terms in the same order as the
+    tiled prolongation pass: V-cycles with and without it are bitwise equal,
+    and both match the oracle.  (136, 16): partial tiles on level 1 (hx2 =
+    34); nu_post = 2: the later post-smoothing pairs follow the fused sweep;
+    (64, 8): a two-row level 2 (coarse rows wrap onto themselves)."""
+    g = grid_for(orc, shape, **mg)
+    r = np.random.default_rng(11).standard_normal(g.shape) * (g.hx * g.hy * g.dz)[:, None, None]
+    out = []
+    for fused in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_FUSED_PROLONG, fused)
+        try:
+            G = gpu_grid(ell, g)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_FUSED_PROLONG, 1)
+        assert G.features["coarse_prolong"] == bool(fused), G.features
+        out.append(host(G.vcycle(dev(r))))
+        G.close()
+    assert np.array_equal(out[0], out[1])
+    assert rel(out[0], orc.vcycle(g, r)) <= 1e-11
+
+
 @pytest.mark.parametrize("nx,ny,nz,levels", [(64, 16, 32, 3), (68, 12, 100, 2), (136, 8, 40, 2),
                                            (64, 64, 48, 4)])
 def test_fused_prolongation_equals_prolongation_pass(ell, orc, nx, ny, nz, levels):
