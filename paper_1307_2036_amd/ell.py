@@ -25,7 +25,7 @@ ELL_OK, ELL_NOT_CONVERGED, ELL_PENDING = 0, 1, 2
 ELL_ERR_INVALID, ELL_ERR_OOM, ELL_ERR_HIP, ELL_ERR_NUMERIC, ELL_ERR_BUDGET = -1, -2, -3, -4, -5
 ELL_FP64, ELL_FP32_PRECOND, ELL_FP32_BF16COEF = 0, 1, 2
 PRECISIONS = {"fp64": ELL_FP64, "fp32": ELL_FP32_PRECOND, "bf16coef": ELL_FP32_BF16COEF}
-ELL_K_SMOOTH0, ELL_K_APPLY, ELL_K_RESTRICT0, ELL_K_PROLONG0, ELL_K_UPDATE = 0, 1, 2, 3, 4
+ELL_K_SMOOTH0, ELL_K_APPLY, ELL_K_RESTRICT0, ELL_K_PROLONG0, ELL_K_UPDATE, ELL_K_COUNT = 0, 1, 2, 3, 4, 5
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
