@@ -813,6 +813,22 @@ int launch_smooth_upd(ell_grid *g, int c, double *r, R *u, const R *tab, int pba
 // coarse correction to the colour-0 values it reads (no prolongation pass),
 // the colour-0 sweep forms <r, z> of both colours into the first tile-count
 // partial slots.  The caller has checked pro_path.
+// The staged coarse values of a fused prolongation load in aligned pairs
+// (k_smooth_tile_pro<..., PAIR>): coarse half-width, colour and plane strides
+// even, the array 16-byte aligned.
+bool pro_pairs_ok(const Geo &C, const void *uc) {
+  return C.nx % 4 == 0 && C.cs % 2 == 0 && C.S % 2 == 0 && (reinterpret_cast<uintptr_t>(uc) & 15) == 0;
+}
+
+template <int SEG, int NSEG, bool FINE>
+void launch_tile_pro(int nbt, hipStream_t s, const Geo &F, const Geo &C, const double *tab, const double *b1,
+                     const double *u, double *u1, const double *uc, const int *done) {
+  if (pro_pairs_ok(C, uc))
+    k_smooth_tile_pro<SEG, NSEG, FINE, true><<<nbt, NSEG * 64, 0, s>>>(F, C, tab, b1, u, u1, uc, done);
+  else
+    k_smooth_tile_pro<SEG, NSEG, FINE, false><<<nbt, NSEG * 64, 0, s>>>(F, C, tab, b1, u, u1, uc, done);
+}
+
 template <int SEG, int NSEG>
 void pro_pair_k(ell_grid *g, const double *b, double *u, const int *done, hipStream_t s) {
   const Geo &F = g->lev[0].geo, &C = g->lev[1].geo;
@@ -821,8 +837,7 @@ void pro_pair_k(ell_grid *g, const double *b, double *u, const int *done, hipStr
   const long long cs = F.cs;
   {
     ProfScope ps(g, ELL_K_SMOOTH0, s);
-    k_smooth_tile_pro<SEG, NSEG><<<nbt, NSEG * 64, 0, s>>>(F, C, tab, b + cs, u, u + cs,
-                                                           (const double *)g->lev[1].u, done);
+    launch_tile_pro<SEG, NSEG, true>(nbt, s, F, C, tab, b + cs, u, u + cs, (const double *)g->lev[1].u, done);
   }
   ProfScope ps(g, ELL_K_SMOOTH0, s);
   k_smooth_tile_dot3<SEG, NSEG><<<nbt, NSEG * 64, 0, s>>>(F, tab, b, u + cs, u, done, g->partial, b + cs);
@@ -843,14 +858,10 @@ int coarse_pro_sweep(ell_grid *g, int l, const double *b, double *u, const int *
   const int nbt = blocks8((long long)smooth_tiles(F) * kBlock);
   const int Ls = seg_len(F.nz, F.nseg);
   const long long cs = F.cs;
-  if (F.nseg == 16)
-    k_smooth_tile_pro<8, 16, false><<<nbt, 16 * 64, 0, s>>>(F, C, tab, b + cs, u, u + cs, uc, done);
-  else if (F.nseg == 8)
-    k_smooth_tile_pro<16, 8, false><<<nbt, 8 * 64, 0, s>>>(F, C, tab, b + cs, u, u + cs, uc, done);
-  else if (Ls <= 16)
-    k_smooth_tile_pro<16, 4, false><<<nbt, 4 * 64, 0, s>>>(F, C, tab, b + cs, u, u + cs, uc, done);
-  else
-    k_smooth_tile_pro<32, 4, false><<<nbt, 4 * 64, 0, s>>>(F, C, tab, b + cs, u, u + cs, uc, done);
+  if (F.nseg == 16) launch_tile_pro<8, 16, false>(nbt, s, F, C, tab, b + cs, u, u + cs, uc, done);
+  else if (F.nseg == 8) launch_tile_pro<16, 8, false>(nbt, s, F, C, tab, b + cs, u, u + cs, uc, done);
+  else if (Ls <= 16) launch_tile_pro<16, 4, false>(nbt, s, F, C, tab, b + cs, u, u + cs, uc, done);
+  else launch_tile_pro<32, 4, false>(nbt, s, F, C, tab, b + cs, u, u + cs, uc, done);
   return check_launch("k_smooth_tile_pro");
 }
 

@@ -726,7 +726,12 @@ constexpr int kCRow = 48;  // LDS row stride of the staged coarse values (40 use
 // of the written columns plus <r1, z1> over the colour-1 cells of the tile's
 // rows, z1 from the staged values and r1 loaded (r1c: colour 1 of r), into
 // partial[pbase + lb].
-template <int SEG, int NSEG, bool FINE, int DOT = 0, bool UPD = false, bool PRO = false, int CH = 8>
+// PAIR (with PRO; the coarse level's half-width, colour stride and plane
+// stride even, its array 16-byte aligned): the staged coarse values come in
+// pairs of neighbouring same-colour columns, one 16-byte load per lane on 60
+// lanes instead of two 8-byte loads on 128.
+template <int SEG, int NSEG, bool FINE, int DOT = 0, bool UPD = false, bool PRO = false, int CH = 8,
+          bool PAIR = false>
 __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict__ tab, int c,
                                                  const double *__restrict__ bo,
                                                  const double *__restrict__ uo,
@@ -752,7 +757,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   __shared__ __align__(16) double ot[NSEG][4][36];
   __shared__ double bsh[DOT ? NSEG : 1][DOT ? SEG : 1][64];
   __shared__ double red[NQ ? NSEG : 1][2];
-  __shared__ double csl[PRO ? NSEG : 1][PRO ? 3 * kCRow : 1];
+  __shared__ __align__(16) double csl[PRO ? NSEG : 1][PRO ? 3 * kCRow : 1];
   const int tiles_x = (L.hx2 + kSTX - 1) / kSTX;
   if (is_done(done) || lb >= tiles_x * (L.ny / 2)) return;  // whole blocks: no barrier is skipped
   const int lane = threadIdx.x & 63;
@@ -815,10 +820,25 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
       return (long long)((I + J) & 1) * C.cs + col_m(C, I, J);
     };
     auto cslot = [](int v) -> int { return v < 120 ? (v / 40) * kCRow + v % 40 : 2 * kCRow + 40 + (v - 120); };
-    co0 = coff(lane);
-    co1 = coff(64 + lane);
-    cs0 = cslot(lane);
-    cs1 = cslot(64 + lane);
+    if constexpr (PAIR) {
+      // lane v < 60: row v / 20, parity par = (v % 20) / 10, pair t2 = v % 10,
+      // columns I = mx0 - 4 + 4 t2 + par and I + 2 (split neighbours: with the
+      // half-width even, I - par is a multiple of 4 also after the wrap, so a
+      // pair starts at an even split index and never straddles the wrap);
+      // pairs no staged fine cell reads, and v >= 60, load an aligned dummy
+      const int v = lane, row = v / 20, rem = v - row * 20, par = rem / 10, t2 = rem - par * 10;
+      const int q = 4 * t2 + par - 2;  // I - (mx0 - 2) of the pair's first column
+      const bool need = v < 60 && q + 2 >= 0 && q <= nxm + 3;
+      const int I = wrapi(mx0 - 2 + (need ? q : 2), C.nx);
+      const int J = wrapi(J0 - 1 + (need ? row : 1), C.ny);
+      co0 = (long long)((I + J) & 1) * C.cs + col_m(C, I, J);
+      cs0 = v < 60 ? row * kCRow + par * 20 + 2 * t2 : 2 * kCRow + 40 + 2 * (v - 60);
+    } else {
+      co0 = coff(lane);
+      co1 = coff(64 + lane);
+      cs0 = cslot(lane);
+      cs1 = cslot(64 + lane);
+    }
     HC = C.S;
     ucg = gp(uc);
     csf = csl[sg];
@@ -851,7 +871,9 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
 #pragma unroll
   for (int c0 = 0; c0 < SEG; c0 += CH) {
     if (c0 < len) {
-      double bv[CH], ev[CH], qv[UPD ? CH : 1], cv0[PRO ? CH : 1], cv1[PRO ? CH : 1], r1v[DOT == 3 ? CH : 1];
+      double bv[CH], ev[CH], qv[UPD ? CH : 1], cv0[PRO && !PAIR ? CH : 1], cv1[PRO && !PAIR ? CH : 1],
+          r1v[DOT == 3 ? CH : 1];
+      nt_d2 cvp[PRO && PAIR ? CH : 1];
       nt_d2 tv[CH];
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
@@ -862,8 +884,12 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
         tv[t] = *(const nt_d2 *)&ug[o + po];
         ev[t] = lane < 2 ? ug[o + eo] : 0.0;
         if constexpr (PRO) {
-          cv0[t] = ucg[kc * HC + co0];
-          cv1[t] = ucg[kc * HC + co1];
+          if constexpr (PAIR) {
+            cvp[t] = *(const nt_d2 *)&ucg[kc * HC + co0];
+          } else {
+            cv0[t] = ucg[kc * HC + co0];
+            cv1[t] = ucg[kc * HC + co1];
+          }
         }
         if constexpr (DOT == 3) r1v[t] = __builtin_nontemporal_load(&r1g[o + mo]);
       }
@@ -880,8 +906,12 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
         nt_d2 pr = tv[t];
         double evk = ev[t];
         if constexpr (PRO) {
-          csf[cs0] = cv0[t];
-          csf[cs1] = cv1[t];
+          if constexpr (PAIR) {
+            *(nt_d2 *)&csf[cs0] = cvp[t];
+          } else {
+            csf[cs0] = cv0[t];
+            csf[cs1] = cv1[t];
+          }
           __asm__ volatile("" ::: "memory");
           pr.x = pr.x + corr(pa, pb, pd, 2 + 2 * pp);
           pr.y = pr.y + corr(pa, pb, pd, 3 + 2 * pp);
@@ -965,15 +995,15 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_upd(Geo L, const doub
 // A level's first post-smoothing sweep (colour 1) with the coarse correction
 // of colour 0 applied on the fly (no separate prolongation); FINE: the finest
 // level (streaming accesses).
-template <int SEG, int NSEG, bool FINE = true>
+template <int SEG, int NSEG, bool FINE = true, bool PAIR = false>
 __global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_pro(Geo L, Geo C, const double *__restrict__ tab,
                                                                const double *__restrict__ bo,
                                                                const double *__restrict__ uo,
                                                                double *__restrict__ own,
                                                                const double *__restrict__ uc,
                                                                const int *__restrict__ done) {
-  smooth_tile_body<SEG, NSEG, FINE, 0, false, true, 4>(L, tab, 1, bo, uo, own, done, logical_block(), nullptr, 0,
-                                                       nullptr, nullptr, nullptr, &C, uc);
+  smooth_tile_body<SEG, NSEG, FINE, 0, false, true, 4, PAIR>(L, tab, 1, bo, uo, own, done, logical_block(), nullptr,
+                                                             0, nullptr, nullptr, nullptr, &C, uc);
 }
 
 // The last sweep (colour 0) after it, with <r, z> of both colours.
