@@ -607,12 +607,16 @@ def varying_summary(a, steps, precision="fp64", p=None):
     ts_ = G.profile_times(ell.ELL_K_SMOOTH0)
     ts_ = ts_[ts_ > 0.25 * float(np.median(ts_))]
     avg_ms = float(ts_.mean())
+    feat = G.features
+    fu, fd = feat["fused_update"], feat["fused_dots"]
     if precision == "fp64":
-        launch_bytes = perfmodel.smooth0_launch_bytes_varying(p.n)
-        it_bytes = perfmodel.pcg_iteration_bytes_varying(p.n, G.levels, p.nu_coarse, flexible=False)
+        launch_bytes = perfmodel.smooth0_launch_bytes_varying(p.n, fused_update=fu)
+        it_bytes = perfmodel.pcg_iteration_bytes_varying(p.n, G.levels, p.nu_coarse, flexible=False,
+                                                         fused_update=fu, fused_dots=fd)
     else:
-        launch_bytes = perfmodel.smooth0_launch_bytes_varying_hybrid(p.n)
-        it_bytes = perfmodel.pcg_iteration_bytes_varying_hybrid(p.n, G.levels, p.nu_coarse)
+        launch_bytes = perfmodel.smooth0_launch_bytes_varying_hybrid(p.n, fused_update=fu, dot_q=fd)
+        it_bytes = perfmodel.pcg_iteration_bytes_varying_hybrid(p.n, G.levels, p.nu_coarse, fused_update=fu,
+                                                                fused_dots=fd)
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
     solves = steps / elapsed
     G.close()
@@ -630,7 +634,9 @@ def varying_summary(a, steps, precision="fp64", p=None):
             "unknowns_iter_per_s": p.n * iters * solves,
             "hbm_gbs_algorithmic": it_bytes * iters * solves / 1e9,
             "roofline": {"bound": "hbm", "kernel": "finest-level line relaxation, k_smooth_seg3 (per-column "
-                                                   "coefficients), average over the four half-sweeps",
+                                                   "coefficients), average over the four half-sweeps" +
+                                                   (" (residual update fused into the first pair)" if fu else "") +
+                                                   (" (CG dots fused into the last pair)" if fd else ""),
                          "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "avg_launch_us": avg_ms * 1e3,
                          "launches": int(ts_.size), "timed_steps_sampled": sample,

@@ -100,6 +100,9 @@ inline long long partial_blocks(const Geo &G0, long long n0) {
   long long b = std::max<long long>(seg_blocks(2LL * G0.H), flat_blocks(n0 / 2));
   b = std::max<long long>(b, batch_flat_blocks(n0 / 2));
   b = std::max<long long>(b, 2LL * ((G0.hx2 + kSTX - 1) / kSTX) * (G0.ny / 2));  // fused dots
+  // fused forms of the per-column sweep: one slot per block of either colour
+  b = std::max<long long>(b, blocks8(((long long)G0.ncol0 + kSegCols - 1) / kSegCols * kBlock) +
+                                 blocks8(((long long)G0.ncol1 + kSegCols - 1) / kSegCols * kBlock));
   return std::max<long long>(b, blocks8(tile_blocks(G0, 4) * kBlock));
 }
 
@@ -589,6 +592,56 @@ bool tile_ok(const ell_grid *g, int l) {
 // Blocks (tiles of 32 x 2 columns of one colour) of a tiled half-sweep.
 inline int smooth_tiles(const Geo &G) { return ((G.hx2 + kSTX - 1) / kSTX) * (G.ny / 2); }
 
+// The per-column-coefficient sweep (k_smooth_seg3) of one colour of a level:
+// one block per 64 columns, sixteen k-segments on small (latency-bound)
+// levels, eight on large ones.
+struct Seg3Shape {
+  int nbs;     // blocks (each writes a partial slot in the fused forms)
+  bool small;  // sixteen segments
+  int Ls;      // levels per segment
+};
+inline Seg3Shape seg3_shape(const Geo &G, int c) {
+  const int ncol = c ? G.ncol1 : G.ncol0;
+  Seg3Shape sh;
+  sh.nbs = blocks8(((long long)ncol + kSegCols - 1) / kSegCols * kBlock);
+  sh.small = G.H < 16384 && seg_len(G.nz, 16) <= 16;
+  sh.Ls = seg_len(G.nz, sh.small ? 16 : 8);
+  return sh;
+}
+
+// Where the per-column sweep applies: a grid with per-column coefficients,
+// rho = 1, both horizontal directions, at most 256 levels.
+bool seg3_ok(const ell_grid *g, int l) {
+  const Geo &G = g->lev[l].geo;
+  return g->varying && g->d.rho == 1.0 && G.has_x && G.has_y && G.nz <= 256;
+}
+
+int dot_colour_slots(const ell_grid *g, int c);
+
+template <typename R, typename TB, typename F, bool Z, bool FN, int DOT = 0, bool UPD = false>
+void seg3_launch(hipStream_t s, const Geo &G, const R *tab, int c, const TB *bo, const R *uo, R *own,
+                 const int *done, const F *t3, const F *i3, const F *c3, double *partial = nullptr, int pbase = 0,
+                 double *rw = nullptr, const double *qo = nullptr, const PcgState *st = nullptr) {
+  const Seg3Shape sh = seg3_shape(G, c);
+  auto go = [&](auto seg, auto nseg, auto ch) {
+    constexpr int SEG = decltype(seg)::value, NSEG = decltype(nseg)::value, CH = decltype(ch)::value;
+    k_smooth_seg3<R, TB, F, Z, FN, SEG, NSEG, CH, DOT, UPD><<<sh.nbs, NSEG * 64, 0, s>>>(
+        G, tab, c, bo, uo, own, done, t3, i3, c3, partial, pbase, rw, qo, st);
+  };
+  using I4 = std::integral_constant<int, 4>;
+  using I8 = std::integral_constant<int, 8>;
+  using I16 = std::integral_constant<int, 16>;
+  using I32 = std::integral_constant<int, 32>;
+  if (sh.small) {
+    if (sh.Ls <= 8) go(I8{}, I16{}, I4{});
+    else go(I16{}, I16{}, I4{});
+  } else {
+    if (sh.Ls <= 8) go(I8{}, I8{}, I8{});
+    else if (sh.Ls <= 16) go(I16{}, I8{}, I8{});
+    else go(I32{}, I8{}, I8{});
+  }
+}
+
 // One colour of line relaxation on level l.  tab: coefficient table in the
 // arithmetic type R (nullptr: the level's own table).  TB != R is supported
 // on the finest level only.
@@ -616,27 +669,10 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
     // excess of a strongly coupled column (T/p = 1 - O(1e-7) or closer), so
     // FP32 factors there would undo what that sweep is for.
     if (rho1 && hxy && G.nz <= 256) {
-      // k-segmented: sixteen segments on small (latency-bound) levels, eight
-      // on large ones
-      const int nbs = blocks8(((long long)ncol + kSegCols - 1) / kSegCols * kBlock);
-      const bool small = G.H < 16384 && seg_len(G.nz, 16) <= 16;
-      const int Ls = seg_len(G.nz, small ? 16 : 8);
       auto go = [&](auto z, auto fn, const auto *t3, const auto *i3, const auto *c3) {
         constexpr bool Z = decltype(z)::value, FN = decltype(fn)::value;
         using F = std::remove_cv_t<std::remove_pointer_t<decltype(t3)>>;
-        if (small) {
-          if (Ls <= 8)
-            k_smooth_seg3<R, TB, F, Z, FN, 8, 16, 4><<<nbs, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
-          else
-            k_smooth_seg3<R, TB, F, Z, FN, 16, 16, 4><<<nbs, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
-        } else {
-          if (Ls <= 8)
-            k_smooth_seg3<R, TB, F, Z, FN, 8, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
-          else if (Ls <= 16)
-            k_smooth_seg3<R, TB, F, Z, FN, 16, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
-          else
-            k_smooth_seg3<R, TB, F, Z, FN, 32, 8, 8><<<nbs, 8 * 64, 0, s>>>(G, tab, c, bo, uo, own, done, t3, i3, c3);
-        }
+        seg3_launch<R, TB, F, Z, FN>(s, G, tab, c, bo, uo, own, done, t3, i3, c3);
       };
       auto go_f = [&](auto z, auto fn) {
         if constexpr (std::is_same<R, double>::value)
@@ -757,6 +793,16 @@ int launch_smooth_dot(ell_grid *g, int c, const double *b, double *u, const doub
   const double *qc = g->q + (long long)c * G.cs;
   const int nbt = blocks8((long long)smooth_tiles(G) * kBlock);
   ProfScope ps(g, ELL_K_SMOOTH0, s);
+  if (g->varying) {  // the per-column sweep, FP64 fields
+    const Level &Lv = g->lev[0];
+    if (dot == 2)
+      seg3_launch<double, double, double, false, true, 2>(s, G, tab, c, bo, uo, own, done, Lv.tz3, Lv.ip3, Lv.cf3,
+                                                          g->partial, pbase, nullptr, qc);
+    else
+      seg3_launch<double, double, double, false, true, 1>(s, G, tab, c, bo, uo, own, done, Lv.tz3, Lv.ip3, Lv.cf3,
+                                                          g->partial, pbase);
+    return check_launch("k_smooth_seg3");
+  }
   if (G.nseg == 16) tile_dot<8, 16>(dot, nbt, s, G, tab, c, bo, uo, own, done, g->partial, pbase, qc);
   else if (G.nseg == 8) tile_dot<16, 8>(dot, nbt, s, G, tab, c, bo, uo, own, done, g->partial, pbase, qc);
   else if (Ls <= 16) tile_dot<16, 4>(dot, nbt, s, G, tab, c, bo, uo, own, done, g->partial, pbase, qc);
@@ -779,6 +825,26 @@ int launch_smooth_upd(ell_grid *g, int c, double *r, R *u, const R *tab, int pba
   const R *uo = u + (long long)(1 - c) * G.cs;
   R *own = u + (long long)c * G.cs;
   ProfScope ps(g, ELL_K_SMOOTH0, s);
+  if (g->varying) {  // the per-column sweep, fields in the arithmetic type
+    const Level &Lv = g->lev[0];
+    const int *done = &g->st->done;
+    auto go = [&](auto z, const auto *t3, const auto *i3, const auto *c3) {
+      constexpr bool Z = decltype(z)::value;
+      using F = std::remove_cv_t<std::remove_pointer_t<decltype(t3)>>;
+      seg3_launch<R, double, F, Z, true, 0, true>(s, G, tab, c, rc, uo, own, done, t3, i3, c3, g->partial, pbase,
+                                                 rc, qc, g->st);
+    };
+    if constexpr (std::is_same<R, double>::value) {
+      if (c == 0) go(std::true_type{}, Lv.tz3, Lv.ip3, Lv.cf3);
+      else go(std::false_type{}, Lv.tz3, Lv.ip3, Lv.cf3);
+    } else {
+      const float *t3 = (const float *)Lv.tz3f, *i3 = (const float *)Lv.ip3f, *c3 = (const float *)Lv.cf3f;
+      if (c == 0) go(std::true_type{}, t3, i3, c3);
+      else go(std::false_type{}, t3, i3, c3);
+    }
+    *slots = seg3_shape(G, c).nbs;  // every block writes its slot
+    return check_launch("k_smooth_seg3");
+  }
   if constexpr (std::is_same<R, double>::value) {
     if (c == 1) {
       const int nbt = blocks8((long long)smooth_tiles(G) * kBlock);
@@ -1108,7 +1174,7 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
     for (int it = 0; it < g->d.nu_post; ++it) {
       if constexpr (std::is_same<R, double>::value) {
         if (dot && l == 0 && it == g->d.nu_post - 1) {
-          const int nt = smooth_tiles(g->lev[0].geo);
+          const int nt = dot_colour_slots(g, 1);
           CHK(launch_smooth_dot(g, 1, B(l), U(l), (const double *)g->lev[0].tab, dot, 0, done, s));
           CHK(launch_smooth_dot(g, 0, B(l), U(l), (const double *)g->lev[0].tab, dot, nt, done, s));
           continue;
@@ -1180,7 +1246,7 @@ int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipS
   }
   for (int it = 0; it < g->d.nu_post; ++it) {
     if (dot && it == g->d.nu_post - 1) {
-      const int nt = smooth_tiles(g->lev[0].geo);
+      const int nt = dot_colour_slots(g, 1);
       CHK(launch_smooth_dot(g, 1, r, z, g->tab64_0, dot, 0, done, s));
       CHK(launch_smooth_dot(g, 0, r, z, g->tab64_0, dot, nt, done, s));
       continue;
@@ -1199,12 +1265,12 @@ template <typename R>
 bool fused_update_path(const ell_grid *g) {
   const Geo &G = g->lev[0].geo;
   const int Ls = seg_len(G.nz, G.nseg);
-  const bool segs = (G.nseg == 8 && Ls <= 16) || (G.nseg == 4 && Ls <= 32);
+  const bool segs = g->varying ? seg3_ok(g, 0) : ((G.nseg == 8 && Ls <= 16) || (G.nseg == 4 && Ls <= 32));
   // at least two levels: the finest level's pre-smoothing, and with it the
   // convergence test, then runs once per step
   const bool base =
       g->fused_update && g->L >= 2 && g->d.rho == 1.0 && g->d.nu_pre >= 1 && G.has_x && G.has_y && segs;
-  if constexpr (std::is_same<R, double>::value) return base && tile_ok(g, 0);
+  if constexpr (std::is_same<R, double>::value) return base && (tile_ok(g, 0) || g->varying);
   else return base && hybrid_ok(g);
 }
 
@@ -1213,7 +1279,7 @@ bool fused_update_path(const ell_grid *g) {
 // the mixed-precision one with its FP64 finest post-smoothing).
 template <typename R>
 bool fused_dot_path(const ell_grid *g) {
-  const bool base = g->fused_dot && g->L >= 2 && g->d.nu_post >= 1 && tile_ok(g, 0);
+  const bool base = g->fused_dot && g->L >= 2 && g->d.nu_post >= 1 && (tile_ok(g, 0) || seg3_ok(g, 0));
   if constexpr (std::is_same<R, double>::value) return base;
   else return base && hybrid_ok(g);
 }
@@ -1226,10 +1292,15 @@ bool pro_path(const ell_grid *g, int dot) {
          g->d.nu_post == 1 && g->d.prolong == 0;
 }
 
+// Partial slots of one colour's fused-dot sweep (colour 1 takes the first
+// ones, colour 0 follows).
+int dot_colour_slots(const ell_grid *g, int c) {
+  return g->varying ? seg3_shape(g->lev[0].geo, c).nbs : smooth_tiles(g->lev[0].geo);
+}
+
 // Partial slots of the fused dots.
 int dot_slots(const ell_grid *g, int dot) {
-  const int t = smooth_tiles(g->lev[0].geo);
-  return pro_path(g, dot) ? t : 2 * t;
+  return pro_path(g, dot) ? smooth_tiles(g->lev[0].geo) : dot_colour_slots(g, 1) + dot_colour_slots(g, 0);
 }
 
 int launch_apply64(ell_grid *g, const double *x, double *y, bool dot, const int *done, hipStream_t s) {
@@ -1723,9 +1794,9 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->tiled_ends = (g_tiled_ends && desc->nx > 1 && desc->ny > 1) ? 1 : 0;
   g->coarse_tail = g_coarse_tail && !batch_layout;
   g->batch_layout = batch_layout;
-  if (lam3) {  // per-column coefficients: no LDS-tiled sweeps (tile_ok), ends or fused forms
+  if (lam3) {  // per-column coefficients: no LDS-tiled sweeps (tile_ok), ends or fused prolongation
     g->varying = true;
-    g->fused_dot = g->fused_update = g->fused_prolong = g->tiled_ends = 0;
+    g->fused_prolong = g->tiled_ends = 0;
   }
   g->lev.resize(L);
   auto bail = [&](int rc) {

@@ -571,9 +571,16 @@ __device__ __forceinline__ void smooth_seg_body(Geo L, const R *__restrict__ tab
 // -------------------------------------------------------------------------
 // R: arithmetic and element type of u and tab; TB: element type of b (the
 // FP32 preconditioner's finest level reads the FP64 CG residual); F: element
-// type of the per-column fields (FP32 copies for the mixed-precision V-cycles,
-// also under its FP64 finest post-smoothing).
-template <typename R, typename TB, typename F, bool ZERO, bool FINE, int SEG, int NSEG, int CH>
+// type of the per-column fields (FP32 copies for the FP32 sweeps of the
+// mixed-precision V-cycle).
+// The finest level's fused CG forms, as in smooth_seg_body and the tiled
+// sweeps: UPD (the first pre-smoothing pair, TB = double) advances b to
+// b - alpha q, writes it back to rw and leaves the block's sum of its squares
+// in partial[pbase + block]; DOT = 1 (the last post-smoothing pair) leaves
+// <b, w> of the written columns there, DOT = 2 also <q, w> (qo: this colour's
+// part of q), at partial[2 (pbase + block)] and [2 (pbase + block) + 1].
+template <typename R, typename TB, typename F, bool ZERO, bool FINE, int SEG, int NSEG, int CH, int DOT = 0,
+          bool UPD = false>
 __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const R *__restrict__ tab, int c,
                                                            const TB *__restrict__ bo,
                                                            const R *__restrict__ uo,
@@ -581,8 +588,19 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const R *__res
                                                            const int *__restrict__ done,
                                                            const F *__restrict__ tz3,
                                                            const F *__restrict__ ip3,
-                                                           const F *__restrict__ cf3) {
+                                                           const F *__restrict__ cf3,
+                                                           double *__restrict__ partial = nullptr, int pbase = 0,
+                                                           double *__restrict__ rw = nullptr,
+                                                           const double *__restrict__ qo = nullptr,
+                                                           const PcgState *__restrict__ st = nullptr) {
+  static_assert(!UPD || std::is_same<TB, double>::value, "the residual update reads the FP64 residual");
+  static_assert(!(UPD && DOT), "one fused form per sweep");
+  constexpr int NQ = DOT ? DOT : (UPD ? 1 : 0);
   __shared__ R xv[NSEG][kSegCols], xq[NSEG][kSegCols];
+  __shared__ double red[NQ ? NSEG : 1][2];
+  // DOT: each lane keeps its column's b in LDS for <b, w> (read again from
+  // memory at the end, it would come back from HBM)
+  __shared__ double bsh[DOT ? NSEG : 1][DOT ? SEG : 1][DOT ? kSegCols : 1];
   if (is_done(done)) return;
   const int lane = threadIdx.x & 63;
   const int sg = wave_id();
@@ -612,6 +630,13 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const R *__res
   static_assert(SEG % CH == 0, "chunks must tile the segment");
   R y[SEG], pr[SEG];
   R prev = R(0), prod = R(1);
+  // UPD: go, an update is pending (always in a single grid's step)
+  double alpha = 0.0, rr = 0.0;
+  bool go = false;
+  if constexpr (UPD) {
+    go = st->pending != 0;
+    alpha = st->alpha;
+  }
 #pragma unroll
   for (int c0 = 0; c0 < SEG; c0 += CH) {
     if (c0 < len) {
@@ -620,7 +645,23 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const R *__res
       for (int t = 0; t < CH; ++t) {
         const int k = min(k0 + c0 + t, k1 - 1);
         const long long o = (long long)k * H;
-        R v = (R)ld_s<FINE>(&bb[o]);
+        R v;
+        if constexpr (UPD) {
+          // the residual update of the CG step; only the lane that owns the
+          // column writes it
+          const double b0 = __builtin_nontemporal_load(&bb[o]);
+          const double q0 = __builtin_nontemporal_load(&qo[mm + o]);
+          const double rv = go ? b0 - alpha * q0 : b0;  // a select: q may hold anything without go
+          if (go && valid && c0 + t < len) {
+            __builtin_nontemporal_store(rv, &rw[mm + o]);
+            rr += rv * rv;
+          }
+          v = (R)rv;
+        } else {
+          const TB braw = ld_s<FINE>(&bb[o]);
+          v = (R)braw;
+          if constexpr (DOT > 0) bsh[sg][c0 + t][lane] = (double)braw;
+        }
         if (!ZERO) {
           v = v + tx[k] * (uw[o] + ue[o]);
           v = v + ty[k] * (us[o] + un[o]);
@@ -680,10 +721,37 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const R *__res
     const R cand = xv[q][lane] + xq[q][lane] * win;
     win = q > sg ? cand : win;
   }
+  double d0 = 0.0, d1 = 0.0;  // DOT: <b, w>, <q, w> of this lane's column
   if (valid) {
 #pragma unroll
     for (int t = 0; t < SEG; ++t)
-      if (t < len) ow[(long long)(k0 + t) * H] = y[t] + pr[t] * win;
+      if (t < len) {
+        const long long o = (long long)(k0 + t) * H;
+        const R w = y[t] + pr[t] * win;
+        ow[o] = w;
+        if constexpr (DOT > 0) {
+          d0 += bsh[sg][t][lane] * (double)w;
+          if constexpr (DOT == 2) d1 += __builtin_nontemporal_load(&qo[mm + o]) * (double)w;
+        }
+      }
+  }
+  if constexpr (NQ > 0) {
+    double v0 = UPD ? rr : d0, v1 = d1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      v0 += __shfl_down(v0, o, 64);
+      if constexpr (NQ == 2) v1 += __shfl_down(v1, o, 64);
+    }
+    if (lane == 0) {
+      red[sg][0] = v0;
+      red[sg][1] = v1;
+    }
+    __syncthreads();
+    if (threadIdx.x < NQ) {
+      double v = 0.0;
+      for (int w = 0; w < NSEG; ++w) v += red[w][threadIdx.x];
+      partial[(long long)(pbase + logical_block()) * NQ + threadIdx.x] = v;
+    }
   }
 }
 

@@ -124,17 +124,21 @@ def smooth_bytes_varying(n: int, zero: bool) -> float:
     return smooth_bytes(n, 8, zero) + 12 * n
 
 
-def smooth0_launch_bytes_varying(n0: int, nu_pre=1, nu_post=1) -> float:
-    """Average algorithmic bytes of one finest-level half-sweep launch."""
+def smooth0_launch_bytes_varying(n0: int, nu_pre=1, nu_post=1, fused_update=False, dot_q=False) -> float:
+    """Average algorithmic bytes of one finest-level half-sweep launch (the
+    fused residual update adds the q read and the r write to the first pair,
+    the fused <z, q> the q read to the last, as in smooth0_launch_bytes)."""
     launches = 2 * nu_pre + 2 * nu_post
     total = smooth_bytes_varying(n0, True) + (launches - 1) * smooth_bytes_varying(n0, False)
+    total += (16 * n0 if fused_update else 0) + (8 * n0 if dot_q else 0)
     return total / launches
 
 
 def pcg_iteration_bytes_varying(n0: int, levels: int, nu_coarse=1, flexible=True, nu_pre=1,
-                                nu_post=1) -> float:
-    """One PCG iteration on a varying grid (separate residual update and dots)."""
-    total = cg_bytes(n0, flexible) + 8 * n0 + vcycle_bytes(n0, levels, 8, nu_pre, nu_post, nu_coarse)
+                                nu_post=1, fused_update=False, fused_dots=False) -> float:
+    """One PCG iteration on a varying grid (cg_bytes for the fused forms)."""
+    total = (cg_bytes(n0, flexible, fused_update, fused_dots) + 8 * n0 +
+             vcycle_bytes(n0, levels, 8, nu_pre, nu_post, nu_coarse))
     n = n0
     for l in range(levels):
         if l == levels - 1:
@@ -147,24 +151,26 @@ def pcg_iteration_bytes_varying(n0: int, levels: int, nu_coarse=1, flexible=True
     return total
 
 
-def smooth0_launch_bytes_varying_hybrid(n0: int) -> float:
+def smooth0_launch_bytes_varying_hybrid(n0: int, fused_update=False, dot_q=False) -> float:
     """Average algorithmic bytes of a finest-level half-sweep launch of the
     mixed-precision V-cycle on a varying grid, per unknown of the level: the
     FP32 pre-sweeps read the FP64 residual (4 B), write FP32 u (2 B), the second
     reads the other colour (2 B), and each reads its colour's FP32 faces, 1/p
     and T/p (6 B); the FP64 post-sweeps read r (4 B) and the other colour of z
     (4 B), write z (4 B) and read the FP64 fields (12 B):
-    (12 + 14 + 24 + 24) / 4 = 18.5 B."""
-    return (12 + 14 + 24 + 24) * n0 / 4
+    (12 + 14 + 24 + 24) / 4 = 18.5 B; the fused forms add their q reads and r
+    writes as in smooth0_launch_bytes_hybrid."""
+    return ((12 + 14 + 24 + 24) + (16 if fused_update else 0) + (8 if dot_q else 0)) * n0 / 4
 
 
-def pcg_iteration_bytes_varying_hybrid(n0: int, levels: int, nu_coarse=1, nu_pre=1, nu_post=1) -> float:
+def pcg_iteration_bytes_varying_hybrid(n0: int, levels: int, nu_coarse=1, nu_pre=1, nu_post=1,
+                                       fused_update=False, fused_dots=False) -> float:
     """One flexible PCG iteration on a varying grid with the mixed-precision
     V-cycle (separate residual update and dots): the FP64 CG work with the
     operator step's faces, the hybrid V-cycle, and the fields of every
     half-sweep (6 B per unknown of the level in FP32, 12 B for the FP64 finest
     post-sweeps) and restriction (2 B)."""
-    total = cg_bytes(n0, True) + 8 * n0 + hybrid_vcycle_bytes(n0, levels, nu_coarse)
+    total = cg_bytes(n0, True, fused_update, fused_dots) + 8 * n0 + hybrid_vcycle_bytes(n0, levels, nu_coarse)
     n = n0
     for l in range(levels):
         if l == levels - 1:

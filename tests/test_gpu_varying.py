@@ -61,7 +61,11 @@ SHAPES = [((64, 32, 24), 3), ((34, 10, 100), 1), ((68, 12, 100), 2), ((6, 1, 5),
 def test_varying_operator_and_levels_match_oracle(ell, orc, shape, levels):
     nx, ny, nz = shape
     g, G, _ = pair(ell, orc, nx, ny, nz, seed=nx + nz, n_levels=levels)
-    assert G.varying and not any(G.features.values())
+    f = G.features
+    assert G.varying and not (f["tiled_smooth"] or f["fused_prolong"] or f["tiled_ends"] or f["coarse_prolong"])
+    # the fused CG forms ride on the per-column sweep where it applies
+    seg3 = nx > 1 and ny > 1 and nz <= 256 and G.levels >= 2
+    assert f["fused_dots"] == seg3 and f["fused_update"] == seg3, (shape, f)
     rng = np.random.default_rng(nz)
     x = rng.standard_normal(g.shape)
     y = host(G.apply_A(dev(x)))
@@ -130,6 +134,48 @@ def test_varying_solves_match_oracle(ell, orc, shape, levels):
     assert st.status == 0
     u_k, st_k = orc.mg_solve(g, p.f, rtol=0.0, maxiter=st.iters)
     assert rel(host(u), u_k) <= 1e-10
+
+
+@pytest.mark.parametrize("shape,levels,precision", [((64, 32, 24), 3, "fp64"), ((96, 32, 64), 3, "fp64"),
+                                                    ((68, 12, 100), 2, "fp64"), ((136, 24, 40), 0, "fp64"),
+                                                    ((64, 64, 32), 0, "fp32"), ((96, 32, 64), 3, "fp32")])
+def test_varying_fused_forms_equal_separate_passes(ell, orc, shape, levels, precision):
+    """With per-column coefficients the CG residual update rides on the first
+    pre-smoothing pair and the dots on the last post-smoothing pair
+    (k_smooth_seg3's UPD and DOT forms): the same iteration counts and
+    iterates within 1e-10 as the separate passes, for both betas in FP64 and
+    the flexible one in mixed precision, the same state at an iteration limit,
+    and (FP64) the oracle's solution.  (68, 12): eight ragged k-segments;
+    (136, 24): a partial 64-column block."""
+    nx, ny, nz = shape
+    p = I.paper_graded_problem(f"varf{nx}", nx, ny, nz, 1e-2, 41 + nz, 42 + nz)
+    p.n_levels = levels
+    p.lambda2_3d = I.lambda2_3d(nx, ny, p.lambda2, 0.8, 43 + nz)
+    betas = (True, False) if precision == "fp64" else (True,)
+    res = {}
+    for fused in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_FUSED_DOT, fused)
+        ell.set_tuning(ell.ELL_TUNE_FUSED_UPDATE, fused)
+        try:
+            G = ell.Grid.from_problem(p, precision=precision)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_FUSED_DOT, 1)
+            ell.set_tuning(ell.ELL_TUNE_FUSED_UPDATE, 1)
+        assert G.features["fused_dots"] == bool(fused) and G.features["fused_update"] == bool(fused)
+        for flexible in betas:
+            u, st = G.pcg_solve(dev(p.f), rtol=1e-8, flexible=flexible)
+            assert st.status == 0
+            ul, stl = G.pcg_solve(dev(p.f), rtol=1e-14, maxiter=3, flexible=flexible)
+            assert stl.status == ell.ELL_NOT_CONVERGED and stl.iters == 3
+            res[fused, flexible] = (host(u), st, host(ul), stl)
+        G.close()
+    for flexible in betas:
+        (u1, s1, l1, t1), (u0, s0, l0, t0) = res[1, flexible], res[0, flexible]
+        assert s1.iters == s0.iters
+        assert rel(u1, u0) <= 1e-10 and rel(l1, l0) <= 1e-10
+        assert abs(t1.r_norm / t0.r_norm - 1) <= 1e-8
+        if precision == "fp64":
+            check_solve(orc, orc.Grid.from_problem(p), p.f, u1, s1, 1e-8, flexible=flexible)
 
 
 def test_horizontally_constant_field_equals_the_plain_grid(ell, orc):
