@@ -178,6 +178,54 @@ def test_varying_fused_forms_equal_separate_passes(ell, orc, shape, levels, prec
             check_solve(orc, orc.Grid.from_problem(p), p.f, u1, s1, 1e-8, flexible=flexible)
 
 
+def colour_mask(nx, ny):
+    j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    return (i + j) % 2
+
+
+@pytest.mark.parametrize("shape,levels", [((64, 32, 24), 3), ((68, 12, 100), 2), ((6, 1, 5), 1),
+                                          ((16, 8, 300), 2), ((40, 24, 200), 3)])
+def test_varying_sweep_and_restriction_skip_poison(ell, orc, shape, levels):
+    """Colour discipline with per-column coefficients (rho = 1): NaN in the
+    old values of the colour being swept never reaches the output, which
+    equals the sweep from zeroed own-colour values bitwise, on every level and
+    for both colours (k_smooth_seg3; the column kernel on the one-wide grid
+    and for 300 levels); the restriction right after a colour-1 sweep never
+    reads colour 1 of the right-hand side (k_resid_restrict_bz with faces)."""
+    nx, ny, nz = shape
+    g, G, _ = pair(ell, orc, nx, ny, nz, seed=5 * nx + nz, n_levels=levels)
+    rng = np.random.default_rng(3 * nx + nz)
+    gl = g
+    for lv in range(G.levels):
+        mask = colour_mask(gl.nx, gl.ny)
+        b = rng.standard_normal(gl.shape) * (gl.hx * gl.hy * gl.dz)[:, None, None]
+        u = rng.standard_normal(gl.shape) * 1e-3
+        bs = G.to_split(lv, dev(b))
+        for c in (0, 1):
+            own = np.broadcast_to(mask == c, gl.shape)
+            out = []
+            for start in (np.where(own, 0.0, u), np.where(own, np.nan, u)):
+                us = G.to_split(lv, dev(start))
+                G.level_smooth(lv, c, bs, us)
+                out.append(host(G.from_split(lv, us, zeros(gl.shape))))
+            assert np.all(np.isfinite(out[1])), (lv, c)
+            np.testing.assert_array_equal(out[1], out[0])
+        if lv + 1 < G.levels:
+            gc = gl.coarse()
+            black = np.broadcast_to(mask == 1, gl.shape)
+            us = G.level_empty(lv)
+            G.level_smooth(lv, 0, bs, us, zero_init=True)
+            G.level_smooth(lv, 1, bs, us)
+            res = []
+            for bb in (b, np.where(black, np.nan, b)):
+                bc = G.level_empty(lv + 1)
+                G.level_resid_restrict(lv, G.to_split(lv, dev(bb)), us, bc, black_zero=True)
+                res.append(host(G.from_split(lv + 1, bc, zeros(gc.shape))))
+            assert np.all(np.isfinite(res[1])), lv
+            np.testing.assert_array_equal(res[1], res[0])
+            gl = gc
+
+
 def test_horizontally_constant_field_equals_the_plain_grid(ell, orc):
     p = I.paper_graded_problem("const3d", 64, 32, 40, 1e-2, 5, 6)
     G0 = ell.Grid.from_problem(p)
