@@ -3,7 +3,8 @@
 // Every stage of a CG iteration (the fused operator step, the residual
 // update, each V-cycle half-sweep / restriction / prolongation, the dots and
 // the scalar updates) is one grouped launch covering every active grid: a
-// block looks up its grid in a stage table (binary search over block offsets)
+// block looks up its grid in a stage table (a ballot over the entries' first
+// blocks)
 // and runs the same device body as the single-grid kernel on that grid's
 // arrays.  Grids of different depth share the launches of the levels they
 // have; each grid carries its own CG state on the device, so converged grids
