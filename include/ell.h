@@ -128,12 +128,14 @@ int ell_grid_destroy(ell_grid *g);
  * desc->precision is ELL_FP64 or ELL_FP32_PRECOND (ELL_BF16COEF returns
  * ELL_ERR_INVALID).  The grid works with every grid entry point (ell_apply_A,
  * ell_vcycle, ell_pcg_solve, ell_mg_solve, the level entry points); its sweeps
- * run k-segmented column kernels and none of the fused forms
- * (ell_grid_features reports none).  It holds three FP64 fields per level
+ * run k-segmented column kernels, which also carry the fused CG residual
+ * update and dots (ELL_FEAT_FUSED_UPDATE, ELL_FEAT_FUSED_DOTS); the LDS-tiled
+ * sweeps, the fused prolongation and the tiled ends do not apply.  It holds
+ * three FP64 fields per level
  * (faces, 1/p_k, T_{k+1/2}/p_k) more than ell_grid_bytes reports, and with
- * ELL_FP32_PRECOND their FP32 copies too, which every V-cycle sweep reads
- * (the FP64 finest post-smoothing included); the operator step and the
- * solve's ends read the FP64 faces.  The batch engine does not take such
+ * ELL_FP32_PRECOND their FP32 copies too, which the FP32 sweeps and
+ * restrictions read (the FP64 finest post-smoothing reads the FP64 fields);
+ * the operator step and the solve's ends read the FP64 faces.  The batch engine does not take such
  * grids.  Synchronous; ELL_ERR_INVALID for a bad descriptor or field. */
 int ell_grid_create_varying(const ell_grid_desc *desc, const double *lambda2_3d, ell_grid **out);
 
