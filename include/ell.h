@@ -158,7 +158,11 @@ int ell_grid_levels(const ell_grid *g);
  * runtime refused that launch, the sweeps then run one by one),
  * ELL_FEAT_COARSE_PROLONG (on at least one coarse level the bilinear
  * prolongation rides on the first post-smoothing sweep, as the finest one
- * does: FP64, rho = 1, LDS-tiled sweeps; any beta).  They change
+ * does: FP64, rho = 1, LDS-tiled sweeps; any beta), ELL_FEAT_COARSE_PAIR (each
+ * of the coarsest level's sweep pairs runs in one launch: every block sweeps
+ * colour 0 on its 8 x 8 tile and the ring around it, keeps that in LDS and
+ * sweeps colour 1 on the tile; rho = 1, constant coefficients, nx and ny
+ * multiples of 8).  They change
  * where bytes move and how many launches there are, not what is computed;
  * a benchmark's byte model reads them.  Returns ELL_OK or a negative error. */
 enum {
@@ -168,7 +172,8 @@ enum {
   ELL_FEAT_FUSED_PROLONG = 8,
   ELL_FEAT_TILED_ENDS = 16,
   ELL_FEAT_COARSE_TAIL = 32,
-  ELL_FEAT_COARSE_PROLONG = 64
+  ELL_FEAT_COARSE_PROLONG = 64,
+  ELL_FEAT_COARSE_PAIR = 128
 };
 int ell_grid_features(const ell_grid *g, int32_t *mask);
 
@@ -316,7 +321,9 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * horizontal directions, segments of at most 16 levels); 0 (default) launches
  * them one by one (the same values, bitwise; on MI355X a barrier across the
  * eight XCDs costs more than a kernel boundary, so one launch per half-sweep
- * is faster). */
+ * is faster); COARSE_PAIR 1 (default) runs each of those sweep pairs in one
+ * launch where ELL_FEAT_COARSE_PAIR applies, 0 as two half-sweeps (the same
+ * values, bitwise). */
 enum {
   ELL_TUNE_PLANE_PAD = 0,
   ELL_TUNE_COLOUR_PAD = 1,
@@ -328,7 +335,8 @@ enum {
   ELL_TUNE_FUSED_UPDATE = 7,
   ELL_TUNE_FUSED_PROLONG = 8,
   ELL_TUNE_TILED_ENDS = 9,
-  ELL_TUNE_COARSE_TAIL = 10
+  ELL_TUNE_COARSE_TAIL = 10,
+  ELL_TUNE_COARSE_PAIR = 11
 };
 int ell_set_tuning(int key, int value);
 

@@ -177,6 +177,7 @@ struct ell_grid {
   int fused_prolong = 0;                // the first post-smoothing sweep applies the finest correction
   int tiled_ends = 0;                   // a solve's start and end run on the operator step's LDS tiles
   int coarse_tail = 0;                  // the coarsest level's sweeps in one cooperative launch
+  int coarse_pair = 0;                  // the coarsest level's sweep pairs one launch each
   double *partial = nullptr;
   long long partial_cap = 0;
   PcgState *st = nullptr;
@@ -218,6 +219,7 @@ int g_fused_dot = 1;    // 1: the last post-smoothing half-sweeps form the CG do
 int g_fused_update = 1; // 1: the first pre-smoothing pair updates the CG residual
 int g_fused_prolong = 1;  // 1: the first post-smoothing sweep applies the finest correction
 int g_tiled_ends = 1;     // 1: a solve's start and end on LDS tiles where both horizontal directions exist
+int g_coarse_pair = 1;    // 1: each coarsest-level sweep pair in one launch (k_coarse_pair) where it applies
 int g_coarse_tail = 0;    // 1: the coarsest level's sweeps in one cooperative launch where it applies
                           //    (off by default: measured slower than one launch per half-sweep)
 
@@ -1050,6 +1052,42 @@ bool pro_path(const ell_grid *g, int dot);
 // with the segmented one (segments of at most 16 levels).  Returns false if it
 // does not apply or the launch was refused (the caller then launches the
 // sweeps one by one, and the grid stops trying).
+// The coarsest level's sweep pairs one launch each (k_coarse_pair): rho = 1,
+// constant coefficients, both horizontal directions, nx and ny multiples of 8,
+// the level's own segment count (8 or 16) so the columns are split as the
+// half-sweep kernels split them.
+bool coarse_pair_ok(const ell_grid *g, int l) {
+  const Geo &G = g->lev[l].geo;
+  const int Ls = seg_len(G.nz, G.nseg);
+  return g->coarse_pair && l == g->L - 1 && !g->varying && g->d.rho == 1.0 && G.has_x && G.has_y &&
+         G.nx % 8 == 0 && G.ny % 8 == 0 && ((G.nseg == 16 && Ls <= 16) || (G.nseg == 8 && Ls <= 32));
+}
+
+template <typename R>
+int launch_coarse_pair(ell_grid *g, int l, const R *b, R *u, bool zero, const int *done, hipStream_t s) {
+  const Geo &G = g->lev[l].geo;
+  const R *tab = (const R *)g->lev[l].tab;
+  const int Ls = seg_len(G.nz, G.nseg);
+  const int nb = ((G.nx / 8) * (G.ny / 8) + 7) / 8 * 8;  // a multiple of 8 (logical_block)
+  auto go = [&](auto seg, auto nseg) {
+    constexpr int SEG = decltype(seg)::value, NSEG = decltype(nseg)::value;
+    if (zero) k_coarse_pair<R, true, SEG, NSEG><<<nb, NSEG * 64, 0, s>>>(G, tab, b, u, done);
+    else k_coarse_pair<R, false, SEG, NSEG><<<nb, NSEG * 64, 0, s>>>(G, tab, b, u, done);
+  };
+  using I8 = std::integral_constant<int, 8>;
+  using I16 = std::integral_constant<int, 16>;
+  using I32 = std::integral_constant<int, 32>;
+  if (G.nseg == 16) {
+    if (Ls <= 8) go(I8{}, I16{});
+    else go(I16{}, I16{});
+  } else {
+    if (Ls <= 8) go(I8{}, I8{});
+    else if (Ls <= 16) go(I16{}, I8{});
+    else go(I32{}, I8{});
+  }
+  return check_launch("k_coarse_pair");
+}
+
 template <typename R>
 bool coarse_tail_applies(const ell_grid *g, int l) {
   const Geo &G = g->lev[l].geo;
@@ -1133,6 +1171,8 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
     const int l = L - 1;
     if (g->d.nu_coarse > 0 && launch_coarse_tail<R>(g, l, B(l), U(l), done, s)) {
       // all coarsest-level sweeps in one launch
+    } else if (g->d.nu_coarse > 0 && coarse_pair_ok(g, l)) {
+      for (int it = 0; it < g->d.nu_coarse; ++it) CHK(launch_coarse_pair<R>(g, l, B(l), U(l), it == 0, done, s));
     } else if (g->d.nu_coarse > 0) {
       for (int it = 0; it < g->d.nu_coarse; ++it) {
         CHK(launch_smooth<R>(g, l, 0, it == 0, B(l), U(l), done, s));
@@ -1793,6 +1833,7 @@ static int grid_create(const ell_grid_desc *desc, bool batch_layout, ell_grid **
   g->fused_prolong = g_fused_prolong;
   g->tiled_ends = (g_tiled_ends && desc->nx > 1 && desc->ny > 1) ? 1 : 0;
   g->coarse_tail = g_coarse_tail && !batch_layout;
+  g->coarse_pair = g_coarse_pair;
   g->batch_layout = batch_layout;
   if (lam3) {  // per-column coefficients: no LDS-tiled sweeps (tile_ok), ends or fused prolongation
     g->varying = true;
@@ -1915,8 +1956,10 @@ int ell_grid_levels(const ell_grid *g) {
 int ell_grid_features(const ell_grid *g, int32_t *mask) {
   if (!g || !mask) return fail(ELL_ERR_INVALID, "NULL argument");
   int m = 0;
-  if (g->prec == ELL_FP64 ? coarse_tail_applies<double>(g, g->L - 1) : coarse_tail_applies<float>(g, g->L - 1))
-    m |= ELL_FEAT_COARSE_TAIL;
+  const bool tail =
+      g->prec == ELL_FP64 ? coarse_tail_applies<double>(g, g->L - 1) : coarse_tail_applies<float>(g, g->L - 1);
+  if (tail) m |= ELL_FEAT_COARSE_TAIL;
+  else if (g->d.nu_coarse > 0 && coarse_pair_ok(g, g->L - 1)) m |= ELL_FEAT_COARSE_PAIR;
   if (g->prec == ELL_FP64) {
     if (tile_ok(g, 0)) m |= ELL_FEAT_TILED_SMOOTH;
     if (fused_dot_path<double>(g)) m |= ELL_FEAT_FUSED_DOTS;
@@ -2329,6 +2372,10 @@ int ell_set_tuning(int key, int value) {
     case ELL_TUNE_COARSE_TAIL:
       if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "the coarse tail is 0 or 1");
       g_coarse_tail = value;
+      return ELL_OK;
+    case ELL_TUNE_COARSE_PAIR:
+      if (value != 0 && value != 1) return fail(ELL_ERR_INVALID, "the coarse sweep pairs are 0 or 1");
+      g_coarse_pair = value;
       return ELL_OK;
     default: return fail(ELL_ERR_INVALID, "unknown tuning key %d", key);
   }

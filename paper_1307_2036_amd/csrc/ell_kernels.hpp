@@ -756,6 +756,135 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_seg3(Geo L, const R *__res
 }
 
 // -------------------------------------------------------------------------
+// One sweep pair of the coarsest level (colour 0, then colour 1, rho = 1;
+// Alg. "Multigrid V-cycle", coarsest-level smoothing) in one launch.  A block
+// owns an 8 x 8 tile of columns.  Phase A sweeps colour 0 on the tile and the
+// ring of columns around it (50 columns, lane = column), from the old colour-1
+// values; the ring's columns belong to neighbouring tiles, which compute the
+// same values from the same operands, so the block needs nothing from them.
+// The results go to LDS (and, for the tile's own columns, to memory).  Phase
+// B sweeps the tile's 32 colour-1 columns with their colour-0 neighbours from
+// LDS.  Both phases take the segmented column solve of smooth_seg_body and
+// the tiled sweep (the same segments, recurrences, joins and operand order),
+// so the result equals two half-sweep launches bitwise, with one launch
+// boundary instead of two.  ZERO: the first pair of a V-cycle's coarsest
+// solve, from u = 0 (phase A then has no neighbour terms).  Needs nx and ny
+// multiples of 8, both horizontal directions, nz <= SEG * NSEG.
+// Region coordinates (a, b) are relative to the tile's corner (i0, j0), both
+// multiples of 8, so a column (a, b) has colour (a + b) & 1:
+//   phase A lane l < 50: b = l / 5 - 1, a = (b odd ? -1 : 0) + 2 (l % 5)
+//   phase B lane l < 32: b = l / 4,     a = (b odd ? 0 : 1) + 2 (l % 4)
+// -------------------------------------------------------------------------
+__device__ __forceinline__ int pair_lane_a(int a, int b) { return (b + 1) * 5 + ((a - ((b & 1) ? -1 : 0)) >> 1); }
+
+template <typename R, bool ZERO, int SEG, int NSEG>
+__global__ __launch_bounds__(NSEG * 64) void k_coarse_pair(Geo L, const R *__restrict__ tab,
+                                                           const R *__restrict__ b, R *__restrict__ u,
+                                                           const int *__restrict__ done) {
+  __shared__ R xch[NSEG][kSegCols];
+  __shared__ R cu[SEG * NSEG][kSegCols];  // phase A's colour-0 values: [level][lane]
+  if (is_done(done)) return;
+  const int tiles_x = L.nx >> 3, lb = logical_block();
+  if (lb >= tiles_x * (L.ny >> 3)) return;  // whole blocks: no barrier is skipped
+  const int lane = threadIdx.x & 63;
+  const int sg = wave_id();
+  const int i0 = (lb % tiles_x) << 3, j0 = (lb / tiles_x) << 3;
+  const int nz = L.nz, Ls = seg_len(nz, NSEG);
+  const int k0 = min(sg * Ls, nz), k1 = min(k0 + Ls, nz), len = k1 - k0;
+  const long long H = L.S, cs = L.cs;
+  const R *__restrict__ tx = tab + TX * L.P;
+  const R *__restrict__ ty = tab + TY * L.P;
+  const R *__restrict__ tz = tab + TZ * L.P;
+  const R *__restrict__ ip = tab + TIP * L.P;
+  const R *__restrict__ cf = tab + TCF * L.P;
+  const R *__restrict__ pf = tab + TPF * L.P;
+  const R *__restrict__ qb = tab + TQB * L.P;
+
+  // ---- phase A: colour 0 on the tile and its ring
+  {
+    const bool valid = lane < 50;
+    const int l = valid ? lane : 0;
+    const int bb = l / 5 - 1, aa = ((bb & 1) ? -1 : 0) + 2 * (l % 5);
+    const int i = wrapi(i0 + aa, L.nx), j = wrapi(j0 + bb, L.ny);
+    const long long m = col_m(L, i, j);
+    const Nbr nb = neighbours(L, i, j);
+    const R *__restrict__ b0 = b + m;
+    const R *__restrict__ u1 = u + cs;
+    R y[SEG];
+    R prev = R(0);
+#pragma unroll
+    for (int c0 = 0; c0 < SEG; c0 += 8) {
+      if (c0 < len) {
+        R g[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int k = min(k0 + c0 + t, k1 - 1);
+          const long long o = (long long)k * H;
+          R v = b0[o];
+          if (!ZERO) {
+            v = v + tx[k] * (u1[nb.w + o] + u1[nb.e + o]);
+            v = v + ty[k] * (u1[nb.s + o] + u1[nb.n + o]);
+          }
+          g[t] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          if (c0 + t < len) {
+            const int k = k0 + c0 + t;
+            prev = (g[t] + tz[k] * prev) * ip[k];
+            y[c0 + t] = prev;
+          }
+        }
+      }
+    }
+    seg_join_store<R, ZERO, true, false, SEG, NSEG>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf, qb, valid,
+                                                    &cu[0][lane], kSegCols, R(1));
+    // the tile's own columns to memory (this lane wrote them: no barrier)
+    if (valid && aa >= 0 && aa < 8 && bb >= 0 && bb < 8) {
+      R *__restrict__ ow = u + m;
+      for (int k = k0; k < k1; ++k) ow[(long long)k * H] = cu[k][lane];
+    }
+  }
+  __syncthreads();
+  // ---- phase B: colour 1 on the tile
+  {
+    const bool valid = lane < 32;
+    const int l = valid ? lane : 0;
+    const int bb = l >> 2, aa = ((bb & 1) ? 0 : 1) + 2 * (l & 3);
+    const long long m = col_m(L, i0 + aa, j0 + bb);
+    const int lw = pair_lane_a(aa - 1, bb), le = pair_lane_a(aa + 1, bb);
+    const int ls = pair_lane_a(aa, bb - 1), ln = pair_lane_a(aa, bb + 1);
+    const R *__restrict__ b1 = b + cs + m;
+    R y[SEG];
+    R prev = R(0);
+#pragma unroll
+    for (int c0 = 0; c0 < SEG; c0 += 8) {
+      if (c0 < len) {
+        R g[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const int k = min(k0 + c0 + t, k1 - 1);
+          R v = b1[(long long)k * H];
+          v = v + tx[k] * (cu[k][lw] + cu[k][le]);
+          v = v + ty[k] * (cu[k][ls] + cu[k][ln]);
+          g[t] = v;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          if (c0 + t < len) {
+            const int k = k0 + c0 + t;
+            prev = (g[t] + tz[k] * prev) * ip[k];
+            y[c0 + t] = prev;
+          }
+        }
+      }
+    }
+    seg_join_store<R, false, true, false, SEG, NSEG>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf, qb, valid,
+                                                     u + cs + m, H, R(1));
+  }
+}
+
+// -------------------------------------------------------------------------
 // The same FP64 half-sweep with rho = 1 after the first sweep, with the other
 // colour staged in LDS (FINE: the finest level, streaming accesses).  Five
 // 64-lane loads per level (b and four neighbours) keep the texture units near

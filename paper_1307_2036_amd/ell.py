@@ -174,10 +174,12 @@ ELL_TUNE_FUSED_UPDATE = 7
 ELL_TUNE_FUSED_PROLONG = 8
 ELL_TUNE_TILED_ENDS = 9
 ELL_TUNE_COARSE_TAIL = 10
+ELL_TUNE_COARSE_PAIR = 11
 ELL_FEAT_TILED_SMOOTH, ELL_FEAT_FUSED_DOTS, ELL_FEAT_FUSED_UPDATE, ELL_FEAT_FUSED_PROLONG = 1, 2, 4, 8
 ELL_FEAT_TILED_ENDS = 16
 ELL_FEAT_COARSE_TAIL = 32
 ELL_FEAT_COARSE_PROLONG = 64
+ELL_FEAT_COARSE_PAIR = 128
 
 
 def set_tuning(key: int, value: int) -> None:
@@ -282,6 +284,7 @@ class Grid:
                          "fused_update": bool(m.value & ELL_FEAT_FUSED_UPDATE),
                          "fused_prolong": bool(m.value & ELL_FEAT_FUSED_PROLONG),
                          "coarse_prolong": bool(m.value & ELL_FEAT_COARSE_PROLONG),
+                         "coarse_pair": bool(m.value & ELL_FEAT_COARSE_PAIR),
                          "tiled_ends": bool(m.value & ELL_FEAT_TILED_ENDS),
                          "coarse_tail": bool(m.value & ELL_FEAT_COARSE_TAIL)}
 

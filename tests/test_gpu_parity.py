@@ -430,6 +430,35 @@ def test_coarse_prolongation_in_sweep_is_bitwise(ell, orc, shape, mg):
     assert rel(out[0], orc.vcycle(g, r)) <= 1e-11
 
 
+@pytest.mark.parametrize("shape,mg,precision", [
+    ((128, 128, 128), dict(n_levels=5, nu_coarse=5), "fp64"),  # coarsest 8 x 8: the ring wraps onto the tile
+    ((256, 128, 128), dict(n_levels=4, nu_coarse=5), "fp64"),  # 32 x 16, 16 segments of 8 levels
+    ((128, 64, 200), dict(n_levels=3, nu_coarse=3), "fp64"),   # 16 segments of 13 levels (ragged)
+    ((64, 64, 96), dict(n_levels=3, nu_coarse=2), "fp64"),     # 8 segments of 12 levels
+    ((64, 64, 256), dict(n_levels=3, nu_coarse=1), "fp64"),    # 16 segments of 16 levels
+    ((64, 32, 128), dict(n_levels=3, nu_coarse=5), "fp32"),    # one tile row; the FP32 coarsest level
+])
+def test_coarse_sweep_pairs_are_bitwise(ell, orc, shape, mg, precision):
+    """Each coarsest-level sweep pair in one launch (k_coarse_pair: colour 0
+    on the tile and its ring kept in LDS, then colour 1 on the tile) gives
+    the V-cycle of two half-sweep launches bitwise, and (FP64) the oracle's."""
+    g = grid_for(orc, shape, **mg)
+    r = np.random.default_rng(13).standard_normal(g.shape) * (g.hx * g.hy * g.dz)[:, None, None]
+    out = []
+    for paired in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_COARSE_PAIR, paired)
+        try:
+            G = gpu_grid(ell, g, precision)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_COARSE_PAIR, 1)
+        assert G.features["coarse_pair"] == bool(paired), G.features
+        out.append(host(G.vcycle(dev(r))))
+        G.close()
+    assert np.array_equal(out[0], out[1])
+    if precision == "fp64":
+        assert rel(out[0], orc.vcycle(g, r)) <= 1e-11
+
+
 @pytest.mark.parametrize("nx,ny,nz,levels", [(64, 16, 32, 3), (68, 12, 100, 2), (136, 8, 40, 2),
                                            (64, 64, 48, 4)])
 def test_fused_prolongation_equals_prolongation_pass(ell, orc, nx, ny, nz, levels):
