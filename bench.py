@@ -572,7 +572,7 @@ def sampled_steps(steps):
 
 
 def varying_summary(a, steps, precision="fp64", p=None):
-    """The 512 x 512 x 128 graded problem of config 1 with its lambda^2 profile
+    """The 512 x 512 x 128 graded problem (four levels, five coarse sweeps) with its lambda^2 profile
     modulated horizontally (every column its own vertical coefficients), four
     levels, five coarse sweeps, from u0 = 0 to 1e-5: FP64 with the printed beta,
     or the mixed-precision V-cycle (FP32 per-column fields) in flexible CG; the

@@ -232,7 +232,7 @@ def paper_graded_problem(name: str, nx: int, ny: int, nz: int, omega2: float, se
 
 def varying_problem(nx: int = 512, nz: int = 128, n_levels: int = 4, nu_coarse: int = 5,
                     sigma_h: float = 0.5, with_f: bool = True) -> Problem:
-    """The 512 x 512 x 128 graded problem of config 1 with its lambda^2 profile
+    """The 512 x 512 x 128 graded problem (four levels, five coarse sweeps) with its lambda^2 profile
     modulated horizontally (lambda2_3d, sigma_h = 0.5): every column has its own
     vertical coefficients."""
     p = graded_problem(f"varying_{nx}x{nx}x{nz}_L{n_levels}", nx, nz, 1e-2, seed_for(5),

@@ -252,7 +252,7 @@ def test_varying_grid_rejects_bad_input(ell, orc):
 
 @pytest.mark.slow
 def test_varying_fullsize_solve(ell, orc):
-    """512 x 512 x 128, the graded profile of config 1 modulated horizontally,
+    """512 x 512 x 128, the graded lambda^2 profile of the benchmark solve modulated horizontally,
     four levels, five coarse sweeps: the iterates at the GPU's stopping count
     against the oracle's (printed beta)."""
     p = I.varying_problem()
