@@ -301,7 +301,8 @@ def bench_c1(a):
     launch_bytes = (perfmodel.smooth0_launch_bytes(n, 8, fused_update=feat["fused_update"], dot_q=dot_q,
                                                    fused_prolong=fpro)
                     if a.precision == "fp64" else
-                    perfmodel.smooth0_launch_bytes_hybrid(n, fused_update=feat["fused_update"], dot_q=dot_q))
+                    perfmodel.smooth0_launch_bytes_hybrid(n, fused_update=feat["fused_update"], dot_q=dot_q,
+                                                          fused_prolong=feat["fused_prolong"]))
     avg_ms = float(t_s.mean())
     achieved = launch_bytes / (avg_ms * 1e-3) / 1e9
     # the CG operator step reads z (and p_old after the first iteration) and writes
@@ -314,7 +315,8 @@ def bench_c1(a):
     solves = a.steps / elapsed
     it_bytes = perfmodel.pcg_iteration_bytes(n, G.levels, e, nu_coarse=p.nu_coarse, flexible=flexible,
                                              fused_update=feat["fused_update"], fused_dots=feat["fused_dots"],
-                                             fused_prolong=fpro, coarse_prolong=feat["coarse_prolong"])
+                                             fused_prolong=fpro if e == 8 else feat["fused_prolong"],
+                                             coarse_prolong=feat["coarse_prolong"])
     lat_ms = np.array(lat) * 1e3
     out = {
         "metric": METRIC,
@@ -443,9 +445,12 @@ def c2_sweep(steps=3, precision="bf16coef"):
                 keep = (u.cpu().numpy(), st.iters)
             ut = torch.zeros_like(f)
             G.pcg_solve(f, ut, rtol=1e-12, maxiter=300)
-            per[name] = dict(iters=st.iters, s=t, tight=ut, levels=G.levels)
+            per[name] = dict(iters=st.iters, s=t, tight=ut, levels=G.levels, feat=G.features)
             G.close()
-        mixed_bytes = perfmodel.pcg_iteration_bytes(p.n, per[precision]["levels"], 4) * per[precision]["iters"]
+        fm = per[precision]["feat"]
+        mixed_bytes = perfmodel.pcg_iteration_bytes(p.n, per[precision]["levels"], 4, fused_update=fm["fused_update"],
+                                                    fused_dots=fm["fused_dots"],
+                                                    fused_prolong=fm["fused_prolong"]) * per[precision]["iters"]
         err = float(torch.linalg.vector_norm(per[precision]["tight"] - per["fp64"]["tight"]) /
                     torch.linalg.vector_norm(per["fp64"]["tight"]))
         rows.append({"omega2": omega2, "levels": per[precision]["levels"],

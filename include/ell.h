@@ -151,7 +151,8 @@ int ell_grid_levels(const ell_grid *g);
  * products ride on the last two post-smoothing half-sweeps),
  * ELL_FEAT_FUSED_UPDATE (the residual update r -= alpha q rides on the first
  * pre-smoothing pair), ELL_FEAT_FUSED_PROLONG (the finest prolongation rides
- * on the first post-smoothing sweep, for solves with the printed beta),
+ * on the first post-smoothing sweep: FP64 grids for solves with the printed
+ * beta, mixed-precision grids with either beta),
  * ELL_FEAT_TILED_ENDS (a solve's start, r = V f - A u0, and end, the final
  * update and true residual, run on LDS tiles), ELL_FEAT_COARSE_TAIL (the
  * coarsest level's sweeps run in one cooperative launch; cleared if the
@@ -308,7 +309,11 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * to the colour-0 values it reads instead of a prolongation pass (the
  * colour-0 sweep that follows overwrites them), the colour-0 sweep then forming
  * <r, z> of both colours, and does the same on every coarse FP64 level with
- * LDS-tiled sweeps and rho = 1 (any beta; same values, bitwise); 0 always
+ * LDS-tiled sweeps and rho = 1 (any beta; same values, bitwise), and lets the
+ * mixed-precision V-cycle's first FP64 post-smoothing sweep of the finest
+ * level (colour 1, LDS-tiled, bilinear prolongation) read the FP32 colour-0
+ * values and the FP32 coarse correction and form the values the prolongation
+ * pass would write into the FP64 output (any beta; bitwise the same); 0 always
  * runs the prolongation pass; TILED_ENDS 1
  * (default) runs the start of a solve (us = u0, r = V f - A u0) and its end (u
  * = us + alpha p written plane-major, the true residual) on the LDS tiles of

@@ -1252,6 +1252,63 @@ bool hybrid_ok(const ell_grid *g) {
          ((G.nseg == 4 && seg_len(G.nz, 4) <= 64) || (G.nseg == 8 && seg_len(G.nz, 8) <= 16));
 }
 
+// The mixed-precision V-cycle's finest prolongation rides on the first FP64
+// post-smoothing sweep (colour 1): bilinear prolongation, the LDS-tiled FP64
+// sweep, eight k-segments of at most 16 levels or four of at most 32.  The
+// colour-0 sweep after it overwrites colour 0 of z without reading it.
+bool pro32_path(const ell_grid *g) {
+  const Geo &F = g->lev[0].geo;
+  const int Ls = seg_len(F.nz, F.nseg);
+  return g->prec != ELL_FP64 && g->fused_prolong && g->d.prolong == 0 && hybrid_ok(g) && tile_ok(g, 0) &&
+         ((F.nseg == 8 && Ls <= 16) || (F.nseg == 4 && Ls <= 32));
+}
+
+// The staged FP32 coarse values load in aligned pairs: coarse half-width,
+// colour and plane strides even, the array 8-byte aligned.
+bool pro32_pairs_ok(const Geo &C, const void *uc) {
+  return C.nx % 4 == 0 && C.cs % 2 == 0 && C.S % 2 == 0 && (reinterpret_cast<uintptr_t>(uc) & 7) == 0;
+}
+
+template <int SEG, int NSEG, int DOT>
+void launch_pro32(int nbt, hipStream_t s, const Geo &F, const Geo &C, const double *tab, const double *b1,
+                  const float *u0, double *z1, const float *uc, const int *done, double *partial, int pbase,
+                  const double *q1) {
+  if (pro32_pairs_ok(C, uc))
+    k_smooth_tile_pro32<SEG, NSEG, DOT, true><<<nbt, NSEG * 64, 0, s>>>(F, C, tab, b1, u0, z1, uc, done, partial,
+                                                                        pbase, q1);
+  else
+    k_smooth_tile_pro32<SEG, NSEG, DOT, false><<<nbt, NSEG * 64, 0, s>>>(F, C, tab, b1, u0, z1, uc, done, partial,
+                                                                         pbase, q1);
+}
+
+template <int SEG, int NSEG>
+void pro32_k(int dot, int nbt, hipStream_t s, const Geo &F, const Geo &C, const double *tab, const double *b1,
+             const float *u0, double *z1, const float *uc, const int *done, double *partial, const double *q1) {
+  if (dot == 2) launch_pro32<SEG, NSEG, 2>(nbt, s, F, C, tab, b1, u0, z1, uc, done, partial, 0, q1);
+  else if (dot == 1) launch_pro32<SEG, NSEG, 1>(nbt, s, F, C, tab, b1, u0, z1, uc, done, partial, 0, q1);
+  else launch_pro32<SEG, NSEG, 0>(nbt, s, F, C, tab, b1, u0, z1, uc, done, partial, 0, q1);
+}
+
+// The fused sweep of colour 1 (pro32_path checked): z1 from r1, the FP32
+// colour-0 values u32 and the coarse correction; with dot, the colour's
+// partial sums go to the first tile-count slots as launch_smooth_dot's.
+int pro32_sweep(ell_grid *g, const double *r, const float *u32, double *z, int dot, const int *done,
+                hipStream_t s) {
+  const Geo &F = g->lev[0].geo, &C = g->lev[1].geo;
+  const int Ls = seg_len(F.nz, F.nseg);
+  const int nbt = blocks8((long long)smooth_tiles(F) * kBlock);
+  const long long cs = F.cs;
+  const float *uc = (const float *)g->lev[1].u;
+  ProfScope ps(g, ELL_K_SMOOTH0, s);
+  if (F.nseg == 8)
+    pro32_k<16, 8>(dot, nbt, s, F, C, g->tab64_0, r + cs, u32, z + cs, uc, done, g->partial, g->q + cs);
+  else if (Ls <= 16)
+    pro32_k<16, 4>(dot, nbt, s, F, C, g->tab64_0, r + cs, u32, z + cs, uc, done, g->partial, g->q + cs);
+  else
+    pro32_k<32, 4>(dot, nbt, s, F, C, g->tab64_0, r + cs, u32, z + cs, uc, done, g->partial, g->q + cs);
+  return check_launch("k_smooth_tile_pro32");
+}
+
 int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipStream_t s, int dot = 0,
                   bool upd = false) {
   float *u32 = (float *)g->z32;
@@ -1265,7 +1322,8 @@ int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipS
   }
   CHK((launch_restrict<float, double>(g, 0, r, u32, (float *)g->lev[1].b, true, done, s)));
   CHK(vcycle_from<float>(g, 1, (const float *)g->lev[1].b, (float *)g->lev[1].u, done, s));
-  {
+  const bool pro = pro32_path(g);
+  if (!pro) {
     const Geo &F = g->lev[0].geo, &C = g->lev[1].geo;
     const int nb = seg_blocks(F.ncol0);
     ProfScope ps(g, ELL_K_PROLONG0, s);
@@ -1285,13 +1343,16 @@ int vcycle_hybrid(ell_grid *g, const double *r, double *z, const int *done, hipS
     CHK(check_launch("k_prolong_out"));
   }
   for (int it = 0; it < g->d.nu_post; ++it) {
+    const bool fused = pro && it == 0;  // colour 1 applies the coarse correction
     if (dot && it == g->d.nu_post - 1) {
       const int nt = dot_colour_slots(g, 1);
-      CHK(launch_smooth_dot(g, 1, r, z, g->tab64_0, dot, 0, done, s));
+      if (fused) CHK(pro32_sweep(g, r, u32, z, dot, done, s));
+      else CHK(launch_smooth_dot(g, 1, r, z, g->tab64_0, dot, 0, done, s));
       CHK(launch_smooth_dot(g, 0, r, z, g->tab64_0, dot, nt, done, s));
       continue;
     }
-    CHK(launch_smooth<double>(g, 0, 1, false, r, z, done, s, g->tab64_0));
+    if (fused) CHK(pro32_sweep(g, r, u32, z, 0, done, s));
+    else CHK(launch_smooth<double>(g, 0, 1, false, r, z, done, s, g->tab64_0));
     CHK(launch_smooth<double>(g, 0, 0, false, r, z, done, s, g->tab64_0));
   }
   return ELL_OK;
@@ -1972,6 +2033,7 @@ int ell_grid_features(const ell_grid *g, int32_t *mask) {
     if (tile_ok(g, 0)) m |= ELL_FEAT_TILED_SMOOTH;
     if (fused_dot_path<float>(g)) m |= ELL_FEAT_FUSED_DOTS;
     if (fused_update_path<float>(g)) m |= ELL_FEAT_FUSED_UPDATE;
+    if (pro32_path(g)) m |= ELL_FEAT_FUSED_PROLONG;
     if (g->tiled_ends) m |= ELL_FEAT_TILED_ENDS;
   }
   *mask = m;

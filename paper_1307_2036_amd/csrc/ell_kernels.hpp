@@ -927,11 +927,18 @@ constexpr int kCRow = 48;  // LDS row stride of the staged coarse values (40 use
 // stride even, its array 16-byte aligned): the staged coarse values come in
 // pairs of neighbouring same-colour columns, one 16-byte load per lane on 60
 // lanes instead of two 8-byte loads on 128.
+// TU (with PRO): element type of uo and uc.  TU = float is the mixed-precision
+// V-cycle's finest level: FP32 colour-0 values and FP32 coarse correction,
+// the correction formed in FP32 and both widened before their FP64 sum, as in
+// k_prolong_out_tile; the staged coarse values (128 floats per wavefront, row
+// stride 40) then live in the wavefront's own row of the join exchange array,
+// which the wavefront alone touches until the first join (a DOT sweep's LDS
+// stays under half of a compute unit's).
 template <int SEG, int NSEG, bool FINE, int DOT = 0, bool UPD = false, bool PRO = false, int CH = 8,
-          bool PAIR = false>
+          bool PAIR = false, typename TU = double>
 __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict__ tab, int c,
                                                  const double *__restrict__ bo,
-                                                 const double *__restrict__ uo,
+                                                 const TU *__restrict__ uo,
                                                  double *__restrict__ own,
                                                  const int *__restrict__ done, int lb,
                                                  double *__restrict__ partial = nullptr, int pbase = 0,
@@ -939,8 +946,12 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
                                                  double *__restrict__ rwc = nullptr,
                                                  const PcgState *__restrict__ st = nullptr,
                                                  const Geo *Cg = nullptr,
-                                                 const double *__restrict__ uc = nullptr,
+                                                 const typename std::common_type<TU>::type *__restrict__ uc = nullptr,
                                                  const double *__restrict__ r1c = nullptr) {
+  constexpr bool F32 = std::is_same<TU, float>::value;
+  static_assert(!F32 || PRO, "FP32 colour-0 values only with the fused prolongation");
+  typedef TU nt_p2 __attribute__((ext_vector_type(2)));  // a pair of staged values
+  constexpr int CR = F32 ? 40 : kCRow;                      // row stride of the staged coarse values
   constexpr int NQ = DOT ? (DOT == 3 ? 1 : DOT) : (UPD ? 1 : 0);  // partial sums per block
   constexpr int SJ = DOT == 3 ? 1 : DOT;                         // seg_join_store's products
   if constexpr (UPD) {
@@ -954,7 +965,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   __shared__ __align__(16) double ot[NSEG][4][36];
   __shared__ double bsh[DOT ? NSEG : 1][DOT ? SEG : 1][64];
   __shared__ double red[NQ ? NSEG : 1][2];
-  __shared__ __align__(16) double csl[PRO ? NSEG : 1][PRO ? 3 * kCRow : 1];
+  __shared__ __align__(16) double csl[PRO && !F32 ? NSEG : 1][PRO && !F32 ? 3 * kCRow : 1];
   const int tiles_x = (L.hx2 + kSTX - 1) / kSTX;
   if (is_done(done) || lb >= tiles_x * (L.ny / 2)) return;  // whole blocks: no barrier is skipped
   const int lane = threadIdx.x & 63;
@@ -988,7 +999,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   const double *__restrict__ pf = tab + TPF * L.P;
   const double *__restrict__ qb = tab + TQB * L.P;
   double(*slot)[36] = ot[sg];
-  const double *ug = gp(uo);
+  const TU *ug = gp(uo);
   const double *bg = gp(bo);
   const double *qg = UPD ? gp(qc) : nullptr;
   double alpha = 0.0, rsq = 0.0;
@@ -1002,8 +1013,8 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   // no staged fine cell reads, and v >= 120, load an in-bounds dummy.
   long long co0 = 0, co1 = 0, HC = 0;
   int cs0 = 0, cs1 = 0;
-  const double *ucg = nullptr;
-  double *csf = nullptr;
+  const TU *ucg = nullptr;
+  TU *csf = nullptr;
   int pa = 0, pb = 0, pd = 0, ea = 0, eb = 0, ed = 0;
   if constexpr (PRO) {
     const Geo C = *Cg;
@@ -1016,7 +1027,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
       const int J = wrapi(J0 - 1 + (need ? row : 0), C.ny);
       return (long long)((I + J) & 1) * C.cs + col_m(C, I, J);
     };
-    auto cslot = [](int v) -> int { return v < 120 ? (v / 40) * kCRow + v % 40 : 2 * kCRow + 40 + (v - 120); };
+    auto cslot = [](int v) -> int { return v < 120 ? (v / 40) * CR + v % 40 : 2 * CR + 40 + (v - 120); };
     if constexpr (PAIR) {
       // lane v < 60: row v / 20, parity par = (v % 20) / 10, pair t2 = v % 10,
       // columns I = mx0 - 4 + 4 t2 + par and I + 2 (split neighbours: with the
@@ -1029,7 +1040,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
       const int I = wrapi(mx0 - 2 + (need ? q : 2), C.nx);
       const int J = wrapi(J0 - 1 + (need ? row : 1), C.ny);
       co0 = (long long)((I + J) & 1) * C.cs + col_m(C, I, J);
-      cs0 = v < 60 ? row * kCRow + par * 20 + 2 * t2 : 2 * kCRow + 40 + 2 * (v - 60);
+      cs0 = v < 60 ? row * CR + par * 20 + 2 * t2 : 2 * CR + 40 + 2 * (v - 60);
     } else {
       co0 = coff(lane);
       co1 = coff(64 + lane);
@@ -1038,7 +1049,8 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
     }
     HC = C.S;
     ucg = gp(uc);
-    csf = csl[sg];
+    if constexpr (F32) csf = reinterpret_cast<float *>(&xch[sg][0]);
+    else csf = csl[sg];
     // staged row q -> coarse rows of its parent (pa) and y-neighbour (pb),
     // x-neighbour direction pd (fine row odd: +1)
     pa = (rr + 1) >> 1;
@@ -1052,12 +1064,12 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   // staged row (coarse rows a, b, direction d; coarse column I = mx0 - 2 + q
   // sits at slot row * kCRow + 20 ((q + 2) & 1) + ((q + 2) >> 1)), in the
   // column kernel's order
-  auto cv = [&](int row, int q) -> double { return csf[row * kCRow + 20 * ((q + 2) & 1) + ((q + 2) >> 1)]; };
-  auto corr = [&](int a, int b, int d, int idx) -> double {
-    double e = 9.0 / 16.0 * cv(a, idx);
-    e = e + 3.0 / 16.0 * cv(a, idx + d);
-    e = e + 3.0 / 16.0 * cv(b, idx);
-    e = e + 1.0 / 16.0 * cv(b, idx + d);
+  auto cv = [&](int row, int q) -> TU { return csf[row * CR + 20 * ((q + 2) & 1) + ((q + 2) >> 1)]; };
+  auto corr = [&](int a, int b, int d, int idx) -> TU {
+    TU e = TU(9.0 / 16.0) * cv(a, idx);
+    e = e + TU(3.0 / 16.0) * cv(a, idx + d);
+    e = e + TU(3.0 / 16.0) * cv(b, idx);
+    e = e + TU(1.0 / 16.0) * cv(b, idx + d);
     return e;
   };
   const double *r1g = DOT == 3 ? gp(r1c) : nullptr;
@@ -1068,21 +1080,21 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
 #pragma unroll
   for (int c0 = 0; c0 < SEG; c0 += CH) {
     if (c0 < len) {
-      double bv[CH], ev[CH], qv[UPD ? CH : 1], cv0[PRO && !PAIR ? CH : 1], cv1[PRO && !PAIR ? CH : 1],
-          r1v[DOT == 3 ? CH : 1];
-      nt_d2 cvp[PRO && PAIR ? CH : 1];
-      nt_d2 tv[CH];
+      double bv[CH], qv[UPD ? CH : 1], r1v[DOT == 3 ? CH : 1];
+      TU ev[CH], cv0[PRO && !PAIR ? CH : 1], cv1[PRO && !PAIR ? CH : 1];
+      nt_p2 cvp[PRO && PAIR ? CH : 1];
+      nt_p2 tv[CH];
 #pragma unroll
       for (int t = 0; t < CH; ++t) {
         const int kc = min(k0 + c0 + t, k1 - 1);
         const long long o = (long long)kc * H;
         bv[t] = ld_s<FINE>(&bg[o + mo]);
         if constexpr (UPD) qv[t] = __builtin_nontemporal_load(&qg[o + mo]);
-        tv[t] = *(const nt_d2 *)&ug[o + po];
-        ev[t] = lane < 2 ? ug[o + eo] : 0.0;
+        tv[t] = *(const nt_p2 *)&ug[o + po];
+        ev[t] = lane < 2 ? ug[o + eo] : TU(0);
         if constexpr (PRO) {
           if constexpr (PAIR) {
-            cvp[t] = *(const nt_d2 *)&ucg[kc * HC + co0];
+            cvp[t] = *(const nt_p2 *)&ucg[kc * HC + co0];
           } else {
             cv0[t] = ucg[kc * HC + co0];
             cv1[t] = ucg[kc * HC + co1];
@@ -1100,19 +1112,19 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
         // empty asm keeps the compiler from moving them across each other).
         // Lanes past the tile's last pair write pads or the right end's place,
         // which the end values written next overwrite.
-        nt_d2 pr = tv[t];
-        double evk = ev[t];
+        nt_d2 pr = {(double)tv[t].x, (double)tv[t].y};
+        double evk = (double)ev[t];
         if constexpr (PRO) {
           if constexpr (PAIR) {
-            *(nt_d2 *)&csf[cs0] = cvp[t];
+            *(nt_p2 *)&csf[cs0] = cvp[t];
           } else {
             csf[cs0] = cv0[t];
             csf[cs1] = cv1[t];
           }
           __asm__ volatile("" ::: "memory");
-          pr.x = pr.x + corr(pa, pb, pd, 2 + 2 * pp);
-          pr.y = pr.y + corr(pa, pb, pd, 3 + 2 * pp);
-          evk = evk + corr(ea, eb, ed, ei);
+          pr.x = pr.x + (double)corr(pa, pb, pd, 2 + 2 * pp);
+          pr.y = pr.y + (double)corr(pa, pb, pd, 3 + 2 * pp);
+          evk = evk + (double)corr(ea, eb, ed, ei);
           __asm__ volatile("" ::: "memory");
         }
         *(nt_d2 *)&slot[rr][2 + 2 * pp] = pr;
@@ -1201,6 +1213,25 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_pro(Geo L, Geo C, con
                                                                const int *__restrict__ done) {
   smooth_tile_body<SEG, NSEG, FINE, 0, false, true, 4, PAIR>(L, tab, 1, bo, uo, own, done, logical_block(), nullptr,
                                                              0, nullptr, nullptr, nullptr, &C, uc);
+}
+
+// The mixed-precision V-cycle's finest colour-1 post-smoothing sweep (FP64)
+// with the last prolongation applied on the fly: it reads the FP32 colour-0
+// values of the pre-smoothed iterate and the FP32 coarse correction, and the
+// colour-0 values it stages are the ones the prolongation pass would write
+// into the FP64 output (base + P e, e in FP32, the sum in FP64); DOT as
+// k_smooth_tile_dot.
+template <int SEG, int NSEG, int DOT, bool PAIR>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_pro32(Geo L, Geo C, const double *__restrict__ tab,
+                                                                 const double *__restrict__ bo,
+                                                                 const float *__restrict__ uo,
+                                                                 double *__restrict__ own,
+                                                                 const float *__restrict__ uc,
+                                                                 const int *__restrict__ done,
+                                                                 double *__restrict__ partial, int pbase,
+                                                                 const double *__restrict__ qc) {
+  smooth_tile_body<SEG, NSEG, true, DOT, false, true, 4, PAIR, float>(L, tab, 1, bo, uo, own, done, logical_block(),
+                                                                      partial, pbase, qc, nullptr, nullptr, &C, uc);
 }
 
 // The last sweep (colour 0) after it, with <r, z> of both colours.

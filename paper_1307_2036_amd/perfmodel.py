@@ -67,14 +67,20 @@ def cg_bytes(n0: int, flexible: bool = True, fused_update: bool = False, fused_d
     return (44 + update + dots) * n0
 
 
-def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1) -> float:
+def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1, fused_prolong=False) -> float:
     """Mixed-precision V-cycle: FP32 everywhere except the finest level, whose
     pre-smoothing and restriction read the FP64 residual and write FP32, and
-    whose colour-0 prolongation and post-smoothing write the FP64 output."""
+    whose colour-0 prolongation and post-smoothing write the FP64 output.
+    fused_prolong: no prolongation pass; the first FP64 post-sweep reads the
+    FP32 colour-0 values and the coarse correction (3 B) in place of the FP64
+    colour-0 values (4 B)."""
     fine = (6 + 8) * n0          # pre red (b64 read, u32 write), pre black (+ u32 red read)
     fine += (4 + 4 + 1) * n0     # restriction: b64 red, u32 both colours, coarse write
-    fine += (2 + 1 + 4) * n0     # prolongation: u32 red, coarse, z64 red write
-    fine += 2 * 12 * n0          # FP64 post-smoothing, black then red
+    if fused_prolong:
+        fine += (4 + 2 + 1 + 4) * n0 + 12 * n0  # post black (r, u32 red, coarse, z), post red
+    else:
+        fine += (2 + 1 + 4) * n0     # prolongation: u32 red, coarse, z64 red write
+        fine += 2 * 12 * n0          # FP64 post-smoothing, black then red
     return fine + vcycle_bytes(n0 // 4, levels - 1, 4, nu_coarse=nu_coarse)
 
 
@@ -83,20 +89,25 @@ def pcg_iteration_bytes(n0: int, levels: int, e: int, nu_coarse=1, flexible=True
     """fused_prolong: the finest prolongation (10 B/unknown) rides on the first
     post-smoothing sweep, which reads the coarse correction (2 B/unknown), and
     the last sweep reads colour 1 of r for <r, z> (4 B/unknown); coarse_prolong:
-    the same on the coarse levels (vcycle_bytes)."""
+    the same on the coarse levels (vcycle_bytes).  e = 4: the mixed-precision
+    V-cycle (hybrid_vcycle_bytes, its own fused prolongation)."""
     cg = cg_bytes(n0, flexible, fused_update, fused_dots)
     if e == 8:
         return (cg + vcycle_bytes(n0, levels, 8, nu_coarse=nu_coarse, coarse_prolong=coarse_prolong, **mg) -
                 (4 * n0 if fused_prolong else 0))
-    return cg + hybrid_vcycle_bytes(n0, levels, nu_coarse)
+    return cg + hybrid_vcycle_bytes(n0, levels, nu_coarse, fused_prolong)
 
 
-def smooth0_launch_bytes_hybrid(n0: int, fused_update: bool = False, dot_q: bool = False) -> float:
+def smooth0_launch_bytes_hybrid(n0: int, fused_update: bool = False, dot_q: bool = False,
+                                fused_prolong: bool = False) -> float:
     """Average bytes of a finest-level half-sweep launch in the mixed-precision
     V-cycle: FP32 pre-sweeps reading the FP64 residual, FP64 post-sweeps; with
     the fused residual update the pre-sweeps also read q and write r (16 B per
-    unknown of their colour), with the fused <z,q> the post-sweeps read q."""
-    return ((6 + 8 + 12 + 12) + (16 if fused_update else 0) + (8 if dot_q else 0)) * n0 / 4
+    unknown of their colour), with the fused <z,q> the post-sweeps read q; with
+    the fused prolongation the first post-sweep reads the FP32 colour-0 values
+    and the coarse correction (3 B) in place of the FP64 ones (4 B)."""
+    post = (11 if fused_prolong else 12) + 12
+    return ((6 + 8 + post) + (16 if fused_update else 0) + (8 if dot_q else 0)) * n0 / 4
 
 
 def smooth0_launch_bytes(n0: int, e: int, nu_pre=1, nu_post=1, fused_update: bool = False,

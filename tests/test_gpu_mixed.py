@@ -70,6 +70,42 @@ def test_tiled_kernels_in_mixed_vcycle_are_bitwise(name):
     np.testing.assert_array_equal(out[0], out[1])
 
 
+@pytest.mark.parametrize("nx,nz,levels,precision", [(64, 32, 4, "fp32"), (68, 100, 2, "fp32"),
+                                                     (136, 40, 3, "bf16coef"), (64, 128, 4, "fp32")])
+def test_mixed_fused_prolongation_is_bitwise(nx, nz, levels, precision):
+    """The mixed-precision V-cycle's finest prolongation applied inside the first
+    FP64 post-smoothing sweep (the FP32 colour-0 values and coarse correction
+    staged, the correction formed in FP32 and added in FP64) gives the values
+    of the prolongation pass into the FP64 output, bitwise: one V-cycle, a
+    flexible solve (fused <r, z> and <z, q>) and three printed-beta steps
+    (fused <r, z>).  (68, 100) stages the coarse values one by one (coarse
+    half-width 34), has eight ragged 13-level segments and partial tiles;
+    (136, 40) has partial tiles; (64, 128) is the 512^2 x 128 finest level's
+    kernel shape."""
+    from paper_1307_2036_amd import ell
+    p = I.graded_problem("mixed_pro", nx, nz, 1e-2, 27, 28, n_levels=levels, nu_coarse=5)
+    r = dev(p.f * (p.hx * p.hy * p.dz)[:, None, None])
+    res = []
+    for fused in (1, 0):
+        ell.set_tuning(ell.ELL_TUNE_FUSED_PROLONG, fused)
+        try:
+            G = ell.Grid.from_problem(p, precision=precision)
+        finally:
+            ell.set_tuning(ell.ELL_TUNE_FUSED_PROLONG, 1)
+        assert G.features["fused_prolong"] == bool(fused)
+        z = host(G.vcycle(r))
+        u, st = G.pcg_solve(dev(p.f), rtol=1e-8)
+        assert st.status == 0
+        ul, stl = G.pcg_solve(dev(p.f), rtol=1e-14, maxiter=3, flexible=False)
+        assert stl.status == ell.ELL_NOT_CONVERGED and stl.iters == 3
+        res.append((z, host(u), st, host(ul), stl))
+    (z1, u1, s1, l1, t1), (z0, u0, s0, l0, t0) = res
+    np.testing.assert_array_equal(z1, z0)
+    np.testing.assert_array_equal(u1, u0)
+    np.testing.assert_array_equal(l1, l0)
+    assert s1.iters == s0.iters and s1.r_norm == s0.r_norm and t1.r_norm == t0.r_norm
+
+
 @pytest.mark.parametrize("name", list(PROBLEMS))
 @pytest.mark.parametrize("precision", ["fp32", "bf16coef"])
 def test_tight_solve_reaches_fp64_solution(orc, name, precision):

@@ -33,6 +33,11 @@ def test_vcycle_and_iteration():
         (91.0625 - 8 * (1 / 4 + 1 / 16)) * N)
     assert P.pcg_iteration_bytes(N, 4, 8, nu_coarse=5) == pytest.approx(183.0625 * N)
     assert P.hybrid_vcycle_bytes(N, 4, 5) == pytest.approx(65.53125 * N)
+    # mixed precision with the fused prolongation: the 7 B pass goes, the
+    # first FP64 post-sweep reads 3 B of FP32 values for 4 B of FP64 ones
+    assert P.hybrid_vcycle_bytes(N, 4, 5, fused_prolong=True) == pytest.approx(57.53125 * N)
+    assert P.smooth0_launch_bytes_hybrid(N) == pytest.approx(9.5 * N)
+    assert P.smooth0_launch_bytes_hybrid(N, fused_prolong=True) == pytest.approx(9.25 * N)
 
 
 def test_cg_vector_work():
