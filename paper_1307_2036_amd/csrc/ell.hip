@@ -2222,7 +2222,10 @@ int ell_profile_enable(ell_grid *g, int family, int max_events) {
   Prof &p = g->prof[family];
   for (auto &e : p.ev) (void)hipEventDestroy(e);
   p.ev.assign(2 * (size_t)max_events, nullptr);
-  for (auto &e : p.ev) HIPCHK(hipEventCreate(&e));
+  // device-scope release only: the timestamps are read after the stream has
+  // been synchronized, and a record without the system-scope fence adds less
+  // idle time to the stream (and to the launches it brackets)
+  for (auto &e : p.ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   p.cap = max_events;
   p.n = 0;
   p.paused = false;
