@@ -1122,9 +1122,23 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
             csf[cs1] = cv1[t];
           }
           __asm__ volatile("" ::: "memory");
-          pr.x = pr.x + (double)corr(pa, pb, pd, 2 + 2 * pp);
-          pr.y = pr.y + (double)corr(pa, pb, pd, 3 + 2 * pp);
-          evk = evk + (double)corr(ea, eb, ed, ei);
+          // the pair's columns idx0 = 2 + 2 pp and idx0 + 1 read three coarse
+          // values per row (columns idx0, idx0 + 1 and idx0 + 2 or idx0 - 1):
+          // slots base, base + 20 and base + 1 or base + 19
+          const int sa = pa * CR + 2 + pp, sb = pb * CR + 2 + pp, s2 = pd > 0 ? 1 : 19;
+          const TU a0 = csf[sa], a1 = csf[sa + 20], a2 = csf[sa + s2];
+          const TU b0 = csf[sb], b1 = csf[sb + 20], b2 = csf[sb + s2];
+          TU e0 = TU(9.0 / 16.0) * a0;
+          e0 = e0 + TU(3.0 / 16.0) * (pd > 0 ? a1 : a2);
+          e0 = e0 + TU(3.0 / 16.0) * b0;
+          e0 = e0 + TU(1.0 / 16.0) * (pd > 0 ? b1 : b2);
+          TU e1 = TU(9.0 / 16.0) * a1;
+          e1 = e1 + TU(3.0 / 16.0) * (pd > 0 ? a2 : a0);
+          e1 = e1 + TU(3.0 / 16.0) * b1;
+          e1 = e1 + TU(1.0 / 16.0) * (pd > 0 ? b2 : b0);
+          pr.x = pr.x + (double)e0;
+          pr.y = pr.y + (double)e1;
+          if (lane < 2) evk = evk + (double)corr(ea, eb, ed, ei);
           __asm__ volatile("" ::: "memory");
         }
         *(nt_d2 *)&slot[rr][2 + 2 * pp] = pr;
