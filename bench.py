@@ -450,7 +450,8 @@ def c2_sweep(steps=3, precision="bf16coef"):
         fm = per[precision]["feat"]
         mixed_bytes = perfmodel.pcg_iteration_bytes(p.n, per[precision]["levels"], 4, fused_update=fm["fused_update"],
                                                     fused_dots=fm["fused_dots"],
-                                                    fused_prolong=fm["fused_prolong"]) * per[precision]["iters"]
+                                                    fused_prolong=fm["fused_prolong"],
+                                                    coarse_prolong=fm["coarse_prolong"]) * per[precision]["iters"]
         err = float(torch.linalg.vector_norm(per[precision]["tight"] - per["fp64"]["tight"]) /
                     torch.linalg.vector_norm(per["fp64"]["tight"]))
         rows.append({"omega2": omega2, "levels": per[precision]["levels"],

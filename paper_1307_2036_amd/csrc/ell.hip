@@ -586,8 +586,9 @@ bool seg_dispatch(bool fine, int nb, hipStream_t s, const Geo &G, const R *tab, 
 bool tile_ok(const ell_grid *g, int l) {
   const Geo &G = g->lev[l].geo;
   const int Ls = seg_len(G.nz, G.nseg);
+  // pairs of columns load as one vector: even half-width, plane and colour strides
   return g->d.rho == 1.0 && G.has_x && G.has_y && g->smooth_tile && !g->varying && G.hx2 % 2 == 0 &&
-         G.ny % 2 == 0 &&
+         G.ny % 2 == 0 && G.S % 2 == 0 && G.cs % 2 == 0 &&
          ((G.nseg == 16 && Ls <= 8) || (G.nseg == 8 && Ls <= 16) || (G.nseg == 4 && Ls <= 32));
 }
 
@@ -725,13 +726,16 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
       return fail(ELL_ERR_INVALID, "no line-relaxation kernel for this level shape");
     }
   }
-  if constexpr (std::is_same<R, double>::value && std::is_same<TB, double>::value) {
+  if constexpr (std::is_same<R, TB>::value) {
     // after the first sweep, rho = 1: the LDS-tiled half-sweep (streaming
-    // accesses on the finest level)
+    // accesses on the finest level; FP32 on the coarse levels of the
+    // mixed-precision V-cycle)
+    constexpr bool F64 = std::is_same<R, double>::value;
     const int Ls = seg_len(G.nz, G.nseg);
-    if (!zero && tile_ok(g, l)) {
+    if (!zero && tile_ok(g, l) && (F64 || l >= 1)) {
       const int nbt = blocks8((long long)smooth_tiles(G) * kBlock);
       if (l == 0) {
+        if constexpr (F64) {
         if (G.nseg == 16)
           k_smooth_tile<8, 16, true><<<nbt, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
         else if (G.nseg == 8)
@@ -740,6 +744,7 @@ int launch_smooth(ell_grid *g, int l, int c, bool zero, const TB *b, R *u, const
           k_smooth_tile<16, 4, true><<<nbt, 4 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
         else
           k_smooth_tile<32, 4, true><<<nbt, 4 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
+        }
       } else {
         if (G.nseg == 16)
           k_smooth_tile<8, 16, false><<<nbt, 16 * 64, 0, s>>>(G, tab, c, bo, uo, own, done);
@@ -883,15 +888,15 @@ int launch_smooth_upd(ell_grid *g, int c, double *r, R *u, const R *tab, int pba
 // partial slots.  The caller has checked pro_path.
 // The staged coarse values of a fused prolongation load in aligned pairs
 // (k_smooth_tile_pro<..., PAIR>): coarse half-width, colour and plane strides
-// even, the array 16-byte aligned.
-bool pro_pairs_ok(const Geo &C, const void *uc) {
-  return C.nx % 4 == 0 && C.cs % 2 == 0 && C.S % 2 == 0 && (reinterpret_cast<uintptr_t>(uc) & 15) == 0;
+// even, the array aligned to a pair (16 bytes in FP64, 8 in FP32).
+bool pro_pairs_ok(const Geo &C, const void *uc, uintptr_t pair_bytes = 16) {
+  return C.nx % 4 == 0 && C.cs % 2 == 0 && C.S % 2 == 0 && (reinterpret_cast<uintptr_t>(uc) & (pair_bytes - 1)) == 0;
 }
 
-template <int SEG, int NSEG, bool FINE>
-void launch_tile_pro(int nbt, hipStream_t s, const Geo &F, const Geo &C, const double *tab, const double *b1,
-                     const double *u, double *u1, const double *uc, const int *done) {
-  if (pro_pairs_ok(C, uc))
+template <int SEG, int NSEG, bool FINE, typename R>
+void launch_tile_pro(int nbt, hipStream_t s, const Geo &F, const Geo &C, const R *tab, const R *b1, const R *u,
+                     R *u1, const R *uc, const int *done) {
+  if (pro_pairs_ok(C, uc, 2 * sizeof(R)))
     k_smooth_tile_pro<SEG, NSEG, FINE, true><<<nbt, NSEG * 64, 0, s>>>(F, C, tab, b1, u, u1, uc, done);
   else
     k_smooth_tile_pro<SEG, NSEG, FINE, false><<<nbt, NSEG * 64, 0, s>>>(F, C, tab, b1, u, u1, uc, done);
@@ -915,14 +920,19 @@ void pro_pair_k(ell_grid *g, const double *b, double *u, const int *done, hipStr
 // same way: FP64 level with a coarser one below it and the LDS-tiled sweep,
 // rho = 1 (the colour-0 sweep that follows overwrites colour 0 without
 // reading it, the colour-1 sweep overwrites colour 1), bilinear prolongation.
+// R = float: the coarse levels of the mixed-precision V-cycle (the FP32
+// prolongation's values, in FP32).
+template <typename R>
 bool coarse_pro_ok(const ell_grid *g, int l) {
-  return l >= 1 && l <= g->L - 2 && g->prec == ELL_FP64 && g->fused_prolong && g->d.nu_post >= 1 &&
-         g->d.prolong == 0 && tile_ok(g, l);
+  const bool prec = std::is_same<R, double>::value ? g->prec == ELL_FP64 : g->prec != ELL_FP64;
+  return l >= 1 && l <= g->L - 2 && prec && g->fused_prolong && g->d.nu_post >= 1 && g->d.prolong == 0 &&
+         tile_ok(g, l);
 }
 
-int coarse_pro_sweep(ell_grid *g, int l, const double *b, double *u, const int *done, hipStream_t s) {
+template <typename R>
+int coarse_pro_sweep(ell_grid *g, int l, const R *b, R *u, const int *done, hipStream_t s) {
   const Geo &F = g->lev[l].geo, &C = g->lev[l + 1].geo;
-  const double *tab = (const double *)g->lev[l].tab, *uc = (const double *)g->lev[l + 1].u;
+  const R *tab = (const R *)g->lev[l].tab, *uc = (const R *)g->lev[l + 1].u;
   const int nbt = blocks8((long long)smooth_tiles(F) * kBlock);
   const int Ls = seg_len(F.nz, F.nseg);
   const long long cs = F.cs;
@@ -1200,15 +1210,15 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
         CHK(pro_pair(g, B(0), U(0), done, s));
         continue;
       }
-      if (coarse_pro_ok(g, l)) {  // prolongation inside the first post-smoothing sweep
-        CHK(coarse_pro_sweep(g, l, B(l), U(l), done, s));
+    }
+    if (coarse_pro_ok<R>(g, l)) {  // prolongation inside the first post-smoothing sweep
+      CHK(coarse_pro_sweep<R>(g, l, B(l), U(l), done, s));
+      CHK(launch_smooth<R>(g, l, 0, false, B(l), U(l), done, s));
+      for (int it = 1; it < g->d.nu_post; ++it) {
+        CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
         CHK(launch_smooth<R>(g, l, 0, false, B(l), U(l), done, s));
-        for (int it = 1; it < g->d.nu_post; ++it) {
-          CHK(launch_smooth<R>(g, l, 1, false, B(l), U(l), done, s));
-          CHK(launch_smooth<R>(g, l, 0, false, B(l), U(l), done, s));
-        }
-        continue;
       }
+      continue;
     }
     CHK(launch_prolong<R>(g, l, (const R *)g->lev[l + 1].u, U(l), rho1 && g->d.nu_post > 0, done, s));
     for (int it = 0; it < g->d.nu_post; ++it) {
@@ -1265,9 +1275,7 @@ bool pro32_path(const ell_grid *g) {
 
 // The staged FP32 coarse values load in aligned pairs: coarse half-width,
 // colour and plane strides even, the array 8-byte aligned.
-bool pro32_pairs_ok(const Geo &C, const void *uc) {
-  return C.nx % 4 == 0 && C.cs % 2 == 0 && C.S % 2 == 0 && (reinterpret_cast<uintptr_t>(uc) & 7) == 0;
-}
+bool pro32_pairs_ok(const Geo &C, const void *uc) { return pro_pairs_ok(C, uc, 8); }
 
 template <int SEG, int NSEG, int DOT>
 void launch_pro32(int nbt, hipStream_t s, const Geo &F, const Geo &C, const double *tab, const double *b1,
@@ -2028,13 +2036,15 @@ int ell_grid_features(const ell_grid *g, int32_t *mask) {
     if (pro_path(g, 1)) m |= ELL_FEAT_FUSED_PROLONG;
     if (g->tiled_ends) m |= ELL_FEAT_TILED_ENDS;
     for (int l = 1; l <= g->L - 2; ++l)
-      if (coarse_pro_ok(g, l)) m |= ELL_FEAT_COARSE_PROLONG;
+      if (coarse_pro_ok<double>(g, l)) m |= ELL_FEAT_COARSE_PROLONG;
   } else if (hybrid_ok(g)) {  // the FP64 post-smoothing of the mixed-precision V-cycle
     if (tile_ok(g, 0)) m |= ELL_FEAT_TILED_SMOOTH;
     if (fused_dot_path<float>(g)) m |= ELL_FEAT_FUSED_DOTS;
     if (fused_update_path<float>(g)) m |= ELL_FEAT_FUSED_UPDATE;
     if (pro32_path(g)) m |= ELL_FEAT_FUSED_PROLONG;
     if (g->tiled_ends) m |= ELL_FEAT_TILED_ENDS;
+    for (int l = 1; l <= g->L - 2; ++l)
+      if (coarse_pro_ok<float>(g, l)) m |= ELL_FEAT_COARSE_PROLONG;
   }
   *mask = m;
   return ELL_OK;

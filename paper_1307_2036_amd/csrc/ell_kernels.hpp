@@ -934,12 +934,14 @@ constexpr int kCRow = 48;  // LDS row stride of the staged coarse values (40 use
 // stride 40) then live in the wavefront's own row of the join exchange array,
 // which the wavefront alone touches until the first join (a DOT sweep's LDS
 // stays under half of a compute unit's).
+// R: element type of the level (b, u, coefficients, arithmetic): float on
+// the mixed-precision V-cycle's coarse levels (plain sweeps and PRO only).
 template <int SEG, int NSEG, bool FINE, int DOT = 0, bool UPD = false, bool PRO = false, int CH = 8,
-          bool PAIR = false, typename TU = double>
-__device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict__ tab, int c,
-                                                 const double *__restrict__ bo,
+          bool PAIR = false, typename TU = double, typename R = double>
+__device__ __forceinline__ void smooth_tile_body(Geo L, const R *__restrict__ tab, int c,
+                                                 const R *__restrict__ bo,
                                                  const TU *__restrict__ uo,
-                                                 double *__restrict__ own,
+                                                 R *__restrict__ own,
                                                  const int *__restrict__ done, int lb,
                                                  double *__restrict__ partial = nullptr, int pbase = 0,
                                                  const double *__restrict__ qc = nullptr,
@@ -949,8 +951,11 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
                                                  const typename std::common_type<TU>::type *__restrict__ uc = nullptr,
                                                  const double *__restrict__ r1c = nullptr) {
   constexpr bool F32 = std::is_same<TU, float>::value;
-  static_assert(!F32 || PRO, "FP32 colour-0 values only with the fused prolongation");
+  constexpr bool ALIAS = F32 && std::is_same<R, double>::value;  // staged coarse values in xch rows
+  static_assert(std::is_same<TU, R>::value || PRO, "mixed element types only with the fused prolongation");
+  static_assert(std::is_same<R, double>::value || (DOT == 0 && !UPD), "CG forms only on FP64 levels");
   typedef TU nt_p2 __attribute__((ext_vector_type(2)));  // a pair of staged values
+  typedef R nt_r2 __attribute__((ext_vector_type(2)));   // a pair of level values
   constexpr int CR = F32 ? 40 : kCRow;                      // row stride of the staged coarse values
   constexpr int NQ = DOT ? (DOT == 3 ? 1 : DOT) : (UPD ? 1 : 0);  // partial sums per block
   constexpr int SJ = DOT == 3 ? 1 : DOT;                         // seg_join_store's products
@@ -961,11 +966,11 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
       return;
     }
   }
-  __shared__ double xch[NSEG][kSegCols];
-  __shared__ __align__(16) double ot[NSEG][4][36];
+  __shared__ R xch[NSEG][kSegCols];
+  __shared__ __align__(16) R ot[NSEG][4][36];
   __shared__ double bsh[DOT ? NSEG : 1][DOT ? SEG : 1][64];
   __shared__ double red[NQ ? NSEG : 1][2];
-  __shared__ __align__(16) double csl[PRO && !F32 ? NSEG : 1][PRO && !F32 ? 3 * kCRow : 1];
+  __shared__ __align__(16) TU csl[PRO && !ALIAS ? NSEG : 1][PRO && !ALIAS ? (F32 ? 128 : 3 * kCRow) : 1];
   const int tiles_x = (L.hx2 + kSTX - 1) / kSTX;
   if (is_done(done) || lb >= tiles_x * (L.ny / 2)) return;  // whole blocks: no barrier is skipped
   const int lane = threadIdx.x & 63;
@@ -991,16 +996,16 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   const long long H = L.S;
   const int nz = L.nz, Ls = seg_len(nz, NSEG);
   const int k0 = min(sg * Ls, nz), k1 = min(k0 + Ls, nz), len = k1 - k0;
-  const double *__restrict__ txv = tab + TX * L.P;
-  const double *__restrict__ tyv = tab + TY * L.P;
-  const double *__restrict__ tz = tab + TZ * L.P;
-  const double *__restrict__ ip = tab + TIP * L.P;
-  const double *__restrict__ cf = tab + TCF * L.P;
-  const double *__restrict__ pf = tab + TPF * L.P;
-  const double *__restrict__ qb = tab + TQB * L.P;
-  double(*slot)[36] = ot[sg];
+  const R *__restrict__ txv = tab + TX * L.P;
+  const R *__restrict__ tyv = tab + TY * L.P;
+  const R *__restrict__ tz = tab + TZ * L.P;
+  const R *__restrict__ ip = tab + TIP * L.P;
+  const R *__restrict__ cf = tab + TCF * L.P;
+  const R *__restrict__ pf = tab + TPF * L.P;
+  const R *__restrict__ qb = tab + TQB * L.P;
+  R(*slot)[36] = ot[sg];
   const TU *ug = gp(uo);
-  const double *bg = gp(bo);
+  const R *bg = gp(bo);
   const double *qg = UPD ? gp(qc) : nullptr;
   double alpha = 0.0, rsq = 0.0;
   if constexpr (UPD) alpha = st->alpha;
@@ -1049,7 +1054,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
     }
     HC = C.S;
     ucg = gp(uc);
-    if constexpr (F32) csf = reinterpret_cast<float *>(&xch[sg][0]);
+    if constexpr (ALIAS) csf = reinterpret_cast<TU *>(&xch[sg][0]);
     else csf = csl[sg];
     // staged row q -> coarse rows of its parent (pa) and y-neighbour (pb),
     // x-neighbour direction pd (fine row odd: +1)
@@ -1075,12 +1080,13 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   const double *r1g = DOT == 3 ? gp(r1c) : nullptr;
   double d1 = 0.0;  // DOT 3: <r1, z1> of this lane's colour-1 cell
 
-  double y[SEG];
-  double prev = 0.0;
+  R y[SEG];
+  R prev = R(0);
 #pragma unroll
   for (int c0 = 0; c0 < SEG; c0 += CH) {
     if (c0 < len) {
-      double bv[CH], qv[UPD ? CH : 1], r1v[DOT == 3 ? CH : 1];
+      R bv[CH];
+      double qv[UPD ? CH : 1], r1v[DOT == 3 ? CH : 1];
       TU ev[CH], cv0[PRO && !PAIR ? CH : 1], cv1[PRO && !PAIR ? CH : 1];
       nt_p2 cvp[PRO && PAIR ? CH : 1];
       nt_p2 tv[CH];
@@ -1112,8 +1118,8 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
         // empty asm keeps the compiler from moving them across each other).
         // Lanes past the tile's last pair write pads or the right end's place,
         // which the end values written next overwrite.
-        nt_d2 pr = {(double)tv[t].x, (double)tv[t].y};
-        double evk = (double)ev[t];
+        nt_r2 pr = {(R)tv[t].x, (R)tv[t].y};
+        R evk = (R)ev[t];
         if constexpr (PRO) {
           if constexpr (PAIR) {
             *(nt_p2 *)&csf[cs0] = cvp[t];
@@ -1136,23 +1142,23 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
           e1 = e1 + TU(3.0 / 16.0) * (pd > 0 ? a2 : a0);
           e1 = e1 + TU(3.0 / 16.0) * b1;
           e1 = e1 + TU(1.0 / 16.0) * (pd > 0 ? b2 : b0);
-          pr.x = pr.x + (double)e0;
-          pr.y = pr.y + (double)e1;
-          if (lane < 2) evk = evk + (double)corr(ea, eb, ed, ei);
+          pr.x = pr.x + (R)e0;
+          pr.y = pr.y + (R)e1;
+          if (lane < 2) evk = evk + (R)corr(ea, eb, ed, ei);
           __asm__ volatile("" ::: "memory");
         }
-        *(nt_d2 *)&slot[rr][2 + 2 * pp] = pr;
+        *(nt_r2 *)&slot[rr][2 + 2 * pp] = pr;
         __asm__ volatile("" ::: "memory");
         if (lane < 2) slot[er][ei] = evk;
         __asm__ volatile("" ::: "memory");
-        const double w = slot[r + 1][x + 1 + par], e = slot[r + 1][x + 2 + par];
-        const double so = slot[r][x + 2], no = slot[r + 2][x + 2];
+        const R w = slot[r + 1][x + 1 + par], e = slot[r + 1][x + 2 + par];
+        const R so = slot[r][x + 2], no = slot[r + 2][x + 2];
         if constexpr (DOT == 3) {
           const double z1 = slot[r + 1][x + 2];  // the colour-1 cell (j, mx0 + x)
           d1 += (valid && c0 + t < len) ? r1v[t] * z1 : 0.0;
         }
         __asm__ volatile("" ::: "memory");
-        double g = bv[t];
+        R g = bv[t];
         if constexpr (UPD) {
           // the residual update of the CG step; only the lane that owns the
           // column writes it
@@ -1164,7 +1170,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
         }
         g = g + txv[k] * (w + e);
         g = g + tyv[k] * (so + no);
-        const double nv = (g + tz[k] * prev) * ip[k];
+        const R nv = (g + tz[k] * prev) * ip[k];
         prev = c0 + t < len ? nv : prev;
         y[c0 + t] = prev;
         if constexpr (DOT > 0) bsh[sg][c0 + t][lane] = bv[t];
@@ -1172,8 +1178,8 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
     }
   }
   double dsum[2] = {UPD ? rsq : d1, 0.0};
-  seg_join_store<double, false, true, FINE, SEG, NSEG, SJ>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf,
-                                                           qb, valid, own + mo, H, 1.0, &bsh[DOT ? sg : 0][0][0],
+  seg_join_store<R, false, true, FINE, SEG, NSEG, SJ>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf,
+                                                      qb, valid, own + mo, H, R(1), &bsh[DOT ? sg : 0][0][0],
                                                            DOT == 2 ? qc + mo : nullptr, dsum);
   if constexpr (NQ > 0) {
 #pragma unroll
@@ -1192,13 +1198,13 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const double *__restrict
   }
 }
 
-template <int SEG, int NSEG, bool FINE>
-__global__ __launch_bounds__(NSEG * 64) void k_smooth_tile(Geo L, const double *__restrict__ tab, int c,
-                                                           const double *__restrict__ bo,
-                                                           const double *__restrict__ uo,
-                                                           double *__restrict__ own,
+template <int SEG, int NSEG, bool FINE, typename R = double>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_tile(Geo L, const R *__restrict__ tab, int c,
+                                                           const R *__restrict__ bo,
+                                                           const R *__restrict__ uo,
+                                                           R *__restrict__ own,
                                                            const int *__restrict__ done) {
-  smooth_tile_body<SEG, NSEG, FINE>(L, tab, c, bo, uo, own, done, logical_block());
+  smooth_tile_body<SEG, NSEG, FINE, 0, false, false, 8, false, R, R>(L, tab, c, bo, uo, own, done, logical_block());
 }
 
 // The finest level's colour-1 half-sweep of the first pre-smoothing pair
@@ -1218,15 +1224,15 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_upd(Geo L, const doub
 // A level's first post-smoothing sweep (colour 1) with the coarse correction
 // of colour 0 applied on the fly (no separate prolongation); FINE: the finest
 // level (streaming accesses).
-template <int SEG, int NSEG, bool FINE = true, bool PAIR = false>
-__global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_pro(Geo L, Geo C, const double *__restrict__ tab,
-                                                               const double *__restrict__ bo,
-                                                               const double *__restrict__ uo,
-                                                               double *__restrict__ own,
-                                                               const double *__restrict__ uc,
+template <int SEG, int NSEG, bool FINE = true, bool PAIR = false, typename R = double>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_pro(Geo L, Geo C, const R *__restrict__ tab,
+                                                               const R *__restrict__ bo,
+                                                               const R *__restrict__ uo,
+                                                               R *__restrict__ own,
+                                                               const R *__restrict__ uc,
                                                                const int *__restrict__ done) {
-  smooth_tile_body<SEG, NSEG, FINE, 0, false, true, 4, PAIR>(L, tab, 1, bo, uo, own, done, logical_block(), nullptr,
-                                                             0, nullptr, nullptr, nullptr, &C, uc);
+  smooth_tile_body<SEG, NSEG, FINE, 0, false, true, 4, PAIR, R, R>(L, tab, 1, bo, uo, own, done, logical_block(),
+                                                                   nullptr, 0, nullptr, nullptr, nullptr, &C, uc);
 }
 
 // The mixed-precision V-cycle's finest colour-1 post-smoothing sweep (FP64)

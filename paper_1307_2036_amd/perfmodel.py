@@ -22,11 +22,12 @@ def smooth_bytes(n: int, e: int, zero: bool) -> float:
     return n * (e if zero else 1.5 * e)
 
 
-def vcycle_bytes(n0: int, levels: int, e: int, nu_pre=1, nu_post=1, nu_coarse=1, coarse_prolong=False) -> float:
+def vcycle_bytes(n0: int, levels: int, e: int, nu_pre=1, nu_post=1, nu_coarse=1, coarse_prolong=False,
+                 pro_from=1) -> float:
     """Bytes of one V-cycle with rho = 1 (the shortcuts of the schedule).
-    coarse_prolong: on levels 1 .. levels - 2 the prolongation rides on the
-    first post-smoothing sweep, which reads the coarse correction (0.25 e per
-    unknown of the level) instead of the 1.25 e of the pass."""
+    coarse_prolong: on levels pro_from .. levels - 2 the prolongation rides on
+    the first post-smoothing sweep, which reads the coarse correction (0.25 e
+    per unknown of the level) instead of the 1.25 e of the pass."""
     total = 0.0
     n = n0
     for l in range(levels):
@@ -44,7 +45,7 @@ def vcycle_bytes(n0: int, levels: int, e: int, nu_pre=1, nu_post=1, nu_coarse=1,
                 total += smooth_bytes(n, e, True) + smooth_bytes(n, e, False)
                 total += (nu_pre - 1) * 2 * smooth_bytes(n, e, False)
             total += 1.75 * e * n                      # residual + restriction
-            total += (0.25 if coarse_prolong and l >= 1 else 1.25) * e * n  # prolongation (red only)
+            total += (0.25 if coarse_prolong and l >= pro_from else 1.25) * e * n  # prolongation (red only)
             total += nu_post * 2 * smooth_bytes(n, e, False)
         n //= 4
     return total
@@ -67,13 +68,14 @@ def cg_bytes(n0: int, flexible: bool = True, fused_update: bool = False, fused_d
     return (44 + update + dots) * n0
 
 
-def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1, fused_prolong=False) -> float:
+def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1, fused_prolong=False, coarse_prolong=False) -> float:
     """Mixed-precision V-cycle: FP32 everywhere except the finest level, whose
     pre-smoothing and restriction read the FP64 residual and write FP32, and
     whose colour-0 prolongation and post-smoothing write the FP64 output.
     fused_prolong: no prolongation pass; the first FP64 post-sweep reads the
     FP32 colour-0 values and the coarse correction (3 B) in place of the FP64
-    colour-0 values (4 B)."""
+    colour-0 values (4 B); coarse_prolong: the same on the FP32 levels 1 ..
+    levels - 2 (vcycle_bytes)."""
     fine = (6 + 8) * n0          # pre red (b64 read, u32 write), pre black (+ u32 red read)
     fine += (4 + 4 + 1) * n0     # restriction: b64 red, u32 both colours, coarse write
     if fused_prolong:
@@ -81,7 +83,8 @@ def hybrid_vcycle_bytes(n0: int, levels: int, nu_coarse=1, fused_prolong=False) 
     else:
         fine += (2 + 1 + 4) * n0     # prolongation: u32 red, coarse, z64 red write
         fine += 2 * 12 * n0          # FP64 post-smoothing, black then red
-    return fine + vcycle_bytes(n0 // 4, levels - 1, 4, nu_coarse=nu_coarse)
+    return fine + vcycle_bytes(n0 // 4, levels - 1, 4, nu_coarse=nu_coarse, coarse_prolong=coarse_prolong,
+                               pro_from=0)
 
 
 def pcg_iteration_bytes(n0: int, levels: int, e: int, nu_coarse=1, flexible=True, fused_update=False,
@@ -95,7 +98,7 @@ def pcg_iteration_bytes(n0: int, levels: int, e: int, nu_coarse=1, flexible=True
     if e == 8:
         return (cg + vcycle_bytes(n0, levels, 8, nu_coarse=nu_coarse, coarse_prolong=coarse_prolong, **mg) -
                 (4 * n0 if fused_prolong else 0))
-    return cg + hybrid_vcycle_bytes(n0, levels, nu_coarse, fused_prolong)
+    return cg + hybrid_vcycle_bytes(n0, levels, nu_coarse, fused_prolong, coarse_prolong)
 
 
 def smooth0_launch_bytes_hybrid(n0: int, fused_update: bool = False, dot_q: bool = False,

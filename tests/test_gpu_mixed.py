@@ -75,8 +75,9 @@ def test_tiled_kernels_in_mixed_vcycle_are_bitwise(name):
 def test_mixed_fused_prolongation_is_bitwise(nx, nz, levels, precision):
     """The mixed-precision V-cycle's finest prolongation applied inside the first
     FP64 post-smoothing sweep (the FP32 colour-0 values and coarse correction
-    staged, the correction formed in FP32 and added in FP64) gives the values
-    of the prolongation pass into the FP64 output, bitwise: one V-cycle, a
+    staged, the correction formed in FP32 and added in FP64), and the FP32
+    coarse levels' prolongations inside their first tiled post-smoothing
+    sweeps, give the values of the prolongation passes, bitwise: one V-cycle, a
     flexible solve (fused <r, z> and <z, q>) and three printed-beta steps
     (fused <r, z>).  (68, 100) stages the coarse values one by one (coarse
     half-width 34), has eight ragged 13-level segments and partial tiles;
@@ -93,6 +94,7 @@ def test_mixed_fused_prolongation_is_bitwise(nx, nz, levels, precision):
         finally:
             ell.set_tuning(ell.ELL_TUNE_FUSED_PROLONG, 1)
         assert G.features["fused_prolong"] == bool(fused)
+        assert G.features["coarse_prolong"] == (bool(fused) and levels >= 3)
         z = host(G.vcycle(r))
         u, st = G.pcg_solve(dev(p.f), rtol=1e-8)
         assert st.status == 0

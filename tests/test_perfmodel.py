@@ -38,6 +38,9 @@ def test_vcycle_and_iteration():
     assert P.hybrid_vcycle_bytes(N, 4, 5, fused_prolong=True) == pytest.approx(57.53125 * N)
     assert P.smooth0_launch_bytes_hybrid(N) == pytest.approx(9.5 * N)
     assert P.smooth0_launch_bytes_hybrid(N, fused_prolong=True) == pytest.approx(9.25 * N)
+    # and on the FP32 levels 1, 2: 1 e = 4 B per unknown of those levels
+    assert P.hybrid_vcycle_bytes(N, 4, 5, fused_prolong=True, coarse_prolong=True) == pytest.approx(
+        (57.53125 - 4 * (1 / 4 + 1 / 16)) * N)
 
 
 def test_cg_vector_work():
