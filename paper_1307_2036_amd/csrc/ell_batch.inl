@@ -167,6 +167,28 @@ __global__ __launch_bounds__(NSEG * 64) void kb_smooth_tile(const StageEnt *__re
                                               c == 1 ? 0 : ui(gd->nb_tiles), gp(gd->q) + c * cs);
 }
 
+// The mixed-precision V-cycle's finest colour-1 post-smoothing sweep (FP64)
+// with the last prolongation applied on the fly, as k_smooth_tile_pro32: the
+// FP32 colour-0 values of u32 and the FP32 coarse correction are staged, the
+// correction formed in FP32 and added in FP64 (the values the prolongation
+// pass would write into z); DOT as kb_smooth_tile.  The coarse values load
+// one by one (the grids of a stage differ in their coarse half-widths).
+template <int SEG, int NSEG, bool DOT>
+__global__ __launch_bounds__(NSEG * 64) void kb_smooth_tile_pro32(const StageEnt *__restrict__ ents, int nent,
+                                                                  int total) {
+  const int bg = logical_block();
+  if (bg >= total) return;
+  const int e = find_ent(ents, nent, bg);
+  const GridDev *gd = gp(ents[e].g);
+  const Geo G = ugeo(gd->lev[0].geo);
+  const Geo C = ugeo(gd->lev[1].geo);
+  const long long cs = G.cs;
+  smooth_tile_body<SEG, NSEG, true, DOT ? 2 : 0, false, true, 4, false, float>(
+      G, cp(gd->tab64_0), 1, gp(gd->r) + cs, gp((const float *)gd->u32), gp(gd->z) + cs, gp(&gd->st->done),
+      ui(bg - ents[e].block0), gp(gd->partial), 0, gp(gd->q) + cs, nullptr, nullptr, &C,
+      gp((const float *)gd->lev[1].u));
+}
+
 // The finest level's first pre-smoothing pair of the grids with the fused
 // residual update (column kernel; ROLE_PRE32: the FP32 sweep of the
 // mixed-precision V-cycle, ROLE_FINE64: FP64).  HEAD: at the start of a
@@ -445,6 +467,13 @@ bool batch_tile(const ell_grid *g) {
   return tile_ok(g, 0) && ((ns == 4 && seg_len(g->d.nz, 4) <= 32) || (ns == 8 && seg_len(g->d.nz, 8) <= 16));
 }
 bool batch_fused_dot(const ell_grid *g) { return batch_tile(g) && g->fused_dot && g->L >= 2 && g->d.nu_post >= 1; }
+// The mixed-precision V-cycle's finest prolongation rides on the first FP64
+// colour-1 post-smoothing sweep (bilinear, the tiled sweep; the colour-0
+// sweep after it overwrites colour 0 of z without reading it).
+bool batch_pro32(const ell_grid *g) {
+  return g->prec != ELL_FP64 && g->fused_prolong && g->d.prolong == 0 && g->L >= 2 && g->d.nu_post >= 1 &&
+         batch_tile(g);
+}
 // The residual update rides on the finest level's first pre-smoothing pair
 // (four k-segments of at most 32 levels or eight of at most 16).
 bool batch_fused_update(const ell_grid *g) {
@@ -537,10 +566,10 @@ struct Ticket {
 // One stage of a grouped iteration.
 struct Stage {
   enum Kind { APPLY_DIR, UPDATE_R, DOTS, FINALIZE, SMOOTH, SMOOTH_TILE, SMOOTH_UPD, SMOOTH_TILE_UPD, RESTRICT,
-              PROLONG, PROLONG_OUT, PROLONG_TILE, PROLONG_OUT_TILE } kind;
+              PROLONG, PROLONG_OUT, PROLONG_TILE, PROLONG_OUT_TILE, SMOOTH_TILE_PRO } kind;
   int level, colour, zero, role, mode;  // mode: finalize mode; SMOOTH_TILE: 1 with the fused dots
   int seg;                              // SMOOTH: register segment length (16/32/64)
-  int nseg;                             // SMOOTH, SMOOTH_TILE: k-segments (block of nseg wavefronts)
+  int nseg;                             // SMOOTH, SMOOTH_TILE(_PRO): k-segments (block of nseg wavefronts)
   size_t off;                           // offset of the entry table in the device buffer
   int nent, total;
 };
@@ -737,6 +766,30 @@ int batch_build(ell_batch *b) {
       add(t, tile_dot, tiles);
     }
   };
+  // The fused colour-1 sweeps of the mixed-precision grids that take them
+  // (the first post-smoothing sweep of the finest level).
+  auto add_pro = [&](const std::vector<ell_grid *> &gs, bool last_post) {
+    for (int ns : {4, 8}) {
+      std::vector<ell_grid *> plain, dot;
+      for (ell_grid *g : gs) {
+        if (g->lev[0].geo.nseg != ns) continue;
+        (last_post && batch_fused_dot(g) ? dot : plain).push_back(g);
+      }
+      auto tiles = [](ell_grid *g) { return smooth_tiles(g->lev[0].geo); };
+      Stage t{};
+      t.kind = Stage::SMOOTH_TILE_PRO;
+      t.level = 0;
+      t.colour = 1;
+      t.role = ROLE_FINE64;
+      t.nseg = ns;
+      t.mode = 0;
+      t.seg = ns == 8 ? 16 : seg_of(plain, 0);
+      add(t, plain, tiles);
+      t.mode = 1;
+      t.seg = ns == 8 ? 16 : seg_of(dot, 0);
+      add(t, dot, tiles);
+    }
+  };
   // One step is iteration K of every active grid, in the order
   //   z = M r (V-cycle), <r,z> and <z,q>, beta (kappa at K = 1),
   //   p = z + beta p, q = A p and <p,q>, alpha, r -= alpha q, convergence;
@@ -819,6 +872,10 @@ int batch_build(ell_batch *b) {
     for (ell_grid *g : all)
       if (d < g->L - 1) gs.push_back(g);
     if (gs.empty()) continue;
+    // mixed finest level: the grids whose prolongation rides on the first
+    // colour-1 sweep take no prolongation stage
+    std::vector<ell_grid *> pro, rest;
+    for (ell_grid *g : gs) (d == 0 && mixed && batch_pro32(g) ? pro : rest).push_back(g);
     Stage st{};
     if (d == 0 && mixed) {
       st.kind = Stage::PROLONG_OUT;
@@ -832,7 +889,7 @@ int batch_build(ell_batch *b) {
     {
       // bilinear prolongations on the tiled kernel where the level takes it
       std::vector<ell_grid *> col, tile;
-      for (ell_grid *g : gs) {
+      for (ell_grid *g : rest) {
         const Geo &F = g->lev[d].geo;
         (g->d.prolong == 0 && g->smooth_tile && F.has_x && F.ny % 2 == 0 ? tile : col).push_back(g);
       }
@@ -850,7 +907,13 @@ int batch_build(ell_batch *b) {
         sm.zero = 0;
         sm.role = d == 0 ? ROLE_FINE64 : ROLE_COARSE;
         sm.seg = seg_of(gs, d);
-        add_smooth(sm, gs, it == nu_post - 1);
+        if (it == 0 && c == 1 && !pro.empty()) {
+          add_pro(pro, it == nu_post - 1);
+          sm.seg = seg_of(rest, d);
+          add_smooth(sm, rest, it == nu_post - 1);
+        } else {
+          add_smooth(sm, gs, it == nu_post - 1);
+        }
       }
     }
   }
@@ -968,6 +1031,18 @@ int batch_step(ell_batch *b) {
         } else {
           if (st.mode) kb_smooth_tile<32, 4, true><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.colour);
           else kb_smooth_tile<32, 4, false><<<nb, kBlock, 0, s>>>(e, st.nent, st.total, st.colour);
+        }
+        break;
+      case Stage::SMOOTH_TILE_PRO:
+        if (st.nseg == 8) {
+          if (st.mode) kb_smooth_tile_pro32<16, 8, true><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total);
+          else kb_smooth_tile_pro32<16, 8, false><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total);
+        } else if (st.seg == 16) {
+          if (st.mode) kb_smooth_tile_pro32<16, 4, true><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
+          else kb_smooth_tile_pro32<16, 4, false><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
+        } else {
+          if (st.mode) kb_smooth_tile_pro32<32, 4, true><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
+          else kb_smooth_tile_pro32<32, 4, false><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
         }
         break;
       case Stage::FINALIZE: kb_finalize<<<st.nent, kBlock, 0, s>>>(e, st.mode); break;

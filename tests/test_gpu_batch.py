@@ -325,3 +325,31 @@ def test_fused_dots_and_tiles_in_batch(E, precision, flexible):
     assert i1 == i0
     for a, b in zip(u1, u0):
         assert np.linalg.norm(a - b) <= 1e-9 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("flexible", [True, False])
+def test_mixed_fused_prolongation_in_batch_is_bitwise(E, flexible):
+    """The mixed-precision batch's finest prolongation applied inside the first
+    FP64 colour-1 post-smoothing sweep (FP32 colour-0 values and coarse
+    correction staged, the correction formed in FP32 and added in FP64) gives
+    the iterates of the batch with the prolongation pass, bitwise, with the
+    fused dots of either beta; the grids differ in size, depth and segments."""
+    ps = problems()
+    res = []
+    for on in (1, 0):
+        E.set_tuning(E.ELL_TUNE_FUSED_PROLONG, on)
+        try:
+            B = E.Batch(8 << 30)
+            grids = [B.grid(p, precision="fp32") for p in ps]
+        finally:
+            E.set_tuning(E.ELL_TUNE_FUSED_PROLONG, 1)
+        fs = [dev(p.f) for p in ps]
+        us = [torch.zeros_like(f) for f in fs]
+        st = B.wait(B.submit(grids, fs, us, rtol=1e-8, flexible=flexible))
+        assert all(s.status == 0 for s in st)
+        res.append(([host(u) for u in us], [s.iters for s in st]))
+        B.close()
+    (u1, i1), (u0, i0) = res
+    assert i1 == i0
+    for a, b in zip(u1, u0):
+        np.testing.assert_array_equal(a, b)
