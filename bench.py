@@ -297,7 +297,7 @@ def bench_c1(a):
     t_a = live(G.profile_times(ell.ELL_K_APPLY))
     feat = G.features
     dot_q = feat["fused_dots"] and flexible
-    fpro = feat["fused_prolong"] and not flexible
+    fpro = feat["fused_prolong"]
     launch_bytes = (perfmodel.smooth0_launch_bytes(n, 8, fused_update=feat["fused_update"], dot_q=dot_q,
                                                    fused_prolong=fpro)
                     if a.precision == "fp64" else

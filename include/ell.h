@@ -151,8 +151,7 @@ int ell_grid_levels(const ell_grid *g);
  * products ride on the last two post-smoothing half-sweeps),
  * ELL_FEAT_FUSED_UPDATE (the residual update r -= alpha q rides on the first
  * pre-smoothing pair), ELL_FEAT_FUSED_PROLONG (the finest prolongation rides
- * on the first post-smoothing sweep: FP64 grids for solves with the printed
- * beta, mixed-precision grids with either beta),
+ * on the first post-smoothing sweep),
  * ELL_FEAT_TILED_ENDS (a solve's start, r = V f - A u0, and end, the final
  * update and true residual, run on LDS tiles), ELL_FEAT_COARSE_TAIL (the
  * coarsest level's sweeps run in one cooperative launch; cleared if the
@@ -305,10 +304,10 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * place of a separate pass over r and q; 0 always uses the separate pass;
  * FUSED_PROLONG 1 (default) lets the finest level's first post-smoothing sweep
  * of an FP64 V-cycle (one post-smoothing sweep, bilinear prolongation, fused
- * dots taking <r, z> alone, i.e. the printed beta) apply the coarse correction
- * to the colour-0 values it reads instead of a prolongation pass (the
- * colour-0 sweep that follows overwrites them), the colour-0 sweep then forming
- * <r, z> of both colours, and does the same on every coarse FP64 level with
+ * dots, either beta) apply the coarse correction to the colour-0 values it
+ * reads instead of a prolongation pass (the colour-0 sweep that follows
+ * overwrites them), the colour-0 sweep then forming <r, z> (and, with the
+ * flexible beta, <z, q>) of both colours, and does the same on every coarse FP64 level with
  * LDS-tiled sweeps and rho = 1 (any beta; same values, bitwise), and lets the
  * mixed-precision V-cycle's first FP64 post-smoothing sweep of the finest
  * level (colour 1, LDS-tiled, bilinear prolongation) read the FP32 colour-0

@@ -882,10 +882,10 @@ int launch_smooth_upd(ell_grid *g, int c, double *r, R *u, const R *tab, int pba
 }
 
 // The finest level's post-smoothing (nu_post = 1) of an FP64 V-cycle whose
-// CG dots are fused and take <r, z> alone: the colour-1 sweep applies the
-// coarse correction to the colour-0 values it reads (no prolongation pass),
-// the colour-0 sweep forms <r, z> of both colours into the first tile-count
-// partial slots.  The caller has checked pro_path.
+// CG dots are fused: the colour-1 sweep applies the coarse correction to the
+// colour-0 values it reads (no prolongation pass), the colour-0 sweep forms
+// <r, z> (dot = 1; and <z, q>, dot = 2) of both colours into the first
+// tile-count partial slots.  The caller has checked pro_path.
 // The staged coarse values of a fused prolongation load in aligned pairs
 // (k_smooth_tile_pro<..., PAIR>): coarse half-width, colour and plane strides
 // even, the array aligned to a pair (16 bytes in FP64, 8 in FP32).
@@ -903,7 +903,7 @@ void launch_tile_pro(int nbt, hipStream_t s, const Geo &F, const Geo &C, const R
 }
 
 template <int SEG, int NSEG>
-void pro_pair_k(ell_grid *g, const double *b, double *u, const int *done, hipStream_t s) {
+void pro_pair_k(ell_grid *g, const double *b, double *u, const int *done, hipStream_t s, int dot) {
   const Geo &F = g->lev[0].geo, &C = g->lev[1].geo;
   const double *tab = (const double *)g->lev[0].tab;
   const int nbt = blocks8((long long)smooth_tiles(F) * kBlock);
@@ -913,7 +913,11 @@ void pro_pair_k(ell_grid *g, const double *b, double *u, const int *done, hipStr
     launch_tile_pro<SEG, NSEG, true>(nbt, s, F, C, tab, b + cs, u, u + cs, (const double *)g->lev[1].u, done);
   }
   ProfScope ps(g, ELL_K_SMOOTH0, s);
-  k_smooth_tile_dot3<SEG, NSEG><<<nbt, NSEG * 64, 0, s>>>(F, tab, b, u + cs, u, done, g->partial, b + cs);
+  if (dot == 2)
+    k_smooth_tile_dot4<SEG, NSEG><<<nbt, NSEG * 64, 0, s>>>(F, tab, b, u + cs, u, done, g->partial, b + cs, g->q,
+                                                            g->q + cs);
+  else
+    k_smooth_tile_dot3<SEG, NSEG><<<nbt, NSEG * 64, 0, s>>>(F, tab, b, u + cs, u, done, g->partial, b + cs);
 }
 
 // A coarse level's prolongation rides on its first post-smoothing sweep the
@@ -943,14 +947,14 @@ int coarse_pro_sweep(ell_grid *g, int l, const R *b, R *u, const int *done, hipS
   return check_launch("k_smooth_tile_pro");
 }
 
-int pro_pair(ell_grid *g, const double *b, double *u, const int *done, hipStream_t s) {
+int pro_pair(ell_grid *g, const double *b, double *u, const int *done, hipStream_t s, int dot) {
   const Geo &F = g->lev[0].geo;
   const int Ls = seg_len(F.nz, F.nseg);
-  if (F.nseg == 16) pro_pair_k<8, 16>(g, b, u, done, s);
-  else if (F.nseg == 8) pro_pair_k<16, 8>(g, b, u, done, s);
-  else if (Ls <= 16) pro_pair_k<16, 4>(g, b, u, done, s);
-  else pro_pair_k<32, 4>(g, b, u, done, s);
-  return check_launch("k_smooth_tile_pro / k_smooth_tile_dot3");
+  if (F.nseg == 16) pro_pair_k<8, 16>(g, b, u, done, s, dot);
+  else if (F.nseg == 8) pro_pair_k<16, 8>(g, b, u, done, s, dot);
+  else if (Ls <= 16) pro_pair_k<16, 4>(g, b, u, done, s, dot);
+  else pro_pair_k<32, 4>(g, b, u, done, s, dot);
+  return check_launch("k_smooth_tile_pro / k_smooth_tile_dot3 / k_smooth_tile_dot4");
 }
 
 // The first pre-smoothing pair with the fused residual update, then the
@@ -1207,7 +1211,7 @@ int vcycle_from(ell_grid *g, int top, const R *btop, R *utop, const int *done, h
   for (int l = L - 2; l >= top; --l) {
     if constexpr (std::is_same<R, double>::value) {
       if (l == 0 && pro_path(g, dot)) {  // prolongation inside the post-smoothing pair
-        CHK(pro_pair(g, B(0), U(0), done, s));
+        CHK(pro_pair(g, B(0), U(0), done, s, dot));
         continue;
       }
     }
@@ -1394,10 +1398,11 @@ bool fused_dot_path(const ell_grid *g) {
 }
 
 // The finest prolongation rides on the first post-smoothing sweep (pro_pair):
-// FP64 V-cycle with fused dots taking <r, z> alone (dot = 1), one
-// post-smoothing sweep, bilinear prolongation.
+// FP64 V-cycle with fused dots (dot = 1: <r, z>, the printed beta; 2: <r, z>
+// and <z, q>, the flexible beta), one post-smoothing sweep, bilinear
+// prolongation.
 bool pro_path(const ell_grid *g, int dot) {
-  return dot == 1 && g->fused_prolong && g->prec == ELL_FP64 && fused_dot_path<double>(g) &&
+  return (dot == 1 || dot == 2) && g->fused_prolong && g->prec == ELL_FP64 && fused_dot_path<double>(g) &&
          g->d.nu_post == 1 && g->d.prolong == 0;
 }
 

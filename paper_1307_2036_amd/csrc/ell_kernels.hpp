@@ -923,6 +923,8 @@ constexpr int kCRow = 48;  // LDS row stride of the staged coarse values (40 use
 // of the written columns plus <r1, z1> over the colour-1 cells of the tile's
 // rows, z1 from the staged values and r1 loaded (r1c: colour 1 of r), into
 // partial[pbase + lb].
+// DOT = 4 (the same with the flexible beta): <b, w> + <r1, z1> and <q, w> +
+// <q1, z1> (q1c: colour 1 of q) into partial[2 (pbase + lb)] and [... + 1].
 // PAIR (with PRO; the coarse level's half-width, colour stride and plane
 // stride even, its array 16-byte aligned): the staged coarse values come in
 // pairs of neighbouring same-colour columns, one 16-byte load per lane on 60
@@ -949,7 +951,8 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const R *__restrict__ ta
                                                  const PcgState *__restrict__ st = nullptr,
                                                  const Geo *Cg = nullptr,
                                                  const typename std::common_type<TU>::type *__restrict__ uc = nullptr,
-                                                 const double *__restrict__ r1c = nullptr) {
+                                                 const double *__restrict__ r1c = nullptr,
+                                                 const double *__restrict__ q1c = nullptr) {
   constexpr bool F32 = std::is_same<TU, float>::value;
   constexpr bool ALIAS = F32 && std::is_same<R, double>::value;  // staged coarse values in xch rows
   static_assert(std::is_same<TU, R>::value || PRO, "mixed element types only with the fused prolongation");
@@ -957,8 +960,8 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const R *__restrict__ ta
   typedef TU nt_p2 __attribute__((ext_vector_type(2)));  // a pair of staged values
   typedef R nt_r2 __attribute__((ext_vector_type(2)));   // a pair of level values
   constexpr int CR = F32 ? 40 : kCRow;                      // row stride of the staged coarse values
-  constexpr int NQ = DOT ? (DOT == 3 ? 1 : DOT) : (UPD ? 1 : 0);  // partial sums per block
-  constexpr int SJ = DOT == 3 ? 1 : DOT;                         // seg_join_store's products
+  constexpr int NQ = DOT ? (DOT == 3 ? 1 : (DOT == 4 ? 2 : DOT)) : (UPD ? 1 : 0);  // partial sums per block
+  constexpr int SJ = DOT == 3 ? 1 : (DOT == 4 ? 2 : DOT);                         // seg_join_store's products
   if constexpr (UPD) {
     // no update pending (a batched grid's first step): the plain sweep of b = r
     if (st->pending == 0) {
@@ -1077,8 +1080,9 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const R *__restrict__ ta
     e = e + TU(1.0 / 16.0) * cv(b, idx + d);
     return e;
   };
-  const double *r1g = DOT == 3 ? gp(r1c) : nullptr;
-  double d1 = 0.0;  // DOT 3: <r1, z1> of this lane's colour-1 cell
+  const double *r1g = DOT >= 3 ? gp(r1c) : nullptr;
+  const double *q1g = DOT == 4 ? gp(q1c) : nullptr;
+  double d1 = 0.0, d2 = 0.0;  // DOT 3, 4: <r1, z1> (and <q1, z1>) of this lane's colour-1 cell
 
   R y[SEG];
   R prev = R(0);
@@ -1086,7 +1090,7 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const R *__restrict__ ta
   for (int c0 = 0; c0 < SEG; c0 += CH) {
     if (c0 < len) {
       R bv[CH];
-      double qv[UPD ? CH : 1], r1v[DOT == 3 ? CH : 1];
+      double qv[UPD ? CH : 1], r1v[DOT >= 3 ? CH : 1], q1v[DOT == 4 ? CH : 1];
       TU ev[CH], cv0[PRO && !PAIR ? CH : 1], cv1[PRO && !PAIR ? CH : 1];
       nt_p2 cvp[PRO && PAIR ? CH : 1];
       nt_p2 tv[CH];
@@ -1106,7 +1110,8 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const R *__restrict__ ta
             cv1[t] = ucg[kc * HC + co1];
           }
         }
-        if constexpr (DOT == 3) r1v[t] = __builtin_nontemporal_load(&r1g[o + mo]);
+        if constexpr (DOT >= 3) r1v[t] = __builtin_nontemporal_load(&r1g[o + mo]);
+        if constexpr (DOT == 4) q1v[t] = __builtin_nontemporal_load(&q1g[o + mo]);
       }
       // Every level of the chunk runs without a branch (levels past the
       // segment's end repeat its last level and are discarded), so no load is
@@ -1153,9 +1158,11 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const R *__restrict__ ta
         __asm__ volatile("" ::: "memory");
         const R w = slot[r + 1][x + 1 + par], e = slot[r + 1][x + 2 + par];
         const R so = slot[r][x + 2], no = slot[r + 2][x + 2];
-        if constexpr (DOT == 3) {
+        if constexpr (DOT >= 3) {
           const double z1 = slot[r + 1][x + 2];  // the colour-1 cell (j, mx0 + x)
-          d1 += (valid && c0 + t < len) ? r1v[t] * z1 : 0.0;
+          const bool on = valid && c0 + t < len;
+          d1 += on ? r1v[t] * z1 : 0.0;
+          if constexpr (DOT == 4) d2 += on ? q1v[t] * z1 : 0.0;
         }
         __asm__ volatile("" ::: "memory");
         R g = bv[t];
@@ -1177,10 +1184,10 @@ __device__ __forceinline__ void smooth_tile_body(Geo L, const R *__restrict__ ta
       }
     }
   }
-  double dsum[2] = {UPD ? rsq : d1, 0.0};
+  double dsum[2] = {UPD ? rsq : d1, d2};
   seg_join_store<R, false, true, FINE, SEG, NSEG, SJ>(y, prev, xch, sg, lane, k0, k1, len, nz, Ls, pf, cf,
                                                       qb, valid, own + mo, H, R(1), &bsh[DOT ? sg : 0][0][0],
-                                                           DOT == 2 ? qc + mo : nullptr, dsum);
+                                                           (DOT == 2 || DOT == 4) ? qc + mo : nullptr, dsum);
   if constexpr (NQ > 0) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -1265,6 +1272,21 @@ __global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_dot3(Geo L, const dou
                                                                 const double *__restrict__ r1c) {
   smooth_tile_body<SEG, NSEG, true, 3, false, false, 4>(L, tab, 0, bo, uo, own, done, logical_block(), partial, 0,
                                                         nullptr, nullptr, nullptr, nullptr, nullptr, r1c);
+}
+
+// The same with the flexible beta: <r, z> and <z, q> of both colours.
+template <int SEG, int NSEG>
+__global__ __launch_bounds__(NSEG * 64) void k_smooth_tile_dot4(Geo L, const double *__restrict__ tab,
+                                                                const double *__restrict__ bo,
+                                                                const double *__restrict__ uo,
+                                                                double *__restrict__ own,
+                                                                const int *__restrict__ done,
+                                                                double *__restrict__ partial,
+                                                                const double *__restrict__ r1c,
+                                                                const double *__restrict__ q0c,
+                                                                const double *__restrict__ q1c) {
+  smooth_tile_body<SEG, NSEG, true, 4, false, false, 4>(L, tab, 0, bo, uo, own, done, logical_block(), partial, 0,
+                                                        q0c, nullptr, nullptr, nullptr, nullptr, r1c, q1c);
 }
 
 // The finest level's tiled half-sweep with the fused CG inner products.

@@ -459,12 +459,14 @@ def test_coarse_sweep_pairs_are_bitwise(ell, orc, shape, mg, precision):
         assert rel(out[0], orc.vcycle(g, r)) <= 1e-11
 
 
+@pytest.mark.parametrize("flexible", [False, True])
 @pytest.mark.parametrize("nx,ny,nz,levels", [(64, 16, 32, 3), (68, 12, 100, 2), (136, 8, 40, 2),
                                            (64, 64, 48, 4)])
-def test_fused_prolongation_equals_prolongation_pass(ell, orc, nx, ny, nz, levels):
-    """With the printed beta, the finest coarse correction applied inside the
-    first post-smoothing sweep (and <r, z> of both colours formed by the last)
-    gives the iterates of the prolongation pass: the same iteration count,
+def test_fused_prolongation_equals_prolongation_pass(ell, orc, nx, ny, nz, levels, flexible):
+    """With either beta, the finest coarse correction applied inside the
+    first post-smoothing sweep (and <r, z>, with the flexible beta also
+    <z, q>, of both colours formed by the last) gives the iterates of the
+    prolongation pass: the same iteration count,
     solutions within 1e-10, the same state at an iteration limit, and the
     oracle's solution.  (136, 8) has partial tiles, nz = 100 eight ragged
     k-segments."""
@@ -480,19 +482,21 @@ def test_fused_prolongation_equals_prolongation_pass(ell, orc, nx, ny, nz, level
         finally:
             ell.set_tuning(ell.ELL_TUNE_FUSED_PROLONG, 1)
         assert G.features["fused_prolong"] == bool(fused)
-        u, st = G.pcg_solve(dev(p.f), rtol=1e-8, flexible=False)
+        u, st = G.pcg_solve(dev(p.f), rtol=1e-8, flexible=flexible)
         assert st.status == 0
-        ul, stl = G.pcg_solve(dev(p.f), rtol=1e-14, maxiter=3, flexible=False)
+        ul, stl = G.pcg_solve(dev(p.f), rtol=1e-14, maxiter=3, flexible=flexible)
         assert stl.status == ell.ELL_NOT_CONVERGED and stl.iters == 3
         res.append((host(u), st, host(ul), stl))
     (u1, s1, l1, t1), (u0, s0, l0, t0) = res
     assert s1.iters == s0.iters
     assert rel(u1, u0) <= 1e-10 and rel(l1, l0) <= 1e-10
-    # the recurrence residual after 3 steps is 0.07 of ||r0|| on the slowest
-    # case: iterates equal to ~1e-11 move it by up to ~1e-9 of itself
-    assert abs(t1.r_norm / t0.r_norm - 1) <= 1e-8
+    # the recurrence residual r_k = r_0 - sum alpha_i q_i after 3 steps lies
+    # between 1e-3 and 0.07 of ||r0|| here: the fused dots sum in another order,
+    # and rounding-size differences of alpha and beta reach r_k in proportion
+    # to ||r0||, not to ||r_k||
+    assert abs(t1.r_norm - t0.r_norm) <= 1e-9 * t0.r0_norm
     g = orc.Grid.from_problem(p)
-    check_solve(orc, g, p.f, u1, s1, 1e-8, flexible=False)
+    check_solve(orc, g, p.f, u1, s1, 1e-8, flexible=flexible)
 
 
 @pytest.mark.parametrize("nx,ny,nz,levels", [(64, 16, 32, 3), (68, 12, 100, 2), (136, 36, 40, 2),
