@@ -171,9 +171,10 @@ __global__ __launch_bounds__(NSEG * 64) void kb_smooth_tile(const StageEnt *__re
 // with the last prolongation applied on the fly, as k_smooth_tile_pro32: the
 // FP32 colour-0 values of u32 and the FP32 coarse correction are staged, the
 // correction formed in FP32 and added in FP64 (the values the prolongation
-// pass would write into z); DOT as kb_smooth_tile.  The coarse values load
-// one by one (the grids of a stage differ in their coarse half-widths).
-template <int SEG, int NSEG, bool DOT>
+// pass would write into z); DOT as kb_smooth_tile.  PAIR: every grid of the
+// stage has the coarse layout of paired loads (pro32_pairs_ok), else the
+// coarse values load one by one.
+template <int SEG, int NSEG, bool DOT, bool PAIR>
 __global__ __launch_bounds__(NSEG * 64) void kb_smooth_tile_pro32(const StageEnt *__restrict__ ents, int nent,
                                                                   int total) {
   const int bg = logical_block();
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(NSEG * 64) void kb_smooth_tile_pro32(const StageEnt
   const Geo G = ugeo(gd->lev[0].geo);
   const Geo C = ugeo(gd->lev[1].geo);
   const long long cs = G.cs;
-  smooth_tile_body<SEG, NSEG, true, DOT ? 2 : 0, false, true, 4, false, float>(
+  smooth_tile_body<SEG, NSEG, true, DOT ? 2 : 0, false, true, 4, PAIR, float>(
       G, cp(gd->tab64_0), 1, gp(gd->r) + cs, gp((const float *)gd->u32), gp(gd->z) + cs, gp(&gd->st->done),
       ui(bg - ents[e].block0), gp(gd->partial), 0, gp(gd->q) + cs, nullptr, nullptr, &C,
       gp((const float *)gd->lev[1].u));
@@ -570,6 +571,7 @@ struct Stage {
   int level, colour, zero, role, mode;  // mode: finalize mode; SMOOTH_TILE: 1 with the fused dots
   int seg;                              // SMOOTH: register segment length (16/32/64)
   int nseg;                             // SMOOTH, SMOOTH_TILE(_PRO): k-segments (block of nseg wavefronts)
+  int pair;                             // SMOOTH_TILE_PRO: paired loads of the coarse values
   size_t off;                           // offset of the entry table in the device buffer
   int nent, total;
 };
@@ -770,24 +772,27 @@ int batch_build(ell_batch *b) {
   // (the first post-smoothing sweep of the finest level).
   auto add_pro = [&](const std::vector<ell_grid *> &gs, bool last_post) {
     for (int ns : {4, 8}) {
-      std::vector<ell_grid *> plain, dot;
-      for (ell_grid *g : gs) {
-        if (g->lev[0].geo.nseg != ns) continue;
-        (last_post && batch_fused_dot(g) ? dot : plain).push_back(g);
+      for (int pair = 1; pair >= 0; --pair) {
+        std::vector<ell_grid *> plain, dot;
+        for (ell_grid *g : gs) {
+          if (g->lev[0].geo.nseg != ns || (int)pro32_pairs_ok(g->lev[1].geo, g->lev[1].u) != pair) continue;
+          (last_post && batch_fused_dot(g) ? dot : plain).push_back(g);
+        }
+        auto tiles = [](ell_grid *g) { return smooth_tiles(g->lev[0].geo); };
+        Stage t{};
+        t.kind = Stage::SMOOTH_TILE_PRO;
+        t.level = 0;
+        t.colour = 1;
+        t.role = ROLE_FINE64;
+        t.nseg = ns;
+        t.pair = pair;
+        t.mode = 0;
+        t.seg = ns == 8 ? 16 : seg_of(plain, 0);
+        add(t, plain, tiles);
+        t.mode = 1;
+        t.seg = ns == 8 ? 16 : seg_of(dot, 0);
+        add(t, dot, tiles);
       }
-      auto tiles = [](ell_grid *g) { return smooth_tiles(g->lev[0].geo); };
-      Stage t{};
-      t.kind = Stage::SMOOTH_TILE_PRO;
-      t.level = 0;
-      t.colour = 1;
-      t.role = ROLE_FINE64;
-      t.nseg = ns;
-      t.mode = 0;
-      t.seg = ns == 8 ? 16 : seg_of(plain, 0);
-      add(t, plain, tiles);
-      t.mode = 1;
-      t.seg = ns == 8 ? 16 : seg_of(dot, 0);
-      add(t, dot, tiles);
     }
   };
   // One step is iteration K of every active grid, in the order
@@ -997,6 +1002,20 @@ void launch_kb_tile_upd(const Stage &st, const StageEnt *e, int nb, hipStream_t 
   else kb_smooth_tile_upd<32, 4, HEAD><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
 }
 
+template <bool PAIR>
+void launch_kb_pro32(const Stage &st, const StageEnt *e, int nb, hipStream_t s) {
+  if (st.nseg == 8) {
+    if (st.mode) kb_smooth_tile_pro32<16, 8, true, PAIR><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total);
+    else kb_smooth_tile_pro32<16, 8, false, PAIR><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total);
+  } else if (st.seg == 16) {
+    if (st.mode) kb_smooth_tile_pro32<16, 4, true, PAIR><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
+    else kb_smooth_tile_pro32<16, 4, false, PAIR><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
+  } else {
+    if (st.mode) kb_smooth_tile_pro32<32, 4, true, PAIR><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
+    else kb_smooth_tile_pro32<32, 4, false, PAIR><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
+  }
+}
+
 // Enqueue one grouped CG iteration for every active grid.
 int batch_step(ell_batch *b) {
   hipStream_t s = b->stream;
@@ -1034,16 +1053,8 @@ int batch_step(ell_batch *b) {
         }
         break;
       case Stage::SMOOTH_TILE_PRO:
-        if (st.nseg == 8) {
-          if (st.mode) kb_smooth_tile_pro32<16, 8, true><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total);
-          else kb_smooth_tile_pro32<16, 8, false><<<nb, 8 * 64, 0, s>>>(e, st.nent, st.total);
-        } else if (st.seg == 16) {
-          if (st.mode) kb_smooth_tile_pro32<16, 4, true><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
-          else kb_smooth_tile_pro32<16, 4, false><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
-        } else {
-          if (st.mode) kb_smooth_tile_pro32<32, 4, true><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
-          else kb_smooth_tile_pro32<32, 4, false><<<nb, kBlock, 0, s>>>(e, st.nent, st.total);
-        }
+        if (st.pair) launch_kb_pro32<true>(st, e, nb, s);
+        else launch_kb_pro32<false>(st, e, nb, s);
         break;
       case Stage::FINALIZE: kb_finalize<<<st.nent, kBlock, 0, s>>>(e, st.mode); break;
       case Stage::SMOOTH:
