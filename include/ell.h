@@ -289,10 +289,11 @@ int ell_profile_times(ell_grid *g, int family, float *ms, int cap);
  * tiles, 0 on the column-walking kernel; BATCH_GRAPH 1 (default) makes batch
  * engines created afterwards replay each grouped step from a captured HIP
  * graph, 0 launches the kernels directly (same results, bitwise); SMOOTH_TILE
- * 1 (default) stages neighbour values in LDS tiles for the FP64 half-sweeps
- * after the first on every level (rho = 1, nx/2 and ny even) and for the
- * bilinear colour-0 prolongation (ny even), 0 uses the column kernels (same
- * values, bitwise); FUSED_DOT 1 (default) lets the finest level's last two
+ * 1 (default) stages neighbour values in LDS tiles for the half-sweeps after
+ * the first on every level (FP64, and FP32 on the coarse levels of the
+ * mixed-precision V-cycle; rho = 1, nx/2 and ny even, even plane and colour
+ * strides) and for the bilinear colour-0 prolongation (ny even), 0 uses the
+ * column kernels (same values, bitwise); FUSED_DOT 1 (default) lets the finest level's last two
  * post-smoothing half-sweeps of a CG preconditioner application (tiled, with
  * at least two levels) also form the partial sums of <r, z> (and <z, q> for
  * the flexible beta) that the next CG scalar needs, in place of a separate
